@@ -1,0 +1,469 @@
+/*
+ * FP64 CPU oracle for accelerated spherical k-means (Schubert, Lang, Feher,
+ * "Accelerating Spherical k-Means", arXiv 2107.04074).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+ * benchmark's CPU-baseline leg load this file's library.  It shares no code,
+ * header, table or constant with the GPU library and must never be used as
+ * a fallback for it.
+ *
+ * Everything is plain double-precision loops written for readability:
+ *   - similarities are dot products of unit vectors (Section 2), summed
+ *     sequentially over the stored entries of a row;
+ *   - the assignment keeps argmax_j <x(i), c(j)> (Section 5, assignment
+ *     equation) with a fixed tie rule (see ARGMAX below);
+ *   - the update sets c(j) to the member sum scaled to unit length
+ *     (Section 5, centre equation);
+ *   - Elkan, simplified Elkan, Hamerly and simplified Hamerly follow the
+ *     steps of Sections 5.1 to 5.4 with the bound updates of Eq. (6), (7)
+ *     and (9) of Section 4 / 5.3.
+ * The plain Lloyd iteration is the definition of the result; the bounded
+ * variants exist to count similarity computations and to show that they
+ * reach exactly the same assignments (the central claim of Section 4).
+ *
+ * Readings where the paper is silent (documented with the project design):
+ *   ARGMAX   ties: keep the previous assignment if it attains the maximum,
+ *            otherwise the lowest index among the maxima.
+ *   STOP     an iteration is one assignment step; stop when no assignment
+ *            changed or after max_iter steps; after every step that changed
+ *            something the centres are updated, so the returned centres are
+ *            always the normalised member sums of the returned assignment.
+ *   EMPTY    a cluster without members keeps its previous centre (p = 1).
+ *   GUARDS   Eq. (7) is cos(theta_u - theta_p) and only bounds while
+ *            theta_u >= theta_p, so u <- 1 when u >= p; Eq. (6) is
+ *            cos(theta_l + theta_p) and only bounds while the sum stays
+ *            below pi, so l <- -1 when l <= -p.
+ *   HAMERLY  the default upper-bound update applies the guarded Eq. (7)
+ *            with p'(a) = min_{j != a} p(j); the guarded form is monotone in
+ *            the movement angle, so the largest movement is the worst case.
+ *            bound_form = 1 uses Eq. (9) instead where it is valid
+ *            (u >= 0 and p' >= 0) and the guarded Eq. (7) elsewhere.
+ *            bound_form = 2 applies Eq. (6)/(7) exactly as printed, without
+ *            guards; it exists only so tests can show what the guards
+ *            prevent and is never a correct configuration.
+ *   MOVEMENT 1 - p(j) is evaluated as |c(j) - c'(j)|^2 / 2 (Eq. (2)
+ *            relation) rather than 1 - <c, c'>, which cancels near 1.
+ *   MARGIN   every pruning test leaves a margin DELTA = 1e-10 so that
+ *            double rounding in the bounds can never prune a centre whose
+ *            computed similarity could reach the maximum.
+ *   INIT     the initial centres are rescaled to unit length in double
+ *            precision before the first step: the paper's centres are unit
+ *            vectors, and rows picked as initial centres are unit only up to
+ *            float rounding.
+ *   COSINE   stored rows are unit only up to float rounding, so bounds are
+ *            kept on the cosine <x, c> / |x| (the definition of sim in
+ *            Section 2), for which the triangle inequalities of Eq. (4)/(5)
+ *            hold exactly; assignment decisions compare the dot products
+ *            themselves, which rank centres the same way for a fixed row.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define DELTA 1e-10
+
+enum { ORC_LLOYD = 0, ORC_ELKAN = 1, ORC_HAMERLY = 2, ORC_SIMP_ELKAN = 3,
+       ORC_SIMP_HAMERLY = 4 };
+
+typedef struct {
+  int64_t n, d;
+  const int64_t *rp;
+  const int32_t *ci;
+  const float *v;
+} csr_t;
+
+/* <x(i), c> with c a dense length-d vector, summed in stored-entry order. */
+static double sim(const csr_t *X, int64_t i, const double *c) {
+  double s = 0.0;
+  for (int64_t e = X->rp[i]; e < X->rp[i + 1]; ++e)
+    s += (double)X->v[e] * c[X->ci[e]];
+  return s;
+}
+
+static void all_sims(const csr_t *X, int64_t i, int32_t k, const double *C,
+                     double *s) {
+  for (int32_t j = 0; j < k; ++j) s[j] = sim(X, i, C + (size_t)j * X->d);
+}
+
+/* ARGMAX reading; *second = max over j != result (or -inf when k == 1). */
+static int32_t argmax_rule(const double *s, int32_t k, int32_t prev,
+                           double *best, double *second) {
+  double mx = -INFINITY;
+  for (int32_t j = 0; j < k; ++j)
+    if (s[j] > mx) mx = s[j];
+  int32_t a = -1;
+  if (prev >= 0 && prev < k && s[prev] == mx) {
+    a = prev;
+  } else {
+    for (int32_t j = 0; j < k; ++j)
+      if (s[j] == mx) { a = j; break; }
+  }
+  double sc = -INFINITY;
+  for (int32_t j = 0; j < k; ++j)
+    if (j != a && s[j] > sc) sc = s[j];
+  *best = mx;
+  *second = sc;
+  return a;
+}
+
+/* -------------------------------------------------------------------- */
+/* exported single steps                                                 */
+/* -------------------------------------------------------------------- */
+
+/* Assignment step from given centres C (k x d, row-major).  a_prev may be
+ * NULL (first iteration).  Outputs: a, best similarity, second best. */
+void oracle_assign(int64_t n, int64_t d, const int64_t *rp, const int32_t *ci,
+                   const float *v, int32_t k, const double *C,
+                   const int32_t *a_prev, int32_t *a_out, double *s1_out,
+                   double *s2_out) {
+  csr_t X = {n, d, rp, ci, v};
+#pragma omp parallel
+  {
+    double *s = (double *)malloc(sizeof(double) * (size_t)k);
+#pragma omp for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n; ++i) {
+      double b, sc;
+      all_sims(&X, i, k, C, s);
+      a_out[i] = argmax_rule(s, k, a_prev ? a_prev[i] : -1, &b, &sc);
+      if (s1_out) s1_out[i] = b;
+      if (s2_out) s2_out[i] = sc;
+    }
+    free(s);
+  }
+}
+
+/* Similarities of the listed rows to all centres: out is m x k. */
+void oracle_sims(int64_t n, int64_t d, const int64_t *rp, const int32_t *ci,
+                 const float *v, int32_t k, const double *C,
+                 const int64_t *rows, int64_t m, double *out) {
+  csr_t X = {n, d, rp, ci, v};
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t q = 0; q < m; ++q) all_sims(&X, rows[q], k, C, out + (size_t)q * k);
+}
+
+/* Centre step: c(j) = S(j) / |S(j)| with S(j) the member sum; an empty
+ * cluster keeps C_prev(j).  norms_out (nullable) receives |S(j)|.  Returns
+ * sum_j |S(j)|, which equals sum_i <x(i), c(a(i))> after the update. */
+double oracle_update(int64_t n, int64_t d, const int64_t *rp, const int32_t *ci,
+                     const float *v, int32_t k, const int32_t *a,
+                     const double *C_prev, double *C_out, double *norms_out) {
+  double *S = (double *)calloc((size_t)k * (size_t)d, sizeof(double));
+  for (int64_t i = 0; i < n; ++i) {
+    double *Sj = S + (size_t)a[i] * (size_t)d;
+    for (int64_t e = rp[i]; e < rp[i + 1]; ++e) Sj[ci[e]] += (double)v[e];
+  }
+  double obj = 0.0;
+  for (int32_t j = 0; j < k; ++j) {
+    const double *Sj = S + (size_t)j * (size_t)d;
+    double ss = 0.0;
+    for (int64_t t = 0; t < d; ++t) ss += Sj[t] * Sj[t];
+    const double nrm = sqrt(ss);
+    if (norms_out) norms_out[j] = nrm;
+    obj += nrm;
+    double *Cj = C_out + (size_t)j * (size_t)d;
+    if (nrm > 0.0) {
+      for (int64_t t = 0; t < d; ++t) Cj[t] = Sj[t] / nrm;
+    } else if (Cj != C_prev + (size_t)j * (size_t)d) {
+      memcpy(Cj, C_prev + (size_t)j * (size_t)d, sizeof(double) * (size_t)d);
+    }
+  }
+  free(S);
+  return obj;
+}
+
+/* -------------------------------------------------------------------- */
+/* bound updates (Section 4 and 5.3), exported for the tests             */
+/* -------------------------------------------------------------------- */
+
+static double clamp1(double x) { return x > 1.0 ? 1.0 : (x < -1.0 ? -1.0 : x); }
+
+/* Eq. (6) with the GUARDS reading; omp = 1 - p. */
+double oracle_lower_update(double l, double p, double omp) {
+  l = clamp1(l);
+  if (l <= -p) return -1.0;
+  return clamp1(l * p - sqrt((1.0 - l) * (1.0 + l) * omp * (1.0 + p)));
+}
+
+/* Eq. (7) with the GUARDS reading; omp = 1 - p. */
+double oracle_upper_update(double u, double p, double omp) {
+  u = clamp1(u);
+  if (u >= p) return 1.0;
+  return clamp1(u * p + sqrt((1.0 - u) * (1.0 + u) * omp * (1.0 + p)));
+}
+
+/* Eq. (9), valid for u >= 0 and p >= 0; elsewhere the guarded Eq. (7). */
+double oracle_upper_eq9(double u, double p, double omp) {
+  u = clamp1(u);
+  if (u < 0.0 || p < 0.0) return oracle_upper_update(u, p, omp);
+  return clamp1(u + sqrt((1.0 - u) * (1.0 + u) * omp * (1.0 + p)));
+}
+
+/* The printed forms without guards, for tests that show why guards exist. */
+double oracle_lower_unguarded(double l, double p) {
+  return l * p - sqrt((1.0 - l * l) * (1.0 - p * p));
+}
+double oracle_upper_unguarded(double u, double p) {
+  return u * p + sqrt((1.0 - u * u) * (1.0 - p * p));
+}
+
+/* Centre-centre half-angle bound of Section 5.2: cc = sqrt((<ci,cj>+1)/2). */
+double oracle_cc(double g) { return sqrt((clamp1(g) + 1.0) / 2.0); }
+
+/* -------------------------------------------------------------------- */
+/* full fit                                                              */
+/* -------------------------------------------------------------------- */
+
+/* p(j) and 1 - p(j) from old and new centres (MOVEMENT reading). */
+static void movement(int32_t k, int64_t d, const double *Cold,
+                     const double *Cnew, double *p, double *omp) {
+  for (int32_t j = 0; j < k; ++j) {
+    const double *a = Cold + (size_t)j * (size_t)d, *b = Cnew + (size_t)j * (size_t)d;
+    double ss = 0.0;
+    for (int64_t t = 0; t < d; ++t) {
+      const double q = b[t] - a[t];
+      ss += q * q;
+    }
+    omp[j] = 0.5 * ss;
+    p[j] = 1.0 - omp[j];
+  }
+}
+
+/* cc(j, j') for all pairs and s(j) = max_{j' != j} cc(j, j'). */
+static void center_bounds(int32_t k, int64_t d, const double *C, double *cc,
+                          double *s) {
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int32_t j = 0; j < k; ++j) {
+    for (int32_t q = 0; q < k; ++q) {
+      if (q == j) { cc[(size_t)j * k + q] = 1.0; continue; }
+      const double *a = C + (size_t)j * (size_t)d, *b = C + (size_t)q * (size_t)d;
+      double g = 0.0;
+      for (int64_t t = 0; t < d; ++t) g += a[t] * b[t];
+      cc[(size_t)j * k + q] = oracle_cc(g);
+    }
+  }
+  for (int32_t j = 0; j < k; ++j) {
+    double m = -INFINITY;
+    for (int32_t q = 0; q < k; ++q)
+      if (q != j && cc[(size_t)j * k + q] > m) m = cc[(size_t)j * k + q];
+    s[j] = m;
+  }
+}
+
+/* Runs spherical k-means from C_init (k x d) with the given variant.
+ * Per-iteration traces (each of length max_iter, nullable):
+ *   changed    number of points whose assignment changed in the step
+ *   sims       point-centre similarities computed in the step
+ *   ccsims     centre-centre similarities computed in the step
+ *   obj_assign sum_i <x(i), c(a(i))> with the centres used in the step
+ *              (Lloyd only; NaN for the bounded variants)
+ *   obj_update sum_j |S(j)| after the following update (NaN if none)
+ *   a_trace    n x max_iter assignments (column t = step t+1)
+ * check_bounds != 0 recomputes every similarity before each step's tests
+ * and counts bound violations (l above its similarity, u below) into
+ * *violations.  Returns the number of assignment steps executed. */
+int32_t oracle_fit(int64_t n, int64_t d, const int64_t *rp, const int32_t *ci,
+                   const float *v, int32_t k, const double *C_init,
+                   int32_t variant, int32_t max_iter, int32_t bound_form,
+                   int32_t check_bounds, int32_t *a_out, double *C_out,
+                   int64_t *changed_tr, int64_t *sims_tr, int64_t *ccsims_tr,
+                   double *obj_assign_tr, double *obj_update_tr,
+                   int32_t *a_trace, int64_t *violations, int32_t *converged) {
+  csr_t X = {n, d, rp, ci, v};
+  const int elkan = variant == ORC_ELKAN || variant == ORC_SIMP_ELKAN;
+  const int hamerly = variant == ORC_HAMERLY || variant == ORC_SIMP_HAMERLY;
+  const int simplified = variant == ORC_SIMP_ELKAN || variant == ORC_SIMP_HAMERLY;
+
+  double *C = (double *)malloc(sizeof(double) * (size_t)k * (size_t)d);
+  double *Cold = (double *)malloc(sizeof(double) * (size_t)k * (size_t)d);
+  memcpy(C, C_init, sizeof(double) * (size_t)k * (size_t)d);
+  for (int32_t j = 0; j < k; ++j) { /* INIT reading */
+    double *c = C + (size_t)j * (size_t)d, ss = 0.0;
+    for (int64_t t = 0; t < d; ++t) ss += c[t] * c[t];
+    if (ss > 0.0) {
+      const double nrm = sqrt(ss);
+      for (int64_t t = 0; t < d; ++t) c[t] /= nrm;
+    }
+  }
+  int32_t *a = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+  for (int64_t i = 0; i < n; ++i) a[i] = -1;
+  double *l = (double *)malloc(sizeof(double) * (size_t)n);
+  double *uh = hamerly ? (double *)malloc(sizeof(double) * (size_t)n) : NULL;
+  double *ue = elkan ? (double *)malloc(sizeof(double) * (size_t)n * (size_t)k) : NULL;
+  double *p = (double *)malloc(sizeof(double) * (size_t)k);
+  double *omp = (double *)malloc(sizeof(double) * (size_t)k);
+  double *cc = (!simplified && (elkan || hamerly))
+                   ? (double *)malloc(sizeof(double) * (size_t)k * (size_t)k) : NULL;
+  double *sthr = (double *)malloc(sizeof(double) * (size_t)k);
+  double *rn = (double *)malloc(sizeof(double) * (size_t)n);
+  for (int64_t i = 0; i < n; ++i) {
+    double ss = 0.0;
+    for (int64_t e = rp[i]; e < rp[i + 1]; ++e) ss += (double)v[e] * (double)v[e];
+    rn[i] = sqrt(ss);
+  }
+  int64_t viol = 0;
+  int32_t t, done = 0;
+
+  for (t = 0; t < max_iter; ++t) {
+    int64_t changed = 0, sims = 0, ccsims = 0;
+    double obj_assign = NAN;
+
+    if (variant == ORC_LLOYD || t == 0) {
+      /* exhaustive step: Lloyd, and the first step of every variant */
+      double oa = 0.0;
+#pragma omp parallel reduction(+ : changed, oa)
+      {
+        double *s = (double *)malloc(sizeof(double) * (size_t)k);
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t i = 0; i < n; ++i) {
+          double b, sc;
+          all_sims(&X, i, k, C, s);
+          const int32_t na = argmax_rule(s, k, a[i], &b, &sc);
+          if (na != a[i]) changed += 1;
+          a[i] = na;
+          oa += b;
+          if (elkan || hamerly) l[i] = b / rn[i];
+          if (hamerly) uh[i] = sc / rn[i];
+          if (elkan)
+            for (int32_t j = 0; j < k; ++j) ue[(size_t)i * k + j] = s[j] / rn[i];
+        }
+        free(s);
+      }
+      sims = n * (int64_t)k;
+      obj_assign = oa;
+    } else {
+      /* bounded step: p and omp describe the last centre update */
+      if (cc) {
+        center_bounds(k, d, C, cc, sthr);
+        ccsims = (int64_t)k * (k - 1) / 2;
+      }
+      /* p'(j) = min_{j' != j} p(j') for Hamerly: smallest and second
+       * smallest movement cosine */
+      int32_t jmin = -1;
+      double pmin = INFINITY, pmin2 = INFINITY, ompmin = 0.0, ompmin2 = 0.0;
+      for (int32_t j = 0; j < k; ++j) {
+        if (p[j] < pmin) {
+          pmin2 = pmin; ompmin2 = ompmin;
+          pmin = p[j]; ompmin = omp[j]; jmin = j;
+        } else if (p[j] < pmin2) {
+          pmin2 = p[j]; ompmin2 = omp[j];
+        }
+      }
+      if (k == 1) { pmin2 = 1.0; ompmin2 = 0.0; }
+
+#pragma omp parallel reduction(+ : changed, sims, viol)
+      {
+        double *s = check_bounds ? (double *)malloc(sizeof(double) * (size_t)k) : NULL;
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t i = 0; i < n; ++i) {
+          const int32_t prev = a[i];
+          int32_t cur = prev;
+          /* Eq. (6) for l(i) */
+          const int raw = bound_form == 2;
+          l[i] = raw ? oracle_lower_unguarded(l[i], p[cur])
+                     : oracle_lower_update(l[i], p[cur], omp[cur]);
+          if (elkan) {
+            /* Eq. (7) for every u(i, j) */
+            double *ui = ue + (size_t)i * k;
+            for (int32_t j = 0; j < k; ++j)
+              ui[j] = raw ? oracle_upper_unguarded(ui[j], p[j])
+                          : oracle_upper_update(ui[j], p[j], omp[j]);
+          } else {
+            const double pp = (cur == jmin) ? pmin2 : pmin;
+            const double oo = (cur == jmin) ? ompmin2 : ompmin;
+            uh[i] = raw ? oracle_upper_unguarded(uh[i], pp)
+                        : bound_form == 1 ? oracle_upper_eq9(uh[i], pp, oo)
+                                          : oracle_upper_update(uh[i], pp, oo);
+          }
+          if (s) {
+            all_sims(&X, i, k, C, s);
+            for (int32_t j = 0; j < k; ++j) s[j] /= rn[i];
+            if (l[i] > s[cur] + 1e-12) viol += 1;
+            if (elkan) {
+              for (int32_t j = 0; j < k; ++j)
+                if (ue[(size_t)i * k + j] < s[j] - 1e-12) viol += 1;
+            } else {
+              for (int32_t j = 0; j < k; ++j)
+                if (j != cur && uh[i] < s[j] - 1e-12) { viol += 1; break; }
+            }
+          }
+
+          if (elkan) {
+            /* Sections 5.1 / 5.2 */
+            if (!simplified && sthr[cur] <= l[i] - DELTA) continue;
+            double *ui = ue + (size_t)i * k;
+            int tight = 0;
+            double best_raw = 0.0; /* dot product with c(cur) once tight */
+            for (int32_t j = 0; j < k; ++j) {
+              if (j == cur) continue;
+              if (ui[j] <= l[i] - DELTA) continue;
+              if (!simplified && cc[(size_t)cur * k + j] <= l[i] - DELTA) continue;
+              if (!tight) {
+                best_raw = sim(&X, i, C + (size_t)cur * d);
+                l[i] = best_raw / rn[i];
+                ui[cur] = l[i];
+                sims += 1;
+                tight = 1;
+                if (ui[j] <= l[i] - DELTA) continue;
+                if (!simplified && cc[(size_t)cur * k + j] <= l[i] - DELTA) continue;
+              }
+              const double sj = sim(&X, i, C + (size_t)j * d);
+              ui[j] = sj / rn[i];
+              sims += 1;
+              if (sj > best_raw) {
+                cur = j;
+                best_raw = sj;
+                l[i] = ui[j];
+              }
+            }
+          } else {
+            /* Sections 5.3 / 5.4 */
+            if (uh[i] <= l[i] - DELTA) continue;
+            if (!simplified && sthr[cur] <= l[i] - DELTA) continue;
+            l[i] = sim(&X, i, C + (size_t)cur * d) / rn[i];
+            sims += 1;
+            if (uh[i] <= l[i] - DELTA) continue;
+            if (!simplified && sthr[cur] <= l[i] - DELTA) continue;
+            double best = -INFINITY, second = -INFINITY;
+            double *sv = (double *)malloc(sizeof(double) * (size_t)k);
+            all_sims(&X, i, k, C, sv);
+            sims += k - 1;
+            cur = argmax_rule(sv, k, prev, &best, &second);
+            free(sv);
+            l[i] = best / rn[i];
+            uh[i] = second / rn[i];
+          }
+          if (cur != prev) changed += 1;
+          a[i] = cur;
+        }
+        free(s);
+      }
+    }
+
+    if (changed_tr) changed_tr[t] = changed;
+    if (sims_tr) sims_tr[t] = sims;
+    if (ccsims_tr) ccsims_tr[t] = ccsims;
+    if (obj_assign_tr) obj_assign_tr[t] = obj_assign;
+    if (a_trace)
+      for (int64_t i = 0; i < n; ++i) a_trace[(size_t)i * max_iter + t] = a[i];
+
+    if (changed == 0) {
+      if (obj_update_tr) obj_update_tr[t] = NAN;
+      done = 1;
+      t += 1;
+      break;
+    }
+    memcpy(Cold, C, sizeof(double) * (size_t)k * (size_t)d);
+    const double ou = oracle_update(n, d, rp, ci, v, k, a, Cold, C, NULL);
+    if (obj_update_tr) obj_update_tr[t] = ou;
+    movement(k, d, Cold, C, p, omp);
+  }
+
+  memcpy(a_out, a, sizeof(int32_t) * (size_t)n);
+  memcpy(C_out, C, sizeof(double) * (size_t)k * (size_t)d);
+  if (violations) *violations = viol;
+  if (converged) *converged = done;
+  free(rn); free(sthr); free(cc); free(omp); free(p); free(ue); free(uh); free(l);
+  free(a); free(Cold); free(C);
+  return t;
+}
