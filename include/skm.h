@@ -1,0 +1,183 @@
+/*
+ * skm.h -- C ABI of the MI355X (gfx950) spherical k-means library.
+ *
+ * Method: Schubert, Lang, Feher, "Accelerating Spherical k-Means"
+ * (arXiv 2107.04074).  The library runs the assignment step
+ *     a(i) <- argmax_j <x(i), c(j)>                 (Section 5)
+ * over unit-length rows x(i), optionally pruned by the cosine-domain bounds
+ * of Section 4 (Eq. (6), (7)) in the forms of Elkan (Sections 5.1-5.2) and
+ * Hamerly (Sections 5.3-5.4, Eq. (9)), and the centre step
+ *     c(j) <- sum_{a(i)=j} x(i) / |sum_{a(i)=j} x(i)| (Section 5).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every array pointer is a DEVICE pointer unless its comment says [host].
+ *    The caller owns all inputs, outputs and the workspace; the library never
+ *    frees or reallocates caller memory.
+ *  - All work is enqueued on `stream` (a hipStream_t passed as void*; NULL is
+ *    the default stream).  skm_assign returns without synchronising;
+ *    skm_fit synchronises with `stream` once per iteration (it reads the
+ *    number of changed assignments) and returns after the fit completed.
+ *  - Every function returns an skm_status; no C++ exception crosses the ABI.
+ *    On error the outputs are unspecified and skm_last_error() describes the
+ *    failure (thread-local string, valid until the next call on the thread).
+ *  - Workspace: pass a device buffer of at least skm_workspace_size() bytes,
+ *    256-byte aligned, or NULL to let the call allocate (stream-ordered
+ *    hipMallocAsync) and free it before returning.  A smaller buffer fails
+ *    with SKM_ERR_OUT_OF_MEMORY.
+ *  - Concurrent calls on distinct workspaces and streams are safe.
+ *
+ * Input matrix (skm_matrix)
+ * -------------------------
+ *  SKM_CSR_F32:   row_ptr int64[n+1] (row_ptr[0] = 0, non-decreasing,
+ *                 row_ptr[n] = nnz), col_idx int32[nnz] in [0, d), val
+ *                 float[nnz].  Column ids ascending within a row is the
+ *                 expected layout (the paper stores sparse vectors as sorted
+ *                 (index, value) pairs, Section 2) but not required.
+ *  SKM_DENSE_F32: dense float[n * ld], row-major, ld >= d.
+ *  Rows must have unit L2 norm (Section 5: samples are normalised during
+ *  initialisation).  Float rounding of the norm is tolerated: internal
+ *  bounds account for each row's measured deviation.
+ *
+ * Numerics
+ * --------
+ *  Similarities are evaluated in FP32 (sparse: one sequential FMA chain per
+ *  (row, centre) over the stored entries; dense: MFMA).  Whenever the best
+ *  and second best FP32 values lie within the rigorous FP32 error bound of
+ *  each other, the candidates are re-evaluated in FP64 against the FP64
+ *  master centres, so every assignment equals the argmax of the FP64 dot
+ *  products.  Ties are resolved by keeping the previous assignment if it
+ *  attains the maximum, else by the lowest centre index.  Pruning tests use
+ *  bounds on true cosines with outward rounding and margins, so the bounded
+ *  variants produce exactly the assignments of SKM_LLOYD.
+ */
+#ifndef SKM_H_
+#define SKM_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SKM_LLOYD = 0,        /* exhaustive spherical Lloyd (Section 5)            */
+  SKM_ELKAN = 1,        /* per-centre bounds + centre-centre tests (5.2)     */
+  SKM_HAMERLY = 2,      /* one upper and one lower bound + s(a) test (5.3)   */
+  SKM_SIMP_ELKAN = 3,   /* Elkan without centre-centre tests (5.1)           */
+  SKM_SIMP_HAMERLY = 4  /* Hamerly without the s(a) test (5.4)               */
+} skm_variant;
+
+typedef enum {
+  SKM_OK = 0,
+  SKM_ERR_INVALID_ARG = 1,    /* null pointer, size out of range, bad enum   */
+  SKM_ERR_NOT_NORMALIZED = 2, /* validation found a row that is not unit     */
+  SKM_ERR_OUT_OF_MEMORY = 3,  /* workspace too small or allocation failed    */
+  SKM_ERR_HIP = 4,            /* a HIP runtime call failed                   */
+  SKM_ERR_UNSUPPORTED = 5     /* valid request this build does not handle    */
+} skm_status;
+
+typedef enum { SKM_CSR_F32 = 0, SKM_DENSE_F32 = 1 } skm_format;
+
+typedef struct {
+  int32_t fmt;              /* skm_format                                     */
+  int32_t reserved0;
+  int64_t n, d, nnz;        /* rows, columns, stored entries (CSR)            */
+  const int64_t* row_ptr;   /* CSR                                            */
+  const int32_t* col_idx;   /* CSR                                            */
+  const float* val;         /* CSR                                            */
+  const float* dense;       /* DENSE: n x ld row-major                        */
+  int64_t ld;               /* DENSE leading dimension (>= d)                 */
+} skm_matrix;
+
+typedef struct {            /* [host]; an all-zero struct means defaults      */
+  int32_t bound_form;       /* Hamerly upper-bound update: 0 = guarded Eq. (7)
+                               with p'(a) = min_{j!=a} p(j) (default);
+                               1 = Eq. (9) where valid (u, p' >= 0)           */
+  int32_t precision;        /* 0 = FP32 similarities; 1 = BF16 MFMA (dense
+                               input only), same exact-argmax guarantee       */
+  int32_t validate;         /* 0 = none; 1 = initial centres must be unit
+                               within norm_tol; 2 = also every data row      */
+  int32_t profile;          /* 1 = time every launch of the similarity kernel
+                               with HIP events on `stream` (fills the
+                               sim_kernel_* statistics; adds event records) */
+  double norm_tol;          /* default 1e-4                                   */
+} skm_options;
+
+typedef struct {            /* [host] filled by skm_fit                       */
+  int32_t iterations;       /* assignment steps executed                      */
+  int32_t converged;        /* 1 if the last step changed no assignment       */
+  double objective;         /* sum_i <x(i), c(a(i))> for the returned centres */
+  int64_t sims_point_center;  /* point-centre similarities evaluated         */
+  int64_t sims_center_center; /* centre-centre inner products evaluated      */
+  int64_t rechecks;         /* rows whose decision was re-evaluated in FP64   */
+  /* optional per-iteration records, [host] arrays of per_iter_len entries
+     (nullable); entry t describes assignment step t+1 */
+  int64_t* changed_per_iter;
+  int64_t* sims_per_iter;
+  double* objective_per_iter; /* objective after the update following step t
+                                 (the previous value when nothing changed)  */
+  int32_t per_iter_len;
+  int32_t reserved0;
+  /* work of the similarity kernel (the dominant kernel): launches, rows and
+     stored entries it processed, and (profile = 1) its summed duration */
+  int64_t sim_kernel_launches;
+  int64_t sim_kernel_rows;
+  int64_t sim_kernel_nnz;
+  double sim_kernel_ms;
+} skm_stats;
+
+/* Bytes of workspace skm_fit needs for this problem (0 on invalid input;
+ * then skm_last_error() says why).  opt may be NULL. */
+size_t skm_workspace_size(const skm_matrix* X, int32_t k, int32_t variant,
+                          const skm_options* opt);
+
+/* Bytes of workspace skm_assign needs. */
+size_t skm_assign_workspace_size(const skm_matrix* X, int32_t k);
+
+/* Spherical k-means from the given initial centres.
+ *   init_centers   float[k*d] row-major; rows are rescaled to unit length in
+ *                  FP64 before the first step (the paper's centres are unit
+ *                  vectors; rows picked from float data are unit only to
+ *                  rounding).
+ *   variant        skm_variant.
+ *   max_iter       >= 1; counts assignment steps.  The fit stops early when
+ *                  a step changes no assignment.  After every step that
+ *                  changed something the centres are updated, so the returned
+ *                  centres are the normalised member sums of the returned
+ *                  assignment; a cluster that loses all members keeps its
+ *                  previous centre.
+ *   assign_out     int32[n]: final assignment (also used as working state).
+ *   centers_out    float[k*d] row-major (nullable): final centres.
+ *   centers64_out  double[k*d] row-major (nullable): final FP64 centres.
+ *   stats          [host] (nullable).
+ */
+int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers,
+            int32_t variant, int32_t max_iter, const skm_options* opt,
+            void* workspace, size_t workspace_bytes, int32_t* assign_out,
+            float* centers_out, double* centers64_out, skm_stats* stats,
+            void* stream);
+
+/* One assignment step against fixed centres (Section 5, assignment
+ * equation), for every row.
+ *   centers          float[k*d] row-major, used as given (not rescaled).
+ *   assign_out       int32[n]; ties go to the lowest index.
+ *   best_sim_out     float[n] (nullable): <x(i), c(a(i))>.
+ *   second_sim_out   float[n] (nullable): largest similarity to any other
+ *                    centre (FP32 value; -inf when k = 1).
+ * Asynchronous: returns after enqueueing. */
+int skm_assign(const skm_matrix* X, int32_t k, const float* centers,
+               int32_t* assign_out, float* best_sim_out, float* second_sim_out,
+               void* workspace, size_t workspace_bytes, void* stream);
+
+const char* skm_status_string(int status);
+const char* skm_last_error(void);
+
+/* Version of this ABI (major * 10000 + minor * 100 + patch). */
+int skm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SKM_H_ */

@@ -66,6 +66,8 @@ def _load():
         for name in ("oracle_lower_unguarded", "oracle_upper_unguarded"):
             getattr(lib, name).restype = dbl
             getattr(lib, name).argtypes = [dbl, dbl]
+        lib.oracle_threads.restype = ctypes.c_int
+        lib.oracle_threads.argtypes = []
         lib.oracle_cc.restype = dbl
         lib.oracle_cc.argtypes = [dbl]
         lib.oracle_fit.restype = i32
@@ -150,6 +152,11 @@ def lower_unguarded(l, p):
 
 def upper_unguarded(u, p):
     return _load().oracle_upper_unguarded(u, p)
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's parallel loops use."""
+    return int(_load().oracle_threads())
 
 
 def cc(g):

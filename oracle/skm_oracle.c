@@ -57,11 +57,15 @@
  *            themselves, which rank centres the same way for a fixed row.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 
 #define DELTA 1e-10
+
+/* Threads the OpenMP loops of this library use. */
+int oracle_threads(void) { return omp_get_max_threads(); }
 
 enum { ORC_LLOYD = 0, ORC_ELKAN = 1, ORC_HAMERLY = 2, ORC_SIMP_ELKAN = 3,
        ORC_SIMP_HAMERLY = 4 };

@@ -1,0 +1,651 @@
+// Assignment-step kernels for gfx950 (wave64).
+//
+//  k_assign_csr  similarities of CSR rows against all k centres (Section 5,
+//                assignment equation; sparse-dense products as in Section 2),
+//                group top-2 reduction, FP64 re-decision of near ties, and in
+//                fit mode the bounds of Section 4; in Hamerly mode each row
+//                first runs the bound update and tests of Section 5.3 and is
+//                walked only when they fail.
+//  k_elkan       one Elkan step per row (Sections 5.1 and 5.2): Eq. (6) for
+//                l(i), guarded Eq. (7) for every u(i,j), the point test on
+//                s(a(i)) and the pair tests u(i,j) <= l(i) and
+//                cc(a(i),j) <= l(i), then the surviving similarities.
+//
+// Row mapping: a group of G lanes (4 <= G <= 64, G divides 64) owns one row;
+// lane g of the group owns the centres 4*(g + G*r) + q, q < 4, r < R, i.e.
+// float4 chunk (g + G*r) of each centre-minor CT row (kp = 4*G*R floats).
+// For every stored entry (t, x) of the row the group reads CT row t with
+// coalesced float4 loads and every lane advances its 4R accumulators with
+// one FMA each, so every similarity is a sequential FMA chain over the
+// row's stored entries in storage order (the same chain in every kernel).
+#include <float.h>
+#include <limits.h>
+
+#include "skm_device.h"
+#include "skm_internal.h"
+
+namespace skm {
+
+Geometry pick_geometry(int k) {
+  if (k <= 16) return {4, 1, 16};
+  if (k <= 32) return {8, 1, 32};
+  if (k <= 64) return {16, 1, 64};
+  if (k <= 128) return {32, 1, 128};
+  if (k <= 256) return {64, 1, 256};
+  if (k <= 512) return {64, 2, 512};
+  if (k <= 1024) return {64, 4, 1024};
+  if (k <= 2048) return {64, 8, 2048};
+  if (k <= 4096) return {64, 16, 4096};
+  return {0, 0, 0};
+}
+
+namespace {
+using namespace dev;
+
+__device__ __forceinline__ float f4get(const float4& f, int q) {
+  return q == 0 ? f.x : (q == 1 ? f.y : (q == 2 ? f.z : f.w));
+}
+
+__device__ __forceinline__ void f4set(float4& f, int q, float x) {
+  if (q == 0) f.x = x;
+  else if (q == 1) f.y = x;
+  else if (q == 2) f.z = x;
+  else f.w = x;
+}
+
+// Gathers in flight per lane and batch: enough independent float4 loads
+// to cover L2/MALL latency without exhausting registers.
+template <int G, int R>
+struct Batch {
+  static constexpr int raw = (R >= 8) ? 1 : (R >= 4 ? 2 : (R >= 2 ? 4 : 8));
+  static constexpr int U = raw < G ? raw : G;
+};
+
+// Accumulates the FP32 similarities of the row [beg, end) for the chunks
+// selected by `need` (bit r = chunk r).  Entries are handled G at a time
+// (one per lane, broadcast by shuffles) in batches of U: the U gathers of a
+// batch are issued before any of its FMAs, and the next G entries are
+// fetched while the current ones are consumed.  Entries past the end of the
+// row are padded with x = 0, which leaves every FMA chain unchanged, so
+// each similarity is still the sequential chain over the stored entries.
+// Returns the row's squared norm summed over the group (float).
+template <int G, int R, bool MASKED>
+__device__ __forceinline__ float row_sims(const int32_t* __restrict__ ci,
+                                          const float* __restrict__ v, int64_t beg,
+                                          int64_t end, const float4* __restrict__ CT4,
+                                          int kp4, int gl, unsigned need, float4 (&acc)[R]) {
+  constexpr int U = Batch<G, R>::U;
+#pragma unroll
+  for (int r = 0; r < R; ++r) acc[r] = make_float4(0.f, 0.f, 0.f, 0.f);
+  float nrm2 = 0.f;
+  int c = 0;
+  float x = 0.f;
+  if (beg + gl < end) {
+    c = ci[beg + gl];
+    x = v[beg + gl];
+  }
+  for (int64_t base = beg; base < end; base += G) {
+    const int cnt = (int)((end - base) < G ? (end - base) : G);
+    // prefetch the next G entries
+    int cn = 0;
+    float xn = 0.f;
+    const int64_t en = base + G + gl;
+    if (en < end) {
+      cn = ci[en];
+      xn = v[en];
+    }
+    nrm2 = fmaf(x, x, nrm2);
+    for (int q0 = 0; q0 < cnt; q0 += U) {
+      int cq[U];
+      float xq[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        cq[u] = __shfl(c, q0 + u, G);
+        xq[u] = __shfl(x, q0 + u, G);
+      }
+      float4 f[U][R];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const float4* p = CT4 + (uint32_t)((uint32_t)cq[u] * (uint32_t)kp4) + gl;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          if (!MASKED || ((need >> r) & 1u)) f[u][r] = p[r * G];
+          else f[u][r] = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          acc[r].x = fmaf(xq[u], f[u][r].x, acc[r].x);
+          acc[r].y = fmaf(xq[u], f[u][r].y, acc[r].y);
+          acc[r].z = fmaf(xq[u], f[u][r].z, acc[r].z);
+          acc[r].w = fmaf(xq[u], f[u][r].w, acc[r].w);
+        }
+    }
+    c = cn;
+    x = xn;
+  }
+  return group_sum<G>(nrm2);
+}
+
+// ------------------------------------------------------------------------
+// k_assign_csr
+// ------------------------------------------------------------------------
+// Hamerly mode prologue (Sections 5.3 / 5.4): Eq. (6) for l(i), the guarded
+// Eq. (7) with p'(a) = min_{j != a} p(j) (or Eq. (9)) for u(i), the tests
+// l >= u and l >= s(a), and the tightening of l(i).  Returns true when the
+// row needs no similarity walk; the bounds are then already stored.
+template <int G>
+__device__ __forceinline__ bool hamerly_prologue(const AssignArgs& A, int64_t row, int prev,
+                                                 int64_t beg, int64_t end, int gl,
+                                                 unsigned long long& tight,
+                                                 unsigned long long& saved) {
+  const int m = (int)(end - beg);
+  const double eta = (double)A.eta[row];
+  const double slack = 1.01 * (eta + A.delta_c);
+  const double rho32 = (double)(m + 3) * kU32 * (1.0 + eta) * 1.01 + slack + 1e-12;
+  // prune margin: keeps the FP64 re-decision of every pruned pair on the
+  // side the bounds prove
+  const double mu = 4.0 * (double)(m + 2) * kU64 * (1.0 + eta) + 4.0 * A.delta_c + 1e-15;
+  const MoveMin mm = *A.mm;
+  double ld = lower_upd((double)A.l[row], A.pc[prev], A.ps[prev]) - 4e-15;
+  const double pcx = (prev == mm.idx1) ? mm.pc2 : mm.pc1;
+  const double psx = (prev == mm.idx1) ? mm.ps2 : mm.ps1;
+  const double u0 = fmin(1.0, fmax(-1.0, (double)A.u[row]));
+  double ud;
+  if (A.bound_form == 1 && u0 >= 0.0 && pcx >= 0.0)
+    ud = u0 + sqrt((1.0 - u0) * (1.0 + u0)) * psx;  // Eq. (9)
+  else
+    ud = upper_upd(u0, pcx, psx);
+  ud = fmin(1.0, ud + 4e-15);
+  const double smax = A.simplified ? 2.0 : A.gmax[prev];
+  auto pruned = [&](double lcur) -> bool {
+    if (lcur - ud >= mu) return true;
+    const double M = lcur - mu;
+    return !A.simplified && lcur > 0.0 && M > 0.0 && smax <= cc_threshold(lcur, M) - 4e-15;
+  };
+  bool skip = pruned(ld);
+  if (!skip && A.try_tighten) {
+    const float s32 = group_col_dot32<G>(A.ci, A.v, beg, end, A.CT, A.kp, prev, gl);
+    ld = fmax(ld, (double)s32 - rho32);
+    if (gl == 0) tight += 1;
+    skip = pruned(ld);
+    if (skip && gl == 0) saved += 1;
+  }
+  if (skip && gl == 0) {
+    A.l[row] = __double2float_rd(fmax(ld, -1.0));
+    A.u[row] = __double2float_ru(ud);
+  }
+  return skip;
+}
+
+template <int G, int R, int MODE>
+__global__ __launch_bounds__(kBlock) void k_assign_csr(AssignArgs A) {
+  constexpr int GPB = kBlock / G;
+  const int gl = threadIdx.x & (G - 1);
+  const int gib = threadIdx.x / G;
+  __shared__ unsigned long long sh[6];
+  if (threadIdx.x < 6) sh[threadIdx.x] = 0;
+  __syncthreads();
+  unsigned long long my_rows = 0, my_rechecks = 0, my_nnz = 0, my_changed = 0, my_tight = 0,
+                     my_saved = 0;
+  const float4* CT4 = reinterpret_cast<const float4*>(A.CT);
+  const int kp4 = A.kp >> 2;
+  const int k = A.k;
+
+  for (int64_t row = (int64_t)blockIdx.x * GPB + gib; row < A.n_rows;
+       row += (int64_t)gridDim.x * GPB) {
+    const int64_t beg = A.rp[row], end = A.rp[row + 1];
+    const int m = (int)(end - beg);
+    const int prev = A.read_prev ? A.a[row] : -1;
+    if (MODE == kModeHamerly) {
+      if (hamerly_prologue<G>(A, row, prev, beg, end, gl, my_tight, my_saved)) continue;
+    }
+
+    float4 acc[R];
+    const float nrm2 = row_sims<G, R, false>(A.ci, A.v, beg, end, CT4, kp4, gl, ~0u, acc);
+
+    float b = -INFINITY, s2 = -INFINITY;
+    int bj = INT_MAX;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int j = 4 * (gl + G * r) + q;
+        if (j < k) {
+          const float sv = f4get(acc[r], q);
+          if (better32(sv, j, b, bj, prev)) {
+            s2 = fmaxf(s2, b);
+            b = sv;
+            bj = j;
+          } else {
+            s2 = fmaxf(s2, sv);
+          }
+        }
+      }
+    }
+    group_top2<G>(b, bj, s2, prev);
+
+    // rigorous bound on |fl32 sim - <x, c>| for any summation order: (m+1)
+    // roundings of the FMA chain plus the float rounding of the centre,
+    // scaled by |x| |c|
+    const double nx = sqrt((double)nrm2) * 1.01 + 1e-30;
+    const double eps = (double)(m + 3) * kU32 * nx;
+
+    bool rechecked = false;
+    double best64 = 0.0;
+    int abest = bj;
+    if (k > 1 && (double)b - (double)s2 <= 2.0 * eps) {
+      // 1e-12 below the band: the FP64 winner is a candidate whichever FP32
+      // summation order produced b
+      const double thr = (double)b - 2.0 * eps - 1e-12;
+      unsigned long long cm = 0ull;
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int j = 4 * (gl + G * r) + q;
+          if (j < k && (double)f4get(acc[r], q) >= thr) cm |= 1ull << (4 * r + q);
+        }
+      double cb = -INFINITY;
+      int cj = INT_MAX;
+      while (cm) {
+        const int bit = __builtin_ctzll(cm);
+        cm &= cm - 1ull;
+        const int j = 4 * (gl + G * (bit >> 2)) + (bit & 3);
+        const double sv = dot64(A.ci, A.v, beg, end, A.C64 + (size_t)j * A.d);
+        if (better64(sv, j, cb, cj, prev)) {
+          cb = sv;
+          cj = j;
+        }
+      }
+      group_best64<G>(cb, cj, prev);
+      abest = cj;
+      best64 = cb;
+      rechecked = true;
+    }
+
+    if (MODE == kModeAssign) {
+      if (gl == 0) {
+        A.a[row] = abest;
+        if (A.best_out) A.best_out[row] = rechecked ? (float)best64 : b;
+        if (A.second_out) A.second_out[row] = (rechecked && abest != bj) ? b : s2;
+      }
+    } else {
+      // bounds on true cosines (Section 4): l(i) <= cos(x, c_a),
+      // u(i) >= max_{j != a} cos(x, c_j)
+      const double eta = (double)A.eta[row];
+      const double slack = 1.01 * (eta + A.delta_c);
+      const double rho32 = eps + slack + 1e-12;
+      if (gl == 0) {
+        const double rho64 = (double)(m + 2) * kU64 * nx + slack + 1e-15;
+        A.a[row] = abest;
+        my_changed += (abest != prev) ? 1ull : 0ull;
+        if (A.l) {
+          const double lo = rechecked ? best64 - rho64 : (double)b - rho32;
+          A.l[row] = __double2float_rd(fmax(lo, -1.0));
+        }
+        if (A.u) {
+          const double hi = (k == 1) ? -1.0 : (rechecked ? (double)b : (double)s2) + rho32;
+          A.u[row] = __double2float_ru(fmin(hi, 1.0));
+        }
+      }
+      if (MODE == kModeFitElkanInit) {
+        float4* ue4 = reinterpret_cast<float4*>(A.ue + (size_t)row * A.kp);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          float4 o;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int j = 4 * (gl + G * r) + q;
+            const float val = (j < k) ? __double2float_ru(fmin((double)f4get(acc[r], q) + rho32, 1.0))
+                                      : 1.0f;
+            f4set(o, q, val);
+          }
+          ue4[gl + G * r] = o;
+        }
+      }
+    }
+    if (gl == 0) {
+      my_rows += 1;
+      my_nnz += (unsigned long long)m;
+      my_rechecks += rechecked ? 1 : 0;
+    }
+  }
+
+  if (A.cnt == nullptr) return;
+  if (my_rows) atomicAdd(&sh[0], my_rows);
+  if (my_nnz) atomicAdd(&sh[1], my_nnz);
+  if (my_rechecks) atomicAdd(&sh[2], my_rechecks);
+  if (my_changed) atomicAdd(&sh[3], my_changed);
+  if (my_tight) atomicAdd(&sh[4], my_tight);
+  if (my_saved) atomicAdd(&sh[5], my_saved);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    Counters* c = counter_slot(A.cnt);
+    if (sh[0]) {
+      atomicAdd(&c->sims, sh[0] * (unsigned long long)k + sh[4]);
+      atomicAdd(&c->rows_done, sh[0]);
+      atomicAdd(&c->nnz_done, sh[1]);
+    } else if (sh[4]) {
+      atomicAdd(&c->sims, sh[4]);
+    }
+    if (sh[2]) atomicAdd(&c->rechecks, sh[2]);
+    if (sh[3]) atomicAdd(&c->changed, sh[3]);
+    if (sh[4]) atomicAdd(&c->tightened, sh[4]);
+    if (sh[5]) atomicAdd(&c->tight_saved, sh[5]);
+  }
+}
+
+// ------------------------------------------------------------------------
+// k_elkan
+// ------------------------------------------------------------------------
+template <int R>
+__device__ __forceinline__ void set_slot(float4 (&acc)[R], int bit, float val) {
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (bit == 4 * r + q) f4set(acc[r], q, val);
+}
+
+template <int G, int R>
+__global__ __launch_bounds__(kBlock) void k_elkan(ElkanArgs A) {
+  constexpr int GPB = kBlock / G;
+  // 128-byte lines in one CT row: a row walk costs about this many lines per
+  // stored entry, one surviving pair about one
+  constexpr int kLines = (4 * G * R) / 32;
+  const int gl = threadIdx.x & (G - 1);
+  const int gib = threadIdx.x / G;
+  const int gbase = (int)(threadIdx.x & 63) & ~(G - 1);
+  const unsigned long long gmask = (G == 64) ? ~0ull : ((1ull << G) - 1ull);
+  __shared__ unsigned long long sh_sims, sh_tight, sh_rechecks, sh_rows, sh_nnz, sh_changed;
+  if (threadIdx.x == 0) {
+    sh_sims = 0;
+    sh_tight = 0;
+    sh_rechecks = 0;
+    sh_rows = 0;
+    sh_nnz = 0;
+    sh_changed = 0;
+  }
+  __syncthreads();
+  unsigned long long my_sims = 0, my_tight = 0, my_rechecks = 0, my_rows = 0, my_nnz = 0,
+                     my_changed = 0;
+  const float4* CT4 = reinterpret_cast<const float4*>(A.CT);
+  const int kp4 = A.kp >> 2;
+  const int k = A.k;
+
+  for (int64_t row = (int64_t)blockIdx.x * GPB + gib; row < A.n;
+       row += (int64_t)gridDim.x * GPB) {
+    const int64_t beg = A.rp[row], end = A.rp[row + 1];
+    const int m = (int)(end - beg);
+    const int prev = A.a[row];
+    const double eta = (double)A.eta[row];
+    const double slack = 1.01 * (eta + A.delta_c);
+    const double eps = (double)(m + 3) * kU32 * (1.0 + eta) * 1.01;
+    const double rho32 = eps + slack + 1e-12;
+    const double rho64 = (double)(m + 2) * kU64 * (1.0 + eta) * 1.01 + slack + 1e-15;
+    // prune margin: keeps the FP64 re-decision of every pruned pair on the
+    // side the bounds prove
+    const double mu = 4.0 * (double)(m + 2) * kU64 * (1.0 + eta) + 4.0 * A.delta_c + 1e-15;
+
+    // Eq. (6) for l(i), guarded Eq. (7) for every u(i, j)
+    double ld = lower_upd((double)A.l[row], A.pc[prev], A.ps[prev]) - 4e-15;
+    float4* ue4 = reinterpret_cast<float4*>(A.ue + (size_t)row * A.kp);
+    float4 uv[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      uv[r] = ue4[gl + G * r];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int j = 4 * (gl + G * r) + q;
+        if (j < k) {
+          const double nu = upper_upd((double)f4get(uv[r], q), A.pc[j], A.ps[j]) + 4e-15;
+          f4set(uv[r], q, __double2float_ru(fmin(nu, 1.0)));
+        }
+      }
+    }
+
+    const double* Grow = A.G + (size_t)prev * k;
+    auto alive_mask = [&](double lcur) -> unsigned long long {
+      const double M = lcur - mu;
+      const bool cc_ok = !A.simplified && lcur > 0.0 && M > 0.0;
+      const double T = cc_ok ? cc_threshold(lcur, M) - 4e-15 : -3.0;
+      if (cc_ok && A.gmax[prev] <= T) return 0ull;  // s(a) test: skip the point
+      unsigned long long mask = 0ull;
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int j = 4 * (gl + G * r) + q;
+          if (j < k && j != prev) {
+            const bool by_u = (lcur - (double)f4get(uv[r], q)) >= mu;   // u(i,j) <= l(i)
+            const bool by_cc = cc_ok && (Grow[j] + A.delta_g <= T);     // cc(a,j) <= l(i)
+            if (!by_u && !by_cc) mask |= 1ull << (4 * r + q);
+          }
+        }
+      return mask;
+    };
+
+    unsigned long long mask = alive_mask(ld);
+    int nalive = group_sum<G>((int)__popcll(mask));
+    int abest = prev;
+    if (nalive > 0) {
+      // tighten l(i) with one column of CT
+      const float sa = group_col_dot32<G>(A.ci, A.v, beg, end, A.CT, A.kp, prev, gl);
+      ld = fmax(ld, (double)sa - rho32);
+      if (gl == 0) my_tight += 1;
+      mask = alive_mask(ld);
+      nalive = group_sum<G>((int)__popcll(mask));
+      if (nalive > 0) {
+        int prev_bit = -1;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int rel = prev - 4 * (gl + G * r);
+          if (rel >= 0 && rel < 4) prev_bit = 4 * r + rel;
+        }
+        float4 acc[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] = make_float4(0.f, 0.f, 0.f, 0.f);
+        unsigned long long comp = mask;
+        if (nalive <= kLines) {
+          // few survivors: one column gather per surviving pair
+          unsigned long long my = mask;
+          for (int it = 0; it < nalive; ++it) {
+            const unsigned long long gb = (__ballot(my != 0ull) >> gbase) & gmask;
+            const int owner = __ffsll((long long)gb) - 1;
+            int bit = (gl == owner) ? (__ffsll((long long)my) - 1) : 0;
+            bit = __shfl(bit, owner, G);
+            const int j = 4 * (owner + G * (bit >> 2)) + (bit & 3);
+            const float sj = group_col_dot32<G>(A.ci, A.v, beg, end, A.CT, A.kp, j, gl);
+            if (gl == owner) {
+              set_slot<R>(acc, bit, sj);
+              my &= my - 1ull;
+            }
+          }
+          if (prev_bit >= 0) {
+            set_slot<R>(acc, prev_bit, sa);
+            comp |= 1ull << prev_bit;
+          }
+        } else {
+          // many survivors: walk the row once for the chunks that hold them
+          if (prev_bit >= 0) comp |= 1ull << prev_bit;
+          unsigned need = 0u;
+#pragma unroll
+          for (int r = 0; r < R; ++r)
+            if ((comp >> (4 * r)) & 0xFull) need |= 1u << r;
+          row_sims<G, R, true>(A.ci, A.v, beg, end, CT4, kp4, gl, need, acc);
+          if (gl == 0) {
+            my_rows += 1;
+            my_nnz += (unsigned long long)m;
+          }
+        }
+        my_sims += (unsigned long long)__builtin_popcountll(mask);
+
+        float b = -INFINITY, s2 = -INFINITY;
+        int bj = INT_MAX;
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int bit = 4 * r + q;
+            if ((comp >> bit) & 1ull) {
+              const int j = 4 * (gl + G * r) + q;
+              const float sv = f4get(acc[r], q);
+              if (better32(sv, j, b, bj, prev)) {
+                s2 = fmaxf(s2, b);
+                b = sv;
+                bj = j;
+              } else {
+                s2 = fmaxf(s2, sv);
+              }
+            }
+          }
+        group_top2<G>(b, bj, s2, prev);
+        abest = bj;
+        bool rechecked = false;
+        double lo;
+        if ((double)b - (double)s2 <= 2.0 * eps) {
+          const double thr = (double)b - 2.0 * eps - 1e-12;
+          double cb = -INFINITY;
+          int cj = INT_MAX;
+          unsigned long long cm = 0ull;
+#pragma unroll
+          for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int bit = 4 * r + q;
+              if (((comp >> bit) & 1ull) && (double)f4get(acc[r], q) >= thr) cm |= 1ull << bit;
+            }
+          while (cm) {
+            const int bit = __builtin_ctzll(cm);
+            cm &= cm - 1ull;
+            const int j = 4 * (gl + G * (bit >> 2)) + (bit & 3);
+            const double sv = dot64(A.ci, A.v, beg, end, A.C64 + (size_t)j * A.d);
+            if (better64(sv, j, cb, cj, prev)) {
+              cb = sv;
+              cj = j;
+            }
+          }
+          group_best64<G>(cb, cj, prev);
+          abest = cj;
+          rechecked = true;
+          lo = cb - rho64;
+        } else {
+          lo = (double)b - rho32;
+        }
+        ld = (abest == prev) ? fmax(ld, lo) : lo;
+        // computed similarities become exact upper bounds
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int bit = 4 * r + q;
+            if ((comp >> bit) & 1ull)
+              f4set(uv[r], q, __double2float_ru(fmin((double)f4get(acc[r], q) + rho32, 1.0)));
+          }
+        if (gl == 0 && rechecked) my_rechecks += 1;
+      }
+    }
+
+#pragma unroll
+    for (int r = 0; r < R; ++r) ue4[gl + G * r] = uv[r];
+    if (gl == 0) {
+      A.l[row] = __double2float_rd(fmax(ld, -1.0));
+      A.a[row] = abest;
+      my_changed += (abest != prev) ? 1ull : 0ull;
+    }
+  }
+
+  if (my_sims) atomicAdd(&sh_sims, my_sims);
+  if (my_tight) atomicAdd(&sh_tight, my_tight);
+  if (my_rechecks) atomicAdd(&sh_rechecks, my_rechecks);
+  if (my_rows) {
+    atomicAdd(&sh_rows, my_rows);
+    atomicAdd(&sh_nnz, my_nnz);
+  }
+  if (my_changed) atomicAdd(&sh_changed, my_changed);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    Counters* c = counter_slot(A.cnt);
+    if (sh_sims + sh_tight) atomicAdd(&c->sims, sh_sims + sh_tight);
+    if (sh_tight) atomicAdd(&c->tightened, sh_tight);
+    if (sh_rechecks) atomicAdd(&c->rechecks, sh_rechecks);
+    if (sh_changed) atomicAdd(&c->changed, sh_changed);
+    if (sh_rows) {
+      atomicAdd(&c->rows_done, sh_rows);
+      atomicAdd(&c->nnz_done, sh_nnz);
+    }
+  }
+}
+
+template <int MODE>
+hipError_t launch_assign_mode(const AssignArgs& A, hipStream_t s) {
+  const Geometry g = pick_geometry(A.k);
+  if (g.G == 0 || g.kp != A.kp) return hipErrorInvalidValue;
+  const int gpb = kBlock / g.G;
+  int64_t blocks = (A.n_rows + gpb - 1) / gpb;
+  if (blocks > kMaxGridBlocks) blocks = kMaxGridBlocks;
+  if (blocks < 1) blocks = 1;
+  const dim3 grid((unsigned)blocks), block(kBlock);
+#define SKM_CASE(GG, RR)                                                  \
+  case GG * 100 + RR:                                                     \
+    hipLaunchKernelGGL((k_assign_csr<GG, RR, MODE>), grid, block, 0, s, A); \
+    break;
+  switch (g.G * 100 + g.R) {
+    SKM_CASE(4, 1)
+    SKM_CASE(8, 1)
+    SKM_CASE(16, 1)
+    SKM_CASE(32, 1)
+    SKM_CASE(64, 1)
+    SKM_CASE(64, 2)
+    SKM_CASE(64, 4)
+    SKM_CASE(64, 8)
+    SKM_CASE(64, 16)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef SKM_CASE
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_assign(const AssignArgs& A, int mode, hipStream_t s) {
+  if (mode == kModeAssign) return launch_assign_mode<kModeAssign>(A, s);
+  if (mode == kModeFit) return launch_assign_mode<kModeFit>(A, s);
+  if (mode == kModeHamerly) return launch_assign_mode<kModeHamerly>(A, s);
+  return launch_assign_mode<kModeFitElkanInit>(A, s);
+}
+
+hipError_t launch_elkan(const ElkanArgs& A, hipStream_t s) {
+  const Geometry g = pick_geometry(A.k);
+  if (g.G == 0 || g.kp != A.kp) return hipErrorInvalidValue;
+  const int gpb = kBlock / g.G;
+  int64_t blocks = (A.n + gpb - 1) / gpb;
+  if (blocks > kMaxGridBlocks) blocks = kMaxGridBlocks;
+  if (blocks < 1) blocks = 1;
+  const dim3 grid((unsigned)blocks), block(kBlock);
+#define SKM_CASE(GG, RR)                                              \
+  case GG * 100 + RR:                                                 \
+    hipLaunchKernelGGL((k_elkan<GG, RR>), grid, block, 0, s, A);      \
+    break;
+  switch (g.G * 100 + g.R) {
+    SKM_CASE(4, 1)
+    SKM_CASE(8, 1)
+    SKM_CASE(16, 1)
+    SKM_CASE(32, 1)
+    SKM_CASE(64, 1)
+    SKM_CASE(64, 2)
+    SKM_CASE(64, 4)
+    SKM_CASE(64, 8)
+    SKM_CASE(64, 16)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef SKM_CASE
+  return hipGetLastError();
+}
+
+}  // namespace skm

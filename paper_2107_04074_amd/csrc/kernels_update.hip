@@ -1,0 +1,524 @@
+// Centre-step, movement, centre-centre and Hamerly kernels for gfx950.
+//
+//  k_row_eta           per-row bound on | |x(i)| - 1 | (rows are unit only
+//                      to float rounding; every bound accounts for it)
+//  k_init_centres      FP64 master centres from the initial rows, rescaled to
+//                      unit length
+//  k_transpose         FP64 k x d masters -> FP32 d x kp centre-minor copy
+//                      read by the similarity kernels (LDS-tiled transpose)
+//  k_update_scan       S(old) -= x(i), S(new) += x(i) for every row whose
+//                      assignment changed (Section 5, baseline optimisation
+//                      (iii): keep the unnormalised sums and update them on
+//                      reassignment) in 64-bit fixed point, so the sums do
+//                      not depend on the order of the atomics
+//  k_sumsq_partial     |S(j)|^2 over column chunks for every touched cluster
+//  k_normalize_move    c(j) = S(j)/|S(j)| and |c(j) - c'(j)|^2 partials
+//  k_centre_finalize   movement p(j) = <c(j), c'(j)> (Section 4) as the
+//                      cosine/sine of an upper bound of the movement angle,
+//                      the two largest movements (p' of Section 5.3) and the
+//                      objective sum_j |S(j)|
+//  k_gram_*            <c(j), c(j')> for the centre-centre tests of Sections
+//                      5.2 and 5.4 (split-K tiles, deterministic reduction)
+#include <float.h>
+#include <limits.h>
+
+#include "skm_device.h"
+#include "skm_internal.h"
+
+namespace skm {
+namespace {
+using namespace dev;
+
+template <typename T>
+__device__ __forceinline__ T block_sum(T x, T* sh) {
+  sh[threadIdx.x] = x;
+  __syncthreads();
+#pragma unroll
+  for (int s = kBlock / 2; s >= 1; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  const T r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(kBlock) void k_row_eta(const int64_t* __restrict__ rp,
+                                                    const float* __restrict__ v, int64_t n,
+                                                    float* __restrict__ eta,
+                                                    float* __restrict__ max_eta) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  float e32 = 0.f;
+  if (i < n) {
+    const int64_t beg = rp[i], end = rp[i + 1];
+    double ss = 0.0;
+    for (int64_t e = beg; e < end; ++e) ss = fma((double)v[e], (double)v[e], ss);
+    const double dev = fabs(sqrt(ss) - 1.0) + (double)(end - beg + 4) * kU64 * 2.0 + 1e-300;
+    e32 = __double2float_ru(dev);
+    eta[i] = e32;
+  }
+  if (max_eta) {
+    // non-negative floats order like their bit patterns
+    for (int off = 32; off >= 1; off >>= 1) e32 = fmaxf(e32, __shfl_xor(e32, off, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(reinterpret_cast<int*>(max_eta), __float_as_int(e32));
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_init_centres(const float* __restrict__ init,
+                                                         int64_t d, int normalize,
+                                                         double* __restrict__ C64,
+                                                         double* __restrict__ init_norm) {
+  __shared__ double sh[kBlock];
+  const int j = blockIdx.x;
+  const float* x = init + (size_t)j * d;
+  double ss = 0.0;
+  for (int64_t t = threadIdx.x; t < d; t += kBlock) ss = fma((double)x[t], (double)x[t], ss);
+  const double nrm = sqrt(block_sum(ss, sh));
+  if (threadIdx.x == 0 && init_norm) init_norm[j] = nrm;
+  const bool scale = normalize && nrm > 0.0;
+  double* c = C64 + (size_t)j * d;
+  for (int64_t t = threadIdx.x; t < d; t += kBlock) c[t] = scale ? (double)x[t] / nrm : (double)x[t];
+}
+
+// 64 x 64 tile transpose with float conversion.  Tiles whose 64 centres are
+// all clean are skipped (their FP32 copy is already current).
+__global__ __launch_bounds__(kBlock) void k_transpose(const double* __restrict__ C64, int32_t k,
+                                                      int64_t d, int32_t kp,
+                                                      const int32_t* __restrict__ dirty,
+                                                      float* __restrict__ CT) {
+  __shared__ float tile[64][65];
+  __shared__ int any;
+  const int64_t t0 = (int64_t)blockIdx.x * 64;
+  const int j0 = blockIdx.y * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 64 x 4
+  if (threadIdx.x == 0) any = 0;
+  __syncthreads();
+  if (dirty) {
+    if (threadIdx.x < 64 && j0 + (int)threadIdx.x < k && dirty[j0 + threadIdx.x]) any = 1;
+    __syncthreads();
+    if (!any) return;
+  }
+  for (int jj = ty; jj < 64; jj += 4) {
+    const int j = j0 + jj;
+    const int64_t t = t0 + tx;
+    tile[jj][tx] = (j < k && t < d) ? (float)C64[(size_t)j * d + t] : 0.f;
+  }
+  __syncthreads();
+  for (int tt = ty; tt < 64; tt += 4) {
+    const int64_t t = t0 + tt;
+    const int j = j0 + tx;
+    if (t < d && j < k) CT[(size_t)t * kp + j] = tile[tx][tt];
+  }
+}
+
+// Scans the assignment for rows that moved since the last centre step and
+// applies S(old) -= x(i), S(new) += x(i) for each of them; a_old starts at -1
+// so the first step adds every row.  Lanes test 64 rows at a time, then the
+// wave handles the moved rows one after another with one lane per stored
+// entry.
+__global__ __launch_bounds__(kBlock) void k_update_scan(
+    const int64_t* __restrict__ rp, const int32_t* __restrict__ ci, const float* __restrict__ v,
+    const int32_t* __restrict__ a, int32_t* __restrict__ a_old, int64_t n, int64_t d,
+    double fx, long long* __restrict__ S, int32_t* __restrict__ dirty) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wave0 = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63);
+  for (int64_t base = wave0; base < n; base += (int64_t)gridDim.x * kBlock) {
+    const int64_t i = base + lane;
+    int32_t nw = -1, old = -1;
+    if (i < n) {
+      nw = a[i];
+      old = a_old[i];
+    }
+    unsigned long long moved = __ballot(i < n && nw != old);
+    while (moved) {
+      const int src = __ffsll((long long)moved) - 1;
+      moved &= moved - 1ull;
+      const int64_t row = base + src;
+      const int32_t rn = __shfl(nw, src, 64);
+      const int32_t ro = __shfl(old, src, 64);
+      const int64_t beg = rp[row], end = rp[row + 1];
+      unsigned long long* Sn = reinterpret_cast<unsigned long long*>(S + (size_t)rn * d);
+      unsigned long long* So =
+          ro >= 0 ? reinterpret_cast<unsigned long long*>(S + (size_t)ro * d) : nullptr;
+      for (int64_t e = beg + lane; e < end; e += 64) {
+        const long long q = __double2ll_rn((double)v[e] * fx);
+        const int32_t c = ci[e];
+        atomicAdd(Sn + c, (unsigned long long)q);
+        if (So) atomicAdd(So + c, (unsigned long long)(-q));
+      }
+      if (lane == 0) {
+        dirty[rn] = 1;
+        if (ro >= 0) dirty[ro] = 1;
+      }
+    }
+    if (i < n && nw != old) a_old[i] = nw;
+  }
+}
+
+constexpr int kMoveChunk = 4096;
+
+// Partial sums of squares of S(j) over column chunks (dirty clusters only).
+__global__ __launch_bounds__(kBlock) void k_sumsq_partial(const long long* __restrict__ S,
+                                                          int64_t d, double fx_inv,
+                                                          const int32_t* __restrict__ dirty,
+                                                          double* __restrict__ part_sq,
+                                                          int nchunk) {
+  __shared__ double sh[kBlock];
+  const int j = blockIdx.y;
+  const int ch = blockIdx.x;
+  if (!dirty[j]) return;
+  const int64_t t0 = (int64_t)ch * kMoveChunk;
+  const int64_t t1 = (t0 + kMoveChunk < d) ? t0 + kMoveChunk : d;
+  const long long* s = S + (size_t)j * d;
+  double ss = 0.0;
+  for (int64_t t = t0 + threadIdx.x; t < t1; t += kBlock) {
+    const double x = (double)s[t] * fx_inv;
+    ss = fma(x, x, ss);
+  }
+  const double tot = block_sum(ss, sh);
+  if (threadIdx.x == 0) part_sq[(size_t)j * nchunk + ch] = tot;
+}
+
+__device__ __forceinline__ double chunk_norm(const double* __restrict__ part_sq, int j,
+                                             int nchunk) {
+  double ss = 0.0;
+  for (int q = 0; q < nchunk; ++q) ss += part_sq[(size_t)j * nchunk + q];
+  return sqrt(ss);
+}
+
+__global__ __launch_bounds__(kBlock) void k_normalize_move(
+    const long long* __restrict__ S, int64_t d, double fx_inv, const int32_t* __restrict__ dirty,
+    const double* __restrict__ part_sq, double* __restrict__ C64, double* __restrict__ part,
+    int nchunk) {
+  __shared__ double sh[kBlock];
+  const int j = blockIdx.y;
+  const int ch = blockIdx.x;
+  if (!dirty[j]) return;
+  const double nrm = chunk_norm(part_sq, j, nchunk);
+  const int64_t t0 = (int64_t)ch * kMoveChunk;
+  const int64_t t1 = (t0 + kMoveChunk < d) ? t0 + kMoveChunk : d;
+  double acc = 0.0;
+  if (nrm > 0.0) {
+    const long long* s = S + (size_t)j * d;
+    double* c = C64 + (size_t)j * d;
+    for (int64_t t = t0 + threadIdx.x; t < t1; t += kBlock) {
+      const double nv = ((double)s[t] * fx_inv) / nrm;
+      const double dd = nv - c[t];
+      acc = fma(dd, dd, acc);
+      c[t] = nv;
+    }
+  }
+  const double tot = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[(size_t)j * nchunk + ch] = tot;
+}
+
+struct MinPair {
+  double v;
+  int j;
+};
+
+__device__ __forceinline__ MinPair min_pair(MinPair a, MinPair b) {
+  if (b.v < a.v || (b.v == a.v && b.j < a.j)) return b;
+  return a;
+}
+
+// Single block.
+__global__ __launch_bounds__(kBlock) void k_centre_finalize(
+    int32_t k, int64_t d, const int32_t* __restrict__ dirty, double* __restrict__ norm64,
+    const double* __restrict__ part_sq, const double* __restrict__ part, int nchunk,
+    double delta_c, double* __restrict__ pc, double* __restrict__ ps, MoveMin* __restrict__ mm,
+    Persist* __restrict__ per) {
+  __shared__ double shd[kBlock];
+  __shared__ double shv[kBlock];
+  __shared__ int shj[kBlock];
+  double obj = 0.0;
+  MinPair best = {INFINITY, INT_MAX};
+  const double grow = 1.0 + (double)(d + 4) * kU64;
+  for (int j = threadIdx.x; j < k; j += kBlock) {
+    double c = 1.0, s = 0.0;
+    if (dirty[j]) norm64[j] = chunk_norm(part_sq, j, nchunk);
+    if (dirty[j] && norm64[j] > 0.0) {
+      double c2 = 0.0;
+      for (int q = 0; q < nchunk; ++q) c2 += part[(size_t)j * nchunk + q];
+      // chord |c - c'| between the stored FP64 vectors, widened for their
+      // norms deviating from 1; the angle 2 asin(h/2) bounds the movement
+      double h = sqrt(c2) * grow + 2.0 * delta_c + 1e-300;
+      if (h > 2.0) h = 2.0;
+      c = 1.0 - 0.5 * h * h;
+      s = h * sqrt(fmax(0.0, 1.0 - 0.25 * h * h));
+    }
+    pc[j] = c;
+    ps[j] = s;
+    obj += norm64[j];
+    best = min_pair(best, MinPair{c, j});
+  }
+  const double total = block_sum(obj, shd);
+  // smallest movement cosine
+  shv[threadIdx.x] = best.v;
+  shj[threadIdx.x] = best.j;
+  __syncthreads();
+  for (int st = kBlock / 2; st >= 1; st >>= 1) {
+    if ((int)threadIdx.x < st) {
+      MinPair r = min_pair(MinPair{shv[threadIdx.x], shj[threadIdx.x]},
+                           MinPair{shv[threadIdx.x + st], shj[threadIdx.x + st]});
+      shv[threadIdx.x] = r.v;
+      shj[threadIdx.x] = r.j;
+    }
+    __syncthreads();
+  }
+  const int j1 = shj[0];
+  __syncthreads();
+  MinPair second = {INFINITY, INT_MAX};
+  for (int j = threadIdx.x; j < k; j += kBlock)
+    if (j != j1) second = min_pair(second, MinPair{pc[j], j});
+  shv[threadIdx.x] = second.v;
+  shj[threadIdx.x] = second.j;
+  __syncthreads();
+  for (int st = kBlock / 2; st >= 1; st >>= 1) {
+    if ((int)threadIdx.x < st) {
+      MinPair r = min_pair(MinPair{shv[threadIdx.x], shj[threadIdx.x]},
+                           MinPair{shv[threadIdx.x + st], shj[threadIdx.x + st]});
+      shv[threadIdx.x] = r.v;
+      shj[threadIdx.x] = r.j;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const int j2 = shj[0];
+    MoveMin r;
+    r.idx1 = j1;
+    r.pc1 = pc[j1];
+    r.ps1 = ps[j1];
+    r.pc2 = (j2 < k) ? pc[j2] : 1.0;
+    r.ps2 = (j2 < k) ? ps[j2] : 0.0;
+    r.pad = 0;
+    *mm = r;
+    per->objective = total;
+  }
+}
+
+__global__ void k_clear_dirty(int32_t* dirty, int32_t k) {
+  const int j = blockIdx.x * kBlock + threadIdx.x;
+  if (j < k) dirty[j] = 0;
+}
+
+// Gram matrix of the FP64 centres, 64 x 64 output tiles (upper triangle of
+// tiles), split over d into slices; partials persist so that tiles of clean
+// centres need not be recomputed.
+__global__ __launch_bounds__(kBlock) void k_gram_partial(const double* __restrict__ C64,
+                                                         int32_t k, int64_t d,
+                                                         const int32_t* __restrict__ dirty,
+                                                         int force_all, double* __restrict__ part,
+                                                         int64_t slice_len,
+                                                         Persist* __restrict__ per) {
+  __shared__ double As[16][65];
+  __shared__ double Bs[16][65];
+  __shared__ int any;
+  const int nt = (k + 63) / 64;
+  int idx = blockIdx.x, ta = 0;
+  while (idx >= nt - ta) {
+    idx -= nt - ta;
+    ++ta;
+  }
+  const int tb = ta + idx;
+  const int a0 = ta * 64, b0 = tb * 64;
+  if (!force_all) {
+    if (threadIdx.x == 0) any = 0;
+    __syncthreads();
+    if (threadIdx.x < 64) {
+      const int ja = a0 + threadIdx.x, jb = b0 + threadIdx.x;
+      if ((ja < k && dirty[ja]) || (jb < k && dirty[jb])) any = 1;
+    }
+    __syncthreads();
+    if (!any) return;
+  }
+  const int s = blockIdx.y;
+  const int64_t tb0 = (int64_t)s * slice_len;
+  const int64_t te = (tb0 + slice_len < d) ? tb0 + slice_len : d;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  double acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[i][q] = 0.0;
+  for (int64_t t0 = tb0; t0 < te; t0 += 16) {
+    for (int e = threadIdx.x; e < 1024; e += kBlock) {
+      const int r = e >> 4, c = e & 15;
+      const int64_t t = t0 + c;
+      const int ja = a0 + r, jb = b0 + r;
+      As[c][r] = (ja < k && t < te) ? C64[(size_t)ja * d + t] : 0.0;
+      Bs[c][r] = (jb < k && t < te) ? C64[(size_t)jb * d + t] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        av[i] = As[c][ty * 4 + i];
+        bv[i] = Bs[c][tx * 4 + i];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[i][q] = fma(av[i], bv[q], acc[i][q]);
+    }
+    __syncthreads();
+  }
+  double* P = part + (size_t)s * k * k;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int ja = a0 + ty * 4 + i, jb = b0 + tx * 4 + q;
+      if (ja < k && jb < k) P[(size_t)ja * k + jb] = acc[i][q];
+    }
+  if (s == 0 && threadIdx.x == 0) {
+    unsigned long long pairs = 0;
+    for (int i = 0; i < 64; ++i) {
+      const int ja = a0 + i;
+      if (ja >= k) break;
+      const int lo = (ta == tb) ? ja + 1 : b0;
+      const int hi = (b0 + 64 < k) ? b0 + 64 : k;
+      if (hi > lo) pairs += (unsigned long long)(hi - lo);
+    }
+    atomicAdd(&per->ccsims, pairs);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_gram_finalize(const double* __restrict__ part,
+                                                          int32_t k, int nslice,
+                                                          double* __restrict__ G) {
+  const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t kk = (int64_t)k * k;
+  if (e >= kk) return;
+  const int a = (int)(e / k), b = (int)(e % k);
+  const int64_t src = ((a >> 6) <= (b >> 6)) ? e : (int64_t)b * k + a;
+  double g = 0.0;
+  for (int s = 0; s < nslice; ++s) g += part[(size_t)s * kk + src];
+  G[e] = g;
+}
+
+__global__ __launch_bounds__(kBlock) void k_gram_gmax(const double* __restrict__ G, int32_t k,
+                                                      double delta_g, double* __restrict__ gmax) {
+  __shared__ double sh[kBlock];
+  const int a = blockIdx.x;
+  double m = -INFINITY;
+  for (int b = threadIdx.x; b < k; b += kBlock)
+    if (b != a) m = fmax(m, G[(size_t)a * k + b]);
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int st = kBlock / 2; st >= 1; st >>= 1) {
+    if ((int)threadIdx.x < st) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + st]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) gmax[a] = (k > 1) ? fmin(1.0, sh[0] + delta_g) : -3.0;
+}
+
+__global__ void k_c64_to_f32(const double* __restrict__ in, int64_t count, float* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (e < count) out[e] = (float)in[e];
+}
+
+__global__ void k_fill_i32(int32_t* p, int64_t count, int32_t value) {
+  const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (e < count) p[e] = value;
+}
+
+unsigned blocks_for(int64_t count) {
+  int64_t b = (count + kBlock - 1) / kBlock;
+  return (unsigned)(b < 1 ? 1 : b);
+}
+
+}  // namespace
+
+hipError_t launch_row_eta(const int64_t* rp, const float* v, int64_t n, float* eta,
+                          float* max_eta, hipStream_t s) {
+  hipLaunchKernelGGL(k_row_eta, dim3(blocks_for(n)), dim3(kBlock), 0, s, rp, v, n, eta, max_eta);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_centres(const float* init, int32_t k, int64_t d, int normalize,
+                               double* C64, double* init_norm, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_centres, dim3(k), dim3(kBlock), 0, s, init, d, normalize, C64,
+                     init_norm);
+  return hipGetLastError();
+}
+
+hipError_t launch_transpose(const double* C64, int32_t k, int64_t d, int32_t kp,
+                            const int32_t* dirty, float* CT, hipStream_t s) {
+  const dim3 grid((unsigned)((d + 63) / 64), (unsigned)((k + 63) / 64));
+  hipLaunchKernelGGL(k_transpose, grid, dim3(kBlock), 0, s, C64, k, d, kp, dirty, CT);
+  return hipGetLastError();
+}
+
+hipError_t launch_update_scan(const int64_t* rp, const int32_t* ci, const float* v,
+                              const int32_t* a, int32_t* a_old, int64_t n, int64_t d,
+                              double fx_scale, long long* S, int32_t* dirty, hipStream_t s) {
+  int64_t blocks = (n + kBlock - 1) / kBlock;
+  if (blocks > kMaxGridBlocks) blocks = kMaxGridBlocks;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_update_scan, dim3((unsigned)blocks), dim3(kBlock), 0, s, rp, ci, v, a,
+                     a_old, n, d, fx_scale, S, dirty);
+  return hipGetLastError();
+}
+
+hipError_t launch_sumsq_partial(const long long* S, int32_t k, int64_t d, double fx_inv,
+                               const int32_t* dirty, double* part_sq, int nchunk, hipStream_t s) {
+  const dim3 grid((unsigned)nchunk, (unsigned)k);
+  hipLaunchKernelGGL(k_sumsq_partial, grid, dim3(kBlock), 0, s, S, d, fx_inv, dirty, part_sq,
+                     nchunk);
+  return hipGetLastError();
+}
+
+hipError_t launch_normalize_move(const long long* S, int32_t k, int64_t d, double fx_inv,
+                                 const int32_t* dirty, const double* part_sq, double* C64,
+                                 double* part, int nchunk, hipStream_t s) {
+  const dim3 grid((unsigned)nchunk, (unsigned)k);
+  hipLaunchKernelGGL(k_normalize_move, grid, dim3(kBlock), 0, s, S, d, fx_inv, dirty, part_sq,
+                     C64, part, nchunk);
+  return hipGetLastError();
+}
+
+hipError_t launch_centre_finalize(int32_t k, int64_t d, const int32_t* dirty, double* norm64,
+                                  const double* part_sq, const double* part, int nchunk,
+                                  double delta_c, double* pc, double* ps, MoveMin* mm,
+                                  Persist* per, hipStream_t s) {
+  hipLaunchKernelGGL(k_centre_finalize, dim3(1), dim3(kBlock), 0, s, k, d, dirty, norm64,
+                     part_sq, part, nchunk, delta_c, pc, ps, mm, per);
+  return hipGetLastError();
+}
+
+hipError_t launch_clear_dirty(int32_t* dirty, int32_t k, hipStream_t s) {
+  hipLaunchKernelGGL(k_clear_dirty, dim3(blocks_for(k)), dim3(kBlock), 0, s, dirty, k);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram(const double* C64, int32_t k, int64_t d, const int32_t* dirty,
+                       int force_all, double* part, int nslice, int64_t slice_len, double* G,
+                       double* gmax, double delta_g, Persist* per, hipStream_t s) {
+  const int nt = (k + 63) / 64;
+  const dim3 grid((unsigned)(nt * (nt + 1) / 2), (unsigned)nslice);
+  hipLaunchKernelGGL(k_gram_partial, grid, dim3(kBlock), 0, s, C64, k, d, dirty, force_all, part,
+                     slice_len, per);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_gram_finalize, dim3(blocks_for((int64_t)k * k)), dim3(kBlock), 0, s, part,
+                     k, nslice, G);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_gram_gmax, dim3(k), dim3(kBlock), 0, s, G, k, delta_g, gmax);
+  return hipGetLastError();
+}
+
+hipError_t launch_c64_to_f32(const double* C64, int64_t count, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_c64_to_f32, dim3(blocks_for(count)), dim3(kBlock), 0, s, C64, count, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t* p, int64_t count, int32_t value, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(count)), dim3(kBlock), 0, s, p, count, value);
+  return hipGetLastError();
+}
+
+}  // namespace skm

@@ -1,0 +1,552 @@
+// Host side of libskm: argument validation, workspace planning and the
+// iteration driver behind the C ABI declared in include/skm.h.
+//
+// One fit runs, per assignment step (Section 5 outline of the paper):
+//   step 1          exhaustive similarities for every row -> a, l, u
+//   later steps     Lloyd: exhaustive again; Hamerly: bound update + tests
+//                   (k_hamerly) then exhaustive similarities for the rows
+//                   that failed them; Elkan: k_elkan per row
+//   sync            read the changed count; stop when it is zero
+//   centre step     fixed-point sums of the changed rows, renormalisation,
+//                   movement p(j), FP32 transpose, centre-centre products
+//                   (Elkan and Hamerly only)
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <new>
+#include <string>
+
+#include "../../include/skm.h"
+#include "skm_internal.h"
+
+namespace skm {
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int status, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int status, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return status;
+}
+
+#define SKM_HIP(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t _e = (expr);                                                            \
+    if (_e != hipSuccess) {                                                            \
+      rc = fail(SKM_ERR_HIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(_e),    \
+                __FILE__, __LINE__);                                                   \
+      goto done;                                                                       \
+    }                                                                                  \
+  } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Plan {
+  int64_t n = 0, d = 0, nnz = 0;
+  int32_t k = 0, kp = 0;
+  int variant = 0;
+  bool bounds = false, elkan = false, gram = false;
+  int nchunk = 1, nslice = 1;
+  int64_t slice_len = 0;
+  // byte offsets into the workspace
+  size_t CT = 0, C64 = 0, S = 0, l = 0, u = 0, ue = 0, eta = 0, a_old = 0, norm64 = 0,
+         part = 0, part_sq = 0, pc = 0, ps = 0, dirty = 0, mm = 0, G = 0, gmax = 0, gpart = 0,
+         cnt = 0, per = 0, maxeta = 0, initnorm = 0, total = 0;
+};
+
+int check_matrix(const skm_matrix* X) {
+  if (!X) return fail(SKM_ERR_INVALID_ARG, "X is NULL");
+  if (X->n < 1 || X->d < 1) return fail(SKM_ERR_INVALID_ARG, "need n >= 1 and d >= 1");
+  if (X->n > INT32_MAX) return fail(SKM_ERR_INVALID_ARG, "n must fit in int32");
+  if (X->d > INT32_MAX) return fail(SKM_ERR_INVALID_ARG, "d must fit in int32");
+  if (X->fmt == SKM_CSR_F32) {
+    if (!X->row_ptr || (!X->col_idx && X->nnz > 0) || (!X->val && X->nnz > 0))
+      return fail(SKM_ERR_INVALID_ARG, "CSR arrays must not be NULL");
+    if (X->nnz < 0) return fail(SKM_ERR_INVALID_ARG, "nnz must be >= 0");
+    return SKM_OK;
+  }
+  if (X->fmt == SKM_DENSE_F32)
+    return fail(SKM_ERR_UNSUPPORTED, "dense input is not supported by this build");
+  return fail(SKM_ERR_INVALID_ARG, "unknown matrix format %d", (int)X->fmt);
+}
+
+int make_plan(const skm_matrix* X, int32_t k, int32_t variant, Plan* P) {
+  int rc = check_matrix(X);
+  if (rc != SKM_OK) return rc;
+  if (k < 1 || (int64_t)k > X->n) return fail(SKM_ERR_INVALID_ARG, "need 1 <= k <= n");
+  if (variant < SKM_LLOYD || variant > SKM_SIMP_HAMERLY)
+    return fail(SKM_ERR_INVALID_ARG, "unknown variant %d", (int)variant);
+  const Geometry g = pick_geometry(k);
+  if (g.G == 0) return fail(SKM_ERR_UNSUPPORTED, "k = %d exceeds the supported 4096", (int)k);
+  P->n = X->n;
+  P->d = X->d;
+  P->nnz = X->nnz;
+  P->k = k;
+  P->kp = g.kp;
+  P->variant = variant;
+  P->elkan = variant == SKM_ELKAN || variant == SKM_SIMP_ELKAN;
+  P->bounds = variant != SKM_LLOYD;
+  P->gram = variant == SKM_ELKAN || variant == SKM_HAMERLY;
+  P->nchunk = (int)((X->d + 4095) / 4096);
+  {
+    const int nt = (k + 63) / 64;
+    const int tiles = nt * (nt + 1) / 2;
+    int ns = (512 + tiles - 1) / tiles;
+    const int64_t max_ns = std::max<int64_t>(1, X->d / 256);
+    if (ns > max_ns) ns = (int)max_ns;
+    if (ns < 1) ns = 1;
+    int64_t len = (X->d + ns - 1) / ns;
+    len = (len + 15) / 16 * 16;
+    P->slice_len = len;
+    P->nslice = (int)((X->d + len - 1) / len);
+  }
+  size_t cur = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = cur;
+    cur += align256(bytes);
+    return o;
+  };
+  const size_t n = (size_t)X->n, d = (size_t)X->d, kk = (size_t)k;
+  P->CT = take(d * (size_t)g.kp * sizeof(float));
+  P->C64 = take(kk * d * sizeof(double));
+  P->S = take(kk * d * sizeof(long long));
+  P->eta = take(n * sizeof(float));
+  P->a_old = take(n * sizeof(int32_t));
+  if (P->bounds) {
+    P->l = take(n * sizeof(float));
+    if (!P->elkan) P->u = take(n * sizeof(float));
+  }
+  if (P->elkan) P->ue = take(n * (size_t)g.kp * sizeof(float));
+  P->norm64 = take(kk * sizeof(double));
+  P->part = take(kk * (size_t)P->nchunk * sizeof(double));
+  P->part_sq = take(kk * (size_t)P->nchunk * sizeof(double));
+  P->pc = take(kk * sizeof(double));
+  P->ps = take(kk * sizeof(double));
+  P->dirty = take(kk * sizeof(int32_t));
+  P->mm = take(sizeof(MoveMin));
+  if (P->gram) {
+    P->G = take(kk * kk * sizeof(double));
+    P->gmax = take(kk * sizeof(double));
+    P->gpart = take((size_t)P->nslice * kk * kk * sizeof(double));
+  }
+  // counter slots followed directly by the persistent block: one copy per
+  // step brings both to the host
+  P->cnt = take(kCounterSlots * sizeof(Counters) + sizeof(Persist));
+  P->per = P->cnt + kCounterSlots * sizeof(Counters);
+  P->maxeta = take(sizeof(float));
+  P->initnorm = take(kk * sizeof(double));
+  P->total = cur;
+  return SKM_OK;
+}
+
+template <typename T>
+T* at(void* base, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(base) + off);
+}
+
+// Pinned host mirror of the counter slots and the persistent block, one
+// per host thread.
+struct HostMirror {
+  Counters slots[kCounterSlots];
+  Persist per;
+};
+static_assert(sizeof(HostMirror) == kCounterSlots * sizeof(Counters) + sizeof(Persist),
+              "host mirror must match the device layout");
+
+HostMirror* host_mirror() {
+  thread_local HostMirror* h = nullptr;
+  if (!h) {
+    void* p = nullptr;
+    if (hipHostMalloc(&p, sizeof(HostMirror), hipHostMallocDefault) != hipSuccess) return nullptr;
+    h = static_cast<HostMirror*>(p);
+  }
+  return h;
+}
+
+Counters sum_slots(const HostMirror* h) {
+  Counters t{};
+  for (int i = 0; i < kCounterSlots; ++i) {
+    const Counters& c = h->slots[i];
+    t.changed += c.changed;
+    t.sims += c.sims;
+    t.rechecks += c.rechecks;
+    t.tightened += c.tightened;
+    t.tight_saved += c.tight_saved;
+    t.rows_done += c.rows_done;
+    t.nnz_done += c.nnz_done;
+  }
+  return t;
+}
+
+// Fixed-point scale for the member sums: |x_t| <= 1 (unit rows), so
+// |S_jt| <= n and n * 2^F stays below 2^61.
+double fixed_point_scale(int64_t n) {
+  int bits = 0;
+  while ((int64_t(1) << bits) <= n) ++bits;
+  return std::ldexp(1.0, 61 - bits);
+}
+
+}  // namespace
+}  // namespace skm
+
+using namespace skm;
+
+extern "C" {
+
+int skm_version(void) { return 10000; }
+
+const char* skm_status_string(int status) {
+  switch (status) {
+    case SKM_OK: return "ok";
+    case SKM_ERR_INVALID_ARG: return "invalid argument";
+    case SKM_ERR_NOT_NORMALIZED: return "input not normalised";
+    case SKM_ERR_OUT_OF_MEMORY: return "out of memory";
+    case SKM_ERR_HIP: return "HIP runtime error";
+    case SKM_ERR_UNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+  }
+}
+
+const char* skm_last_error(void) { return g_last_error.c_str(); }
+
+size_t skm_workspace_size(const skm_matrix* X, int32_t k, int32_t variant,
+                          const skm_options* opt) {
+  (void)opt;
+  Plan P;
+  if (make_plan(X, k, variant, &P) != SKM_OK) return 0;
+  return P.total;
+}
+
+size_t skm_assign_workspace_size(const skm_matrix* X, int32_t k) {
+  if (check_matrix(X) != SKM_OK) return 0;
+  if (k < 1) {
+    fail(SKM_ERR_INVALID_ARG, "need k >= 1");
+    return 0;
+  }
+  const Geometry g = pick_geometry(k);
+  if (g.G == 0) {
+    fail(SKM_ERR_UNSUPPORTED, "k = %d exceeds the supported 4096", (int)k);
+    return 0;
+  }
+  return align256((size_t)X->d * g.kp * sizeof(float)) +
+         align256((size_t)k * X->d * sizeof(double));
+}
+
+int skm_assign(const skm_matrix* X, int32_t k, const float* centers, int32_t* assign_out,
+               float* best_sim_out, float* second_sim_out, void* workspace,
+               size_t workspace_bytes, void* stream) {
+  g_last_error.clear();
+  int rc = check_matrix(X);
+  if (rc != SKM_OK) return rc;
+  if (k < 1) return fail(SKM_ERR_INVALID_ARG, "need k >= 1");
+  if (!centers || !assign_out) return fail(SKM_ERR_INVALID_ARG, "centers/assign_out NULL");
+  const Geometry g = pick_geometry(k);
+  if (g.G == 0) return fail(SKM_ERR_UNSUPPORTED, "k = %d exceeds the supported 4096", (int)k);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t need = skm_assign_workspace_size(X, k);
+  bool owned = false;
+  void* ws = workspace;
+  if (!ws) {
+    if (hipMallocAsync(&ws, need, s) != hipSuccess)
+      return fail(SKM_ERR_OUT_OF_MEMORY, "could not allocate %zu bytes of workspace", need);
+    owned = true;
+  } else if (workspace_bytes < need) {
+    return fail(SKM_ERR_OUT_OF_MEMORY, "workspace has %zu bytes, %zu needed", workspace_bytes,
+                need);
+  }
+  float* CT = at<float>(ws, 0);
+  double* C64 = at<double>(ws, align256((size_t)X->d * g.kp * sizeof(float)));
+  {
+    SKM_HIP(hipMemsetAsync(CT, 0, (size_t)X->d * g.kp * sizeof(float), s));
+    SKM_HIP(launch_init_centres(centers, k, X->d, 0, C64, nullptr, s));
+    SKM_HIP(launch_transpose(C64, k, X->d, g.kp, nullptr, CT, s));
+    AssignArgs A{};
+    A.rp = X->row_ptr;
+    A.ci = X->col_idx;
+    A.v = X->val;
+    A.CT = CT;
+    A.C64 = C64;
+    A.d = X->d;
+    A.k = k;
+    A.kp = g.kp;
+    A.n_rows = X->n;
+    A.a = assign_out;
+    A.read_prev = 0;
+    A.best_out = best_sim_out;
+    A.second_out = second_sim_out;
+    SKM_HIP(launch_assign(A, kModeAssign, s));
+  }
+done:
+  if (owned) (void)hipFreeAsync(ws, s);
+  return rc;
+}
+
+int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t variant,
+            int32_t max_iter, const skm_options* opt, void* workspace, size_t workspace_bytes,
+            int32_t* assign_out, float* centers_out, double* centers64_out, skm_stats* stats,
+            void* stream) {
+  g_last_error.clear();
+  Plan P;
+  int rc = make_plan(X, k, variant, &P);
+  if (rc != SKM_OK) return rc;
+  if (!init_centers || !assign_out) return fail(SKM_ERR_INVALID_ARG, "init/assign_out NULL");
+  if (max_iter < 1) return fail(SKM_ERR_INVALID_ARG, "need max_iter >= 1");
+  skm_options o{};
+  if (opt) o = *opt;
+  if (o.norm_tol <= 0.0) o.norm_tol = 1e-4;
+  if (o.bound_form != 0 && o.bound_form != 1)
+    return fail(SKM_ERR_INVALID_ARG, "bound_form must be 0 or 1");
+  if (o.precision != 0)
+    return fail(SKM_ERR_UNSUPPORTED, "bf16 precision needs dense input");
+  if (workspace && workspace_bytes < P.total)
+    return fail(SKM_ERR_OUT_OF_MEMORY, "workspace has %zu bytes, %zu needed", workspace_bytes,
+                P.total);
+  HostMirror* hm = host_mirror();
+  if (!hm) return fail(SKM_ERR_HIP, "could not allocate pinned host memory");
+
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  bool owned = false;
+  void* ws = workspace;
+  if (!ws) {
+    if (hipMallocAsync(&ws, P.total, s) != hipSuccess)
+      return fail(SKM_ERR_OUT_OF_MEMORY, "could not allocate %zu bytes of workspace", P.total);
+    owned = true;
+  } else if (workspace_bytes < P.total) {
+    return fail(SKM_ERR_OUT_OF_MEMORY, "workspace has %zu bytes, %zu needed", workspace_bytes,
+                P.total);
+  }
+
+  const int64_t n = P.n, d = P.d;
+  const double delta_c = (double)(d + 8) * kU64 * 1.01 + 1e-300;
+  const double delta_g = (double)(d + 2) * kU64 * 1.01 + 2.0 * delta_c + 1e-15;
+  const double fx = fixed_point_scale(n);
+  const double fx_inv = 1.0 / fx;
+
+  float* CT = at<float>(ws, P.CT);
+  double* C64 = at<double>(ws, P.C64);
+  long long* S = at<long long>(ws, P.S);
+  float* eta = at<float>(ws, P.eta);
+  int32_t* a_old = at<int32_t>(ws, P.a_old);
+  float* l = P.bounds ? at<float>(ws, P.l) : nullptr;
+  float* u = (P.bounds && !P.elkan) ? at<float>(ws, P.u) : nullptr;
+  float* ue = P.elkan ? at<float>(ws, P.ue) : nullptr;
+  double* norm64 = at<double>(ws, P.norm64);
+  double* part = at<double>(ws, P.part);
+  double* part_sq = at<double>(ws, P.part_sq);
+  double* pc = at<double>(ws, P.pc);
+  double* ps = at<double>(ws, P.ps);
+  int32_t* dirty = at<int32_t>(ws, P.dirty);
+  MoveMin* mm = at<MoveMin>(ws, P.mm);
+  double* G = P.gram ? at<double>(ws, P.G) : nullptr;
+  double* gmax = P.gram ? at<double>(ws, P.gmax) : nullptr;
+  double* gpart = P.gram ? at<double>(ws, P.gpart) : nullptr;
+  Counters* cnt = at<Counters>(ws, P.cnt);
+  Persist* per = at<Persist>(ws, P.per);
+  float* maxeta = at<float>(ws, P.maxeta);
+  double* initnorm = at<double>(ws, P.initnorm);
+
+  int32_t iterations = 0, converged = 0;
+  int64_t tot_sims = 0, tot_rechecks = 0, sk_launches = 0, sk_rows = 0, sk_nnz = 0;
+  double sk_ms = 0.0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  double objective = 0.0;
+  bool first_gram = true;
+  double tight_rate = 1.0;
+  {
+    if (o.profile) {
+      SKM_HIP(hipEventCreate(&ev0));
+      SKM_HIP(hipEventCreate(&ev1));
+    }
+    SKM_HIP(hipMemsetAsync(CT, 0, (size_t)d * P.kp * sizeof(float), s));
+    SKM_HIP(hipMemsetAsync(S, 0, (size_t)k * d * sizeof(long long), s));
+    SKM_HIP(hipMemsetAsync(per, 0, sizeof(Persist), s));
+    SKM_HIP(launch_fill_i32(a_old, n, -1, s));
+    SKM_HIP(hipMemsetAsync(dirty, 0, (size_t)k * sizeof(int32_t), s));
+    SKM_HIP(hipMemsetAsync(norm64, 0, (size_t)k * sizeof(double), s));
+    SKM_HIP(hipMemsetAsync(maxeta, 0, sizeof(float), s));
+    SKM_HIP(launch_row_eta(X->row_ptr, X->val, n, eta, maxeta, s));
+    SKM_HIP(launch_init_centres(init_centers, k, d, 1, C64, initnorm, s));
+    SKM_HIP(launch_transpose(C64, k, d, P.kp, nullptr, CT, s));
+    if (o.validate >= 1) {
+      double* hn = new (std::nothrow) double[k];
+      float hmax = 0.f;
+      if (!hn) {
+        rc = fail(SKM_ERR_OUT_OF_MEMORY, "host allocation failed");
+        goto done;
+      }
+      hipError_t e1 = hipMemcpyAsync(hn, initnorm, (size_t)k * sizeof(double),
+                                     hipMemcpyDeviceToHost, s);
+      hipError_t e2 = hipMemcpyAsync(&hmax, maxeta, sizeof(float), hipMemcpyDeviceToHost, s);
+      hipError_t e3 = hipStreamSynchronize(s);
+      if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+        delete[] hn;
+        rc = fail(SKM_ERR_HIP, "validation copy failed");
+        goto done;
+      }
+      int bad = -1;
+      for (int j = 0; j < k; ++j)
+        if (!(std::fabs(hn[j] - 1.0) <= o.norm_tol)) {
+          bad = j;
+          break;
+        }
+      const double badnorm = bad >= 0 ? hn[bad] : 0.0;
+      delete[] hn;
+      if (bad >= 0) {
+        rc = fail(SKM_ERR_NOT_NORMALIZED, "initial centre %d has norm %.9g", bad, badnorm);
+        goto done;
+      }
+      if (o.validate >= 2 && !((double)hmax <= o.norm_tol)) {
+        rc = fail(SKM_ERR_NOT_NORMALIZED, "a data row deviates from unit norm by %.3g", hmax);
+        goto done;
+      }
+    }
+
+    for (int32_t t = 0; t < max_iter; ++t) {
+      SKM_HIP(hipMemsetAsync(cnt, 0, kCounterSlots * sizeof(Counters), s));
+      const bool exhaustive = (t == 0) || variant == SKM_LLOYD;
+      if (ev0) SKM_HIP(hipEventRecord(ev0, s));
+      if (exhaustive || !P.elkan) {
+        AssignArgs A{};
+        A.rp = X->row_ptr;
+        A.ci = X->col_idx;
+        A.v = X->val;
+        A.CT = CT;
+        A.C64 = C64;
+        A.d = d;
+        A.k = k;
+        A.kp = P.kp;
+        A.n_rows = n;
+        A.a = assign_out;
+        A.read_prev = t > 0 ? 1 : 0;
+        A.l = l;
+        A.u = u;
+        A.ue = ue;
+        A.eta = eta;
+        A.delta_c = delta_c;
+        A.cnt = cnt;
+        A.pc = pc;
+        A.ps = ps;
+        A.mm = mm;
+        A.gmax = gmax;
+        A.simplified = variant == SKM_SIMP_HAMERLY;
+        A.bound_form = o.bound_form;
+        // tightening costs about one cache line per stored entry, a full
+        // row walk about kp/32; keep tightening while it prunes often enough
+        A.try_tighten = (t <= 2 || tight_rate >= 0.2 || t % 4 == 0) ? 1 : 0;
+        const int mode = exhaustive ? ((t == 0 && P.elkan) ? kModeFitElkanInit : kModeFit)
+                                    : kModeHamerly;
+        SKM_HIP(launch_assign(A, mode, s));
+      } else {
+        ElkanArgs E{};
+        E.rp = X->row_ptr;
+        E.ci = X->col_idx;
+        E.v = X->val;
+        E.CT = CT;
+        E.C64 = C64;
+        E.d = d;
+        E.k = k;
+        E.kp = P.kp;
+        E.n = n;
+        E.a = assign_out;
+        E.l = l;
+        E.ue = ue;
+        E.eta = eta;
+        E.pc = pc;
+        E.ps = ps;
+        E.G = G;
+        E.gmax = gmax;
+        E.delta_c = delta_c;
+        E.delta_g = delta_g;
+        E.simplified = variant == SKM_SIMP_ELKAN;
+        E.cnt = cnt;
+        SKM_HIP(launch_elkan(E, s));
+      }
+      if (ev1) SKM_HIP(hipEventRecord(ev1, s));
+      SKM_HIP(hipMemcpyAsync(hm, cnt, sizeof(HostMirror), hipMemcpyDeviceToHost, s));
+      SKM_HIP(hipStreamSynchronize(s));
+      const Counters tc = sum_slots(hm);
+      const int64_t changed = (int64_t)tc.changed;
+      if (ev0) {
+        float ms = 0.f;
+        SKM_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+        sk_ms += ms;
+      }
+      if (tc.tightened > 0) tight_rate = (double)tc.tight_saved / (double)tc.tightened;
+      sk_launches += 1;
+      sk_rows += (int64_t)tc.rows_done;
+      sk_nnz += (int64_t)tc.nnz_done;
+      tot_sims += (int64_t)tc.sims;
+      tot_rechecks += (int64_t)tc.rechecks;
+      if (t > 0) objective = hm->per.objective;
+      if (stats && t < stats->per_iter_len) {
+        if (stats->changed_per_iter) stats->changed_per_iter[t] = changed;
+        if (stats->sims_per_iter) stats->sims_per_iter[t] = (int64_t)tc.sims;
+        if (stats->objective_per_iter && t > 0 && t - 1 < stats->per_iter_len)
+          stats->objective_per_iter[t - 1] = hm->per.objective;
+      }
+      iterations = t + 1;
+      if (changed == 0) {
+        converged = 1;
+        break;
+      }
+      // centre step
+      SKM_HIP(launch_update_scan(X->row_ptr, X->col_idx, X->val, assign_out, a_old, n, d, fx, S,
+                                 dirty, s));
+      SKM_HIP(launch_sumsq_partial(S, k, d, fx_inv, dirty, part_sq, P.nchunk, s));
+      SKM_HIP(launch_normalize_move(S, k, d, fx_inv, dirty, part_sq, C64, part, P.nchunk, s));
+      SKM_HIP(launch_centre_finalize(k, d, dirty, norm64, part_sq, part, P.nchunk, delta_c, pc,
+                                     ps, mm, per, s));
+      SKM_HIP(launch_transpose(C64, k, d, P.kp, dirty, CT, s));
+      if (P.gram) {
+        SKM_HIP(launch_gram(C64, k, d, dirty, first_gram ? 1 : 0, gpart, P.nslice, P.slice_len,
+                            G, gmax, delta_g, per, s));
+        first_gram = false;
+      }
+      SKM_HIP(launch_clear_dirty(dirty, k, s));
+    }
+    // final objective (after the last update) and centre-centre count
+    SKM_HIP(hipMemcpyAsync(&hm->per, per, sizeof(Persist), hipMemcpyDeviceToHost, s));
+    if (centers_out) SKM_HIP(launch_c64_to_f32(C64, (int64_t)k * d, centers_out, s));
+    if (centers64_out)
+      SKM_HIP(hipMemcpyAsync(centers64_out, C64, (size_t)k * d * sizeof(double),
+                             hipMemcpyDeviceToDevice, s));
+    SKM_HIP(hipStreamSynchronize(s));
+    objective = hm->per.objective;
+    if (stats) {
+      stats->iterations = iterations;
+      stats->converged = converged;
+      stats->objective = objective;
+      stats->sims_point_center = tot_sims;
+      stats->sims_center_center = (int64_t)hm->per.ccsims;
+      stats->rechecks = tot_rechecks;
+      if (stats->objective_per_iter && iterations - 1 < stats->per_iter_len)
+        stats->objective_per_iter[iterations - 1] = objective;
+      stats->sim_kernel_launches = sk_launches;
+      stats->sim_kernel_rows = sk_rows;
+      stats->sim_kernel_nnz = sk_nnz;
+      stats->sim_kernel_ms = sk_ms;
+    }
+  }
+done:
+  if (ev0) (void)hipEventDestroy(ev0);
+  if (ev1) (void)hipEventDestroy(ev1);
+  if (owned) {
+    (void)hipFreeAsync(ws, s);
+    if (rc == SKM_OK) {
+      hipError_t e = hipStreamSynchronize(s);
+      if (e != hipSuccess) rc = fail(SKM_ERR_HIP, "final synchronise: %s", hipGetErrorString(e));
+    }
+  }
+  return rc;
+}
+
+}  // extern "C"

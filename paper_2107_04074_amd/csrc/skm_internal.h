@@ -1,0 +1,149 @@
+// Internal declarations shared by the kernel translation units and the
+// host driver of libskm.  Nothing here is part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace skm {
+
+// Unit roundoff of float and double.
+constexpr double kU32 = 5.9604644775390625e-08;   // 2^-24
+constexpr double kU64 = 1.1102230246251565e-16;   // 2^-53
+
+constexpr int kBlock = 256;       // threads per block for every kernel
+constexpr int kMaxGridBlocks = 2048;  // persistent grids: 8 blocks per CU
+
+// Per-step statistics.  Kernels add into slot (blockIdx.x % kCounterSlots)
+// so that no single address takes more than a few atomics; the host sums
+// the slots after each step and clears them before the next.
+constexpr int kCounterSlots = 64;
+struct Counters {                 // one 128-byte line
+  unsigned long long changed;     // rows whose assignment changed
+  unsigned long long sims;        // point-centre similarities evaluated
+  unsigned long long rechecks;    // rows re-decided in FP64
+  unsigned long long tightened;   // rows whose lower bound was recomputed
+  unsigned long long tight_saved; // tightenings that pruned the row
+  unsigned long long rows_done;   // rows walked by the similarity kernel
+  unsigned long long nnz_done;    // their stored entries
+  unsigned long long reserved[9];
+};
+
+// Values that persist across steps (written by single threads).
+struct Persist {
+  double objective;               // sum_j |S_j| after the last update
+  unsigned long long ccsims;      // centre-centre inner products (whole fit)
+  double pad[14];
+};
+
+__device__ __forceinline__ Counters* counter_slot(Counters* base) {
+  return base + (blockIdx.x % kCounterSlots);
+}
+
+// Smallest and second smallest movement cosine over all centres, with the
+// sine of the same (upper-bounded) movement angle.
+struct MoveMin {
+  double pc1, ps1, pc2, ps2;
+  int32_t idx1;
+  int32_t pad;
+};
+
+// Group geometry of the row kernels: G lanes per row, each lane owning R
+// float4 chunks of centres, so kp = 4 * G * R padded centres per CT row.
+struct Geometry {
+  int G, R, kp;
+};
+Geometry pick_geometry(int k);
+
+enum AssignMode {
+  kModeAssign = 0,        // skm_assign: a, best, second
+  kModeFit = 1,           // exhaustive step of a fit: a, l, u
+  kModeFitElkanInit = 2,  // first step of an Elkan fit: also u(i, j) for all j
+  kModeHamerly = 3        // Hamerly step: bound update and tests, walk if needed
+};
+
+struct AssignArgs {
+  const int64_t* rp;
+  const int32_t* ci;
+  const float* v;
+  const float* CT;      // d x kp float, centre-minor
+  const double* C64;    // k x d double, row-major
+  int64_t d;
+  int32_t k, kp;
+  int64_t n_rows;
+  int32_t* a;                 // prev (read when read_prev) and new assignment
+  int32_t read_prev;
+  // assign mode
+  float* best_out;
+  float* second_out;
+  // fit modes
+  float* l;
+  float* u;
+  float* ue;                  // Elkan upper bounds n x kp (init mode)
+  const float* eta;           // per-row bound on | |x| - 1 |
+  double delta_c;             // bound on | |c| - 1 | of the FP64 centres
+  Counters* cnt;              // kCounterSlots slots (nullable in assign mode)
+  // Hamerly mode
+  const double* pc;
+  const double* ps;
+  const MoveMin* mm;
+  const double* gmax;         // per centre max_{j != a} <c_a, c_j> + delta_G
+  int32_t simplified;
+  int32_t bound_form;
+  int32_t try_tighten;
+};
+
+struct ElkanArgs {
+  const int64_t* rp;
+  const int32_t* ci;
+  const float* v;
+  const float* CT;
+  const double* C64;
+  int64_t d;
+  int32_t k, kp;
+  int64_t n;
+  int32_t* a;
+  float* l;
+  float* ue;
+  const float* eta;
+  const double* pc;
+  const double* ps;
+  const double* G;      // k x k centre inner products
+  const double* gmax;   // per centre max_{j != a} G + delta_G
+  double delta_c, delta_g;
+  int32_t simplified;
+  Counters* cnt;
+};
+
+// ---- launchers (kernels_assign.hip) ----
+hipError_t launch_assign(const AssignArgs& A, int mode, hipStream_t s);
+hipError_t launch_elkan(const ElkanArgs& A, hipStream_t s);
+
+// ---- launchers (kernels_update.hip) ----
+hipError_t launch_row_eta(const int64_t* rp, const float* v, int64_t n, float* eta,
+                          float* max_eta, hipStream_t s);
+hipError_t launch_init_centres(const float* init, int32_t k, int64_t d, int normalize,
+                               double* C64, double* init_norm, hipStream_t s);
+hipError_t launch_transpose(const double* C64, int32_t k, int64_t d, int32_t kp,
+                            const int32_t* dirty, float* CT, hipStream_t s);
+hipError_t launch_update_scan(const int64_t* rp, const int32_t* ci, const float* v,
+                              const int32_t* a, int32_t* a_old, int64_t n, int64_t d,
+                              double fx_scale, long long* S, int32_t* dirty, hipStream_t s);
+hipError_t launch_sumsq_partial(const long long* S, int32_t k, int64_t d, double fx_inv,
+                               const int32_t* dirty, double* part_sq, int nchunk, hipStream_t s);
+hipError_t launch_normalize_move(const long long* S, int32_t k, int64_t d, double fx_inv,
+                                 const int32_t* dirty, const double* part_sq, double* C64,
+                                 double* part, int nchunk, hipStream_t s);
+hipError_t launch_centre_finalize(int32_t k, int64_t d, const int32_t* dirty, double* norm64,
+                                  const double* part_sq, const double* part, int nchunk,
+                                  double delta_c, double* pc, double* ps, MoveMin* mm,
+                                  Persist* per, hipStream_t s);
+hipError_t launch_clear_dirty(int32_t* dirty, int32_t k, hipStream_t s);
+hipError_t launch_gram(const double* C64, int32_t k, int64_t d, const int32_t* dirty,
+                       int force_all, double* part, int nslice, int64_t slice_len,
+                       double* G, double* gmax, double delta_g, Persist* per,
+                       hipStream_t s);
+hipError_t launch_c64_to_f32(const double* C64, int64_t count, float* out, hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, int64_t count, int32_t value, hipStream_t s);
+
+}  // namespace skm

@@ -1,0 +1,233 @@
+"""ctypes binding of libskm (include/skm.h).
+
+Argument marshalling only: every step of the clustering runs in the HIP
+library.  Device memory comes from torch tensors on a ROCm device and work is
+enqueued on torch's current stream.  There is no fallback: without the built
+library every entry point raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "libskm.so")
+
+LLOYD, ELKAN, HAMERLY, SIMP_ELKAN, SIMP_HAMERLY = 0, 1, 2, 3, 4
+VARIANTS = {"lloyd": LLOYD, "elkan": ELKAN, "hamerly": HAMERLY,
+            "simp_elkan": SIMP_ELKAN, "simp_hamerly": SIMP_HAMERLY}
+CSR_F32, DENSE_F32 = 0, 1
+OK, ERR_INVALID_ARG, ERR_NOT_NORMALIZED, ERR_OUT_OF_MEMORY, ERR_HIP, ERR_UNSUPPORTED = range(6)
+
+# Every symbol include/skm.h declares.
+EXPORTS = ("skm_workspace_size", "skm_assign_workspace_size", "skm_fit", "skm_assign",
+           "skm_status_string", "skm_last_error", "skm_version")
+
+
+class SkmMatrix(ctypes.Structure):
+    _fields_ = [("fmt", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("n", ctypes.c_int64), ("d", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p),
+                ("val", ctypes.c_void_p), ("dense", ctypes.c_void_p), ("ld", ctypes.c_int64)]
+
+
+class SkmOptions(ctypes.Structure):
+    _fields_ = [("bound_form", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("validate", ctypes.c_int32), ("profile", ctypes.c_int32),
+                ("norm_tol", ctypes.c_double)]
+
+
+class SkmStats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("objective", ctypes.c_double), ("sims_point_center", ctypes.c_int64),
+                ("sims_center_center", ctypes.c_int64), ("rechecks", ctypes.c_int64),
+                ("changed_per_iter", ctypes.c_void_p), ("sims_per_iter", ctypes.c_void_p),
+                ("objective_per_iter", ctypes.c_void_p), ("per_iter_len", ctypes.c_int32),
+                ("reserved0", ctypes.c_int32), ("sim_kernel_launches", ctypes.c_int64),
+                ("sim_kernel_rows", ctypes.c_int64), ("sim_kernel_nnz", ctypes.c_int64),
+                ("sim_kernel_ms", ctypes.c_double)]
+
+
+class SkmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("skm status %d: %s" % (status, msg))
+        self.status = status
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Loads libskm.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libskm.so not built (expected at %s); run "
+                           "`python -m paper_2107_04074_amd.build`" % path)
+    lib = ctypes.CDLL(path)
+    p, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    lib.skm_workspace_size.restype = sz
+    lib.skm_workspace_size.argtypes = [ctypes.POINTER(SkmMatrix), i32, i32,
+                                       ctypes.POINTER(SkmOptions)]
+    lib.skm_assign_workspace_size.restype = sz
+    lib.skm_assign_workspace_size.argtypes = [ctypes.POINTER(SkmMatrix), i32]
+    lib.skm_fit.restype = ctypes.c_int
+    lib.skm_fit.argtypes = [ctypes.POINTER(SkmMatrix), i32, p, i32, i32,
+                            ctypes.POINTER(SkmOptions), p, sz, p, p, p,
+                            ctypes.POINTER(SkmStats), p]
+    lib.skm_assign.restype = ctypes.c_int
+    lib.skm_assign.argtypes = [ctypes.POINTER(SkmMatrix), i32, p, p, p, p, p, sz, p]
+    lib.skm_status_string.restype = ctypes.c_char_p
+    lib.skm_status_string.argtypes = [ctypes.c_int]
+    lib.skm_last_error.restype = ctypes.c_char_p
+    lib.skm_last_error.argtypes = []
+    lib.skm_version.restype = ctypes.c_int
+    lib.skm_version.argtypes = []
+    _ = i64
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != OK:
+        raise SkmError(status, load().skm_last_error().decode(errors="replace"))
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _stream():
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+@dataclass
+class DeviceCSR:
+    """CSR matrix resident on the GPU (torch tensors)."""
+    n: int
+    d: int
+    row_ptr: "object"  # torch.int64 [n+1]
+    col: "object"      # torch.int32 [nnz]
+    val: "object"      # torch.float32 [nnz]
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col.numel())
+
+    @staticmethod
+    def from_host(X, device="cuda") -> "DeviceCSR":
+        """From any object with n, d, row_ptr, col, val (numpy)."""
+        import torch
+        return DeviceCSR(int(X.n), int(X.d),
+                         torch.from_numpy(np.ascontiguousarray(X.row_ptr, np.int64)).to(device),
+                         torch.from_numpy(np.ascontiguousarray(X.col, np.int32)).to(device),
+                         torch.from_numpy(np.ascontiguousarray(X.val, np.float32)).to(device))
+
+    def matrix(self) -> SkmMatrix:
+        return SkmMatrix(CSR_F32, 0, self.n, self.d, self.nnz, _ptr(self.row_ptr),
+                         _ptr(self.col), _ptr(self.val), None, 0)
+
+
+@dataclass
+class FitStats:
+    iterations: int
+    converged: bool
+    objective: float
+    sims_point_center: int
+    sims_center_center: int
+    rechecks: int
+    sim_kernel_launches: int = 0
+    sim_kernel_rows: int = 0
+    sim_kernel_nnz: int = 0
+    sim_kernel_ms: float = 0.0
+    changed_per_iter: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int64))
+    sims_per_iter: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int64))
+    objective_per_iter: np.ndarray = field(default_factory=lambda: np.zeros(0))
+
+
+def _options(bound_form=0, precision=0, validate=0, norm_tol=0.0, profile=0):
+    return SkmOptions(bound_form, precision, validate, profile, norm_tol)
+
+
+def workspace_size(X: DeviceCSR, k: int, variant="hamerly", **opts) -> int:
+    lib = load()
+    v = VARIANTS[variant] if isinstance(variant, str) else int(variant)
+    m = X.matrix()
+    o = _options(**opts)
+    size = lib.skm_workspace_size(ctypes.byref(m), k, v, ctypes.byref(o))
+    if size == 0:
+        raise SkmError(ERR_INVALID_ARG, lib.skm_last_error().decode(errors="replace"))
+    return int(size)
+
+
+def fit(X: DeviceCSR, k: int, init_centers, variant="hamerly", max_iter: int = 100,
+        workspace=None, want_centers=True, want_centers64=False, per_iter=True, **opts):
+    """Runs skm_fit.  init_centers: float32 (k, d) device tensor.
+    Returns (assign int32 tensor, centers float32 or None, centers64 or None,
+    FitStats)."""
+    import torch
+    lib = load()
+    v = VARIANTS[variant] if isinstance(variant, str) else int(variant)
+    dev = X.col.device
+    m = X.matrix()
+    o = _options(**opts)
+    if workspace is None:
+        size = lib.skm_workspace_size(ctypes.byref(m), k, v, ctypes.byref(o))
+        if size == 0:
+            raise SkmError(ERR_INVALID_ARG, lib.skm_last_error().decode(errors="replace"))
+        workspace = torch.empty(size, dtype=torch.uint8, device=dev)
+    assign = torch.empty(X.n, dtype=torch.int32, device=dev)
+    centers = torch.empty((k, X.d), dtype=torch.float32, device=dev) if want_centers else None
+    centers64 = torch.empty((k, X.d), dtype=torch.float64, device=dev) if want_centers64 else None
+    init = init_centers.contiguous()
+    st = SkmStats()
+    ch = sm = ob = None
+    if per_iter:
+        ch = np.zeros(max_iter, np.int64)
+        sm = np.zeros(max_iter, np.int64)
+        ob = np.zeros(max_iter, np.float64)
+        st.changed_per_iter = ch.ctypes.data
+        st.sims_per_iter = sm.ctypes.data
+        st.objective_per_iter = ob.ctypes.data
+        st.per_iter_len = max_iter
+    _check(lib.skm_fit(ctypes.byref(m), k, _ptr(init), v, max_iter, ctypes.byref(o),
+                       _ptr(workspace), workspace.numel(), _ptr(assign), _ptr(centers),
+                       _ptr(centers64), ctypes.byref(st), _stream()))
+    it = st.iterations
+    stats = FitStats(it, bool(st.converged), st.objective, st.sims_point_center,
+                     st.sims_center_center, st.rechecks, st.sim_kernel_launches,
+                     st.sim_kernel_rows, st.sim_kernel_nnz, st.sim_kernel_ms)
+    if per_iter:
+        stats.changed_per_iter = ch[:it].copy()
+        stats.sims_per_iter = sm[:it].copy()
+        stats.objective_per_iter = ob[:it].copy()
+    return assign, centers, centers64, stats
+
+
+def assign(X: DeviceCSR, centers, workspace=None, want_second=True):
+    """Runs skm_assign against fixed float32 (k, d) centres.  Returns
+    (assign, best, second) device tensors; asynchronous on the current
+    stream."""
+    import torch
+    lib = load()
+    dev = X.col.device
+    k = int(centers.shape[0])
+    m = X.matrix()
+    if workspace is None:
+        size = lib.skm_assign_workspace_size(ctypes.byref(m), k)
+        if size == 0:
+            raise SkmError(ERR_INVALID_ARG, lib.skm_last_error().decode(errors="replace"))
+        workspace = torch.empty(size, dtype=torch.uint8, device=dev)
+    a = torch.empty(X.n, dtype=torch.int32, device=dev)
+    best = torch.empty(X.n, dtype=torch.float32, device=dev)
+    second = torch.empty(X.n, dtype=torch.float32, device=dev) if want_second else None
+    c = centers.contiguous()
+    _check(lib.skm_assign(ctypes.byref(m), k, _ptr(c), _ptr(a), _ptr(best), _ptr(second),
+                          _ptr(workspace), workspace.numel(), _stream()))
+    return a, best, second

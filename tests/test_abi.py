@@ -1,0 +1,122 @@
+"""Host-side checks of the C ABI: the library loads, exports every symbol the
+header declares, and rejects invalid arguments before touching a GPU."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2107_04074_amd import skm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "skm.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(skm.LIB_PATH):
+        from paper_2107_04074_amd import build
+        build.build()
+    return skm.load()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(skm_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_binding_exports():
+    assert declared_functions() == sorted(skm.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol(lib):
+    out = subprocess.run(["nm", "-D", "--defined-only", skm.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (skm_[a-z0-9_]+)$", out, flags=re.M))
+    for name in declared_functions():
+        assert name in exported, name
+        assert getattr(lib, name) is not None
+
+
+def test_header_compiles_as_c(tmp_path):
+    src = tmp_path / "t.c"
+    src.write_text('#include "skm.h"\nint main(void){skm_stats s; (void)s; '
+                   'return skm_version() > 0 ? 0 : 1;}\n')
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-fsyntax-only", "-I",
+                    os.path.join(ROOT, "include"), str(src)], check=True)
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """The ctypes mirrors of the structs have the header's sizes/offsets."""
+    src = tmp_path / "l.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "skm.h"\n'
+                   'int main(void){printf("%zu %zu %zu %zu %zu\\n", sizeof(skm_matrix), '
+                   'sizeof(skm_options), sizeof(skm_stats), offsetof(skm_stats, per_iter_len), '
+                   'offsetof(skm_matrix, ld)); return 0;}\n')
+    exe = tmp_path / "l"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    vals = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True,
+                                           check=True).stdout.split()]
+    assert vals == [ctypes.sizeof(skm.SkmMatrix), ctypes.sizeof(skm.SkmOptions),
+                    ctypes.sizeof(skm.SkmStats), skm.SkmStats.per_iter_len.offset,
+                    skm.SkmMatrix.ld.offset]
+
+
+def _fake_csr(n=10, d=20, nnz=30):
+    # host pointers that are never dereferenced by the validation paths
+    return skm.SkmMatrix(skm.CSR_F32, 0, n, d, nnz, 0x1000, 0x2000, 0x3000, None, 0)
+
+
+def test_invalid_arguments_are_rejected(lib):
+    m = _fake_csr()
+    o = skm.SkmOptions()
+    st = skm.SkmStats()
+    # k out of range
+    assert lib.skm_workspace_size(ctypes.byref(m), 0, 0, None) == 0
+    assert b"k" in lib.skm_last_error()
+    assert lib.skm_workspace_size(ctypes.byref(m), 11, 0, None) == 0
+    # bad variant
+    assert lib.skm_workspace_size(ctypes.byref(m), 3, 9, None) == 0
+    assert b"variant" in lib.skm_last_error()
+    # valid request has a positive size that grows with the variant's state
+    lloyd = lib.skm_workspace_size(ctypes.byref(m), 3, skm.LLOYD, ctypes.byref(o))
+    ham = lib.skm_workspace_size(ctypes.byref(m), 3, skm.HAMERLY, ctypes.byref(o))
+    elk = lib.skm_workspace_size(ctypes.byref(m), 3, skm.ELKAN, ctypes.byref(o))
+    assert 0 < lloyd < ham and lloyd < elk
+    # fit: NULL init, max_iter 0, bad bound_form: rejected before any GPU call
+    rc = lib.skm_fit(ctypes.byref(m), 3, None, 0, 5, None, None, 0, 0x4000, None, None,
+                     ctypes.byref(st), None)
+    assert rc == skm.ERR_INVALID_ARG
+    rc = lib.skm_fit(ctypes.byref(m), 3, 0x5000, 0, 0, None, None, 0, 0x4000, None, None,
+                     ctypes.byref(st), None)
+    assert rc == skm.ERR_INVALID_ARG and b"max_iter" in lib.skm_last_error()
+    bad = skm.SkmOptions(7, 0, 0, 0, 0.0)
+    rc = lib.skm_fit(ctypes.byref(m), 3, 0x5000, 0, 5, ctypes.byref(bad), None, 0, 0x4000,
+                     None, None, ctypes.byref(st), None)
+    assert rc == skm.ERR_INVALID_ARG
+    # undersized caller workspace
+    rc = lib.skm_fit(ctypes.byref(m), 3, 0x5000, 0, 5, None, 0x6000, 16, 0x4000, None, None,
+                     ctypes.byref(st), None)
+    assert rc == skm.ERR_OUT_OF_MEMORY
+    # empty / unknown formats
+    m0 = _fake_csr(n=0)
+    assert lib.skm_workspace_size(ctypes.byref(m0), 1, 0, None) == 0
+    md = skm.SkmMatrix(skm.DENSE_F32, 0, 10, 20, 0, None, None, None, 0x1000, 20)
+    m9 = skm.SkmMatrix(9, 0, 10, 20, 0, None, None, None, None, 0)
+    assert lib.skm_workspace_size(ctypes.byref(m9), 2, 0, None) == 0
+    assert b"format" in lib.skm_last_error()
+    del md
+    # k beyond the largest supported geometry
+    big = _fake_csr(n=10000)
+    assert lib.skm_workspace_size(ctypes.byref(big), 5000, 0, None) == 0
+    assert lib.skm_status_string(skm.ERR_UNSUPPORTED) == b"unsupported"
+
+
+def test_product_path_refuses_without_library(monkeypatch, tmp_path):
+    """The binding never falls back to CPU code: a missing library raises."""
+    monkeypatch.setattr(skm, "_lib", None)
+    with pytest.raises(RuntimeError):
+        skm.load(str(tmp_path / "missing.so"))

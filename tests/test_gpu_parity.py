@@ -1,0 +1,255 @@
+"""GPU parity: libskm (through the C ABI) against the FP64 oracle.
+
+Bar: assignments identical wherever the oracle's top-1/top-2 similarity gap
+exceeds 1e-5 (the FP64 re-decision makes them identical far below that; the
+number of points inside the band is reported), centres within 1e-6
+(Euclidean, unit vectors), objective within 1e-6 relative.  Bounded variants
+must reproduce the GPU Lloyd trajectory bit for bit."""
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+GAP = 1e-5
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    return torch
+
+
+@pytest.fixture(scope="module")
+def skm(torch_cuda):
+    from paper_2107_04074_amd import skm as s
+    s.load()
+    return s
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def gap_of(S):
+    if S.shape[1] == 1:
+        return np.full(S.shape[0], np.inf)
+    part = np.partition(S, -2, axis=1)
+    return part[:, -1] - part[:, -2]
+
+
+def check_assign(X, C32, a_gpu, best_gpu, label):
+    a_ref, s1, s2 = oracle.assign(X, C32.astype(np.float64))
+    gap = s1 - s2 if C32.shape[0] > 1 else np.full(X.n, np.inf)
+    clear = gap > GAP
+    bad = np.flatnonzero(clear & (a_gpu != a_ref))
+    say("%s: n=%d k=%d band=%d mismatches(clear)=%d mismatches(all)=%d" %
+        (label, X.n, C32.shape[0], int((~clear).sum()), len(bad), int((a_gpu != a_ref).sum())))
+    assert len(bad) == 0, bad[:10]
+    # every assignment in the band still attains the FP64 maximum to 1e-12
+    assert np.all(s1 - np.take_along_axis(
+        oracle.sims(X, C32.astype(np.float64), np.arange(X.n)), a_gpu[:, None].astype(np.int64),
+        1)[:, 0] <= 1e-12)
+    m = X.row_lengths()
+    err = np.abs(best_gpu.astype(np.float64) - s1)
+    assert np.all(err <= (m + 3) * 2.0 ** -24 * 1.02 + 1e-12)
+    return a_ref
+
+
+# ----------------------------------------------------------------- assign
+
+@pytest.mark.parametrize("k", [1, 3, 10, 17, 40, 100, 130, 300, 700, 1500, 2600])
+def test_assign_matches_oracle(skm, torch_cuda, k):
+    torch = torch_cuda
+    say("case assign k=%d" % k)
+    X = datagen.sparse_tfidf(2500, 3000, 30.0, 1000 + k)
+    rng = np.random.default_rng(k)
+    rows = rng.choice(X.n, size=k, replace=k > X.n)
+    C = datagen.init_centers_csr(X, rows).astype(np.float64)
+    C += 0.05 * np.abs(rng.normal(size=C.shape)) * (rng.random(C.shape) < 0.01)
+    C /= np.linalg.norm(C, axis=1, keepdims=True)
+    C32 = C.astype(np.float32)
+    Xd = skm.DeviceCSR.from_host(X)
+    a, best, second = skm.assign(Xd, torch.from_numpy(C32).cuda())
+    torch.cuda.synchronize()
+    check_assign(X, C32, a.cpu().numpy(), best.cpu().numpy(), "assign k=%d" % k)
+
+
+def test_assign_ties_and_empty_rows(skm, torch_cuda):
+    torch = torch_cuda
+    say("case assign ties/empty rows")
+    X = datagen.sparse_tfidf(600, 800, 12.0, 77)
+    # insert empty rows 0, 5, 599 by rebuilding row_ptr
+    lens = np.diff(X.row_ptr)
+    lens[[0, 5, 599]] = 0
+    keep = np.ones(X.nnz, bool)
+    for r in [0, 5, 599]:
+        keep[X.row_ptr[r]:X.row_ptr[r + 1]] = False
+    rp = np.zeros(X.n + 1, np.int64)
+    np.cumsum(lens, out=rp[1:])
+    Y = datagen.CSR(X.n, X.d, rp, X.col[keep], X.val[keep])
+    C = datagen.init_centers_csr(Y, np.array([10, 20, 10, 30, 20]))  # duplicates
+    Yd = skm.DeviceCSR.from_host(Y)
+    a, best, second = skm.assign(Yd, torch.from_numpy(C).cuda())
+    a = a.cpu().numpy()
+    a_ref = check_assign(Y, C, a, best.cpu().numpy(), "ties")
+    assert np.array_equal(a, a_ref)  # exact ties resolve to the lowest index
+    assert not np.any(np.isin(a, [2, 4]))
+    assert a[0] == 0 and a[5] == 0 and a[599] == 0
+
+
+# ----------------------------------------------------------------- fit
+
+VARIANTS = ["lloyd", "hamerly", "elkan", "simp_hamerly", "simp_elkan"]
+
+
+def run_fit(skm, torch, Xd, C0, k, variant, max_iter, **kw):
+    a, C, C64, st = skm.fit(Xd, k, torch.from_numpy(C0).cuda(), variant, max_iter,
+                            want_centers64=True, **kw)
+    torch.cuda.synchronize()
+    return a.cpu().numpy(), C.cpu().numpy(), C64.cpu().numpy(), st
+
+
+def test_fit_c1_all_variants_match_oracle(skm, torch_cuda):
+    torch = torch_cuda
+    X, init, cfg = datagen.sparse_workload("c1")
+    C0 = datagen.init_centers_csr(X, init)
+    Xd = skm.DeviceCSR.from_host(X)
+    ref = oracle.fit(X, C0, "lloyd", cfg.max_iter, trace=True)
+    base = None
+    for v in VARIANTS:
+        for bf in ([0, 1] if "hamerly" in v else [0]):
+            say("case fit c1 %s bound_form=%d" % (v, bf))
+            a, C, C64, st = run_fit(skm, torch, Xd, C0, cfg.k, v, cfg.max_iter, bound_form=bf)
+            assert st.iterations == ref.iterations and st.converged == ref.converged
+            assert np.array_equal(st.changed_per_iter, ref.changed)
+            assert np.array_equal(a, ref.a)
+            assert np.abs(C64 - ref.C).max() < 1e-6
+            assert np.linalg.norm(C.astype(np.float64) - ref.C, axis=1).max() < 1e-6
+            obj_ref = float(ref.obj_update[~np.isnan(ref.obj_update)][-1])
+            assert abs(st.objective - obj_ref) <= 1e-6 * obj_ref
+            say("  iters=%d sims=%d (lloyd %d) rechecks=%d max|dC|=%.2e" %
+                (st.iterations, st.sims_point_center, ref.sims.sum(), st.rechecks,
+                 np.abs(C64 - ref.C).max()))
+            if base is None:
+                base = (a, C64)
+            else:
+                assert np.array_equal(a, base[0]) and np.array_equal(C64, base[1])
+            if v != "lloyd":
+                assert st.sims_point_center < ref.sims.sum()
+
+
+def test_fit_c1_step_locked(skm, torch_cuda):
+    """Every step t against the oracle fed the GPU's own state at t-1."""
+    torch = torch_cuda
+    X, init, cfg = datagen.sparse_workload("c1")
+    C0 = datagen.init_centers_csr(X, init).astype(np.float64)
+    Xd = skm.DeviceCSR.from_host(X)
+    Cprev = C0 / np.linalg.norm(C0, axis=1, keepdims=True)
+    aprev = None
+    for t in range(1, 8):
+        for v in ["lloyd", "hamerly", "elkan"]:
+            say("case step-locked c1 t=%d %s" % (t, v))
+            a, C, C64, st = run_fit(skm, torch, Xd, C0.astype(np.float32), cfg.k, v, t)
+            a_ref, s1, s2 = oracle.assign(X, Cprev, aprev)
+            clear = (s1 - s2) > GAP
+            assert np.array_equal(a[clear], a_ref[clear])
+            Cu, _, obj = oracle.update(X, a, Cprev)
+            assert np.linalg.norm(C64 - Cu, axis=1).max() < 1e-6
+            assert abs(st.objective - obj) < 1e-6 * obj
+        aprev, Cprev = a, C64
+        if st.converged:
+            break
+
+
+@pytest.mark.parametrize("bound_form", [0, 1])
+def test_fit_reduced_c2(skm, torch_cuda, bound_form):
+    torch = torch_cuda
+    X, init, cfg = datagen.sparse_workload("c2", n=20000)
+    C0 = datagen.init_centers_csr(X, init)
+    Xd = skm.DeviceCSR.from_host(X)
+    T = 25
+    ref = oracle.fit(X, C0, "lloyd", T)
+    base = None
+    for v in VARIANTS:
+        say("case fit reduced c2 %s bf=%d" % (v, bound_form))
+        a, C, C64, st = run_fit(skm, torch, Xd, C0, cfg.k, v, T, bound_form=bound_form)
+        say("  iters=%d sims=%d/%d rechecks=%d" % (st.iterations, st.sims_point_center,
+                                                    ref.sims.sum(), st.rechecks))
+        assert st.iterations == ref.iterations
+        assert np.array_equal(st.changed_per_iter, ref.changed)
+        assert np.array_equal(a, ref.a)
+        assert np.linalg.norm(C64 - ref.C, axis=1).max() < 1e-6
+        if base is None:
+            base = (a, C64)
+        else:
+            assert np.array_equal(a, base[0]) and np.array_equal(C64, base[1])
+
+
+def sampled_step_check(X, a_t, C_prev, a_prev, C_t, sample, label):
+    rows = np.sort(sample)
+    S = oracle.sims(X, C_prev, rows)
+    ref = np.argmax(S, axis=1)
+    if a_prev is not None:  # keep-previous tie rule
+        keep = S[np.arange(len(rows)), a_prev[rows]] == S.max(1)
+        ref = np.where(keep, a_prev[rows], ref)
+    gap = gap_of(S)
+    clear = gap > GAP
+    say("%s: sampled %d rows, band %d" % (label, len(rows), int((~clear).sum())))
+    assert np.array_equal(a_t[rows][clear], ref[clear])
+    Cu, _, _ = oracle.update(X, a_t, C_prev)
+    err = np.linalg.norm(C_t - Cu, axis=1).max()
+    say("%s: max centre error %.3e" % (label, err))
+    assert err < 1e-6
+
+
+def test_fit_c2_full_size(skm, torch_cuda):
+    """Full c2 workload (n=1e5, d=5e4, k=100) run to no-change: all variants
+    identical; the last step checked against the oracle on sampled rows."""
+    torch = torch_cuda
+    X, init, cfg = datagen.sparse_workload("c2")
+    C0 = datagen.init_centers_csr(X, init)
+    Xd = skm.DeviceCSR.from_host(X)
+    res = {}
+    for v in ["lloyd", "hamerly", "elkan", "simp_hamerly"]:
+        say("case fit c2 %s" % v)
+        res[v] = run_fit(skm, torch, Xd, C0, cfg.k, v, cfg.max_iter)
+        st = res[v][3]
+        say("  iters=%d converged=%d sims=%d rechecks=%d" % (st.iterations, st.converged,
+                                                            st.sims_point_center, st.rechecks))
+    a, C, C64, st = res["lloyd"]
+    for v, (a2, C2, C642, st2) in res.items():
+        assert st2.iterations == st.iterations, v
+        assert np.array_equal(a2, a) and np.array_equal(C642, C64), v
+    T = st.iterations
+    a1, _, Cm1, _ = run_fit(skm, torch, Xd, C0, cfg.k, "lloyd", T - 1)
+    sample = np.random.default_rng(0).choice(X.n, 3000, replace=False)
+    sampled_step_check(X, a, Cm1, a1, C64, sample, "c2 t=%d" % T)
+
+
+def test_fit_c3_full_size_sampled(skm, torch_cuda):
+    """Full c3 workload (n=1e6, d=1e5, k=1000): Hamerly and Lloyd identical
+    over the first steps; one step checked against the oracle on sampled
+    rows, centres checked in full."""
+    torch = torch_cuda
+    say("case c3 generate")
+    X, init, cfg = datagen.sparse_workload("c3")
+    C0 = datagen.init_centers_csr(X, init)
+    Xd = skm.DeviceCSR.from_host(X)
+    T = 4
+    out = {}
+    for v in ["lloyd", "hamerly"]:
+        say("case fit c3 %s max_iter=%d" % (v, T))
+        out[v] = run_fit(skm, torch, Xd, C0, cfg.k, v, T)
+        say("  sims=%d rechecks=%d" % (out[v][3].sims_point_center, out[v][3].rechecks))
+    assert np.array_equal(out["lloyd"][0], out["hamerly"][0])
+    assert np.array_equal(out["lloyd"][2], out["hamerly"][2])
+    a_prev, _, C_prev, _ = run_fit(skm, torch, Xd, C0, cfg.k, "lloyd", T - 1)
+    sample = np.random.default_rng(1).choice(X.n, 1000, replace=False)
+    sampled_step_check(X, out["lloyd"][0], C_prev, a_prev, out["lloyd"][2], sample,
+                       "c3 t=%d" % T)
