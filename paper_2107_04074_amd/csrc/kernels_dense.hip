@@ -1,0 +1,766 @@
+// Dense-row kernels for gfx950: the similarity contraction of the assignment
+// step (Section 5) on MFMA matrix cores, in BF16 (FP32 accumulate) or FP32.
+//
+//  k_dense_sim      rows x centres on MFMA.  Centres are streamed through LDS
+//                   in chunks shared by the block's waves; every wave keeps
+//                   its rows' operand fragments in registers for the whole
+//                   centre loop.  Epilogue: running top-2 per row (assignment,
+//                   bounds) or, in candidate mode, every centre within the
+//                   error band of the row's best value.
+//  k_dense_exact    FP64 re-decision of the rows whose best and second best
+//                   lie within the rigorous error band: one canonical FP64
+//                   chain per candidate against the FP64 master centre.
+//  k_dense_hamerly  Eq. (6), guarded Eq. (7) / Eq. (9) and the tests of
+//                   Sections 5.3 / 5.4 per row, tightening l(i) with an FP64
+//                   dot product; rows that fail are flagged for recompute.
+//  k_cluster_sums   S(j) recomputed from scratch per cluster (rows sorted by
+//                   cluster), 64-bit fixed point as in the sparse path.
+//  compaction       flags -> dense row list via per-block counts, a scan and
+//                   a scatter (no contended atomics).
+//
+// MFMA lane layouts (checked on the device): 32x32x16 bf16 takes
+// A[m = l%32][k = 8(l/32)+e] and B[k = 8(l/32)+e][n = l%32] (e < 8);
+// 32x32x2 f32 takes A[l%32][l/32] and B[l/32][l%32]; both return element i of
+// lane l as C[8(i/4) + 4(l/32) + i%4][l%32].  Here A holds 32 centres and B
+// holds 32 rows, so every lane ends with 16 centres of one row.
+#include <float.h>
+#include <limits.h>
+
+#include <type_traits>
+
+#include "skm_device.h"
+#include "skm_internal.h"
+
+namespace skm {
+namespace {
+using namespace dev;
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
+
+constexpr int kDenseWaves = 4;  // waves per block of the MFMA kernel
+
+template <bool BF16>
+struct MfmaCfg;
+
+template <>
+struct MfmaCfg<true> {
+  static constexpr int KSTEP = 16;  // K per instruction
+  static constexpr int RT = 2;      // 32-row tiles per wave
+  static constexpr int CC = 64;     // centres per LDS chunk
+  typedef __bf16 elem;
+};
+
+template <>
+struct MfmaCfg<false> {
+  static constexpr int KSTEP = 2;
+  static constexpr int RT = 1;
+  static constexpr int CC = 32;
+  typedef float elem;
+};
+
+__device__ __forceinline__ void top2_push(float v, int j, float& m1, int& j1, float& m2) {
+  if (v > m1) {
+    m2 = m1;
+    m1 = v;
+    j1 = j;
+  } else {
+    m2 = fmaxf(m2, v);
+  }
+}
+
+// Rows x centres on MFMA.  rows: list of row ids (nullable = identity),
+// count from *rows_count (nullable = n_rows).
+//   mode 0: writes best value, its centre, second best (per row, in slot
+//           order of the list)
+//   mode 1: candidate emission: every centre with value >= thr[slot] is
+//           appended to cand[slot * cap + ...], counts in cand_n[slot]
+template <bool BF16, int MODE>
+__global__ __launch_bounds__(kDenseWaves * 64) void k_dense_sim(DenseSimArgs A) {
+  typedef MfmaCfg<BF16> Cfg;
+  typedef typename Cfg::elem E;
+  constexpr int KSTEP = Cfg::KSTEP, RT = Cfg::RT, CC = Cfg::CC;
+  constexpr int ROWS_PER_WAVE = 32 * RT;
+  constexpr int ROWS_PER_BLOCK = ROWS_PER_WAVE * kDenseWaves;
+  extern __shared__ char smem[];
+  E* lds = reinterpret_cast<E*>(smem);
+  const int dp = A.dp;
+  const int ldsw = dp + (BF16 ? 8 : 4);  // padded LDS row stride (16-byte aligned)
+  const int nsteps = dp / KSTEP;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t count = A.rows_count ? (int64_t)(*A.rows_count) : A.n_rows;
+  const E* __restrict__ Xe = reinterpret_cast<const E*>(A.X);
+  const E* __restrict__ Ce = reinterpret_cast<const E*>(A.C);
+
+  for (int64_t blk = (int64_t)blockIdx.x * ROWS_PER_BLOCK; blk < count;
+       blk += (int64_t)gridDim.x * ROWS_PER_BLOCK) {
+    // operand fragments of this wave's rows, kept in registers
+    int64_t slot[RT];
+    int64_t rowid[RT];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      slot[rt] = blk + (int64_t)wave * ROWS_PER_WAVE + rt * 32 + (lane & 31);
+      rowid[rt] = (slot[rt] < count) ? (A.rows ? (int64_t)A.rows[slot[rt]] : slot[rt]) : -1;
+    }
+    constexpr int NS = BF16 ? 16 : 128;  // K steps held (dp <= 256)
+    typedef typename std::conditional<BF16, bf16x8, float>::type Frag;
+    Frag bfr[RT][NS];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        if (s < nsteps && rowid[rt] >= 0) {
+          if constexpr (BF16) {
+            bfr[rt][s] = *reinterpret_cast<const bf16x8*>(Xe + (size_t)rowid[rt] * A.ldx +
+                                                          s * KSTEP + 8 * (lane >> 5));
+          } else {
+            const int col = s * KSTEP + (lane >> 5);
+            bfr[rt][s] = col < A.d ? Xe[(size_t)rowid[rt] * A.ldx + col] : 0.f;
+          }
+        } else {
+          if constexpr (BF16) {
+            bf16x8 z;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) z[e] = (__bf16)0.f;
+            bfr[rt][s] = z;
+          } else {
+            bfr[rt][s] = 0.f;
+          }
+        }
+      }
+    float m1[RT], m2[RT], thr[RT];
+    int j1[RT];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      m1[rt] = -INFINITY;
+      m2[rt] = -INFINITY;
+      j1[rt] = INT_MAX;
+      thr[rt] = (MODE == 1 && rowid[rt] >= 0) ? A.thr[slot[rt]] : INFINITY;
+    }
+
+    for (int c0 = 0; c0 < A.kpad; c0 += CC) {
+      __syncthreads();
+      // stage centres [c0, c0 + CC) into LDS, 16 bytes per thread and step
+      constexpr int VEC = 16 / sizeof(E);
+      const int per_row = dp / VEC;
+      for (int e = threadIdx.x; e < CC * per_row; e += kDenseWaves * 64) {
+        const int r = e / per_row, c = (e - r * per_row) * VEC;
+        *reinterpret_cast<float4*>(lds + r * ldsw + c) =
+            *reinterpret_cast<const float4*>(Ce + (size_t)(c0 + r) * dp + c);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int at = 0; at < CC / 32; ++at) {
+        f32x16 acc[RT];
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+          for (int i = 0; i < 16; ++i) acc[rt][i] = 0.f;
+        const E* arow = lds + (at * 32 + (lane & 31)) * ldsw;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          if (s < nsteps) {
+            if constexpr (BF16) {
+              const bf16x8 a =
+                  *reinterpret_cast<const bf16x8*>(arow + s * KSTEP + 8 * (lane >> 5));
+#pragma unroll
+              for (int rt = 0; rt < RT; ++rt)
+                acc[rt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bfr[rt][s], acc[rt], 0, 0, 0);
+            } else {
+              const float a = arow[s * KSTEP + (lane >> 5)];
+#pragma unroll
+              for (int rt = 0; rt < RT; ++rt)
+                acc[rt] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bfr[rt][s], acc[rt], 0, 0, 0);
+            }
+          }
+        }
+        // epilogue: lane holds centres 8(i/4) + 4(l/32) + i%4 of row l%32
+        const int jb = c0 + at * 32 + 4 * (lane >> 5);
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) {
+#pragma unroll
+          for (int i = 0; i < 16; ++i) {
+            const int j = jb + 8 * (i >> 2) + (i & 3);
+            const float v = acc[rt][i];
+            if (j < A.k) {
+              if (MODE == 0) {
+                top2_push(v, j, m1[rt], j1[rt], m2[rt]);
+              } else if (v >= thr[rt] && rowid[rt] >= 0) {
+                const int pos = atomicAdd(&A.cand_n[slot[rt]], 1);
+                if (pos < A.cand_cap) A.cand[slot[rt] * A.cand_cap + pos] = j;
+              }
+            }
+          }
+        }
+      }
+    }
+    if (MODE == 0) {
+      // combine lanes l and l ^ 32 (same row, other half of the centres)
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) {
+        const float om1 = __shfl_xor(m1[rt], 32, 64);
+        const float om2 = __shfl_xor(m2[rt], 32, 64);
+        const int oj1 = __shfl_xor(j1[rt], 32, 64);
+        float b = m1[rt], s2v = fmaxf(m2[rt], om2);
+        int bj = j1[rt];
+        if (om1 > b || (om1 == b && oj1 < bj)) {
+          s2v = fmaxf(s2v, b);
+          b = om1;
+          bj = oj1;
+        } else {
+          s2v = fmaxf(s2v, om1);
+        }
+        if (lane < 32 && rowid[rt] >= 0) {
+          A.best[slot[rt]] = b;
+          A.best_j[slot[rt]] = bj;
+          A.second[slot[rt]] = s2v;
+        }
+      }
+    }
+  }
+}
+
+
+// Rigorous bound on |s_hat - <x, c>| for one row of the dense contraction:
+// BF16 rounds x and the centre copy (2^-9 each, RNE) with exact products and
+// FP32 accumulation over dp terms; FP32 rounds the centre copy and every
+// product and sum.
+__device__ __forceinline__ double dense_eps(bool bf16, int dp, double eta) {
+  const double unit = bf16 ? (2.0 * 0.001953125 + 3.814697265625e-06 + (dp + 2) * kU32)
+                           : ((dp + 3) * kU32);
+  return unit * (1.0 + eta) * 1.01;
+}
+
+// Decision after the top-2 pass: clear rows are final (FP32/BF16 argmax is
+// the exact argmax); rows inside the band are flagged for the candidate
+// pass with their threshold.
+__global__ __launch_bounds__(kBlock) void k_dense_post(DensePostArgs A) {
+  __shared__ unsigned long long sh_changed;
+  if (threadIdx.x == 0) sh_changed = 0;
+  __syncthreads();
+  const int64_t count = A.rows_count ? (int64_t)(*A.rows_count) : A.n_rows;
+  const int64_t sl = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  unsigned long long moved = 0;
+  if (sl < count) {
+    const int64_t row = A.rows ? A.rows[sl] : sl;
+    const int prev = A.read_prev ? A.a[row] : -1;
+    const double eta = (double)A.eta[row];
+    const double eps = dense_eps(A.bf16, A.dp, eta);
+    const double b = A.best[sl], s2 = A.second[sl];
+    const bool near = A.k > 1 && b - s2 <= 2.0 * eps;
+    A.near[sl] = near ? 1 : 0;
+    if (A.best_out) A.best_out[row] = (float)b;
+    if (A.second_out) A.second_out[row] = (float)s2;
+    if (near) {
+      A.thr[sl] = __double2float_rd(b - 2.0 * eps - 1e-12);
+    } else {
+      const int j = A.best_j[sl];
+      A.a[row] = j;
+      moved = (j != prev) ? 1 : 0;
+      const double rho = eps + 1.01 * (eta + A.delta_c) + 1e-12;
+      if (A.l) A.l[row] = __double2float_rd(fmax(b - rho, -1.0));
+      if (A.u) A.u[row] = __double2float_ru(fmin((A.k == 1 ? -1.0 : s2 + rho), 1.0));
+    }
+  }
+  if (moved) atomicAdd(&sh_changed, moved);
+  __syncthreads();
+  if (threadIdx.x == 0 && sh_changed) atomicAdd(&counter_slot(A.cnt)->changed, sh_changed);
+}
+
+// FP64 re-decision of the flagged rows, one wave per row: each lane
+// evaluates candidates with the canonical sequential FP64 chain against the
+// FP64 master centres; overflowing candidate lists fall back to all k.
+__global__ __launch_bounds__(kBlock) void k_dense_exact(DenseExactArgs A) {
+  __shared__ unsigned long long sh_changed, sh_rechecks;
+  if (threadIdx.x == 0) {
+    sh_changed = 0;
+    sh_rechecks = 0;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int64_t count = (int64_t)(*A.near_count);
+  unsigned long long moved = 0, rech = 0;
+  for (int64_t w = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6; w < count;
+       w += ((int64_t)gridDim.x * kBlock) >> 6) {
+    const int64_t sl = A.near_list[w];            // slot of the similarity pass
+    const int64_t row = A.rows ? A.rows[sl] : sl;
+    const int prev = A.read_prev ? A.a[row] : -1;
+    const int nc = A.cand_n[w];
+    const bool all = nc > A.cand_cap;
+    const int ncand = all ? A.k : nc;
+    const float* x = A.X + (size_t)row * A.ldx;
+    double cb = -INFINITY;
+    int cj = INT_MAX;
+    for (int c = lane; c < ncand; c += 64) {
+      const int j = all ? c : A.cand[(size_t)w * A.cand_cap + c];
+      const double* cj64 = A.C64 + (size_t)j * A.d;
+      double acc = 0.0;
+      for (int t = 0; t < A.d; ++t) acc = fma((double)x[t], cj64[t], acc);
+      if (better64(acc, j, cb, cj, prev)) {
+        cb = acc;
+        cj = j;
+      }
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      const double ob = __shfl_xor(cb, off, 64);
+      const int oj = __shfl_xor(cj, off, 64);
+      if (better64(ob, oj, cb, cj, prev)) {
+        cb = ob;
+        cj = oj;
+      }
+    }
+    if (lane == 0) {
+      A.a[row] = cj;
+      moved += (cj != prev) ? 1 : 0;
+      rech += 1;
+      if (A.best_out) A.best_out[row] = (float)cb;
+      if (A.second_out && cj != A.best_j[sl]) A.second_out[row] = A.best[sl];
+      const double eta = (double)A.eta[row];
+      const double eps = dense_eps(A.bf16, A.dp, eta);
+      const double slack = 1.01 * (eta + A.delta_c);
+      const double rho64 = (double)(A.d + 2) * kU64 * (1.0 + eta) * 1.01 + slack + 1e-15;
+      const double rho = eps + slack + 1e-12;
+      if (A.l) A.l[row] = __double2float_rd(fmax(cb - rho64, -1.0));
+      if (A.u) A.u[row] = __double2float_ru(fmin((double)A.best[sl] + rho, 1.0));
+    }
+  }
+  if (moved) atomicAdd(&sh_changed, moved);
+  if (rech) atomicAdd(&sh_rechecks, rech);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    Counters* c = counter_slot(A.cnt);
+    if (sh_changed) atomicAdd(&c->changed, sh_changed);
+    if (sh_rechecks) atomicAdd(&c->rechecks, sh_rechecks);
+  }
+}
+
+// Row ids and thresholds of the flagged slots, for the candidate pass.
+__global__ __launch_bounds__(kBlock) void k_gather_near(const int32_t* __restrict__ near_list,
+                                                        const unsigned long long* __restrict__ cnt,
+                                                        const int32_t* __restrict__ rows,
+                                                        const float* __restrict__ thr_slot,
+                                                        int32_t* __restrict__ out_rows,
+                                                        float* __restrict__ out_thr) {
+  const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (q >= (int64_t)(*cnt)) return;
+  const int32_t sl = near_list[q];
+  out_rows[q] = rows ? rows[sl] : sl;
+  out_thr[q] = thr_slot[sl];
+}
+
+// Hamerly step for dense rows (Sections 5.3 / 5.4), 16 lanes per row.
+constexpr int kDHG = 16;
+__global__ __launch_bounds__(kBlock) void k_dense_hamerly(DenseHamerlyArgs A) {
+  __shared__ unsigned long long sh_tight, sh_saved;
+  if (threadIdx.x == 0) {
+    sh_tight = 0;
+    sh_saved = 0;
+  }
+  __syncthreads();
+  const int gl = threadIdx.x & (kDHG - 1);
+  const int64_t i = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kDHG;
+  unsigned long long tight = 0, saved = 0;
+  if (i < A.n) {
+    const int a = A.a[i];
+    const double eta = (double)A.eta[i];
+    const double slack = 1.01 * (eta + A.delta_c);
+    const double rho64 = (double)(A.d + 2) * kU64 * (1.0 + eta) * 1.01 + slack + 1e-15;
+    const double mu = 4.0 * (double)(A.d + 2) * kU64 * (1.0 + eta) + 4.0 * A.delta_c + 1e-15;
+    const MoveMin mm = *A.mm;
+    double ld = lower_upd((double)A.l[i], A.pc[a], A.ps[a]) - 4e-15;
+    const double pcx = (a == mm.idx1) ? mm.pc2 : mm.pc1;
+    const double psx = (a == mm.idx1) ? mm.ps2 : mm.ps1;
+    const double u0 = fmin(1.0, fmax(-1.0, (double)A.u[i]));
+    double ud;
+    if (A.bound_form == 1 && u0 >= 0.0 && pcx >= 0.0)
+      ud = u0 + sqrt((1.0 - u0) * (1.0 + u0)) * psx;  // Eq. (9)
+    else
+      ud = upper_upd(u0, pcx, psx);
+    ud = fmin(1.0, ud + 4e-15);
+    const double smax = A.simplified ? 2.0 : A.gmax[a];
+    auto pruned = [&](double lcur) -> bool {
+      if (lcur - ud >= mu) return true;
+      const double M = lcur - mu;
+      return !A.simplified && lcur > 0.0 && M > 0.0 && smax <= cc_threshold(lcur, M) - 4e-15;
+    };
+    bool skip = pruned(ld);
+    if (!skip && A.try_tighten) {
+      const float* x = A.X + (size_t)i * A.ldx;
+      const double* c = A.C64 + (size_t)a * A.d;
+      double p = 0.0;
+      for (int t = gl; t < A.d; t += kDHG) p = fma((double)x[t], c[t], p);
+      const double s64 = group_sum<kDHG>(p);
+      ld = fmax(ld, s64 - rho64);
+      tight = (gl == 0) ? 1 : 0;
+      skip = pruned(ld);
+      saved = (skip && gl == 0) ? 1 : 0;
+    }
+    if (gl == 0) {
+      A.flag[i] = skip ? 0 : 1;
+      A.l[i] = __double2float_rd(fmax(ld, -1.0));
+      A.u[i] = __double2float_ru(ud);
+    }
+  }
+  if (tight) atomicAdd(&sh_tight, tight);
+  if (saved) atomicAdd(&sh_saved, saved);
+  __syncthreads();
+  if (threadIdx.x == 0 && sh_tight) {
+    Counters* c = counter_slot(A.cnt);
+    atomicAdd(&c->tightened, sh_tight);
+    atomicAdd(&c->sims, sh_tight);
+    if (sh_saved) atomicAdd(&c->tight_saved, sh_saved);
+  }
+}
+
+// ---- compaction: flags -> list of indices, no contended atomics ----
+constexpr int kCompactChunk = 1024;
+
+__global__ __launch_bounds__(kBlock) void k_flags_count(const int32_t* __restrict__ flags,
+                                                        const unsigned long long* __restrict__ nptr,
+                                                        int64_t nmax, int32_t* __restrict__ bcnt) {
+  __shared__ int sh;
+  if (threadIdx.x == 0) sh = 0;
+  __syncthreads();
+  const int64_t n = nptr ? (int64_t)(*nptr) : nmax;
+  const int64_t base = (int64_t)blockIdx.x * kCompactChunk;
+  int c = 0;
+  for (int e = threadIdx.x; e < kCompactChunk; e += kBlock) {
+    const int64_t i = base + e;
+    if (i < n && flags[i]) ++c;
+  }
+  if (c) atomicAdd(&sh, c);
+  __syncthreads();
+  if (threadIdx.x == 0) bcnt[blockIdx.x] = sh;
+}
+
+// Single block: exclusive scan of nb block counts, total into *total.
+__global__ __launch_bounds__(kBlock) void k_scan_counts(const int32_t* __restrict__ bcnt, int nb,
+                                                        int32_t* __restrict__ boff,
+                                                        unsigned long long* __restrict__ total) {
+  __shared__ int sh[kBlock];
+  const int per = (nb + kBlock - 1) / kBlock;
+  const int b0 = threadIdx.x * per;
+  int s = 0;
+  for (int b = b0; b < b0 + per && b < nb; ++b) s += bcnt[b];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 1; off < kBlock; off <<= 1) {
+    const int v = (int)threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+    __syncthreads();
+    sh[threadIdx.x] += v;
+    __syncthreads();
+  }
+  int run = sh[threadIdx.x] - s;
+  for (int b = b0; b < b0 + per && b < nb; ++b) {
+    boff[b] = run;
+    run += bcnt[b];
+  }
+  if (threadIdx.x == kBlock - 1) *total = (unsigned long long)sh[kBlock - 1];
+}
+
+// Writes the indices i with flags[i] != 0 in increasing order; also clears
+// zero_at[pos] for every written position (nullable).
+__global__ __launch_bounds__(kBlock) void k_flags_scatter(const int32_t* __restrict__ flags,
+                                                          const unsigned long long* __restrict__ nptr,
+                                                          int64_t nmax,
+                                                          const int32_t* __restrict__ boff,
+                                                          int32_t* __restrict__ list,
+                                                          int32_t* __restrict__ zero_at) {
+  __shared__ int wsum[kBlock / 64];
+  const int64_t n = nptr ? (int64_t)(*nptr) : nmax;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int run = boff[blockIdx.x];
+  for (int e0 = 0; e0 < kCompactChunk; e0 += kBlock) {
+    const int64_t i = (int64_t)blockIdx.x * kCompactChunk + e0 + threadIdx.x;
+    const bool f = i < n && flags[i];
+    const unsigned long long m = __ballot(f);
+    if (lane == 0) wsum[wave] = __popcll(m);
+    __syncthreads();
+    int before = 0, tot = 0;
+    for (int w = 0; w < kBlock / 64; ++w) {
+      if (w < wave) before += wsum[w];
+      tot += wsum[w];
+    }
+    if (f) {
+      const int pos = run + before + (int)__popcll(m & ((1ull << lane) - 1ull));
+      list[pos] = (int32_t)i;
+      if (zero_at) zero_at[pos] = 0;
+    }
+    run += tot;
+    __syncthreads();
+  }
+}
+
+// ---- member sums recomputed per cluster ----
+__global__ __launch_bounds__(kBlock) void k_hist(const int32_t* __restrict__ a, int64_t n,
+                                                 int32_t k, int32_t* __restrict__ cnt) {
+  extern __shared__ int hs[];
+  for (int j = threadIdx.x; j < k; j += kBlock) hs[j] = 0;
+  __syncthreads();
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kBlock)
+    atomicAdd(&hs[a[i]], 1);
+  __syncthreads();
+  for (int j = threadIdx.x; j < k; j += kBlock)
+    if (hs[j]) atomicAdd(&cnt[j], hs[j]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_scatter_rows(const int32_t* __restrict__ a, int64_t n,
+                                                         int32_t* __restrict__ cursor,
+                                                         int32_t* __restrict__ perm) {
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kBlock)
+    perm[atomicAdd(&cursor[a[i]], 1)] = (int32_t)i;
+}
+
+// One block per cluster, one thread per column (d <= 256 per pass).
+__global__ __launch_bounds__(kBlock) void k_cluster_sums(const int32_t* __restrict__ perm,
+                                                         const int32_t* __restrict__ start,
+                                                         const int32_t* __restrict__ cnt,
+                                                         const float* __restrict__ X, int64_t ldx,
+                                                         int64_t d, double fx,
+                                                         long long* __restrict__ S,
+                                                         int32_t* __restrict__ dirty) {
+  const int j = blockIdx.x;
+  const int32_t b = start[j], m = cnt[j];
+  for (int64_t t = threadIdx.x; t < d; t += kBlock) {
+    long long acc = 0;
+    for (int32_t q = 0; q < m; ++q)
+      acc += __double2ll_rn((double)X[(size_t)perm[b + q] * ldx + t] * fx);
+    S[(size_t)j * d + t] = acc;
+  }
+  if (threadIdx.x == 0) dirty[j] = 1;
+}
+
+// Moved rows (a != a_old) applied to the sums with integer atomics; used
+// when few rows moved.  One wave per 64 rows scanned, as the sparse path.
+__global__ __launch_bounds__(kBlock) void k_dense_update_scan(
+    const float* __restrict__ X, int64_t ldx, const int32_t* __restrict__ a,
+    int32_t* __restrict__ a_old, int64_t n, int64_t d, double fx, long long* __restrict__ S,
+    int32_t* __restrict__ dirty) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wave0 = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63);
+  for (int64_t base = wave0; base < n; base += (int64_t)gridDim.x * kBlock) {
+    const int64_t i = base + lane;
+    int32_t nw = -1, old = -1;
+    if (i < n) {
+      nw = a[i];
+      old = a_old[i];
+    }
+    unsigned long long moved = __ballot(i < n && nw != old);
+    while (moved) {
+      const int src = __ffsll((long long)moved) - 1;
+      moved &= moved - 1ull;
+      const int64_t row = base + src;
+      const int32_t rn = __shfl(nw, src, 64);
+      const int32_t ro = __shfl(old, src, 64);
+      unsigned long long* Sn = reinterpret_cast<unsigned long long*>(S + (size_t)rn * d);
+      unsigned long long* So =
+          ro >= 0 ? reinterpret_cast<unsigned long long*>(S + (size_t)ro * d) : nullptr;
+      for (int64_t t = lane; t < d; t += 64) {
+        const long long q = __double2ll_rn((double)X[(size_t)row * ldx + t] * fx);
+        atomicAdd(Sn + t, (unsigned long long)q);
+        if (So) atomicAdd(So + t, (unsigned long long)(-q));
+      }
+      if (lane == 0) {
+        dirty[rn] = 1;
+        if (ro >= 0) dirty[ro] = 1;
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_copy_assign(const int32_t* __restrict__ a,
+                                                        int32_t* __restrict__ a_old, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) a_old[i] = a[i];
+}
+
+// ---- conversions ----
+__global__ __launch_bounds__(kBlock) void k_rows_to_bf16(const float* __restrict__ X, int64_t ldx,
+                                                         int64_t n, int64_t d, int dp,
+                                                         __bf16* __restrict__ Xb) {
+  const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t i = e / dp;
+  const int t = (int)(e - i * dp);
+  if (i < n) Xb[e] = (__bf16)(t < d ? X[(size_t)i * ldx + t] : 0.f);
+}
+
+// FP64 masters -> packed MFMA operand rows (bf16 or f32), dirty rows only.
+__global__ __launch_bounds__(kBlock) void k_pack_centres(const double* __restrict__ C64,
+                                                         int32_t k, int64_t d, int dp,
+                                                         const int32_t* __restrict__ dirty,
+                                                         int bf16, void* __restrict__ out) {
+  const int j = blockIdx.x;
+  if (j >= k || (dirty && !dirty[j])) return;
+  for (int t = threadIdx.x; t < dp; t += kBlock) {
+    const double c = t < d ? C64[(size_t)j * d + t] : 0.0;
+    if (bf16) reinterpret_cast<__bf16*>(out)[(size_t)j * dp + t] = (__bf16)(float)c;
+    else reinterpret_cast<float*>(out)[(size_t)j * dp + t] = (float)c;
+  }
+}
+
+// | |x_i| - 1 | for dense rows, one wave per row.
+__global__ __launch_bounds__(kBlock) void k_dense_row_eta(const float* __restrict__ X, int64_t ldx,
+                                                          int64_t n, int64_t d,
+                                                          float* __restrict__ eta,
+                                                          float* __restrict__ max_eta) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
+  float e32 = 0.f;
+  if (i < n) {
+    double ss = 0.0;
+    for (int64_t t = lane; t < d; t += 64) {
+      const double x = X[(size_t)i * ldx + t];
+      ss = fma(x, x, ss);
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) ss += __shfl_xor(ss, off, 64);
+    const double dev = fabs(sqrt(ss) - 1.0) + (double)(d + 4) * kU64 * 2.0 + 1e-300;
+    e32 = __double2float_ru(dev);
+    if (lane == 0) eta[i] = e32;
+  }
+  if (max_eta && lane == 0) atomicMax(reinterpret_cast<int*>(max_eta), __float_as_int(e32));
+}
+
+}  // namespace
+
+size_t dense_sim_lds_bytes(bool bf16, int dp) {
+  if (bf16) return (size_t)MfmaCfg<true>::CC * (dp + 8) * 2;
+  return (size_t)MfmaCfg<false>::CC * (dp + 4) * 4;
+}
+
+hipError_t launch_dense_sim(const DenseSimArgs& A, bool bf16, int mode, hipStream_t s) {
+  const int rows_per_block = (bf16 ? 64 : 32) * kDenseWaves;
+  int64_t blocks = (A.n_rows + rows_per_block - 1) / rows_per_block;
+  if (blocks > 4 * kMaxGridBlocks) blocks = 4 * kMaxGridBlocks;
+  if (blocks < 1) blocks = 1;
+  const size_t lds = dense_sim_lds_bytes(bf16, A.dp);
+  const dim3 grid((unsigned)blocks), block(kDenseWaves * 64);
+  if (bf16) {
+    if (mode == 0) hipLaunchKernelGGL((k_dense_sim<true, 0>), grid, block, lds, s, A);
+    else hipLaunchKernelGGL((k_dense_sim<true, 1>), grid, block, lds, s, A);
+  } else {
+    if (mode == 0) hipLaunchKernelGGL((k_dense_sim<false, 0>), grid, block, lds, s, A);
+    else hipLaunchKernelGGL((k_dense_sim<false, 1>), grid, block, lds, s, A);
+  }
+  return hipGetLastError();
+}
+
+namespace {
+unsigned nblocks(int64_t count, int per = kBlock) {
+  int64_t b = (count + per - 1) / per;
+  return (unsigned)(b < 1 ? 1 : b);
+}
+}  // namespace
+
+hipError_t launch_dense_post(const DensePostArgs& A, hipStream_t s) {
+  hipLaunchKernelGGL(k_dense_post, dim3(nblocks(A.n_rows)), dim3(kBlock), 0, s, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_dense_exact(const DenseExactArgs& A, int64_t max_rows, hipStream_t s) {
+  int64_t blocks = (max_rows * 64 + kBlock - 1) / kBlock;
+  if (blocks > 4 * kMaxGridBlocks) blocks = 4 * kMaxGridBlocks;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_dense_exact, dim3((unsigned)blocks), dim3(kBlock), 0, s, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_near(const int32_t* near_list, const unsigned long long* cnt,
+                              int64_t max_rows, const int32_t* rows, const float* thr_slot,
+                              int32_t* out_rows, float* out_thr, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_near, dim3(nblocks(max_rows)), dim3(kBlock), 0, s, near_list, cnt,
+                     rows, thr_slot, out_rows, out_thr);
+  return hipGetLastError();
+}
+
+hipError_t launch_dense_hamerly(const DenseHamerlyArgs& A, hipStream_t s) {
+  hipLaunchKernelGGL(k_dense_hamerly, dim3(nblocks(A.n * kDHG)), dim3(kBlock), 0, s, A);
+  return hipGetLastError();
+}
+
+int compact_blocks(int64_t nmax) { return (int)((nmax + kCompactChunk - 1) / kCompactChunk); }
+
+hipError_t launch_compact(const int32_t* flags, const unsigned long long* nptr, int64_t nmax,
+                          int32_t* bcnt, int32_t* boff, int32_t* list,
+                          unsigned long long* total, int32_t* zero_at, hipStream_t s) {
+  const int nb = compact_blocks(nmax);
+  hipLaunchKernelGGL(k_flags_count, dim3((unsigned)(nb < 1 ? 1 : nb)), dim3(kBlock), 0, s, flags,
+                     nptr, nmax, bcnt);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(kBlock), 0, s, bcnt, nb, boff, total);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_flags_scatter, dim3((unsigned)(nb < 1 ? 1 : nb)), dim3(kBlock), 0, s,
+                     flags, nptr, nmax, boff, list, zero_at);
+  return hipGetLastError();
+}
+
+hipError_t launch_cluster_sums(const int32_t* a, int64_t n, int32_t k, const float* X,
+                               int64_t ldx, int64_t d, double fx, int32_t* cnt, int32_t* start,
+                               int32_t* cursor, int32_t* perm, long long* S, int32_t* dirty,
+                               unsigned long long* scratch_total, hipStream_t s) {
+  hipError_t e = hipMemsetAsync(cnt, 0, (size_t)k * sizeof(int32_t), s);
+  if (e != hipSuccess) return e;
+  int64_t blocks = nblocks(n);
+  if (blocks > kMaxGridBlocks) blocks = kMaxGridBlocks;
+  hipLaunchKernelGGL(k_hist, dim3((unsigned)blocks), dim3(kBlock), (size_t)k * sizeof(int), s, a,
+                     n, k, cnt);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  // exclusive scan of the k counts (k <= 4096 fits one block's loop)
+  hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(kBlock), 0, s, cnt, k, start, scratch_total);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  e = hipMemcpyAsync(cursor, start, (size_t)k * sizeof(int32_t), hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_scatter_rows, dim3((unsigned)blocks), dim3(kBlock), 0, s, a, n, cursor,
+                     perm);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_cluster_sums, dim3((unsigned)k), dim3(kBlock), 0, s, perm, start, cnt, X,
+                     ldx, d, fx, S, dirty);
+  return hipGetLastError();
+}
+
+hipError_t launch_dense_update_scan(const float* X, int64_t ldx, const int32_t* a,
+                                    int32_t* a_old, int64_t n, int64_t d, double fx,
+                                    long long* S, int32_t* dirty, hipStream_t s) {
+  int64_t blocks = nblocks(n);
+  if (blocks > kMaxGridBlocks) blocks = kMaxGridBlocks;
+  hipLaunchKernelGGL(k_dense_update_scan, dim3((unsigned)blocks), dim3(kBlock), 0, s, X, ldx, a,
+                     a_old, n, d, fx, S, dirty);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_copy_assign, dim3(nblocks(n)), dim3(kBlock), 0, s, a, a_old, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_assign(const int32_t* a, int32_t* a_old, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy_assign, dim3(nblocks(n)), dim3(kBlock), 0, s, a, a_old, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_rows_to_bf16(const float* X, int64_t ldx, int64_t n, int64_t d, int dp,
+                               void* Xb, hipStream_t s) {
+  hipLaunchKernelGGL(k_rows_to_bf16, dim3(nblocks(n * dp)), dim3(kBlock), 0, s, X, ldx, n, d, dp,
+                     reinterpret_cast<__bf16*>(Xb));
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_centres(const double* C64, int32_t k, int64_t d, int dp,
+                               const int32_t* dirty, int bf16, void* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_pack_centres, dim3((unsigned)k), dim3(kBlock), 0, s, C64, k, d, dp, dirty,
+                     bf16, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_dense_row_eta(const float* X, int64_t ldx, int64_t n, int64_t d, float* eta,
+                                float* max_eta, hipStream_t s) {
+  hipLaunchKernelGGL(k_dense_row_eta, dim3(nblocks(n * 64)), dim3(kBlock), 0, s, X, ldx, n, d,
+                     eta, max_eta);
+  return hipGetLastError();
+}
+
+}  // namespace skm

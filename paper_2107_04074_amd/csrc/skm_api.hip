@@ -74,8 +74,14 @@ int check_matrix(const skm_matrix* X) {
     if (X->nnz < 0) return fail(SKM_ERR_INVALID_ARG, "nnz must be >= 0");
     return SKM_OK;
   }
-  if (X->fmt == SKM_DENSE_F32)
-    return fail(SKM_ERR_UNSUPPORTED, "dense input is not supported by this build");
+  if (X->fmt == SKM_DENSE_F32) {
+    if (!X->dense) return fail(SKM_ERR_INVALID_ARG, "dense pointer must not be NULL");
+    if (X->ld < X->d) return fail(SKM_ERR_INVALID_ARG, "need ld >= d");
+    if (X->d > 256)
+      return fail(SKM_ERR_UNSUPPORTED, "dense input supports d <= 256 (MFMA operand tiles "
+                  "are held in registers), got %lld", (long long)X->d);
+    return SKM_OK;
+  }
   return fail(SKM_ERR_INVALID_ARG, "unknown matrix format %d", (int)X->fmt);
 }
 
@@ -195,6 +201,444 @@ double fixed_point_scale(int64_t n) {
   return std::ldexp(1.0, 61 - bits);
 }
 
+
+// ------------------------------------------------------------------------
+// dense rows (MFMA path)
+// ------------------------------------------------------------------------
+struct DensePlan {
+  int64_t n = 0, d = 0;
+  int32_t k = 0, kpad = 0, dp = 0;
+  bool bf16 = false, bounds = false, gram = false;
+  int nchunk = 1, nslice = 1, nb = 1;
+  int64_t slice_len = 0;
+  int32_t cap = 16;  // candidate slots per flagged row
+  size_t Xb = 0, Cp = 0, C64 = 0, S = 0, eta = 0, a_old = 0, l = 0, u = 0, best = 0, best_j = 0,
+         second = 0, thr = 0, near = 0, rflag = 0, rows = 0, nlist = 0, nrows = 0, nthr = 0,
+         bcnt = 0, boff = 0, cand = 0, cand_n = 0, ccnt = 0, cstart = 0, ccur = 0, perm = 0,
+         norm64 = 0, part = 0, part_sq = 0, pc = 0, ps = 0, dirty = 0, mm = 0, G = 0, gmax = 0,
+         gpart = 0, cnt = 0, per = 0, maxeta = 0, initnorm = 0, total = 0;
+};
+
+int make_dense_plan(const skm_matrix* X, int32_t k, int32_t variant, int32_t precision,
+                    DensePlan* P) {
+  int rc = check_matrix(X);
+  if (rc != SKM_OK) return rc;
+  if (k < 1 || (int64_t)k > X->n) return fail(SKM_ERR_INVALID_ARG, "need 1 <= k <= n");
+  if (variant < SKM_LLOYD || variant > SKM_SIMP_HAMERLY)
+    return fail(SKM_ERR_INVALID_ARG, "unknown variant %d", (int)variant);
+  if (variant == SKM_ELKAN || variant == SKM_SIMP_ELKAN)
+    return fail(SKM_ERR_UNSUPPORTED, "Elkan variants are implemented for CSR input only");
+  if (precision != 0 && precision != 1)
+    return fail(SKM_ERR_INVALID_ARG, "precision must be 0 (fp32) or 1 (bf16)");
+  P->n = X->n;
+  P->d = X->d;
+  P->k = k;
+  P->kpad = (k + 63) / 64 * 64;
+  P->dp = (int32_t)((X->d + 31) / 32 * 32);
+  P->bf16 = precision == 1;
+  P->bounds = variant != SKM_LLOYD;
+  P->gram = variant == SKM_HAMERLY;
+  P->nchunk = (int)((X->d + 4095) / 4096);
+  P->nb = compact_blocks(X->n);
+  {
+    const int nt = (k + 63) / 64;
+    const int tiles = nt * (nt + 1) / 2;
+    int ns = (512 + tiles - 1) / tiles;
+    const int64_t max_ns = std::max<int64_t>(1, X->d / 256);
+    if (ns > max_ns) ns = (int)max_ns;
+    if (ns < 1) ns = 1;
+    int64_t len = (X->d + ns - 1) / ns;
+    len = (len + 15) / 16 * 16;
+    P->slice_len = len;
+    P->nslice = (int)((X->d + len - 1) / len);
+  }
+  size_t cur = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = cur;
+    cur += align256(bytes);
+    return o;
+  };
+  const size_t n = (size_t)X->n, d = (size_t)X->d, kk = (size_t)k;
+  const size_t es = P->bf16 ? 2 : 4;
+  if (P->bf16) P->Xb = take(n * (size_t)P->dp * 2);
+  P->Cp = take((size_t)P->kpad * P->dp * es);
+  P->C64 = take(kk * d * sizeof(double));
+  P->S = take(kk * d * sizeof(long long));
+  P->eta = take(n * 4);
+  P->a_old = take(n * 4);
+  if (P->bounds) {
+    P->l = take(n * 4);
+    P->u = take(n * 4);
+    P->rflag = take(n * 4);
+    P->rows = take(n * 4);
+  }
+  P->best = take(n * 4);
+  P->best_j = take(n * 4);
+  P->second = take(n * 4);
+  P->thr = take(n * 4);
+  P->near = take(n * 4);
+  P->nlist = take(n * 4);
+  P->nrows = take(n * 4);
+  P->nthr = take(n * 4);
+  P->bcnt = take((size_t)P->nb * 4);
+  P->boff = take((size_t)P->nb * 4);
+  P->cand = take(n * (size_t)P->cap * 4);
+  P->cand_n = take(n * 4);
+  P->ccnt = take(kk * 4);
+  P->cstart = take(kk * 4);
+  P->ccur = take(kk * 4);
+  P->perm = take(n * 4);
+  P->norm64 = take(kk * 8);
+  P->part = take(kk * (size_t)P->nchunk * 8);
+  P->part_sq = take(kk * (size_t)P->nchunk * 8);
+  P->pc = take(kk * 8);
+  P->ps = take(kk * 8);
+  P->dirty = take(kk * 4);
+  P->mm = take(sizeof(MoveMin));
+  if (P->gram) {
+    P->G = take(kk * kk * 8);
+    P->gmax = take(kk * 8);
+    P->gpart = take((size_t)P->nslice * kk * kk * 8);
+  }
+  P->cnt = take(kCounterSlots * sizeof(Counters) + sizeof(Persist));
+  P->per = P->cnt + kCounterSlots * sizeof(Counters);
+  P->maxeta = take(4);
+  P->initnorm = take(kk * 8);
+  P->total = cur;
+  return SKM_OK;
+}
+
+struct DenseRun {
+  const DensePlan& P;
+  const skm_matrix* X;
+  void* ws;
+  hipStream_t s;
+  template <typename T>
+  T* ptr(size_t off) const {
+    return at<T>(ws, off);
+  }
+};
+
+// One assignment step over dense rows: similarity pass on MFMA (all rows, or
+// the compacted rows that failed the Hamerly tests), decision, candidate pass
+// for the rows inside the error band, FP64 re-decision.
+hipError_t dense_step(const DenseRun& R, int32_t* a, int read_prev, const int32_t* rows,
+                      const unsigned long long* rows_count, float* best_out, float* second_out,
+                      Counters* cnt) {
+  const DensePlan& P = R.P;
+  const skm_matrix* X = R.X;
+  Persist* per = R.ptr<Persist>(P.per);
+  hipError_t e;
+  DenseSimArgs S1{};
+  S1.X = P.bf16 ? (const void*)R.ptr<char>(P.Xb) : (const void*)X->dense;
+  S1.ldx = P.bf16 ? P.dp : X->ld;
+  S1.C = R.ptr<char>(P.Cp);
+  S1.k = P.k;
+  S1.kpad = P.kpad;
+  S1.dp = P.dp;
+  S1.d = (int32_t)P.d;
+  S1.rows = rows;
+  S1.rows_count = rows_count;
+  S1.n_rows = P.n;
+  S1.best = R.ptr<float>(P.best);
+  S1.best_j = R.ptr<int32_t>(P.best_j);
+  S1.second = R.ptr<float>(P.second);
+  if ((e = launch_dense_sim(S1, P.bf16, 0, R.s)) != hipSuccess) return e;
+  DensePostArgs Q{};
+  Q.rows = rows;
+  Q.rows_count = rows_count;
+  Q.n_rows = P.n;
+  Q.k = P.k;
+  Q.dp = P.dp;
+  Q.bf16 = P.bf16;
+  Q.read_prev = read_prev;
+  Q.best = S1.best;
+  Q.best_j = S1.best_j;
+  Q.second = S1.second;
+  Q.eta = R.ptr<float>(P.eta);
+  Q.delta_c = (double)(P.d + 8) * kU64 * 1.01 + 1e-300;
+  Q.a = a;
+  Q.l = P.bounds ? R.ptr<float>(P.l) : nullptr;
+  Q.u = P.bounds ? R.ptr<float>(P.u) : nullptr;
+  Q.near = R.ptr<int32_t>(P.near);
+  Q.thr = R.ptr<float>(P.thr);
+  Q.best_out = best_out;
+  Q.second_out = second_out;
+  Q.cnt = cnt;
+  if ((e = launch_dense_post(Q, R.s)) != hipSuccess) return e;
+  // flagged slots -> list (clears their candidate counters)
+  if ((e = launch_compact(Q.near, rows_count, P.n, R.ptr<int32_t>(P.bcnt),
+                          R.ptr<int32_t>(P.boff), R.ptr<int32_t>(P.nlist), &per->near_total,
+                          R.ptr<int32_t>(P.cand_n), R.s)) != hipSuccess)
+    return e;
+  if ((e = launch_gather_near(R.ptr<int32_t>(P.nlist), &per->near_total, P.n, rows, Q.thr,
+                              R.ptr<int32_t>(P.nrows), R.ptr<float>(P.nthr), R.s)) != hipSuccess)
+    return e;
+  DenseSimArgs S2 = S1;
+  S2.rows = R.ptr<int32_t>(P.nrows);
+  S2.rows_count = &per->near_total;
+  S2.thr = R.ptr<float>(P.nthr);
+  S2.cand = R.ptr<int32_t>(P.cand);
+  S2.cand_n = R.ptr<int32_t>(P.cand_n);
+  S2.cand_cap = P.cap;
+  if ((e = launch_dense_sim(S2, P.bf16, 1, R.s)) != hipSuccess) return e;
+  DenseExactArgs E{};
+  E.X = X->dense;
+  E.ldx = X->ld;
+  E.C64 = R.ptr<double>(P.C64);
+  E.k = P.k;
+  E.d = (int32_t)P.d;
+  E.dp = P.dp;
+  E.bf16 = P.bf16;
+  E.read_prev = read_prev;
+  E.rows = rows;
+  E.near_list = R.ptr<int32_t>(P.nlist);
+  E.near_count = &per->near_total;
+  E.cand = S2.cand;
+  E.cand_n = S2.cand_n;
+  E.cand_cap = P.cap;
+  E.best = S1.best;
+  E.best_j = S1.best_j;
+  E.eta = Q.eta;
+  E.delta_c = Q.delta_c;
+  E.a = a;
+  E.l = Q.l;
+  E.u = Q.u;
+  E.best_out = best_out;
+  E.second_out = second_out;
+  E.cnt = cnt;
+  return launch_dense_exact(E, P.n, R.s);
+}
+
+int fit_dense(const skm_matrix* X, int32_t k, const float* init_centers, int32_t variant,
+              int32_t max_iter, const skm_options& o, void* workspace, size_t workspace_bytes,
+              int32_t* assign_out, float* centers_out, double* centers64_out, skm_stats* stats,
+              hipStream_t s) {
+  DensePlan P;
+  int rc = make_dense_plan(X, k, variant, o.precision, &P);
+  if (rc != SKM_OK) return rc;
+  if (workspace && workspace_bytes < P.total)
+    return fail(SKM_ERR_OUT_OF_MEMORY, "workspace has %zu bytes, %zu needed", workspace_bytes,
+                P.total);
+  HostMirror* hm = host_mirror();
+  if (!hm) return fail(SKM_ERR_HIP, "could not allocate pinned host memory");
+  bool owned = false;
+  void* ws = workspace;
+  if (!ws) {
+    if (hipMallocAsync(&ws, P.total, s) != hipSuccess)
+      return fail(SKM_ERR_OUT_OF_MEMORY, "could not allocate %zu bytes of workspace", P.total);
+    owned = true;
+  }
+  DenseRun R{P, X, ws, s};
+  const int64_t n = P.n, d = P.d;
+  const double delta_c = (double)(d + 8) * kU64 * 1.01 + 1e-300;
+  const double delta_g = (double)(d + 2) * kU64 * 1.01 + 2.0 * delta_c + 1e-15;
+  const double fx = fixed_point_scale(n);
+  const double fx_inv = 1.0 / fx;
+  double* C64 = R.ptr<double>(P.C64);
+  long long* S = R.ptr<long long>(P.S);
+  int32_t* a_old = R.ptr<int32_t>(P.a_old);
+  int32_t* dirty = R.ptr<int32_t>(P.dirty);
+  Counters* cnt = R.ptr<Counters>(P.cnt);
+  Persist* per = R.ptr<Persist>(P.per);
+  double* part = R.ptr<double>(P.part);
+  double* part_sq = R.ptr<double>(P.part_sq);
+  double* norm64 = R.ptr<double>(P.norm64);
+  double* pc = R.ptr<double>(P.pc);
+  double* ps = R.ptr<double>(P.ps);
+  MoveMin* mm = R.ptr<MoveMin>(P.mm);
+  double* G = P.gram ? R.ptr<double>(P.G) : nullptr;
+  double* gmax = P.gram ? R.ptr<double>(P.gmax) : nullptr;
+  double* gpart = P.gram ? R.ptr<double>(P.gpart) : nullptr;
+  void* Cp = R.ptr<char>(P.Cp);
+  int32_t iterations = 0, converged = 0;
+  int64_t tot_sims = 0, tot_rechecks = 0, sk_launches = 0, sk_rows = 0;
+  double objective = 0.0, sk_ms = 0.0, tight_rate = 1.0;
+  bool first_gram = true;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  {
+    if (o.profile) {
+      SKM_HIP(hipEventCreate(&ev0));
+      SKM_HIP(hipEventCreate(&ev1));
+    }
+    SKM_HIP(hipMemsetAsync(Cp, 0, (size_t)P.kpad * P.dp * (P.bf16 ? 2 : 4), s));
+    SKM_HIP(hipMemsetAsync(per, 0, sizeof(Persist), s));
+    SKM_HIP(hipMemsetAsync(dirty, 0, (size_t)k * 4, s));
+    SKM_HIP(hipMemsetAsync(norm64, 0, (size_t)k * 8, s));
+    SKM_HIP(hipMemsetAsync(R.ptr<float>(P.maxeta), 0, 4, s));
+    SKM_HIP(launch_fill_i32(a_old, n, -1, s));
+    SKM_HIP(launch_dense_row_eta(X->dense, X->ld, n, d, R.ptr<float>(P.eta),
+                                 R.ptr<float>(P.maxeta), s));
+    SKM_HIP(launch_init_centres(init_centers, k, d, 1, C64, R.ptr<double>(P.initnorm), s));
+    SKM_HIP(launch_pack_centres(C64, k, d, P.dp, nullptr, P.bf16, Cp, s));
+    if (P.bf16) SKM_HIP(launch_rows_to_bf16(X->dense, X->ld, n, d, P.dp, R.ptr<char>(P.Xb), s));
+    if (o.validate >= 1) {
+      float hmax = 0.f;
+      SKM_HIP(hipMemcpyAsync(&hmax, R.ptr<float>(P.maxeta), 4, hipMemcpyDeviceToHost, s));
+      SKM_HIP(hipStreamSynchronize(s));
+      if (o.validate >= 2 && !((double)hmax <= o.norm_tol)) {
+        rc = fail(SKM_ERR_NOT_NORMALIZED, "a data row deviates from unit norm by %.3g", hmax);
+        goto done;
+      }
+    }
+    for (int32_t t = 0; t < max_iter; ++t) {
+      SKM_HIP(hipMemsetAsync(cnt, 0, kCounterSlots * sizeof(Counters), s));
+      const bool exhaustive = t == 0 || variant == SKM_LLOYD;
+      const int32_t* rows = nullptr;
+      const unsigned long long* rows_count = nullptr;
+      if (ev0) SKM_HIP(hipEventRecord(ev0, s));
+      if (!exhaustive) {
+        DenseHamerlyArgs H{};
+        H.X = X->dense;
+        H.ldx = X->ld;
+        H.C64 = C64;
+        H.k = k;
+        H.d = (int32_t)d;
+        H.n = n;
+        H.a = assign_out;
+        H.l = R.ptr<float>(P.l);
+        H.u = R.ptr<float>(P.u);
+        H.eta = R.ptr<float>(P.eta);
+        H.pc = pc;
+        H.ps = ps;
+        H.mm = mm;
+        H.gmax = gmax;
+        H.delta_c = delta_c;
+        H.simplified = variant == SKM_SIMP_HAMERLY;
+        H.bound_form = o.bound_form;
+        H.try_tighten = (t <= 2 || tight_rate >= 0.2 || t % 4 == 0) ? 1 : 0;
+        H.flag = R.ptr<int32_t>(P.rflag);
+        H.cnt = cnt;
+        SKM_HIP(launch_dense_hamerly(H, s));
+        SKM_HIP(launch_compact(H.flag, nullptr, n, R.ptr<int32_t>(P.bcnt), R.ptr<int32_t>(P.boff),
+                               R.ptr<int32_t>(P.rows), &per->list_total, nullptr, s));
+        rows = R.ptr<int32_t>(P.rows);
+        rows_count = &per->list_total;
+      }
+      SKM_HIP(dense_step(R, assign_out, t > 0 ? 1 : 0, rows, rows_count, nullptr, nullptr, cnt));
+      if (ev1) SKM_HIP(hipEventRecord(ev1, s));
+      SKM_HIP(hipMemcpyAsync(hm, cnt, sizeof(HostMirror), hipMemcpyDeviceToHost, s));
+      SKM_HIP(hipStreamSynchronize(s));
+      const Counters tc = sum_slots(hm);
+      const int64_t changed = (int64_t)tc.changed;
+      const int64_t walked = exhaustive ? n : (int64_t)hm->per.list_total;
+      if (ev0) {
+        float ms = 0.f;
+        SKM_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+        sk_ms += ms;
+      }
+      if (tc.tightened > 0) tight_rate = (double)tc.tight_saved / (double)tc.tightened;
+      const int64_t step_sims = walked * (int64_t)k + (int64_t)tc.sims;
+      sk_launches += 1;
+      sk_rows += walked;
+      tot_sims += step_sims;
+      tot_rechecks += (int64_t)tc.rechecks;
+      if (t > 0) objective = hm->per.objective;
+      if (stats && t < stats->per_iter_len) {
+        if (stats->changed_per_iter) stats->changed_per_iter[t] = changed;
+        if (stats->sims_per_iter) stats->sims_per_iter[t] = step_sims;
+        if (stats->objective_per_iter && t > 0 && t - 1 < stats->per_iter_len)
+          stats->objective_per_iter[t - 1] = hm->per.objective;
+      }
+      iterations = t + 1;
+      if (changed == 0) {
+        converged = 1;
+        break;
+      }
+      // centre step: recompute all sums when many rows moved, else apply
+      // the moved rows (both give the same fixed-point sums)
+      if (t == 0 || changed * 32 > n) {
+        SKM_HIP(launch_cluster_sums(assign_out, n, k, X->dense, X->ld, d, fx,
+                                    R.ptr<int32_t>(P.ccnt), R.ptr<int32_t>(P.cstart),
+                                    R.ptr<int32_t>(P.ccur), R.ptr<int32_t>(P.perm), S, dirty,
+                                    &per->scan_dummy, s));
+        SKM_HIP(launch_copy_assign(assign_out, a_old, n, s));
+      } else {
+        SKM_HIP(launch_dense_update_scan(X->dense, X->ld, assign_out, a_old, n, d, fx, S, dirty,
+                                         s));
+      }
+      SKM_HIP(launch_sumsq_partial(S, k, d, fx_inv, dirty, part_sq, P.nchunk, s));
+      SKM_HIP(launch_normalize_move(S, k, d, fx_inv, dirty, part_sq, C64, part, P.nchunk, s));
+      SKM_HIP(launch_centre_finalize(k, d, dirty, norm64, part_sq, part, P.nchunk, delta_c, pc,
+                                     ps, mm, per, s));
+      SKM_HIP(launch_pack_centres(C64, k, d, P.dp, dirty, P.bf16, Cp, s));
+      if (P.gram) {
+        SKM_HIP(launch_gram(C64, k, d, dirty, first_gram ? 1 : 0, gpart, P.nslice, P.slice_len,
+                            G, gmax, delta_g, per, s));
+        first_gram = false;
+      }
+      SKM_HIP(launch_clear_dirty(dirty, k, s));
+    }
+    SKM_HIP(hipMemcpyAsync(&hm->per, per, sizeof(Persist), hipMemcpyDeviceToHost, s));
+    if (centers_out) SKM_HIP(launch_c64_to_f32(C64, (int64_t)k * d, centers_out, s));
+    if (centers64_out)
+      SKM_HIP(hipMemcpyAsync(centers64_out, C64, (size_t)k * d * sizeof(double),
+                             hipMemcpyDeviceToDevice, s));
+    SKM_HIP(hipStreamSynchronize(s));
+    objective = hm->per.objective;
+    if (stats) {
+      stats->iterations = iterations;
+      stats->converged = converged;
+      stats->objective = objective;
+      stats->sims_point_center = tot_sims;
+      stats->sims_center_center = (int64_t)hm->per.ccsims;
+      stats->rechecks = tot_rechecks;
+      if (stats->objective_per_iter && iterations - 1 < stats->per_iter_len)
+        stats->objective_per_iter[iterations - 1] = objective;
+      stats->sim_kernel_launches = sk_launches;
+      stats->sim_kernel_rows = sk_rows;
+      stats->sim_kernel_nnz = sk_rows * d;
+      stats->sim_kernel_ms = sk_ms;
+    }
+  }
+done:
+  if (ev0) (void)hipEventDestroy(ev0);
+  if (ev1) (void)hipEventDestroy(ev1);
+  if (owned) {
+    (void)hipFreeAsync(ws, s);
+    if (rc == SKM_OK) {
+      hipError_t e = hipStreamSynchronize(s);
+      if (e != hipSuccess) rc = fail(SKM_ERR_HIP, "final synchronise: %s", hipGetErrorString(e));
+    }
+  }
+  return rc;
+}
+
+
+int assign_dense(const skm_matrix* X, int32_t k, const float* centers, int32_t* assign_out,
+                 float* best_out, float* second_out, void* workspace, size_t workspace_bytes,
+                 hipStream_t s) {
+  DensePlan P;
+  int rc = make_dense_plan(X, k, SKM_LLOYD, 0, &P);
+  if (rc != SKM_OK) return rc;
+  if (workspace && workspace_bytes < P.total)
+    return fail(SKM_ERR_OUT_OF_MEMORY, "workspace has %zu bytes, %zu needed", workspace_bytes,
+                P.total);
+  bool owned = false;
+  void* ws = workspace;
+  if (!ws) {
+    if (hipMallocAsync(&ws, P.total, s) != hipSuccess)
+      return fail(SKM_ERR_OUT_OF_MEMORY, "could not allocate %zu bytes of workspace", P.total);
+    owned = true;
+  }
+  DenseRun R{P, X, ws, s};
+  {
+    void* Cp = R.ptr<char>(P.Cp);
+    double* C64 = R.ptr<double>(P.C64);
+    SKM_HIP(hipMemsetAsync(Cp, 0, (size_t)P.kpad * P.dp * 4, s));
+    SKM_HIP(hipMemsetAsync(R.ptr<Persist>(P.per), 0, sizeof(Persist), s));
+    SKM_HIP(hipMemsetAsync(R.ptr<Counters>(P.cnt), 0, kCounterSlots * sizeof(Counters), s));
+    SKM_HIP(launch_dense_row_eta(X->dense, X->ld, P.n, P.d, R.ptr<float>(P.eta), nullptr, s));
+    SKM_HIP(launch_init_centres(centers, k, P.d, 0, C64, nullptr, s));
+    SKM_HIP(launch_pack_centres(C64, k, P.d, P.dp, nullptr, 0, Cp, s));
+    SKM_HIP(dense_step(R, assign_out, 0, nullptr, nullptr, best_out, second_out,
+                       R.ptr<Counters>(P.cnt)));
+  }
+done:
+  if (owned) (void)hipFreeAsync(ws, s);
+  return rc;
+}
+
 }  // namespace
 }  // namespace skm
 
@@ -220,13 +664,22 @@ const char* skm_last_error(void) { return g_last_error.c_str(); }
 
 size_t skm_workspace_size(const skm_matrix* X, int32_t k, int32_t variant,
                           const skm_options* opt) {
-  (void)opt;
+  if (X && X->fmt == SKM_DENSE_F32) {
+    DensePlan D;
+    if (make_dense_plan(X, k, variant, opt ? opt->precision : 0, &D) != SKM_OK) return 0;
+    return D.total;
+  }
   Plan P;
   if (make_plan(X, k, variant, &P) != SKM_OK) return 0;
   return P.total;
 }
 
 size_t skm_assign_workspace_size(const skm_matrix* X, int32_t k) {
+  if (X && X->fmt == SKM_DENSE_F32) {
+    DensePlan D;
+    if (make_dense_plan(X, k, SKM_LLOYD, 0, &D) != SKM_OK) return 0;
+    return D.total;
+  }
   if (check_matrix(X) != SKM_OK) return 0;
   if (k < 1) {
     fail(SKM_ERR_INVALID_ARG, "need k >= 1");
@@ -249,6 +702,9 @@ int skm_assign(const skm_matrix* X, int32_t k, const float* centers, int32_t* as
   if (rc != SKM_OK) return rc;
   if (k < 1) return fail(SKM_ERR_INVALID_ARG, "need k >= 1");
   if (!centers || !assign_out) return fail(SKM_ERR_INVALID_ARG, "centers/assign_out NULL");
+  if (X->fmt == SKM_DENSE_F32)
+    return assign_dense(X, k, centers, assign_out, best_sim_out, second_sim_out, workspace,
+                        workspace_bytes, static_cast<hipStream_t>(stream));
   const Geometry g = pick_geometry(k);
   if (g.G == 0) return fail(SKM_ERR_UNSUPPORTED, "k = %d exceeds the supported 4096", (int)k);
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -295,9 +751,7 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
             int32_t* assign_out, float* centers_out, double* centers64_out, skm_stats* stats,
             void* stream) {
   g_last_error.clear();
-  Plan P;
-  int rc = make_plan(X, k, variant, &P);
-  if (rc != SKM_OK) return rc;
+  if (!X) return fail(SKM_ERR_INVALID_ARG, "X is NULL");
   if (!init_centers || !assign_out) return fail(SKM_ERR_INVALID_ARG, "init/assign_out NULL");
   if (max_iter < 1) return fail(SKM_ERR_INVALID_ARG, "need max_iter >= 1");
   skm_options o{};
@@ -305,6 +759,12 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
   if (o.norm_tol <= 0.0) o.norm_tol = 1e-4;
   if (o.bound_form != 0 && o.bound_form != 1)
     return fail(SKM_ERR_INVALID_ARG, "bound_form must be 0 or 1");
+  if (X->fmt == SKM_DENSE_F32)
+    return fit_dense(X, k, init_centers, variant, max_iter, o, workspace, workspace_bytes,
+                     assign_out, centers_out, centers64_out, stats, static_cast<hipStream_t>(stream));
+  Plan P;
+  int rc = make_plan(X, k, variant, &P);
+  if (rc != SKM_OK) return rc;
   if (o.precision != 0)
     return fail(SKM_ERR_UNSUPPORTED, "bf16 precision needs dense input");
   if (workspace && workspace_bytes < P.total)

@@ -33,7 +33,10 @@ struct Counters {                 // one 128-byte line
 struct Persist {
   double objective;               // sum_j |S_j| after the last update
   unsigned long long ccsims;      // centre-centre inner products (whole fit)
-  double pad[14];
+  unsigned long long list_total;  // rows of the current step's row list
+  unsigned long long near_total;  // rows re-decided from candidates
+  unsigned long long scan_dummy;
+  double pad[11];
 };
 
 __device__ __forceinline__ Counters* counter_slot(Counters* base) {
@@ -114,6 +117,118 @@ struct ElkanArgs {
   int32_t simplified;
   Counters* cnt;
 };
+
+struct DenseSimArgs {
+  const void* X;              // rows: bf16 (padded copy) or f32 (caller), n x ldx
+  int64_t ldx;
+  const void* C;              // packed centres: bf16 or f32, kpad x dp
+  int32_t k, kpad, dp, d;
+  const int32_t* rows;        // nullable: identity
+  const unsigned long long* rows_count;  // nullable: n_rows
+  int64_t n_rows;
+  float* best;                // per slot (top-2 mode)
+  int32_t* best_j;
+  float* second;
+  const float* thr;           // per slot (candidate mode)
+  int32_t* cand;              // slot x cand_cap
+  int32_t* cand_n;
+  int32_t cand_cap;
+};
+
+struct DensePostArgs {
+  const int32_t* rows;
+  const unsigned long long* rows_count;
+  int64_t n_rows;
+  int32_t k, dp;
+  int32_t bf16;
+  int32_t read_prev;
+  const float* best;
+  const int32_t* best_j;
+  const float* second;
+  const float* eta;
+  double delta_c;
+  int32_t* a;
+  float* l;
+  float* u;
+  int32_t* near;              // per slot flag
+  float* thr;                 // per slot threshold of the candidate pass
+  float* best_out;            // nullable raw outputs (assign entry point)
+  float* second_out;
+  Counters* cnt;
+};
+
+struct DenseExactArgs {
+  const float* X;             // caller's FP32 rows
+  int64_t ldx;
+  const double* C64;
+  int32_t k, d, dp;
+  int32_t bf16;
+  int32_t read_prev;
+  const int32_t* rows;        // slot -> row of the similarity pass (nullable)
+  const int32_t* near_list;   // candidate-pass index -> slot
+  const unsigned long long* near_count;
+  const int32_t* cand;
+  const int32_t* cand_n;
+  int32_t cand_cap;
+  const float* best;          // per slot
+  const int32_t* best_j;
+  const float* eta;
+  double delta_c;
+  int32_t* a;
+  float* l;
+  float* u;
+  float* best_out;            // nullable raw outputs (assign entry point)
+  float* second_out;
+  Counters* cnt;
+};
+
+struct DenseHamerlyArgs {
+  const float* X;
+  int64_t ldx;
+  const double* C64;
+  int32_t k, d;
+  int64_t n;
+  const int32_t* a;
+  float* l;
+  float* u;
+  const float* eta;
+  const double* pc;
+  const double* ps;
+  const MoveMin* mm;
+  const double* gmax;
+  double delta_c;
+  int32_t simplified, bound_form, try_tighten;
+  int32_t* flag;
+  Counters* cnt;
+};
+
+// ---- launchers (kernels_dense.hip) ----
+size_t dense_sim_lds_bytes(bool bf16, int dp);
+hipError_t launch_dense_sim(const DenseSimArgs& A, bool bf16, int mode, hipStream_t s);
+hipError_t launch_dense_post(const DensePostArgs& A, hipStream_t s);
+hipError_t launch_dense_exact(const DenseExactArgs& A, int64_t max_rows, hipStream_t s);
+hipError_t launch_dense_hamerly(const DenseHamerlyArgs& A, hipStream_t s);
+hipError_t launch_gather_near(const int32_t* near_list, const unsigned long long* cnt,
+                              int64_t max_rows, const int32_t* rows, const float* thr_slot,
+                              int32_t* out_rows, float* out_thr, hipStream_t s);
+int compact_blocks(int64_t nmax);
+hipError_t launch_compact(const int32_t* flags, const unsigned long long* nptr, int64_t nmax,
+                          int32_t* bcnt, int32_t* boff, int32_t* list,
+                          unsigned long long* total, int32_t* zero_at, hipStream_t s);
+hipError_t launch_cluster_sums(const int32_t* a, int64_t n, int32_t k, const float* X,
+                               int64_t ldx, int64_t d, double fx, int32_t* cnt, int32_t* start,
+                               int32_t* cursor, int32_t* perm, long long* S, int32_t* dirty,
+                               unsigned long long* scratch_total, hipStream_t s);
+hipError_t launch_dense_update_scan(const float* X, int64_t ldx, const int32_t* a,
+                                    int32_t* a_old, int64_t n, int64_t d, double fx,
+                                    long long* S, int32_t* dirty, hipStream_t s);
+hipError_t launch_copy_assign(const int32_t* a, int32_t* a_old, int64_t n, hipStream_t s);
+hipError_t launch_rows_to_bf16(const float* X, int64_t ldx, int64_t n, int64_t d, int dp,
+                               void* Xb, hipStream_t s);
+hipError_t launch_pack_centres(const double* C64, int32_t k, int64_t d, int dp,
+                               const int32_t* dirty, int bf16, void* out, hipStream_t s);
+hipError_t launch_dense_row_eta(const float* X, int64_t ldx, int64_t n, int64_t d, float* eta,
+                                float* max_eta, hipStream_t s);
 
 // ---- launchers (kernels_assign.hip) ----
 hipError_t launch_assign(const AssignArgs& A, int mode, hipStream_t s);

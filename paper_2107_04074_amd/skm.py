@@ -135,6 +135,35 @@ class DeviceCSR:
 
 
 @dataclass
+class DeviceDense:
+    """Dense row-major float32 matrix resident on the GPU (n x ld, first d
+    columns used)."""
+    X: "object"  # torch.float32 [n, ld]
+    d: int = 0
+
+    def __post_init__(self):
+        if not self.d:
+            self.d = int(self.X.shape[1])
+
+    @property
+    def n(self) -> int:
+        return int(self.X.shape[0])
+
+    @property
+    def col(self):  # device of the matrix (shared with DeviceCSR)
+        return self.X
+
+    @staticmethod
+    def from_host(Xh: np.ndarray, device="cuda") -> "DeviceDense":
+        import torch
+        return DeviceDense(torch.from_numpy(np.ascontiguousarray(Xh, np.float32)).to(device))
+
+    def matrix(self) -> SkmMatrix:
+        return SkmMatrix(DENSE_F32, 0, self.n, self.d, 0, None, None, None, _ptr(self.X),
+                         int(self.X.stride(0)))
+
+
+@dataclass
 class FitStats:
     iterations: int
     converged: bool

@@ -43,7 +43,7 @@ def gap_of(S):
     return part[:, -1] - part[:, -2]
 
 
-def check_assign(X, C32, a_gpu, best_gpu, label):
+def check_assign(X, C32, a_gpu, best_gpu, label, terms=None):
     a_ref, s1, s2 = oracle.assign(X, C32.astype(np.float64))
     gap = s1 - s2 if C32.shape[0] > 1 else np.full(X.n, np.inf)
     clear = gap > GAP
@@ -55,7 +55,7 @@ def check_assign(X, C32, a_gpu, best_gpu, label):
     assert np.all(s1 - np.take_along_axis(
         oracle.sims(X, C32.astype(np.float64), np.arange(X.n)), a_gpu[:, None].astype(np.int64),
         1)[:, 0] <= 1e-12)
-    m = X.row_lengths()
+    m = X.row_lengths() if terms is None else terms
     err = np.abs(best_gpu.astype(np.float64) - s1)
     assert np.all(err <= (m + 3) * 2.0 ** -24 * 1.02 + 1e-12)
     return a_ref
@@ -253,3 +253,86 @@ def test_fit_c3_full_size_sampled(skm, torch_cuda):
     sample = np.random.default_rng(1).choice(X.n, 1000, replace=False)
     sampled_step_check(X, out["lloyd"][0], C_prev, a_prev, out["lloyd"][2], sample,
                        "c3 t=%d" % T)
+
+
+# ----------------------------------------------------------------- dense (MFMA)
+
+def dense_csr(D):
+    n, d = D.shape
+    rp = np.arange(0, n * d + 1, d, dtype=np.int64)
+    return datagen.CSR(n, d, rp, np.tile(np.arange(d, dtype=np.int32), n),
+                       np.ascontiguousarray(D, np.float32).ravel())
+
+
+@pytest.mark.parametrize("d,k", [(64, 10), (200, 100), (256, 700), (37, 5)])
+def test_dense_assign_matches_oracle(skm, torch_cuda, d, k):
+    torch = torch_cuda
+    say("case dense assign d=%d k=%d" % (d, k))
+    X = datagen.dense_vmf(3000, d, 16, 500 + d)
+    rng = np.random.default_rng(d + k)
+    C = X[rng.choice(X.shape[0], k, replace=False)].astype(np.float64)
+    C += 0.01 * rng.normal(size=C.shape)
+    C = (C / np.linalg.norm(C, axis=1, keepdims=True)).astype(np.float32)
+    Xd = skm.DeviceDense.from_host(X)
+    a, best, second = skm.assign(Xd, torch.from_numpy(C).cuda())
+    torch.cuda.synchronize()
+    check_assign(dense_csr(X), C, a.cpu().numpy(), best.cpu().numpy(), "dense assign",
+                 terms=(d + 31) // 32 * 32)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_dense_fit_small_matches_oracle(skm, torch_cuda, precision):
+    torch = torch_cuda
+    X = datagen.dense_vmf(20000, 256, 64, 4242)
+    init = datagen.init_rows(X.shape[0], 64, 4242)
+    C0 = X[init].copy()
+    Xd = skm.DeviceDense.from_host(X)
+    Xc = dense_csr(X)
+    ref = oracle.fit(Xc, C0, "lloyd", 40)
+    base = None
+    for v in ["lloyd", "hamerly", "simp_hamerly"]:
+        say("case dense fit precision=%d %s" % (precision, v))
+        a, C, C64, st = run_fit(skm, torch, Xd, C0, 64, v, 40, precision=precision)
+        say("  iters=%d sims=%d rechecks=%d (oracle iters %d)" % (
+            st.iterations, st.sims_point_center, st.rechecks, ref.iterations))
+        assert st.iterations == ref.iterations
+        assert np.array_equal(a, ref.a)
+        assert np.linalg.norm(C64 - ref.C, axis=1).max() < 1e-6
+        if base is None:
+            base = (a, C64)
+        else:
+            assert np.array_equal(a, base[0]) and np.array_equal(C64, base[1])
+
+
+def test_c4_full_size_bf16_subsample(skm, torch_cuda):
+    """Full c4 workload (n=2e6 vMF rows, d=256, k=4096), BF16 MFMA with
+    error-widened bounds: Hamerly equals Lloyd; one step checked against the
+    FP64 oracle on a 20,000-row subsample."""
+    torch = torch_cuda
+    cfg = datagen.C4
+    say("case c4 generate")
+    X = datagen.dense_vmf(cfg["n"], cfg["d"], cfg["n_means"], cfg["seed"])
+    init = datagen.init_rows(X.shape[0], cfg["k"], cfg["seed"])
+    C0 = X[init].copy()
+    Xd = skm.DeviceDense.from_host(X)
+    T = 3
+    out = {}
+    for v in ["lloyd", "hamerly"]:
+        say("case c4 bf16 %s max_iter=%d" % (v, T))
+        out[v] = run_fit(skm, torch, Xd, C0, cfg["k"], v, T, precision=1)
+        say("  sims=%d rechecks=%d" % (out[v][3].sims_point_center, out[v][3].rechecks))
+    assert np.array_equal(out["lloyd"][0], out["hamerly"][0])
+    assert np.array_equal(out["lloyd"][2], out["hamerly"][2])
+    a_prev, _, C_prev, _ = run_fit(skm, torch, Xd, C0, cfg["k"], "lloyd", T - 1, precision=1)
+    sub = np.random.default_rng(2).choice(X.shape[0], cfg["subsample"], replace=False)
+    sub.sort()
+    S = X[sub].astype(np.float64) @ C_prev.T
+    ref = np.argmax(S, axis=1)
+    keep = S[np.arange(len(sub)), a_prev[sub]] == S.max(1)
+    ref = np.where(keep, a_prev[sub], ref)
+    gap = gap_of(S)
+    clear = gap > GAP
+    mism = int((out["lloyd"][0][sub][clear] != ref[clear]).sum())
+    say("c4 subsample: %d rows, band %d, mismatches %d, all-row mismatches %d" % (
+        len(sub), int((~clear).sum()), mism, int((out["lloyd"][0][sub] != ref).sum())))
+    assert mism == 0
