@@ -44,7 +44,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--variant", default="hamerly")
-    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4"])
+    ap.add_argument("--max-iter", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-iters", type=int, default=0,
                     help="oracle sample: first N assignment steps (0 = auto)")
@@ -69,24 +70,49 @@ def main():
     skm.load()
 
     t0 = time.time()
-    X, init, cfg = datagen.sparse_workload(args.workload)
-    C0 = datagen.init_centers_csr(X, init)
-    log("generated %s: n=%d d=%d nnz=%d k=%d in %.1fs" % (cfg.name, X.n, X.d, X.nnz, cfg.k,
+    dense = args.workload == "c4"
+    if dense:
+        c4 = datagen.C4
+        Xh = datagen.dense_vmf(c4["n"], c4["d"], c4["n_means"], c4["seed"])
+        init = datagen.init_rows(Xh.shape[0], c4["k"], c4["seed"])
+        C0 = Xh[init].copy()
+        Xd = skm.DeviceDense.from_host(Xh, dev)
+        k, max_iter = c4["k"], args.max_iter or 20
+        n_rows, d_cols, nnz = Xh.shape[0], Xh.shape[1], Xh.size
+        name = "c4"
+        X = None
+    else:
+        X, init, cfg = datagen.sparse_workload(args.workload)
+        C0 = datagen.init_centers_csr(X, init)
+        Xd = skm.DeviceCSR.from_host(X, dev)
+        k, max_iter = cfg.k, args.max_iter or cfg.max_iter
+        n_rows, d_cols, nnz = X.n, X.d, X.nnz
+        name = cfg.name
+    log("generated %s: n=%d d=%d nnz=%d k=%d in %.1fs" % (name, n_rows, d_cols, nnz, k,
                                                          time.time() - t0))
-    Xd = skm.DeviceCSR.from_host(X, dev)
     C0d = torch.from_numpy(C0).to(dev)
-    k, max_iter = cfg.k, cfg.max_iter
 
     ws = {}
 
+    def split(v):
+        # "<variant>" or "<variant>_fp32" / "<variant>_bf16" for dense input
+        if v.endswith("_fp32"):
+            return v[:-5], 0
+        if v.endswith("_bf16"):
+            return v[:-5], 1
+        return v, (1 if dense else 0)
+
     def workspace(v):
         if v not in ws:
-            ws[v] = torch.empty(skm.workspace_size(Xd, k, v), dtype=torch.uint8, device=dev)
+            base, prec = split(v)
+            ws[v] = torch.empty(skm.workspace_size(Xd, k, base, precision=prec),
+                                dtype=torch.uint8, device=dev)
         return ws[v]
 
     def one_fit(v, profile=0):
-        return skm.fit(Xd, k, C0d, v, max_iter, workspace=workspace(v), want_centers=False,
-                       per_iter=False, profile=profile)
+        base, prec = split(v)
+        return skm.fit(Xd, k, C0d, base, max_iter, workspace=workspace(v), want_centers=False,
+                       per_iter=False, profile=profile, precision=prec)
 
     if args.calib_copy_mib:
         nbytes = args.calib_copy_mib << 20
@@ -97,14 +123,18 @@ def main():
         torch.cuda.synchronize()
         log("calibration copy: %d bytes read + written per launch" % nbytes)
 
-    # plain GPU Lloyd: the reference the speedup and the assignment check use
-    a_ref, _, _, st_ref = one_fit("lloyd")
+    # plain GPU FP32 Lloyd: the reference the speedup and the assignment
+    # check use
+    base_v = "lloyd_fp32" if dense else "lloyd"
+    if args.variant == "hamerly" and dense:
+        args.variant = "hamerly_bf16"
+    a_ref, _, _, st_ref = one_fit(base_v)
     torch.cuda.synchronize()
     lloyd_times = []
     for _ in range(2):
         torch.cuda.synchronize()
         t = time.perf_counter()
-        a_l, _, _, st_l = one_fit("lloyd")
+        a_l, _, _, st_l = one_fit(base_v)
         torch.cuda.synchronize()
         lloyd_times.append(time.perf_counter() - t)
     lloyd_s = min(lloyd_times)
@@ -127,8 +157,10 @@ def main():
 
     # every variant, timed the same way (best of 2), for the comparison table
     variants = {}
-    for v in ([] if args.quick else ["lloyd", "simp_hamerly", "hamerly", "simp_elkan",
-                                     "elkan"]):
+    table = (["lloyd_fp32", "lloyd_bf16", "simp_hamerly_bf16", "hamerly_bf16",
+              "hamerly_fp32"] if dense else
+             ["lloyd", "simp_hamerly", "hamerly", "simp_elkan", "elkan"])
+    for v in ([] if args.quick else table):
         one_fit(v)
         best = None
         for _ in range(2):
@@ -142,7 +174,7 @@ def main():
                        "iters_per_s": round(st_x.iterations / best, 3),
                        "speedup_vs_gpu_lloyd": round(lloyd_s / best, 3),
                        "sims_fraction": round(st_x.sims_point_center /
-                                              (X.n * k * st_x.iterations), 4),
+                                              (n_rows * k * st_x.iterations), 4),
                        "identical": bool(torch.equal(a_x, a_ref)) and
                        st_x.iterations == st_ref.iterations}
         log("%-13s %8.3f ms/fit  sims %.3f  identical %s" % (
@@ -151,7 +183,7 @@ def main():
     ms_per_step = elapsed / args.steps * 1e3
     value = iters / elapsed
     sims = sum(s.sims_point_center for s in stats)
-    lloyd_equiv_sims = X.n * k * iters
+    lloyd_equiv_sims = n_rows * k * iters
     st = stats[-1]
 
     # dominant kernel: the similarity kernel, timed with HIP events on the
@@ -165,6 +197,14 @@ def main():
     achieved_tflops = flops_per_launch / avg_launch_s / 1e12 if avg_launch_s > 0 else 0.0
     operand_bytes_per_launch = (4.0 * k * kern_nnz + 8.0 * kern_nnz + 20.0 * kern_rows) / max(
         launches, 1)
+    if dense:
+        # MFMA-bound contraction: the peak of the precision it runs in
+        vbase, vprec = split(args.variant)
+        roof = {"kernel": "k_dense_sim", "bound": "mfma",
+                "peak": 2500.0 if vprec == 1 else 157.3,
+                "dtype": "bf16" if vprec == 1 else "f32"}
+    else:
+        roof = {"kernel": "k_assign_csr", "bound": "alu", "peak": PEAK_FP32_TFLOPS}
 
     out = {
         "metric": METRIC,
@@ -177,13 +217,15 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": ("bf16" if split(args.variant)[1] == 1 else "f32") if dense else "f32",
         "data": "synthetic",
         "config": {"workload": "%s: spherical k-means %s, n=%d d=%d nnz=%d k=%d, seeded "
-                               "random-doc init, run to no-change" % (
-                                   cfg.name, args.variant, X.n, X.d, X.nnz, k),
-                   "variant": args.variant, "n": X.n, "d": X.d, "nnz": X.nnz, "k": k,
-                   "parallelism": "single GPU"},
+                               "random-row init, %s" % (
+                                   name, args.variant, n_rows, d_cols, nnz, k,
+                                   "run to no-change" if not dense else
+                                   "%d assignment steps" % max_iter),
+                   "variant": args.variant, "n": n_rows, "d": d_cols, "nnz": nnz, "k": k,
+                   "max_iter": max_iter, "parallelism": "single GPU"},
         "iterations_per_fit": st.iterations,
         "converged": st.converged,
         "identical_assignments_to_lloyd": identical,
@@ -197,12 +239,12 @@ def main():
         "rechecks_per_fit": st.rechecks,
         "variants": variants,
         "roofline": {
-            "kernel": "k_assign_csr",
-            "bound": "alu",
+            "kernel": roof["kernel"],
+            "bound": roof["bound"],
             "achieved": round(achieved_tflops, 3),
-            "peak": PEAK_FP32_TFLOPS,
+            "peak": roof["peak"],
             "unit": "TFLOP/s",
-            "frac": round(achieved_tflops / PEAK_FP32_TFLOPS, 4),
+            "frac": round(achieved_tflops / roof["peak"], 4),
             "traffic": None,
             "avg_launch_us": round(avg_launch_s * 1e6, 3),
             "launches": launches,
@@ -213,7 +255,7 @@ def main():
         },
     }
 
-    if not args.no_cpu:
+    if not args.no_cpu and not dense:
         import oracle
         n_it = args.cpu_iters or max(1, min(st.iterations, 10))
         t = time.perf_counter()
@@ -225,7 +267,27 @@ def main():
             "cores": oracle.threads(),
             "kind": "oracle",
             "sample": "FP64 oracle %s on the same %s input, first %d assignment steps "
-                      "(%.1f s)" % (args.variant, cfg.name, r.iterations, cpu_s),
+                      "(%.1f s)" % (args.variant, name, r.iterations, cpu_s),
+        }
+    elif not args.no_cpu and dense:
+        import oracle
+        sub = np.arange(0, n_rows, n_rows // 20000)[:20000]
+        Xs = Xh[sub]
+        rp = np.arange(0, Xs.size + 1, Xs.shape[1], dtype=np.int64)
+        Xc = datagen.CSR(Xs.shape[0], Xs.shape[1], rp,
+                         np.tile(np.arange(Xs.shape[1], dtype=np.int32), Xs.shape[0]),
+                         Xs.ravel())
+        t = time.perf_counter()
+        oracle.assign(Xc, C0.astype(np.float64))
+        cpu_s = time.perf_counter() - t
+        step_s = cpu_s * n_rows / len(sub)
+        out["cpu_baseline"] = {
+            "value": round(1.0 / step_s, 5),
+            "unit": "iters/s",
+            "cores": oracle.threads(),
+            "kind": "oracle",
+            "sample": "FP64 oracle assignment step on %d of %d rows (%.1f s), scaled to all "
+                      "rows" % (len(sub), n_rows, cpu_s),
         }
     print(json.dumps(out), flush=True)
 

@@ -59,13 +59,43 @@ struct MfmaCfg<false> {
   typedef float elem;
 };
 
-__device__ __forceinline__ void top2_push(float v, int j, float& m1, int& j1, float& m2) {
-  if (v > m1) {
-    m2 = m1;
-    m1 = v;
-    j1 = j;
+// One 32x32 accumulator tile of a row block.  Mode 0 folds the lane's 16
+// values into its running top-2: first a tile-local top-2 (index as a
+// compile-time offset, second best by median-of-three), then one merge.
+// Selects instead of fmaxf keep NaN canonicalisation out of the loop; the
+// inputs are finite.  Mode 1 emits every centre at or above the row's
+// threshold.  `ragged` masks centres >= k (only the last tile has them).
+template <int MODE>
+__device__ __forceinline__ void tile_epilogue(const f32x16& acc, int jb, int k, bool ragged,
+                                              float& m1, int& j1, float& m2, float thr,
+                                              int64_t rowid, int64_t slot,
+                                              const DenseSimArgs& A) {
+  if (MODE == 0) {
+    float t1 = -INFINITY, t2 = -INFINITY;
+    int ti = 0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int off = 8 * (i >> 2) + (i & 3);
+      const float v = (!ragged || jb + off < k) ? acc[i] : -INFINITY;
+      t2 = __builtin_amdgcn_fmed3f(t1, t2, v);
+      const bool gt = v > t1;
+      t1 = gt ? v : t1;
+      ti = gt ? off : ti;
+    }
+    const bool gt = t1 > m1;
+    m2 = __builtin_amdgcn_fmed3f(m1, m2, t1);
+    m2 = t2 > m2 ? t2 : m2;
+    j1 = gt ? jb + ti : j1;
+    m1 = gt ? t1 : m1;
   } else {
-    m2 = fmaxf(m2, v);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int j = jb + 8 * (i >> 2) + (i & 3);
+      if ((!ragged || j < k) && acc[i] >= thr && rowid >= 0) {
+        const int pos = atomicAdd(&A.cand_n[slot], 1);
+        if (pos < A.cand_cap) A.cand[slot * A.cand_cap + pos] = j;
+      }
+    }
   }
 }
 
@@ -75,7 +105,7 @@ __device__ __forceinline__ void top2_push(float v, int j, float& m1, int& j1, fl
 //           order of the list)
 //   mode 1: candidate emission: every centre with value >= thr[slot] is
 //           appended to cand[slot * cap + ...], counts in cand_n[slot]
-template <bool BF16, int MODE>
+template <bool BF16, int MODE, int DP>
 __global__ __launch_bounds__(kDenseWaves * 64) void k_dense_sim(DenseSimArgs A) {
   typedef MfmaCfg<BF16> Cfg;
   typedef typename Cfg::elem E;
@@ -84,9 +114,9 @@ __global__ __launch_bounds__(kDenseWaves * 64) void k_dense_sim(DenseSimArgs A) 
   constexpr int ROWS_PER_BLOCK = ROWS_PER_WAVE * kDenseWaves;
   extern __shared__ char smem[];
   E* lds = reinterpret_cast<E*>(smem);
-  const int dp = A.dp;
-  const int ldsw = dp + (BF16 ? 8 : 4);  // padded LDS row stride (16-byte aligned)
-  const int nsteps = dp / KSTEP;
+  constexpr int dp = DP;
+  constexpr int ldsw = dp + (BF16 ? 8 : 4);  // padded LDS row stride (16-byte aligned)
+  constexpr int nsteps = dp / KSTEP;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int64_t count = A.rows_count ? (int64_t)(*A.rows_count) : A.n_rows;
@@ -103,14 +133,14 @@ __global__ __launch_bounds__(kDenseWaves * 64) void k_dense_sim(DenseSimArgs A) 
       slot[rt] = blk + (int64_t)wave * ROWS_PER_WAVE + rt * 32 + (lane & 31);
       rowid[rt] = (slot[rt] < count) ? (A.rows ? (int64_t)A.rows[slot[rt]] : slot[rt]) : -1;
     }
-    constexpr int NS = BF16 ? 16 : 128;  // K steps held (dp <= 256)
+    constexpr int NS = nsteps;  // K steps, all held in registers
     typedef typename std::conditional<BF16, bf16x8, float>::type Frag;
     Frag bfr[RT][NS];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
-        if (s < nsteps && rowid[rt] >= 0) {
+        if (rowid[rt] >= 0) {
           if constexpr (BF16) {
             bfr[rt][s] = *reinterpret_cast<const bf16x8*>(Xe + (size_t)rowid[rt] * A.ldx +
                                                           s * KSTEP + 8 * (lane >> 5));
@@ -141,13 +171,27 @@ __global__ __launch_bounds__(kDenseWaves * 64) void k_dense_sim(DenseSimArgs A) 
 
     for (int c0 = 0; c0 < A.kpad; c0 += CC) {
       __syncthreads();
-      // stage centres [c0, c0 + CC) into LDS, 16 bytes per thread and step
-      constexpr int VEC = 16 / sizeof(E);
-      const int per_row = dp / VEC;
-      for (int e = threadIdx.x; e < CC * per_row; e += kDenseWaves * 64) {
-        const int r = e / per_row, c = (e - r * per_row) * VEC;
-        *reinterpret_cast<float4*>(lds + r * ldsw + c) =
-            *reinterpret_cast<const float4*>(Ce + (size_t)(c0 + r) * dp + c);
+      // stage centres [c0, c0 + CC) into LDS, 16 bytes per thread and step;
+      // all loads are issued before the first LDS write
+      {
+        constexpr int VEC = 16 / sizeof(E);
+        constexpr int per_row = dp / VEC;
+        constexpr int NT = kDenseWaves * 64;
+        constexpr int STEPS = CC * per_row / NT;
+        static_assert(CC * per_row % NT == 0, "staging must tile the block");
+        float4 st[STEPS];
+#pragma unroll
+        for (int q = 0; q < STEPS; ++q) {
+          const int e = threadIdx.x + q * NT;
+          const int r = e / per_row, c = (e - r * per_row) * VEC;
+          st[q] = *reinterpret_cast<const float4*>(Ce + (size_t)(c0 + r) * dp + c);
+        }
+#pragma unroll
+        for (int q = 0; q < STEPS; ++q) {
+          const int e = threadIdx.x + q * NT;
+          const int r = e / per_row, c = (e - r * per_row) * VEC;
+          *reinterpret_cast<float4*>(lds + r * ldsw + c) = st[q];
+        }
       }
       __syncthreads();
 #pragma unroll
@@ -160,38 +204,30 @@ __global__ __launch_bounds__(kDenseWaves * 64) void k_dense_sim(DenseSimArgs A) 
         const E* arow = lds + (at * 32 + (lane & 31)) * ldsw;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-          if (s < nsteps) {
-            if constexpr (BF16) {
-              const bf16x8 a =
-                  *reinterpret_cast<const bf16x8*>(arow + s * KSTEP + 8 * (lane >> 5));
+          if constexpr (BF16) {
+            const bf16x8 a = *reinterpret_cast<const bf16x8*>(arow + s * KSTEP + 8 * (lane >> 5));
 #pragma unroll
-              for (int rt = 0; rt < RT; ++rt)
-                acc[rt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bfr[rt][s], acc[rt], 0, 0, 0);
-            } else {
-              const float a = arow[s * KSTEP + (lane >> 5)];
+            for (int rt = 0; rt < RT; ++rt)
+              acc[rt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bfr[rt][s], acc[rt], 0, 0, 0);
+          } else {
+            const float a = arow[s * KSTEP + (lane >> 5)];
 #pragma unroll
-              for (int rt = 0; rt < RT; ++rt)
-                acc[rt] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bfr[rt][s], acc[rt], 0, 0, 0);
-            }
+            for (int rt = 0; rt < RT; ++rt)
+              acc[rt] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bfr[rt][s], acc[rt], 0, 0, 0);
           }
         }
         // epilogue: lane holds centres 8(i/4) + 4(l/32) + i%4 of row l%32
         const int jb = c0 + at * 32 + 4 * (lane >> 5);
+        if (c0 + at * 32 + 32 <= A.k) {  // wave-uniform: no padding centre in the tile
 #pragma unroll
-        for (int rt = 0; rt < RT; ++rt) {
+          for (int rt = 0; rt < RT; ++rt) tile_epilogue<MODE>(acc[rt], jb, A.k, false, m1[rt],
+                                                              j1[rt], m2[rt], thr[rt], rowid[rt],
+                                                              slot[rt], A);
+        } else {
 #pragma unroll
-          for (int i = 0; i < 16; ++i) {
-            const int j = jb + 8 * (i >> 2) + (i & 3);
-            const float v = acc[rt][i];
-            if (j < A.k) {
-              if (MODE == 0) {
-                top2_push(v, j, m1[rt], j1[rt], m2[rt]);
-              } else if (v >= thr[rt] && rowid[rt] >= 0) {
-                const int pos = atomicAdd(&A.cand_n[slot[rt]], 1);
-                if (pos < A.cand_cap) A.cand[slot[rt] * A.cand_cap + pos] = j;
-              }
-            }
-          }
+          for (int rt = 0; rt < RT; ++rt) tile_epilogue<MODE>(acc[rt], jb, A.k, true, m1[rt],
+                                                              j1[rt], m2[rt], thr[rt], rowid[rt],
+                                                              slot[rt], A);
         }
       }
     }
@@ -622,7 +658,17 @@ __global__ __launch_bounds__(kBlock) void k_dense_row_eta(const float* __restric
     e32 = __double2float_ru(dev);
     if (lane == 0) eta[i] = e32;
   }
-  if (max_eta && lane == 0) atomicMax(reinterpret_cast<int*>(max_eta), __float_as_int(e32));
+  if (max_eta) {
+    __shared__ float wmax[kBlock / 64];
+    if (lane == 0) wmax[threadIdx.x >> 6] = e32;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      float m = 0.f;
+      for (int w = 0; w < kBlock / 64; ++w) m = fmaxf(m, wmax[w]);
+      if (m > 0.f) atomicMax(reinterpret_cast<int*>(max_eta) + (blockIdx.x % kCounterSlots),
+                             __float_as_int(m));
+    }
+  }
 }
 
 }  // namespace
@@ -639,13 +685,23 @@ hipError_t launch_dense_sim(const DenseSimArgs& A, bool bf16, int mode, hipStrea
   if (blocks < 1) blocks = 1;
   const size_t lds = dense_sim_lds_bytes(bf16, A.dp);
   const dim3 grid((unsigned)blocks), block(kDenseWaves * 64);
-  if (bf16) {
-    if (mode == 0) hipLaunchKernelGGL((k_dense_sim<true, 0>), grid, block, lds, s, A);
-    else hipLaunchKernelGGL((k_dense_sim<true, 1>), grid, block, lds, s, A);
-  } else {
-    if (mode == 0) hipLaunchKernelGGL((k_dense_sim<false, 0>), grid, block, lds, s, A);
-    else hipLaunchKernelGGL((k_dense_sim<false, 1>), grid, block, lds, s, A);
+#define SKM_DS(B, M, D) \
+  hipLaunchKernelGGL((k_dense_sim<B, M, D>), grid, block, lds, s, A)
+#define SKM_DS_DP(B, M)                       \
+  switch (A.dp) {                             \
+    case 32: SKM_DS(B, M, 32); break;         \
+    case 64: SKM_DS(B, M, 64); break;         \
+    case 128: SKM_DS(B, M, 128); break;       \
+    case 256: SKM_DS(B, M, 256); break;       \
+    default: return hipErrorInvalidValue;     \
   }
+  if (bf16) {
+    if (mode == 0) { SKM_DS_DP(true, 0) } else { SKM_DS_DP(true, 1) }
+  } else {
+    if (mode == 0) { SKM_DS_DP(false, 0) } else { SKM_DS_DP(false, 1) }
+  }
+#undef SKM_DS_DP
+#undef SKM_DS
   return hipGetLastError();
 }
 

@@ -58,9 +58,18 @@ __global__ __launch_bounds__(kBlock) void k_row_eta(const int64_t* __restrict__ 
     eta[i] = e32;
   }
   if (max_eta) {
-    // non-negative floats order like their bit patterns
+    // non-negative floats order like their bit patterns; one atomic per
+    // block, spread over kCounterSlots words
+    __shared__ float wmax[kBlock / 64];
     for (int off = 32; off >= 1; off >>= 1) e32 = fmaxf(e32, __shfl_xor(e32, off, 64));
-    if ((threadIdx.x & 63) == 0) atomicMax(reinterpret_cast<int*>(max_eta), __float_as_int(e32));
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = e32;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      float m = 0.f;
+      for (int w = 0; w < kBlock / 64; ++w) m = fmaxf(m, wmax[w]);
+      if (m > 0.f) atomicMax(reinterpret_cast<int*>(max_eta) + (blockIdx.x % kCounterSlots),
+                             __float_as_int(m));
+    }
   }
 }
 

@@ -148,7 +148,7 @@ int make_plan(const skm_matrix* X, int32_t k, int32_t variant, Plan* P) {
   // step brings both to the host
   P->cnt = take(kCounterSlots * sizeof(Counters) + sizeof(Persist));
   P->per = P->cnt + kCounterSlots * sizeof(Counters);
-  P->maxeta = take(sizeof(float));
+  P->maxeta = take(kCounterSlots * sizeof(float));
   P->initnorm = take(kk * sizeof(double));
   P->total = cur;
   return SKM_OK;
@@ -234,7 +234,8 @@ int make_dense_plan(const skm_matrix* X, int32_t k, int32_t variant, int32_t pre
   P->d = X->d;
   P->k = k;
   P->kpad = (k + 63) / 64 * 64;
-  P->dp = (int32_t)((X->d + 31) / 32 * 32);
+  P->dp = 32;  // MFMA K padded to 32, 64, 128 or 256
+  while (P->dp < X->d) P->dp *= 2;
   P->bf16 = precision == 1;
   P->bounds = variant != SKM_LLOYD;
   P->gram = variant == SKM_HAMERLY;
@@ -302,7 +303,7 @@ int make_dense_plan(const skm_matrix* X, int32_t k, int32_t variant, int32_t pre
   }
   P->cnt = take(kCounterSlots * sizeof(Counters) + sizeof(Persist));
   P->per = P->cnt + kCounterSlots * sizeof(Counters);
-  P->maxeta = take(4);
+  P->maxeta = take(kCounterSlots * 4);
   P->initnorm = take(kk * 8);
   P->total = cur;
   return SKM_OK;
@@ -465,7 +466,7 @@ int fit_dense(const skm_matrix* X, int32_t k, const float* init_centers, int32_t
     SKM_HIP(hipMemsetAsync(per, 0, sizeof(Persist), s));
     SKM_HIP(hipMemsetAsync(dirty, 0, (size_t)k * 4, s));
     SKM_HIP(hipMemsetAsync(norm64, 0, (size_t)k * 8, s));
-    SKM_HIP(hipMemsetAsync(R.ptr<float>(P.maxeta), 0, 4, s));
+    SKM_HIP(hipMemsetAsync(R.ptr<float>(P.maxeta), 0, kCounterSlots * 4, s));
     SKM_HIP(launch_fill_i32(a_old, n, -1, s));
     SKM_HIP(launch_dense_row_eta(X->dense, X->ld, n, d, R.ptr<float>(P.eta),
                                  R.ptr<float>(P.maxeta), s));
@@ -473,9 +474,12 @@ int fit_dense(const skm_matrix* X, int32_t k, const float* init_centers, int32_t
     SKM_HIP(launch_pack_centres(C64, k, d, P.dp, nullptr, P.bf16, Cp, s));
     if (P.bf16) SKM_HIP(launch_rows_to_bf16(X->dense, X->ld, n, d, P.dp, R.ptr<char>(P.Xb), s));
     if (o.validate >= 1) {
+      float hslots[kCounterSlots];
       float hmax = 0.f;
-      SKM_HIP(hipMemcpyAsync(&hmax, R.ptr<float>(P.maxeta), 4, hipMemcpyDeviceToHost, s));
+      SKM_HIP(hipMemcpyAsync(hslots, R.ptr<float>(P.maxeta), sizeof(hslots),
+                             hipMemcpyDeviceToHost, s));
       SKM_HIP(hipStreamSynchronize(s));
+      for (int q = 0; q < kCounterSlots; ++q) hmax = std::max(hmax, hslots[q]);
       if (o.validate >= 2 && !((double)hmax <= o.norm_tol)) {
         rc = fail(SKM_ERR_NOT_NORMALIZED, "a data row deviates from unit norm by %.3g", hmax);
         goto done;
@@ -832,12 +836,13 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
     SKM_HIP(launch_fill_i32(a_old, n, -1, s));
     SKM_HIP(hipMemsetAsync(dirty, 0, (size_t)k * sizeof(int32_t), s));
     SKM_HIP(hipMemsetAsync(norm64, 0, (size_t)k * sizeof(double), s));
-    SKM_HIP(hipMemsetAsync(maxeta, 0, sizeof(float), s));
+    SKM_HIP(hipMemsetAsync(maxeta, 0, kCounterSlots * sizeof(float), s));
     SKM_HIP(launch_row_eta(X->row_ptr, X->val, n, eta, maxeta, s));
     SKM_HIP(launch_init_centres(init_centers, k, d, 1, C64, initnorm, s));
     SKM_HIP(launch_transpose(C64, k, d, P.kp, nullptr, CT, s));
     if (o.validate >= 1) {
       double* hn = new (std::nothrow) double[k];
+      float hslots[kCounterSlots];
       float hmax = 0.f;
       if (!hn) {
         rc = fail(SKM_ERR_OUT_OF_MEMORY, "host allocation failed");
@@ -845,8 +850,9 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
       }
       hipError_t e1 = hipMemcpyAsync(hn, initnorm, (size_t)k * sizeof(double),
                                      hipMemcpyDeviceToHost, s);
-      hipError_t e2 = hipMemcpyAsync(&hmax, maxeta, sizeof(float), hipMemcpyDeviceToHost, s);
+      hipError_t e2 = hipMemcpyAsync(hslots, maxeta, sizeof(hslots), hipMemcpyDeviceToHost, s);
       hipError_t e3 = hipStreamSynchronize(s);
+      for (int q = 0; q < kCounterSlots; ++q) hmax = std::max(hmax, hslots[q]);
       if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
         delete[] hn;
         rc = fail(SKM_ERR_HIP, "validation copy failed");

@@ -277,7 +277,7 @@ def test_dense_assign_matches_oracle(skm, torch_cuda, d, k):
     a, best, second = skm.assign(Xd, torch.from_numpy(C).cuda())
     torch.cuda.synchronize()
     check_assign(dense_csr(X), C, a.cpu().numpy(), best.cpu().numpy(), "dense assign",
-                 terms=(d + 31) // 32 * 32)
+                 terms=max(32, 1 << (d - 1).bit_length()))
 
 
 @pytest.mark.parametrize("precision", [0, 1])
