@@ -38,6 +38,43 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# Kernel sources whose change invalidates a stored counter measurement.
+KERNEL_SOURCES = {
+    "k_assign_csr": ["kernels_assign.hip", "skm_device.h", "skm_internal.h"],
+    "k_elkan": ["kernels_assign.hip", "skm_device.h", "skm_internal.h"],
+    "k_dense_sim": ["kernels_dense.hip", "skm_internal.h"],
+}
+
+
+def source_digest(kernel):
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(ROOT, "paper_2107_04074_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload, variant):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    profiles/<kernel>_<workload>_<variant>_traffic.md (FETCH_SIZE + WRITE_SIZE
+    per dispatch, scaled by a plain-copy calibration).  None when there is no
+    summary or the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "%s_%s_%s_traffic.md" % (kernel, workload, variant))
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("- ") and ":" in line:
+                key, val = line[2:].split(":", 1)
+                fields[key.strip()] = val.strip().strip("`")
+    if fields.get("source_digest") != source_digest(kernel):
+        return None
+    return {"bytes_per_launch": float(fields["hbm_bytes_per_launch"]),
+            "file": os.path.relpath(path, ROOT)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -53,6 +90,9 @@ def main():
                     help="skip the per-variant comparison table")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
+    ap.add_argument("--skip-baseline", action="store_true",
+                    help="time only the chosen variant (for counter runs: every launch of "
+                         "the similarity kernel then belongs to the timed fits)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -128,17 +168,21 @@ def main():
     base_v = "lloyd_fp32" if dense else "lloyd"
     if args.variant == "hamerly" and dense:
         args.variant = "hamerly_bf16"
-    a_ref, _, _, st_ref = one_fit(base_v)
-    torch.cuda.synchronize()
-    lloyd_times = []
-    for _ in range(2):
+    if args.skip_baseline:
+        a_ref = st_ref = st_l = None
+        lloyd_s = None
+    else:
+        a_ref, _, _, st_ref = one_fit(base_v)
         torch.cuda.synchronize()
-        t = time.perf_counter()
-        a_l, _, _, st_l = one_fit(base_v)
-        torch.cuda.synchronize()
-        lloyd_times.append(time.perf_counter() - t)
-    lloyd_s = min(lloyd_times)
-    log("lloyd: %d steps, %.3f ms/fit" % (st_l.iterations, lloyd_s * 1e3))
+        lloyd_times = []
+        for _ in range(2):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            a_l, _, _, st_l = one_fit(base_v)
+            torch.cuda.synchronize()
+            lloyd_times.append(time.perf_counter() - t)
+        lloyd_s = min(lloyd_times)
+        log("lloyd: %d steps, %.3f ms/fit" % (st_l.iterations, lloyd_s * 1e3))
 
     # timed variant
     for _ in range(args.warmup):
@@ -152,15 +196,15 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
 
-    identical = bool(torch.equal(a_v, a_ref)) and all(s.iterations == st_ref.iterations
-                                                      for s in stats)
+    identical = None if a_ref is None else (
+        bool(torch.equal(a_v, a_ref)) and all(s.iterations == st_ref.iterations for s in stats))
 
     # every variant, timed the same way (best of 2), for the comparison table
     variants = {}
     table = (["lloyd_fp32", "lloyd_bf16", "simp_hamerly_bf16", "hamerly_bf16",
               "hamerly_fp32"] if dense else
              ["lloyd", "simp_hamerly", "hamerly", "simp_elkan", "elkan"])
-    for v in ([] if args.quick else table):
+    for v in ([] if (args.quick or args.skip_baseline) else table):
         one_fit(v)
         best = None
         for _ in range(2):
@@ -203,8 +247,11 @@ def main():
         roof = {"kernel": "k_dense_sim", "bound": "mfma",
                 "peak": 2500.0 if vprec == 1 else 157.3,
                 "dtype": "bf16" if vprec == 1 else "f32"}
+    elif split(args.variant)[0] in ("elkan", "simp_elkan"):
+        roof = {"kernel": "k_elkan", "bound": "alu", "peak": PEAK_FP32_TFLOPS}
     else:
         roof = {"kernel": "k_assign_csr", "bound": "alu", "peak": PEAK_FP32_TFLOPS}
+    traffic = measured_traffic(roof["kernel"], name, args.variant)
 
     out = {
         "metric": METRIC,
@@ -229,10 +276,12 @@ def main():
         "iterations_per_fit": st.iterations,
         "converged": st.converged,
         "identical_assignments_to_lloyd": identical,
-        "speedup_vs_gpu_lloyd": round(lloyd_s / (elapsed / args.steps), 3),
-        "gpu_lloyd": {"iters_per_s": round(st_l.iterations / lloyd_s, 3),
-                      "ms_per_fit": round(lloyd_s * 1e3, 4),
-                      "sims_per_s": round(st_l.sims_point_center / lloyd_s, 1)},
+        "speedup_vs_gpu_lloyd": None if lloyd_s is None else
+        round(lloyd_s / (elapsed / args.steps), 3),
+        "gpu_lloyd": None if lloyd_s is None else {
+            "iters_per_s": round(st_l.iterations / lloyd_s, 3),
+            "ms_per_fit": round(lloyd_s * 1e3, 4),
+            "sims_per_s": round(st_l.sims_point_center / lloyd_s, 1)},
         "sims_per_s_raw": round(sims / elapsed, 1),
         "sims_per_s_lloyd_equiv": round(lloyd_equiv_sims / elapsed, 1),
         "pruned_fraction": round(1.0 - sims / lloyd_equiv_sims, 4),
@@ -245,7 +294,8 @@ def main():
             "peak": roof["peak"],
             "unit": "TFLOP/s",
             "frac": round(achieved_tflops / roof["peak"], 4),
-            "traffic": None,
+            "traffic": traffic["bytes_per_launch"] if traffic else None,
+            "traffic_source": traffic["file"] if traffic else None,
             "avg_launch_us": round(avg_launch_s * 1e6, 3),
             "launches": launches,
             "flops_per_launch": flops_per_launch,

@@ -120,8 +120,11 @@ typedef struct {            /* [host] filled by skm_fit                       */
                                  (the previous value when nothing changed)  */
   int32_t per_iter_len;
   int32_t reserved0;
-  /* work of the similarity kernel (the dominant kernel): launches, rows and
-     stored entries it processed, and (profile = 1) its summed duration */
+  /* work of the dominant similarity kernel: for CSR input the row-walk
+     (or Elkan) kernel of each assignment step, for dense input the first
+     MFMA similarity pass of each step; launches, rows and stored entries
+     (rows x d for dense) it processed, and (profile = 1) its summed duration
+     from HIP events recorded around each launch on `stream` */
   int64_t sim_kernel_launches;
   int64_t sim_kernel_rows;
   int64_t sim_kernel_nnz;

@@ -314,6 +314,7 @@ struct DenseRun {
   const skm_matrix* X;
   void* ws;
   hipStream_t s;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;  // bracket the first similarity pass
   template <typename T>
   T* ptr(size_t off) const {
     return at<T>(ws, off);
@@ -344,7 +345,9 @@ hipError_t dense_step(const DenseRun& R, int32_t* a, int read_prev, const int32_
   S1.best = R.ptr<float>(P.best);
   S1.best_j = R.ptr<int32_t>(P.best_j);
   S1.second = R.ptr<float>(P.second);
+  if (R.ev0 && (e = hipEventRecord(R.ev0, R.s)) != hipSuccess) return e;
   if ((e = launch_dense_sim(S1, P.bf16, 0, R.s)) != hipSuccess) return e;
+  if (R.ev1 && (e = hipEventRecord(R.ev1, R.s)) != hipSuccess) return e;
   DensePostArgs Q{};
   Q.rows = rows;
   Q.rows_count = rows_count;
@@ -490,7 +493,6 @@ int fit_dense(const skm_matrix* X, int32_t k, const float* init_centers, int32_t
       const bool exhaustive = t == 0 || variant == SKM_LLOYD;
       const int32_t* rows = nullptr;
       const unsigned long long* rows_count = nullptr;
-      if (ev0) SKM_HIP(hipEventRecord(ev0, s));
       if (!exhaustive) {
         DenseHamerlyArgs H{};
         H.X = X->dense;
@@ -519,8 +521,10 @@ int fit_dense(const skm_matrix* X, int32_t k, const float* init_centers, int32_t
         rows = R.ptr<int32_t>(P.rows);
         rows_count = &per->list_total;
       }
+      R.ev0 = ev0;
+      R.ev1 = ev1;
       SKM_HIP(dense_step(R, assign_out, t > 0 ? 1 : 0, rows, rows_count, nullptr, nullptr, cnt));
-      if (ev1) SKM_HIP(hipEventRecord(ev1, s));
+      R.ev0 = R.ev1 = nullptr;
       SKM_HIP(hipMemcpyAsync(hm, cnt, sizeof(HostMirror), hipMemcpyDeviceToHost, s));
       SKM_HIP(hipStreamSynchronize(s));
       const Counters tc = sum_slots(hm);
