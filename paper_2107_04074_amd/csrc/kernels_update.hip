@@ -311,30 +311,40 @@ __global__ void k_clear_dirty(int32_t* dirty, int32_t k) {
   if (j < k) dirty[j] = 0;
 }
 
-// Gram matrix of the FP64 centres, 64 x 64 output tiles (upper triangle of
-// tiles), split over d into slices; partials persist so that tiles of clean
-// centres need not be recomputed.
+// Gram matrix of the FP64 centres on the FP64 matrix cores: 64 x 64 output
+// tiles (upper triangle of tiles), split over d into slices so that the
+// launch fills the chip; partials persist so that tiles of clean centres
+// need not be recomputed.  Each of the four waves owns a 32 x 32 quarter as
+// 2 x 2 MFMA 16x16x4 tiles; centre panels of kGramK columns are staged in LDS
+// with the next panel's loads in flight during the current panel's MFMAs.
+// MFMA f64 16x16x4 lane layout: lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16]; element e of lane l is D[4 e + l / 16][l % 16].
+typedef __attribute__((__vector_size__(4 * sizeof(double)))) double f64x4;
+constexpr int kGramT = 64;
+constexpr int kGramK = 32;
+constexpr int kGramLoads = kGramT * kGramK / kBlock;  // per panel and thread
+
 __global__ __launch_bounds__(kBlock) void k_gram_partial(const double* __restrict__ C64,
                                                          int32_t k, int64_t d,
                                                          const int32_t* __restrict__ dirty,
                                                          int force_all, double* __restrict__ part,
                                                          int64_t slice_len,
                                                          Persist* __restrict__ per) {
-  __shared__ double As[16][65];
-  __shared__ double Bs[16][65];
+  __shared__ double As[kGramT][kGramK + 1];
+  __shared__ double Bs[kGramT][kGramK + 1];
   __shared__ int any;
-  const int nt = (k + 63) / 64;
+  const int nt = (k + kGramT - 1) / kGramT;
   int idx = blockIdx.x, ta = 0;
   while (idx >= nt - ta) {
     idx -= nt - ta;
     ++ta;
   }
   const int tb = ta + idx;
-  const int a0 = ta * 64, b0 = tb * 64;
+  const int a0 = ta * kGramT, b0 = tb * kGramT;
   if (!force_all) {
     if (threadIdx.x == 0) any = 0;
     __syncthreads();
-    if (threadIdx.x < 64) {
+    if (threadIdx.x < kGramT) {
       const int ja = a0 + threadIdx.x, jb = b0 + threadIdx.x;
       if ((ja < k && dirty[ja]) || (jb < k && dirty[jb])) any = 1;
     }
@@ -342,86 +352,114 @@ __global__ __launch_bounds__(kBlock) void k_gram_partial(const double* __restric
     if (!any) return;
   }
   const int s = blockIdx.y;
-  const int64_t tb0 = (int64_t)s * slice_len;
-  const int64_t te = (tb0 + slice_len < d) ? tb0 + slice_len : d;
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  double acc[4][4];
+  const int64_t ts = (int64_t)s * slice_len;
+  const int64_t te = (ts + slice_len < d) ? ts + slice_len : d;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  // staging: element q of this thread is row (tid + q*256) / kGramK, column
+  // (tid + q*256) % kGramK of the panel (consecutive lanes, consecutive t)
+  double ra[kGramLoads], rb[kGramLoads];
+  auto load = [&](int64_t t0) {
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) acc[i][q] = 0.0;
-  for (int64_t t0 = tb0; t0 < te; t0 += 16) {
-    for (int e = threadIdx.x; e < 1024; e += kBlock) {
-      const int r = e >> 4, c = e & 15;
+    for (int q = 0; q < kGramLoads; ++q) {
+      const int e = threadIdx.x + q * kBlock;
+      const int r = e / kGramK, c = e % kGramK;
       const int64_t t = t0 + c;
-      const int ja = a0 + r, jb = b0 + r;
-      As[c][r] = (ja < k && t < te) ? C64[(size_t)ja * d + t] : 0.0;
-      Bs[c][r] = (jb < k && t < te) ? C64[(size_t)jb * d + t] : 0.0;
+      ra[q] = (a0 + r < k && t < te) ? C64[(size_t)(a0 + r) * d + t] : 0.0;
+      rb[q] = (b0 + r < k && t < te) ? C64[(size_t)(b0 + r) * d + t] : 0.0;
     }
+  };
+  f64x4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+  load(ts);
+  for (int64_t t0 = ts; t0 < te; t0 += kGramK) {
     __syncthreads();
 #pragma unroll
-    for (int c = 0; c < 16; ++c) {
-      double av[4], bv[4];
+    for (int q = 0; q < kGramLoads; ++q) {
+      const int e = threadIdx.x + q * kBlock;
+      As[e / kGramK][e % kGramK] = ra[q];
+      Bs[e / kGramK][e % kGramK] = rb[q];
+    }
+    __syncthreads();
+    if (t0 + kGramK < te) load(t0 + kGramK);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        av[i] = As[c][ty * 4 + i];
-        bv[i] = Bs[c][tx * 4 + i];
+    for (int kk = 0; kk < kGramK / 4; ++kk) {
+      const int c = kk * 4 + (lane >> 4);
+      double af[2], bf[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        af[i] = As[wr + i * 16 + (lane & 15)][c];
+        bf[i] = Bs[wc + i * 16 + (lane & 15)][c];
       }
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc[i][q] = fma(av[i], bv[q], acc[i][q]);
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
     }
-    __syncthreads();
   }
   double* P = part + (size_t)s * k * k;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int ja = a0 + ty * 4 + i, jb = b0 + tx * 4 + q;
-      if (ja < k && jb < k) P[(size_t)ja * k + jb] = acc[i][q];
-    }
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int ja = a0 + wr + i * 16 + 4 * e + (lane >> 4);
+        const int jb = b0 + wc + j * 16 + (lane & 15);
+        if (ja < k && jb < k) P[(size_t)ja * k + jb] = acc[i][j][e];
+      }
   if (s == 0 && threadIdx.x == 0) {
     unsigned long long pairs = 0;
-    for (int i = 0; i < 64; ++i) {
+    for (int i = 0; i < kGramT; ++i) {
       const int ja = a0 + i;
       if (ja >= k) break;
       const int lo = (ta == tb) ? ja + 1 : b0;
-      const int hi = (b0 + 64 < k) ? b0 + 64 : k;
+      const int hi = (b0 + kGramT < k) ? b0 + kGramT : k;
       if (hi > lo) pairs += (unsigned long long)(hi - lo);
     }
     atomicAdd(&per->ccsims, pairs);
   }
 }
 
+// Row a of G (slices summed in slice order) and gmax[a] = the largest
+// off-diagonal entry of the row widened by delta_g (capped at 1), or -3
+// (no centre-centre pruning) for k = 1.  One block per row.
 __global__ __launch_bounds__(kBlock) void k_gram_finalize(const double* __restrict__ part,
-                                                          int32_t k, int nslice,
-                                                          double* __restrict__ G) {
-  const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const int64_t kk = (int64_t)k * k;
-  if (e >= kk) return;
-  const int a = (int)(e / k), b = (int)(e % k);
-  const int64_t src = ((a >> 6) <= (b >> 6)) ? e : (int64_t)b * k + a;
-  double g = 0.0;
-  for (int s = 0; s < nslice; ++s) g += part[(size_t)s * kk + src];
-  G[e] = g;
-}
-
-__global__ __launch_bounds__(kBlock) void k_gram_gmax(const double* __restrict__ G, int32_t k,
-                                                      double delta_g, double* __restrict__ gmax) {
-  __shared__ double sh[kBlock];
+                                                          int32_t k, int nslice, double delta_g,
+                                                          double* __restrict__ G,
+                                                          double* __restrict__ gmax) {
+  __shared__ double sh[kBlock / 64];
   const int a = blockIdx.x;
+  const int64_t kk = (int64_t)k * k;
   double m = -INFINITY;
-  for (int b = threadIdx.x; b < k; b += kBlock)
-    if (b != a) m = fmax(m, G[(size_t)a * k + b]);
-  sh[threadIdx.x] = m;
-  __syncthreads();
-  for (int st = kBlock / 2; st >= 1; st >>= 1) {
-    if ((int)threadIdx.x < st) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + st]);
-    __syncthreads();
+  for (int b = threadIdx.x; b < k; b += kBlock) {
+    const int64_t src = ((a / kGramT) <= (b / kGramT)) ? (int64_t)a * k + b : (int64_t)b * k + a;
+    const double* p = part + src;
+    double g = 0.0;
+    int s = 0;
+    for (; s + 16 <= nslice; s += 16) {  // 16 loads in flight, added in slice order
+      double v[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) v[q] = p[(size_t)(s + q) * kk];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) g += v[q];
+    }
+    for (; s < nslice; ++s) g += p[(size_t)s * kk];
+    G[(size_t)a * k + b] = g;
+    if (b != a) m = fmax(m, g);
   }
-  if (threadIdx.x == 0) gmax[a] = (k > 1) ? fmin(1.0, sh[0] + delta_g) : -3.0;
+  for (int off = 32; off >= 1; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double mm = sh[0];
+    for (int w = 1; w < kBlock / 64; ++w) mm = fmax(mm, sh[w]);
+    gmax[a] = (k > 1) ? fmin(1.0, mm + delta_g) : -3.0;
+  }
 }
 
 __global__ void k_c64_to_f32(const double* __restrict__ in, int64_t count, float* __restrict__ out) {
@@ -503,20 +541,31 @@ hipError_t launch_clear_dirty(int32_t* dirty, int32_t k, hipStream_t s) {
   return hipGetLastError();
 }
 
+void gram_slicing(int32_t k, int64_t d, int* nslice, int64_t* slice_len) {
+  // about 1024 blocks (four per CU), slices of at least 256 columns
+  const int nt = (k + kGramT - 1) / kGramT;
+  const int tiles = nt * (nt + 1) / 2;
+  int ns = (1024 + tiles - 1) / tiles;
+  const int64_t max_ns = d / 256 > 1 ? d / 256 : 1;
+  if (ns > max_ns) ns = (int)max_ns;
+  if (ns < 1) ns = 1;
+  int64_t len = (d + ns - 1) / ns;
+  len = (len + kGramK - 1) / kGramK * kGramK;
+  *slice_len = len;
+  *nslice = (int)((d + len - 1) / len);
+}
+
 hipError_t launch_gram(const double* C64, int32_t k, int64_t d, const int32_t* dirty,
                        int force_all, double* part, int nslice, int64_t slice_len, double* G,
                        double* gmax, double delta_g, Persist* per, hipStream_t s) {
-  const int nt = (k + 63) / 64;
+  const int nt = (k + kGramT - 1) / kGramT;
   const dim3 grid((unsigned)(nt * (nt + 1) / 2), (unsigned)nslice);
   hipLaunchKernelGGL(k_gram_partial, grid, dim3(kBlock), 0, s, C64, k, d, dirty, force_all, part,
                      slice_len, per);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_gram_finalize, dim3(blocks_for((int64_t)k * k)), dim3(kBlock), 0, s, part,
-                     k, nslice, G);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_gram_gmax, dim3(k), dim3(kBlock), 0, s, G, k, delta_g, gmax);
+  hipLaunchKernelGGL(k_gram_finalize, dim3((unsigned)k), dim3(kBlock), 0, s, part, k, nslice,
+                     delta_g, G, gmax);
   return hipGetLastError();
 }
 

@@ -103,18 +103,7 @@ int make_plan(const skm_matrix* X, int32_t k, int32_t variant, Plan* P) {
   P->bounds = variant != SKM_LLOYD;
   P->gram = variant == SKM_ELKAN || variant == SKM_HAMERLY;
   P->nchunk = (int)((X->d + 4095) / 4096);
-  {
-    const int nt = (k + 63) / 64;
-    const int tiles = nt * (nt + 1) / 2;
-    int ns = (512 + tiles - 1) / tiles;
-    const int64_t max_ns = std::max<int64_t>(1, X->d / 256);
-    if (ns > max_ns) ns = (int)max_ns;
-    if (ns < 1) ns = 1;
-    int64_t len = (X->d + ns - 1) / ns;
-    len = (len + 15) / 16 * 16;
-    P->slice_len = len;
-    P->nslice = (int)((X->d + len - 1) / len);
-  }
+  gram_slicing(k, X->d, &P->nslice, &P->slice_len);
   size_t cur = 0;
   auto take = [&](size_t bytes) {
     const size_t o = cur;
@@ -241,18 +230,7 @@ int make_dense_plan(const skm_matrix* X, int32_t k, int32_t variant, int32_t pre
   P->gram = variant == SKM_HAMERLY;
   P->nchunk = (int)((X->d + 4095) / 4096);
   P->nb = compact_blocks(X->n);
-  {
-    const int nt = (k + 63) / 64;
-    const int tiles = nt * (nt + 1) / 2;
-    int ns = (512 + tiles - 1) / tiles;
-    const int64_t max_ns = std::max<int64_t>(1, X->d / 256);
-    if (ns > max_ns) ns = (int)max_ns;
-    if (ns < 1) ns = 1;
-    int64_t len = (X->d + ns - 1) / ns;
-    len = (len + 15) / 16 * 16;
-    P->slice_len = len;
-    P->nslice = (int)((X->d + len - 1) / len);
-  }
+  gram_slicing(k, X->d, &P->nslice, &P->slice_len);
   size_t cur = 0;
   auto take = [&](size_t bytes) {
     const size_t o = cur;

@@ -254,6 +254,8 @@ hipError_t launch_centre_finalize(int32_t k, int64_t d, const int32_t* dirty, do
                                   double delta_c, double* pc, double* ps, MoveMin* mm,
                                   Persist* per, hipStream_t s);
 hipError_t launch_clear_dirty(int32_t* dirty, int32_t k, hipStream_t s);
+// Gram slicing over d: number of column slices and their length.
+void gram_slicing(int32_t k, int64_t d, int* nslice, int64_t* slice_len);
 hipError_t launch_gram(const double* C64, int32_t k, int64_t d, const int32_t* dirty,
                        int force_all, double* part, int nslice, int64_t slice_len,
                        double* G, double* gmax, double delta_g, Persist* per,
