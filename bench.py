@@ -81,7 +81,10 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--variant", default="hamerly")
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--workers", type=int, default=0,
+                    help="c5: concurrent streams of the batched fit (0 = sweep 1, 2, 4, 8 "
+                         "untimed and keep the fastest)")
     ap.add_argument("--max-iter", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-iters", type=int, default=0,
@@ -108,6 +111,9 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     skm.load()
+
+    if args.workload == "c5":
+        return run_batched(args, torch, dev, datagen, skm)
 
     t0 = time.time()
     dense = args.workload == "c4"
@@ -338,6 +344,159 @@ def main():
             "kind": "oracle",
             "sample": "FP64 oracle assignment step on %d of %d rows (%.1f s), scaled to all "
                       "rows" % (len(sub), n_rows, cpu_s),
+        }
+    print(json.dumps(out), flush=True)
+
+
+def run_batched(args, torch, dev, datagen, skm):
+    """c5: 256 independent sparse problems (n_b log-normal in [1e3, 5e4],
+    k_b = 8 * U{1..32}, d = 20,000, ~80 stored entries per row, 30 steps at
+    most), solved by one skm_fit_batched call against the plain GPU Lloyd fit
+    of each problem one after another."""
+    t0 = time.time()
+    insts = datagen.batched_instances()
+    probs = []
+    for p in insts:
+        Xd = skm.DeviceCSR.from_host(p.X, dev)
+        C0 = torch.from_numpy(datagen.init_centers_csr(p.X, p.init)).to(dev)
+        probs.append((Xd, p.k, C0, args.max_iter or p.max_iter))
+    n_tot = sum(p.X.n for p in insts)
+    nnz_tot = sum(p.X.nnz for p in insts)
+    log("generated c5: %d problems, %d rows, %d stored entries in %.1fs" % (
+        len(insts), n_tot, nnz_tot, time.time() - t0))
+    variant = args.variant
+
+    def total_steps(res):
+        return sum(r[2].iterations for r in res)
+
+    # plain GPU FP32 Lloyd, one problem after another on the current stream
+    base_res = None
+    base_s = None
+    if not args.skip_baseline:
+        ws_size = max(skm.workspace_size(X, k, "lloyd") for X, k, _, _ in probs)
+        ws = torch.empty(ws_size, dtype=torch.uint8, device=dev)
+
+        def sequential():
+            out = []
+            for X, k, C0, it in probs:
+                a, C, _, st = skm.fit(X, k, C0, "lloyd", it, workspace=ws, want_centers=False,
+                                      per_iter=False)
+                out.append((a, C, st))
+            return out
+        sequential()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        base_res = sequential()
+        torch.cuda.synchronize()
+        base_s = time.perf_counter() - t
+        log("sequential lloyd: %d steps, %.1f ms" % (total_steps(base_res), base_s * 1e3))
+
+    # worker count: the requested one, or the fastest of a short sweep
+    sweep = {}
+    workers = args.workers
+    if workers == 0:
+        for w in (1, 2, 4, 8):
+            skm.fit_batched(probs, variant, workers=w, want_centers=False)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            skm.fit_batched(probs, variant, workers=w, want_centers=False)
+            torch.cuda.synchronize()
+            sweep[w] = round((time.perf_counter() - t) * 1e3, 3)
+            log("batched %s workers=%d: %.1f ms" % (variant, w, sweep[w]))
+        workers = min(sweep, key=sweep.get)
+    bws = torch.empty(skm.batched_workspace_size(probs, variant, workers=workers),
+                      dtype=torch.uint8, device=dev)
+    for _ in range(args.warmup):
+        skm.fit_batched(probs, variant, workers=workers, workspace=bws, want_centers=False,
+                        profile=1)
+    torch.cuda.synchronize()
+    runs = []
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        runs.append(skm.fit_batched(probs, variant, workers=workers, workspace=bws,
+                                    want_centers=False, profile=1))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    res = runs[-1]
+    steps = total_steps(res)
+    identical = None
+    if base_res is not None:
+        identical = all(torch.equal(a, b[0]) and s.iterations == b[2].iterations
+                        for (a, _, s), b in zip(res, base_res))
+    value = steps * args.steps / elapsed
+    sims = sum(r[2].sims_point_center for run in runs for r in run)
+    lloyd_sims = sum(X.n * k * r[2].iterations for run in runs
+                     for (X, k, _, _), r in zip(probs, run))
+    launches = sum(r[2].sim_kernel_launches for run in runs for r in run)
+    kern_ms = sum(r[2].sim_kernel_ms for run in runs for r in run)
+    flops = sum(2.0 * k * r[2].sim_kernel_nnz for run in runs
+                for (X, k, _, _), r in zip(probs, run))
+    avg_launch_s = kern_ms / 1e3 / max(launches, 1)
+    achieved = flops / max(launches, 1) / avg_launch_s / 1e12 if avg_launch_s > 0 else 0.0
+    traffic = measured_traffic("k_assign_csr", "c5", variant)
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "c5: %d batched spherical k-means problems (%s), n_b log-normal "
+                               "in [1e3, 5e4] (sum %d), k_b in 8..256, d=20000, nnz %d, at most "
+                               "%d steps each, one skm_fit_batched call per step" % (
+                                   len(probs), variant, n_tot, nnz_tot, probs[0][3]),
+                   "variant": variant, "problems": len(probs), "rows": n_tot, "nnz": nnz_tot,
+                   "workers": workers, "parallelism": "single GPU"},
+        "assignment_steps_per_call": steps,
+        "identical_assignments_to_lloyd": identical,
+        "speedup_vs_sequential_gpu_lloyd": None if base_s is None else
+        round(base_s / (elapsed / args.steps), 3),
+        "sequential_gpu_lloyd": None if base_s is None else {
+            "ms": round(base_s * 1e3, 3), "iters_per_s": round(total_steps(base_res) / base_s, 3)},
+        "worker_sweep_ms": sweep,
+        "sims_per_s_raw": round(sims / elapsed, 1),
+        "sims_per_s_lloyd_equiv": round(lloyd_sims / elapsed, 1),
+        "pruned_fraction": round(1.0 - sims / max(lloyd_sims, 1), 4),
+        "roofline": {
+            "kernel": "k_assign_csr", "bound": "alu", "achieved": round(achieved, 3),
+            "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+            "traffic": traffic["bytes_per_launch"] if traffic else None,
+            "traffic_source": traffic["file"] if traffic else None,
+            "avg_launch_us": round(avg_launch_s * 1e6, 3), "launches": launches,
+        },
+    }
+    if not args.no_cpu:
+        import oracle
+        # bounded sample: the first problems in index order until ~10 s of
+        # oracle work, each fitted to the same step count as on the GPU;
+        # scaled to the whole batch by stored entries x k x steps
+        work = [X.nnz * k * r[2].iterations for (X, k, _, _), r in zip(probs, res)]
+        t = time.perf_counter()
+        done = 0
+        w_done = 0.0
+        for b, p in enumerate(insts):
+            C0 = datagen.init_centers_csr(p.X, p.init)
+            oracle.fit(p.X, C0, variant, res[b][2].iterations)
+            done += 1
+            w_done += work[b]
+            if time.perf_counter() - t > 10.0:
+                break
+        cpu_s = time.perf_counter() - t
+        est_all = cpu_s * sum(work) / max(w_done, 1.0)
+        out["cpu_baseline"] = {
+            "value": round(steps / est_all, 4),
+            "unit": "iters/s",
+            "cores": oracle.threads(),
+            "kind": "oracle",
+            "sample": "FP64 oracle %s on the first %d of %d problems (%.1f s), scaled to the "
+                      "batch by stored entries x k x steps" % (variant, done, len(insts), cpu_s),
         }
     print(json.dumps(out), flush=True)
 

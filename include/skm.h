@@ -174,6 +174,38 @@ int skm_assign(const skm_matrix* X, int32_t k, const float* centers,
                int32_t* assign_out, float* best_sim_out, float* second_sim_out,
                void* workspace, size_t workspace_bytes, void* stream);
 
+/* Many independent problems in one call (the batched setting: hundreds of
+ * small clustering problems, each solved as in skm_fit).  The library runs
+ * `workers` host threads, each with its own HIP stream on the caller's
+ * current device and its own slice of the workspace; problems are dealt to
+ * the first free worker, most expensive first (stored entries x k), so their
+ * per-step launches and synchronisations overlap on the GPU.  Results are
+ * identical to calling skm_fit on each problem.
+ *   nprob            >= 1 problems.
+ *   Xs, ks           [host] arrays of nprob matrices and centre counts.
+ *   inits            [host] array of nprob device pointers (float[k_b*d_b]).
+ *   variant, opt     as in skm_fit, shared by all problems (opt nullable).
+ *   max_iters        [host] int32[nprob], each >= 1.
+ *   workers          concurrent streams; 0 picks min(nprob, 4) (the GPU
+ *                    runs four hardware queues per process by default).
+ *   workspace        >= skm_fit_batched_workspace_size() bytes or NULL.
+ *   assign_outs      [host] array of nprob device pointers (int32[n_b]).
+ *   centers_outs     [host] array (nullable; entries nullable) of float[k_b*d_b].
+ *   stats            [host] skm_stats[nprob] (nullable), as in skm_fit.
+ * Ordering: the workers start after the work already enqueued on `stream`
+ * and the call returns after every problem finished.  On error the first
+ * failing problem (lowest index) is reported and problems not yet started
+ * are skipped. */
+size_t skm_fit_batched_workspace_size(int32_t nprob, const skm_matrix* Xs,
+                                      const int32_t* ks, int32_t variant,
+                                      const skm_options* opt, int32_t workers);
+int skm_fit_batched(int32_t nprob, const skm_matrix* Xs, const int32_t* ks,
+                    const float* const* inits, int32_t variant,
+                    const int32_t* max_iters, const skm_options* opt,
+                    int32_t workers, void* workspace, size_t workspace_bytes,
+                    int32_t* const* assign_outs, float* const* centers_outs,
+                    skm_stats* stats, void* stream);
+
 const char* skm_status_string(int status);
 const char* skm_last_error(void);
 

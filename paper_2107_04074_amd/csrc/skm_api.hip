@@ -15,9 +15,12 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <new>
 #include <string>
+#include <thread>
+#include <vector>
 
 #include "../../include/skm.h"
 #include "skm_internal.h"
@@ -157,14 +160,30 @@ struct HostMirror {
 static_assert(sizeof(HostMirror) == kCounterSlots * sizeof(Counters) + sizeof(Persist),
               "host mirror must match the device layout");
 
+thread_local HostMirror* t_mirror = nullptr;
+
 HostMirror* host_mirror() {
-  thread_local HostMirror* h = nullptr;
-  if (!h) {
+  if (!t_mirror) {
     void* p = nullptr;
     if (hipHostMalloc(&p, sizeof(HostMirror), hipHostMallocDefault) != hipSuccess) return nullptr;
-    h = static_cast<HostMirror*>(p);
+    t_mirror = static_cast<HostMirror*>(p);
   }
-  return h;
+  return t_mirror;
+}
+
+// Frees this thread's mirror (worker threads call it before they exit).
+void release_host_mirror() {
+  if (t_mirror) (void)hipHostFree(t_mirror);
+  t_mirror = nullptr;
+}
+
+// Worker threads of a batched call: the requested count, or min(nprob, 4)
+// (four hardware queues per process by default), never more than nprob.
+int batch_workers(int32_t workers, int32_t nprob) {
+  int w = workers > 0 ? workers : 4;
+  if (w > nprob) w = nprob;
+  if (w > 64) w = 64;
+  return w < 1 ? 1 : w;
 }
 
 Counters sum_slots(const HostMirror* h) {
@@ -994,6 +1013,139 @@ done:
       if (e != hipSuccess) rc = fail(SKM_ERR_HIP, "final synchronise: %s", hipGetErrorString(e));
     }
   }
+  return rc;
+}
+
+
+size_t skm_fit_batched_workspace_size(int32_t nprob, const skm_matrix* Xs, const int32_t* ks,
+                                      int32_t variant, const skm_options* opt,
+                                      int32_t workers) {
+  g_last_error.clear();
+  if (nprob < 1 || !Xs || !ks) {
+    fail(SKM_ERR_INVALID_ARG, "need nprob >= 1 and non-NULL Xs, ks");
+    return 0;
+  }
+  size_t slot = 0;
+  for (int32_t b = 0; b < nprob; ++b) {
+    const size_t need = skm_workspace_size(&Xs[b], ks[b], variant, opt);
+    if (need == 0) {
+      const std::string m = g_last_error;
+      fail(SKM_ERR_INVALID_ARG, "problem %d: %s", (int)b, m.c_str());
+      return 0;
+    }
+    slot = std::max(slot, align256(need));
+  }
+  return slot * (size_t)batch_workers(workers, nprob);
+}
+
+int skm_fit_batched(int32_t nprob, const skm_matrix* Xs, const int32_t* ks,
+                    const float* const* inits, int32_t variant, const int32_t* max_iters,
+                    const skm_options* opt, int32_t workers, void* workspace,
+                    size_t workspace_bytes, int32_t* const* assign_outs,
+                    float* const* centers_outs, skm_stats* stats, void* stream) {
+  g_last_error.clear();
+  if (nprob < 1) return fail(SKM_ERR_INVALID_ARG, "need nprob >= 1");
+  if (!Xs || !ks || !inits || !max_iters || !assign_outs)
+    return fail(SKM_ERR_INVALID_ARG, "Xs, ks, inits, max_iters and assign_outs must be non-NULL");
+  if (workers < 0) return fail(SKM_ERR_INVALID_ARG, "workers must be >= 0");
+  for (int32_t b = 0; b < nprob; ++b) {
+    if (!inits[b] || !assign_outs[b])
+      return fail(SKM_ERR_INVALID_ARG, "problem %d: init or assign_out NULL", (int)b);
+    if (max_iters[b] < 1) return fail(SKM_ERR_INVALID_ARG, "problem %d: max_iter < 1", (int)b);
+  }
+  const int W = batch_workers(workers, nprob);
+  const size_t total = skm_fit_batched_workspace_size(nprob, Xs, ks, variant, opt, workers);
+  if (total == 0) return g_last_error.empty() ? fail(SKM_ERR_INVALID_ARG, "bad problem") :
+                                               SKM_ERR_INVALID_ARG;
+  if (workspace && workspace_bytes < total)
+    return fail(SKM_ERR_OUT_OF_MEMORY, "workspace has %zu bytes, %zu needed", workspace_bytes,
+                total);
+  const size_t slot = total / (size_t)W;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int device = 0;
+  if (hipGetDevice(&device) != hipSuccess) return fail(SKM_ERR_HIP, "hipGetDevice failed");
+  bool owned = false;
+  void* ws = workspace;
+  if (!ws) {
+    if (hipMallocAsync(&ws, total, s) != hipSuccess)
+      return fail(SKM_ERR_OUT_OF_MEMORY, "could not allocate %zu bytes of workspace", total);
+    owned = true;
+  }
+  hipEvent_t start = nullptr;
+  if (hipEventCreateWithFlags(&start, hipEventDisableTiming) != hipSuccess ||
+      hipEventRecord(start, s) != hipSuccess) {
+    if (start) (void)hipEventDestroy(start);
+    if (owned) (void)hipFreeAsync(ws, s);
+    return fail(SKM_ERR_HIP, "could not record the start event");
+  }
+  // most expensive problems first (the vectors below are small; an
+  // allocation failure here ends the process like any other host OOM)
+  std::vector<int32_t> order(nprob);
+  std::vector<double> cost(nprob);
+  for (int32_t b = 0; b < nprob; ++b) {
+    order[b] = b;
+    const double entries =
+        Xs[b].fmt == SKM_DENSE_F32 ? (double)Xs[b].n * (double)Xs[b].d : (double)Xs[b].nnz;
+    cost[b] = entries * (double)ks[b] * (double)max_iters[b];
+  }
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int32_t x, int32_t y) { return cost[x] > cost[y]; });
+  std::atomic<int32_t> next{0};
+  std::atomic<bool> abort{false};
+  std::vector<int> status(nprob, SKM_OK);
+  std::vector<std::string> msg(nprob);
+  std::vector<int> wstatus(W, SKM_OK);
+  std::vector<std::string> wmsg(W);
+  auto work = [&](int w) {
+    if (hipSetDevice(device) != hipSuccess) {
+      wstatus[w] = SKM_ERR_HIP;
+      wmsg[w] = "hipSetDevice failed in a worker";
+      abort = true;
+      return;
+    }
+    hipStream_t ws_stream = nullptr;
+    if (hipStreamCreateWithFlags(&ws_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamWaitEvent(ws_stream, start, 0) != hipSuccess) {
+      wstatus[w] = SKM_ERR_HIP;
+      wmsg[w] = "could not create a worker stream";
+      abort = true;
+      if (ws_stream) (void)hipStreamDestroy(ws_stream);
+      return;
+    }
+    void* slot_ptr = static_cast<char*>(ws) + (size_t)w * slot;
+    for (;;) {
+      const int32_t i = next.fetch_add(1);
+      if (i >= nprob || abort.load()) break;
+      const int32_t b = order[i];
+      const int rc = skm_fit(&Xs[b], ks[b], inits[b], variant, max_iters[b], opt, slot_ptr, slot,
+                             assign_outs[b], centers_outs ? centers_outs[b] : nullptr, nullptr,
+                             stats ? &stats[b] : nullptr, ws_stream);
+      if (rc != SKM_OK) {
+        status[b] = rc;
+        msg[b] = g_last_error;
+        abort = true;
+      }
+    }
+    (void)hipStreamSynchronize(ws_stream);
+    (void)hipStreamDestroy(ws_stream);
+    release_host_mirror();
+  };
+  std::vector<std::thread> pool;
+  int rc = SKM_OK;
+  try {
+    pool.reserve(W);
+    for (int w = 0; w < W; ++w) pool.emplace_back(work, w);
+  } catch (...) {  // thread creation failed: stop the started workers
+    abort = true;
+    rc = fail(SKM_ERR_OUT_OF_MEMORY, "could not start %d worker threads", W);
+  }
+  for (auto& t : pool) t.join();
+  (void)hipEventDestroy(start);
+  for (int32_t b = 0; b < nprob && rc == SKM_OK; ++b)
+    if (status[b] != SKM_OK) rc = fail(status[b], "problem %d: %s", (int)b, msg[b].c_str());
+  for (int w = 0; w < W && rc == SKM_OK; ++w)
+    if (wstatus[w] != SKM_OK) rc = fail(wstatus[w], "%s", wmsg[w].c_str());
+  if (owned) (void)hipFreeAsync(ws, s);
   return rc;
 }
 

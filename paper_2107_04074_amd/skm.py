@@ -25,6 +25,7 @@ OK, ERR_INVALID_ARG, ERR_NOT_NORMALIZED, ERR_OUT_OF_MEMORY, ERR_HIP, ERR_UNSUPPO
 
 # Every symbol include/skm.h declares.
 EXPORTS = ("skm_workspace_size", "skm_assign_workspace_size", "skm_fit", "skm_assign",
+           "skm_fit_batched_workspace_size", "skm_fit_batched",
            "skm_status_string", "skm_last_error", "skm_version")
 
 
@@ -82,6 +83,13 @@ def load(path: str = LIB_PATH):
                             ctypes.POINTER(SkmStats), p]
     lib.skm_assign.restype = ctypes.c_int
     lib.skm_assign.argtypes = [ctypes.POINTER(SkmMatrix), i32, p, p, p, p, p, sz, p]
+    lib.skm_fit_batched_workspace_size.restype = sz
+    lib.skm_fit_batched_workspace_size.argtypes = [i32, ctypes.POINTER(SkmMatrix), p, i32,
+                                                   ctypes.POINTER(SkmOptions), i32]
+    lib.skm_fit_batched.restype = ctypes.c_int
+    lib.skm_fit_batched.argtypes = [i32, ctypes.POINTER(SkmMatrix), p, p, i32, p,
+                                    ctypes.POINTER(SkmOptions), i32, p, sz, p, p,
+                                    ctypes.POINTER(SkmStats), p]
     lib.skm_status_string.restype = ctypes.c_char_p
     lib.skm_status_string.argtypes = [ctypes.c_int]
     lib.skm_last_error.restype = ctypes.c_char_p
@@ -260,3 +268,58 @@ def assign(X: DeviceCSR, centers, workspace=None, want_second=True):
     _check(lib.skm_assign(ctypes.byref(m), k, _ptr(c), _ptr(a), _ptr(best), _ptr(second),
                           _ptr(workspace), workspace.numel(), _stream()))
     return a, best, second
+
+
+def _batch_arrays(problems):
+    ms = (SkmMatrix * len(problems))(*[X.matrix() for X, _, _, _ in problems])
+    ks = np.array([int(k) for _, k, _, _ in problems], np.int32)
+    its = np.array([int(it) for _, _, _, it in problems], np.int32)
+    return ms, ks, its
+
+
+def batched_workspace_size(problems, variant="hamerly", workers=0, **opts) -> int:
+    """problems: list of (X, k, init_centers, max_iter)."""
+    lib = load()
+    v = VARIANTS[variant] if isinstance(variant, str) else int(variant)
+    ms, ks, _ = _batch_arrays(problems)
+    o = _options(**opts)
+    size = lib.skm_fit_batched_workspace_size(len(problems), ms, ks.ctypes.data, v,
+                                              ctypes.byref(o), workers)
+    if size == 0:
+        raise SkmError(ERR_INVALID_ARG, lib.skm_last_error().decode(errors="replace"))
+    return int(size)
+
+
+def fit_batched(problems, variant="hamerly", workers=0, workspace=None, want_centers=True,
+                **opts):
+    """Runs skm_fit_batched over problems = [(X, k, init (k, d) float32
+    device tensor, max_iter), ...].  Returns a list of (assign, centers or
+    None, FitStats) per problem."""
+    import torch
+    lib = load()
+    v = VARIANTS[variant] if isinstance(variant, str) else int(variant)
+    nb = len(problems)
+    ms, ks, its = _batch_arrays(problems)
+    o = _options(**opts)
+    if workspace is None:
+        workspace = torch.empty(batched_workspace_size(problems, variant, workers, **opts),
+                                dtype=torch.uint8, device=problems[0][0].col.device)
+    inits = [init.contiguous() for _, _, init, _ in problems]
+    outs = [torch.empty(X.n, dtype=torch.int32, device=X.col.device) for X, _, _, _ in problems]
+    cents = ([torch.empty((int(k), X.d), dtype=torch.float32, device=X.col.device)
+              for X, k, _, _ in problems] if want_centers else None)
+    init_p = (ctypes.c_void_p * nb)(*[_ptr(t) for t in inits])
+    out_p = (ctypes.c_void_p * nb)(*[_ptr(t) for t in outs])
+    cen_p = (ctypes.c_void_p * nb)(*[_ptr(t) for t in cents]) if want_centers else None
+    st = (SkmStats * nb)()
+    _check(lib.skm_fit_batched(nb, ms, ks.ctypes.data, init_p, v, its.ctypes.data,
+                               ctypes.byref(o), workers, _ptr(workspace), workspace.numel(),
+                               out_p, cen_p, st, _stream()))
+    res = []
+    for b in range(nb):
+        x = st[b]
+        res.append((outs[b], cents[b] if want_centers else None,
+                    FitStats(x.iterations, bool(x.converged), x.objective, x.sims_point_center,
+                             x.sims_center_center, x.rechecks, x.sim_kernel_launches,
+                             x.sim_kernel_rows, x.sim_kernel_nnz, x.sim_kernel_ms)))
+    return res

@@ -115,6 +115,39 @@ def test_invalid_arguments_are_rejected(lib):
     assert lib.skm_status_string(skm.ERR_UNSUPPORTED) == b"unsupported"
 
 
+def test_batched_arguments_are_rejected(lib):
+    """skm_fit_batched validates every problem before any GPU call; its
+    workspace is one slot (the largest problem's need) per worker."""
+    ms = (skm.SkmMatrix * 3)(_fake_csr(), _fake_csr(n=40), _fake_csr())
+    ks = (ctypes.c_int32 * 3)(3, 5, 2)
+    its = (ctypes.c_int32 * 3)(5, 5, 5)
+    ptrs = (ctypes.c_void_p * 3)(0x5000, 0x6000, 0x7000)
+    st = (skm.SkmStats * 3)()
+    one = lib.skm_fit_batched_workspace_size(3, ms, ks, skm.HAMERLY, None, 1)
+    three = lib.skm_fit_batched_workspace_size(3, ms, ks, skm.HAMERLY, None, 3)
+    biggest = max(lib.skm_workspace_size(ctypes.byref(ms[b]), ks[b], skm.HAMERLY, None)
+                  for b in range(3))
+    assert one >= biggest and three == 3 * one
+    # auto worker count never exceeds the number of problems
+    assert lib.skm_fit_batched_workspace_size(3, ms, ks, skm.HAMERLY, None, 0) == three
+    # a bad problem is named
+    ks_bad = (ctypes.c_int32 * 3)(3, 0, 2)
+    assert lib.skm_fit_batched_workspace_size(3, ms, ks_bad, skm.HAMERLY, None, 1) == 0
+    assert b"problem 1" in lib.skm_last_error()
+    assert lib.skm_fit_batched(0, ms, ks, ptrs, 0, its, None, 0, None, 0, ptrs, None, st,
+                               None) == skm.ERR_INVALID_ARG
+    its_bad = (ctypes.c_int32 * 3)(5, 0, 5)
+    rc = lib.skm_fit_batched(3, ms, ks, ptrs, 0, its_bad, None, 0, None, 0, ptrs, None, st,
+                             None)
+    assert rc == skm.ERR_INVALID_ARG and b"problem 1" in lib.skm_last_error()
+    rc = lib.skm_fit_batched(3, ms, ks, None, 0, its, None, 0, None, 0, ptrs, None, st, None)
+    assert rc == skm.ERR_INVALID_ARG
+    rc = lib.skm_fit_batched(3, ms, ks, ptrs, 0, its, None, -1, None, 0, ptrs, None, st, None)
+    assert rc == skm.ERR_INVALID_ARG
+    rc = lib.skm_fit_batched(3, ms, ks, ptrs, 0, its, None, 1, 0x8000, 16, ptrs, None, st, None)
+    assert rc == skm.ERR_OUT_OF_MEMORY
+
+
 def test_product_path_refuses_without_library(monkeypatch, tmp_path):
     """The binding never falls back to CPU code: a missing library raises."""
     monkeypatch.setattr(skm, "_lib", None)

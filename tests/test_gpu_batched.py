@@ -1,0 +1,98 @@
+"""GPU checks of skm_fit_batched (through the C ABI): every problem of a
+batch gets exactly what skm_fit gives it alone (assignments, FP32 centres,
+iteration counts: bit for bit), and small problems match the FP64 oracle's
+Lloyd trajectory."""
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    return torch
+
+
+@pytest.fixture(scope="module")
+def skm(torch_cuda):
+    from paper_2107_04074_amd import skm as s
+    s.load()
+    return s
+
+
+@pytest.fixture(scope="module")
+def problems():
+    # the batched workload's generator at 4% of its row counts: 12 problems
+    # of 40..2000 rows, k from 8 to 256 (capped at the row count)
+    return datagen.batched_instances(n_inst=12, scale=0.04)
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def device_problems(skm, torch, insts, max_iter=None):
+    out = []
+    for p in insts:
+        Xd = skm.DeviceCSR.from_host(p.X)
+        C0 = torch.from_numpy(datagen.init_centers_csr(p.X, p.init)).cuda()
+        out.append((Xd, p.k, C0, max_iter or p.max_iter))
+    return out
+
+
+@pytest.mark.parametrize("variant,workers", [("lloyd", 3), ("hamerly", 4), ("elkan", 2),
+                                             ("simp_hamerly", 1)])
+def test_batched_equals_individual_fits(skm, torch_cuda, problems, variant, workers):
+    torch = torch_cuda
+    say("case batched %s workers=%d" % (variant, workers))
+    dp = device_problems(skm, torch, problems)
+    res = skm.fit_batched(dp, variant, workers=workers)
+    torch.cuda.synchronize()
+    for b, ((Xd, k, C0, it), (a, C, st)) in enumerate(zip(dp, res)):
+        a1, C1, _, st1 = skm.fit(Xd, k, C0, variant, it, per_iter=False)
+        torch.cuda.synchronize()
+        assert torch.equal(a, a1), b
+        assert torch.equal(C, C1), b
+        assert st.iterations == st1.iterations and st.converged == st1.converged, b
+        assert st.sims_point_center == st1.sims_point_center, b
+    say("  %d problems, iterations %s" % (len(res), [r[2].iterations for r in res]))
+
+
+def test_batched_matches_oracle(skm, torch_cuda, problems):
+    torch = torch_cuda
+    small = sorted(problems, key=lambda p: p.X.nnz * p.k)[:4]
+    dp = device_problems(skm, torch, small)
+    res = skm.fit_batched(dp, "hamerly", workers=2)
+    torch.cuda.synchronize()
+    for p, (Xd, k, C0, it), (a, C, st) in zip(small, dp, res):
+        say("case batched oracle n=%d k=%d" % (p.X.n, k))
+        ref = oracle.fit(p.X, C0.cpu().numpy(), "lloyd", it)
+        assert st.iterations == ref.iterations and st.converged == ref.converged
+        assert np.array_equal(a.cpu().numpy(), ref.a)
+        assert np.linalg.norm(C.cpu().numpy().astype(np.float64) - ref.C, axis=1).max() < 1e-6
+
+
+def test_batched_twice_with_fewer_problems(skm, torch_cuda, problems):
+    """Two calls in a row on one workspace, the second with fewer and
+    smaller problems: no state leaks from the first call."""
+    torch = torch_cuda
+    dp = device_problems(skm, torch, problems, max_iter=6)
+    ws = torch.empty(skm.batched_workspace_size(dp, "hamerly", workers=3), dtype=torch.uint8,
+                     device="cuda")
+    first = skm.fit_batched(dp, "hamerly", workers=3, workspace=ws)
+    sub = dp[5:8]
+    second = skm.fit_batched(sub, "hamerly", workers=3, workspace=ws)
+    torch.cuda.synchronize()
+    for (Xd, k, C0, it), (a, C, st) in zip(sub, second):
+        a1, C1, _, _ = skm.fit(Xd, k, C0, "hamerly", it, per_iter=False)
+        torch.cuda.synchronize()
+        assert torch.equal(a, a1) and torch.equal(C, C1)
+    for (a, C, st), (a2, C2, _) in zip(first[5:8], second):
+        assert torch.equal(a, a2) and torch.equal(C, C2)
