@@ -462,6 +462,46 @@ __global__ __launch_bounds__(kBlock) void k_gram_finalize(const double* __restri
   }
 }
 
+// Carries the centre-centre bounds across a centre step without the d-long
+// products: centres a and b moved by at most the angles whose cosines and
+// sines are (pc, ps), so their angle shrank by at most theta_a + theta_b and
+// the guarded Eq. (7) with that combined movement keeps G(a, b) an upper
+// bound of <c_a, c_b> (1 once theta_a + theta_b reaches pi or the old angle).
+// Every update adds 4e-15 for its own FP64 rounding.  One block per row;
+// (a, b) and (b, a) get bitwise equal values.
+__global__ __launch_bounds__(kBlock) void k_gram_carry(double* __restrict__ G, int32_t k,
+                                                       const double* __restrict__ pc,
+                                                       const double* __restrict__ ps,
+                                                       double delta_g,
+                                                       double* __restrict__ gmax) {
+  __shared__ double sh[kBlock / 64];
+  const int a = blockIdx.x;
+  const double pa = pc[a], sa = ps[a];
+  double m = -INFINITY;
+  for (int b = threadIdx.x; b < k; b += kBlock) {
+    if (b == a) continue;
+    const double pb = pc[b], sb = ps[b];
+    double g = G[(size_t)a * k + b];
+    if (pa + pb <= 0.0) {
+      g = 1.0;
+    } else {
+      const double cm = pa * pb - sa * sb;  // cos(theta_a + theta_b)
+      const double sm = sa * pb + pa * sb;  // sin(theta_a + theta_b) >= 0
+      g = fmin(1.0, dev::upper_upd(g, cm, sm) + 4e-15);
+    }
+    G[(size_t)a * k + b] = g;
+    m = fmax(m, g);
+  }
+  for (int off = 32; off >= 1; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double mm = sh[0];
+    for (int w = 1; w < kBlock / 64; ++w) mm = fmax(mm, sh[w]);
+    gmax[a] = (k > 1) ? fmin(1.0, mm + delta_g) : -3.0;
+  }
+}
+
 __global__ void k_c64_to_f32(const double* __restrict__ in, int64_t count, float* __restrict__ out) {
   const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (e < count) out[e] = (float)in[e];
@@ -566,6 +606,13 @@ hipError_t launch_gram(const double* C64, int32_t k, int64_t d, const int32_t* d
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_gram_finalize, dim3((unsigned)k), dim3(kBlock), 0, s, part, k, nslice,
                      delta_g, G, gmax);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram_carry(double* G, int32_t k, const double* pc, const double* ps,
+                             double delta_g, double* gmax, hipStream_t s) {
+  hipLaunchKernelGGL(k_gram_carry, dim3((unsigned)k), dim3(kBlock), 0, s, G, k, pc, ps, delta_g,
+                     gmax);
   return hipGetLastError();
 }
 

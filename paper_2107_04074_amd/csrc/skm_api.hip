@@ -456,6 +456,7 @@ int fit_dense(const skm_matrix* X, int32_t k, const float* init_centers, int32_t
   int64_t tot_sims = 0, tot_rechecks = 0, sk_launches = 0, sk_rows = 0;
   double objective = 0.0, sk_ms = 0.0, tight_rate = 1.0;
   bool first_gram = true;
+  int gram_updates = 0, gram_since_exact = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   {
     if (o.profile) {
@@ -568,9 +569,17 @@ int fit_dense(const skm_matrix* X, int32_t k, const float* init_centers, int32_t
                                      ps, mm, per, s));
       SKM_HIP(launch_pack_centres(C64, k, d, P.dp, dirty, P.bf16, Cp, s));
       if (P.gram) {
-        SKM_HIP(launch_gram(C64, k, d, dirty, first_gram ? 1 : 0, gpart, P.nslice, P.slice_len,
-                            G, gmax, delta_g, per, s));
-        first_gram = false;
+        if (gram_exact_step(gram_updates, gram_since_exact, changed, n)) {
+          // after carried steps every tile's partials are stale
+          SKM_HIP(launch_gram(C64, k, d, dirty, (first_gram || gram_since_exact > 0) ? 1 : 0,
+                              gpart, P.nslice, P.slice_len, G, gmax, delta_g, per, s));
+          first_gram = false;
+          gram_since_exact = 0;
+        } else {
+          SKM_HIP(launch_gram_carry(G, k, pc, ps, delta_g, gmax, s));
+          ++gram_since_exact;
+        }
+        ++gram_updates;
       }
       SKM_HIP(launch_clear_dirty(dirty, k, s));
     }
@@ -825,6 +834,7 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   double objective = 0.0;
   bool first_gram = true;
+  int gram_updates = 0, gram_since_exact = 0;
   double tight_rate = 1.0;
   {
     if (o.profile) {
@@ -974,9 +984,17 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
                                      ps, mm, per, s));
       SKM_HIP(launch_transpose(C64, k, d, P.kp, dirty, CT, s));
       if (P.gram) {
-        SKM_HIP(launch_gram(C64, k, d, dirty, first_gram ? 1 : 0, gpart, P.nslice, P.slice_len,
-                            G, gmax, delta_g, per, s));
-        first_gram = false;
+        if (gram_exact_step(gram_updates, gram_since_exact, changed, n)) {
+          // after carried steps every tile's partials are stale
+          SKM_HIP(launch_gram(C64, k, d, dirty, (first_gram || gram_since_exact > 0) ? 1 : 0,
+                              gpart, P.nslice, P.slice_len, G, gmax, delta_g, per, s));
+          first_gram = false;
+          gram_since_exact = 0;
+        } else {
+          SKM_HIP(launch_gram_carry(G, k, pc, ps, delta_g, gmax, s));
+          ++gram_since_exact;
+        }
+        ++gram_updates;
       }
       SKM_HIP(launch_clear_dirty(dirty, k, s));
     }

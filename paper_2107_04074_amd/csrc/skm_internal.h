@@ -254,6 +254,15 @@ hipError_t launch_centre_finalize(int32_t k, int64_t d, const int32_t* dirty, do
                                   double delta_c, double* pc, double* ps, MoveMin* mm,
                                   Persist* per, hipStream_t s);
 hipError_t launch_clear_dirty(int32_t* dirty, int32_t k, hipStream_t s);
+// Movement-bound update of G and gmax in place of an exact Gram.
+hipError_t launch_gram_carry(double* G, int32_t k, const double* pc, const double* ps,
+                             double delta_g, double* gmax, hipStream_t s);
+// Whether the centre step after assignment step t recomputes the Gram
+// exactly (else it carries the bounds): the first two centre steps, every
+// fourth after an exact one, and whenever more than 5% of the rows changed.
+inline bool gram_exact_step(int updates_done, int since_exact, int64_t changed, int64_t n) {
+  return updates_done < 2 || since_exact >= 3 || changed * 20 > n;
+}
 // Gram slicing over d: number of column slices and their length.
 void gram_slicing(int32_t k, int64_t d, int* nslice, int64_t* slice_len);
 hipError_t launch_gram(const double* C64, int32_t k, int64_t d, const int32_t* dirty,
