@@ -73,6 +73,8 @@ def _load():
         lib.oracle_fit.restype = i32
         lib.oracle_fit.argtypes = [i64, i64, p, p, p, i32, p, i32, i32, i32, i32, p, p,
                                    p, p, p, p, p, p, p, p]
+        lib.oracle_kmeanspp.restype = None
+        lib.oracle_kmeanspp.argtypes = [i64, i64, p, p, p, i32, dbl, p, p, p, p, p]
         _lib = lib
     return _lib
 
@@ -102,6 +104,23 @@ def assign(X, C: np.ndarray, a_prev: Optional[np.ndarray] = None):
     ap = None if a_prev is None else np.ascontiguousarray(a_prev, dtype=np.int32)
     lib.oracle_assign(X.n, X.d, _p(rp), _p(ci), _p(v), k, _p(C), _p(ap), _p(a), _p(s1), _p(s2))
     return a, s1, s2
+
+
+def kmeanspp(X, k: int, alpha: float, u: np.ndarray):
+    """Spherical k-means++ seeding with the given uniforms u[0..k) in [0, 1):
+    (chosen rows, assign, best, second), the last three being the assignment
+    step against the chosen rows rescaled to unit length."""
+    lib = _load()
+    rp, ci, v = _csr_args(X)
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    assert u.shape == (k,)
+    chosen = np.empty(k, dtype=np.int32)
+    a = np.empty(X.n, dtype=np.int32)
+    s1 = np.empty(X.n)
+    s2 = np.empty(X.n)
+    lib.oracle_kmeanspp(X.n, X.d, _p(rp), _p(ci), _p(v), k, float(alpha), _p(u), _p(chosen),
+                        _p(a), _p(s1), _p(s2))
+    return chosen, a, s1, s2
 
 
 def sims(X, C: np.ndarray, rows: np.ndarray) -> np.ndarray:

@@ -177,6 +177,90 @@ double oracle_update(int64_t n, int64_t d, const int64_t *rp, const int32_t *ci,
 }
 
 /* -------------------------------------------------------------------- */
+/* spherical k-means++ seeding (Section 6, "Spherical k-means++")        */
+/* -------------------------------------------------------------------- */
+
+/* The first centre is row floor(u[0] n); centre t >= 1 is drawn with
+ * probability proportional to alpha - max_c <x(i), c> over the centres
+ * chosen so far (alpha = 1 is the cosine form, alpha = 1.5 the metric form
+ * the section mentions), by inverse transform sampling with u[t]: the first
+ * row whose running weight sum exceeds u[t] * W, W the total.  Readings
+ * (SEED): rows already chosen get weight 0, so no row is drawn twice;
+ * negative weights count as 0; if W = 0 the lowest-index row not yet chosen
+ * is taken.  Centres are the chosen rows rescaled to unit length (INIT
+ * reading).  The maximum over the chosen centres is cached per row and
+ * updated once per new centre (the O(nk) scheme of the section); on return
+ * best/assign/second hold the assignment step against all k centres
+ * (ARGMAX with no previous assignment: the lowest index among maxima). */
+void oracle_kmeanspp(int64_t n, int64_t d, const int64_t *rp, const int32_t *ci,
+                     const float *v, int32_t k, double alpha, const double *u,
+                     int32_t *chosen, int32_t *assign, double *best, double *second) {
+  csr_t X = {n, d, rp, ci, v};
+  double *c = (double *)calloc((size_t)d, sizeof(double));
+  double *w = (double *)malloc(sizeof(double) * (size_t)n);
+  char *taken = (char *)calloc((size_t)n, 1);
+  for (int64_t i = 0; i < n; ++i) {
+    best[i] = -INFINITY;
+    second[i] = -INFINITY;
+    assign[i] = -1;
+  }
+  int64_t p = (int64_t)floor(u[0] * (double)n);
+  if (p > n - 1) p = n - 1;
+  for (int32_t t = 0; t < k; ++t) {
+    if (t > 0) {
+      double W = 0.0;
+      for (int64_t i = 0; i < n; ++i) {
+        const double wi = taken[i] ? 0.0 : alpha - best[i];
+        w[i] = wi > 0.0 ? wi : 0.0;
+        W += w[i];
+      }
+      p = -1;
+      if (W > 0.0) {
+        const double target = u[t] * W;
+        double run = 0.0;
+        int64_t last = -1;
+        for (int64_t i = 0; i < n; ++i) {
+          if (w[i] > 0.0) last = i;
+          run += w[i];
+          if (run > target) { p = i; break; }
+        }
+        if (p < 0) p = last; /* rounding left the target unreached */
+      }
+      if (p < 0)
+        for (int64_t i = 0; i < n; ++i)
+          if (!taken[i]) { p = i; break; }
+    }
+    chosen[t] = (int32_t)p;
+    taken[p] = 1;
+    /* centre t: row p scaled to unit length */
+    memset(c, 0, sizeof(double) * (size_t)d);
+    double ss = 0.0;
+    for (int64_t e = rp[p]; e < rp[p + 1]; ++e) {
+      c[ci[e]] = (double)v[e];
+      ss += (double)v[e] * (double)v[e];
+    }
+    if (ss > 0.0) {
+      const double nrm = sqrt(ss);
+      for (int64_t e = rp[p]; e < rp[p + 1]; ++e) c[ci[e]] /= nrm;
+    }
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+      const double s = sim(&X, i, c);
+      if (s > best[i]) {
+        second[i] = best[i];
+        best[i] = s;
+        assign[i] = t;
+      } else if (s > second[i]) {
+        second[i] = s;
+      }
+    }
+  }
+  free(c);
+  free(w);
+  free(taken);
+}
+
+/* -------------------------------------------------------------------- */
 /* bound updates (Section 4 and 5.3), exported for the tests             */
 /* -------------------------------------------------------------------- */
 

@@ -338,3 +338,74 @@ def test_d2_arcs_by_hand():
     a, _, _ = oracle.assign(dense_csr(D), C)
     diff = np.abs((ang[:, None] - cang[None, :] + math.pi) % (2 * math.pi) - math.pi)
     assert np.array_equal(a, np.argmin(diff, axis=1))
+
+
+# ---------------------------------------------- Section 6, spherical k-means++
+
+def _circle(deg):
+    """Unit vectors at the given angles; multiples of 90 degrees are exact."""
+    a = np.radians(np.asarray(deg, dtype=np.float64))
+    P = np.stack([np.cos(a), np.sin(a)], 1)
+    exact = np.asarray(deg) % 90 == 0
+    P[exact] = np.rint(P[exact])
+    return dense_csr(P)
+
+
+def test_kmeanspp_by_hand():
+    """Points at 0, 10, 90, 180 and 270 degrees, alpha = 1.  u0 = 0.1 picks
+    row floor(0.5) = 0.  Weights 1 - cos(angle to 0 deg) are then
+    (0, 0.01519, 1, 2, 1), total 4.01519, so u1 = 0.6 (target 2.40911) is
+    first exceeded at the 180 degree row (running sums 0, 0.0152, 1.0152,
+    3.0152).  With centres at 0 and 180 the weights are (0, 0.01519, 1, 0,
+    1), total 2.01519: u2 = 0.5 (target 1.00760) stops at the 90 degree row
+    (running sum 1.01519) and u2 = 0.51 (target 1.02775) passes it and stops
+    at 270 degrees."""
+    X = _circle([0, 10, 90, 180, 270])
+    ch, a, s1, s2 = oracle.kmeanspp(X, 3, 1.0, np.array([0.1, 0.6, 0.5]))
+    assert list(ch) == [0, 3, 2]
+    # the cached step: 10 deg -> centre 0 (cos 10 vs cos 80); 270 deg is at
+    # 90 deg from centres 0 and 1 alike: the lower index wins
+    assert list(a) == [0, 0, 2, 1, 0]
+    c10, c80 = math.cos(math.radians(10)), math.cos(math.radians(80))
+    assert np.allclose(s1, [1, c10, 1, 1, 0], atol=1e-6)
+    assert np.allclose(s2, [0, c80, 0, 0, 0], atol=1e-6)
+    ch, _, _, _ = oracle.kmeanspp(X, 3, 1.0, np.array([0.1, 0.6, 0.51]))
+    assert list(ch) == [0, 3, 4]
+
+
+def test_kmeanspp_alpha_and_edge_draws():
+    """alpha = 1 gives a duplicate of a chosen row weight 0; the metric form
+    alpha = 1.5 gives it 0.5, so u = 0 (first row of positive weight) picks
+    it.  u just below 1 picks the last row of positive weight."""
+    X = _circle([0, 0, 90, 200])
+    ch, _, _, _ = oracle.kmeanspp(X, 2, 1.0, np.array([0.0, 0.0]))
+    assert list(ch) == [0, 2]
+    ch, _, _, _ = oracle.kmeanspp(X, 2, 1.5, np.array([0.0, 0.0]))
+    assert list(ch) == [0, 1]
+    ch, _, _, _ = oracle.kmeanspp(X, 2, 1.0, np.array([0.0, 1.0 - 1e-12]))
+    assert list(ch) == [0, 3]
+
+
+def test_kmeanspp_all_weights_zero():
+    """Identical, exactly unit rows: after the first draw every weight is 0
+    (alpha = 1), so the lowest-index rows not yet chosen follow."""
+    X = _circle([90, 90, 90, 90])
+    ch, a, _, _ = oracle.kmeanspp(X, 3, 1.0, np.array([0.9, 0.5, 0.5]))
+    assert list(ch) == [3, 0, 1]
+    assert np.all(a == 0)  # equal similarities: the lowest centre index
+
+
+def test_kmeanspp_cache_equals_assignment_step():
+    """The running maximum cached during seeding equals the exhaustive
+    assignment step against the chosen rows (unit length), and no row is
+    drawn twice."""
+    X, _, _ = datagen.sparse_workload("c1")
+    u = np.random.default_rng(5).random(10)
+    for alpha in (1.0, 1.5):
+        ch, a, s1, s2 = oracle.kmeanspp(X, 10, alpha, u)
+        assert len(set(ch.tolist())) == 10
+        C = datagen.init_centers_csr(X, ch).astype(np.float64)
+        C /= np.linalg.norm(C, axis=1, keepdims=True)
+        a2, t1, t2 = oracle.assign(X, C)
+        assert np.array_equal(a, a2)
+        assert np.max(np.abs(s1 - t1)) < 1e-13 and np.max(np.abs(s2 - t2)) < 1e-13
