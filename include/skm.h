@@ -103,6 +103,16 @@ typedef struct {            /* [host]; an all-zero struct means defaults      */
                                with HIP events on `stream` (fills the
                                sim_kernel_* statistics; adds event records) */
   double norm_tol;          /* default 1e-4                                   */
+  /* Warm start (CSR input; all three set or all NULL): the result of the
+     first assignment step against init_centers, as skm_seed_kmeanspp
+     returns it -- assignment int32[n] and the FP64 best and second-best
+     similarities double[n] in the canonical order.  skm_fit then takes
+     that step from these arrays instead of recomputing it and sets its
+     bounds from them, so pruning starts with the second step (the
+     seeding/bounds synergy named in the paper's conclusion). */
+  const int32_t* warm_assign;
+  const double* warm_best;
+  const double* warm_second;
 } skm_options;
 
 typedef struct {            /* [host] filled by skm_fit                       */
@@ -173,6 +183,33 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers,
 int skm_assign(const skm_matrix* X, int32_t k, const float* centers,
                int32_t* assign_out, float* best_sim_out, float* second_sim_out,
                void* workspace, size_t workspace_bytes, void* stream);
+
+/* Bytes of workspace skm_seed_kmeanspp needs. */
+size_t skm_seed_workspace_size(const skm_matrix* X, int32_t k);
+
+/* Spherical k-means++ seeding (Section 6, "Spherical k-means++"): centre 0
+ * is row floor(u[0] n); centre t >= 1 is drawn with probability
+ * proportional to alpha - max_c <x(i), c> over the centres chosen so far
+ * (alpha = 1: cosine dissimilarity; alpha = 1.5: the metric form), as the
+ * first row whose running weight sum exceeds u[t] W (W = total weight).
+ * Rows already chosen have weight 0 (no row is drawn twice); when W = 0 the
+ * lowest-index row not yet chosen is taken.  CSR input only.
+ *   alpha          >= 1.
+ *   uniforms       [host] double[k], each in [0, 1): the caller's draws.
+ *   chosen_out     int32[k]: the chosen row indices in draw order.
+ *   centers_out    float[k*d] row-major (nullable): the chosen rows.
+ *   assign_out, best_out, second_out (nullable; int32[n], double[n],
+ *                  double[n]): the assignment step against the chosen rows
+ *                  rescaled to unit length, cached during the seeding
+ *                  (ties to the lower index); skm_fit can start from it
+ *                  (skm_options.warm_*), so pruning already works in the
+ *                  first step.
+ * Asynchronous: returns after enqueueing. */
+int skm_seed_kmeanspp(const skm_matrix* X, int32_t k, double alpha,
+                      const double* uniforms, int32_t* chosen_out,
+                      float* centers_out, int32_t* assign_out, double* best_out,
+                      double* second_out, void* workspace, size_t workspace_bytes,
+                      void* stream);
 
 /* Many independent problems in one call (the batched setting: hundreds of
  * small clustering problems, each solved as in skm_fit).  The library runs

@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "lib")
 LIB = os.path.join(OUT, "libskm.so")
-SOURCES = ["kernels_assign.hip", "kernels_update.hip", "kernels_dense.hip", "skm_api.hip"]
+SOURCES = ["kernels_assign.hip", "kernels_update.hip", "kernels_dense.hip",
+           "kernels_seed.hip", "skm_api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          # packed FP32 instructions stay off (hipcc flag for the device pass)

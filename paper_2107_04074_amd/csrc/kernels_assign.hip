@@ -580,6 +580,37 @@ __global__ __launch_bounds__(kBlock) void k_elkan(ElkanArgs A) {
   }
 }
 
+// First assignment step taken from a given assignment and its FP64 top-2
+// (canonical order, e.g. cached by the k-means++ seeding): the assignment is
+// copied and the bounds are those of an exhaustive step whose decision was
+// taken in FP64 -- l <= cos(x, c_a), u and every Elkan u(i, j) >= the
+// second-best cosine (u(i, a) >= the best), rounded outward to float.
+__global__ __launch_bounds__(kBlock) void k_warm_start(
+    const int64_t* __restrict__ rp, int64_t n, int32_t k, int32_t kp,
+    const int32_t* __restrict__ wa, const double* __restrict__ wb,
+    const double* __restrict__ ws2, const float* __restrict__ eta, double delta_c,
+    int32_t* __restrict__ a, float* __restrict__ l, float* __restrict__ u,
+    float* __restrict__ ue) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const int64_t m = rp[i + 1] - rp[i];
+  const double e = (double)eta[i];
+  const double nx = (1.0 + e) * 1.01 + 1e-30;
+  const double rho64 = (double)(m + 2) * kU64 * nx + 1.01 * (e + delta_c) + 1e-15;
+  const int32_t ai = wa[i];
+  a[i] = ai;
+  const double lo = wb[i] - rho64;
+  const double hi = (k == 1) ? -1.0 : ws2[i] + rho64;
+  if (l) l[i] = __double2float_rd(fmax(lo, -1.0));
+  if (u) u[i] = __double2float_ru(fmin(hi, 1.0));
+  if (ue) {
+    const float top = __double2float_ru(fmin(wb[i] + rho64, 1.0));
+    const float other = __double2float_ru(fmin(hi, 1.0));
+    float* row = ue + (size_t)i * kp;
+    for (int j = 0; j < kp; ++j) row[j] = (j >= k) ? 1.0f : (j == ai ? top : other);
+  }
+}
+
 template <int MODE>
 hipError_t launch_assign_mode(const AssignArgs& A, hipStream_t s) {
   const Geometry g = pick_geometry(A.k);
@@ -611,6 +642,16 @@ hipError_t launch_assign_mode(const AssignArgs& A, hipStream_t s) {
 }
 
 }  // namespace
+
+hipError_t launch_warm_start(const int64_t* rp, int64_t n, int32_t k, int32_t kp,
+                             const int32_t* wa, const double* wb, const double* ws2,
+                             const float* eta, double delta_c, int32_t* a, float* l, float* u,
+                             float* ue, hipStream_t s) {
+  const unsigned blocks = (unsigned)((n + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_warm_start, dim3(blocks), dim3(kBlock), 0, s, rp, n, k, kp, wa, wb, ws2,
+                     eta, delta_c, a, l, u, ue);
+  return hipGetLastError();
+}
 
 hipError_t launch_assign(const AssignArgs& A, int mode, hipStream_t s) {
   if (mode == kModeAssign) return launch_assign_mode<kModeAssign>(A, s);

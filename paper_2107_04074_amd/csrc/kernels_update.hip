@@ -507,6 +507,11 @@ __global__ void k_c64_to_f32(const double* __restrict__ in, int64_t count, float
   if (e < count) out[e] = (float)in[e];
 }
 
+__global__ void k_fill_f64(double* p, int64_t count, double value) {
+  const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (e < count) p[e] = value;
+}
+
 __global__ void k_fill_i32(int32_t* p, int64_t count, int32_t value) {
   const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (e < count) p[e] = value;
@@ -618,6 +623,11 @@ hipError_t launch_gram_carry(double* G, int32_t k, const double* pc, const doubl
 
 hipError_t launch_c64_to_f32(const double* C64, int64_t count, float* out, hipStream_t s) {
   hipLaunchKernelGGL(k_c64_to_f32, dim3(blocks_for(count)), dim3(kBlock), 0, s, C64, count, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_f64(double* p, int64_t count, double value, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_f64, dim3(blocks_for(count)), dim3(kBlock), 0, s, p, count, value);
   return hipGetLastError();
 }
 

@@ -773,9 +773,16 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
   if (o.norm_tol <= 0.0) o.norm_tol = 1e-4;
   if (o.bound_form != 0 && o.bound_form != 1)
     return fail(SKM_ERR_INVALID_ARG, "bound_form must be 0 or 1");
-  if (X->fmt == SKM_DENSE_F32)
+  const int nwarm = (o.warm_assign != nullptr) + (o.warm_best != nullptr) +
+                    (o.warm_second != nullptr);
+  if (nwarm != 0 && nwarm != 3)
+    return fail(SKM_ERR_INVALID_ARG, "warm_assign, warm_best and warm_second go together");
+  const bool warm = nwarm == 3;
+  if (X->fmt == SKM_DENSE_F32) {
+    if (warm) return fail(SKM_ERR_UNSUPPORTED, "warm start needs CSR input");
     return fit_dense(X, k, init_centers, variant, max_iter, o, workspace, workspace_bytes,
                      assign_out, centers_out, centers64_out, stats, static_cast<hipStream_t>(stream));
+  }
   Plan P;
   int rc = make_plan(X, k, variant, &P);
   if (rc != SKM_OK) return rc;
@@ -888,7 +895,19 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
     }
 
     for (int32_t t = 0; t < max_iter; ++t) {
+      int64_t changed = n;
+      if (t == 0 && warm) {
+        // the first step's assignment and FP64 top-2 are given: bounds only
+        SKM_HIP(launch_warm_start(X->row_ptr, n, k, P.kp, o.warm_assign, o.warm_best,
+                                  o.warm_second, eta, delta_c, assign_out, l, u, ue, s));
+        if (stats && stats->changed_per_iter && stats->per_iter_len > 0)
+          stats->changed_per_iter[0] = n;
+        if (stats && stats->sims_per_iter && stats->per_iter_len > 0) stats->sims_per_iter[0] = 0;
+        iterations = 1;
+        goto centre_step;
+      }
       SKM_HIP(hipMemsetAsync(cnt, 0, kCounterSlots * sizeof(Counters), s));
+      {
       const bool exhaustive = (t == 0) || variant == SKM_LLOYD;
       if (ev0) SKM_HIP(hipEventRecord(ev0, s));
       if (exhaustive || !P.elkan) {
@@ -951,7 +970,7 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
       SKM_HIP(hipMemcpyAsync(hm, cnt, sizeof(HostMirror), hipMemcpyDeviceToHost, s));
       SKM_HIP(hipStreamSynchronize(s));
       const Counters tc = sum_slots(hm);
-      const int64_t changed = (int64_t)tc.changed;
+      changed = (int64_t)tc.changed;
       if (ev0) {
         float ms = 0.f;
         SKM_HIP(hipEventElapsedTime(&ms, ev0, ev1));
@@ -975,6 +994,8 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
         converged = 1;
         break;
       }
+      }
+    centre_step:
       // centre step
       SKM_HIP(launch_update_scan(X->row_ptr, X->col_idx, X->val, assign_out, a_old, n, d, fx, S,
                                  dirty, s));
@@ -1034,6 +1055,94 @@ done:
   return rc;
 }
 
+
+namespace {
+struct SeedPlan {
+  size_t taken = 0, a = 0, best = 0, second = 0, w = 0, part = 0, c64 = 0, u = 0, centres = 0,
+         chosen_dummy = 0, total = 0;
+};
+
+int make_seed_plan(const skm_matrix* X, int32_t k, SeedPlan* S) {
+  int rc = check_matrix(X);
+  if (rc != SKM_OK) return rc;
+  if (X->fmt != SKM_CSR_F32) return fail(SKM_ERR_UNSUPPORTED, "k-means++ seeding needs CSR input");
+  if (k < 1 || k > X->n) return fail(SKM_ERR_INVALID_ARG, "need 1 <= k <= n (k = %d)", (int)k);
+  const size_t n = (size_t)X->n, d = (size_t)X->d, nb = (n + kBlock - 1) / kBlock;
+  size_t cur = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = cur;
+    cur += align256(bytes);
+    return o;
+  };
+  S->taken = take(n);
+  S->a = take(n * 4);
+  S->best = take(n * 8);
+  S->second = take(n * 8);
+  S->w = take(n * 8);
+  S->part = take(nb * 8);
+  S->c64 = take(d * 8);
+  S->u = take((size_t)k * 8);
+  S->centres = take((size_t)k * d * 4);
+  S->total = cur;
+  return SKM_OK;
+}
+}  // namespace
+
+size_t skm_seed_workspace_size(const skm_matrix* X, int32_t k) {
+  g_last_error.clear();
+  SeedPlan S;
+  if (make_seed_plan(X, k, &S) != SKM_OK) return 0;
+  return S.total;
+}
+
+int skm_seed_kmeanspp(const skm_matrix* X, int32_t k, double alpha, const double* uniforms,
+                      int32_t* chosen_out, float* centers_out, int32_t* assign_out,
+                      double* best_out, double* second_out, void* workspace,
+                      size_t workspace_bytes, void* stream) {
+  g_last_error.clear();
+  SeedPlan S;
+  int rc = make_seed_plan(X, k, &S);
+  if (rc != SKM_OK) return rc;
+  if (!uniforms || !chosen_out) return fail(SKM_ERR_INVALID_ARG, "uniforms/chosen_out NULL");
+  if (!(alpha >= 1.0) || !std::isfinite(alpha))
+    return fail(SKM_ERR_INVALID_ARG, "need alpha >= 1 (got %g)", alpha);
+  for (int32_t t = 0; t < k; ++t)
+    if (!(uniforms[t] >= 0.0 && uniforms[t] < 1.0))
+      return fail(SKM_ERR_INVALID_ARG, "uniform %d = %g is not in [0, 1)", (int)t, uniforms[t]);
+  if (workspace && workspace_bytes < S.total)
+    return fail(SKM_ERR_OUT_OF_MEMORY, "workspace has %zu bytes, %zu needed", workspace_bytes,
+                S.total);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  bool owned = false;
+  void* ws = workspace;
+  if (!ws) {
+    if (hipMallocAsync(&ws, S.total, s) != hipSuccess)
+      return fail(SKM_ERR_OUT_OF_MEMORY, "could not allocate %zu bytes of workspace", S.total);
+    owned = true;
+  }
+  {
+    const int64_t n = X->n, d = X->d;
+    uint8_t* taken = at<uint8_t>(ws, S.taken);
+    int32_t* a = assign_out ? assign_out : at<int32_t>(ws, S.a);
+    double* best = best_out ? best_out : at<double>(ws, S.best);
+    double* second = second_out ? second_out : at<double>(ws, S.second);
+    float* centres = centers_out ? centers_out : at<float>(ws, S.centres);
+    double* u_dev = at<double>(ws, S.u);
+    SKM_HIP(hipMemcpyAsync(u_dev, uniforms, (size_t)k * sizeof(double), hipMemcpyHostToDevice, s));
+    SKM_HIP(hipMemsetAsync(taken, 0, (size_t)n, s));
+    SKM_HIP(hipMemsetAsync(centres, 0, (size_t)k * d * sizeof(float), s));
+    SKM_HIP(launch_fill_i32(a, n, -1, s));
+    SKM_HIP(launch_fill_f64(best, n, -INFINITY, s));
+    SKM_HIP(launch_fill_f64(second, n, -INFINITY, s));
+    for (int32_t t = 0; t < k; ++t)
+      SKM_HIP(launch_kpp_step(X->row_ptr, X->col_idx, X->val, n, d, t, alpha, u_dev, taken,
+                              chosen_out, centres, at<double>(ws, S.c64), a, best, second,
+                              at<double>(ws, S.w), at<double>(ws, S.part), s));
+  }
+done:
+  if (owned) (void)hipFreeAsync(ws, s);
+  return rc;
+}
 
 size_t skm_fit_batched_workspace_size(int32_t nprob, const skm_matrix* Xs, const int32_t* ks,
                                       int32_t variant, const skm_options* opt,

@@ -263,6 +263,20 @@ hipError_t launch_gram_carry(double* G, int32_t k, const double* pc, const doubl
 inline bool gram_exact_step(int updates_done, int since_exact, int64_t changed, int64_t n) {
   return updates_done < 2 || since_exact >= 3 || changed * 20 > n;
 }
+// First assignment step from a given assignment and FP64 top-2.
+hipError_t launch_warm_start(const int64_t* rp, int64_t n, int32_t k, int32_t kp,
+                             const int32_t* wa, const double* wb, const double* ws2,
+                             const float* eta, double delta_c, int32_t* a, float* l, float* u,
+                             float* ue, hipStream_t s);
+// One step of spherical k-means++ seeding: choose centre t, write it to
+// centres (FP32 k x d, zeroed) and its unit FP64 copy to c64 (d), refresh
+// every row's running top-2 (a, best, second), weights w and per-block
+// weight sums part.
+hipError_t launch_kpp_step(const int64_t* rp, const int32_t* ci, const float* v, int64_t n,
+                           int64_t d, int32_t t, double alpha, const double* u_dev,
+                           uint8_t* taken, int32_t* chosen, float* centres, double* c64,
+                           int32_t* a, double* best, double* second, double* w, double* part,
+                           hipStream_t s);
 // Gram slicing over d: number of column slices and their length.
 void gram_slicing(int32_t k, int64_t d, int* nslice, int64_t* slice_len);
 hipError_t launch_gram(const double* C64, int32_t k, int64_t d, const int32_t* dirty,
@@ -270,6 +284,7 @@ hipError_t launch_gram(const double* C64, int32_t k, int64_t d, const int32_t* d
                        double* G, double* gmax, double delta_g, Persist* per,
                        hipStream_t s);
 hipError_t launch_c64_to_f32(const double* C64, int64_t count, float* out, hipStream_t s);
+hipError_t launch_fill_f64(double* p, int64_t count, double value, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t count, int32_t value, hipStream_t s);
 
 }  // namespace skm

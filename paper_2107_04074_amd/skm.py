@@ -25,6 +25,7 @@ OK, ERR_INVALID_ARG, ERR_NOT_NORMALIZED, ERR_OUT_OF_MEMORY, ERR_HIP, ERR_UNSUPPO
 
 # Every symbol include/skm.h declares.
 EXPORTS = ("skm_workspace_size", "skm_assign_workspace_size", "skm_fit", "skm_assign",
+           "skm_seed_workspace_size", "skm_seed_kmeanspp",
            "skm_fit_batched_workspace_size", "skm_fit_batched",
            "skm_status_string", "skm_last_error", "skm_version")
 
@@ -39,7 +40,8 @@ class SkmMatrix(ctypes.Structure):
 class SkmOptions(ctypes.Structure):
     _fields_ = [("bound_form", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("validate", ctypes.c_int32), ("profile", ctypes.c_int32),
-                ("norm_tol", ctypes.c_double)]
+                ("norm_tol", ctypes.c_double), ("warm_assign", ctypes.c_void_p),
+                ("warm_best", ctypes.c_void_p), ("warm_second", ctypes.c_void_p)]
 
 
 class SkmStats(ctypes.Structure):
@@ -90,6 +92,11 @@ def load(path: str = LIB_PATH):
     lib.skm_fit_batched.argtypes = [i32, ctypes.POINTER(SkmMatrix), p, p, i32, p,
                                     ctypes.POINTER(SkmOptions), i32, p, sz, p, p,
                                     ctypes.POINTER(SkmStats), p]
+    lib.skm_seed_workspace_size.restype = sz
+    lib.skm_seed_workspace_size.argtypes = [ctypes.POINTER(SkmMatrix), i32]
+    lib.skm_seed_kmeanspp.restype = ctypes.c_int
+    lib.skm_seed_kmeanspp.argtypes = [ctypes.POINTER(SkmMatrix), i32, ctypes.c_double, p, p, p,
+                                      p, p, p, p, sz, p]
     lib.skm_status_string.restype = ctypes.c_char_p
     lib.skm_status_string.argtypes = [ctypes.c_int]
     lib.skm_last_error.restype = ctypes.c_char_p
@@ -188,8 +195,37 @@ class FitStats:
     objective_per_iter: np.ndarray = field(default_factory=lambda: np.zeros(0))
 
 
-def _options(bound_form=0, precision=0, validate=0, norm_tol=0.0, profile=0):
-    return SkmOptions(bound_form, precision, validate, profile, norm_tol)
+def _options(bound_form=0, precision=0, validate=0, norm_tol=0.0, profile=0, warm=None):
+    """warm: (assign, best, second) device tensors from seed_kmeanspp."""
+    w = (None, None, None) if warm is None else tuple(_ptr(t) for t in warm)
+    return SkmOptions(bound_form, precision, validate, profile, norm_tol, *w)
+
+
+def seed_kmeanspp(X: DeviceCSR, k: int, uniforms, alpha: float = 1.0, workspace=None):
+    """Runs skm_seed_kmeanspp with the caller's uniforms (k floats in
+    [0, 1)).  Returns (chosen int32, centers float32 (k, d), assign int32,
+    best float64, second float64) device tensors; asynchronous."""
+    import torch
+    lib = load()
+    dev = X.col.device
+    m = X.matrix()
+    u = np.ascontiguousarray(uniforms, dtype=np.float64)
+    if u.shape != (k,):
+        raise ValueError("need k uniforms")
+    if workspace is None:
+        size = lib.skm_seed_workspace_size(ctypes.byref(m), k)
+        if size == 0:
+            raise SkmError(ERR_INVALID_ARG, lib.skm_last_error().decode(errors="replace"))
+        workspace = torch.empty(size, dtype=torch.uint8, device=dev)
+    chosen = torch.empty(k, dtype=torch.int32, device=dev)
+    centers = torch.empty((k, X.d), dtype=torch.float32, device=dev)
+    a = torch.empty(X.n, dtype=torch.int32, device=dev)
+    best = torch.empty(X.n, dtype=torch.float64, device=dev)
+    second = torch.empty(X.n, dtype=torch.float64, device=dev)
+    _check(lib.skm_seed_kmeanspp(ctypes.byref(m), k, float(alpha), u.ctypes.data, _ptr(chosen),
+                                 _ptr(centers), _ptr(a), _ptr(best), _ptr(second),
+                                 _ptr(workspace), workspace.numel(), _stream()))
+    return chosen, centers, a, best, second
 
 
 def workspace_size(X: DeviceCSR, k: int, variant="hamerly", **opts) -> int:

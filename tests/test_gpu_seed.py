@@ -1,0 +1,85 @@
+"""GPU checks of spherical k-means++ seeding and the warm start (through the
+C ABI) against the FP64 oracle: the same uniforms give the same chosen rows;
+the cached assignment step matches the oracle's; a fit started from the
+cache reaches exactly the result of a cold fit from the same centres while
+computing fewer similarities."""
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    return torch
+
+
+@pytest.fixture(scope="module")
+def skm(torch_cuda):
+    from paper_2107_04074_amd import skm as s
+    s.load()
+    return s
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+CASES = [("c1", None, 10, 1.0), ("c1", None, 10, 1.5), ("c2", 20000, 100, 1.0),
+         ("c2", 3000, 3000, 1.0)]
+
+
+@pytest.mark.parametrize("name,n,k,alpha", CASES)
+def test_seeding_matches_oracle(skm, torch_cuda, name, n, k, alpha):
+    torch = torch_cuda
+    say("case seed %s n=%s k=%d alpha=%g" % (name, n, k, alpha))
+    X, _, _ = datagen.sparse_workload(name, n)
+    u = np.random.default_rng(k + int(10 * alpha)).random(k)
+    ch_ref, a_ref, s1_ref, s2_ref = oracle.kmeanspp(X, k, alpha, u)
+    Xd = skm.DeviceCSR.from_host(X)
+    ch, C, a, s1, s2 = skm.seed_kmeanspp(Xd, k, u, alpha)
+    torch.cuda.synchronize()
+    assert np.array_equal(ch.cpu().numpy(), ch_ref)
+    assert np.array_equal(C.cpu().numpy(), datagen.init_centers_csr(X, ch_ref))
+    assert np.array_equal(a.cpu().numpy(), a_ref)
+    assert np.abs(s1.cpu().numpy() - s1_ref).max() < 1e-12
+    fin = np.isfinite(s2_ref)
+    assert np.array_equal(np.isfinite(s2.cpu().numpy()), fin)
+    assert np.abs(s2.cpu().numpy()[fin] - s2_ref[fin]).max(initial=0.0) < 1e-12
+
+
+@pytest.mark.parametrize("variant", ["lloyd", "hamerly", "elkan", "simp_hamerly"])
+def test_warm_start_equals_cold_fit(skm, torch_cuda, variant):
+    torch = torch_cuda
+    X, _, cfg = datagen.sparse_workload("c2", 20000)
+    k = 100
+    u = np.random.default_rng(11).random(k)
+    Xd = skm.DeviceCSR.from_host(X)
+    ch, C, a, s1, s2 = skm.seed_kmeanspp(Xd, k, u)
+    say("case warm start %s" % variant)
+    ac, Cc, _, stc = skm.fit(Xd, k, C, variant, 60)
+    aw, Cw, _, stw = skm.fit(Xd, k, C, variant, 60, warm=(a, s1, s2))
+    torch.cuda.synchronize()
+    assert torch.equal(ac, aw) and torch.equal(Cc, Cw)
+    assert stc.iterations == stw.iterations and stc.converged == stw.converged
+    assert np.array_equal(stc.changed_per_iter, stw.changed_per_iter)
+    # step 1 is free (Lloyd: exactly n k fewer similarities); the bounded
+    # variants prune from step 2 on with bounds set from the FP64 cache
+    if variant == "lloyd":
+        assert stw.sims_point_center == stc.sims_point_center - X.n * k
+    else:
+        assert stw.sims_point_center < stc.sims_point_center
+    say("  iterations %d, sims cold %d warm %d" % (stc.iterations, stc.sims_point_center,
+                                                  stw.sims_point_center))
+    # and the result is the oracle's Lloyd fit from the same centres
+    if variant == "hamerly":
+        ref = oracle.fit(X, C.cpu().numpy(), "lloyd", 60)
+        assert ref.iterations == stw.iterations
+        assert np.array_equal(aw.cpu().numpy(), ref.a)
