@@ -129,6 +129,207 @@ __device__ __forceinline__ float row_sims(const int32_t* __restrict__ ci,
   return group_sum<G>(nrm2);
 }
 
+// One row per wave (G = 64): lane l owns the VEC-float chunks l + 64 r of
+// every CT row (centres VEC (l + 64 r) + q).  Column ids and values of 64
+// consecutive entries sit one per lane and are broadcast with readlane, so a
+// gather's address is a scalar base plus the lane's fixed offset.  Gathers
+// are double buffered in batches of U entries: the next batch is in flight
+// while the current one is consumed, also across 64-entry windows.  Every
+// similarity is still the sequential FMA chain over the row's entries in
+// storage order (entries past the end contribute x = 0).
+template <int R, int VEC>
+struct WaveBatch {
+  static constexpr int U = (R * VEC >= 16) ? 1 : 16 / (R * VEC);
+};
+
+template <int VEC>
+struct VecT;
+template <>
+struct VecT<2> {
+  typedef float2 type;
+};
+template <>
+struct VecT<4> {
+  typedef float4 type;
+};
+
+template <int R, int VEC>
+using WaveBuf = typename VecT<VEC>::type[WaveBatch<R, VEC>::U][R];
+
+__device__ __forceinline__ int lane_int(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ __forceinline__ float lane_float(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
+// Issues the gathers of U consecutive entries whose column ids sit in lanes
+// first .. first + U - 1 of cw.  No bounds branch: lanes past the row end
+// hold column 0 and value 0, so their gathers read centre row 0 and add
+// exactly nothing.
+template <int R, int VEC>
+__device__ __forceinline__ void wave_issue(WaveBuf<R, VEC>& dst, int cw, int first,
+                                           const float* __restrict__ CT, int kp, int lane) {
+  typedef typename VecT<VEC>::type V;
+  constexpr int U = WaveBatch<R, VEC>::U;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int cu = lane_int(cw, first + u);
+    const V* p = reinterpret_cast<const V*>(CT + (size_t)(uint32_t)cu * (uint32_t)kp) + lane;
+#pragma unroll
+    for (int r = 0; r < R; ++r) dst[u][r] = p[64 * r];
+  }
+}
+
+template <int R, int VEC>
+__device__ __forceinline__ void wave_consume(const WaveBuf<R, VEC>& src, float xw, int first, float4 (&acc)[R]) {
+  constexpr int U = WaveBatch<R, VEC>::U;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const float xu = lane_float(xw, first + u);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      acc[r].x = fmaf(xu, src[u][r].x, acc[r].x);
+      acc[r].y = fmaf(xu, src[u][r].y, acc[r].y);
+      if constexpr (VEC == 4) {
+        acc[r].z = fmaf(xu, src[u][r].z, acc[r].z);
+        acc[r].w = fmaf(xu, src[u][r].w, acc[r].w);
+      }
+    }
+  }
+}
+
+template <int R, int VEC>
+__device__ __forceinline__ float row_sims_wave(const int32_t* __restrict__ ci,
+                                               const float* __restrict__ v, int64_t beg,
+                                               int64_t end, const float* __restrict__ CT, int kp,
+                                               int lane, float4 (&acc)[R]) {
+  constexpr int U = WaveBatch<R, VEC>::U;
+  constexpr int NB = 64 / U;  // batches per window (even)
+#pragma unroll
+  for (int r = 0; r < R; ++r) acc[r] = make_float4(0.f, 0.f, 0.f, 0.f);
+  float nrm2 = 0.f;
+  WaveBuf<R, VEC> buf0, buf1;
+  int c = 0;
+  float x = 0.f;
+  if (beg + lane < end) {
+    c = ci[beg + lane];
+    x = v[beg + lane];
+  }
+  wave_issue<R, VEC>(buf0, c, 0, CT, kp, lane);
+  for (int64_t w0 = beg; w0 < end; w0 += 64) {
+    int cn = 0;
+    float xn = 0.f;
+    if (w0 + 64 + lane < end) {
+      cn = ci[w0 + 64 + lane];
+      xn = v[w0 + 64 + lane];
+    }
+    nrm2 = fmaf(x, x, nrm2);
+    // unrolled: straight-line code lets the compiler count the loads in
+    // flight exactly and wait only for the buffer being consumed
+#pragma unroll
+    for (int b = 0; b < NB; b += 2) {
+      const int64_t eb = w0 + (int64_t)b * U;
+      if (eb >= end) break;
+      wave_issue<R, VEC>(buf1, c, (b + 1) * U, CT, kp, lane);
+      __builtin_amdgcn_sched_barrier(0);  // keep these loads ahead of the FMAs below
+      wave_consume<R, VEC>(buf0, x, b * U, acc);
+      if (eb + U >= end) break;
+      if (b + 2 < NB) wave_issue<R, VEC>(buf0, c, (b + 2) * U, CT, kp, lane);
+      else wave_issue<R, VEC>(buf0, cn, 0, CT, kp, lane);
+      __builtin_amdgcn_sched_barrier(0);
+      wave_consume<R, VEC>(buf1, x, (b + 1) * U, acc);
+    }
+    c = cn;
+    x = xn;
+  }
+  return group_sum<64>(nrm2);
+}
+
+// One row per wave for kp = 128: each half-wave covers all 128 centres with
+// float4 chunks (lane l & 31 owns centres 4 (l & 31) + q); half 0 takes the
+// even entries of the row, half 1 the odd ones, so every gather instruction
+// fetches two entries' CT rows (1 KB).  Column ids and values come from the
+// 64-entry window by readlane; gathers are double buffered in batches of
+// U entry pairs.  The two partial FMA chains are added at the end, so both
+// halves hold the same sums (a fixed order: deterministic; any order is
+// covered by the error bound of the re-decision).
+template <int U>
+__device__ __forceinline__ void split_issue(float4 (&dst)[U], int cw, int first_pair,
+                                            const float4* __restrict__ CT4, int kp4, int gl,
+                                            bool odd) {
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int ce = lane_int(cw, 2 * (first_pair + u));
+    const int co = lane_int(cw, 2 * (first_pair + u) + 1);
+    const int cu = odd ? co : ce;
+    dst[u] = CT4[(uint32_t)((uint32_t)cu * (uint32_t)kp4) + gl];
+  }
+}
+
+template <int U>
+__device__ __forceinline__ void split_consume(const float4 (&src)[U], float xw, int first_pair,
+                                              bool odd, float4& acc) {
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const float xe = lane_float(xw, 2 * (first_pair + u));
+    const float xo = lane_float(xw, 2 * (first_pair + u) + 1);
+    const float xu = odd ? xo : xe;
+    acc.x = fmaf(xu, src[u].x, acc.x);
+    acc.y = fmaf(xu, src[u].y, acc.y);
+    acc.z = fmaf(xu, src[u].z, acc.z);
+    acc.w = fmaf(xu, src[u].w, acc.w);
+  }
+}
+
+__device__ __forceinline__ float row_sims_split(const int32_t* __restrict__ ci,
+                                                const float* __restrict__ v, int64_t beg,
+                                                int64_t end, const float4* __restrict__ CT4,
+                                                int kp4, int lane, float4 (&acc)[1]) {
+  constexpr int U = 8;
+  constexpr int NB = 32 / U;  // batches of U pairs per 64-entry window (even)
+  const int gl = lane & 31;
+  const bool odd = (lane >> 5) != 0;
+  float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
+  float nrm2 = 0.f;
+  float4 buf0[U], buf1[U];
+  int c = 0;
+  float x = 0.f;
+  if (beg + lane < end) {
+    c = ci[beg + lane];
+    x = v[beg + lane];
+  }
+  split_issue<U>(buf0, c, 0, CT4, kp4, gl, odd);
+  for (int64_t w0 = beg; w0 < end; w0 += 64) {
+    int cn = 0;
+    float xn = 0.f;
+    if (w0 + 64 + lane < end) {
+      cn = ci[w0 + 64 + lane];
+      xn = v[w0 + 64 + lane];
+    }
+    nrm2 = fmaf(x, x, nrm2);
+#pragma unroll
+    for (int b = 0; b < NB; b += 2) {
+      const int64_t eb = w0 + (int64_t)(2 * U) * b;
+      if (eb >= end) break;
+      split_issue<U>(buf1, c, (b + 1) * U, CT4, kp4, gl, odd);
+      __builtin_amdgcn_sched_barrier(0);  // keep these loads ahead of the FMAs below
+      split_consume<U>(buf0, x, b * U, odd, a);
+      if (eb + 2 * U >= end) break;
+      if (b + 2 < NB) split_issue<U>(buf0, c, (b + 2) * U, CT4, kp4, gl, odd);
+      else split_issue<U>(buf0, cn, 0, CT4, kp4, gl, odd);
+      __builtin_amdgcn_sched_barrier(0);
+      split_consume<U>(buf1, x, (b + 1) * U, odd, a);
+    }
+    c = cn;
+    x = xn;
+  }
+  a.x += __shfl_xor(a.x, 32, 64);
+  a.y += __shfl_xor(a.y, 32, 64);
+  a.z += __shfl_xor(a.z, 32, 64);
+  a.w += __shfl_xor(a.w, 32, 64);
+  acc[0] = a;
+  return group_sum<64>(nrm2);
+}
+
 // ------------------------------------------------------------------------
 // k_assign_csr
 // ------------------------------------------------------------------------
@@ -138,7 +339,7 @@ __device__ __forceinline__ float row_sims(const int32_t* __restrict__ ci,
 // row needs no similarity walk; the bounds are then already stored.
 template <int G>
 __device__ __forceinline__ bool hamerly_prologue(const AssignArgs& A, int64_t row, int prev,
-                                                 int64_t beg, int64_t end, int gl,
+                                                 int64_t beg, int64_t end, int gl, bool leader,
                                                  unsigned long long& tight,
                                                  unsigned long long& saved) {
   const int m = (int)(end - beg);
@@ -169,22 +370,28 @@ __device__ __forceinline__ bool hamerly_prologue(const AssignArgs& A, int64_t ro
   if (!skip && A.try_tighten) {
     const float s32 = group_col_dot32<G>(A.ci, A.v, beg, end, A.CT, A.kp, prev, gl);
     ld = fmax(ld, (double)s32 - rho32);
-    if (gl == 0) tight += 1;
+    if (leader) tight += 1;
     skip = pruned(ld);
-    if (skip && gl == 0) saved += 1;
+    if (skip && leader) saved += 1;
   }
-  if (skip && gl == 0) {
+  if (skip && leader) {
     A.l[row] = __double2float_rd(fmax(ld, -1.0));
     A.u[row] = __double2float_ru(ud);
   }
   return skip;
 }
 
-template <int G, int R, int MODE>
+template <int G, int R, int VEC, int MODE, bool SPLIT>
 __global__ __launch_bounds__(kBlock) void k_assign_csr(AssignArgs A) {
-  constexpr int GPB = kBlock / G;
+  static_assert(VEC == 4 || (VEC == 2 && G == 64), "float2 chunks need the wave layout");
+  static_assert(!SPLIT || (G == 32 && R == 1), "split rows are for kp = 128");
+  constexpr bool WAVE_ROW = SPLIT || G == 64;  // one row per wave
+  constexpr int GPB = WAVE_ROW ? kBlock / 64 : kBlock / G;
   const int gl = threadIdx.x & (G - 1);
-  const int gib = threadIdx.x / G;
+  const int gib = WAVE_ROW ? (int)(threadIdx.x >> 6) : (int)(threadIdx.x / G);
+  // the lane that writes per-row results and counts (split rows: both
+  // halves hold the same values; the lower half writes)
+  const bool leader = WAVE_ROW ? (threadIdx.x & 63) == 0 : gl == 0;
   __shared__ unsigned long long sh[6];
   if (threadIdx.x < 6) sh[threadIdx.x] = 0;
   __syncthreads();
@@ -196,23 +403,35 @@ __global__ __launch_bounds__(kBlock) void k_assign_csr(AssignArgs A) {
 
   for (int64_t row = (int64_t)blockIdx.x * GPB + gib; row < A.n_rows;
        row += (int64_t)gridDim.x * GPB) {
-    const int64_t beg = A.rp[row], end = A.rp[row + 1];
+    int64_t beg = A.rp[row], end = A.rp[row + 1];
+    if constexpr (WAVE_ROW) {  // one row per wave: keep the loop bounds scalar
+      beg = ((int64_t)__builtin_amdgcn_readfirstlane((int)(beg >> 32)) << 32) |
+            (uint32_t)__builtin_amdgcn_readfirstlane((int)beg);
+      end = ((int64_t)__builtin_amdgcn_readfirstlane((int)(end >> 32)) << 32) |
+            (uint32_t)__builtin_amdgcn_readfirstlane((int)end);
+    }
     const int m = (int)(end - beg);
     const int prev = A.read_prev ? A.a[row] : -1;
     if (MODE == kModeHamerly) {
-      if (hamerly_prologue<G>(A, row, prev, beg, end, gl, my_tight, my_saved)) continue;
+      if (hamerly_prologue<G>(A, row, prev, beg, end, gl, leader, my_tight, my_saved)) continue;
     }
 
     float4 acc[R];
-    const float nrm2 = row_sims<G, R, false>(A.ci, A.v, beg, end, CT4, kp4, gl, ~0u, acc);
+    float nrm2;
+    if constexpr (SPLIT)
+      nrm2 = row_sims_split(A.ci, A.v, beg, end, CT4, kp4, threadIdx.x & 63, acc);
+    else if constexpr (G == 64)
+      nrm2 = row_sims_wave<R, VEC>(A.ci, A.v, beg, end, A.CT, A.kp, gl, acc);
+    else
+      nrm2 = row_sims<G, R, false>(A.ci, A.v, beg, end, CT4, kp4, gl, ~0u, acc);
 
     float b = -INFINITY, s2 = -INFINITY;
     int bj = INT_MAX;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int j = 4 * (gl + G * r) + q;
+      for (int q = 0; q < VEC; ++q) {
+        const int j = VEC * (gl + G * r) + q;
         if (j < k) {
           const float sv = f4get(acc[r], q);
           if (better32(sv, j, b, bj, prev)) {
@@ -244,8 +463,8 @@ __global__ __launch_bounds__(kBlock) void k_assign_csr(AssignArgs A) {
 #pragma unroll
       for (int r = 0; r < R; ++r)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int j = 4 * (gl + G * r) + q;
+        for (int q = 0; q < VEC; ++q) {
+          const int j = VEC * (gl + G * r) + q;
           if (j < k && (double)f4get(acc[r], q) >= thr) cm |= 1ull << (4 * r + q);
         }
       double cb = -INFINITY;
@@ -253,7 +472,7 @@ __global__ __launch_bounds__(kBlock) void k_assign_csr(AssignArgs A) {
       while (cm) {
         const int bit = __builtin_ctzll(cm);
         cm &= cm - 1ull;
-        const int j = 4 * (gl + G * (bit >> 2)) + (bit & 3);
+        const int j = VEC * (gl + G * (bit >> 2)) + (bit & 3);
         const double sv = dot64(A.ci, A.v, beg, end, A.C64 + (size_t)j * A.d);
         if (better64(sv, j, cb, cj, prev)) {
           cb = sv;
@@ -267,7 +486,7 @@ __global__ __launch_bounds__(kBlock) void k_assign_csr(AssignArgs A) {
     }
 
     if (MODE == kModeAssign) {
-      if (gl == 0) {
+      if (leader) {
         A.a[row] = abest;
         if (A.best_out) A.best_out[row] = rechecked ? (float)best64 : b;
         if (A.second_out) A.second_out[row] = (rechecked && abest != bj) ? b : s2;
@@ -278,7 +497,7 @@ __global__ __launch_bounds__(kBlock) void k_assign_csr(AssignArgs A) {
       const double eta = (double)A.eta[row];
       const double slack = 1.01 * (eta + A.delta_c);
       const double rho32 = eps + slack + 1e-12;
-      if (gl == 0) {
+      if (leader) {
         const double rho64 = (double)(m + 2) * kU64 * nx + slack + 1e-15;
         A.a[row] = abest;
         my_changed += (abest != prev) ? 1ull : 0ull;
@@ -291,23 +510,24 @@ __global__ __launch_bounds__(kBlock) void k_assign_csr(AssignArgs A) {
           A.u[row] = __double2float_ru(fmin(hi, 1.0));
         }
       }
-      if (MODE == kModeFitElkanInit) {
-        float4* ue4 = reinterpret_cast<float4*>(A.ue + (size_t)row * A.kp);
+      if (MODE == kModeFitElkanInit && (!SPLIT || (threadIdx.x & 32) == 0)) {
+        float* uer = A.ue + (size_t)row * A.kp;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           float4 o;
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const int j = 4 * (gl + G * r) + q;
+          for (int q = 0; q < VEC; ++q) {
+            const int j = VEC * (gl + G * r) + q;
             const float val = (j < k) ? __double2float_ru(fmin((double)f4get(acc[r], q) + rho32, 1.0))
                                       : 1.0f;
             f4set(o, q, val);
           }
-          ue4[gl + G * r] = o;
+          if constexpr (VEC == 4) reinterpret_cast<float4*>(uer)[gl + G * r] = o;
+          else reinterpret_cast<float2*>(uer)[gl + G * r] = make_float2(o.x, o.y);
         }
       }
     }
-    if (gl == 0) {
+    if (leader) {
       my_rows += 1;
       my_nnz += (unsigned long long)m;
       my_rechecks += rechecked ? 1 : 0;
@@ -615,25 +835,28 @@ template <int MODE>
 hipError_t launch_assign_mode(const AssignArgs& A, hipStream_t s) {
   const Geometry g = pick_geometry(A.k);
   if (g.G == 0 || g.kp != A.kp) return hipErrorInvalidValue;
-  const int gpb = kBlock / g.G;
+  const int gpb = kBlock / (g.G == 32 ? 64 : g.G);  // rows per block
   int64_t blocks = (A.n_rows + gpb - 1) / gpb;
   if (blocks > kMaxGridBlocks) blocks = kMaxGridBlocks;
   if (blocks < 1) blocks = 1;
   const dim3 grid((unsigned)blocks), block(kBlock);
-#define SKM_CASE(GG, RR)                                                  \
-  case GG * 100 + RR:                                                     \
-    hipLaunchKernelGGL((k_assign_csr<GG, RR, MODE>), grid, block, 0, s, A); \
+#define SKM_CASE(GG, RR, SP)                                                        \
+  case GG * 100 + RR:                                                               \
+    hipLaunchKernelGGL((k_assign_csr<GG, RR, 4, MODE, SP>), grid, block, 0, s, A); \
     break;
+  // k <= 64: several rows per wave (groups of 4..16 lanes); k in (64, 128]:
+  // one row per wave, half-waves on alternating entries; larger k: one row
+  // per wave, float4 chunks per lane
   switch (g.G * 100 + g.R) {
-    SKM_CASE(4, 1)
-    SKM_CASE(8, 1)
-    SKM_CASE(16, 1)
-    SKM_CASE(32, 1)
-    SKM_CASE(64, 1)
-    SKM_CASE(64, 2)
-    SKM_CASE(64, 4)
-    SKM_CASE(64, 8)
-    SKM_CASE(64, 16)
+    SKM_CASE(4, 1, false)
+    SKM_CASE(8, 1, false)
+    SKM_CASE(16, 1, false)
+    SKM_CASE(32, 1, true)
+    SKM_CASE(64, 1, false)
+    SKM_CASE(64, 2, false)
+    SKM_CASE(64, 4, false)
+    SKM_CASE(64, 8, false)
+    SKM_CASE(64, 16, false)
     default:
       return hipErrorInvalidValue;
   }
