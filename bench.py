@@ -141,11 +141,15 @@ def main():
     ws = {}
 
     def split(v):
-        # "<variant>" or "<variant>_fp32" / "<variant>_bf16" for dense input
+        # "<variant>", or with a precision suffix: "_fp32" (FP32 similarities),
+        # "_bf16" (dense: BF16 matrix cores), "_fp16" (CSR: FP16 centre copy
+        # for the row walk); every precision gives the same exact assignments
         if v.endswith("_fp32"):
             return v[:-5], 0
         if v.endswith("_bf16"):
             return v[:-5], 1
+        if v.endswith("_fp16"):
+            return v[:-5], 2
         return v, (1 if dense else 0)
 
     def workspace(v):
@@ -209,7 +213,8 @@ def main():
     variants = {}
     table = (["lloyd_fp32", "lloyd_bf16", "simp_hamerly_bf16", "hamerly_bf16",
               "hamerly_fp32"] if dense else
-             ["lloyd", "simp_hamerly", "hamerly", "simp_elkan", "elkan"])
+             ["lloyd", "simp_hamerly", "hamerly", "simp_elkan", "elkan", "lloyd_fp16",
+              "simp_hamerly_fp16", "hamerly_fp16"])
     for v in ([] if (args.quick or args.skip_baseline) else table):
         one_fit(v)
         best = None
@@ -270,7 +275,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": ("bf16" if split(args.variant)[1] == 1 else "f32") if dense else "f32",
+        "dtype": {0: "f32", 1: "bf16", 2: "f32"}[split(args.variant)[1]],
         "data": "synthetic",
         "config": {"workload": "%s: spherical k-means %s, n=%d d=%d nnz=%d k=%d, seeded "
                                "random-row init, %s" % (
@@ -278,7 +283,8 @@ def main():
                                    "run to no-change" if not dense else
                                    "%d assignment steps" % max_iter),
                    "variant": args.variant, "n": n_rows, "d": d_cols, "nnz": nnz, "k": k,
-                   "max_iter": max_iter, "parallelism": "single GPU"},
+                   "max_iter": max_iter, "parallelism": "single GPU",
+                   "centre_copy": {0: "fp32", 1: "bf16", 2: "fp16"}[split(args.variant)[1]]},
         "iterations_per_fit": st.iterations,
         "converged": st.converged,
         "identical_assignments_to_lloyd": identical,

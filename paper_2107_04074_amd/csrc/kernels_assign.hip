@@ -21,6 +21,8 @@
 #include <float.h>
 #include <limits.h>
 
+#include <hip/hip_fp16.h>
+
 #include "skm_device.h"
 #include "skm_internal.h"
 
@@ -129,92 +131,109 @@ __device__ __forceinline__ float row_sims(const int32_t* __restrict__ ci,
   return group_sum<G>(nrm2);
 }
 
-// One row per wave (G = 64): lane l owns the VEC-float chunks l + 64 r of
-// every CT row (centres VEC (l + 64 r) + q).  Column ids and values of 64
-// consecutive entries sit one per lane and are broadcast with readlane, so a
-// gather's address is a scalar base plus the lane's fixed offset.  Gathers
-// are double buffered in batches of U entries: the next batch is in flight
-// while the current one is consumed, also across 64-entry windows.  Every
-// similarity is still the sequential FMA chain over the row's entries in
-// storage order (entries past the end contribute x = 0).
-template <int R, int VEC>
-struct WaveBatch {
-  static constexpr int U = (R * VEC >= 16) ? 1 : 16 / (R * VEC);
+// One row per wave.  The 64 lanes form S = 64 / L sub-waves of L lanes;
+// sub-wave s takes the entries s, s + S, s + 2S, ... of the row, and lane
+// gl of a sub-wave owns chunks gl + L r (r < R) of every centre row: VEC
+// consecutive centres, stored as FP32 (VEC = 4) or FP16 (VEC = 8), 16 bytes
+// either way, so one gather instruction fetches S entries' rows.  Column
+// ids and values of 64 consecutive entries sit one per lane and are handed
+// to the sub-waves by readlane (S = 1) or a lane shuffle; gathers are double
+// buffered in batches of U entries per sub-wave, the next batch in flight
+// while the current one is consumed, also across 64-entry windows.  Lanes
+// past the row end hold column 0 and value 0: their gathers read centre row
+// 0 and add exactly nothing, so no bounds branch sits between the loads.
+// Each sub-wave's sums are a sequential FMA chain; the S partial chains are
+// added by a fixed xor tree at the end, so all sub-waves hold the same sums
+// (the order is covered by the error bound of the re-decision).
+template <int R>
+struct WalkBatch {
+  static constexpr int U = (R >= 8) ? 1 : 8 / R;
 };
-
-template <int VEC>
-struct VecT;
-template <>
-struct VecT<2> {
-  typedef float2 type;
-};
-template <>
-struct VecT<4> {
-  typedef float4 type;
-};
-
-template <int R, int VEC>
-using WaveBuf = typename VecT<VEC>::type[WaveBatch<R, VEC>::U][R];
 
 __device__ __forceinline__ int lane_int(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
 __device__ __forceinline__ float lane_float(float v, int l) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
 
-// Issues the gathers of U consecutive entries whose column ids sit in lanes
-// first .. first + U - 1 of cw.  No bounds branch: lanes past the row end
-// hold column 0 and value 0, so their gathers read centre row 0 and add
-// exactly nothing.
-template <int R, int VEC>
-__device__ __forceinline__ void wave_issue(WaveBuf<R, VEC>& dst, int cw, int first,
-                                           const float* __restrict__ CT, int kp, int lane) {
-  typedef typename VecT<VEC>::type V;
-  constexpr int U = WaveBatch<R, VEC>::U;
+template <int S>
+__device__ __forceinline__ int entry_int(int w, int idx_uniform, int sub) {
+  if constexpr (S == 1) return lane_int(w, idx_uniform);
+  else return __shfl(w, idx_uniform + sub, 64);
+}
+template <int S>
+__device__ __forceinline__ float entry_float(float w, int idx_uniform, int sub) {
+  if constexpr (S == 1) return lane_float(w, idx_uniform);
+  else return __shfl(w, idx_uniform + sub, 64);
+}
+
+template <int L, int R>
+__device__ __forceinline__ void walk_issue(uint4 (&dst)[WalkBatch<R>::U][R], int cw, int first,
+                                           int sub, const uint4* __restrict__ C16B, int kp16,
+                                           int gl) {
+  constexpr int S = 64 / L;
+  constexpr int U = WalkBatch<R>::U;
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    const int cu = lane_int(cw, first + u);
-    const V* p = reinterpret_cast<const V*>(CT + (size_t)(uint32_t)cu * (uint32_t)kp) + lane;
+    const int cu = entry_int<S>(cw, S * (first + u), sub);
+    const uint4* p = C16B + (uint32_t)((uint32_t)cu * (uint32_t)kp16) + gl;
 #pragma unroll
-    for (int r = 0; r < R; ++r) dst[u][r] = p[64 * r];
+    for (int r = 0; r < R; ++r) dst[u][r] = p[L * r];
   }
 }
 
-template <int R, int VEC>
-__device__ __forceinline__ void wave_consume(const WaveBuf<R, VEC>& src, float xw, int first, float4 (&acc)[R]) {
-  constexpr int U = WaveBatch<R, VEC>::U;
+template <int L, int R, int VEC>
+__device__ __forceinline__ void walk_consume(const uint4 (&src)[WalkBatch<R>::U][R], float xw,
+                                             int first, int sub,
+                                             float4 (&acc)[R * VEC / 4]) {
+  constexpr int S = 64 / L;
+  constexpr int U = WalkBatch<R>::U;
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    const float xu = lane_float(xw, first + u);
+    const float xu = entry_float<S>(xw, S * (first + u), sub);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      acc[r].x = fmaf(xu, src[u][r].x, acc[r].x);
-      acc[r].y = fmaf(xu, src[u][r].y, acc[r].y);
       if constexpr (VEC == 4) {
-        acc[r].z = fmaf(xu, src[u][r].z, acc[r].z);
-        acc[r].w = fmaf(xu, src[u][r].w, acc[r].w);
+        float4& a = acc[r];
+        a.x = fmaf(xu, __uint_as_float(src[u][r].x), a.x);
+        a.y = fmaf(xu, __uint_as_float(src[u][r].y), a.y);
+        a.z = fmaf(xu, __uint_as_float(src[u][r].z), a.z);
+        a.w = fmaf(xu, __uint_as_float(src[u][r].w), a.w);
+      } else {
+        const uint32_t wv[4] = {src[u][r].x, src[u][r].y, src[u][r].z, src[u][r].w};
+        float4& a = acc[2 * r];
+        float4& b = acc[2 * r + 1];
+        a.x = fmaf(xu, __half2float(__ushort_as_half((unsigned short)(wv[0] & 0xffffu))), a.x);
+        a.y = fmaf(xu, __half2float(__ushort_as_half((unsigned short)(wv[0] >> 16))), a.y);
+        a.z = fmaf(xu, __half2float(__ushort_as_half((unsigned short)(wv[1] & 0xffffu))), a.z);
+        a.w = fmaf(xu, __half2float(__ushort_as_half((unsigned short)(wv[1] >> 16))), a.w);
+        b.x = fmaf(xu, __half2float(__ushort_as_half((unsigned short)(wv[2] & 0xffffu))), b.x);
+        b.y = fmaf(xu, __half2float(__ushort_as_half((unsigned short)(wv[2] >> 16))), b.y);
+        b.z = fmaf(xu, __half2float(__ushort_as_half((unsigned short)(wv[3] & 0xffffu))), b.z);
+        b.w = fmaf(xu, __half2float(__ushort_as_half((unsigned short)(wv[3] >> 16))), b.w);
       }
     }
   }
 }
 
-template <int R, int VEC>
-__device__ __forceinline__ float row_sims_wave(const int32_t* __restrict__ ci,
-                                               const float* __restrict__ v, int64_t beg,
-                                               int64_t end, const float* __restrict__ CT, int kp,
-                                               int lane, float4 (&acc)[R]) {
-  constexpr int U = WaveBatch<R, VEC>::U;
-  constexpr int NB = 64 / U;  // batches per window (even)
+template <int L, int R, int VEC>
+__device__ __forceinline__ float row_walk(const int32_t* __restrict__ ci,
+                                          const float* __restrict__ v, int64_t beg, int64_t end,
+                                          int c0, float x0, const void* __restrict__ CTB, int kp,
+                                          int lane, float4 (&acc)[R * VEC / 4]) {
+  constexpr int S = 64 / L;
+  constexpr int U = WalkBatch<R>::U;
+  constexpr int PER_WIN = 64 / (S * U);  // batches per 64-entry window (even)
+  static_assert(PER_WIN % 2 == 0, "double buffering needs an even batch count");
+  const int sub = lane / L, gl = lane % L;
+  const uint4* C16B = reinterpret_cast<const uint4*>(CTB);
+  const int kp16 = kp / VEC;  // 16-byte chunks per centre row
 #pragma unroll
-  for (int r = 0; r < R; ++r) acc[r] = make_float4(0.f, 0.f, 0.f, 0.f);
+  for (int q = 0; q < R * VEC / 4; ++q) acc[q] = make_float4(0.f, 0.f, 0.f, 0.f);
   float nrm2 = 0.f;
-  WaveBuf<R, VEC> buf0, buf1;
-  int c = 0;
-  float x = 0.f;
-  if (beg + lane < end) {
-    c = ci[beg + lane];
-    x = v[beg + lane];
-  }
-  wave_issue<R, VEC>(buf0, c, 0, CT, kp, lane);
+  uint4 buf0[U][R], buf1[U][R];
+  int c = c0;  // entries beg .. beg + 63, loaded by the caller (0 past the end)
+  float x = x0;
+  walk_issue<L, R>(buf0, c, 0, sub, C16B, kp16, gl);
   for (int64_t w0 = beg; w0 < end; w0 += 64) {
     int cn = 0;
     float xn = 0.f;
@@ -226,107 +245,30 @@ __device__ __forceinline__ float row_sims_wave(const int32_t* __restrict__ ci,
     // unrolled: straight-line code lets the compiler count the loads in
     // flight exactly and wait only for the buffer being consumed
 #pragma unroll
-    for (int b = 0; b < NB; b += 2) {
-      const int64_t eb = w0 + (int64_t)b * U;
+    for (int b = 0; b < PER_WIN; b += 2) {
+      const int64_t eb = w0 + (int64_t)(S * U) * b;
       if (eb >= end) break;
-      wave_issue<R, VEC>(buf1, c, (b + 1) * U, CT, kp, lane);
+      walk_issue<L, R>(buf1, c, (b + 1) * U, sub, C16B, kp16, gl);
       __builtin_amdgcn_sched_barrier(0);  // keep these loads ahead of the FMAs below
-      wave_consume<R, VEC>(buf0, x, b * U, acc);
-      if (eb + U >= end) break;
-      if (b + 2 < NB) wave_issue<R, VEC>(buf0, c, (b + 2) * U, CT, kp, lane);
-      else wave_issue<R, VEC>(buf0, cn, 0, CT, kp, lane);
+      walk_consume<L, R, VEC>(buf0, x, b * U, sub, acc);
+      if (eb + S * U >= end) break;
+      if (b + 2 < PER_WIN) walk_issue<L, R>(buf0, c, (b + 2) * U, sub, C16B, kp16, gl);
+      else walk_issue<L, R>(buf0, cn, 0, sub, C16B, kp16, gl);
       __builtin_amdgcn_sched_barrier(0);
-      wave_consume<R, VEC>(buf1, x, (b + 1) * U, acc);
+      walk_consume<L, R, VEC>(buf1, x, (b + 1) * U, sub, acc);
     }
     c = cn;
     x = xn;
   }
-  return group_sum<64>(nrm2);
-}
-
-// One row per wave for kp = 128: each half-wave covers all 128 centres with
-// float4 chunks (lane l & 31 owns centres 4 (l & 31) + q); half 0 takes the
-// even entries of the row, half 1 the odd ones, so every gather instruction
-// fetches two entries' CT rows (1 KB).  Column ids and values come from the
-// 64-entry window by readlane; gathers are double buffered in batches of
-// U entry pairs.  The two partial FMA chains are added at the end, so both
-// halves hold the same sums (a fixed order: deterministic; any order is
-// covered by the error bound of the re-decision).
-template <int U>
-__device__ __forceinline__ void split_issue(float4 (&dst)[U], int cw, int first_pair,
-                                            const float4* __restrict__ CT4, int kp4, int gl,
-                                            bool odd) {
 #pragma unroll
-  for (int u = 0; u < U; ++u) {
-    const int ce = lane_int(cw, 2 * (first_pair + u));
-    const int co = lane_int(cw, 2 * (first_pair + u) + 1);
-    const int cu = odd ? co : ce;
-    dst[u] = CT4[(uint32_t)((uint32_t)cu * (uint32_t)kp4) + gl];
-  }
-}
-
-template <int U>
-__device__ __forceinline__ void split_consume(const float4 (&src)[U], float xw, int first_pair,
-                                              bool odd, float4& acc) {
+  for (int off = L; off < 64; off <<= 1)
 #pragma unroll
-  for (int u = 0; u < U; ++u) {
-    const float xe = lane_float(xw, 2 * (first_pair + u));
-    const float xo = lane_float(xw, 2 * (first_pair + u) + 1);
-    const float xu = odd ? xo : xe;
-    acc.x = fmaf(xu, src[u].x, acc.x);
-    acc.y = fmaf(xu, src[u].y, acc.y);
-    acc.z = fmaf(xu, src[u].z, acc.z);
-    acc.w = fmaf(xu, src[u].w, acc.w);
-  }
-}
-
-__device__ __forceinline__ float row_sims_split(const int32_t* __restrict__ ci,
-                                                const float* __restrict__ v, int64_t beg,
-                                                int64_t end, const float4* __restrict__ CT4,
-                                                int kp4, int lane, float4 (&acc)[1]) {
-  constexpr int U = 8;
-  constexpr int NB = 32 / U;  // batches of U pairs per 64-entry window (even)
-  const int gl = lane & 31;
-  const bool odd = (lane >> 5) != 0;
-  float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
-  float nrm2 = 0.f;
-  float4 buf0[U], buf1[U];
-  int c = 0;
-  float x = 0.f;
-  if (beg + lane < end) {
-    c = ci[beg + lane];
-    x = v[beg + lane];
-  }
-  split_issue<U>(buf0, c, 0, CT4, kp4, gl, odd);
-  for (int64_t w0 = beg; w0 < end; w0 += 64) {
-    int cn = 0;
-    float xn = 0.f;
-    if (w0 + 64 + lane < end) {
-      cn = ci[w0 + 64 + lane];
-      xn = v[w0 + 64 + lane];
+    for (int q = 0; q < R * VEC / 4; ++q) {
+      acc[q].x += __shfl_xor(acc[q].x, off, 64);
+      acc[q].y += __shfl_xor(acc[q].y, off, 64);
+      acc[q].z += __shfl_xor(acc[q].z, off, 64);
+      acc[q].w += __shfl_xor(acc[q].w, off, 64);
     }
-    nrm2 = fmaf(x, x, nrm2);
-#pragma unroll
-    for (int b = 0; b < NB; b += 2) {
-      const int64_t eb = w0 + (int64_t)(2 * U) * b;
-      if (eb >= end) break;
-      split_issue<U>(buf1, c, (b + 1) * U, CT4, kp4, gl, odd);
-      __builtin_amdgcn_sched_barrier(0);  // keep these loads ahead of the FMAs below
-      split_consume<U>(buf0, x, b * U, odd, a);
-      if (eb + 2 * U >= end) break;
-      if (b + 2 < NB) split_issue<U>(buf0, c, (b + 2) * U, CT4, kp4, gl, odd);
-      else split_issue<U>(buf0, cn, 0, CT4, kp4, gl, odd);
-      __builtin_amdgcn_sched_barrier(0);
-      split_consume<U>(buf1, x, (b + 1) * U, odd, a);
-    }
-    c = cn;
-    x = xn;
-  }
-  a.x += __shfl_xor(a.x, 32, 64);
-  a.y += __shfl_xor(a.y, 32, 64);
-  a.z += __shfl_xor(a.z, 32, 64);
-  a.w += __shfl_xor(a.w, 32, 64);
-  acc[0] = a;
   return group_sum<64>(nrm2);
 }
 
@@ -381,17 +323,73 @@ __device__ __forceinline__ bool hamerly_prologue(const AssignArgs& A, int64_t ro
   return skip;
 }
 
-template <int G, int R, int VEC, int MODE, bool SPLIT>
+// FP64 re-decision among a group's candidates: lane gl's candidates are the
+// set bits of cm (bit VEC r + q = centre VEC (gl + G r) + q).  Candidates are
+// taken one at a time, lowest lane and bit first, and the whole group
+// computes each one's canonical FP64 similarity; every lane returns the same
+// winner under the tie order.
+template <int G, int VEC>
+__device__ __forceinline__ void group_redecide(unsigned long long cm, const int32_t* ci,
+                                               const float* v, int64_t beg, int64_t end,
+                                               const double* C64, int64_t d, int gl, int prev,
+                                               double& cb, int& cj) {
+  cb = -INFINITY;
+  cj = INT_MAX;
+  const int base = (int)(threadIdx.x & 63) - gl;  // first lane of the group
+  for (;;) {
+    const unsigned long long wave = __ballot(cm != 0ull);
+    const unsigned long long mine =
+        G == 64 ? wave : (wave >> base) & ((1ull << G) - 1ull);
+    if (!mine) break;
+    const int src = __builtin_ctzll(mine);
+    const int lo = __shfl((int)(unsigned)cm, src, G);
+    const int hi = __shfl((int)(unsigned)(cm >> 32), src, G);
+    const unsigned long long sm = ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+    const int bit = __builtin_ctzll(sm);
+    if (gl == src) cm &= cm - 1ull;
+    const int j = VEC * (src + G * (bit / VEC)) + bit % VEC;
+    const double sv = dot64_group<G>(ci, v, beg, end, C64 + (size_t)j * d, gl);
+    if (better64(sv, j, cb, cj, prev)) {
+      cb = sv;
+      cj = j;
+    }
+  }
+}
+
+// Bound on |fl32 sim - <x, c>| when the centre copy is FP16: every centre
+// value is rounded twice (FP64 -> FP32 -> FP16), relative error at most
+// 2^-11 + 2^-23 in the normal range and absolute 2^-25 (times 1.01) below
+// it; the FP32 FMA chain adds (m+1) 2^-24 of the sum of |x_t c_t|.  With
+// non-negative rows and centres that sum is the similarity itself, so the
+// bound is relative to the computed best value b (solved for the true
+// value); otherwise it is taken at |x| |c|.
+__device__ __forceinline__ double fp16_eps(double b, int m, double nx, double delta_c,
+                                           bool nonneg) {
+  const double chain = (double)(m + 1) * kU32 * 1.01;
+  const double B = (0x1p-11 + 0x1p-23) * (1.0 + chain) + chain;
+  const double A = 0x1p-25 * 1.01 * sqrt((double)m) * nx * (1.0 + chain);
+  if (nonneg) {
+    const double s = (fmax(b, 0.0) + A) / (1.0 - B);
+    return (B * s + A) * 1.01 + 1e-30;
+  }
+  return (B * nx * (1.0 + delta_c) * 1.01 + A) * 1.01 + 1e-30;
+}
+
+// G lanes share the centres of a row: lane gl owns chunks gl + G r (r < R)
+// of VEC centres.  WAVE_ROW: one row per wave, walked by row_walk (VEC = 4
+// reads the FP32 centre copy, VEC = 8 the FP16 one); otherwise several rows
+// per wave (G <= 16, FP32), walked by row_sims.
+template <int G, int R, int VEC, int MODE, bool WAVE_ROW>
 __global__ __launch_bounds__(kBlock) void k_assign_csr(AssignArgs A) {
-  static_assert(VEC == 4 || (VEC == 2 && G == 64), "float2 chunks need the wave layout");
-  static_assert(!SPLIT || (G == 32 && R == 1), "split rows are for kp = 128");
-  constexpr bool WAVE_ROW = SPLIT || G == 64;  // one row per wave
+  static_assert(VEC == 4 || (VEC == 8 && WAVE_ROW), "FP16 centres need the wave layout");
+  constexpr int NACC = R * VEC / 4;
   constexpr int GPB = WAVE_ROW ? kBlock / 64 : kBlock / G;
   const int gl = threadIdx.x & (G - 1);
   const int gib = WAVE_ROW ? (int)(threadIdx.x >> 6) : (int)(threadIdx.x / G);
-  // the lane that writes per-row results and counts (split rows: both
-  // halves hold the same values; the lower half writes)
+  // the lane that writes per-row results and counts (one row per wave: every
+  // sub-wave holds the same values; lane 0 writes)
   const bool leader = WAVE_ROW ? (threadIdx.x & 63) == 0 : gl == 0;
+  const bool lead_sub = WAVE_ROW ? (int)(threadIdx.x & 63) < G : true;
   __shared__ unsigned long long sh[6];
   if (threadIdx.x < 6) sh[threadIdx.x] = 0;
   __syncthreads();
@@ -401,29 +399,72 @@ __global__ __launch_bounds__(kBlock) void k_assign_csr(AssignArgs A) {
   const int kp4 = A.kp >> 2;
   const int k = A.k;
 
-  for (int64_t row = (int64_t)blockIdx.x * GPB + gib; row < A.n_rows;
-       row += (int64_t)gridDim.x * GPB) {
-    int64_t beg = A.rp[row], end = A.rp[row + 1];
-    if constexpr (WAVE_ROW) {  // one row per wave: keep the loop bounds scalar
-      beg = ((int64_t)__builtin_amdgcn_readfirstlane((int)(beg >> 32)) << 32) |
-            (uint32_t)__builtin_amdgcn_readfirstlane((int)beg);
-      end = ((int64_t)__builtin_amdgcn_readfirstlane((int)(end >> 32)) << 32) |
-            (uint32_t)__builtin_amdgcn_readfirstlane((int)end);
+  // one row per wave: the bounds and the first 64 entries of the wave's next
+  // row are loaded while the current row is processed, so a row's walk
+  // starts without waiting for them
+  const int64_t rstride = (int64_t)gridDim.x * GPB;
+  const int wl = threadIdx.x & 63;
+  int64_t nbeg = 0, nend = 0;
+  int wc = 0;
+  float wx = 0.f;
+  auto uniform64 = [](int64_t x) -> int64_t {
+    return ((int64_t)__builtin_amdgcn_readfirstlane((int)(x >> 32)) << 32) |
+           (uint32_t)__builtin_amdgcn_readfirstlane((int)x);
+  };
+  auto next_window = [&]() {
+    wc = 0;
+    wx = 0.f;
+    if (nbeg + wl < nend) {
+      wc = A.ci[nbeg + wl];
+      wx = A.v[nbeg + wl];
+    }
+  };
+  if constexpr (WAVE_ROW) {
+    const int64_t r0 = (int64_t)blockIdx.x * GPB + gib;
+    if (r0 < A.n_rows) {
+      nbeg = uniform64(A.rp[r0]);
+      nend = uniform64(A.rp[r0 + 1]);
+      next_window();
+    }
+  }
+
+  for (int64_t row = (int64_t)blockIdx.x * GPB + gib; row < A.n_rows; row += rstride) {
+    int64_t beg, end;
+    int c0 = 0;
+    float x0 = 0.f;
+    if constexpr (WAVE_ROW) {
+      beg = nbeg;
+      end = nend;
+      c0 = wc;
+      x0 = wx;
+      nbeg = nend = 0;
+      if (row + rstride < A.n_rows) {
+        nbeg = uniform64(A.rp[row + rstride]);
+        nend = uniform64(A.rp[row + rstride + 1]);
+      }
+    } else {
+      beg = A.rp[row];
+      end = A.rp[row + 1];
     }
     const int m = (int)(end - beg);
     const int prev = A.read_prev ? A.a[row] : -1;
     if (MODE == kModeHamerly) {
-      if (hamerly_prologue<G>(A, row, prev, beg, end, gl, leader, my_tight, my_saved)) continue;
+      if (hamerly_prologue<G>(A, row, prev, beg, end, gl, leader, my_tight, my_saved)) {
+        if constexpr (WAVE_ROW) next_window();
+        continue;
+      }
     }
 
-    float4 acc[R];
+    float4 acc[NACC];
     float nrm2;
-    if constexpr (SPLIT)
-      nrm2 = row_sims_split(A.ci, A.v, beg, end, CT4, kp4, threadIdx.x & 63, acc);
-    else if constexpr (G == 64)
-      nrm2 = row_sims_wave<R, VEC>(A.ci, A.v, beg, end, A.CT, A.kp, gl, acc);
-    else
+    if constexpr (WAVE_ROW) {
+      nrm2 = row_walk<G, R, VEC>(A.ci, A.v, beg, end, c0, x0,
+                                 VEC == 8 ? (const void*)A.CT16 : (const void*)A.CT, A.kp, wl,
+                                 acc);
+      next_window();
+    } else {
       nrm2 = row_sims<G, R, false>(A.ci, A.v, beg, end, CT4, kp4, gl, ~0u, acc);
+    }
 
     float b = -INFINITY, s2 = -INFINITY;
     int bj = INT_MAX;
@@ -433,7 +474,7 @@ __global__ __launch_bounds__(kBlock) void k_assign_csr(AssignArgs A) {
       for (int q = 0; q < VEC; ++q) {
         const int j = VEC * (gl + G * r) + q;
         if (j < k) {
-          const float sv = f4get(acc[r], q);
+          const float sv = f4get(acc[(r * VEC + q) >> 2], q & 3);
           if (better32(sv, j, b, bj, prev)) {
             s2 = fmaxf(s2, b);
             b = sv;
@@ -447,10 +488,11 @@ __global__ __launch_bounds__(kBlock) void k_assign_csr(AssignArgs A) {
     group_top2<G>(b, bj, s2, prev);
 
     // rigorous bound on |fl32 sim - <x, c>| for any summation order: (m+1)
-    // roundings of the FMA chain plus the float rounding of the centre,
+    // roundings of the FMA chain plus the rounding of the centre copy,
     // scaled by |x| |c|
     const double nx = sqrt((double)nrm2) * 1.01 + 1e-30;
-    const double eps = (double)(m + 3) * kU32 * nx;
+    const double eps = VEC == 8 ? fp16_eps((double)b, m, nx, A.delta_c, *A.negflag == 0)
+                                : (double)(m + 3) * kU32 * nx;
 
     bool rechecked = false;
     double best64 = 0.0;
@@ -465,21 +507,12 @@ __global__ __launch_bounds__(kBlock) void k_assign_csr(AssignArgs A) {
 #pragma unroll
         for (int q = 0; q < VEC; ++q) {
           const int j = VEC * (gl + G * r) + q;
-          if (j < k && (double)f4get(acc[r], q) >= thr) cm |= 1ull << (4 * r + q);
+          if (j < k && (double)f4get(acc[(r * VEC + q) >> 2], q & 3) >= thr)
+            cm |= 1ull << (VEC * r + q);
         }
-      double cb = -INFINITY;
-      int cj = INT_MAX;
-      while (cm) {
-        const int bit = __builtin_ctzll(cm);
-        cm &= cm - 1ull;
-        const int j = VEC * (gl + G * (bit >> 2)) + (bit & 3);
-        const double sv = dot64(A.ci, A.v, beg, end, A.C64 + (size_t)j * A.d);
-        if (better64(sv, j, cb, cj, prev)) {
-          cb = sv;
-          cj = j;
-        }
-      }
-      group_best64<G>(cb, cj, prev);
+      double cb;
+      int cj;
+      group_redecide<G, VEC>(cm, A.ci, A.v, beg, end, A.C64, A.d, gl, prev, cb, cj);
       abest = cj;
       best64 = cb;
       rechecked = true;
@@ -510,20 +543,20 @@ __global__ __launch_bounds__(kBlock) void k_assign_csr(AssignArgs A) {
           A.u[row] = __double2float_ru(fmin(hi, 1.0));
         }
       }
-      if (MODE == kModeFitElkanInit && (!SPLIT || (threadIdx.x & 32) == 0)) {
-        float* uer = A.ue + (size_t)row * A.kp;
+      if (MODE == kModeFitElkanInit && lead_sub) {
+        float4* uer4 = reinterpret_cast<float4*>(A.ue + (size_t)row * A.kp);
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
+        for (int q4 = 0; q4 < NACC; ++q4) {
+          const int r = (4 * q4) / VEC, q0 = (4 * q4) % VEC;
           float4 o;
 #pragma unroll
-          for (int q = 0; q < VEC; ++q) {
-            const int j = VEC * (gl + G * r) + q;
-            const float val = (j < k) ? __double2float_ru(fmin((double)f4get(acc[r], q) + rho32, 1.0))
-                                      : 1.0f;
+          for (int q = 0; q < 4; ++q) {
+            const int j = VEC * (gl + G * r) + q0 + q;
+            const float val =
+                (j < k) ? __double2float_ru(fmin((double)f4get(acc[q4], q) + rho32, 1.0)) : 1.0f;
             f4set(o, q, val);
           }
-          if constexpr (VEC == 4) reinterpret_cast<float4*>(uer)[gl + G * r] = o;
-          else reinterpret_cast<float2*>(uer)[gl + G * r] = make_float2(o.x, o.y);
+          uer4[(VEC * (gl + G * r) + q0) / 4] = o;
         }
       }
     }
@@ -738,17 +771,7 @@ __global__ __launch_bounds__(kBlock) void k_elkan(ElkanArgs A) {
               const int bit = 4 * r + q;
               if (((comp >> bit) & 1ull) && (double)f4get(acc[r], q) >= thr) cm |= 1ull << bit;
             }
-          while (cm) {
-            const int bit = __builtin_ctzll(cm);
-            cm &= cm - 1ull;
-            const int j = 4 * (gl + G * (bit >> 2)) + (bit & 3);
-            const double sv = dot64(A.ci, A.v, beg, end, A.C64 + (size_t)j * A.d);
-            if (better64(sv, j, cb, cj, prev)) {
-              cb = sv;
-              cj = j;
-            }
-          }
-          group_best64<G>(cb, cj, prev);
+          group_redecide<G, 4>(cm, A.ci, A.v, beg, end, A.C64, A.d, gl, prev, cb, cj);
           abest = cj;
           rechecked = true;
           lo = cb - rho64;
@@ -835,30 +858,46 @@ template <int MODE>
 hipError_t launch_assign_mode(const AssignArgs& A, hipStream_t s) {
   const Geometry g = pick_geometry(A.k);
   if (g.G == 0 || g.kp != A.kp) return hipErrorInvalidValue;
-  const int gpb = kBlock / (g.G == 32 ? 64 : g.G);  // rows per block
+  const bool half = A.CT16 != nullptr && A.kp >= 128;
+  const int gpb = (half || g.G >= 32) ? kBlock / 64 : kBlock / g.G;  // rows per block
   int64_t blocks = (A.n_rows + gpb - 1) / gpb;
   if (blocks > kMaxGridBlocks) blocks = kMaxGridBlocks;
   if (blocks < 1) blocks = 1;
   const dim3 grid((unsigned)blocks), block(kBlock);
-#define SKM_CASE(GG, RR, SP)                                                        \
-  case GG * 100 + RR:                                                               \
-    hipLaunchKernelGGL((k_assign_csr<GG, RR, 4, MODE, SP>), grid, block, 0, s, A); \
+#define SKM_CASE(KP, GG, RR, VV, WW)                                                  \
+  case KP:                                                                            \
+    hipLaunchKernelGGL((k_assign_csr<GG, RR, VV, MODE, WW>), grid, block, 0, s, A); \
     break;
-  // k <= 64: several rows per wave (groups of 4..16 lanes); k in (64, 128]:
-  // one row per wave, half-waves on alternating entries; larger k: one row
-  // per wave, float4 chunks per lane
-  switch (g.G * 100 + g.R) {
-    SKM_CASE(4, 1, false)
-    SKM_CASE(8, 1, false)
-    SKM_CASE(16, 1, false)
-    SKM_CASE(32, 1, true)
-    SKM_CASE(64, 1, false)
-    SKM_CASE(64, 2, false)
-    SKM_CASE(64, 4, false)
-    SKM_CASE(64, 8, false)
-    SKM_CASE(64, 16, false)
-    default:
-      return hipErrorInvalidValue;
+  if (half) {
+    // FP16 centre copy, 8 centres per 16-byte chunk: 16, 32 or 64 lanes cover
+    // a centre row, so 4, 2 or 1 entries per gather instruction
+    switch (A.kp) {
+      SKM_CASE(128, 16, 1, 8, true)
+      SKM_CASE(256, 32, 1, 8, true)
+      SKM_CASE(512, 64, 1, 8, true)
+      SKM_CASE(1024, 64, 2, 8, true)
+      SKM_CASE(2048, 64, 4, 8, true)
+      SKM_CASE(4096, 64, 8, 8, true)
+      default:
+        return hipErrorInvalidValue;
+    }
+  } else {
+    // k <= 64: several rows per wave (groups of 4..16 lanes); k in (64, 128]:
+    // one row per wave, half-waves on alternating entries; larger k: one row
+    // per wave, R float4 chunks per lane
+    switch (A.kp) {
+      SKM_CASE(16, 4, 1, 4, false)
+      SKM_CASE(32, 8, 1, 4, false)
+      SKM_CASE(64, 16, 1, 4, false)
+      SKM_CASE(128, 32, 1, 4, true)
+      SKM_CASE(256, 64, 1, 4, true)
+      SKM_CASE(512, 64, 2, 4, true)
+      SKM_CASE(1024, 64, 4, 4, true)
+      SKM_CASE(2048, 64, 8, 4, true)
+      SKM_CASE(4096, 64, 16, 4, true)
+      default:
+        return hipErrorInvalidValue;
+    }
   }
 #undef SKM_CASE
   return hipGetLastError();

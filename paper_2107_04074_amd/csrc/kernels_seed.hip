@@ -37,7 +37,7 @@ __global__ __launch_bounds__(kBlock) void k_kpp_update(
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   double wi = 0.0;
   if (i < n) {
-    const double s = dot64(ci, v, rp[i], rp[i + 1], c);
+    const double s = dot64_serial(ci, v, rp[i], rp[i + 1], c);
     double b = best[i], s2 = second[i];
     if (s > b) {
       s2 = b;

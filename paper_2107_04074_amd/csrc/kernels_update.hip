@@ -22,6 +22,8 @@
 #include <float.h>
 #include <limits.h>
 
+#include <hip/hip_fp16.h>
+
 #include "skm_device.h"
 #include "skm_internal.h"
 
@@ -94,7 +96,8 @@ __global__ __launch_bounds__(kBlock) void k_init_centres(const float* __restrict
 __global__ __launch_bounds__(kBlock) void k_transpose(const double* __restrict__ C64, int32_t k,
                                                       int64_t d, int32_t kp,
                                                       const int32_t* __restrict__ dirty,
-                                                      float* __restrict__ CT) {
+                                                      float* __restrict__ CT,
+                                                      __half* __restrict__ CT16) {
   __shared__ float tile[64][65];
   __shared__ int any;
   const int64_t t0 = (int64_t)blockIdx.x * 64;
@@ -116,8 +119,23 @@ __global__ __launch_bounds__(kBlock) void k_transpose(const double* __restrict__
   for (int tt = ty; tt < 64; tt += 4) {
     const int64_t t = t0 + tt;
     const int j = j0 + tx;
-    if (t < d && j < k) CT[(size_t)t * kp + j] = tile[tx][tt];
+    if (t < d && j < k) {
+      CT[(size_t)t * kp + j] = tile[tx][tt];
+      if (CT16) CT16[(size_t)t * kp + j] = __float2half(tile[tx][tt]);
+    }
   }
+}
+
+// Sets *flag when a stored value or an initial-centre value is negative
+// (plain stores of 1: every writer writes the same value).
+__global__ void k_neg_scan(const float* __restrict__ v, int64_t nnz,
+                           const float* __restrict__ init, int64_t ninit,
+                           int32_t* __restrict__ flag) {
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  bool neg = false;
+  for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < nnz + ninit; e += stride)
+    neg |= (e < nnz ? v[e] : init[e - nnz]) < 0.f;
+  if (neg) *flag = 1;
 }
 
 // Scans the assignment for rows that moved since the last centre step and
@@ -538,9 +556,20 @@ hipError_t launch_init_centres(const float* init, int32_t k, int64_t d, int norm
 }
 
 hipError_t launch_transpose(const double* C64, int32_t k, int64_t d, int32_t kp,
-                            const int32_t* dirty, float* CT, hipStream_t s) {
+                            const int32_t* dirty, float* CT, hipStream_t s, void* CT16) {
   const dim3 grid((unsigned)((d + 63) / 64), (unsigned)((k + 63) / 64));
-  hipLaunchKernelGGL(k_transpose, grid, dim3(kBlock), 0, s, C64, k, d, kp, dirty, CT);
+  hipLaunchKernelGGL(k_transpose, grid, dim3(kBlock), 0, s, C64, k, d, kp, dirty, CT,
+                     static_cast<__half*>(CT16));
+  return hipGetLastError();
+}
+
+hipError_t launch_neg_scan(const float* v, int64_t nnz, const float* init, int64_t ninit,
+                           int32_t* flag, hipStream_t s) {
+  int64_t blocks = (nnz + ninit + kBlock - 1) / kBlock;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_neg_scan, dim3((unsigned)blocks), dim3(kBlock), 0, s, v, nnz, init, ninit,
+                     flag);
   return hipGetLastError();
 }
 

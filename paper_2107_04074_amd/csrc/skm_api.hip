@@ -61,9 +61,10 @@ struct Plan {
   int nchunk = 1, nslice = 1;
   int64_t slice_len = 0;
   // byte offsets into the workspace
-  size_t CT = 0, C64 = 0, S = 0, l = 0, u = 0, ue = 0, eta = 0, a_old = 0, norm64 = 0,
-         part = 0, part_sq = 0, pc = 0, ps = 0, dirty = 0, mm = 0, G = 0, gmax = 0, gpart = 0,
-         cnt = 0, per = 0, maxeta = 0, initnorm = 0, total = 0;
+  bool half = false;  // FP16 centre copy for the row walk
+  size_t CT = 0, CT16 = 0, negflag = 0, C64 = 0, S = 0, l = 0, u = 0, ue = 0, eta = 0,
+         a_old = 0, norm64 = 0, part = 0, part_sq = 0, pc = 0, ps = 0, dirty = 0, mm = 0, G = 0,
+         gmax = 0, gpart = 0, cnt = 0, per = 0, maxeta = 0, initnorm = 0, total = 0;
 };
 
 int check_matrix(const skm_matrix* X) {
@@ -88,9 +89,12 @@ int check_matrix(const skm_matrix* X) {
   return fail(SKM_ERR_INVALID_ARG, "unknown matrix format %d", (int)X->fmt);
 }
 
-int make_plan(const skm_matrix* X, int32_t k, int32_t variant, Plan* P) {
+int make_plan(const skm_matrix* X, int32_t k, int32_t variant, int32_t precision, Plan* P) {
   int rc = check_matrix(X);
   if (rc != SKM_OK) return rc;
+  if (precision != 0 && precision != 2)
+    return fail(SKM_ERR_UNSUPPORTED, "CSR input supports precision 0 (FP32) or 2 (FP16 centre "
+                "copy), got %d", (int)precision);
   if (k < 1 || (int64_t)k > X->n) return fail(SKM_ERR_INVALID_ARG, "need 1 <= k <= n");
   if (variant < SKM_LLOYD || variant > SKM_SIMP_HAMERLY)
     return fail(SKM_ERR_INVALID_ARG, "unknown variant %d", (int)variant);
@@ -115,6 +119,10 @@ int make_plan(const skm_matrix* X, int32_t k, int32_t variant, Plan* P) {
   };
   const size_t n = (size_t)X->n, d = (size_t)X->d, kk = (size_t)k;
   P->CT = take(d * (size_t)g.kp * sizeof(float));
+  // the FP16 copy pays where the row walk is gather-bound (kp >= 128)
+  P->half = precision == 2 && g.kp >= 128;
+  if (P->half) P->CT16 = take(d * (size_t)g.kp * 2);
+  P->negflag = take(sizeof(int32_t));
   P->C64 = take(kk * d * sizeof(double));
   P->S = take(kk * d * sizeof(long long));
   P->eta = take(n * sizeof(float));
@@ -684,7 +692,7 @@ size_t skm_workspace_size(const skm_matrix* X, int32_t k, int32_t variant,
     return D.total;
   }
   Plan P;
-  if (make_plan(X, k, variant, &P) != SKM_OK) return 0;
+  if (make_plan(X, k, variant, opt ? opt->precision : 0, &P) != SKM_OK) return 0;
   return P.total;
 }
 
@@ -784,10 +792,8 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
                      assign_out, centers_out, centers64_out, stats, static_cast<hipStream_t>(stream));
   }
   Plan P;
-  int rc = make_plan(X, k, variant, &P);
+  int rc = make_plan(X, k, variant, o.precision, &P);
   if (rc != SKM_OK) return rc;
-  if (o.precision != 0)
-    return fail(SKM_ERR_UNSUPPORTED, "bf16 precision needs dense input");
   if (workspace && workspace_bytes < P.total)
     return fail(SKM_ERR_OUT_OF_MEMORY, "workspace has %zu bytes, %zu needed", workspace_bytes,
                 P.total);
@@ -813,6 +819,8 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
   const double fx_inv = 1.0 / fx;
 
   float* CT = at<float>(ws, P.CT);
+  void* CT16 = P.half ? at<char>(ws, P.CT16) : nullptr;
+  int32_t* negflag = at<int32_t>(ws, P.negflag);
   double* C64 = at<double>(ws, P.C64);
   long long* S = at<long long>(ws, P.S);
   float* eta = at<float>(ws, P.eta);
@@ -857,7 +865,12 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
     SKM_HIP(hipMemsetAsync(maxeta, 0, kCounterSlots * sizeof(float), s));
     SKM_HIP(launch_row_eta(X->row_ptr, X->val, n, eta, maxeta, s));
     SKM_HIP(launch_init_centres(init_centers, k, d, 1, C64, initnorm, s));
-    SKM_HIP(launch_transpose(C64, k, d, P.kp, nullptr, CT, s));
+    SKM_HIP(hipMemsetAsync(negflag, 0, sizeof(int32_t), s));
+    if (P.half) {
+      SKM_HIP(hipMemsetAsync(CT16, 0, (size_t)d * P.kp * 2, s));
+      SKM_HIP(launch_neg_scan(X->val, X->nnz, init_centers, (int64_t)k * d, negflag, s));
+    }
+    SKM_HIP(launch_transpose(C64, k, d, P.kp, nullptr, CT, s, CT16));
     if (o.validate >= 1) {
       double* hn = new (std::nothrow) double[k];
       float hslots[kCounterSlots];
@@ -916,6 +929,8 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
         A.ci = X->col_idx;
         A.v = X->val;
         A.CT = CT;
+        A.CT16 = CT16;
+        A.negflag = negflag;
         A.C64 = C64;
         A.d = d;
         A.k = k;
@@ -1003,7 +1018,7 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
       SKM_HIP(launch_normalize_move(S, k, d, fx_inv, dirty, part_sq, C64, part, P.nchunk, s));
       SKM_HIP(launch_centre_finalize(k, d, dirty, norm64, part_sq, part, P.nchunk, delta_c, pc,
                                      ps, mm, per, s));
-      SKM_HIP(launch_transpose(C64, k, d, P.kp, dirty, CT, s));
+      SKM_HIP(launch_transpose(C64, k, d, P.kp, dirty, CT, s, CT16));
       if (P.gram) {
         if (gram_exact_step(gram_updates, gram_since_exact, changed, n)) {
           // after carried steps every tile's partials are stale

@@ -1,5 +1,5 @@
 // Device helpers shared by every kernel file of libskm: the tie order of
-// the argmax, the canonical FP64 dot product used for every re-decision,
+// the argmax, the canonical FP64 similarity used for every re-decision,
 // and the guarded bound updates of Section 4 (Eq. (6), (7)) and the
 // centre-centre threshold of Section 5.2.
 #pragma once
@@ -26,15 +26,52 @@ __device__ __forceinline__ bool better64(double s, int j, double t, int tj, int 
   return j < tj;
 }
 
-// FP64 dot product of a row with one FP64 centre: a single sequential FMA
-// chain in storage order.  Every re-decision uses exactly this routine so
-// that all kernels reach bit-identical FP64 values.
-__device__ __forceinline__ double dot64(const int32_t* __restrict__ ci,
-                                        const float* __restrict__ v, int64_t beg,
-                                        int64_t end, const double* __restrict__ c) {
-  double s = 0.0;
-  for (int64_t e = beg; e < end; ++e) s = fma((double)v[e], c[ci[e]], s);
-  return s;
+// Canonical FP64 similarity of a CSR row with one FP64 centre.  Entry e of
+// the row (position p = e - beg) goes into partial sum p mod 64; every
+// partial is a sequential FMA chain in storage order and the 64 partials
+// are added by a balanced pairwise tree (pairs (2i, 2i+1), then pairs of
+// pairs, ...).  Every FP64 re-decision uses exactly this value, computed
+// either by a group of G lanes together (dot64_group: lane gl holds the
+// partials gl + G r) or by one lane (dot64_serial: a pairwise stack), and
+// both give bit-identical results (each tree node is one FP64 addition of
+// the same two operands; addition is commutative).
+template <int G>
+__device__ __forceinline__ double dot64_group(const int32_t* __restrict__ ci,
+                                              const float* __restrict__ v, int64_t beg,
+                                              int64_t end, const double* __restrict__ c, int gl) {
+  constexpr int P = 64 / G;
+  double part[P];
+#pragma unroll
+  for (int r = 0; r < P; ++r) {
+    double s = 0.0;
+    for (int64_t e = beg + gl + G * r; e < end; e += 64) s = fma((double)v[e], c[ci[e]], s);
+    part[r] = s;
+  }
+#pragma unroll
+  for (int r = 0; r < P; ++r)
+#pragma unroll
+    for (int off = 1; off < G; off <<= 1) part[r] += __shfl_xor(part[r], off, G);
+#pragma unroll
+  for (int w = 1; w < P; w <<= 1)
+#pragma unroll
+    for (int r = 0; r < P; r += 2 * w) part[r] += part[r + w];
+  return part[0];
+}
+
+__device__ __forceinline__ double dot64_serial(const int32_t* __restrict__ ci,
+                                               const float* __restrict__ v, int64_t beg,
+                                               int64_t end, const double* __restrict__ c) {
+  double st[7];
+#pragma unroll
+  for (int p = 0; p < 64; ++p) {
+    double s = 0.0;
+    for (int64_t e = beg + p; e < end; e += 64) s = fma((double)v[e], c[ci[e]], s);
+    int lev = 0;
+#pragma unroll
+    for (int q = p; q & 1; q >>= 1) s = st[lev++] + s;
+    st[lev] = s;
+  }
+  return st[6];
 }
 
 // Guarded Eq. (6): cos(theta_l + theta_p), or -1 once the sum reaches pi.

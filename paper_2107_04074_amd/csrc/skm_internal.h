@@ -70,6 +70,8 @@ struct AssignArgs {
   const int32_t* ci;
   const float* v;
   const float* CT;      // d x kp float, centre-minor
+  const void* CT16;     // d x kp FP16 copy (nullable): the row walk reads it
+  const int32_t* negflag;  // nonzero if any row or initial centre has a negative value
   const double* C64;    // k x d double, row-major
   int64_t d;
   int32_t k, kp;
@@ -240,7 +242,10 @@ hipError_t launch_row_eta(const int64_t* rp, const float* v, int64_t n, float* e
 hipError_t launch_init_centres(const float* init, int32_t k, int64_t d, int normalize,
                                double* C64, double* init_norm, hipStream_t s);
 hipError_t launch_transpose(const double* C64, int32_t k, int64_t d, int32_t kp,
-                            const int32_t* dirty, float* CT, hipStream_t s);
+                            const int32_t* dirty, float* CT, hipStream_t s, void* CT16 = nullptr);
+// Sets *flag (not cleared here) if any of v[0..nnz) or init[0..ninit) is negative.
+hipError_t launch_neg_scan(const float* v, int64_t nnz, const float* init, int64_t ninit,
+                           int32_t* flag, hipStream_t s);
 hipError_t launch_update_scan(const int64_t* rp, const int32_t* ci, const float* v,
                               const int32_t* a, int32_t* a_old, int64_t n, int64_t d,
                               double fx_scale, long long* S, int32_t* dirty, hipStream_t s);

@@ -336,3 +336,45 @@ def test_c4_full_size_bf16_subsample(skm, torch_cuda):
     say("c4 subsample: %d rows, band %d, mismatches %d, all-row mismatches %d" % (
         len(sub), int((~clear).sum()), mism, int((out["lloyd"][0][sub] != ref).sum())))
     assert mism == 0
+
+
+# ------------------------------------------------- FP16 centre copy (CSR)
+
+@pytest.mark.parametrize("k", [100, 200, 300, 700, 1500])
+def test_fp16_centre_copy_matches_fp32(skm, torch_cuda, k):
+    """precision = 2 walks the rows against an FP16 copy of the centres with
+    a wider (value-relative on non-negative data) error band; the fit must
+    be identical to the FP32 one, and equal to the oracle's."""
+    torch = torch_cuda
+    X = datagen.sparse_tfidf(6000, 8000, 40.0, 77 + k)
+    C0 = datagen.init_centers_csr(X, datagen.init_rows(X.n, k, 5 + k))
+    Xd = skm.DeviceCSR.from_host(X)
+    ref = None
+    for v in ["lloyd", "hamerly", "simp_hamerly"]:
+        say("case fp16 centre copy k=%d %s" % (k, v))
+        a32, C32, _, st32 = run_fit(skm, torch, Xd, C0, k, v, 30)
+        a16, C16, _, st16 = run_fit(skm, torch, Xd, C0, k, v, 30, precision=2)
+        assert np.array_equal(a32, a16) and np.array_equal(C32, C16)
+        assert st32.iterations == st16.iterations
+        say("  iterations %d rechecks fp32 %d fp16 %d" % (st16.iterations, st32.rechecks,
+                                                          st16.rechecks))
+        if ref is None:
+            ref = oracle.fit(X, C0, "lloyd", 30)
+        assert st16.iterations == ref.iterations and np.array_equal(a16, ref.a)
+
+
+def test_fp16_centre_copy_mixed_signs(skm, torch_cuda):
+    """Rows with negative entries take the absolute error bound."""
+    torch = torch_cuda
+    rng = np.random.default_rng(31)
+    D = rng.normal(size=(3000, 48))
+    D /= np.linalg.norm(D, axis=1, keepdims=True)
+    X = dense_csr(D.astype(np.float32))
+    k = 150
+    C0 = datagen.init_centers_csr(X, datagen.init_rows(X.n, k, 9))
+    Xd = skm.DeviceCSR.from_host(X)
+    ref = oracle.fit(X, C0, "lloyd", 25)
+    for v in ["lloyd", "hamerly"]:
+        say("case fp16 mixed signs %s" % v)
+        a16, C16, _, st16 = run_fit(skm, torch, Xd, C0, k, v, 25, precision=2)
+        assert st16.iterations == ref.iterations and np.array_equal(a16, ref.a)
