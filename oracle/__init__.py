@@ -73,6 +73,8 @@ def _load():
         lib.oracle_fit.restype = i32
         lib.oracle_fit.argtypes = [i64, i64, p, p, p, i32, p, i32, i32, i32, i32, p, p,
                                    p, p, p, p, p, p, p, p]
+        lib.oracle_afkmc2.restype = None
+        lib.oracle_afkmc2.argtypes = [i64, i64, p, p, p, i32, i32, dbl, p, p]
         lib.oracle_kmeanspp.restype = None
         lib.oracle_kmeanspp.argtypes = [i64, i64, p, p, p, i32, dbl, p, p, p, p, p]
         _lib = lib
@@ -121,6 +123,20 @@ def kmeanspp(X, k: int, alpha: float, u: np.ndarray):
     lib.oracle_kmeanspp(X.n, X.d, _p(rp), _p(ci), _p(v), k, float(alpha), _p(u), _p(chosen),
                         _p(a), _p(s1), _p(s2))
     return chosen, a, s1, s2
+
+
+def afkmc2(X, k: int, m: int, alpha: float, u: np.ndarray) -> np.ndarray:
+    """AFK-MC2 seeding (spherical form) with chain length m and the given
+    uniforms: u[0], then per centre t >= 1 the m proposal draws and the
+    m - 1 acceptance draws (1 + (k - 1)(2m - 1) values in [0, 1)).
+    Returns the chosen row indices."""
+    lib = _load()
+    rp, ci, v = _csr_args(X)
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    assert u.shape == (1 + (k - 1) * (2 * m - 1),)
+    chosen = np.empty(k, dtype=np.int32)
+    lib.oracle_afkmc2(X.n, X.d, _p(rp), _p(ci), _p(v), k, m, float(alpha), _p(u), _p(chosen))
+    return chosen
 
 
 def sims(X, C: np.ndarray, rows: np.ndarray) -> np.ndarray:

@@ -260,6 +260,82 @@ void oracle_kmeanspp(int64_t n, int64_t d, const int64_t *rp, const int32_t *ci,
   free(taken);
 }
 
+/* AFK-MC2 seeding in its spherical form (Section 6 cites it with the
+ * dissimilarity alpha - <x, c>): centre 0 is row floor(u[0] n) and fixes the
+ * proposal distribution q(x) = w(x) / (2 W) + 1 / (2 n), w(x) = max(0,
+ * alpha - <x, c0>), W = sum w (q = 1/n when W = 0).  Centre t >= 1 comes
+ * from a Markov chain of length m over proposals y_1 .. y_m drawn from q by
+ * inverse transform sampling (the first row whose running q sum exceeds the
+ * uniform; the last row if rounding leaves it unreached): the chain starts
+ * at y_1 and moves to y_j when d(y_j) q(x) > u d(x) q(y_j), d(.) =
+ * max(0, alpha - max_c <., c>) over the centres chosen so far, u the j-th
+ * acceptance uniform (SEED-MC reading: the multiplied form decides the
+ * 0/0 case as "stay").  Uniforms: u[0] for centre 0, then per centre t the
+ * m proposal draws followed by the m - 1 acceptance draws.  Centres are the
+ * chosen rows rescaled to unit length (INIT).  Rows may be chosen twice (the
+ * chain does not exclude centres); the fit then keeps an empty cluster. */
+static void unit_row_centre(const csr_t *X, int64_t p, double *c) {
+  memset(c, 0, sizeof(double) * (size_t)X->d);
+  double ss = 0.0;
+  for (int64_t e = X->rp[p]; e < X->rp[p + 1]; ++e) {
+    c[X->ci[e]] = (double)X->v[e];
+    ss += (double)X->v[e] * (double)X->v[e];
+  }
+  if (ss > 0.0) {
+    const double nrm = sqrt(ss);
+    for (int64_t e = X->rp[p]; e < X->rp[p + 1]; ++e) c[X->ci[e]] /= nrm;
+  }
+}
+
+void oracle_afkmc2(int64_t n, int64_t d, const int64_t *rp, const int32_t *ci,
+                   const float *v, int32_t k, int32_t m, double alpha, const double *u,
+                   int32_t *chosen) {
+  csr_t X = {n, d, rp, ci, v};
+  double *C = (double *)malloc(sizeof(double) * (size_t)k * (size_t)d);
+  double *q = (double *)malloc(sizeof(double) * (size_t)n);
+  int64_t p = (int64_t)floor(u[0] * (double)n);
+  if (p > n - 1) p = n - 1;
+  chosen[0] = (int32_t)p;
+  unit_row_centre(&X, p, C);
+  double W = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    const double w = alpha - sim(&X, i, C);
+    q[i] = w > 0.0 ? w : 0.0;
+    W += q[i];
+  }
+  for (int64_t i = 0; i < n; ++i)
+    q[i] = W > 0.0 ? 0.5 * q[i] / W + 0.5 / (double)n : 1.0 / (double)n;
+  const double *ut = u + 1;
+  for (int32_t t = 1; t < k; ++t, ut += 2 * m - 1) {
+    int64_t x = -1;
+    double dx = 0.0;
+    for (int32_t j = 0; j < m; ++j) {
+      /* proposal j by inverse transform on q */
+      double run = 0.0;
+      int64_t y = n - 1;
+      for (int64_t i = 0; i < n; ++i) {
+        run += q[i];
+        if (run > ut[j]) { y = i; break; }
+      }
+      double best = -INFINITY;
+      for (int32_t c = 0; c < t; ++c) {
+        const double s = sim(&X, y, C + (size_t)c * (size_t)d);
+        if (s > best) best = s;
+      }
+      double dy = alpha - best;
+      if (!(dy > 0.0)) dy = 0.0;
+      if (j == 0 || dy * q[x] > ut[m + j - 1] * dx * q[y]) {
+        x = y;
+        dx = dy;
+      }
+    }
+    chosen[t] = (int32_t)x;
+    unit_row_centre(&X, x, C + (size_t)t * (size_t)d);
+  }
+  free(C);
+  free(q);
+}
+
 /* -------------------------------------------------------------------- */
 /* bound updates (Section 4 and 5.3), exported for the tests             */
 /* -------------------------------------------------------------------- */

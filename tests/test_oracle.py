@@ -409,3 +409,45 @@ def test_kmeanspp_cache_equals_assignment_step():
         a2, t1, t2 = oracle.assign(X, C)
         assert np.array_equal(a, a2)
         assert np.max(np.abs(s1 - t1)) < 1e-13 and np.max(np.abs(s2 - t2)) < 1e-13
+
+
+def test_afkmc2_by_hand():
+    """Four exact points at 0, 90, 180, 270 degrees, alpha = 1, u0 = 0.1:
+    centre 0 is row 0, weights 1 - <x, c0> = (0, 1, 2, 1), W = 4, so
+    q = w / 8 + 1 / 8 = (0.125, 0.25, 0.375, 0.25), running sums 0.125,
+    0.375, 0.75, 1.  Chain of two proposals (draws up0, up1; acceptance
+    draw ua): y2 replaces y1 when d(y2) q(y1) > ua d(y1) q(y2)."""
+    X = _circle([0, 90, 180, 270])
+    # y1 = row 1 (0.2), y2 = row 2 (0.5): 2 * 0.25 > ua * 1 * 0.375 always
+    assert list(oracle.afkmc2(X, 2, 2, 1.0, np.array([0.1, 0.2, 0.5, 0.99]))) == [0, 2]
+    # y1 = row 2, y2 = row 1: 1 * 0.375 > ua * 2 * 0.25 iff ua < 0.75
+    assert list(oracle.afkmc2(X, 2, 2, 1.0, np.array([0.1, 0.5, 0.3, 0.7]))) == [0, 1]
+    assert list(oracle.afkmc2(X, 2, 2, 1.0, np.array([0.1, 0.5, 0.3, 0.8]))) == [0, 2]
+    # chain length 1: the proposal itself (inverse transform on q)
+    assert list(oracle.afkmc2(X, 2, 1, 1.0, np.array([0.1, 0.74]))) == [0, 2]
+    assert list(oracle.afkmc2(X, 2, 1, 1.0, np.array([0.1, 0.76]))) == [0, 3]
+    # both proposals on the centre itself: d = 0 twice, the chain stays
+    assert list(oracle.afkmc2(X, 2, 2, 1.0, np.array([0.1, 0.05, 0.1, 0.5]))) == [0, 0]
+    # third centre with centres at 0 and 180 degrees: d = (0, 1, 0, 1);
+    # y1 = row 2 (d 0), y2 = row 3 (d 1): 1 * 0.375 > 0 always
+    u = np.array([0.1, 0.2, 0.5, 0.99, 0.5, 0.9, 0.3])
+    assert list(oracle.afkmc2(X, 3, 2, 1.0, u)) == [0, 2, 3]
+
+
+def test_afkmc2_long_chain_prefers_far_rows():
+    """With a long chain the draw concentrates where alpha - max <x, c> is
+    large: on two well separated clusters the second centre lands in the
+    other cluster far more often than the uniform share."""
+    rng = np.random.default_rng(3)
+    a = np.array([1.0, 0.0, 0.0])
+    b = np.array([0.0, 0.0, 1.0])
+    P = np.concatenate([a + 0.05 * rng.normal(size=(90, 3)), b + 0.05 * rng.normal(size=(10, 3))])
+    P /= np.linalg.norm(P, axis=1, keepdims=True)
+    X = dense_csr(P)
+    hits = 0
+    for s in range(60):
+        u = np.random.default_rng(100 + s).random(1 + 2 * 20 - 1)
+        u[0] = 0.05  # centre 0 in the large cluster
+        ch = oracle.afkmc2(X, 2, 20, 1.0, u)
+        hits += ch[1] >= 90
+    assert hits >= 50  # the small cluster holds 10% of the rows
