@@ -211,6 +211,30 @@ int skm_seed_kmeanspp(const skm_matrix* X, int32_t k, double alpha,
                       double* second_out, void* workspace, size_t workspace_bytes,
                       void* stream);
 
+/* Bytes of workspace skm_seed_afkmc2 needs. */
+size_t skm_seed_afkmc2_workspace_size(const skm_matrix* X, int32_t k, int32_t chain);
+
+/* AFK-MC2 seeding in the spherical form (Section 6 cites it with the
+ * dissimilarity alpha - <x, c>): centre 0 is row floor(u[0] n) and fixes the
+ * proposal distribution q(x) = w(x)/(2W) + 1/(2n), w(x) = max(0, alpha -
+ * <x, c0>), W = sum of w (q = 1/n if W = 0).  Each further centre is the end
+ * of a Markov chain over `chain` proposals drawn from q by inverse transform
+ * (the first row whose running q sum exceeds the draw): the chain starts at
+ * the first proposal and moves to proposal y when d(y) q(x) > u d(x) q(y),
+ * with d(.) = max(0, alpha - max_c <., c>) over the centres chosen so far.
+ * A row can be chosen twice.  CSR input only.
+ *   chain          >= 1 proposals per centre.
+ *   alpha          >= 1.
+ *   uniforms       [host] double[1 + (k-1)(2 chain - 1)] in [0, 1): u[0],
+ *                  then per centre the `chain` proposal draws followed by the
+ *                  chain - 1 acceptance draws.
+ *   chosen_out     int32[k]: chosen rows in draw order.
+ *   centers_out    float[k*d] (nullable): the chosen rows.
+ * Asynchronous: returns after enqueueing. */
+int skm_seed_afkmc2(const skm_matrix* X, int32_t k, int32_t chain, double alpha,
+                    const double* uniforms, int32_t* chosen_out, float* centers_out,
+                    void* workspace, size_t workspace_bytes, void* stream);
+
 /* Many independent problems in one call (the batched setting: hundreds of
  * small clustering problems, each solved as in skm_fit).  The library runs
  * `workers` host threads, each with its own HIP stream on the caller's

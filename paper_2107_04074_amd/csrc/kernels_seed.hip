@@ -183,3 +183,158 @@ hipError_t launch_kpp_step(const int64_t* rp, const int32_t* ci, const float* v,
 }
 
 }  // namespace skm
+
+// ------------------------------------------------------------------------
+// AFK-MC2 seeding (the Markov-chain alternative to k-means++ that Section 6
+// cites, with the dissimilarity alpha - <x, c>).  Centre 0 fixes the
+// proposal distribution q; every further centre runs a chain of m proposals
+// drawn from q.  The proposals do not depend on the chain's state, so their
+// dissimilarities to the centres chosen so far are computed together (one
+// block per proposal); only the accept/reject walk is sequential.
+// ------------------------------------------------------------------------
+namespace skm {
+namespace {
+using namespace dev;
+
+// w(x) = max(0, alpha - <x, c0>) in the canonical FP64 order.
+__global__ __launch_bounds__(kBlock) void k_afk_weights(const int64_t* __restrict__ rp,
+                                                        const int32_t* __restrict__ ci,
+                                                        const float* __restrict__ v, int64_t n,
+                                                        const double* __restrict__ c0,
+                                                        double alpha, double* __restrict__ w) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const double x = alpha - dot64_serial(ci, v, rp[i], rp[i + 1], c0);
+  w[i] = x > 0.0 ? x : 0.0;
+}
+
+// One thread: W = sum w in row order, then the running sums of
+// q(x) = w(x) / (2W) + 1 / (2n) (1/n when W = 0), in row order, so every
+// value is the same sequence of FP64 operations a plain loop performs.
+__global__ void k_afk_prefix(const double* __restrict__ w, int64_t n, double* __restrict__ W_out,
+                             double* __restrict__ prefix) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double W = 0.0;
+  for (int64_t i = 0; i < n; ++i) W += w[i];
+  double run = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    const double q = W > 0.0 ? 0.5 * w[i] / W + 0.5 / (double)n : 1.0 / (double)n;
+    run += q;
+    prefix[i] = run;
+  }
+  *W_out = W;
+}
+
+// Proposal j of the chain: the first row whose running q sum exceeds u[j]
+// (binary search on the non-decreasing prefix), the last row if none does.
+__global__ void k_afk_propose(const double* __restrict__ prefix, int64_t n,
+                              const double* __restrict__ u, int32_t m,
+                              int32_t* __restrict__ cand) {
+  const int j = blockIdx.x * kBlock + threadIdx.x;
+  if (j >= m) return;
+  const double target = u[j];
+  int64_t lo = 0, hi = n;  // first index with prefix > target lies in [lo, hi]
+  while (lo < hi) {
+    const int64_t mid = lo + (hi - lo) / 2;
+    if (prefix[mid] > target) hi = mid;
+    else lo = mid + 1;
+  }
+  cand[j] = (int32_t)(lo < n ? lo : n - 1);
+}
+
+// d(y_j) = max(0, alpha - max_{c < t} <y_j, c>): one block per proposal,
+// each wave takes every fourth centre.
+__global__ __launch_bounds__(kBlock) void k_afk_dissim(
+    const int64_t* __restrict__ rp, const int32_t* __restrict__ ci, const float* __restrict__ v,
+    int64_t d, const double* __restrict__ C64, int32_t t, double alpha,
+    const int32_t* __restrict__ cand, double* __restrict__ dcand) {
+  __shared__ double wmax[kBlock / 64];
+  const int j = blockIdx.x;
+  const int64_t y = cand[j];
+  const int64_t beg = rp[y], end = rp[y + 1];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double best = -INFINITY;
+  for (int c = wave; c < t; c += kBlock / 64) {
+    const double s = dot64_group<64>(ci, v, beg, end, C64 + (size_t)c * d, lane);
+    best = s > best ? s : best;
+  }
+  if (lane == 0) wmax[wave] = best;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double b = wmax[0];
+    for (int q = 1; q < kBlock / 64; ++q) b = wmax[q] > b ? wmax[q] : b;
+    const double x = alpha - b;
+    dcand[j] = x > 0.0 ? x : 0.0;
+  }
+}
+
+// The chain: start at y_1, move to y_j when d(y_j) q(x) > u d(x) q(y_j).
+__global__ void k_afk_chain(const int32_t* __restrict__ cand, const double* __restrict__ dcand,
+                            const double* __restrict__ w, const double* __restrict__ Wp,
+                            int64_t n, const double* __restrict__ uacc, int32_t m, int32_t t,
+                            int32_t* __restrict__ chosen) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double W = *Wp;
+  auto q = [&](int64_t i) {
+    return W > 0.0 ? 0.5 * w[i] / W + 0.5 / (double)n : 1.0 / (double)n;
+  };
+  int64_t x = cand[0];
+  double dx = dcand[0];
+  for (int j = 1; j < m; ++j) {
+    const int64_t y = cand[j];
+    const double dy = dcand[j];
+    if (dy * q(x) > uacc[j - 1] * dx * q(y)) {
+      x = y;
+      dx = dy;
+    }
+  }
+  chosen[t] = (int32_t)x;
+}
+
+__global__ void k_afk_first(const double* __restrict__ u, int64_t n, int32_t* __restrict__ chosen) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int64_t p = (int64_t)floor(u[0] * (double)n);
+  if (p > n - 1) p = n - 1;
+  if (p < 0) p = 0;
+  chosen[0] = (int32_t)p;
+}
+
+}  // namespace
+
+hipError_t launch_afkmc2(const int64_t* rp, const int32_t* ci, const float* v, int64_t n,
+                         int64_t d, int32_t k, int32_t m, double alpha, const double* u_dev,
+                         int32_t* chosen, float* centres, double* C64, double* w, double* W,
+                         double* prefix, int32_t* cand, double* dcand, hipStream_t s) {
+  hipError_t e;
+  const unsigned nblk = (unsigned)((n + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_afk_first, dim3(1), dim3(64), 0, s, u_dev, n, chosen);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_kpp_densify, dim3(1), dim3(kBlock), 0, s, rp, ci, v, d, chosen, 0, centres);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = launch_init_centres(centres, 1, d, 1, C64, nullptr, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_afk_weights, dim3(nblk), dim3(kBlock), 0, s, rp, ci, v, n, C64, alpha, w);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_afk_prefix, dim3(1), dim3(64), 0, s, w, n, W, prefix);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  for (int32_t t = 1; t < k; ++t) {
+    const double* ut = u_dev + 1 + (size_t)(t - 1) * (2 * m - 1);
+    hipLaunchKernelGGL(k_afk_propose, dim3((unsigned)((m + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                       s, prefix, n, ut, m, cand);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_afk_dissim, dim3((unsigned)m), dim3(kBlock), 0, s, rp, ci, v, d, C64, t,
+                       alpha, cand, dcand);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_afk_chain, dim3(1), dim3(64), 0, s, cand, dcand, w, W, n, ut + m, m, t,
+                       chosen);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_kpp_densify, dim3(1), dim3(kBlock), 0, s, rp, ci, v, d, chosen, t,
+                       centres);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_init_centres(centres + (size_t)t * d, 1, d, 1, C64 + (size_t)t * d, nullptr,
+                                 s)) != hipSuccess)
+      return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace skm

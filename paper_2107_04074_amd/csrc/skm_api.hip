@@ -1159,6 +1159,86 @@ done:
   return rc;
 }
 
+namespace {
+struct AfkPlan {
+  size_t w = 0, W = 0, prefix = 0, cand = 0, dcand = 0, C64 = 0, u = 0, centres = 0, total = 0;
+  size_t nu = 0;
+};
+
+int make_afk_plan(const skm_matrix* X, int32_t k, int32_t chain, AfkPlan* S) {
+  int rc = check_matrix(X);
+  if (rc != SKM_OK) return rc;
+  if (X->fmt != SKM_CSR_F32) return fail(SKM_ERR_UNSUPPORTED, "AFK-MC2 seeding needs CSR input");
+  if (k < 1 || k > X->n) return fail(SKM_ERR_INVALID_ARG, "need 1 <= k <= n (k = %d)", (int)k);
+  if (chain < 1 || chain > (1 << 20))
+    return fail(SKM_ERR_INVALID_ARG, "need 1 <= chain <= 2^20 (chain = %d)", (int)chain);
+  const size_t n = (size_t)X->n, d = (size_t)X->d;
+  size_t cur = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = cur;
+    cur += align256(bytes);
+    return o;
+  };
+  S->nu = 1 + (size_t)(k - 1) * (2 * (size_t)chain - 1);
+  S->w = take(n * 8);
+  S->W = take(8);
+  S->prefix = take(n * 8);
+  S->cand = take((size_t)chain * 4);
+  S->dcand = take((size_t)chain * 8);
+  S->C64 = take((size_t)k * d * 8);
+  S->u = take(S->nu * 8);
+  S->centres = take((size_t)k * d * 4);
+  S->total = cur;
+  return SKM_OK;
+}
+}  // namespace
+
+size_t skm_seed_afkmc2_workspace_size(const skm_matrix* X, int32_t k, int32_t chain) {
+  g_last_error.clear();
+  AfkPlan S;
+  if (make_afk_plan(X, k, chain, &S) != SKM_OK) return 0;
+  return S.total;
+}
+
+int skm_seed_afkmc2(const skm_matrix* X, int32_t k, int32_t chain, double alpha,
+                    const double* uniforms, int32_t* chosen_out, float* centers_out,
+                    void* workspace, size_t workspace_bytes, void* stream) {
+  g_last_error.clear();
+  AfkPlan S;
+  int rc = make_afk_plan(X, k, chain, &S);
+  if (rc != SKM_OK) return rc;
+  if (!uniforms || !chosen_out) return fail(SKM_ERR_INVALID_ARG, "uniforms/chosen_out NULL");
+  if (!(alpha >= 1.0) || !std::isfinite(alpha))
+    return fail(SKM_ERR_INVALID_ARG, "need alpha >= 1 (got %g)", alpha);
+  for (size_t q = 0; q < S.nu; ++q)
+    if (!(uniforms[q] >= 0.0 && uniforms[q] < 1.0))
+      return fail(SKM_ERR_INVALID_ARG, "uniform %zu = %g is not in [0, 1)", q, uniforms[q]);
+  if (workspace && workspace_bytes < S.total)
+    return fail(SKM_ERR_OUT_OF_MEMORY, "workspace has %zu bytes, %zu needed", workspace_bytes,
+                S.total);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  bool owned = false;
+  void* ws = workspace;
+  if (!ws) {
+    if (hipMallocAsync(&ws, S.total, s) != hipSuccess)
+      return fail(SKM_ERR_OUT_OF_MEMORY, "could not allocate %zu bytes of workspace", S.total);
+    owned = true;
+  }
+  {
+    float* centres = centers_out ? centers_out : at<float>(ws, S.centres);
+    double* u_dev = at<double>(ws, S.u);
+    SKM_HIP(hipMemcpyAsync(u_dev, uniforms, S.nu * sizeof(double), hipMemcpyHostToDevice, s));
+    SKM_HIP(hipMemsetAsync(centres, 0, (size_t)k * X->d * sizeof(float), s));
+    SKM_HIP(launch_afkmc2(X->row_ptr, X->col_idx, X->val, X->n, X->d, k, chain, alpha, u_dev,
+                          chosen_out, centres, at<double>(ws, S.C64), at<double>(ws, S.w),
+                          at<double>(ws, S.W), at<double>(ws, S.prefix), at<int32_t>(ws, S.cand),
+                          at<double>(ws, S.dcand), s));
+  }
+done:
+  if (owned) (void)hipFreeAsync(ws, s);
+  return rc;
+}
+
 size_t skm_fit_batched_workspace_size(int32_t nprob, const skm_matrix* Xs, const int32_t* ks,
                                       int32_t variant, const skm_options* opt,
                                       int32_t workers) {

@@ -282,6 +282,13 @@ hipError_t launch_kpp_step(const int64_t* rp, const int32_t* ci, const float* v,
                            uint8_t* taken, int32_t* chosen, float* centres, double* c64,
                            int32_t* a, double* best, double* second, double* w, double* part,
                            hipStream_t s);
+// AFK-MC2 seeding: chooses k rows (chosen), writes them to centres (FP32
+// k x d, zeroed by the caller) and their unit FP64 copies to C64 (k x d).
+// Scratch: w, prefix (n each), W (1), cand (m), dcand (m).
+hipError_t launch_afkmc2(const int64_t* rp, const int32_t* ci, const float* v, int64_t n,
+                         int64_t d, int32_t k, int32_t m, double alpha, const double* u_dev,
+                         int32_t* chosen, float* centres, double* C64, double* w, double* W,
+                         double* prefix, int32_t* cand, double* dcand, hipStream_t s);
 // Gram slicing over d: number of column slices and their length.
 void gram_slicing(int32_t k, int64_t d, int* nslice, int64_t* slice_len);
 hipError_t launch_gram(const double* C64, int32_t k, int64_t d, const int32_t* dirty,

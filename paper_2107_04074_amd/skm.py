@@ -26,6 +26,7 @@ OK, ERR_INVALID_ARG, ERR_NOT_NORMALIZED, ERR_OUT_OF_MEMORY, ERR_HIP, ERR_UNSUPPO
 # Every symbol include/skm.h declares.
 EXPORTS = ("skm_workspace_size", "skm_assign_workspace_size", "skm_fit", "skm_assign",
            "skm_seed_workspace_size", "skm_seed_kmeanspp",
+           "skm_seed_afkmc2_workspace_size", "skm_seed_afkmc2",
            "skm_fit_batched_workspace_size", "skm_fit_batched",
            "skm_status_string", "skm_last_error", "skm_version")
 
@@ -97,6 +98,11 @@ def load(path: str = LIB_PATH):
     lib.skm_seed_kmeanspp.restype = ctypes.c_int
     lib.skm_seed_kmeanspp.argtypes = [ctypes.POINTER(SkmMatrix), i32, ctypes.c_double, p, p, p,
                                       p, p, p, p, sz, p]
+    lib.skm_seed_afkmc2_workspace_size.restype = sz
+    lib.skm_seed_afkmc2_workspace_size.argtypes = [ctypes.POINTER(SkmMatrix), i32, i32]
+    lib.skm_seed_afkmc2.restype = ctypes.c_int
+    lib.skm_seed_afkmc2.argtypes = [ctypes.POINTER(SkmMatrix), i32, i32, ctypes.c_double, p, p,
+                                    p, p, sz, p]
     lib.skm_status_string.restype = ctypes.c_char_p
     lib.skm_status_string.argtypes = [ctypes.c_int]
     lib.skm_last_error.restype = ctypes.c_char_p
@@ -226,6 +232,31 @@ def seed_kmeanspp(X: DeviceCSR, k: int, uniforms, alpha: float = 1.0, workspace=
                                  _ptr(centers), _ptr(a), _ptr(best), _ptr(second),
                                  _ptr(workspace), workspace.numel(), _stream()))
     return chosen, centers, a, best, second
+
+
+def seed_afkmc2(X: DeviceCSR, k: int, chain: int, uniforms, alpha: float = 1.0,
+                workspace=None):
+    """Runs skm_seed_afkmc2 with the caller's draws (1 + (k-1)(2 chain - 1)
+    floats in [0, 1)).  Returns (chosen int32, centers float32 (k, d));
+    asynchronous."""
+    import torch
+    lib = load()
+    dev = X.col.device
+    m = X.matrix()
+    u = np.ascontiguousarray(uniforms, dtype=np.float64)
+    if u.shape != (1 + (k - 1) * (2 * chain - 1),):
+        raise ValueError("need 1 + (k - 1)(2 chain - 1) uniforms")
+    if workspace is None:
+        size = lib.skm_seed_afkmc2_workspace_size(ctypes.byref(m), k, chain)
+        if size == 0:
+            raise SkmError(ERR_INVALID_ARG, lib.skm_last_error().decode(errors="replace"))
+        workspace = torch.empty(size, dtype=torch.uint8, device=dev)
+    chosen = torch.empty(k, dtype=torch.int32, device=dev)
+    centers = torch.empty((k, X.d), dtype=torch.float32, device=dev)
+    _check(lib.skm_seed_afkmc2(ctypes.byref(m), k, chain, float(alpha), u.ctypes.data,
+                               _ptr(chosen), _ptr(centers), _ptr(workspace), workspace.numel(),
+                               _stream()))
+    return chosen, centers
 
 
 def workspace_size(X: DeviceCSR, k: int, variant="hamerly", **opts) -> int:

@@ -176,6 +176,22 @@ def test_seeding_and_warm_start_arguments_are_rejected(lib):
     assert rc == skm.ERR_UNSUPPORTED
 
 
+def test_afkmc2_arguments_are_rejected(lib):
+    m = _fake_csr(n=10)
+    assert lib.skm_seed_afkmc2_workspace_size(ctypes.byref(m), 3, 4) > 0
+    assert lib.skm_seed_afkmc2_workspace_size(ctypes.byref(m), 3, 0) == 0
+    assert b"chain" in lib.skm_last_error()
+    assert lib.skm_seed_afkmc2_workspace_size(ctypes.byref(m), 11, 4) == 0
+    good = (ctypes.c_double * 15)(*([0.5] * 15))  # 1 + 2 * (2 * 4 - 1)
+    rc = lib.skm_seed_afkmc2(ctypes.byref(m), 3, 4, 0.9, good, 0x5000, None, None, 0, None)
+    assert rc == skm.ERR_INVALID_ARG and b"alpha" in lib.skm_last_error()
+    bad = (ctypes.c_double * 15)(*([0.5] * 14 + [1.0]))
+    rc = lib.skm_seed_afkmc2(ctypes.byref(m), 3, 4, 1.0, bad, 0x5000, None, None, 0, None)
+    assert rc == skm.ERR_INVALID_ARG and b"uniform 14" in lib.skm_last_error()
+    rc = lib.skm_seed_afkmc2(ctypes.byref(m), 3, 4, 1.0, good, None, None, None, 0, None)
+    assert rc == skm.ERR_INVALID_ARG
+
+
 def test_product_path_refuses_without_library(monkeypatch, tmp_path):
     """The binding never falls back to CPU code: a missing library raises."""
     monkeypatch.setattr(skm, "_lib", None)

@@ -83,3 +83,20 @@ def test_warm_start_equals_cold_fit(skm, torch_cuda, variant):
         ref = oracle.fit(X, C.cpu().numpy(), "lloyd", 60)
         assert ref.iterations == stw.iterations
         assert np.array_equal(aw.cpu().numpy(), ref.a)
+
+
+@pytest.mark.parametrize("name,n,k,chain,alpha", [("c1", None, 10, 20, 1.0),
+                                                  ("c1", None, 10, 5, 1.5),
+                                                  ("c2", 20000, 100, 50, 1.0),
+                                                  ("c2", 3000, 300, 1, 1.0)])
+def test_afkmc2_matches_oracle(skm, torch_cuda, name, n, k, chain, alpha):
+    torch = torch_cuda
+    say("case afkmc2 %s n=%s k=%d chain=%d alpha=%g" % (name, n, k, chain, alpha))
+    X, _, _ = datagen.sparse_workload(name, n)
+    u = np.random.default_rng(k + chain).random(1 + (k - 1) * (2 * chain - 1))
+    ref = oracle.afkmc2(X, k, chain, alpha, u)
+    Xd = skm.DeviceCSR.from_host(X)
+    ch, C = skm.seed_afkmc2(Xd, k, chain, u, alpha)
+    torch.cuda.synchronize()
+    assert np.array_equal(ch.cpu().numpy(), ref)
+    assert np.array_equal(C.cpu().numpy(), datagen.init_centers_csr(X, ref))
