@@ -10,7 +10,8 @@ helpers for tiny inputs (exhaustive partition search and the bound formulas
 written with explicit angles).
 
 Variants follow the numbering LLOYD=0, ELKAN=1, HAMERLY=2, SIMP_ELKAN=3,
-SIMP_HAMERLY=4 (Sections 5, 5.2, 5.3, 5.1 and 5.4 of the paper).
+SIMP_HAMERLY=4, YINYANG=5 (Sections 5, 5.2, 5.3, 5.1, 5.4 and 5.5 of the
+paper; Yin-Yang with groups of 32 consecutive centres).
 """
 from __future__ import annotations
 
@@ -28,9 +29,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "skm_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-LLOYD, ELKAN, HAMERLY, SIMP_ELKAN, SIMP_HAMERLY = 0, 1, 2, 3, 4
+LLOYD, ELKAN, HAMERLY, SIMP_ELKAN, SIMP_HAMERLY, YINYANG = 0, 1, 2, 3, 4, 5
 VARIANTS = {"lloyd": LLOYD, "elkan": ELKAN, "hamerly": HAMERLY,
-            "simp_elkan": SIMP_ELKAN, "simp_hamerly": SIMP_HAMERLY}
+            "simp_elkan": SIMP_ELKAN, "simp_hamerly": SIMP_HAMERLY, "yinyang": YINYANG}
 
 
 def build(force: bool = True) -> str:

@@ -68,7 +68,17 @@
 int oracle_threads(void) { return omp_get_max_threads(); }
 
 enum { ORC_LLOYD = 0, ORC_ELKAN = 1, ORC_HAMERLY = 2, ORC_SIMP_ELKAN = 3,
-       ORC_SIMP_HAMERLY = 4 };
+       ORC_SIMP_HAMERLY = 4, ORC_YINYANG = 5 };
+
+/* YINYANG reading (Section 5.5 names the method and states that the bounds
+ * transfer unchanged): the centres are split into groups of YY_GROUP
+ * consecutive indices; every point keeps l(i) and one upper bound u(i, f)
+ * per group f >= max over the group's centres other than a(i).  The group
+ * bounds follow the guarded Eq. (7) with the group's largest movement; a
+ * point whose l(i) is at least every group bound is skipped (global
+ * filter), otherwise l(i) is tightened and only the groups whose bound
+ * still exceeds it are recomputed (group filter). */
+#define YY_GROUP 32
 
 typedef struct {
   int64_t n, d;
@@ -437,6 +447,8 @@ int32_t oracle_fit(int64_t n, int64_t d, const int64_t *rp, const int32_t *ci,
   const int elkan = variant == ORC_ELKAN || variant == ORC_SIMP_ELKAN;
   const int hamerly = variant == ORC_HAMERLY || variant == ORC_SIMP_HAMERLY;
   const int simplified = variant == ORC_SIMP_ELKAN || variant == ORC_SIMP_HAMERLY;
+  const int yy = variant == ORC_YINYANG;
+  const int ng = (k + YY_GROUP - 1) / YY_GROUP;
 
   double *C = (double *)malloc(sizeof(double) * (size_t)k * (size_t)d);
   double *Cold = (double *)malloc(sizeof(double) * (size_t)k * (size_t)d);
@@ -454,6 +466,9 @@ int32_t oracle_fit(int64_t n, int64_t d, const int64_t *rp, const int32_t *ci,
   double *l = (double *)malloc(sizeof(double) * (size_t)n);
   double *uh = hamerly ? (double *)malloc(sizeof(double) * (size_t)n) : NULL;
   double *ue = elkan ? (double *)malloc(sizeof(double) * (size_t)n * (size_t)k) : NULL;
+  double *uy = yy ? (double *)malloc(sizeof(double) * (size_t)n * (size_t)ng) : NULL;
+  double *pg = yy ? (double *)malloc(sizeof(double) * (size_t)ng) : NULL;
+  double *ompg = yy ? (double *)malloc(sizeof(double) * (size_t)ng) : NULL;
   double *p = (double *)malloc(sizeof(double) * (size_t)k);
   double *omp = (double *)malloc(sizeof(double) * (size_t)k);
   double *cc = (!simplified && (elkan || hamerly))
@@ -486,8 +501,15 @@ int32_t oracle_fit(int64_t n, int64_t d, const int64_t *rp, const int32_t *ci,
           if (na != a[i]) changed += 1;
           a[i] = na;
           oa += b;
-          if (elkan || hamerly) l[i] = b / rn[i];
+          if (elkan || hamerly || yy) l[i] = b / rn[i];
           if (hamerly) uh[i] = sc / rn[i];
+          if (yy)
+            for (int32_t f = 0; f < ng; ++f) {
+              double gm = -1.0; /* no other centre in the group: any bound holds */
+              for (int32_t j = f * YY_GROUP; j < k && j < (f + 1) * YY_GROUP; ++j)
+                if (j != na && s[j] / rn[i] > gm) gm = s[j] / rn[i];
+              uy[(size_t)i * ng + f] = gm;
+            }
           if (elkan)
             for (int32_t j = 0; j < k; ++j) ue[(size_t)i * k + j] = s[j] / rn[i];
         }
@@ -514,6 +536,13 @@ int32_t oracle_fit(int64_t n, int64_t d, const int64_t *rp, const int32_t *ci,
         }
       }
       if (k == 1) { pmin2 = 1.0; ompmin2 = 0.0; }
+      /* YINYANG: the largest movement (smallest p) of every group */
+      if (yy)
+        for (int32_t f = 0; f < ng; ++f) {
+          pg[f] = INFINITY;
+          for (int32_t j = f * YY_GROUP; j < k && j < (f + 1) * YY_GROUP; ++j)
+            if (p[j] < pg[f]) { pg[f] = p[j]; ompg[f] = omp[j]; }
+        }
 
 #pragma omp parallel reduction(+ : changed, sims, viol)
       {
@@ -526,7 +555,13 @@ int32_t oracle_fit(int64_t n, int64_t d, const int64_t *rp, const int32_t *ci,
           const int raw = bound_form == 2;
           l[i] = raw ? oracle_lower_unguarded(l[i], p[cur])
                      : oracle_lower_update(l[i], p[cur], omp[cur]);
-          if (elkan) {
+          if (yy) {
+            /* Eq. (7) with every group's largest movement */
+            double *ug = uy + (size_t)i * ng;
+            for (int32_t f = 0; f < ng; ++f)
+              ug[f] = raw ? oracle_upper_unguarded(ug[f], pg[f])
+                          : oracle_upper_update(ug[f], pg[f], ompg[f]);
+          } else if (elkan) {
             /* Eq. (7) for every u(i, j) */
             double *ui = ue + (size_t)i * k;
             for (int32_t j = 0; j < k; ++j)
@@ -543,7 +578,10 @@ int32_t oracle_fit(int64_t n, int64_t d, const int64_t *rp, const int32_t *ci,
             all_sims(&X, i, k, C, s);
             for (int32_t j = 0; j < k; ++j) s[j] /= rn[i];
             if (l[i] > s[cur] + 1e-12) viol += 1;
-            if (elkan) {
+            if (yy) {
+              for (int32_t j = 0; j < k; ++j)
+                if (j != cur && uy[(size_t)i * ng + j / YY_GROUP] < s[j] - 1e-12) viol += 1;
+            } else if (elkan) {
               for (int32_t j = 0; j < k; ++j)
                 if (ue[(size_t)i * k + j] < s[j] - 1e-12) viol += 1;
             } else {
@@ -552,7 +590,52 @@ int32_t oracle_fit(int64_t n, int64_t d, const int64_t *rp, const int32_t *ci,
             }
           }
 
-          if (elkan) {
+          if (yy) {
+            double *ug = uy + (size_t)i * ng;
+            double umax = -INFINITY;
+            for (int32_t f = 0; f < ng; ++f) umax = ug[f] > umax ? ug[f] : umax;
+            if (umax <= l[i] - DELTA) continue; /* global filter */
+            const double sa = sim(&X, i, C + (size_t)cur * d);
+            l[i] = sa / rn[i];
+            sims += 1;
+            if (umax <= l[i] - DELTA) continue;
+            /* group filter: recompute the groups whose bound exceeds l */
+            double best = sa;
+            int32_t bj = cur;
+            char *open = (char *)calloc((size_t)ng, 1);
+            double *gs = (double *)malloc(sizeof(double) * (size_t)k);
+            for (int32_t f = 0; f < ng; ++f) {
+              if (ug[f] <= l[i] - DELTA) continue;
+              open[f] = 1;
+              for (int32_t j = f * YY_GROUP; j < k && j < (f + 1) * YY_GROUP; ++j) {
+                if (j == cur) { gs[j] = sa; continue; }
+                gs[j] = sim(&X, i, C + (size_t)j * d);
+                sims += 1;
+                /* ARGMAX: a switch needs a strictly larger value, ties go to
+                 * the lower index among the challengers */
+                if (gs[j] > best || (gs[j] == best && bj != cur && j < bj)) {
+                  best = gs[j];
+                  bj = j;
+                }
+              }
+            }
+            cur = bj;
+            l[i] = best / rn[i];
+            for (int32_t f = 0; f < ng; ++f) {
+              if (!open[f]) continue;
+              double gm = -1.0;
+              for (int32_t j = f * YY_GROUP; j < k && j < (f + 1) * YY_GROUP; ++j)
+                if (j != cur && gs[j] / rn[i] > gm) gm = gs[j] / rn[i];
+              ug[f] = gm;
+            }
+            /* the old centre is now an ordinary member of its group */
+            if (cur != prev) {
+              const int32_t fo = prev / YY_GROUP;
+              if (sa / rn[i] > ug[fo]) ug[fo] = sa / rn[i];
+            }
+            free(gs);
+            free(open);
+          } else if (elkan) {
             /* Sections 5.1 / 5.2 */
             if (!simplified && sthr[cur] <= l[i] - DELTA) continue;
             double *ui = ue + (size_t)i * k;
@@ -628,6 +711,7 @@ int32_t oracle_fit(int64_t n, int64_t d, const int64_t *rp, const int32_t *ci,
   if (violations) *violations = viol;
   if (converged) *converged = done;
   free(rn); free(sthr); free(cc); free(omp); free(p); free(ue); free(uh); free(l);
+  free(uy); free(pg); free(ompg);
   free(a); free(Cold); free(C);
   return t;
 }

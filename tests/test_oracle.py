@@ -204,9 +204,9 @@ def test_objective_monotone_c1():
 
 def _check_variants_equal(X, C0, max_iter, check=True):
     ref = oracle.fit(X, C0, "lloyd", max_iter, trace=True)
-    for v in ["elkan", "hamerly", "simp_elkan", "simp_hamerly"]:
+    for v in ["elkan", "hamerly", "simp_elkan", "simp_hamerly", "yinyang"]:
         for bf in (0, 1):
-            if bf == 1 and "elkan" in v:
+            if bf == 1 and ("elkan" in v or v == "yinyang"):
                 continue
             r = oracle.fit(X, C0, v, max_iter, bound_form=bf, trace=True, check_bounds=check)
             assert r.iterations == ref.iterations, (v, bf)
@@ -240,6 +240,24 @@ def test_variants_equal_lloyd_adversarial_low_dim(seed):
     X = dense_csr(D)
     C0 = D[rng.choice(n, k, replace=False)].astype(np.float32)
     _check_variants_equal(X, C0, 200)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_yinyang_several_groups_low_dim(seed):
+    """Yin-Yang with 2-3 groups of 32 centres on mixed-sign d = 3 data: the
+    group filter, the old centre joining its group's bound and every guard
+    in play; same trajectory as Lloyd, no bound violation, fewer sims."""
+    rng = np.random.default_rng(50 + seed)
+    D = unit_rows(rng, 500, 3)
+    X = dense_csr(D)
+    k = 40 + 13 * seed
+    C0 = D[rng.choice(500, k, replace=False)].astype(np.float32)
+    ref = oracle.fit(X, C0, "lloyd", 200, trace=True)
+    r = oracle.fit(X, C0, "yinyang", 200, trace=True, check_bounds=True)
+    assert r.iterations == ref.iterations
+    assert np.array_equal(r.a_trace, ref.a_trace) and np.array_equal(r.C, ref.C)
+    assert r.violations == 0
+    assert r.sims.sum() < ref.sims.sum()
 
 
 def test_guards_are_necessary():
