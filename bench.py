@@ -213,8 +213,8 @@ def main():
     variants = {}
     table = (["lloyd_fp32", "lloyd_bf16", "simp_hamerly_bf16", "hamerly_bf16",
               "hamerly_fp32"] if dense else
-             ["lloyd", "simp_hamerly", "hamerly", "simp_elkan", "elkan", "lloyd_fp16",
-              "simp_hamerly_fp16", "hamerly_fp16"])
+             ["lloyd", "simp_hamerly", "hamerly", "simp_elkan", "elkan", "yinyang",
+              "lloyd_fp16", "simp_hamerly_fp16", "hamerly_fp16", "yinyang_fp16"])
     for v in ([] if (args.quick or args.skip_baseline) else table):
         one_fit(v)
         best = None

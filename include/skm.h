@@ -66,7 +66,9 @@ typedef enum {
   SKM_ELKAN = 1,        /* per-centre bounds + centre-centre tests (5.2)     */
   SKM_HAMERLY = 2,      /* one upper and one lower bound + s(a) test (5.3)   */
   SKM_SIMP_ELKAN = 3,   /* Elkan without centre-centre tests (5.1)           */
-  SKM_SIMP_HAMERLY = 4  /* Hamerly without the s(a) test (5.4)               */
+  SKM_SIMP_HAMERLY = 4, /* Hamerly without the s(a) test (5.4)               */
+  SKM_YINYANG = 5       /* one upper bound per group of 32 consecutive
+                           centres (5.5); CSR input                          */
 } skm_variant;
 
 typedef enum {

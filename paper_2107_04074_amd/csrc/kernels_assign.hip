@@ -323,6 +323,75 @@ __device__ __forceinline__ bool hamerly_prologue(const AssignArgs& A, int64_t ro
   return skip;
 }
 
+// Yin-Yang prologue (Section 5.5 with the bounds of Section 4): Eq. (6) for
+// l(i), the guarded Eq. (7) for every group bound u(i, f) with the group's
+// largest movement, and the global filter l(i) >= max_f u(i, f), first
+// as is, then with l(i) tightened.  Lanes share the groups.  Returns true
+// when the row needs no walk; the bounds are then stored.
+template <int G>
+__device__ __forceinline__ bool yinyang_prologue(const AssignArgs& A, int64_t row, int prev,
+                                                 int64_t beg, int64_t end, int gl, bool leader,
+                                                 unsigned long long& tight,
+                                                 unsigned long long& saved) {
+  const int m = (int)(end - beg);
+  const double eta = (double)A.eta[row];
+  const double slack = 1.01 * (eta + A.delta_c);
+  const double rho32 = (double)(m + 3) * kU32 * (1.0 + eta) * 1.01 + slack + 1e-12;
+  const double mu = 4.0 * (double)(m + 2) * kU64 * (1.0 + eta) + 4.0 * A.delta_c + 1e-15;
+  double ld = lower_upd((double)A.l[row], A.pc[prev], A.ps[prev]) - 4e-15;
+  float* uyr = A.uy + (size_t)row * A.ng;
+  double umax = -INFINITY;
+  for (int f = gl; f < A.ng; f += G) {
+    const double uf = fmin(1.0, upper_upd((double)uyr[f], A.gpc[f], A.gps[f]) + 4e-15);
+    umax = fmax(umax, uf);
+  }
+#pragma unroll
+  for (int off = G / 2; off >= 1; off >>= 1) umax = fmax(umax, __shfl_xor(umax, off, G));
+  bool skip = ld - umax >= mu;
+  if (!skip && A.try_tighten) {
+    const float s32 = group_col_dot32<G>(A.ci, A.v, beg, end, A.CT, A.kp, prev, gl);
+    ld = fmax(ld, (double)s32 - rho32);
+    if (leader) tight += 1;
+    skip = ld - umax >= mu;
+    if (skip && leader) saved += 1;
+  }
+  if (skip) {
+    if (leader) A.l[row] = __double2float_rd(fmax(ld, -1.0));
+    for (int f = gl; f < A.ng; f += G)
+      uyr[f] = __double2float_ru(fmin(1.0, upper_upd((double)uyr[f], A.gpc[f], A.gps[f]) + 4e-15));
+  }
+  return skip;
+}
+
+// After a walk: every Yin-Yang group bound becomes the largest computed
+// similarity of the group's centres other than the new assignment (plus the
+// error band, rounded up); -1 for a group with no other centre.  A group of
+// kYYGroup centres is kYYGroup / VEC consecutive lanes of one chunk.
+template <int G, int R, int VEC>
+__device__ __forceinline__ void write_group_bounds(const AssignArgs& A, int64_t row,
+                                                   const float4 (&acc)[R * VEC / 4], int gl,
+                                                   int abest, double rho32, bool writer) {
+  constexpr int SEG = (kYYGroup / VEC < G) ? kYYGroup / VEC : G;  // lanes per group
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    float m = -INFINITY;
+#pragma unroll
+    for (int q = 0; q < VEC; ++q) {
+      const int j = VEC * (gl + G * r) + q;
+      if (j < A.k && j != abest) m = fmaxf(m, f4get(acc[(r * VEC + q) >> 2], q & 3));
+    }
+#pragma unroll
+    for (int off = SEG / 2; off >= 1; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, SEG));
+    const int j0 = VEC * (gl + G * r);
+    if (writer && (gl % SEG) == 0 && j0 < A.k) {
+      const int f = j0 / kYYGroup;
+      const float val = (m == -INFINITY) ? -1.0f
+                                         : __double2float_ru(fmin((double)m + rho32, 1.0));
+      A.uy[(size_t)row * A.ng + f] = val;
+    }
+  }
+}
+
 // FP64 re-decision among a group's candidates: lane gl's candidates are the
 // set bits of cm (bit VEC r + q = centre VEC (gl + G r) + q).  Candidates are
 // taken one at a time, lowest lane and bit first, and the whole group
@@ -448,8 +517,12 @@ __global__ __launch_bounds__(kBlock) void k_assign_csr(AssignArgs A) {
     }
     const int m = (int)(end - beg);
     const int prev = A.read_prev ? A.a[row] : -1;
-    if (MODE == kModeHamerly) {
-      if (hamerly_prologue<G>(A, row, prev, beg, end, gl, leader, my_tight, my_saved)) {
+    if (MODE == kModeHamerly || MODE == kModeYinYang) {
+      const bool skip =
+          MODE == kModeHamerly
+              ? hamerly_prologue<G>(A, row, prev, beg, end, gl, leader, my_tight, my_saved)
+              : yinyang_prologue<G>(A, row, prev, beg, end, gl, leader, my_tight, my_saved);
+      if (skip) {
         if constexpr (WAVE_ROW) next_window();
         continue;
       }
@@ -543,6 +616,7 @@ __global__ __launch_bounds__(kBlock) void k_assign_csr(AssignArgs A) {
           A.u[row] = __double2float_ru(fmin(hi, 1.0));
         }
       }
+      if (A.uy) write_group_bounds<G, R, VEC>(A, row, acc, gl, abest, rho32, lead_sub);
       if (MODE == kModeFitElkanInit && lead_sub) {
         float4* uer4 = reinterpret_cast<float4*>(A.ue + (size_t)row * A.kp);
 #pragma unroll
@@ -833,7 +907,7 @@ __global__ __launch_bounds__(kBlock) void k_warm_start(
     const int32_t* __restrict__ wa, const double* __restrict__ wb,
     const double* __restrict__ ws2, const float* __restrict__ eta, double delta_c,
     int32_t* __restrict__ a, float* __restrict__ l, float* __restrict__ u,
-    float* __restrict__ ue) {
+    float* __restrict__ ue, float* __restrict__ uy, int32_t ng) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   const int64_t m = rp[i + 1] - rp[i];
@@ -852,6 +926,27 @@ __global__ __launch_bounds__(kBlock) void k_warm_start(
     float* row = ue + (size_t)i * kp;
     for (int j = 0; j < kp; ++j) row[j] = (j >= k) ? 1.0f : (j == ai ? top : other);
   }
+  if (uy) {  // every centre other than a(i) is at most the second best
+    const float other = __double2float_ru(fmin(hi, 1.0));
+    for (int f = 0; f < ng; ++f) uy[(size_t)i * ng + f] = other;
+  }
+}
+
+// Cosine and sine of every Yin-Yang group's largest movement (the member
+// with the smallest movement cosine).
+__global__ void k_group_move(const double* __restrict__ pc, const double* __restrict__ ps,
+                             int32_t k, int32_t ng, double* __restrict__ gpc,
+                             double* __restrict__ gps) {
+  const int f = blockIdx.x * kBlock + threadIdx.x;
+  if (f >= ng) return;
+  double c = 2.0, sn = 0.0;
+  for (int j = f * kYYGroup; j < k && j < (f + 1) * kYYGroup; ++j)
+    if (pc[j] < c) {
+      c = pc[j];
+      sn = ps[j];
+    }
+  gpc[f] = c;
+  gps[f] = sn;
 }
 
 template <int MODE>
@@ -908,10 +1003,17 @@ hipError_t launch_assign_mode(const AssignArgs& A, hipStream_t s) {
 hipError_t launch_warm_start(const int64_t* rp, int64_t n, int32_t k, int32_t kp,
                              const int32_t* wa, const double* wb, const double* ws2,
                              const float* eta, double delta_c, int32_t* a, float* l, float* u,
-                             float* ue, hipStream_t s) {
+                             float* ue, float* uy, int32_t ng, hipStream_t s) {
   const unsigned blocks = (unsigned)((n + kBlock - 1) / kBlock);
   hipLaunchKernelGGL(k_warm_start, dim3(blocks), dim3(kBlock), 0, s, rp, n, k, kp, wa, wb, ws2,
-                     eta, delta_c, a, l, u, ue);
+                     eta, delta_c, a, l, u, ue, uy, ng);
+  return hipGetLastError();
+}
+
+hipError_t launch_group_move(const double* pc, const double* ps, int32_t k, int32_t ng,
+                             double* gpc, double* gps, hipStream_t s) {
+  hipLaunchKernelGGL(k_group_move, dim3((unsigned)((ng + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                     s, pc, ps, k, ng, gpc, gps);
   return hipGetLastError();
 }
 
@@ -919,6 +1021,7 @@ hipError_t launch_assign(const AssignArgs& A, int mode, hipStream_t s) {
   if (mode == kModeAssign) return launch_assign_mode<kModeAssign>(A, s);
   if (mode == kModeFit) return launch_assign_mode<kModeFit>(A, s);
   if (mode == kModeHamerly) return launch_assign_mode<kModeHamerly>(A, s);
+  if (mode == kModeYinYang) return launch_assign_mode<kModeYinYang>(A, s);
   return launch_assign_mode<kModeFitElkanInit>(A, s);
 }
 

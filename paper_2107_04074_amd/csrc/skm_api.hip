@@ -62,6 +62,9 @@ struct Plan {
   int64_t slice_len = 0;
   // byte offsets into the workspace
   bool half = false;  // FP16 centre copy for the row walk
+  bool yy = false;    // Yin-Yang group bounds
+  int32_t ng = 0;     // Yin-Yang groups
+  size_t uy = 0, gpc = 0, gps = 0;
   size_t CT = 0, CT16 = 0, negflag = 0, C64 = 0, S = 0, l = 0, u = 0, ue = 0, eta = 0,
          a_old = 0, norm64 = 0, part = 0, part_sq = 0, pc = 0, ps = 0, dirty = 0, mm = 0, G = 0,
          gmax = 0, gpart = 0, cnt = 0, per = 0, maxeta = 0, initnorm = 0, total = 0;
@@ -96,7 +99,7 @@ int make_plan(const skm_matrix* X, int32_t k, int32_t variant, int32_t precision
     return fail(SKM_ERR_UNSUPPORTED, "CSR input supports precision 0 (FP32) or 2 (FP16 centre "
                 "copy), got %d", (int)precision);
   if (k < 1 || (int64_t)k > X->n) return fail(SKM_ERR_INVALID_ARG, "need 1 <= k <= n");
-  if (variant < SKM_LLOYD || variant > SKM_SIMP_HAMERLY)
+  if (variant < SKM_LLOYD || variant > SKM_YINYANG)
     return fail(SKM_ERR_INVALID_ARG, "unknown variant %d", (int)variant);
   const Geometry g = pick_geometry(k);
   if (g.G == 0) return fail(SKM_ERR_UNSUPPORTED, "k = %d exceeds the supported 4096", (int)k);
@@ -107,6 +110,8 @@ int make_plan(const skm_matrix* X, int32_t k, int32_t variant, int32_t precision
   P->kp = g.kp;
   P->variant = variant;
   P->elkan = variant == SKM_ELKAN || variant == SKM_SIMP_ELKAN;
+  P->yy = variant == SKM_YINYANG;
+  P->ng = (k + kYYGroup - 1) / kYYGroup;
   P->bounds = variant != SKM_LLOYD;
   P->gram = variant == SKM_ELKAN || variant == SKM_HAMERLY;
   P->nchunk = (int)((X->d + 4095) / 4096);
@@ -129,9 +134,14 @@ int make_plan(const skm_matrix* X, int32_t k, int32_t variant, int32_t precision
   P->a_old = take(n * sizeof(int32_t));
   if (P->bounds) {
     P->l = take(n * sizeof(float));
-    if (!P->elkan) P->u = take(n * sizeof(float));
+    if (!P->elkan && !P->yy) P->u = take(n * sizeof(float));
   }
   if (P->elkan) P->ue = take(n * (size_t)g.kp * sizeof(float));
+  if (P->yy) {
+    P->uy = take(n * (size_t)P->ng * sizeof(float));
+    P->gpc = take((size_t)P->ng * sizeof(double));
+    P->gps = take((size_t)P->ng * sizeof(double));
+  }
   P->norm64 = take(kk * sizeof(double));
   P->part = take(kk * (size_t)P->nchunk * sizeof(double));
   P->part_sq = take(kk * (size_t)P->nchunk * sizeof(double));
@@ -240,10 +250,11 @@ int make_dense_plan(const skm_matrix* X, int32_t k, int32_t variant, int32_t pre
   int rc = check_matrix(X);
   if (rc != SKM_OK) return rc;
   if (k < 1 || (int64_t)k > X->n) return fail(SKM_ERR_INVALID_ARG, "need 1 <= k <= n");
-  if (variant < SKM_LLOYD || variant > SKM_SIMP_HAMERLY)
+  if (variant < SKM_LLOYD || variant > SKM_YINYANG)
     return fail(SKM_ERR_INVALID_ARG, "unknown variant %d", (int)variant);
-  if (variant == SKM_ELKAN || variant == SKM_SIMP_ELKAN)
-    return fail(SKM_ERR_UNSUPPORTED, "Elkan variants are implemented for CSR input only");
+  if (variant == SKM_ELKAN || variant == SKM_SIMP_ELKAN || variant == SKM_YINYANG)
+    return fail(SKM_ERR_UNSUPPORTED, "Elkan and Yin-Yang variants are implemented for CSR "
+                "input only");
   if (precision != 0 && precision != 1)
     return fail(SKM_ERR_INVALID_ARG, "precision must be 0 (fp32) or 1 (bf16)");
   P->n = X->n;
@@ -826,7 +837,10 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
   float* eta = at<float>(ws, P.eta);
   int32_t* a_old = at<int32_t>(ws, P.a_old);
   float* l = P.bounds ? at<float>(ws, P.l) : nullptr;
-  float* u = (P.bounds && !P.elkan) ? at<float>(ws, P.u) : nullptr;
+  float* u = (P.bounds && !P.elkan && !P.yy) ? at<float>(ws, P.u) : nullptr;
+  float* uy = P.yy ? at<float>(ws, P.uy) : nullptr;
+  double* gpc = P.yy ? at<double>(ws, P.gpc) : nullptr;
+  double* gps = P.yy ? at<double>(ws, P.gps) : nullptr;
   float* ue = P.elkan ? at<float>(ws, P.ue) : nullptr;
   double* norm64 = at<double>(ws, P.norm64);
   double* part = at<double>(ws, P.part);
@@ -912,7 +926,8 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
       if (t == 0 && warm) {
         // the first step's assignment and FP64 top-2 are given: bounds only
         SKM_HIP(launch_warm_start(X->row_ptr, n, k, P.kp, o.warm_assign, o.warm_best,
-                                  o.warm_second, eta, delta_c, assign_out, l, u, ue, s));
+                                  o.warm_second, eta, delta_c, assign_out, l, u, ue, uy,
+                                  P.ng, s));
         if (stats && stats->changed_per_iter && stats->per_iter_len > 0)
           stats->changed_per_iter[0] = n;
         if (stats && stats->sims_per_iter && stats->per_iter_len > 0) stats->sims_per_iter[0] = 0;
@@ -950,11 +965,15 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
         A.gmax = gmax;
         A.simplified = variant == SKM_SIMP_HAMERLY;
         A.bound_form = o.bound_form;
+        A.uy = uy;
+        A.ng = P.ng;
+        A.gpc = gpc;
+        A.gps = gps;
         // tightening costs about one cache line per stored entry, a full
         // row walk about kp/32; keep tightening while it prunes often enough
         A.try_tighten = (t <= 2 || tight_rate >= 0.2 || t % 4 == 0) ? 1 : 0;
         const int mode = exhaustive ? ((t == 0 && P.elkan) ? kModeFitElkanInit : kModeFit)
-                                    : kModeHamerly;
+                                    : (P.yy ? kModeYinYang : kModeHamerly);
         SKM_HIP(launch_assign(A, mode, s));
       } else {
         ElkanArgs E{};
@@ -1018,6 +1037,7 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
       SKM_HIP(launch_normalize_move(S, k, d, fx_inv, dirty, part_sq, C64, part, P.nchunk, s));
       SKM_HIP(launch_centre_finalize(k, d, dirty, norm64, part_sq, part, P.nchunk, delta_c, pc,
                                      ps, mm, per, s));
+      if (P.yy) SKM_HIP(launch_group_move(pc, ps, k, P.ng, gpc, gps, s));
       SKM_HIP(launch_transpose(C64, k, d, P.kp, dirty, CT, s, CT16));
       if (P.gram) {
         if (gram_exact_step(gram_updates, gram_since_exact, changed, n)) {

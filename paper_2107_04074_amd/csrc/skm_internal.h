@@ -62,7 +62,8 @@ enum AssignMode {
   kModeAssign = 0,        // skm_assign: a, best, second
   kModeFit = 1,           // exhaustive step of a fit: a, l, u
   kModeFitElkanInit = 2,  // first step of an Elkan fit: also u(i, j) for all j
-  kModeHamerly = 3        // Hamerly step: bound update and tests, walk if needed
+  kModeHamerly = 3,       // Hamerly step: bound update and tests, walk if needed
+  kModeYinYang = 4        // Yin-Yang step: group bounds, tests, walk if needed
 };
 
 struct AssignArgs {
@@ -96,7 +97,14 @@ struct AssignArgs {
   int32_t simplified;
   int32_t bound_form;
   int32_t try_tighten;
+  // Yin-Yang: n x ng group upper bounds (also written by the first step's
+  // fit mode when set) and the cosine/sine of each group's largest movement
+  float* uy;
+  int32_t ng;
+  const double* gpc;
+  const double* gps;
 };
+constexpr int kYYGroup = 32;  // centres per Yin-Yang group
 
 struct ElkanArgs {
   const int64_t* rp;
@@ -268,11 +276,15 @@ hipError_t launch_gram_carry(double* G, int32_t k, const double* pc, const doubl
 inline bool gram_exact_step(int updates_done, int since_exact, int64_t changed, int64_t n) {
   return updates_done < 2 || since_exact >= 3 || changed * 20 > n;
 }
-// First assignment step from a given assignment and FP64 top-2.
+// First assignment step from a given assignment and FP64 top-2 (uy: the
+// Yin-Yang group bounds, nullable, ng per row).
 hipError_t launch_warm_start(const int64_t* rp, int64_t n, int32_t k, int32_t kp,
                              const int32_t* wa, const double* wb, const double* ws2,
                              const float* eta, double delta_c, int32_t* a, float* l, float* u,
-                             float* ue, hipStream_t s);
+                             float* ue, float* uy, int32_t ng, hipStream_t s);
+// Cosine and sine of every Yin-Yang group's largest movement.
+hipError_t launch_group_move(const double* pc, const double* ps, int32_t k, int32_t ng,
+                             double* gpc, double* gps, hipStream_t s);
 // One step of spherical k-means++ seeding: choose centre t, write it to
 // centres (FP32 k x d, zeroed) and its unit FP64 copy to c64 (d), refresh
 // every row's running top-2 (a, best, second), weights w and per-block

@@ -17,9 +17,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "lib", "libskm.so")
 
-LLOYD, ELKAN, HAMERLY, SIMP_ELKAN, SIMP_HAMERLY = 0, 1, 2, 3, 4
+LLOYD, ELKAN, HAMERLY, SIMP_ELKAN, SIMP_HAMERLY, YINYANG = range(6)
 VARIANTS = {"lloyd": LLOYD, "elkan": ELKAN, "hamerly": HAMERLY,
-            "simp_elkan": SIMP_ELKAN, "simp_hamerly": SIMP_HAMERLY}
+            "simp_elkan": SIMP_ELKAN, "simp_hamerly": SIMP_HAMERLY, "yinyang": YINYANG}
 CSR_F32, DENSE_F32 = 0, 1
 OK, ERR_INVALID_ARG, ERR_NOT_NORMALIZED, ERR_OUT_OF_MEMORY, ERR_HIP, ERR_UNSUPPORTED = range(6)
 

@@ -48,7 +48,7 @@ def device_problems(skm, torch, insts, max_iter=None):
 
 
 @pytest.mark.parametrize("variant,workers", [("lloyd", 3), ("hamerly", 4), ("elkan", 2),
-                                             ("simp_hamerly", 1)])
+                                             ("simp_hamerly", 1), ("yinyang", 3)])
 def test_batched_equals_individual_fits(skm, torch_cuda, problems, variant, workers):
     torch = torch_cuda
     say("case batched %s workers=%d" % (variant, workers))

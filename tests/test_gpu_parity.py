@@ -105,7 +105,7 @@ def test_assign_ties_and_empty_rows(skm, torch_cuda):
 
 # ----------------------------------------------------------------- fit
 
-VARIANTS = ["lloyd", "hamerly", "elkan", "simp_hamerly", "simp_elkan"]
+VARIANTS = ["lloyd", "hamerly", "elkan", "simp_hamerly", "simp_elkan", "yinyang"]
 
 
 def run_fit(skm, torch, Xd, C0, k, variant, max_iter, **kw):
@@ -216,7 +216,7 @@ def test_fit_c2_full_size(skm, torch_cuda):
     C0 = datagen.init_centers_csr(X, init)
     Xd = skm.DeviceCSR.from_host(X)
     res = {}
-    for v in ["lloyd", "hamerly", "elkan", "simp_hamerly"]:
+    for v in ["lloyd", "hamerly", "elkan", "simp_hamerly", "yinyang"]:
         say("case fit c2 %s" % v)
         res[v] = run_fit(skm, torch, Xd, C0, cfg.k, v, cfg.max_iter)
         st = res[v][3]
@@ -350,7 +350,7 @@ def test_fp16_centre_copy_matches_fp32(skm, torch_cuda, k):
     C0 = datagen.init_centers_csr(X, datagen.init_rows(X.n, k, 5 + k))
     Xd = skm.DeviceCSR.from_host(X)
     ref = None
-    for v in ["lloyd", "hamerly", "simp_hamerly"]:
+    for v in ["lloyd", "hamerly", "simp_hamerly", "yinyang"]:
         say("case fp16 centre copy k=%d %s" % (k, v))
         a32, C32, _, st32 = run_fit(skm, torch, Xd, C0, k, v, 30)
         a16, C16, _, st16 = run_fit(skm, torch, Xd, C0, k, v, 30, precision=2)
@@ -374,7 +374,7 @@ def test_fp16_centre_copy_mixed_signs(skm, torch_cuda):
     C0 = datagen.init_centers_csr(X, datagen.init_rows(X.n, k, 9))
     Xd = skm.DeviceCSR.from_host(X)
     ref = oracle.fit(X, C0, "lloyd", 25)
-    for v in ["lloyd", "hamerly"]:
+    for v in ["lloyd", "hamerly", "yinyang"]:
         say("case fp16 mixed signs %s" % v)
         a16, C16, _, st16 = run_fit(skm, torch, Xd, C0, k, v, 25, precision=2)
         assert st16.iterations == ref.iterations and np.array_equal(a16, ref.a)

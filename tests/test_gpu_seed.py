@@ -55,7 +55,7 @@ def test_seeding_matches_oracle(skm, torch_cuda, name, n, k, alpha):
     assert np.abs(s2.cpu().numpy()[fin] - s2_ref[fin]).max(initial=0.0) < 1e-12
 
 
-@pytest.mark.parametrize("variant", ["lloyd", "hamerly", "elkan", "simp_hamerly"])
+@pytest.mark.parametrize("variant", ["lloyd", "hamerly", "elkan", "simp_hamerly", "yinyang"])
 def test_warm_start_equals_cold_fit(skm, torch_cuda, variant):
     torch = torch_cuda
     X, _, cfg = datagen.sparse_workload("c2", 20000)
