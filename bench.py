@@ -41,7 +41,6 @@ def log(*a):
 # Kernel sources whose change invalidates a stored counter measurement.
 KERNEL_SOURCES = {
     "k_assign_csr": ["kernels_assign.hip", "skm_device.h", "skm_internal.h"],
-    "k_elkan": ["kernels_assign.hip", "skm_device.h", "skm_internal.h"],
     "k_dense_sim": ["kernels_dense.hip", "skm_internal.h"],
 }
 
@@ -258,8 +257,6 @@ def main():
         roof = {"kernel": "k_dense_sim", "bound": "mfma",
                 "peak": 2500.0 if vprec == 1 else 157.3,
                 "dtype": "bf16" if vprec == 1 else "f32"}
-    elif split(args.variant)[0] in ("elkan", "simp_elkan"):
-        roof = {"kernel": "k_elkan", "bound": "alu", "peak": PEAK_FP32_TFLOPS}
     else:
         roof = {"kernel": "k_assign_csr", "bound": "alu", "peak": PEAK_FP32_TFLOPS}
     traffic = measured_traffic(roof["kernel"], name, args.variant)

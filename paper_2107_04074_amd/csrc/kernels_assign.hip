@@ -6,18 +6,20 @@
 //                fit mode the bounds of Section 4; in Hamerly mode each row
 //                first runs the bound update and tests of Section 5.3 and is
 //                walked only when they fail.
-//  k_elkan       one Elkan step per row (Sections 5.1 and 5.2): Eq. (6) for
-//                l(i), guarded Eq. (7) for every u(i,j), the point test on
-//                s(a(i)) and the pair tests u(i,j) <= l(i) and
-//                cc(a(i),j) <= l(i), then the surviving similarities.
+//                In Elkan mode the row first runs Eq. (6) for l(i), the
+//                guarded Eq. (7) for every pair bound u(i,j), the point test
+//                on s(a(i)) and the pair tests u(i,j) <= l(i), cc(a(i),j) <=
+//                l(i) (Sections 5.1, 5.2); in Yin-Yang mode one bound per
+//                group of 32 centres (Section 5.5).  Rows with a surviving
+//                candidate are walked in full and get exact bounds.
 //
-// Row mapping: a group of G lanes (4 <= G <= 64, G divides 64) owns one row;
-// lane g of the group owns the centres 4*(g + G*r) + q, q < 4, r < R, i.e.
-// float4 chunk (g + G*r) of each centre-minor CT row (kp = 4*G*R floats).
-// For every stored entry (t, x) of the row the group reads CT row t with
-// coalesced float4 loads and every lane advances its 4R accumulators with
-// one FMA each, so every similarity is a sequential FMA chain over the
-// row's stored entries in storage order (the same chain in every kernel).
+// Row mapping: for k <= 64 a group of G = 4, 8 or 16 lanes owns one row and
+// lane g owns the float4 chunk g of each centre-minor CT row (row_sims);
+// for larger k one wave owns a row (row_walk: S sub-waves interleave the
+// row's entries, every lane owns R 16-byte chunks of VEC centres, read from
+// the FP32 copy or, with precision 2, from the FP16 copy).  Similarities are
+// FP32 FMA chains over stored entries in storage order; near ties are
+// re-decided in FP64 (dot64_group, the canonical order).
 #include <float.h>
 #include <limits.h>
 
@@ -363,6 +365,86 @@ __device__ __forceinline__ bool yinyang_prologue(const AssignArgs& A, int64_t ro
   return skip;
 }
 
+// Elkan prologue (Sections 5.1 and 5.2): Eq. (6) for l(i), the guarded
+// Eq. (7) for every pair bound u(i, j), the point test s(a) <= l(i) and the
+// pair tests u(i, j) <= l(i), cc(a, j) <= l(i) (the latter two dropped by the
+// simplified variant), first as is, then with l(i) tightened.  A row
+// without a surviving pair keeps its updated bounds and is not walked; a
+// walked row gets every similarity and hence every pair bound exactly.
+// The lanes hold the pair bounds in the walk's layout.  Returns true when
+// the row needs no walk.
+template <int G, int R, int VEC>
+__device__ __forceinline__ bool elkan_prologue(const AssignArgs& A, int64_t row, int prev,
+                                               int64_t beg, int64_t end, int gl, bool leader,
+                                               bool writer, unsigned long long& tight,
+                                               unsigned long long& saved) {
+  constexpr int NACC = R * VEC / 4;
+  const int k = A.k;
+  const int m = (int)(end - beg);
+  const double eta = (double)A.eta[row];
+  const double slack = 1.01 * (eta + A.delta_c);
+  const double rho32 = (double)(m + 3) * kU32 * (1.0 + eta) * 1.01 + slack + 1e-12;
+  const double mu = 4.0 * (double)(m + 2) * kU64 * (1.0 + eta) + 4.0 * A.delta_c + 1e-15;
+  double ld = lower_upd((double)A.l[row], A.pc[prev], A.ps[prev]) - 4e-15;
+  float4* uer4 = reinterpret_cast<float4*>(A.ue + (size_t)row * A.kp);
+  float4 uv[NACC];
+#pragma unroll
+  for (int q4 = 0; q4 < NACC; ++q4) {
+    const int r = (4 * q4) / VEC, q0 = (4 * q4) % VEC;
+    const int jb = VEC * (gl + G * r) + q0;
+    uv[q4] = uer4[jb / 4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int j = jb + q;
+      if (j < k) {
+        const double nu = upper_upd((double)f4get(uv[q4], q), A.pc[j], A.ps[j]) + 4e-15;
+        f4set(uv[q4], q, __double2float_ru(fmin(nu, 1.0)));
+      }
+    }
+  }
+  const double* Grow = A.Gm ? A.Gm + (size_t)prev * k : nullptr;
+  auto any_alive = [&](double lcur) -> bool {
+    const double M = lcur - mu;
+    const bool cc_ok = !A.simplified && Grow != nullptr && lcur > 0.0 && M > 0.0;
+    const double T = cc_ok ? cc_threshold(lcur, M) - 4e-15 : -3.0;
+    if (cc_ok && A.gmax[prev] <= T) return false;  // point test: no other centre can win
+    unsigned alive = 0u;
+#pragma unroll
+    for (int q4 = 0; q4 < NACC; ++q4) {
+      const int r = (4 * q4) / VEC, q0 = (4 * q4) % VEC;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int j = VEC * (gl + G * r) + q0 + q;
+        if (j < k && j != prev) {
+          const bool by_u = (lcur - (double)f4get(uv[q4], q)) >= mu;  // u(i, j) <= l(i)
+          const bool by_cc = cc_ok && (Grow[j] + A.delta_g <= T);     // cc(a, j) <= l(i)
+          alive |= (!by_u && !by_cc) ? 1u : 0u;
+        }
+      }
+    }
+    return group_or<G>(alive) != 0u;
+  };
+  bool alive = any_alive(ld);
+  if (alive && A.try_tighten) {
+    const float s32 = group_col_dot32<G>(A.ci, A.v, beg, end, A.CT, A.kp, prev, gl);
+    ld = fmax(ld, (double)s32 - rho32);
+    if (leader) tight += 1;
+    alive = any_alive(ld);
+    if (!alive && leader) saved += 1;
+  }
+  if (!alive) {
+    if (leader) A.l[row] = __double2float_rd(fmax(ld, -1.0));
+    if (writer) {
+#pragma unroll
+      for (int q4 = 0; q4 < NACC; ++q4) {
+        const int r = (4 * q4) / VEC, q0 = (4 * q4) % VEC;
+        uer4[(VEC * (gl + G * r) + q0) / 4] = uv[q4];
+      }
+    }
+  }
+  return !alive;
+}
+
 // After a walk: every Yin-Yang group bound becomes the largest computed
 // similarity of the group's centres other than the new assignment (plus the
 // error band, rounded up); -1 for a group with no other centre.  A group of
@@ -407,8 +489,8 @@ __device__ __forceinline__ void group_redecide(unsigned long long cm, const int3
   const int base = (int)(threadIdx.x & 63) - gl;  // first lane of the group
   for (;;) {
     const unsigned long long wave = __ballot(cm != 0ull);
-    const unsigned long long mine =
-        G == 64 ? wave : (wave >> base) & ((1ull << G) - 1ull);
+    unsigned long long mine = wave;
+    if constexpr (G < 64) mine = (wave >> base) & ((1ull << G) - 1ull);
     if (!mine) break;
     const int src = __builtin_ctzll(mine);
     const int lo = __shfl((int)(unsigned)cm, src, G);
@@ -517,11 +599,14 @@ __global__ __launch_bounds__(kBlock) void k_assign_csr(AssignArgs A) {
     }
     const int m = (int)(end - beg);
     const int prev = A.read_prev ? A.a[row] : -1;
-    if (MODE == kModeHamerly || MODE == kModeYinYang) {
+    if (MODE == kModeHamerly || MODE == kModeYinYang || MODE == kModeElkan) {
       const bool skip =
           MODE == kModeHamerly
               ? hamerly_prologue<G>(A, row, prev, beg, end, gl, leader, my_tight, my_saved)
-              : yinyang_prologue<G>(A, row, prev, beg, end, gl, leader, my_tight, my_saved);
+          : MODE == kModeYinYang
+              ? yinyang_prologue<G>(A, row, prev, beg, end, gl, leader, my_tight, my_saved)
+              : elkan_prologue<G, R, VEC>(A, row, prev, beg, end, gl, leader, lead_sub, my_tight,
+                                          my_saved);
       if (skip) {
         if constexpr (WAVE_ROW) next_window();
         continue;
@@ -617,7 +702,7 @@ __global__ __launch_bounds__(kBlock) void k_assign_csr(AssignArgs A) {
         }
       }
       if (A.uy) write_group_bounds<G, R, VEC>(A, row, acc, gl, abest, rho32, lead_sub);
-      if (MODE == kModeFitElkanInit && lead_sub) {
+      if ((MODE == kModeFitElkanInit || MODE == kModeElkan) && lead_sub) {
         float4* uer4 = reinterpret_cast<float4*>(A.ue + (size_t)row * A.kp);
 #pragma unroll
         for (int q4 = 0; q4 < NACC; ++q4) {
@@ -662,238 +747,6 @@ __global__ __launch_bounds__(kBlock) void k_assign_csr(AssignArgs A) {
     if (sh[3]) atomicAdd(&c->changed, sh[3]);
     if (sh[4]) atomicAdd(&c->tightened, sh[4]);
     if (sh[5]) atomicAdd(&c->tight_saved, sh[5]);
-  }
-}
-
-// ------------------------------------------------------------------------
-// k_elkan
-// ------------------------------------------------------------------------
-template <int R>
-__device__ __forceinline__ void set_slot(float4 (&acc)[R], int bit, float val) {
-#pragma unroll
-  for (int r = 0; r < R; ++r)
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-      if (bit == 4 * r + q) f4set(acc[r], q, val);
-}
-
-template <int G, int R>
-__global__ __launch_bounds__(kBlock) void k_elkan(ElkanArgs A) {
-  constexpr int GPB = kBlock / G;
-  // 128-byte lines in one CT row: a row walk costs about this many lines per
-  // stored entry, one surviving pair about one
-  constexpr int kLines = (4 * G * R) / 32;
-  const int gl = threadIdx.x & (G - 1);
-  const int gib = threadIdx.x / G;
-  const int gbase = (int)(threadIdx.x & 63) & ~(G - 1);
-  const unsigned long long gmask = (G == 64) ? ~0ull : ((1ull << G) - 1ull);
-  __shared__ unsigned long long sh_sims, sh_tight, sh_rechecks, sh_rows, sh_nnz, sh_changed;
-  if (threadIdx.x == 0) {
-    sh_sims = 0;
-    sh_tight = 0;
-    sh_rechecks = 0;
-    sh_rows = 0;
-    sh_nnz = 0;
-    sh_changed = 0;
-  }
-  __syncthreads();
-  unsigned long long my_sims = 0, my_tight = 0, my_rechecks = 0, my_rows = 0, my_nnz = 0,
-                     my_changed = 0;
-  const float4* CT4 = reinterpret_cast<const float4*>(A.CT);
-  const int kp4 = A.kp >> 2;
-  const int k = A.k;
-
-  for (int64_t row = (int64_t)blockIdx.x * GPB + gib; row < A.n;
-       row += (int64_t)gridDim.x * GPB) {
-    const int64_t beg = A.rp[row], end = A.rp[row + 1];
-    const int m = (int)(end - beg);
-    const int prev = A.a[row];
-    const double eta = (double)A.eta[row];
-    const double slack = 1.01 * (eta + A.delta_c);
-    const double eps = (double)(m + 3) * kU32 * (1.0 + eta) * 1.01;
-    const double rho32 = eps + slack + 1e-12;
-    const double rho64 = (double)(m + 2) * kU64 * (1.0 + eta) * 1.01 + slack + 1e-15;
-    // prune margin: keeps the FP64 re-decision of every pruned pair on the
-    // side the bounds prove
-    const double mu = 4.0 * (double)(m + 2) * kU64 * (1.0 + eta) + 4.0 * A.delta_c + 1e-15;
-
-    // Eq. (6) for l(i), guarded Eq. (7) for every u(i, j)
-    double ld = lower_upd((double)A.l[row], A.pc[prev], A.ps[prev]) - 4e-15;
-    float4* ue4 = reinterpret_cast<float4*>(A.ue + (size_t)row * A.kp);
-    float4 uv[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      uv[r] = ue4[gl + G * r];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int j = 4 * (gl + G * r) + q;
-        if (j < k) {
-          const double nu = upper_upd((double)f4get(uv[r], q), A.pc[j], A.ps[j]) + 4e-15;
-          f4set(uv[r], q, __double2float_ru(fmin(nu, 1.0)));
-        }
-      }
-    }
-
-    const double* Grow = A.G + (size_t)prev * k;
-    auto alive_mask = [&](double lcur) -> unsigned long long {
-      const double M = lcur - mu;
-      const bool cc_ok = !A.simplified && lcur > 0.0 && M > 0.0;
-      const double T = cc_ok ? cc_threshold(lcur, M) - 4e-15 : -3.0;
-      if (cc_ok && A.gmax[prev] <= T) return 0ull;  // s(a) test: skip the point
-      unsigned long long mask = 0ull;
-#pragma unroll
-      for (int r = 0; r < R; ++r)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int j = 4 * (gl + G * r) + q;
-          if (j < k && j != prev) {
-            const bool by_u = (lcur - (double)f4get(uv[r], q)) >= mu;   // u(i,j) <= l(i)
-            const bool by_cc = cc_ok && (Grow[j] + A.delta_g <= T);     // cc(a,j) <= l(i)
-            if (!by_u && !by_cc) mask |= 1ull << (4 * r + q);
-          }
-        }
-      return mask;
-    };
-
-    unsigned long long mask = alive_mask(ld);
-    int nalive = group_sum<G>((int)__popcll(mask));
-    int abest = prev;
-    if (nalive > 0) {
-      // tighten l(i) with one column of CT
-      const float sa = group_col_dot32<G>(A.ci, A.v, beg, end, A.CT, A.kp, prev, gl);
-      ld = fmax(ld, (double)sa - rho32);
-      if (gl == 0) my_tight += 1;
-      mask = alive_mask(ld);
-      nalive = group_sum<G>((int)__popcll(mask));
-      if (nalive > 0) {
-        int prev_bit = -1;
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-          const int rel = prev - 4 * (gl + G * r);
-          if (rel >= 0 && rel < 4) prev_bit = 4 * r + rel;
-        }
-        float4 acc[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) acc[r] = make_float4(0.f, 0.f, 0.f, 0.f);
-        unsigned long long comp = mask;
-        if (nalive <= kLines) {
-          // few survivors: one column gather per surviving pair
-          unsigned long long my = mask;
-          for (int it = 0; it < nalive; ++it) {
-            const unsigned long long gb = (__ballot(my != 0ull) >> gbase) & gmask;
-            const int owner = __ffsll((long long)gb) - 1;
-            int bit = (gl == owner) ? (__ffsll((long long)my) - 1) : 0;
-            bit = __shfl(bit, owner, G);
-            const int j = 4 * (owner + G * (bit >> 2)) + (bit & 3);
-            const float sj = group_col_dot32<G>(A.ci, A.v, beg, end, A.CT, A.kp, j, gl);
-            if (gl == owner) {
-              set_slot<R>(acc, bit, sj);
-              my &= my - 1ull;
-            }
-          }
-          if (prev_bit >= 0) {
-            set_slot<R>(acc, prev_bit, sa);
-            comp |= 1ull << prev_bit;
-          }
-        } else {
-          // many survivors: walk the row once for the chunks that hold them
-          if (prev_bit >= 0) comp |= 1ull << prev_bit;
-          unsigned need = 0u;
-#pragma unroll
-          for (int r = 0; r < R; ++r)
-            if ((comp >> (4 * r)) & 0xFull) need |= 1u << r;
-          row_sims<G, R, true>(A.ci, A.v, beg, end, CT4, kp4, gl, need, acc);
-          if (gl == 0) {
-            my_rows += 1;
-            my_nnz += (unsigned long long)m;
-          }
-        }
-        my_sims += (unsigned long long)__builtin_popcountll(mask);
-
-        float b = -INFINITY, s2 = -INFINITY;
-        int bj = INT_MAX;
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const int bit = 4 * r + q;
-            if ((comp >> bit) & 1ull) {
-              const int j = 4 * (gl + G * r) + q;
-              const float sv = f4get(acc[r], q);
-              if (better32(sv, j, b, bj, prev)) {
-                s2 = fmaxf(s2, b);
-                b = sv;
-                bj = j;
-              } else {
-                s2 = fmaxf(s2, sv);
-              }
-            }
-          }
-        group_top2<G>(b, bj, s2, prev);
-        abest = bj;
-        bool rechecked = false;
-        double lo;
-        if ((double)b - (double)s2 <= 2.0 * eps) {
-          const double thr = (double)b - 2.0 * eps - 1e-12;
-          double cb = -INFINITY;
-          int cj = INT_MAX;
-          unsigned long long cm = 0ull;
-#pragma unroll
-          for (int r = 0; r < R; ++r)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              const int bit = 4 * r + q;
-              if (((comp >> bit) & 1ull) && (double)f4get(acc[r], q) >= thr) cm |= 1ull << bit;
-            }
-          group_redecide<G, 4>(cm, A.ci, A.v, beg, end, A.C64, A.d, gl, prev, cb, cj);
-          abest = cj;
-          rechecked = true;
-          lo = cb - rho64;
-        } else {
-          lo = (double)b - rho32;
-        }
-        ld = (abest == prev) ? fmax(ld, lo) : lo;
-        // computed similarities become exact upper bounds
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const int bit = 4 * r + q;
-            if ((comp >> bit) & 1ull)
-              f4set(uv[r], q, __double2float_ru(fmin((double)f4get(acc[r], q) + rho32, 1.0)));
-          }
-        if (gl == 0 && rechecked) my_rechecks += 1;
-      }
-    }
-
-#pragma unroll
-    for (int r = 0; r < R; ++r) ue4[gl + G * r] = uv[r];
-    if (gl == 0) {
-      A.l[row] = __double2float_rd(fmax(ld, -1.0));
-      A.a[row] = abest;
-      my_changed += (abest != prev) ? 1ull : 0ull;
-    }
-  }
-
-  if (my_sims) atomicAdd(&sh_sims, my_sims);
-  if (my_tight) atomicAdd(&sh_tight, my_tight);
-  if (my_rechecks) atomicAdd(&sh_rechecks, my_rechecks);
-  if (my_rows) {
-    atomicAdd(&sh_rows, my_rows);
-    atomicAdd(&sh_nnz, my_nnz);
-  }
-  if (my_changed) atomicAdd(&sh_changed, my_changed);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    Counters* c = counter_slot(A.cnt);
-    if (sh_sims + sh_tight) atomicAdd(&c->sims, sh_sims + sh_tight);
-    if (sh_tight) atomicAdd(&c->tightened, sh_tight);
-    if (sh_rechecks) atomicAdd(&c->rechecks, sh_rechecks);
-    if (sh_changed) atomicAdd(&c->changed, sh_changed);
-    if (sh_rows) {
-      atomicAdd(&c->rows_done, sh_rows);
-      atomicAdd(&c->nnz_done, sh_nnz);
-    }
   }
 }
 
@@ -1022,36 +875,9 @@ hipError_t launch_assign(const AssignArgs& A, int mode, hipStream_t s) {
   if (mode == kModeFit) return launch_assign_mode<kModeFit>(A, s);
   if (mode == kModeHamerly) return launch_assign_mode<kModeHamerly>(A, s);
   if (mode == kModeYinYang) return launch_assign_mode<kModeYinYang>(A, s);
+  if (mode == kModeElkan) return launch_assign_mode<kModeElkan>(A, s);
   return launch_assign_mode<kModeFitElkanInit>(A, s);
 }
 
-hipError_t launch_elkan(const ElkanArgs& A, hipStream_t s) {
-  const Geometry g = pick_geometry(A.k);
-  if (g.G == 0 || g.kp != A.kp) return hipErrorInvalidValue;
-  const int gpb = kBlock / g.G;
-  int64_t blocks = (A.n + gpb - 1) / gpb;
-  if (blocks > kMaxGridBlocks) blocks = kMaxGridBlocks;
-  if (blocks < 1) blocks = 1;
-  const dim3 grid((unsigned)blocks), block(kBlock);
-#define SKM_CASE(GG, RR)                                              \
-  case GG * 100 + RR:                                                 \
-    hipLaunchKernelGGL((k_elkan<GG, RR>), grid, block, 0, s, A);      \
-    break;
-  switch (g.G * 100 + g.R) {
-    SKM_CASE(4, 1)
-    SKM_CASE(8, 1)
-    SKM_CASE(16, 1)
-    SKM_CASE(32, 1)
-    SKM_CASE(64, 1)
-    SKM_CASE(64, 2)
-    SKM_CASE(64, 4)
-    SKM_CASE(64, 8)
-    SKM_CASE(64, 16)
-    default:
-      return hipErrorInvalidValue;
-  }
-#undef SKM_CASE
-  return hipGetLastError();
-}
 
 }  // namespace skm

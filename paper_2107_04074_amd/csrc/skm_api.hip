@@ -2,14 +2,15 @@
 // iteration driver behind the C ABI declared in include/skm.h.
 //
 // One fit runs, per assignment step (Section 5 outline of the paper):
-//   step 1          exhaustive similarities for every row -> a, l, u
-//   later steps     Lloyd: exhaustive again; Hamerly: bound update + tests
-//                   (k_hamerly) then exhaustive similarities for the rows
-//                   that failed them; Elkan: k_elkan per row
+//   step 1          exhaustive similarities for every row -> a, l, u (or the
+//                   warm-start arrays of a seeding)
+//   later steps     Lloyd: exhaustive again; Hamerly, Yin-Yang, Elkan: the
+//                   bound update and tests of the variant per row, then the
+//                   full similarity walk of the rows that failed them
 //   sync            read the changed count; stop when it is zero
 //   centre step     fixed-point sums of the changed rows, renormalisation,
-//                   movement p(j), FP32 transpose, centre-centre products
-//                   (Elkan and Hamerly only)
+//                   movement p(j), FP32 (and FP16) transpose, centre-centre
+//                   products (full Elkan and Hamerly only)
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
@@ -938,7 +939,7 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
       {
       const bool exhaustive = (t == 0) || variant == SKM_LLOYD;
       if (ev0) SKM_HIP(hipEventRecord(ev0, s));
-      if (exhaustive || !P.elkan) {
+      {
         AssignArgs A{};
         A.rp = X->row_ptr;
         A.ci = X->col_idx;
@@ -963,7 +964,9 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
         A.ps = ps;
         A.mm = mm;
         A.gmax = gmax;
-        A.simplified = variant == SKM_SIMP_HAMERLY;
+        A.simplified = variant == SKM_SIMP_HAMERLY || variant == SKM_SIMP_ELKAN;
+        A.Gm = G;
+        A.delta_g = delta_g;
         A.bound_form = o.bound_form;
         A.uy = uy;
         A.ng = P.ng;
@@ -973,32 +976,10 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
         // row walk about kp/32; keep tightening while it prunes often enough
         A.try_tighten = (t <= 2 || tight_rate >= 0.2 || t % 4 == 0) ? 1 : 0;
         const int mode = exhaustive ? ((t == 0 && P.elkan) ? kModeFitElkanInit : kModeFit)
-                                    : (P.yy ? kModeYinYang : kModeHamerly);
+                                    : P.elkan ? kModeElkan
+                                    : P.yy    ? kModeYinYang
+                                              : kModeHamerly;
         SKM_HIP(launch_assign(A, mode, s));
-      } else {
-        ElkanArgs E{};
-        E.rp = X->row_ptr;
-        E.ci = X->col_idx;
-        E.v = X->val;
-        E.CT = CT;
-        E.C64 = C64;
-        E.d = d;
-        E.k = k;
-        E.kp = P.kp;
-        E.n = n;
-        E.a = assign_out;
-        E.l = l;
-        E.ue = ue;
-        E.eta = eta;
-        E.pc = pc;
-        E.ps = ps;
-        E.G = G;
-        E.gmax = gmax;
-        E.delta_c = delta_c;
-        E.delta_g = delta_g;
-        E.simplified = variant == SKM_SIMP_ELKAN;
-        E.cnt = cnt;
-        SKM_HIP(launch_elkan(E, s));
       }
       if (ev1) SKM_HIP(hipEventRecord(ev1, s));
       SKM_HIP(hipMemcpyAsync(hm, cnt, sizeof(HostMirror), hipMemcpyDeviceToHost, s));

@@ -63,7 +63,8 @@ enum AssignMode {
   kModeFit = 1,           // exhaustive step of a fit: a, l, u
   kModeFitElkanInit = 2,  // first step of an Elkan fit: also u(i, j) for all j
   kModeHamerly = 3,       // Hamerly step: bound update and tests, walk if needed
-  kModeYinYang = 4        // Yin-Yang step: group bounds, tests, walk if needed
+  kModeYinYang = 4,       // Yin-Yang step: group bounds, tests, walk if needed
+  kModeElkan = 5          // Elkan step: pair bounds, point and pair tests, walk if needed
 };
 
 struct AssignArgs {
@@ -97,6 +98,9 @@ struct AssignArgs {
   int32_t simplified;
   int32_t bound_form;
   int32_t try_tighten;
+  // Elkan: k x k centre inner products (full variant) and their bound
+  const double* Gm;
+  double delta_g;
   // Yin-Yang: n x ng group upper bounds (also written by the first step's
   // fit mode when set) and the cosine/sine of each group's largest movement
   float* uy;
@@ -106,27 +110,6 @@ struct AssignArgs {
 };
 constexpr int kYYGroup = 32;  // centres per Yin-Yang group
 
-struct ElkanArgs {
-  const int64_t* rp;
-  const int32_t* ci;
-  const float* v;
-  const float* CT;
-  const double* C64;
-  int64_t d;
-  int32_t k, kp;
-  int64_t n;
-  int32_t* a;
-  float* l;
-  float* ue;
-  const float* eta;
-  const double* pc;
-  const double* ps;
-  const double* G;      // k x k centre inner products
-  const double* gmax;   // per centre max_{j != a} G + delta_G
-  double delta_c, delta_g;
-  int32_t simplified;
-  Counters* cnt;
-};
 
 struct DenseSimArgs {
   const void* X;              // rows: bf16 (padded copy) or f32 (caller), n x ldx
@@ -242,7 +225,7 @@ hipError_t launch_dense_row_eta(const float* X, int64_t ldx, int64_t n, int64_t 
 
 // ---- launchers (kernels_assign.hip) ----
 hipError_t launch_assign(const AssignArgs& A, int mode, hipStream_t s);
-hipError_t launch_elkan(const ElkanArgs& A, hipStream_t s);
+
 
 // ---- launchers (kernels_update.hip) ----
 hipError_t launch_row_eta(const int64_t* rp, const float* v, int64_t n, float* eta,
