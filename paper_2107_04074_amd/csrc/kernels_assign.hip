@@ -149,7 +149,7 @@ __device__ __forceinline__ float row_sims(const int32_t* __restrict__ ci,
 // (the order is covered by the error bound of the re-decision).
 template <int R>
 struct WalkBatch {
-  static constexpr int U = (R >= 8) ? 1 : 8 / R;
+  static constexpr int U = (R >= 4) ? 1 : 4 / R;
 };
 
 __device__ __forceinline__ int lane_int(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
@@ -277,27 +277,35 @@ __device__ __forceinline__ float row_walk(const int32_t* __restrict__ ci,
 // ------------------------------------------------------------------------
 // k_assign_csr
 // ------------------------------------------------------------------------
+// Per-row inputs of the bound tests: previous assignment, l(i), u(i) and the
+// row's norm deviation (loaded one row ahead in the one-row-per-wave layout).
+struct RowIn {
+  int prev;
+  float l, u, eta;
+};
+
 // Hamerly mode prologue (Sections 5.3 / 5.4): Eq. (6) for l(i), the guarded
 // Eq. (7) with p'(a) = min_{j != a} p(j) (or Eq. (9)) for u(i), the tests
 // l >= u and l >= s(a), and the tightening of l(i).  Returns true when the
 // row needs no similarity walk; the bounds are then already stored.
 template <int G>
-__device__ __forceinline__ bool hamerly_prologue(const AssignArgs& A, int64_t row, int prev,
+__device__ __forceinline__ bool hamerly_prologue(const AssignArgs& A, int64_t row, const RowIn& ri,
                                                  int64_t beg, int64_t end, int gl, bool leader,
-                                                 unsigned long long& tight,
+                                                 int tighten, unsigned long long& tight,
                                                  unsigned long long& saved) {
+  const int prev = ri.prev;
   const int m = (int)(end - beg);
-  const double eta = (double)A.eta[row];
+  const double eta = (double)ri.eta;
   const double slack = 1.01 * (eta + A.delta_c);
   const double rho32 = (double)(m + 3) * kU32 * (1.0 + eta) * 1.01 + slack + 1e-12;
   // prune margin: keeps the FP64 re-decision of every pruned pair on the
   // side the bounds prove
   const double mu = 4.0 * (double)(m + 2) * kU64 * (1.0 + eta) + 4.0 * A.delta_c + 1e-15;
   const MoveMin mm = *A.mm;
-  double ld = lower_upd((double)A.l[row], A.pc[prev], A.ps[prev]) - 4e-15;
+  double ld = lower_upd((double)ri.l, A.pc[prev], A.ps[prev]) - 4e-15;
   const double pcx = (prev == mm.idx1) ? mm.pc2 : mm.pc1;
   const double psx = (prev == mm.idx1) ? mm.ps2 : mm.ps1;
-  const double u0 = fmin(1.0, fmax(-1.0, (double)A.u[row]));
+  const double u0 = fmin(1.0, fmax(-1.0, (double)ri.u));
   double ud;
   if (A.bound_form == 1 && u0 >= 0.0 && pcx >= 0.0)
     ud = u0 + sqrt((1.0 - u0) * (1.0 + u0)) * psx;  // Eq. (9)
@@ -311,7 +319,7 @@ __device__ __forceinline__ bool hamerly_prologue(const AssignArgs& A, int64_t ro
     return !A.simplified && lcur > 0.0 && M > 0.0 && smax <= cc_threshold(lcur, M) - 4e-15;
   };
   bool skip = pruned(ld);
-  if (!skip && A.try_tighten) {
+  if (!skip && tighten) {
     const float s32 = group_col_dot32<G>(A.ci, A.v, beg, end, A.CT, A.kp, prev, gl);
     ld = fmax(ld, (double)s32 - rho32);
     if (leader) tight += 1;
@@ -331,16 +339,17 @@ __device__ __forceinline__ bool hamerly_prologue(const AssignArgs& A, int64_t ro
 // as is, then with l(i) tightened.  Lanes share the groups.  Returns true
 // when the row needs no walk; the bounds are then stored.
 template <int G>
-__device__ __forceinline__ bool yinyang_prologue(const AssignArgs& A, int64_t row, int prev,
+__device__ __forceinline__ bool yinyang_prologue(const AssignArgs& A, int64_t row, const RowIn& ri,
                                                  int64_t beg, int64_t end, int gl, bool leader,
-                                                 unsigned long long& tight,
+                                                 int tighten, unsigned long long& tight,
                                                  unsigned long long& saved) {
+  const int prev = ri.prev;
   const int m = (int)(end - beg);
-  const double eta = (double)A.eta[row];
+  const double eta = (double)ri.eta;
   const double slack = 1.01 * (eta + A.delta_c);
   const double rho32 = (double)(m + 3) * kU32 * (1.0 + eta) * 1.01 + slack + 1e-12;
   const double mu = 4.0 * (double)(m + 2) * kU64 * (1.0 + eta) + 4.0 * A.delta_c + 1e-15;
-  double ld = lower_upd((double)A.l[row], A.pc[prev], A.ps[prev]) - 4e-15;
+  double ld = lower_upd((double)ri.l, A.pc[prev], A.ps[prev]) - 4e-15;
   float* uyr = A.uy + (size_t)row * A.ng;
   double umax = -INFINITY;
   for (int f = gl; f < A.ng; f += G) {
@@ -350,7 +359,7 @@ __device__ __forceinline__ bool yinyang_prologue(const AssignArgs& A, int64_t ro
 #pragma unroll
   for (int off = G / 2; off >= 1; off >>= 1) umax = fmax(umax, __shfl_xor(umax, off, G));
   bool skip = ld - umax >= mu;
-  if (!skip && A.try_tighten) {
+  if (!skip && tighten) {
     const float s32 = group_col_dot32<G>(A.ci, A.v, beg, end, A.CT, A.kp, prev, gl);
     ld = fmax(ld, (double)s32 - rho32);
     if (leader) tight += 1;
@@ -374,18 +383,19 @@ __device__ __forceinline__ bool yinyang_prologue(const AssignArgs& A, int64_t ro
 // The lanes hold the pair bounds in the walk's layout.  Returns true when
 // the row needs no walk.
 template <int G, int R, int VEC>
-__device__ __forceinline__ bool elkan_prologue(const AssignArgs& A, int64_t row, int prev,
+__device__ __forceinline__ bool elkan_prologue(const AssignArgs& A, int64_t row, const RowIn& ri,
                                                int64_t beg, int64_t end, int gl, bool leader,
-                                               bool writer, unsigned long long& tight,
+                                               int tighten, bool writer, unsigned long long& tight,
                                                unsigned long long& saved) {
   constexpr int NACC = R * VEC / 4;
   const int k = A.k;
+  const int prev = ri.prev;
   const int m = (int)(end - beg);
-  const double eta = (double)A.eta[row];
+  const double eta = (double)ri.eta;
   const double slack = 1.01 * (eta + A.delta_c);
   const double rho32 = (double)(m + 3) * kU32 * (1.0 + eta) * 1.01 + slack + 1e-12;
   const double mu = 4.0 * (double)(m + 2) * kU64 * (1.0 + eta) + 4.0 * A.delta_c + 1e-15;
-  double ld = lower_upd((double)A.l[row], A.pc[prev], A.ps[prev]) - 4e-15;
+  double ld = lower_upd((double)ri.l, A.pc[prev], A.ps[prev]) - 4e-15;
   float4* uer4 = reinterpret_cast<float4*>(A.ue + (size_t)row * A.kp);
   float4 uv[NACC];
 #pragma unroll
@@ -425,7 +435,7 @@ __device__ __forceinline__ bool elkan_prologue(const AssignArgs& A, int64_t row,
     return group_or<G>(alive) != 0u;
   };
   bool alive = any_alive(ld);
-  if (alive && A.try_tighten) {
+  if (alive && tighten) {
     const float s32 = group_col_dot32<G>(A.ci, A.v, beg, end, A.CT, A.kp, prev, gl);
     ld = fmax(ld, (double)s32 - rho32);
     if (leader) tight += 1;
@@ -541,6 +551,9 @@ __global__ __launch_bounds__(kBlock) void k_assign_csr(AssignArgs A) {
   // sub-wave holds the same values; lane 0 writes)
   const bool leader = WAVE_ROW ? (threadIdx.x & 63) == 0 : gl == 0;
   const bool lead_sub = WAVE_ROW ? (int)(threadIdx.x & 63) < G : true;
+  // a fit that has stopped leaves the steps queued after it without work
+  if (A.ctl && A.ctl->stop) return;
+  const int tighten = A.ctl ? A.ctl->tighten : A.try_tighten;
   __shared__ unsigned long long sh[6];
   if (threadIdx.x < 6) sh[threadIdx.x] = 0;
   __syncthreads();
@@ -555,6 +568,10 @@ __global__ __launch_bounds__(kBlock) void k_assign_csr(AssignArgs A) {
   // starts without waiting for them
   const int64_t rstride = (int64_t)gridDim.x * GPB;
   const int wl = threadIdx.x & 63;
+  constexpr bool kBounded = MODE == kModeHamerly || MODE == kModeYinYang || MODE == kModeElkan;
+  // row pointers of the next row as loaded (made wave-uniform only when
+  // needed, so that nothing waits for them at the top of a row)
+  int64_t nbr = 0, ner = 0;
   int64_t nbeg = 0, nend = 0;
   int wc = 0;
   float wx = 0.f;
@@ -563,6 +580,8 @@ __global__ __launch_bounds__(kBlock) void k_assign_csr(AssignArgs A) {
            (uint32_t)__builtin_amdgcn_readfirstlane((int)x);
   };
   auto next_window = [&]() {
+    nbeg = uniform64(nbr);
+    nend = uniform64(ner);
     wc = 0;
     wx = 0.f;
     if (nbeg + wl < nend) {
@@ -570,11 +589,21 @@ __global__ __launch_bounds__(kBlock) void k_assign_csr(AssignArgs A) {
       wx = A.v[nbeg + wl];
     }
   };
+  auto load_in = [&](int64_t r) -> RowIn {
+    RowIn x{-1, 0.f, 0.f, 0.f};
+    if (A.read_prev) x.prev = A.a[r];
+    if constexpr (kBounded) x.l = A.l[r];
+    if constexpr (MODE == kModeHamerly) x.u = A.u[r];
+    if constexpr (MODE != kModeAssign) x.eta = A.eta[r];
+    return x;
+  };
+  RowIn nin{-1, 0.f, 0.f, 0.f};
   if constexpr (WAVE_ROW) {
     const int64_t r0 = (int64_t)blockIdx.x * GPB + gib;
     if (r0 < A.n_rows) {
-      nbeg = uniform64(A.rp[r0]);
-      nend = uniform64(A.rp[r0 + 1]);
+      nbr = A.rp[r0];
+      ner = A.rp[r0 + 1];
+      nin = load_in(r0);
       next_window();
     }
   }
@@ -583,30 +612,36 @@ __global__ __launch_bounds__(kBlock) void k_assign_csr(AssignArgs A) {
     int64_t beg, end;
     int c0 = 0;
     float x0 = 0.f;
+    RowIn ri;
     if constexpr (WAVE_ROW) {
       beg = nbeg;
       end = nend;
       c0 = wc;
       x0 = wx;
-      nbeg = nend = 0;
+      ri = nin;
+      nbr = ner = 0;
       if (row + rstride < A.n_rows) {
-        nbeg = uniform64(A.rp[row + rstride]);
-        nend = uniform64(A.rp[row + rstride + 1]);
+        nbr = A.rp[row + rstride];
+        ner = A.rp[row + rstride + 1];
+        nin = load_in(row + rstride);
       }
     } else {
       beg = A.rp[row];
       end = A.rp[row + 1];
+      ri = load_in(row);
     }
     const int m = (int)(end - beg);
-    const int prev = A.read_prev ? A.a[row] : -1;
-    if (MODE == kModeHamerly || MODE == kModeYinYang || MODE == kModeElkan) {
+    const int prev = ri.prev;
+    if constexpr (kBounded) {
       const bool skip =
           MODE == kModeHamerly
-              ? hamerly_prologue<G>(A, row, prev, beg, end, gl, leader, my_tight, my_saved)
+              ? hamerly_prologue<G>(A, row, ri, beg, end, gl, leader, tighten, my_tight,
+                                    my_saved)
           : MODE == kModeYinYang
-              ? yinyang_prologue<G>(A, row, prev, beg, end, gl, leader, my_tight, my_saved)
-              : elkan_prologue<G, R, VEC>(A, row, prev, beg, end, gl, leader, lead_sub, my_tight,
-                                          my_saved);
+              ? yinyang_prologue<G>(A, row, ri, beg, end, gl, leader, tighten, my_tight,
+                                    my_saved)
+              : elkan_prologue<G, R, VEC>(A, row, ri, beg, end, gl, leader, tighten, lead_sub,
+                                          my_tight, my_saved);
       if (skip) {
         if constexpr (WAVE_ROW) next_window();
         continue;
@@ -685,7 +720,7 @@ __global__ __launch_bounds__(kBlock) void k_assign_csr(AssignArgs A) {
     } else {
       // bounds on true cosines (Section 4): l(i) <= cos(x, c_a),
       // u(i) >= max_{j != a} cos(x, c_j)
-      const double eta = (double)A.eta[row];
+      const double eta = (double)ri.eta;
       const double slack = 1.01 * (eta + A.delta_c);
       const double rho32 = eps + slack + 1e-12;
       if (leader) {

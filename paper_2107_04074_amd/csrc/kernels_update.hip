@@ -347,10 +347,15 @@ __global__ __launch_bounds__(kBlock) void k_gram_partial(const double* __restric
                                                          const int32_t* __restrict__ dirty,
                                                          int force_all, double* __restrict__ part,
                                                          int64_t slice_len,
-                                                         Persist* __restrict__ per) {
+                                                         Persist* __restrict__ per,
+                                                         const StepCtl* __restrict__ ctl) {
   __shared__ double As[kGramT][kGramK + 1];
   __shared__ double Bs[kGramT][kGramK + 1];
   __shared__ int any;
+  if (ctl) {
+    if (ctl->gram_mode != 1) return;
+    force_all = ctl->gram_force;
+  }
   const int nt = (k + kGramT - 1) / kGramT;
   int idx = blockIdx.x, ta = 0;
   while (idx >= nt - ta) {
@@ -449,8 +454,10 @@ __global__ __launch_bounds__(kBlock) void k_gram_partial(const double* __restric
 __global__ __launch_bounds__(kBlock) void k_gram_finalize(const double* __restrict__ part,
                                                           int32_t k, int nslice, double delta_g,
                                                           double* __restrict__ G,
-                                                          double* __restrict__ gmax) {
+                                                          double* __restrict__ gmax,
+                                                          const StepCtl* __restrict__ ctl) {
   __shared__ double sh[kBlock / 64];
+  if (ctl && ctl->gram_mode != 1) return;
   const int a = blockIdx.x;
   const int64_t kk = (int64_t)k * k;
   double m = -INFINITY;
@@ -491,8 +498,10 @@ __global__ __launch_bounds__(kBlock) void k_gram_carry(double* __restrict__ G, i
                                                        const double* __restrict__ pc,
                                                        const double* __restrict__ ps,
                                                        double delta_g,
-                                                       double* __restrict__ gmax) {
+                                                       double* __restrict__ gmax,
+                                                       const StepCtl* __restrict__ ctl) {
   __shared__ double sh[kBlock / 64];
+  if (ctl && ctl->gram_mode != 2) return;
   const int a = blockIdx.x;
   const double pa = pc[a], sa = ps[a];
   double m = -INFINITY;
@@ -533,6 +542,95 @@ __global__ void k_fill_f64(double* p, int64_t count, double value) {
 __global__ void k_fill_i32(int32_t* p, int64_t count, int32_t value) {
   const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (e < count) p[e] = value;
+}
+
+__global__ void k_step_init(StepCtl* ctl, int gram_on, int warm, double tight_min) {
+  StepCtl c{};
+  c.gram_on = gram_on;
+  if (warm && gram_on) {  // the warm start's centre update: exact, every tile
+    c.gram_mode = 1;
+    c.gram_force = 1;
+    c.gram_updates = 1;
+  }
+  c.tighten = 1;
+  c.tight_gap = 4;
+  c.tight_rate = 1.0;
+  c.tight_min = tight_min;
+  *ctl = c;
+}
+
+// One wave.  Sums the step's counter slots into its record; a step that
+// changed no assignment stops the fit (the kernels of later queued steps
+// then do nothing or find nothing to do).  Otherwise it decides whether the
+// coming centre update recomputes the centre-centre products (the first two
+// updates, after three carried ones, or when more than 5% of the rows moved)
+// and whether step t + 1 tightens: always at the first three steps and while
+// the last measured pruning rate of tightening reaches tight_min; after a
+// step whose tightening fell below it, the next probe comes tight_gap steps
+// later and the gap doubles (at most 64).
+__global__ void k_step_end(const Counters* __restrict__ cnt, StepCtl* __restrict__ ctl,
+                           StepRec* __restrict__ rec, const Persist* __restrict__ per, int32_t t,
+                           int64_t n) {
+  const int i = threadIdx.x;
+  if (ctl->stop) {
+    if (i == 0) rec->valid = 0;
+    return;
+  }
+  unsigned long long v[7];
+  {
+    const Counters& c = cnt[i];
+    v[0] = c.changed;
+    v[1] = c.sims;
+    v[2] = c.rechecks;
+    v[3] = c.tightened;
+    v[4] = c.tight_saved;
+    v[5] = c.rows_done;
+    v[6] = c.nnz_done;
+  }
+#pragma unroll
+  for (int q = 0; q < 7; ++q)
+    for (int off = 32; off >= 1; off >>= 1) v[q] += __shfl_xor(v[q], off, 64);
+  if (i != 0) return;
+  StepRec r{};
+  r.changed = v[0];
+  r.sims = v[1];
+  r.rechecks = v[2];
+  r.tightened = v[3];
+  r.tight_saved = v[4];
+  r.rows_done = v[5];
+  r.nnz_done = v[6];
+  r.objective = per->objective;
+  r.valid = 1;
+  *rec = r;
+  StepCtl c = *ctl;
+  if (r.changed == 0) {
+    c.stop = 1;
+    c.gram_mode = 0;
+    *ctl = c;
+    return;
+  }
+  if (c.gram_on) {
+    const bool exact = gram_exact_step(c.gram_updates, c.gram_since_exact,
+                                       (int64_t)r.changed, n);
+    c.gram_mode = exact ? 1 : 2;
+    // after carried updates every tile's partial products are stale
+    c.gram_force = (c.gram_updates == 0 || c.gram_since_exact > 0) ? 1 : 0;
+    c.gram_since_exact = exact ? 0 : c.gram_since_exact + 1;
+    c.gram_updates += 1;
+  }
+  const bool was_on = c.tighten != 0;
+  if (r.tightened > 0) c.tight_rate = (double)r.tight_saved / (double)r.tightened;
+  if (t + 1 <= 2 || c.tight_rate >= c.tight_min) {
+    c.tighten = 1;
+    c.tight_gap = 4;
+  } else {
+    if (was_on) {
+      c.tight_next = t + c.tight_gap;
+      c.tight_gap = c.tight_gap < 32 ? 2 * c.tight_gap : 64;
+    }
+    c.tighten = (t + 1 >= c.tight_next) ? 1 : 0;
+  }
+  *ctl = c;
 }
 
 unsigned blocks_for(int64_t count) {
@@ -631,22 +729,35 @@ void gram_slicing(int32_t k, int64_t d, int* nslice, int64_t* slice_len) {
 
 hipError_t launch_gram(const double* C64, int32_t k, int64_t d, const int32_t* dirty,
                        int force_all, double* part, int nslice, int64_t slice_len, double* G,
-                       double* gmax, double delta_g, Persist* per, hipStream_t s) {
+                       double* gmax, double delta_g, Persist* per, hipStream_t s,
+                       const StepCtl* ctl) {
   const int nt = (k + kGramT - 1) / kGramT;
   const dim3 grid((unsigned)(nt * (nt + 1) / 2), (unsigned)nslice);
   hipLaunchKernelGGL(k_gram_partial, grid, dim3(kBlock), 0, s, C64, k, d, dirty, force_all, part,
-                     slice_len, per);
+                     slice_len, per, ctl);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_gram_finalize, dim3((unsigned)k), dim3(kBlock), 0, s, part, k, nslice,
-                     delta_g, G, gmax);
+                     delta_g, G, gmax, ctl);
   return hipGetLastError();
 }
 
 hipError_t launch_gram_carry(double* G, int32_t k, const double* pc, const double* ps,
-                             double delta_g, double* gmax, hipStream_t s) {
+                             double delta_g, double* gmax, hipStream_t s, const StepCtl* ctl) {
   hipLaunchKernelGGL(k_gram_carry, dim3((unsigned)k), dim3(kBlock), 0, s, G, k, pc, ps, delta_g,
-                     gmax);
+                     gmax, ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_step_init(StepCtl* ctl, int gram_on, int warm, double tight_min,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_step_init, dim3(1), dim3(1), 0, s, ctl, gram_on, warm, tight_min);
+  return hipGetLastError();
+}
+
+hipError_t launch_step_end(const Counters* cnt, StepCtl* ctl, StepRec* rec, const Persist* per,
+                           int32_t t, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_step_end, dim3(1), dim3(64), 0, s, cnt, ctl, rec, per, t, n);
   return hipGetLastError();
 }
 

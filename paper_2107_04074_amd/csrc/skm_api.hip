@@ -12,6 +12,7 @@
 //                   movement p(j), FP32 (and FP16) transpose, centre-centre
 //                   products (full Elkan and Hamerly only)
 #include <stdarg.h>
+#include <stddef.h>
 #include <stdio.h>
 #include <string.h>
 
@@ -68,7 +69,8 @@ struct Plan {
   size_t uy = 0, gpc = 0, gps = 0;
   size_t CT = 0, CT16 = 0, negflag = 0, C64 = 0, S = 0, l = 0, u = 0, ue = 0, eta = 0,
          a_old = 0, norm64 = 0, part = 0, part_sq = 0, pc = 0, ps = 0, dirty = 0, mm = 0, G = 0,
-         gmax = 0, gpart = 0, cnt = 0, per = 0, maxeta = 0, initnorm = 0, total = 0;
+         gmax = 0, gpart = 0, cnt = 0, per = 0, ctl = 0, rec = 0, maxeta = 0, initnorm = 0,
+         total = 0;
 };
 
 int check_matrix(const skm_matrix* X) {
@@ -155,10 +157,13 @@ int make_plan(const skm_matrix* X, int32_t k, int32_t variant, int32_t precision
     P->gmax = take(kk * sizeof(double));
     P->gpart = take((size_t)P->nslice * kk * kk * sizeof(double));
   }
-  // counter slots followed directly by the persistent block: one copy per
-  // step brings both to the host
-  P->cnt = take(kCounterSlots * sizeof(Counters) + sizeof(Persist));
-  P->per = P->cnt + kCounterSlots * sizeof(Counters);
+  // counter slots of a chunk of steps; the persistent block, the step
+  // control and the step records follow each other, so one copy per chunk
+  // brings them to the host
+  P->cnt = take((size_t)kStepChunk * kCounterSlots * sizeof(Counters));
+  P->per = take(sizeof(Persist) + sizeof(StepCtl) + kStepChunk * sizeof(StepRec));
+  P->ctl = P->per + sizeof(Persist);
+  P->rec = P->ctl + sizeof(StepCtl);
   P->maxeta = take(kCounterSlots * sizeof(float));
   P->initnorm = take(kk * sizeof(double));
   P->total = cur;
@@ -175,8 +180,12 @@ T* at(void* base, size_t off) {
 struct HostMirror {
   Counters slots[kCounterSlots];
   Persist per;
+  StepCtl ctl;
+  StepRec rec[kStepChunk];
 };
-static_assert(sizeof(HostMirror) == kCounterSlots * sizeof(Counters) + sizeof(Persist),
+static_assert(offsetof(HostMirror, per) == kCounterSlots * sizeof(Counters) &&
+                  offsetof(HostMirror, ctl) == offsetof(HostMirror, per) + sizeof(Persist) &&
+                  offsetof(HostMirror, rec) == offsetof(HostMirror, ctl) + sizeof(StepCtl),
               "host mirror must match the device layout");
 
 thread_local HostMirror* t_mirror = nullptr;
@@ -543,7 +552,7 @@ int fit_dense(const skm_matrix* X, int32_t k, const float* init_centers, int32_t
       R.ev1 = ev1;
       SKM_HIP(dense_step(R, assign_out, t > 0 ? 1 : 0, rows, rows_count, nullptr, nullptr, cnt));
       R.ev0 = R.ev1 = nullptr;
-      SKM_HIP(hipMemcpyAsync(hm, cnt, sizeof(HostMirror), hipMemcpyDeviceToHost, s));
+      SKM_HIP(hipMemcpyAsync(hm, cnt, offsetof(HostMirror, ctl), hipMemcpyDeviceToHost, s));
       SKM_HIP(hipStreamSynchronize(s));
       const Counters tc = sum_slots(hm);
       const int64_t changed = (int64_t)tc.changed;
@@ -855,22 +864,49 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
   double* gpart = P.gram ? at<double>(ws, P.gpart) : nullptr;
   Counters* cnt = at<Counters>(ws, P.cnt);
   Persist* per = at<Persist>(ws, P.per);
+  StepCtl* ctl = at<StepCtl>(ws, P.ctl);
+  StepRec* rec = at<StepRec>(ws, P.rec);
   float* maxeta = at<float>(ws, P.maxeta);
   double* initnorm = at<double>(ws, P.initnorm);
 
   int32_t iterations = 0, converged = 0;
   int64_t tot_sims = 0, tot_rechecks = 0, sk_launches = 0, sk_rows = 0, sk_nnz = 0;
   double sk_ms = 0.0;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  const bool prof = o.profile != 0;
+  hipEvent_t ev0[kStepChunk] = {}, ev1[kStepChunk] = {};
   double objective = 0.0;
-  bool first_gram = true;
-  int gram_updates = 0, gram_since_exact = 0;
-  double tight_rate = 1.0;
   {
-    if (o.profile) {
-      SKM_HIP(hipEventCreate(&ev0));
-      SKM_HIP(hipEventCreate(&ev1));
-    }
+    // centre step: member sums of the moved rows, renormalisation and
+    // movement, the transposed copies, and the centre-centre products as
+    // the step control decided (exact, carried, or nothing after a stop)
+    auto centre_update = [&]() -> hipError_t {
+      hipError_t e;
+      if ((e = launch_update_scan(X->row_ptr, X->col_idx, X->val, assign_out, a_old, n, d, fx,
+                                  S, dirty, s)) != hipSuccess)
+        return e;
+      if ((e = launch_sumsq_partial(S, k, d, fx_inv, dirty, part_sq, P.nchunk, s)) != hipSuccess)
+        return e;
+      if ((e = launch_normalize_move(S, k, d, fx_inv, dirty, part_sq, C64, part, P.nchunk, s)) !=
+          hipSuccess)
+        return e;
+      if ((e = launch_centre_finalize(k, d, dirty, norm64, part_sq, part, P.nchunk, delta_c, pc,
+                                      ps, mm, per, s)) != hipSuccess)
+        return e;
+      if (P.yy && (e = launch_group_move(pc, ps, k, P.ng, gpc, gps, s)) != hipSuccess) return e;
+      if ((e = launch_transpose(C64, k, d, P.kp, dirty, CT, s, CT16)) != hipSuccess) return e;
+      if (P.gram) {
+        if ((e = launch_gram(C64, k, d, dirty, 0, gpart, P.nslice, P.slice_len, G, gmax, delta_g,
+                             per, s, ctl)) != hipSuccess)
+          return e;
+        if ((e = launch_gram_carry(G, k, pc, ps, delta_g, gmax, s, ctl)) != hipSuccess) return e;
+      }
+      return launch_clear_dirty(dirty, k, s);
+    };
+    if (prof)
+      for (int c = 0; c < kStepChunk; ++c) {
+        SKM_HIP(hipEventCreate(&ev0[c]));
+        SKM_HIP(hipEventCreate(&ev1[c]));
+      }
     SKM_HIP(hipMemsetAsync(CT, 0, (size_t)d * P.kp * sizeof(float), s));
     SKM_HIP(hipMemsetAsync(S, 0, (size_t)k * d * sizeof(long long), s));
     SKM_HIP(hipMemsetAsync(per, 0, sizeof(Persist), s));
@@ -922,24 +958,36 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
       }
     }
 
-    for (int32_t t = 0; t < max_iter; ++t) {
-      int64_t changed = n;
-      if (t == 0 && warm) {
-        // the first step's assignment and FP64 top-2 are given: bounds only
-        SKM_HIP(launch_warm_start(X->row_ptr, n, k, P.kp, o.warm_assign, o.warm_best,
-                                  o.warm_second, eta, delta_c, assign_out, l, u, ue, uy,
-                                  P.ng, s));
-        if (stats && stats->changed_per_iter && stats->per_iter_len > 0)
-          stats->changed_per_iter[0] = n;
-        if (stats && stats->sims_per_iter && stats->per_iter_len > 0) stats->sims_per_iter[0] = 0;
-        iterations = 1;
-        goto centre_step;
-      }
-      SKM_HIP(hipMemsetAsync(cnt, 0, kCounterSlots * sizeof(Counters), s));
-      {
-      const bool exhaustive = (t == 0) || variant == SKM_LLOYD;
-      if (ev0) SKM_HIP(hipEventRecord(ev0, s));
-      {
+    // Steps are queued kStepChunk at a time: the stop flag and the Gram and
+    // tightening decisions live on the device (StepCtl), and the host reads
+    // the step records once per chunk.  Steps queued after the fit stopped
+    // find nothing to do.
+    {
+      // tightening reads about one line per stored entry, a row walk
+      // kp * (bytes per centre) / 128; it pays when it prunes more often
+      // than their ratio
+      const double walk_lines = (double)P.kp * (P.half ? 2.0 : 4.0) / 128.0;
+      const double tight_min = std::min(0.9, std::max(0.02, 1.25 / walk_lines));
+      SKM_HIP(launch_step_init(ctl, P.gram ? 1 : 0, warm ? 1 : 0, tight_min, s));
+    }
+    if (warm) {
+      // the first step's assignment and FP64 top-2 are given: bounds only
+      SKM_HIP(launch_warm_start(X->row_ptr, n, k, P.kp, o.warm_assign, o.warm_best,
+                                o.warm_second, eta, delta_c, assign_out, l, u, ue, uy, P.ng, s));
+      if (stats && stats->changed_per_iter && stats->per_iter_len > 0)
+        stats->changed_per_iter[0] = n;
+      if (stats && stats->sims_per_iter && stats->per_iter_len > 0) stats->sims_per_iter[0] = 0;
+      iterations = 1;
+      SKM_HIP(centre_update());
+    }
+    for (int32_t t0 = warm ? 1 : 0; t0 < max_iter;) {
+      const int ch = (int)std::min<int64_t>(kStepChunk, (int64_t)max_iter - t0);
+      SKM_HIP(hipMemsetAsync(cnt, 0, (size_t)ch * kCounterSlots * sizeof(Counters), s));
+      for (int c = 0; c < ch; ++c) {
+        const int32_t t = t0 + c;
+        Counters* cs = cnt + (size_t)c * kCounterSlots;
+        const bool exhaustive = (t == 0) || variant == SKM_LLOYD;
+        if (prof) SKM_HIP(hipEventRecord(ev0[c], s));
         AssignArgs A{};
         A.rp = X->row_ptr;
         A.ci = X->col_idx;
@@ -959,7 +1007,8 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
         A.ue = ue;
         A.eta = eta;
         A.delta_c = delta_c;
-        A.cnt = cnt;
+        A.cnt = cs;
+        A.ctl = ctl;
         A.pc = pc;
         A.ps = ps;
         A.mm = mm;
@@ -972,68 +1021,45 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
         A.ng = P.ng;
         A.gpc = gpc;
         A.gps = gps;
-        // tightening costs about one cache line per stored entry, a full
-        // row walk about kp/32; keep tightening while it prunes often enough
-        A.try_tighten = (t <= 2 || tight_rate >= 0.2 || t % 4 == 0) ? 1 : 0;
         const int mode = exhaustive ? ((t == 0 && P.elkan) ? kModeFitElkanInit : kModeFit)
                                     : P.elkan ? kModeElkan
                                     : P.yy    ? kModeYinYang
                                               : kModeHamerly;
         SKM_HIP(launch_assign(A, mode, s));
+        if (prof) SKM_HIP(hipEventRecord(ev1[c], s));
+        SKM_HIP(launch_step_end(cs, ctl, rec + c, per, t, n, s));
+        SKM_HIP(centre_update());
       }
-      if (ev1) SKM_HIP(hipEventRecord(ev1, s));
-      SKM_HIP(hipMemcpyAsync(hm, cnt, sizeof(HostMirror), hipMemcpyDeviceToHost, s));
+      SKM_HIP(hipMemcpyAsync(&hm->per, per,
+                             sizeof(Persist) + sizeof(StepCtl) + (size_t)ch * sizeof(StepRec),
+                             hipMemcpyDeviceToHost, s));
       SKM_HIP(hipStreamSynchronize(s));
-      const Counters tc = sum_slots(hm);
-      changed = (int64_t)tc.changed;
-      if (ev0) {
-        float ms = 0.f;
-        SKM_HIP(hipEventElapsedTime(&ms, ev0, ev1));
-        sk_ms += ms;
+      for (int c = 0; c < ch; ++c) {
+        const StepRec& r = hm->rec[c];
+        if (!r.valid) break;
+        const int32_t t = t0 + c;
+        if (prof) {
+          float ms = 0.f;
+          SKM_HIP(hipEventElapsedTime(&ms, ev0[c], ev1[c]));
+          sk_ms += ms;
+        }
+        sk_launches += 1;
+        sk_rows += (int64_t)r.rows_done;
+        sk_nnz += (int64_t)r.nnz_done;
+        tot_sims += (int64_t)r.sims;
+        tot_rechecks += (int64_t)r.rechecks;
+        if (stats && t < stats->per_iter_len) {
+          if (stats->changed_per_iter) stats->changed_per_iter[t] = (int64_t)r.changed;
+          if (stats->sims_per_iter) stats->sims_per_iter[t] = (int64_t)r.sims;
+          if (stats->objective_per_iter && t > 0) stats->objective_per_iter[t - 1] = r.objective;
+        }
+        iterations = t + 1;
       }
-      if (tc.tightened > 0) tight_rate = (double)tc.tight_saved / (double)tc.tightened;
-      sk_launches += 1;
-      sk_rows += (int64_t)tc.rows_done;
-      sk_nnz += (int64_t)tc.nnz_done;
-      tot_sims += (int64_t)tc.sims;
-      tot_rechecks += (int64_t)tc.rechecks;
-      if (t > 0) objective = hm->per.objective;
-      if (stats && t < stats->per_iter_len) {
-        if (stats->changed_per_iter) stats->changed_per_iter[t] = changed;
-        if (stats->sims_per_iter) stats->sims_per_iter[t] = (int64_t)tc.sims;
-        if (stats->objective_per_iter && t > 0 && t - 1 < stats->per_iter_len)
-          stats->objective_per_iter[t - 1] = hm->per.objective;
-      }
-      iterations = t + 1;
-      if (changed == 0) {
+      if (hm->ctl.stop) {
         converged = 1;
         break;
       }
-      }
-    centre_step:
-      // centre step
-      SKM_HIP(launch_update_scan(X->row_ptr, X->col_idx, X->val, assign_out, a_old, n, d, fx, S,
-                                 dirty, s));
-      SKM_HIP(launch_sumsq_partial(S, k, d, fx_inv, dirty, part_sq, P.nchunk, s));
-      SKM_HIP(launch_normalize_move(S, k, d, fx_inv, dirty, part_sq, C64, part, P.nchunk, s));
-      SKM_HIP(launch_centre_finalize(k, d, dirty, norm64, part_sq, part, P.nchunk, delta_c, pc,
-                                     ps, mm, per, s));
-      if (P.yy) SKM_HIP(launch_group_move(pc, ps, k, P.ng, gpc, gps, s));
-      SKM_HIP(launch_transpose(C64, k, d, P.kp, dirty, CT, s, CT16));
-      if (P.gram) {
-        if (gram_exact_step(gram_updates, gram_since_exact, changed, n)) {
-          // after carried steps every tile's partials are stale
-          SKM_HIP(launch_gram(C64, k, d, dirty, (first_gram || gram_since_exact > 0) ? 1 : 0,
-                              gpart, P.nslice, P.slice_len, G, gmax, delta_g, per, s));
-          first_gram = false;
-          gram_since_exact = 0;
-        } else {
-          SKM_HIP(launch_gram_carry(G, k, pc, ps, delta_g, gmax, s));
-          ++gram_since_exact;
-        }
-        ++gram_updates;
-      }
-      SKM_HIP(launch_clear_dirty(dirty, k, s));
+      t0 += ch;
     }
     // final objective (after the last update) and centre-centre count
     SKM_HIP(hipMemcpyAsync(&hm->per, per, sizeof(Persist), hipMemcpyDeviceToHost, s));
@@ -1059,8 +1085,10 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
     }
   }
 done:
-  if (ev0) (void)hipEventDestroy(ev0);
-  if (ev1) (void)hipEventDestroy(ev1);
+  for (int c = 0; c < kStepChunk; ++c) {
+    if (ev0[c]) (void)hipEventDestroy(ev0[c]);
+    if (ev1[c]) (void)hipEventDestroy(ev1[c]);
+  }
   if (owned) {
     (void)hipFreeAsync(ws, s);
     if (rc == SKM_OK) {

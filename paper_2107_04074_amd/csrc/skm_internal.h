@@ -39,6 +39,39 @@ struct Persist {
   double pad[11];
 };
 
+// Steps queued between two host reads of the step records.
+constexpr int kStepChunk = 8;
+
+// Totals of one assignment step, summed from its counter slots on the device.
+struct StepRec {
+  unsigned long long changed, sims, rechecks, tightened, tight_saved, rows_done, nnz_done;
+  double objective;               // sum_j |S_j| after the previous centre update
+  int32_t valid;                  // 1: the step ran (the fit had not stopped before it)
+  int32_t pad[7];
+};
+
+// State and decisions of the step loop kept on the device, so that steps are
+// queued without a host round trip: the stop flag (no assignment changed),
+// whether the coming centre update recomputes the centre-centre products or
+// carries them as bounds, and whether the next assignment step tightens lower
+// bounds.  None of these decisions changes a result, only the work.
+struct StepCtl {
+  int32_t stop;
+  int32_t gram_on;                // the variant keeps centre-centre products
+  int32_t gram_mode;              // coming centre update: 0 none, 1 exact, 2 carried
+  int32_t gram_force;             // the exact update recomputes every tile
+  int32_t gram_updates;           // centre updates decided so far
+  int32_t gram_since_exact;       // carried updates since the last exact one
+  int32_t tighten;                // the next assignment step tightens
+  int32_t tight_next;             // step of the next tightening probe
+  int32_t tight_gap;              // probe interval, doubled after each failed probe
+  int32_t pad0;
+  double tight_rate;              // pruned / tightened when last measured
+  double tight_min;               // rate below which tightening is switched off
+  double pad[9];
+};
+static_assert(sizeof(StepRec) == 96 && sizeof(StepCtl) == 128, "record layout");
+
 __device__ __forceinline__ Counters* counter_slot(Counters* base) {
   return base + (blockIdx.x % kCounterSlots);
 }
@@ -98,6 +131,8 @@ struct AssignArgs {
   int32_t simplified;
   int32_t bound_form;
   int32_t try_tighten;
+  // nullable: the fit's step control (stop flag; tightening decided there)
+  const StepCtl* ctl;
   // Elkan: k x k centre inner products (full variant) and their bound
   const double* Gm;
   double delta_g;
@@ -252,11 +287,22 @@ hipError_t launch_centre_finalize(int32_t k, int64_t d, const int32_t* dirty, do
 hipError_t launch_clear_dirty(int32_t* dirty, int32_t k, hipStream_t s);
 // Movement-bound update of G and gmax in place of an exact Gram.
 hipError_t launch_gram_carry(double* G, int32_t k, const double* pc, const double* ps,
-                             double delta_g, double* gmax, hipStream_t s);
+                             double delta_g, double* gmax, hipStream_t s,
+                             const StepCtl* ctl = nullptr);
+// Initial step control: gram_on as given; warm = the first centre update
+// (after a warm start) is already decided as an exact, full one.
+hipError_t launch_step_init(StepCtl* ctl, int gram_on, int warm, double tight_min,
+                            hipStream_t s);
+// After assignment step t: sums its counter slots into rec, stops the fit
+// when no assignment changed, and decides the coming centre-centre update and
+// the next step's tightening (see StepCtl).
+hipError_t launch_step_end(const Counters* cnt, StepCtl* ctl, StepRec* rec, const Persist* per,
+                           int32_t t, int64_t n, hipStream_t s);
 // Whether the centre step after assignment step t recomputes the Gram
 // exactly (else it carries the bounds): the first two centre steps, every
 // fourth after an exact one, and whenever more than 5% of the rows changed.
-inline bool gram_exact_step(int updates_done, int since_exact, int64_t changed, int64_t n) {
+__host__ __device__ inline bool gram_exact_step(int updates_done, int since_exact,
+                                                int64_t changed, int64_t n) {
   return updates_done < 2 || since_exact >= 3 || changed * 20 > n;
 }
 // First assignment step from a given assignment and FP64 top-2 (uy: the
@@ -289,7 +335,7 @@ void gram_slicing(int32_t k, int64_t d, int* nslice, int64_t* slice_len);
 hipError_t launch_gram(const double* C64, int32_t k, int64_t d, const int32_t* dirty,
                        int force_all, double* part, int nslice, int64_t slice_len,
                        double* G, double* gmax, double delta_g, Persist* per,
-                       hipStream_t s);
+                       hipStream_t s, const StepCtl* ctl = nullptr);
 hipError_t launch_c64_to_f32(const double* C64, int64_t count, float* out, hipStream_t s);
 hipError_t launch_fill_f64(double* p, int64_t count, double value, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t count, int32_t value, hipStream_t s);
