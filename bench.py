@@ -233,6 +233,14 @@ def main():
                        st_x.iterations == st_ref.iterations}
         log("%-13s %8.3f ms/fit  sims %.3f  identical %s" % (
             v, best * 1e3, variants[v]["sims_fraction"], variants[v]["identical"]))
+    # pruned fraction of the similarities per assignment step (one more,
+    # untimed fit of the timed variant with per-step statistics)
+    vb, vp = split(args.variant)
+    _, _, _, st_pi = skm.fit(Xd, k, C0d, vb, max_iter, workspace=workspace(args.variant),
+                             want_centers=False, per_iter=True, precision=vp)
+    torch.cuda.synchronize()
+    pruned_per_iter = [round(1.0 - float(x) / (n_rows * k), 4)
+                       for x in st_pi.sims_per_iter[:st_pi.iterations]]
     iters = sum(s.iterations for s in stats)
     ms_per_step = elapsed / args.steps * 1e3
     value = iters / elapsed
@@ -294,6 +302,7 @@ def main():
         "sims_per_s_raw": round(sims / elapsed, 1),
         "sims_per_s_lloyd_equiv": round(lloyd_equiv_sims / elapsed, 1),
         "pruned_fraction": round(1.0 - sims / lloyd_equiv_sims, 4),
+        "pruned_per_iter": pruned_per_iter,
         "rechecks_per_fit": st.rechecks,
         "variants": variants,
         "roofline": {
@@ -318,7 +327,7 @@ def main():
         import oracle
         n_it = args.cpu_iters or max(1, min(st.iterations, 10))
         t = time.perf_counter()
-        r = oracle.fit(X, C0, args.variant, n_it)
+        r = oracle.fit(X, C0, split(args.variant)[0], n_it)
         cpu_s = time.perf_counter() - t
         out["cpu_baseline"] = {
             "value": round(r.iterations / cpu_s, 4),

@@ -540,8 +540,16 @@ __device__ __forceinline__ double fp16_eps(double b, int m, double nx, double de
 // of VEC centres.  WAVE_ROW: one row per wave, walked by row_walk (VEC = 4
 // reads the FP32 centre copy, VEC = 8 the FP16 one); otherwise several rows
 // per wave (G <= 16, FP32), walked by row_sims.
+// One row per wave with one chunk per lane (k <= 256 FP32, k <= 512 FP16):
+// the walk is latency-bound, so at least three waves per SIMD are kept.
+template <int R, bool WAVE_ROW>
+constexpr int assign_min_waves() {
+  return (WAVE_ROW && R == 1) ? 3 : 1;
+}
+
 template <int G, int R, int VEC, int MODE, bool WAVE_ROW>
-__global__ __launch_bounds__(kBlock) void k_assign_csr(AssignArgs A) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
+    assign_min_waves<R, WAVE_ROW>()))) void k_assign_csr(AssignArgs A) {
   static_assert(VEC == 4 || (VEC == 8 && WAVE_ROW), "FP16 centres need the wave layout");
   constexpr int NACC = R * VEC / 4;
   constexpr int GPB = WAVE_ROW ? kBlock / 64 : kBlock / G;
@@ -551,8 +559,13 @@ __global__ __launch_bounds__(kBlock) void k_assign_csr(AssignArgs A) {
   // sub-wave holds the same values; lane 0 writes)
   const bool leader = WAVE_ROW ? (threadIdx.x & 63) == 0 : gl == 0;
   const bool lead_sub = WAVE_ROW ? (int)(threadIdx.x & 63) < G : true;
-  // a fit that has stopped leaves the steps queued after it without work
-  if (A.ctl && A.ctl->stop) return;
+  // a fit that has stopped leaves the steps queued after it without work;
+  // of the two kernels queued for a step with or without bound tests only
+  // the one that matches runs
+  if (A.ctl) {
+    const StepCtl* c = A.ctl;
+    if (c->stop || (A.gate == 1 && !c->tests) || (A.gate == 2 && c->tests)) return;
+  }
   const int tighten = A.ctl ? A.ctl->tighten : A.try_tighten;
   __shared__ unsigned long long sh[6];
   if (threadIdx.x < 6) sh[threadIdx.x] = 0;

@@ -140,13 +140,17 @@ __global__ void k_neg_scan(const float* __restrict__ v, int64_t nnz,
 
 // Scans the assignment for rows that moved since the last centre step and
 // applies S(old) -= x(i), S(new) += x(i) for each of them; a_old starts at -1
-// so the first step adds every row.  Lanes test 64 rows at a time, then the
-// wave handles the moved rows one after another with one lane per stored
-// entry.
+// so the first step adds every row.  A wave tests 64 rows, then the stored
+// entries of its moved rows are laid end to end (a prefix sum of their
+// lengths across the lanes) and the lanes take them 64 at a time, each lane
+// finding its entry's row by a binary search over the prefix; a batch of
+// entries is loaded before its atomics, so no lane waits for one row at a
+// time.  Fixed-point sums make the order of the atomics irrelevant.
 __global__ __launch_bounds__(kBlock) void k_update_scan(
     const int64_t* __restrict__ rp, const int32_t* __restrict__ ci, const float* __restrict__ v,
     const int32_t* __restrict__ a, int32_t* __restrict__ a_old, int64_t n, int64_t d,
     double fx, long long* __restrict__ S, int32_t* __restrict__ dirty) {
+  constexpr int kB = 4;  // entries per lane loaded before their atomics
   const int lane = threadIdx.x & 63;
   const int64_t wave0 = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63);
   for (int64_t base = wave0; base < n; base += (int64_t)gridDim.x * kBlock) {
@@ -156,29 +160,60 @@ __global__ __launch_bounds__(kBlock) void k_update_scan(
       nw = a[i];
       old = a_old[i];
     }
-    unsigned long long moved = __ballot(i < n && nw != old);
-    while (moved) {
-      const int src = __ffsll((long long)moved) - 1;
-      moved &= moved - 1ull;
-      const int64_t row = base + src;
-      const int32_t rn = __shfl(nw, src, 64);
-      const int32_t ro = __shfl(old, src, 64);
-      const int64_t beg = rp[row], end = rp[row + 1];
-      unsigned long long* Sn = reinterpret_cast<unsigned long long*>(S + (size_t)rn * d);
-      unsigned long long* So =
-          ro >= 0 ? reinterpret_cast<unsigned long long*>(S + (size_t)ro * d) : nullptr;
-      for (int64_t e = beg + lane; e < end; e += 64) {
-        const long long q = __double2ll_rn((double)v[e] * fx);
-        const int32_t c = ci[e];
-        atomicAdd(Sn + c, (unsigned long long)q);
-        if (So) atomicAdd(So + c, (unsigned long long)(-q));
+    const bool mv = i < n && nw != old;
+    if (__ballot(mv) == 0ull) continue;
+    int64_t rb = 0;
+    int len = 0;
+    if (mv) {
+      rb = rp[i];
+      len = (int)(rp[i + 1] - rb);
+      dirty[nw] = 1;
+      if (old >= 0) dirty[old] = 1;
+      a_old[i] = nw;
+    }
+    // inclusive prefix of the moved rows' lengths over the lanes
+    int incl = len;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int y = __shfl_up(incl, off, 64);
+      if (lane >= off) incl += y;
+    }
+    const int total = __shfl(incl, 63, 64);
+    for (int e0 = 0; e0 < total; e0 += 64 * kB) {
+      int32_t col[kB], rn[kB], ro[kB];
+      long long q[kB];
+#pragma unroll
+      for (int u = 0; u < kB; ++u) {
+        const int e = e0 + 64 * u + lane;
+        // source lane: the number of lanes whose prefix ends at or before e
+        int r = 0;
+#pragma unroll
+        for (int b = 32; b >= 1; b >>= 1)
+          if (__shfl(incl, r + b - 1, 64) <= e) r += b;
+        const int rs = r < 63 ? r : 63;
+        const int64_t rbr = __shfl(rb, rs, 64);
+        const int exr = __shfl(incl, rs, 64) - __shfl(len, rs, 64);
+        rn[u] = __shfl(nw, rs, 64);
+        ro[u] = __shfl(old, rs, 64);
+        col[u] = -1;
+        q[u] = 0;
+        if (e < total) {
+          const int64_t idx = rbr + (e - exr);
+          col[u] = ci[idx];
+          q[u] = __double2ll_rn((double)v[idx] * fx);
+        }
       }
-      if (lane == 0) {
-        dirty[rn] = 1;
-        if (ro >= 0) dirty[ro] = 1;
+#pragma unroll
+      for (int u = 0; u < kB; ++u) {
+        if (col[u] >= 0) {
+          atomicAdd(reinterpret_cast<unsigned long long*>(S + (size_t)rn[u] * d + col[u]),
+                    (unsigned long long)q[u]);
+          if (ro[u] >= 0)
+            atomicAdd(reinterpret_cast<unsigned long long*>(S + (size_t)ro[u] * d + col[u]),
+                      (unsigned long long)(-q[u]));
+        }
       }
     }
-    if (i < n && nw != old) a_old[i] = nw;
   }
 }
 
@@ -544,7 +579,8 @@ __global__ void k_fill_i32(int32_t* p, int64_t count, int32_t value) {
   if (e < count) p[e] = value;
 }
 
-__global__ void k_step_init(StepCtl* ctl, int gram_on, int warm, double tight_min) {
+__global__ void k_step_init(StepCtl* ctl, int gram_on, int warm, double test_min,
+                            double tight_min) {
   StepCtl c{};
   c.gram_on = gram_on;
   if (warm && gram_on) {  // the warm start's centre update: exact, every tile
@@ -552,6 +588,9 @@ __global__ void k_step_init(StepCtl* ctl, int gram_on, int warm, double tight_mi
     c.gram_force = 1;
     c.gram_updates = 1;
   }
+  c.tests = 1;
+  c.test_gap = 2;
+  c.test_min = test_min;
   c.tighten = 1;
   c.tight_gap = 4;
   c.tight_rate = 1.0;
@@ -561,13 +600,18 @@ __global__ void k_step_init(StepCtl* ctl, int gram_on, int warm, double tight_mi
 
 // One wave.  Sums the step's counter slots into its record; a step that
 // changed no assignment stops the fit (the kernels of later queued steps
-// then do nothing or find nothing to do).  Otherwise it decides whether the
-// coming centre update recomputes the centre-centre products (the first two
-// updates, after three carried ones, or when more than 5% of the rows moved)
-// and whether step t + 1 tightens: always at the first three steps and while
-// the last measured pruning rate of tightening reaches tight_min; after a
-// step whose tightening fell below it, the next probe comes tight_gap steps
-// later and the gap doubles (at most 64).
+// then do nothing or find nothing to do).  Otherwise it decides, for step
+// t + 1 and the centre update in between:
+//  - the bound tests: on while the last step that ran them pruned at least
+//    test_min of the rows; after one that pruned fewer, the next probe comes
+//    test_gap steps later and the gap doubles (at most 64);
+//  - the centre-centre products, needed only before a step with tests:
+//    exact for the first two updates, after three carried ones, when more
+//    than 5% of the rows moved, or when an update was skipped since the
+//    last one (then every tile); carried otherwise;
+//  - tightening: always at the first three steps and while the last
+//    measured pruning rate of tightening reaches tight_min, else probed
+//    with the same doubling gap.
 __global__ void k_step_end(const Counters* __restrict__ cnt, StepCtl* __restrict__ ctl,
                            StepRec* __restrict__ rec, const Persist* __restrict__ per, int32_t t,
                            int64_t n) {
@@ -609,26 +653,53 @@ __global__ void k_step_end(const Counters* __restrict__ cnt, StepCtl* __restrict
     *ctl = c;
     return;
   }
-  if (c.gram_on) {
-    const bool exact = gram_exact_step(c.gram_updates, c.gram_since_exact,
-                                       (int64_t)r.changed, n);
-    c.gram_mode = exact ? 1 : 2;
-    // after carried updates every tile's partial products are stale
-    c.gram_force = (c.gram_updates == 0 || c.gram_since_exact > 0) ? 1 : 0;
-    c.gram_since_exact = exact ? 0 : c.gram_since_exact + 1;
-    c.gram_updates += 1;
-  }
-  const bool was_on = c.tighten != 0;
-  if (r.tightened > 0) c.tight_rate = (double)r.tight_saved / (double)r.tightened;
-  if (t + 1 <= 2 || c.tight_rate >= c.tight_min) {
-    c.tighten = 1;
-    c.tight_gap = 4;
-  } else {
-    if (was_on) {
-      c.tight_next = t + c.tight_gap;
-      c.tight_gap = c.tight_gap < 32 ? 2 * c.tight_gap : 64;
+  // bound tests of step t + 1 (step 0 walks every row and runs none)
+  const bool tested = t > 0 && c.tests != 0;
+  if (tested) {
+    const double pruned = 1.0 - (double)r.rows_done / (double)n;
+    if (pruned >= c.test_min) {
+      c.tests = 1;
+      c.test_gap = 2;
+    } else {
+      c.test_next = t + c.test_gap;
+      c.test_gap = c.test_gap < 32 ? 2 * c.test_gap : 64;
+      c.tests = (t + 1 >= c.test_next) ? 1 : 0;
     }
-    c.tighten = (t + 1 >= c.tight_next) ? 1 : 0;
+  } else {
+    c.tests = (t + 1 >= c.test_next) ? 1 : 0;
+  }
+  // centre-centre products for the coming centre update
+  if (c.gram_on) {
+    if (!c.tests) {
+      c.gram_mode = 0;
+      c.gram_stale = 1;
+    } else {
+      const bool exact = c.gram_stale ||
+                         gram_exact_step(c.gram_updates, c.gram_since_exact,
+                                         (int64_t)r.changed, n);
+      c.gram_mode = exact ? 1 : 2;
+      // after carried or skipped updates every tile's partial products are stale
+      c.gram_force =
+          (c.gram_updates == 0 || c.gram_since_exact > 0 || c.gram_stale) ? 1 : 0;
+      c.gram_since_exact = exact ? 0 : c.gram_since_exact + 1;
+      c.gram_updates += 1;
+      c.gram_stale = 0;
+    }
+  }
+  // tightening (it only matters in a step with tests)
+  if (tested) {
+    const bool was_on = c.tighten != 0;
+    if (r.tightened > 0) c.tight_rate = (double)r.tight_saved / (double)r.tightened;
+    if (t + 1 <= 2 || c.tight_rate >= c.tight_min) {
+      c.tighten = 1;
+      c.tight_gap = 4;
+    } else {
+      if (was_on) {
+        c.tight_next = t + c.tight_gap;
+        c.tight_gap = c.tight_gap < 32 ? 2 * c.tight_gap : 64;
+      }
+      c.tighten = (t + 1 >= c.tight_next) ? 1 : 0;
+    }
   }
   *ctl = c;
 }
@@ -749,9 +820,10 @@ hipError_t launch_gram_carry(double* G, int32_t k, const double* pc, const doubl
   return hipGetLastError();
 }
 
-hipError_t launch_step_init(StepCtl* ctl, int gram_on, int warm, double tight_min,
-                            hipStream_t s) {
-  hipLaunchKernelGGL(k_step_init, dim3(1), dim3(1), 0, s, ctl, gram_on, warm, tight_min);
+hipError_t launch_step_init(StepCtl* ctl, int gram_on, int warm, double test_min,
+                            double tight_min, hipStream_t s) {
+  hipLaunchKernelGGL(k_step_init, dim3(1), dim3(1), 0, s, ctl, gram_on, warm, test_min,
+                     tight_min);
   return hipGetLastError();
 }
 

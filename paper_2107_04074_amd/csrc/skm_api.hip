@@ -968,7 +968,11 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
       // than their ratio
       const double walk_lines = (double)P.kp * (P.half ? 2.0 : 4.0) / 128.0;
       const double tight_min = std::min(0.9, std::max(0.02, 1.25 / walk_lines));
-      SKM_HIP(launch_step_init(ctl, P.gram ? 1 : 0, warm ? 1 : 0, tight_min, s));
+      // the tests of a row cost about a fifth of its walk where the walk is
+      // shortest (two lines per entry) and proportionally less for longer
+      // walks; they run while they prune at least that share of the rows
+      const double test_min = std::min(0.2, std::max(0.01, 0.4 / walk_lines));
+      SKM_HIP(launch_step_init(ctl, P.gram ? 1 : 0, warm ? 1 : 0, test_min, tight_min, s));
     }
     if (warm) {
       // the first step's assignment and FP64 top-2 are given: bounds only
@@ -1021,11 +1025,16 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
         A.ng = P.ng;
         A.gpc = gpc;
         A.gps = gps;
-        const int mode = exhaustive ? ((t == 0 && P.elkan) ? kModeFitElkanInit : kModeFit)
-                                    : P.elkan ? kModeElkan
-                                    : P.yy    ? kModeYinYang
-                                              : kModeHamerly;
-        SKM_HIP(launch_assign(A, mode, s));
+        if (exhaustive) {
+          SKM_HIP(launch_assign(A, (t == 0 && P.elkan) ? kModeFitElkanInit : kModeFit, s));
+        } else {
+          // with the bound tests, or (switched off by the step control) a
+          // full walk that refreshes every bound: the plain fit kernel
+          A.gate = 1;
+          SKM_HIP(launch_assign(A, P.elkan ? kModeElkan : P.yy ? kModeYinYang : kModeHamerly, s));
+          A.gate = 2;
+          SKM_HIP(launch_assign(A, P.elkan ? kModeFitElkanInit : kModeFit, s));
+        }
         if (prof) SKM_HIP(hipEventRecord(ev1[c], s));
         SKM_HIP(launch_step_end(cs, ctl, rec + c, per, t, n, s));
         SKM_HIP(centre_update());

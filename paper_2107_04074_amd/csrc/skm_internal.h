@@ -51,24 +51,32 @@ struct StepRec {
 };
 
 // State and decisions of the step loop kept on the device, so that steps are
-// queued without a host round trip: the stop flag (no assignment changed),
-// whether the coming centre update recomputes the centre-centre products or
-// carries them as bounds, and whether the next assignment step tightens lower
+// queued without a host round trip: the stop flag (no assignment changed);
+// whether the next assignment step runs the bound tests at all (when too few
+// rows were pruned they cost more than they save: the step then walks every
+// row and refreshes every bound exactly); whether the coming centre update
+// recomputes the centre-centre products, carries them as bounds, or skips
+// them (no tests next step); and whether the next step tightens lower
 // bounds.  None of these decisions changes a result, only the work.
 struct StepCtl {
   int32_t stop;
   int32_t gram_on;                // the variant keeps centre-centre products
   int32_t gram_mode;              // coming centre update: 0 none, 1 exact, 2 carried
   int32_t gram_force;             // the exact update recomputes every tile
-  int32_t gram_updates;           // centre updates decided so far
+  int32_t gram_updates;           // exact or carried updates so far
   int32_t gram_since_exact;       // carried updates since the last exact one
+  int32_t gram_stale;             // a centre update was skipped since the last one
+  int32_t tests;                  // the next assignment step runs the bound tests
+  int32_t test_next;              // step of the next test probe
+  int32_t test_gap;               // probe interval, doubled after each failed probe
   int32_t tighten;                // the next assignment step tightens
   int32_t tight_next;             // step of the next tightening probe
   int32_t tight_gap;              // probe interval, doubled after each failed probe
   int32_t pad0;
+  double test_min;                // pruned-row fraction below which tests are switched off
   double tight_rate;              // pruned / tightened when last measured
   double tight_min;               // rate below which tightening is switched off
-  double pad[9];
+  double pad[6];
 };
 static_assert(sizeof(StepRec) == 96 && sizeof(StepCtl) == 128, "record layout");
 
@@ -133,6 +141,9 @@ struct AssignArgs {
   int32_t try_tighten;
   // nullable: the fit's step control (stop flag; tightening decided there)
   const StepCtl* ctl;
+  // with ctl: 0 always runs, 1 only when the step runs the bound tests,
+  // 2 only when it does not (a full walk that refreshes every bound)
+  int32_t gate;
   // Elkan: k x k centre inner products (full variant) and their bound
   const double* Gm;
   double delta_g;
@@ -291,8 +302,8 @@ hipError_t launch_gram_carry(double* G, int32_t k, const double* pc, const doubl
                              const StepCtl* ctl = nullptr);
 // Initial step control: gram_on as given; warm = the first centre update
 // (after a warm start) is already decided as an exact, full one.
-hipError_t launch_step_init(StepCtl* ctl, int gram_on, int warm, double tight_min,
-                            hipStream_t s);
+hipError_t launch_step_init(StepCtl* ctl, int gram_on, int warm, double test_min,
+                            double tight_min, hipStream_t s);
 // After assignment step t: sums its counter slots into rec, stops the fit
 // when no assignment changed, and decides the coming centre-centre update and
 // the next step's tightening (see StepCtl).
