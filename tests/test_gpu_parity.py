@@ -191,6 +191,29 @@ def test_fit_reduced_c2(skm, torch_cuda, bound_form):
             assert np.array_equal(a, base[0]) and np.array_equal(C64, base[1])
 
 
+def test_fit_large_clusters(skm, torch_cuda):
+    """k = 8 on 20,000 rows: clusters of thousands of rows, whose member sums
+    are rebuilt from several parts in the steps where many rows move; the
+    whole trajectory matches the oracle's."""
+    torch = torch_cuda
+    X, init, cfg = datagen.sparse_workload("c2", n=20000)
+    k = 8
+    C0 = datagen.init_centers_csr(X, init[:k])
+    Xd = skm.DeviceCSR.from_host(X)
+    T = 30
+    ref = oracle.fit(X, C0, "lloyd", T)
+    for v in ["lloyd", "hamerly", "yinyang"]:
+        say("case fit large clusters %s" % v)
+        a, C, C64, st = run_fit(skm, torch, Xd, C0, k, v, T)
+        say("  iters=%d sizes=%s" % (st.iterations, np.bincount(a, minlength=k).tolist()))
+        assert st.iterations == ref.iterations
+        assert np.array_equal(st.changed_per_iter, ref.changed)
+        assert np.array_equal(a, ref.a)
+        assert np.linalg.norm(C64 - ref.C, axis=1).max() < 1e-6
+        assert abs(st.objective - ref.obj_update[~np.isnan(ref.obj_update)][-1]) <= \
+            1e-6 * st.objective
+
+
 def sampled_step_check(X, a_t, C_prev, a_prev, C_t, sample, label):
     rows = np.sort(sample)
     S = oracle.sims(X, C_prev, rows)
