@@ -614,8 +614,10 @@ __global__ void k_step_init(StepCtl* ctl, int gram_on, int warm, double test_min
 //    with the same doubling gap.
 __global__ void k_step_end(const Counters* __restrict__ cnt, StepCtl* __restrict__ ctl,
                            StepRec* __restrict__ rec, const Persist* __restrict__ per, int32_t t,
-                           int64_t n) {
+                           int64_t n, int32_t* __restrict__ dirty, int32_t k, int gram_queued) {
   const int i = threadIdx.x;
+  // the previous centre update's dirty flags have been read by now
+  for (int j = i; j < k; j += 64) dirty[j] = 0;
   if (ctl->stop) {
     if (i == 0) rec->valid = 0;
     return;
@@ -668,6 +670,10 @@ __global__ void k_step_end(const Counters* __restrict__ cnt, StepCtl* __restrict
   } else {
     c.tests = (t + 1 >= c.test_next) ? 1 : 0;
   }
+  // tests that need the centre-centre products wait for a step whose centre
+  // update has the Gram kernels queued (the host leaves them out only where
+  // it knows the tests are off)
+  if (c.gram_on && !gram_queued) c.tests = 0;
   // centre-centre products for the coming centre update
   if (c.gram_on) {
     if (!c.tests) {
@@ -828,8 +834,10 @@ hipError_t launch_step_init(StepCtl* ctl, int gram_on, int warm, double test_min
 }
 
 hipError_t launch_step_end(const Counters* cnt, StepCtl* ctl, StepRec* rec, const Persist* per,
-                           int32_t t, int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_step_end, dim3(1), dim3(64), 0, s, cnt, ctl, rec, per, t, n);
+                           int32_t t, int64_t n, int32_t* dirty, int32_t k, int gram_queued,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_step_end, dim3(1), dim3(64), 0, s, cnt, ctl, rec, per, t, n, dirty, k,
+                     gram_queued);
   return hipGetLastError();
 }
 

@@ -879,7 +879,7 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
     // centre step: member sums of the moved rows, renormalisation and
     // movement, the transposed copies, and the centre-centre products as
     // the step control decided (exact, carried, or nothing after a stop)
-    auto centre_update = [&]() -> hipError_t {
+    auto centre_update = [&](bool gram) -> hipError_t {
       hipError_t e;
       if ((e = launch_update_scan(X->row_ptr, X->col_idx, X->val, assign_out, a_old, n, d, fx,
                                   S, dirty, s)) != hipSuccess)
@@ -894,13 +894,13 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
         return e;
       if (P.yy && (e = launch_group_move(pc, ps, k, P.ng, gpc, gps, s)) != hipSuccess) return e;
       if ((e = launch_transpose(C64, k, d, P.kp, dirty, CT, s, CT16)) != hipSuccess) return e;
-      if (P.gram) {
+      if (P.gram && gram) {
         if ((e = launch_gram(C64, k, d, dirty, 0, gpart, P.nslice, P.slice_len, G, gmax, delta_g,
                              per, s, ctl)) != hipSuccess)
           return e;
         if ((e = launch_gram_carry(G, k, pc, ps, delta_g, gmax, s, ctl)) != hipSuccess) return e;
       }
-      return launch_clear_dirty(dirty, k, s);
+      return hipSuccess;
     };
     if (prof)
       for (int c = 0; c < kStepChunk; ++c) {
@@ -982,8 +982,12 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
         stats->changed_per_iter[0] = n;
       if (stats && stats->sims_per_iter && stats->per_iter_len > 0) stats->sims_per_iter[0] = 0;
       iterations = 1;
-      SKM_HIP(centre_update());
+      SKM_HIP(centre_update(true));
     }
+    // steps before off_until are known (from the last read-back) to run
+    // without bound tests: only the plain walk is queued for them, and no
+    // Gram kernels before them
+    int64_t off_until = INT64_MIN;
     for (int32_t t0 = warm ? 1 : 0; t0 < max_iter;) {
       const int ch = (int)std::min<int64_t>(kStepChunk, (int64_t)max_iter - t0);
       SKM_HIP(hipMemsetAsync(cnt, 0, (size_t)ch * kCounterSlots * sizeof(Counters), s));
@@ -1025,8 +1029,9 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
         A.ng = P.ng;
         A.gpc = gpc;
         A.gps = gps;
-        if (exhaustive) {
-          SKM_HIP(launch_assign(A, (t == 0 && P.elkan) ? kModeFitElkanInit : kModeFit, s));
+        const int plain = P.elkan ? kModeFitElkanInit : kModeFit;
+        if (exhaustive || t < off_until) {
+          SKM_HIP(launch_assign(A, plain, s));
         } else {
           // with the bound tests, or (switched off by the step control) a
           // full walk that refreshes every bound: the plain fit kernel
@@ -1036,8 +1041,9 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
           SKM_HIP(launch_assign(A, P.elkan ? kModeFitElkanInit : kModeFit, s));
         }
         if (prof) SKM_HIP(hipEventRecord(ev1[c], s));
-        SKM_HIP(launch_step_end(cs, ctl, rec + c, per, t, n, s));
-        SKM_HIP(centre_update());
+        const bool gram = (int64_t)t + 1 >= off_until;
+        SKM_HIP(launch_step_end(cs, ctl, rec + c, per, t, n, dirty, k, gram ? 1 : 0, s));
+        SKM_HIP(centre_update(gram));
       }
       SKM_HIP(hipMemcpyAsync(&hm->per, per,
                              sizeof(Persist) + sizeof(StepCtl) + (size_t)ch * sizeof(StepRec),
@@ -1069,6 +1075,7 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
         break;
       }
       t0 += ch;
+      off_until = hm->ctl.tests ? INT64_MIN : (int64_t)hm->ctl.test_next;
     }
     // final objective (after the last update) and centre-centre count
     SKM_HIP(hipMemcpyAsync(&hm->per, per, sizeof(Persist), hipMemcpyDeviceToHost, s));

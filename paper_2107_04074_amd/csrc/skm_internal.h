@@ -304,11 +304,15 @@ hipError_t launch_gram_carry(double* G, int32_t k, const double* pc, const doubl
 // (after a warm start) is already decided as an exact, full one.
 hipError_t launch_step_init(StepCtl* ctl, int gram_on, int warm, double test_min,
                             double tight_min, hipStream_t s);
-// After assignment step t: sums its counter slots into rec, stops the fit
-// when no assignment changed, and decides the coming centre-centre update and
-// the next step's tightening (see StepCtl).
+// After assignment step t: clears the dirty flags of the previous centre
+// update, sums the step's counter slots into rec, stops the fit when no
+// assignment changed, and decides the coming centre-centre update, the next
+// step's bound tests and tightening (see StepCtl).  gram_queued: the Gram
+// kernels are queued for the coming centre update (else no tests that need
+// them run in step t + 1).
 hipError_t launch_step_end(const Counters* cnt, StepCtl* ctl, StepRec* rec, const Persist* per,
-                           int32_t t, int64_t n, hipStream_t s);
+                           int32_t t, int64_t n, int32_t* dirty, int32_t k, int gram_queued,
+                           hipStream_t s);
 // Whether the centre step after assignment step t recomputes the Gram
 // exactly (else it carries the bounds): the first two centre steps, every
 // fourth after an exact one, and whenever more than 5% of the rows changed.
