@@ -68,7 +68,7 @@ struct MfmaCfg<false> {
 template <int MODE>
 __device__ __forceinline__ void tile_epilogue(const f32x16& acc, int jb, int k, bool ragged,
                                               float& m1, int& j1, float& m2, float thr,
-                                              int64_t rowid, int64_t slot,
+                                              int64_t rowid, int64_t slot, int* lcnt, int lrow,
                                               const DenseSimArgs& A) {
   if (MODE == 0) {
     float t1 = -INFINITY, t2 = -INFINITY;
@@ -92,7 +92,7 @@ __device__ __forceinline__ void tile_epilogue(const f32x16& acc, int jb, int k, 
     for (int i = 0; i < 16; ++i) {
       const int j = jb + 8 * (i >> 2) + (i & 3);
       if ((!ragged || j < k) && acc[i] >= thr && rowid >= 0) {
-        const int pos = atomicAdd(&A.cand_n[slot], 1);
+        const int pos = atomicAdd(&lcnt[lrow], 1);  // LDS counter of the row
         if (pos < A.cand_cap) A.cand[slot * A.cand_cap + pos] = j;
       }
     }
@@ -114,6 +114,8 @@ __global__ __launch_bounds__(kDenseWaves * 64) void k_dense_sim(DenseSimArgs A) 
   constexpr int ROWS_PER_BLOCK = ROWS_PER_WAVE * kDenseWaves;
   extern __shared__ char smem[];
   E* lds = reinterpret_cast<E*>(smem);
+  // candidate mode: per-row candidate counts of the block's current rows
+  __shared__ int lcnt[MODE == 1 ? ROWS_PER_BLOCK : 1];
   constexpr int dp = DP;
   constexpr int ldsw = dp + (BF16 ? 8 : 4);  // padded LDS row stride (16-byte aligned)
   constexpr int nsteps = dp / KSTEP;
@@ -159,6 +161,8 @@ __global__ __launch_bounds__(kDenseWaves * 64) void k_dense_sim(DenseSimArgs A) 
           }
         }
       }
+    if (MODE == 1)
+      for (int i = threadIdx.x; i < ROWS_PER_BLOCK; i += kDenseWaves * 64) lcnt[i] = 0;
     float m1[RT], m2[RT], thr[RT];
     int j1[RT];
 #pragma unroll
@@ -222,14 +226,21 @@ __global__ __launch_bounds__(kDenseWaves * 64) void k_dense_sim(DenseSimArgs A) 
 #pragma unroll
           for (int rt = 0; rt < RT; ++rt) tile_epilogue<MODE>(acc[rt], jb, A.k, false, m1[rt],
                                                               j1[rt], m2[rt], thr[rt], rowid[rt],
-                                                              slot[rt], A);
+                                                              slot[rt], lcnt,
+                                                              (int)(slot[rt] - blk), A);
         } else {
 #pragma unroll
           for (int rt = 0; rt < RT; ++rt) tile_epilogue<MODE>(acc[rt], jb, A.k, true, m1[rt],
                                                               j1[rt], m2[rt], thr[rt], rowid[rt],
-                                                              slot[rt], A);
+                                                              slot[rt], lcnt,
+                                                              (int)(slot[rt] - blk), A);
         }
       }
+    }
+    if (MODE == 1) {
+      __syncthreads();
+      for (int i = threadIdx.x; i < ROWS_PER_BLOCK; i += kDenseWaves * 64)
+        if (blk + i < count) A.cand_n[blk + i] = lcnt[i];
     }
     if (MODE == 0) {
       // combine lanes l and l ^ 32 (same row, other half of the centres)
@@ -304,9 +315,12 @@ __global__ __launch_bounds__(kBlock) void k_dense_post(DensePostArgs A) {
   if (threadIdx.x == 0 && sh_changed) atomicAdd(&counter_slot(A.cnt)->changed, sh_changed);
 }
 
-// FP64 re-decision of the flagged rows, one wave per row: each lane
-// evaluates candidates with the canonical sequential FP64 chain against the
-// FP64 master centres; overflowing candidate lists fall back to all k.
+// FP64 re-decision of the flagged rows against the FP64 master centres, one
+// wave per row: the listed candidates one after another, each by the whole
+// wave; a row with more candidates than the list holds evaluates all k
+// centres, one lane each with a sequential FP64 chain.  Either order is
+// fixed, and the winner (FP64 argmax, tie rule) does not depend on the order
+// in which the candidates were listed.
 __global__ __launch_bounds__(kBlock) void k_dense_exact(DenseExactArgs A) {
   __shared__ unsigned long long sh_changed, sh_rechecks;
   if (threadIdx.x == 0) {
@@ -328,14 +342,43 @@ __global__ __launch_bounds__(kBlock) void k_dense_exact(DenseExactArgs A) {
     const float* x = A.X + (size_t)row * A.ldx;
     double cb = -INFINITY;
     int cj = INT_MAX;
-    for (int c = lane; c < ncand; c += 64) {
-      const int j = all ? c : A.cand[(size_t)w * A.cand_cap + c];
-      const double* cj64 = A.C64 + (size_t)j * A.d;
-      double acc = 0.0;
-      for (int t = 0; t < A.d; ++t) acc = fma((double)x[t], cj64[t], acc);
-      if (better64(acc, j, cb, cj, prev)) {
-        cb = acc;
-        cj = j;
+    if (!all) {
+      // listed candidates one at a time, the whole wave on each: lane l
+      // holds terms 4l .. 4l+3 (d <= 256), a four-term FMA chain, then a
+      // fixed xor tree over the lanes; every lane ends with the same value
+      double xv[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int t = 4 * lane + q;
+        xv[q] = (t < A.d) ? (double)x[t] : 0.0;
+      }
+      const int32_t* cl = A.cand + (size_t)w * A.cand_cap;
+      for (int c = 0; c < ncand; ++c) {
+        const int j = cl[c];
+        const double* cj64 = A.C64 + (size_t)j * A.d;
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int t = 4 * lane + q;
+          acc = fma(xv[q], (t < A.d) ? cj64[t] : 0.0, acc);
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+        if (better64(acc, j, cb, cj, prev)) {
+          cb = acc;
+          cj = j;
+        }
+      }
+    } else {
+      // more candidates than the list holds: every centre, one lane each
+      for (int c = lane; c < ncand; c += 64) {
+        const double* cj64 = A.C64 + (size_t)c * A.d;
+        double acc = 0.0;
+        for (int t = 0; t < A.d; ++t) acc = fma((double)x[t], cj64[t], acc);
+        if (better64(acc, c, cb, cj, prev)) {
+          cb = acc;
+          cj = c;
+        }
       }
     }
 #pragma unroll

@@ -247,7 +247,7 @@ struct DensePlan {
   bool bf16 = false, bounds = false, gram = false;
   int nchunk = 1, nslice = 1, nb = 1;
   int64_t slice_len = 0;
-  int32_t cap = 16;  // candidate slots per flagged row
+  int32_t cap = 64;  // candidate slots per flagged row
   size_t Xb = 0, Cp = 0, C64 = 0, S = 0, eta = 0, a_old = 0, l = 0, u = 0, best = 0, best_j = 0,
          second = 0, thr = 0, near = 0, rflag = 0, rows = 0, nlist = 0, nrows = 0, nthr = 0,
          bcnt = 0, boff = 0, cand = 0, cand_n = 0, ccnt = 0, cstart = 0, ccur = 0, perm = 0,
