@@ -320,6 +320,13 @@ def main():
             "operand_bytes_per_launch": operand_bytes_per_launch,
             "operand_GBps": round(operand_bytes_per_launch / avg_launch_s / 1e9, 1)
             if avg_launch_s > 0 else 0.0,
+            # measured L2-to-fabric bytes (Infinity Cache or HBM) per launch over
+            # this run's average launch time, against the 8 TB/s HBM peak
+            "traffic_GBps": round(traffic["bytes_per_launch"] / avg_launch_s / 1e9, 1)
+            if traffic and avg_launch_s > 0 else None,
+            "traffic_frac_of_hbm_peak": round(traffic["bytes_per_launch"] / avg_launch_s /
+                                              8.0e12, 4)
+            if traffic and avg_launch_s > 0 else None,
         },
     }
 
