@@ -168,10 +168,10 @@ __device__ __forceinline__ float entry_float(float w, int idx_uniform, int sub) 
   else return __shfl(w, idx_uniform + sub, 64);
 }
 
-template <int L, int R>
+template <int L, int R, bool MASKED>
 __device__ __forceinline__ void walk_issue(uint4 (&dst)[WalkBatch<R>::U][R], int cw, int first,
                                            int sub, const uint4* __restrict__ C16B, int kp16,
-                                           int gl) {
+                                           int gl, unsigned need) {
   constexpr int S = 64 / L;
   constexpr int U = WalkBatch<R>::U;
 #pragma unroll
@@ -179,7 +179,10 @@ __device__ __forceinline__ void walk_issue(uint4 (&dst)[WalkBatch<R>::U][R], int
     const int cu = entry_int<S>(cw, S * (first + u), sub);
     const uint4* p = C16B + (uint32_t)((uint32_t)cu * (uint32_t)kp16) + gl;
 #pragma unroll
-    for (int r = 0; r < R; ++r) dst[u][r] = p[L * r];
+    for (int r = 0; r < R; ++r) {
+      if (!MASKED || ((need >> r) & 1u)) dst[u][r] = p[L * r];
+      else dst[u][r] = make_uint4(0u, 0u, 0u, 0u);
+    }
   }
 }
 
@@ -217,11 +220,12 @@ __device__ __forceinline__ void walk_consume(const uint4 (&src)[WalkBatch<R>::U]
   }
 }
 
-template <int L, int R, int VEC>
+template <int L, int R, int VEC, bool MASKED = false>
 __device__ __forceinline__ float row_walk(const int32_t* __restrict__ ci,
                                           const float* __restrict__ v, int64_t beg, int64_t end,
                                           int c0, float x0, const void* __restrict__ CTB, int kp,
-                                          int lane, float4 (&acc)[R * VEC / 4]) {
+                                          int lane, float4 (&acc)[R * VEC / 4],
+                                          unsigned need = ~0u) {
   constexpr int S = 64 / L;
   constexpr int U = WalkBatch<R>::U;
   constexpr int PER_WIN = 64 / (S * U);  // batches per 64-entry window (even)
@@ -235,7 +239,7 @@ __device__ __forceinline__ float row_walk(const int32_t* __restrict__ ci,
   uint4 buf0[U][R], buf1[U][R];
   int c = c0;  // entries beg .. beg + 63, loaded by the caller (0 past the end)
   float x = x0;
-  walk_issue<L, R>(buf0, c, 0, sub, C16B, kp16, gl);
+  walk_issue<L, R, MASKED>(buf0, c, 0, sub, C16B, kp16, gl, need);
   for (int64_t w0 = beg; w0 < end; w0 += 64) {
     int cn = 0;
     float xn = 0.f;
@@ -250,12 +254,14 @@ __device__ __forceinline__ float row_walk(const int32_t* __restrict__ ci,
     for (int b = 0; b < PER_WIN; b += 2) {
       const int64_t eb = w0 + (int64_t)(S * U) * b;
       if (eb >= end) break;
-      walk_issue<L, R>(buf1, c, (b + 1) * U, sub, C16B, kp16, gl);
+      walk_issue<L, R, MASKED>(buf1, c, (b + 1) * U, sub, C16B, kp16, gl, need);
       __builtin_amdgcn_sched_barrier(0);  // keep these loads ahead of the FMAs below
       walk_consume<L, R, VEC>(buf0, x, b * U, sub, acc);
       if (eb + S * U >= end) break;
-      if (b + 2 < PER_WIN) walk_issue<L, R>(buf0, c, (b + 2) * U, sub, C16B, kp16, gl);
-      else walk_issue<L, R>(buf0, cn, 0, sub, C16B, kp16, gl);
+      if (b + 2 < PER_WIN)
+        walk_issue<L, R, MASKED>(buf0, c, (b + 2) * U, sub, C16B, kp16, gl, need);
+      else
+        walk_issue<L, R, MASKED>(buf0, cn, 0, sub, C16B, kp16, gl, need);
       __builtin_amdgcn_sched_barrier(0);
       walk_consume<L, R, VEC>(buf1, x, (b + 1) * U, sub, acc);
     }
@@ -337,12 +343,17 @@ __device__ __forceinline__ bool hamerly_prologue(const AssignArgs& A, int64_t ro
 // l(i), the guarded Eq. (7) for every group bound u(i, f) with the group's
 // largest movement, and the global filter l(i) >= max_f u(i, f), first
 // as is, then with l(i) tightened.  Lanes share the groups.  Returns true
-// when the row needs no walk; the bounds are then stored.
-template <int G>
+// when the row needs no walk; the bounds are then stored.  PARTIAL (one row
+// per wave): when the row is walked, the group filter u(i, f) <= l(i) marks
+// the groups that cannot hold a better centre; their updated bounds are
+// stored here, they are left out of the walk, and surv0/surv1 (bit f) get
+// the groups that must be walked.
+template <int G, bool PARTIAL>
 __device__ __forceinline__ bool yinyang_prologue(const AssignArgs& A, int64_t row, const RowIn& ri,
                                                  int64_t beg, int64_t end, int gl, bool leader,
                                                  int tighten, unsigned long long& tight,
-                                                 unsigned long long& saved) {
+                                                 unsigned long long& saved, uint64_t& surv0,
+                                                 uint64_t& surv1) {
   const int prev = ri.prev;
   const int m = (int)(end - beg);
   const double eta = (double)ri.eta;
@@ -370,6 +381,26 @@ __device__ __forceinline__ bool yinyang_prologue(const AssignArgs& A, int64_t ro
     if (leader) A.l[row] = __double2float_rd(fmax(ld, -1.0));
     for (int f = gl; f < A.ng; f += G)
       uyr[f] = __double2float_ru(fmin(1.0, upper_upd((double)uyr[f], A.gpc[f], A.gps[f]) + 4e-15));
+  } else if constexpr (PARTIAL) {
+    uint64_t m0 = 0ull, m1 = 0ull;
+    for (int i = 0; G * i < A.ng; ++i) {  // wave-uniform trip count
+      const int f = gl + G * i;
+      bool alive = false;
+      if (f < A.ng) {
+        const double uf = fmin(1.0, upper_upd((double)uyr[f], A.gpc[f], A.gps[f]) + 4e-15);
+        // the assigned centre's group is always walked (its exact similarity
+        // gives the new l(i))
+        alive = !(ld - uf >= mu) || f == prev / kYYGroup;
+        if (!alive) uyr[f] = __double2float_ru(uf);
+      }
+      uint64_t bits = __ballot(alive);
+      if constexpr (G < 64) bits &= (1ull << G) - 1ull;  // sub-wave 0 holds groups f = gl + G i
+      const int sh = G * i;
+      if (sh < 64) m0 |= bits << sh;
+      else m1 |= bits << (sh - 64);
+    }
+    surv0 = m0;
+    surv1 = m1;
   }
   return skip;
 }
@@ -455,14 +486,16 @@ __device__ __forceinline__ bool elkan_prologue(const AssignArgs& A, int64_t row,
   return !alive;
 }
 
-// After a walk: every Yin-Yang group bound becomes the largest computed
-// similarity of the group's centres other than the new assignment (plus the
-// error band, rounded up); -1 for a group with no other centre.  A group of
-// kYYGroup centres is kYYGroup / VEC consecutive lanes of one chunk.
+// After a walk: every walked Yin-Yang group's bound becomes the largest
+// computed similarity of the group's centres other than the new assignment
+// (plus the error band, rounded up); -1 for a group with no other centre.
+// A group of kYYGroup centres is kYYGroup / VEC consecutive lanes of one
+// chunk; need has bit r set when chunk r was walked.
 template <int G, int R, int VEC>
 __device__ __forceinline__ void write_group_bounds(const AssignArgs& A, int64_t row,
                                                    const float4 (&acc)[R * VEC / 4], int gl,
-                                                   int abest, double rho32, bool writer) {
+                                                   int abest, double rho32, bool writer,
+                                                   unsigned need) {
   constexpr int SEG = (kYYGroup / VEC < G) ? kYYGroup / VEC : G;  // lanes per group
 #pragma unroll
   for (int r = 0; r < R; ++r) {
@@ -475,7 +508,7 @@ __device__ __forceinline__ void write_group_bounds(const AssignArgs& A, int64_t 
 #pragma unroll
     for (int off = SEG / 2; off >= 1; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, SEG));
     const int j0 = VEC * (gl + G * r);
-    if (writer && (gl % SEG) == 0 && j0 < A.k) {
+    if (writer && (gl % SEG) == 0 && j0 < A.k && ((need >> r) & 1u)) {
       const int f = j0 / kYYGroup;
       const float val = (m == -INFINITY) ? -1.0f
                                          : __double2float_ru(fmin((double)m + rho32, 1.0));
@@ -567,11 +600,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
     if (c->stop || (A.gate == 1 && !c->tests) || (A.gate == 2 && c->tests)) return;
   }
   const int tighten = A.ctl ? A.ctl->tighten : A.try_tighten;
-  __shared__ unsigned long long sh[6];
-  if (threadIdx.x < 6) sh[threadIdx.x] = 0;
+  __shared__ unsigned long long sh[7];
+  if (threadIdx.x < 7) sh[threadIdx.x] = 0;
   __syncthreads();
   unsigned long long my_rows = 0, my_rechecks = 0, my_nnz = 0, my_changed = 0, my_tight = 0,
-                     my_saved = 0;
+                     my_saved = 0, my_sims = 0;
   const float4* CT4 = reinterpret_cast<const float4*>(A.CT);
   const int kp4 = A.kp >> 2;
   const int k = A.k;
@@ -645,31 +678,62 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
     }
     const int m = (int)(end - beg);
     const int prev = ri.prev;
+    // Yin-Yang with one row per wave and the FP32 copy at k > 256 walks only
+    // the groups its group filter leaves (bit r of need: this lane's chunk r
+    // is walked).  A group is one 128-byte line per stored entry there, and
+    // those walks are bound by the bytes they fetch; shorter or FP16 walks
+    // are bound by latency, where masked gathers save nothing and the masks
+    // cost occupancy.
+    constexpr bool kPartial = MODE == kModeYinYang && WAVE_ROW && VEC == 4 && R >= 2;
+    unsigned need = ~0u;
     if constexpr (kBounded) {
+      uint64_t surv0 = ~0ull, surv1 = ~0ull;
       const bool skip =
           MODE == kModeHamerly
               ? hamerly_prologue<G>(A, row, ri, beg, end, gl, leader, tighten, my_tight,
                                     my_saved)
           : MODE == kModeYinYang
-              ? yinyang_prologue<G>(A, row, ri, beg, end, gl, leader, tighten, my_tight,
-                                    my_saved)
+              ? yinyang_prologue<G, kPartial>(A, row, ri, beg, end, gl, leader, tighten,
+                                              my_tight, my_saved, surv0, surv1)
               : elkan_prologue<G, R, VEC>(A, row, ri, beg, end, gl, leader, tighten, lead_sub,
                                           my_tight, my_saved);
       if (skip) {
         if constexpr (WAVE_ROW) next_window();
         continue;
       }
+      if constexpr (kPartial) {
+        need = 0u;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int j0 = VEC * (gl + G * r);
+          const int f = j0 / kYYGroup;
+          const bool walk =
+              j0 < k && (((f < 64 ? (surv0 >> f) : (surv1 >> (f - 64))) & 1ull) != 0ull);
+          need |= walk ? (1u << r) : 0u;
+        }
+      }
     }
 
     float4 acc[NACC];
     float nrm2;
     if constexpr (WAVE_ROW) {
-      nrm2 = row_walk<G, R, VEC>(A.ci, A.v, beg, end, c0, x0,
-                                 VEC == 8 ? (const void*)A.CT16 : (const void*)A.CT, A.kp, wl,
-                                 acc);
+      nrm2 = row_walk<G, R, VEC, kPartial>(A.ci, A.v, beg, end, c0, x0,
+                                           VEC == 8 ? (const void*)A.CT16 : (const void*)A.CT,
+                                           A.kp, wl, acc, need);
       next_window();
     } else {
       nrm2 = row_sims<G, R, false>(A.ci, A.v, beg, end, CT4, kp4, gl, ~0u, acc);
+    }
+    // similarities computed for this row (wave-uniform)
+    unsigned long long row_sims_done = (unsigned long long)k;
+    if constexpr (kPartial) {
+      int mine = 0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int j0 = VEC * (gl + G * r);
+        if ((need >> r) & 1u) mine += (k - j0 < VEC) ? k - j0 : VEC;
+      }
+      row_sims_done = (unsigned long long)group_sum<G>(mine);
     }
 
     float b = -INFINITY, s2 = -INFINITY;
@@ -679,7 +743,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
       for (int q = 0; q < VEC; ++q) {
         const int j = VEC * (gl + G * r) + q;
-        if (j < k) {
+        if (j < k && ((need >> r) & 1u)) {
           const float sv = f4get(acc[(r * VEC + q) >> 2], q & 3);
           if (better32(sv, j, b, bj, prev)) {
             s2 = fmaxf(s2, b);
@@ -713,7 +777,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
         for (int q = 0; q < VEC; ++q) {
           const int j = VEC * (gl + G * r) + q;
-          if (j < k && (double)f4get(acc[(r * VEC + q) >> 2], q & 3) >= thr)
+          if (j < k && ((need >> r) & 1u) &&
+              (double)f4get(acc[(r * VEC + q) >> 2], q & 3) >= thr)
             cm |= 1ull << (VEC * r + q);
         }
       double cb;
@@ -749,7 +814,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
           A.u[row] = __double2float_ru(fmin(hi, 1.0));
         }
       }
-      if (A.uy) write_group_bounds<G, R, VEC>(A, row, acc, gl, abest, rho32, lead_sub);
+      if (A.uy) write_group_bounds<G, R, VEC>(A, row, acc, gl, abest, rho32, lead_sub, need);
       if ((MODE == kModeFitElkanInit || MODE == kModeElkan) && lead_sub) {
         float4* uer4 = reinterpret_cast<float4*>(A.ue + (size_t)row * A.kp);
 #pragma unroll
@@ -771,6 +836,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
       my_rows += 1;
       my_nnz += (unsigned long long)m;
       my_rechecks += rechecked ? 1 : 0;
+      my_sims += row_sims_done;
     }
   }
 
@@ -781,15 +847,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
   if (my_changed) atomicAdd(&sh[3], my_changed);
   if (my_tight) atomicAdd(&sh[4], my_tight);
   if (my_saved) atomicAdd(&sh[5], my_saved);
+  if (my_sims) atomicAdd(&sh[6], my_sims);
   __syncthreads();
   if (threadIdx.x == 0) {
     Counters* c = counter_slot(A.cnt);
+    // similarities: those of the walked rows (all k, or the walked groups)
+    // plus one per tightened row
+    if (sh[6] + sh[4]) atomicAdd(&c->sims, sh[6] + sh[4]);
     if (sh[0]) {
-      atomicAdd(&c->sims, sh[0] * (unsigned long long)k + sh[4]);
       atomicAdd(&c->rows_done, sh[0]);
       atomicAdd(&c->nnz_done, sh[1]);
-    } else if (sh[4]) {
-      atomicAdd(&c->sims, sh[4]);
     }
     if (sh[2]) atomicAdd(&c->rechecks, sh[2]);
     if (sh[3]) atomicAdd(&c->changed, sh[3]);

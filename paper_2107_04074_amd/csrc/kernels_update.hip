@@ -658,7 +658,10 @@ __global__ void k_step_end(const Counters* __restrict__ cnt, StepCtl* __restrict
   // bound tests of step t + 1 (step 0 walks every row and runs none)
   const bool tested = t > 0 && c.tests != 0;
   if (tested) {
-    const double pruned = 1.0 - (double)r.rows_done / (double)n;
+    // share of the point-centre similarities the tests saved (whole rows,
+    // or groups of a row for Yin-Yang)
+    const double pruned =
+        1.0 - (double)(r.sims - r.tightened) / ((double)n * (double)k);
     if (pruned >= c.test_min) {
       c.tests = 1;
       c.test_gap = 2;
