@@ -413,11 +413,11 @@ __device__ __forceinline__ bool yinyang_prologue(const AssignArgs& A, int64_t ro
 // walked row gets every similarity and hence every pair bound exactly.
 // The lanes hold the pair bounds in the walk's layout.  Returns true when
 // the row needs no walk.
-template <int G, int R, int VEC>
+template <int G, int R, int VEC, bool PARTIAL>
 __device__ __forceinline__ bool elkan_prologue(const AssignArgs& A, int64_t row, const RowIn& ri,
                                                int64_t beg, int64_t end, int gl, bool leader,
                                                int tighten, bool writer, unsigned long long& tight,
-                                               unsigned long long& saved) {
+                                               unsigned long long& saved, unsigned& need) {
   constexpr int NACC = R * VEC / 4;
   const int k = A.k;
   const int prev = ri.prev;
@@ -444,12 +444,14 @@ __device__ __forceinline__ bool elkan_prologue(const AssignArgs& A, int64_t row,
     }
   }
   const double* Grow = A.Gm ? A.Gm + (size_t)prev * k : nullptr;
+  // cmask: bit r set when chunk r of this lane holds a centre that survives
+  unsigned cmask = 0u;
   auto any_alive = [&](double lcur) -> bool {
+    cmask = 0u;
     const double M = lcur - mu;
     const bool cc_ok = !A.simplified && Grow != nullptr && lcur > 0.0 && M > 0.0;
     const double T = cc_ok ? cc_threshold(lcur, M) - 4e-15 : -3.0;
     if (cc_ok && A.gmax[prev] <= T) return false;  // point test: no other centre can win
-    unsigned alive = 0u;
 #pragma unroll
     for (int q4 = 0; q4 < NACC; ++q4) {
       const int r = (4 * q4) / VEC, q0 = (4 * q4) % VEC;
@@ -459,11 +461,11 @@ __device__ __forceinline__ bool elkan_prologue(const AssignArgs& A, int64_t row,
         if (j < k && j != prev) {
           const bool by_u = (lcur - (double)f4get(uv[q4], q)) >= mu;  // u(i, j) <= l(i)
           const bool by_cc = cc_ok && (Grow[j] + A.delta_g <= T);     // cc(a, j) <= l(i)
-          alive |= (!by_u && !by_cc) ? 1u : 0u;
+          cmask |= (!by_u && !by_cc) ? (1u << r) : 0u;
         }
       }
     }
-    return group_or<G>(alive) != 0u;
+    return group_or<G>(cmask) != 0u;
   };
   bool alive = any_alive(ld);
   if (alive && tighten) {
@@ -480,6 +482,18 @@ __device__ __forceinline__ bool elkan_prologue(const AssignArgs& A, int64_t row,
       for (int q4 = 0; q4 < NACC; ++q4) {
         const int r = (4 * q4) / VEC, q0 = (4 * q4) % VEC;
         uer4[(VEC * (gl + G * r) + q0) / 4] = uv[q4];
+      }
+    }
+  } else if constexpr (PARTIAL) {
+    // walk the chunks with a surviving centre and the assigned centre's
+    // chunk; the others keep their updated pair bounds
+    const int pc4 = prev / VEC;
+    need = cmask | ((pc4 % G == gl) ? (1u << (pc4 / G)) : 0u);
+    if (writer) {
+#pragma unroll
+      for (int q4 = 0; q4 < NACC; ++q4) {
+        const int r = (4 * q4) / VEC, q0 = (4 * q4) % VEC;
+        if (!((need >> r) & 1u)) uer4[(VEC * (gl + G * r) + q0) / 4] = uv[q4];
       }
     }
   }
@@ -678,13 +692,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
     }
     const int m = (int)(end - beg);
     const int prev = ri.prev;
-    // Yin-Yang with one row per wave and the FP32 copy at k > 256 walks only
-    // the groups its group filter leaves (bit r of need: this lane's chunk r
-    // is walked).  A group is one 128-byte line per stored entry there, and
-    // those walks are bound by the bytes they fetch; shorter or FP16 walks
-    // are bound by latency, where masked gathers save nothing and the masks
-    // cost occupancy.
-    constexpr bool kPartial = MODE == kModeYinYang && WAVE_ROW && VEC == 4 && R >= 2;
+    // Yin-Yang and Elkan with one row per wave and the FP32 copy at
+    // 256 < k <= 2048 walk only what their filters leave: the groups of the
+    // group filter, or the chunks holding a centre whose pair tests failed
+    // (bit r of need: this lane's chunk r is walked).  A group of 32 centres
+    // is one 128-byte line per stored entry there, and those walks are bound
+    // by the bytes they fetch; shorter or FP16 walks are bound by latency,
+    // where masked gathers save nothing and the masks cost occupancy.
+    constexpr bool kPartial = (MODE == kModeYinYang || MODE == kModeElkan) && WAVE_ROW &&
+                              VEC == 4 && R >= 2 && R <= 8;
     unsigned need = ~0u;
     if constexpr (kBounded) {
       uint64_t surv0 = ~0ull, surv1 = ~0ull;
@@ -695,13 +711,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
           : MODE == kModeYinYang
               ? yinyang_prologue<G, kPartial>(A, row, ri, beg, end, gl, leader, tighten,
                                               my_tight, my_saved, surv0, surv1)
-              : elkan_prologue<G, R, VEC>(A, row, ri, beg, end, gl, leader, tighten, lead_sub,
-                                          my_tight, my_saved);
+              : elkan_prologue<G, R, VEC, kPartial>(A, row, ri, beg, end, gl, leader, tighten,
+                                                    lead_sub, my_tight, my_saved, need);
       if (skip) {
         if constexpr (WAVE_ROW) next_window();
         continue;
       }
-      if constexpr (kPartial) {
+      if constexpr (kPartial && MODE == kModeYinYang) {
         need = 0u;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -820,6 +836,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
         for (int q4 = 0; q4 < NACC; ++q4) {
           const int r = (4 * q4) / VEC, q0 = (4 * q4) % VEC;
+          if (!((need >> r) & 1u)) continue;  // kept its updated bound
           float4 o;
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
