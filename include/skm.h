@@ -98,7 +98,9 @@ typedef struct {            /* [host]; an all-zero struct means defaults      */
                                with p'(a) = min_{j!=a} p(j) (default);
                                1 = Eq. (9) where valid (u, p' >= 0)           */
   int32_t precision;        /* 0 = FP32 similarities; 1 = BF16 MFMA (dense
-                               input only), same exact-argmax guarantee       */
+                               input only); 2 = FP16 copy of the centres for
+                               the CSR row walk (k >= 65); every precision
+                               keeps the same exact-argmax guarantee          */
   int32_t validate;         /* 0 = none; 1 = initial centres must be unit
                                within norm_tol; 2 = also every data row      */
   int32_t profile;          /* 1 = time every launch of the similarity kernel
@@ -115,6 +117,14 @@ typedef struct {            /* [host]; an all-zero struct means defaults      */
   const int32_t* warm_assign;
   const double* warm_best;
   const double* warm_second;
+  int32_t schedule;         /* CSR bounded variants.  0 (default): the bound
+                               tests (Sections 5.1-5.5) and the tightening of
+                               l(i) run only while they prune enough to pay
+                               for themselves, otherwise the step walks every
+                               row and refreshes every bound exactly; 1: they
+                               run at every step, as in the paper.  Results
+                               are the same either way; only work differs.  */
+  int32_t reserved1;
 } skm_options;
 
 typedef struct {            /* [host] filled by skm_fit                       */

@@ -802,6 +802,8 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
   if (o.norm_tol <= 0.0) o.norm_tol = 1e-4;
   if (o.bound_form != 0 && o.bound_form != 1)
     return fail(SKM_ERR_INVALID_ARG, "bound_form must be 0 or 1");
+  if (o.schedule != 0 && o.schedule != 1)
+    return fail(SKM_ERR_INVALID_ARG, "schedule must be 0 or 1");
   const int nwarm = (o.warm_assign != nullptr) + (o.warm_best != nullptr) +
                     (o.warm_second != nullptr);
   if (nwarm != 0 && nwarm != 3)
@@ -967,11 +969,13 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
       // kp * (bytes per centre) / 128; it pays when it prunes more often
       // than their ratio
       const double walk_lines = (double)P.kp * (P.half ? 2.0 : 4.0) / 128.0;
-      const double tight_min = std::min(0.9, std::max(0.02, 1.25 / walk_lines));
+      double tight_min = std::min(0.9, std::max(0.02, 1.25 / walk_lines));
       // the tests of a row cost about a fifth of its walk where the walk is
       // shortest (two lines per entry) and proportionally less for longer
       // walks; they run while they prune at least that share of the rows
-      const double test_min = std::min(0.2, std::max(0.01, 0.4 / walk_lines));
+      double test_min = std::min(0.2, std::max(0.01, 0.4 / walk_lines));
+      // schedule 1: tests and tightening at every step (never switched off)
+      if (o.schedule == 1) test_min = tight_min = -1e300;
       SKM_HIP(launch_step_init(ctl, P.gram ? 1 : 0, warm ? 1 : 0, test_min, tight_min, s));
     }
     if (warm) {

@@ -42,7 +42,8 @@ class SkmOptions(ctypes.Structure):
     _fields_ = [("bound_form", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("validate", ctypes.c_int32), ("profile", ctypes.c_int32),
                 ("norm_tol", ctypes.c_double), ("warm_assign", ctypes.c_void_p),
-                ("warm_best", ctypes.c_void_p), ("warm_second", ctypes.c_void_p)]
+                ("warm_best", ctypes.c_void_p), ("warm_second", ctypes.c_void_p),
+                ("schedule", ctypes.c_int32), ("reserved1", ctypes.c_int32)]
 
 
 class SkmStats(ctypes.Structure):
@@ -201,10 +202,12 @@ class FitStats:
     objective_per_iter: np.ndarray = field(default_factory=lambda: np.zeros(0))
 
 
-def _options(bound_form=0, precision=0, validate=0, norm_tol=0.0, profile=0, warm=None):
-    """warm: (assign, best, second) device tensors from seed_kmeanspp."""
+def _options(bound_form=0, precision=0, validate=0, norm_tol=0.0, profile=0, warm=None,
+             schedule=0):
+    """warm: (assign, best, second) device tensors from seed_kmeanspp;
+    schedule: 1 runs the bound tests at every step (0 = adaptive)."""
     w = (None, None, None) if warm is None else tuple(_ptr(t) for t in warm)
-    return SkmOptions(bound_form, precision, validate, profile, norm_tol, *w)
+    return SkmOptions(bound_form, precision, validate, profile, norm_tol, *w, schedule, 0)
 
 
 def seed_kmeanspp(X: DeviceCSR, k: int, uniforms, alpha: float = 1.0, workspace=None):

@@ -97,6 +97,10 @@ def test_invalid_arguments_are_rejected(lib):
     rc = lib.skm_fit(ctypes.byref(m), 3, 0x5000, 0, 5, ctypes.byref(bad), None, 0, 0x4000,
                      None, None, ctypes.byref(st), None)
     assert rc == skm.ERR_INVALID_ARG
+    bad = skm.SkmOptions(0, 0, 0, 0, 0.0, None, None, None, 2)
+    rc = lib.skm_fit(ctypes.byref(m), 3, 0x5000, 0, 5, ctypes.byref(bad), None, 0, 0x4000,
+                     None, None, ctypes.byref(st), None)
+    assert rc == skm.ERR_INVALID_ARG and b"schedule" in lib.skm_last_error()
     # undersized caller workspace
     rc = lib.skm_fit(ctypes.byref(m), 3, 0x5000, 0, 5, None, 0x6000, 16, 0x4000, None, None,
                      ctypes.byref(st), None)

@@ -214,6 +214,35 @@ def test_fit_large_clusters(skm, torch_cuda):
             1e-6 * st.objective
 
 
+def test_fit_partial_walks(skm, torch_cuda):
+    """k = 300 with the FP32 copy (padded to 512 centres): Yin-Yang and Elkan
+    walk only the groups / chunks their filters leave.  Started from the
+    oracle's centres after 14 steps (where the centres move little and the
+    filters prune), 8 more steps against the oracle's Lloyd trajectory."""
+    torch = torch_cuda
+    X, _, _ = datagen.sparse_workload("c2", n=50000)
+    k, T = 300, 8
+    C0 = datagen.init_centers_csr(X, np.random.default_rng(5).choice(X.n, k, replace=False))
+    say("case partial walks: oracle warm-up")
+    C14 = oracle.fit(X, C0, "lloyd", 14).C.astype(np.float32)
+    say("case partial walks: oracle")
+    ref = oracle.fit(X, C14, "lloyd", T)
+    Xd = skm.DeviceCSR.from_host(X)
+    for v, sched in [("lloyd", 0), ("yinyang", 0), ("yinyang", 1), ("elkan", 1),
+                     ("simp_elkan", 1)]:
+        say("case partial walks %s schedule=%d" % (v, sched))
+        a, C, C64, st = run_fit(skm, torch, Xd, C14, k, v, T, schedule=sched)
+        say("  iters=%d sims=%d of %d" % (st.iterations, st.sims_point_center, X.n * k * T))
+        if sched == 1:
+            # tests at every step: some walked rows skip groups / chunks and
+            # count fewer than k similarities, so the total is no multiple of k
+            assert st.sims_point_center < X.n * k * T and st.sims_point_center % k != 0
+        assert st.iterations == ref.iterations and st.converged == ref.converged
+        assert np.array_equal(st.changed_per_iter, ref.changed)
+        assert np.array_equal(a, ref.a)
+        assert np.linalg.norm(C64 - ref.C, axis=1).max() < 1e-6
+
+
 def sampled_step_check(X, a_t, C_prev, a_prev, C_t, sample, label):
     rows = np.sort(sample)
     S = oracle.sims(X, C_prev, rows)
