@@ -38,7 +38,6 @@ using namespace dev;
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 
-constexpr int kDenseWaves = 4;  // waves per block of the MFMA kernel
 
 template <bool BF16>
 struct MfmaCfg;
@@ -48,6 +47,9 @@ struct MfmaCfg<true> {
   static constexpr int KSTEP = 16;  // K per instruction
   static constexpr int RT = 2;      // 32-row tiles per wave
   static constexpr int CC = 64;     // centres per LDS chunk
+  // waves per block: every block stages all centres through LDS once per
+  // pass, so 512 rows per block halve that traffic (two waves per SIMD fit)
+  static constexpr int WAVES = 8;
   typedef __bf16 elem;
 };
 
@@ -56,6 +58,7 @@ struct MfmaCfg<false> {
   static constexpr int KSTEP = 2;
   static constexpr int RT = 1;
   static constexpr int CC = 32;
+  static constexpr int WAVES = 4;
   typedef float elem;
 };
 
@@ -106,8 +109,9 @@ __device__ __forceinline__ void tile_epilogue(const f32x16& acc, int jb, int k, 
 //   mode 1: candidate emission: every centre with value >= thr[slot] is
 //           appended to cand[slot * cap + ...], counts in cand_n[slot]
 template <bool BF16, int MODE, int DP>
-__global__ __launch_bounds__(kDenseWaves * 64) void k_dense_sim(DenseSimArgs A) {
+__global__ __launch_bounds__(MfmaCfg<BF16>::WAVES * 64) void k_dense_sim(DenseSimArgs A) {
   typedef MfmaCfg<BF16> Cfg;
+  constexpr int kDenseWaves = Cfg::WAVES;
   typedef typename Cfg::elem E;
   constexpr int KSTEP = Cfg::KSTEP, RT = Cfg::RT, CC = Cfg::CC;
   constexpr int ROWS_PER_WAVE = 32 * RT;
@@ -181,20 +185,22 @@ __global__ __launch_bounds__(kDenseWaves * 64) void k_dense_sim(DenseSimArgs A) 
         constexpr int VEC = 16 / sizeof(E);
         constexpr int per_row = dp / VEC;
         constexpr int NT = kDenseWaves * 64;
-        constexpr int STEPS = CC * per_row / NT;
-        static_assert(CC * per_row % NT == 0, "staging must tile the block");
+        constexpr int TOTAL = CC * per_row;
+        constexpr int STEPS = (TOTAL + NT - 1) / NT;
         float4 st[STEPS];
 #pragma unroll
         for (int q = 0; q < STEPS; ++q) {
           const int e = threadIdx.x + q * NT;
           const int r = e / per_row, c = (e - r * per_row) * VEC;
-          st[q] = *reinterpret_cast<const float4*>(Ce + (size_t)(c0 + r) * dp + c);
+          if (TOTAL % NT == 0 || e < TOTAL)
+            st[q] = *reinterpret_cast<const float4*>(Ce + (size_t)(c0 + r) * dp + c);
         }
 #pragma unroll
         for (int q = 0; q < STEPS; ++q) {
           const int e = threadIdx.x + q * NT;
           const int r = e / per_row, c = (e - r * per_row) * VEC;
-          *reinterpret_cast<float4*>(lds + r * ldsw + c) = st[q];
+          if (TOTAL % NT == 0 || e < TOTAL)
+            *reinterpret_cast<float4*>(lds + r * ldsw + c) = st[q];
         }
       }
       __syncthreads();
@@ -722,12 +728,13 @@ size_t dense_sim_lds_bytes(bool bf16, int dp) {
 }
 
 hipError_t launch_dense_sim(const DenseSimArgs& A, bool bf16, int mode, hipStream_t s) {
-  const int rows_per_block = (bf16 ? 64 : 32) * kDenseWaves;
+  const int waves = bf16 ? MfmaCfg<true>::WAVES : MfmaCfg<false>::WAVES;
+  const int rows_per_block = (bf16 ? 64 : 32) * waves;
   int64_t blocks = (A.n_rows + rows_per_block - 1) / rows_per_block;
   if (blocks > 4 * kMaxGridBlocks) blocks = 4 * kMaxGridBlocks;
   if (blocks < 1) blocks = 1;
   const size_t lds = dense_sim_lds_bytes(bf16, A.dp);
-  const dim3 grid((unsigned)blocks), block(kDenseWaves * 64);
+  const dim3 grid((unsigned)blocks), block(waves * 64);
 #define SKM_DS(B, M, D) \
   hipLaunchKernelGGL((k_dense_sim<B, M, D>), grid, block, lds, s, A)
 #define SKM_DS_DP(B, M)                       \
