@@ -16,8 +16,10 @@
  *    frees or reallocates caller memory.
  *  - All work is enqueued on `stream` (a hipStream_t passed as void*; NULL is
  *    the default stream).  skm_assign returns without synchronising;
- *    skm_fit synchronises with `stream` once per iteration (it reads the
- *    number of changed assignments) and returns after the fit completed.
+ *    skm_fit queues assignment steps eight at a time (the stop test and
+ *    the other per-step decisions are taken on the GPU), synchronises with
+ *    `stream` once per eight steps to read the step records, and returns
+ *    after the fit completed.
  *  - Every function returns an skm_status; no C++ exception crosses the ABI.
  *    On error the outputs are unspecified and skm_last_error() describes the
  *    failure (thread-local string, valid until the next call on the thread).
@@ -77,7 +79,7 @@ typedef enum {
   SKM_ERR_NOT_NORMALIZED = 2, /* validation found a row that is not unit     */
   SKM_ERR_OUT_OF_MEMORY = 3,  /* workspace too small or allocation failed    */
   SKM_ERR_HIP = 4,            /* a HIP runtime call failed                   */
-  SKM_ERR_UNSUPPORTED = 5     /* valid request this build does not handle    */
+  SKM_ERR_UNSUPPORTED = 5     /* valid request the library does not handle   */
 } skm_status;
 
 typedef enum { SKM_CSR_F32 = 0, SKM_DENSE_F32 = 1 } skm_format;
@@ -143,10 +145,12 @@ typedef struct {            /* [host] filled by skm_fit                       */
   int32_t per_iter_len;
   int32_t reserved0;
   /* work of the dominant similarity kernel: for CSR input the row-walk
-     (or Elkan) kernel of each assignment step, for dense input the first
-     MFMA similarity pass of each step; launches, rows and stored entries
-     (rows x d for dense) it processed, and (profile = 1) its summed duration
-     from HIP events recorded around each launch on `stream` */
+     kernel of each assignment step (one or two launches per step: with and
+     without bound tests, one of which returns at once), for dense input the
+     first MFMA similarity pass of each step; steps, rows walked and their
+     stored entries (rows x d for dense), and (profile = 1) the summed
+     duration from HIP events recorded around each step's launches on
+     `stream` */
   int64_t sim_kernel_launches;
   int64_t sim_kernel_rows;
   int64_t sim_kernel_nnz;
