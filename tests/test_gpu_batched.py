@@ -73,7 +73,7 @@ def test_batched_matches_oracle(skm, torch_cuda, problems):
     torch.cuda.synchronize()
     for p, (Xd, k, C0, it), (a, C, st) in zip(small, dp, res):
         say("case batched oracle n=%d k=%d" % (p.X.n, k))
-        ref = oracle.fit(p.X, C0.cpu().numpy(), "lloyd", it)
+        ref = oracle.fit(p.X, datagen.init_centers_csr(p.X, p.init), "lloyd", it)
         assert st.iterations == ref.iterations and st.converged == ref.converged
         assert np.array_equal(a.cpu().numpy(), ref.a)
         assert np.linalg.norm(C.cpu().numpy().astype(np.float64) - ref.C, axis=1).max() < 1e-6

@@ -78,9 +78,12 @@ def test_warm_start_equals_cold_fit(skm, torch_cuda, variant):
         assert stw.sims_point_center < stc.sims_point_center
     say("  iterations %d, sims cold %d warm %d" % (stc.iterations, stc.sims_point_center,
                                                   stw.sims_point_center))
-    # and the result is the oracle's Lloyd fit from the same centres
+    # and the result is the oracle's Lloyd fit from the oracle's own seeding
+    # with the same uniforms
     if variant == "hamerly":
-        ref = oracle.fit(X, C.cpu().numpy(), "lloyd", 60)
+        ch_ref, _, _, _ = oracle.kmeanspp(X, k, 1.0, u)
+        assert np.array_equal(ch.cpu().numpy(), ch_ref)
+        ref = oracle.fit(X, datagen.init_centers_csr(X, ch_ref), "lloyd", 60)
         assert ref.iterations == stw.iterations
         assert np.array_equal(aw.cpu().numpy(), ref.a)
 
