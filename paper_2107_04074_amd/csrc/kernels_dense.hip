@@ -68,6 +68,13 @@ struct MfmaCfg<false> {
 // Selects instead of fmaxf keep NaN canonicalisation out of the loop; the
 // inputs are finite.  Mode 1 emits every centre at or above the row's
 // threshold.  `ragged` masks centres >= k (only the last tile has them).
+// Median of three unsigned integers, one instruction.
+__device__ __forceinline__ unsigned umed3(unsigned a, unsigned b, unsigned c) {
+  unsigned r;
+  asm("v_med3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+  return r;
+}
+
 template <int MODE>
 __device__ __forceinline__ void tile_epilogue(const f32x16& acc, int jb, int k, bool ragged,
                                               float& m1, int& j1, float& m2, float thr,
@@ -102,6 +109,28 @@ __device__ __forceinline__ void tile_epilogue(const f32x16& acc, int jb, int k, 
   }
 }
 
+// Direct load of centres [c0, c0 + CC) into one LDS chunk buffer with
+// padded rows of dp + 8 elements (buffer loads that write LDS: no registers,
+// and unlike the global form they leave the LDS-read wait counts exact).  A
+// wave-wide load fills 64 consecutive 16-byte units of the buffer; units
+// that fall on a row's padding slot are masked off.  The resource covers the
+// whole centre array, and the hardware returns zero past its end.
+template <int CC, int dp, int WAVES>
+__device__ __forceinline__ void fetch_chunk(__amdgpu_buffer_rsrc_t res, int c0, __bf16* dst,
+                                            int wave, int lane) {
+  constexpr int PR = dp / 8;              // 16-byte units per centre row
+  constexpr int NI = CC * (PR + 1) / 64;  // wave-wide loads per chunk
+#pragma unroll
+  for (int q = wave; q < NI; q += WAVES) {
+    const int v = q * 64 + lane;
+    const int r = v / (PR + 1), u = v - r * (PR + 1);
+    if (u < PR)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(
+          res, (__attribute__((address_space(3))) void*)(dst + q * 512), 16,
+          ((c0 + r) * dp + u * 8) * 2, 0, 0, 0);
+  }
+}
+
 // Rows x centres on MFMA.  rows: list of row ids (nullable = identity),
 // count from *rows_count (nullable = n_rows).
 //   mode 0: writes best value, its centre, second best (per row, in slot
@@ -114,14 +143,19 @@ __global__ __launch_bounds__(MfmaCfg<BF16>::WAVES * 64) void k_dense_sim(DenseSi
   constexpr int kDenseWaves = Cfg::WAVES;
   typedef typename Cfg::elem E;
   constexpr int KSTEP = Cfg::KSTEP, RT = Cfg::RT, CC = Cfg::CC;
+  // BF16 top-2 pass: values offset by 2 and packed with their place
+  constexpr bool kPack = BF16 && MODE == 0;
   constexpr int ROWS_PER_WAVE = 32 * RT;
   constexpr int ROWS_PER_BLOCK = ROWS_PER_WAVE * kDenseWaves;
   extern __shared__ char smem[];
-  E* lds = reinterpret_cast<E*>(smem);
+  E* lds = reinterpret_cast<E*>(smem);  // FP32: one staged chunk
+  constexpr int ldsw = DP + (BF16 ? 8 : 4);  // padded LDS row stride (16-byte aligned)
+  // BF16: two chunk buffers for the direct loads
+  __shared__ __attribute__((aligned(16))) E ldsA[BF16 ? Cfg::CC * ldsw : 8];
+  __shared__ __attribute__((aligned(16))) E ldsB[BF16 ? Cfg::CC * ldsw : 8];
   // candidate mode: per-row candidate counts of the block's current rows
   __shared__ int lcnt[MODE == 1 ? ROWS_PER_BLOCK : 1];
   constexpr int dp = DP;
-  constexpr int ldsw = dp + (BF16 ? 8 : 4);  // padded LDS row stride (16-byte aligned)
   constexpr int nsteps = dp / KSTEP;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -171,39 +205,133 @@ __global__ __launch_bounds__(MfmaCfg<BF16>::WAVES * 64) void k_dense_sim(DenseSi
     int j1[RT];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
-      m1[rt] = -INFINITY;
-      m2[rt] = -INFINITY;
+      m1[rt] = kPack ? 0.f : -INFINITY;  // packed: the smallest pattern
+      m2[rt] = kPack ? 0.f : -INFINITY;
       j1[rt] = INT_MAX;
       thr[rt] = (MODE == 1 && rowid[rt] >= 0) ? A.thr[slot[rt]] : INFINITY;
     }
 
-    for (int c0 = 0; c0 < A.kpad; c0 += CC) {
-      __syncthreads();
-      // stage centres [c0, c0 + CC) into LDS, 16 bytes per thread and step;
-      // all loads are issued before the first LDS write
-      {
-        constexpr int VEC = 16 / sizeof(E);
-        constexpr int per_row = dp / VEC;
-        constexpr int NT = kDenseWaves * 64;
-        constexpr int TOTAL = CC * per_row;
-        constexpr int STEPS = (TOTAL + NT - 1) / NT;
-        float4 st[STEPS];
+    // BF16 top-2 pass, software-pipelined over tiles: while the products of
+    // one tile run, the previous tile's values are folded into per-lane
+    // top-2 patterns (a few integer operations between MFMAs), so the matrix
+    // core does not wait for the fold.  A tile that reaches past k is folded
+    // after the products with its padding centres masked off.
+    constexpr int PRT = kPack ? RT : 1;
+    f32x16 prv[PRT];
+    unsigned pt1[PRT], pt2[PRT];
+    int prv_jb = 0, prv_state = 0;  // 0 none, 1 whole tile, 2 tile reaching past k
 #pragma unroll
-        for (int q = 0; q < STEPS; ++q) {
-          const int e = threadIdx.x + q * NT;
-          const int r = e / per_row, c = (e - r * per_row) * VEC;
-          if (TOTAL % NT == 0 || e < TOTAL)
-            st[q] = *reinterpret_cast<const float4*>(Ce + (size_t)(c0 + r) * dp + c);
-        }
+    for (int rt = 0; rt < PRT; ++rt) {
 #pragma unroll
-        for (int q = 0; q < STEPS; ++q) {
-          const int e = threadIdx.x + q * NT;
-          const int r = e / per_row, c = (e - r * per_row) * VEC;
-          if (TOTAL % NT == 0 || e < TOTAL)
-            *reinterpret_cast<float4*>(lds + r * ldsw + c) = st[q];
+      for (int i = 0; i < 16; ++i) prv[rt][i] = 0.f;
+      pt1[rt] = pt2[rt] = 0u;
+    }
+    // Value i of a tile into a lane's running top-2.  The accumulator starts
+    // at 2, so a value v arrives as v + 2, in [1, 4), where bit patterns
+    // order like values; the low four bits of the pattern are replaced by
+    // the value's place in the tile (15 - i, so that the earlier centre wins
+    // an exact tie).  The top-2 is then an integer maximum and
+    // median-of-three per value, and the place of the maximum is read back
+    // from its bits.  m1 and m2 hold such patterns; masked values (centres
+    // beyond k) count as the smallest pattern.
+    auto fold = [&](const f32x16& v, int i, bool masked, int jbase, unsigned& t1,
+                    unsigned& t2) __attribute__((always_inline)) {
+      const int off = 8 * (i >> 2) + (i & 3);
+      const unsigned pv = (__float_as_uint(v[i]) & 0xFFFFFFF0u) | (15u - i);
+      const unsigned q = (!masked || jbase + off < A.k) ? pv : 0u;
+      t2 = umed3(t1, t2, q);
+      t1 = max(t1, q);
+    };
+    // a folded tile into the row's running top-2 and best index
+    auto merge = [&](int rt, unsigned t1, unsigned t2, int jbase) __attribute__((always_inline)) {
+      const int i1 = 15 - (int)(t1 & 15u);
+      const int ti = 8 * (i1 >> 2) + (i1 & 3);
+      const unsigned k1 = __float_as_uint(m1[rt]), k2 = __float_as_uint(m2[rt]);
+      const bool gt = t1 > k1;
+      m2[rt] = __uint_as_float(max(umed3(k1, k2, t1), t2));
+      j1[rt] = gt ? jbase + ti : j1[rt];
+      m1[rt] = __uint_as_float(max(k1, t1));
+    };
+    // completes the previous tile: merge what was folded during the
+    // products, or fold it now (ragged, or nothing overlapped it)
+    auto finish_prev = [&](bool folded) __attribute__((always_inline)) {
+      if (prv_state == 1 && folded) {
+#pragma unroll
+        for (int rt = 0; rt < PRT; ++rt) merge(rt, pt1[rt], pt2[rt], prv_jb);
+      } else if (prv_state != 0) {
+        const bool masked = prv_state == 2;
+#pragma unroll
+        for (int rt = 0; rt < PRT; ++rt) {
+          unsigned t1 = 0u, t2 = 0u;
+#pragma unroll
+          for (int i = 0; i < 16; ++i) fold(prv[rt], i, masked, prv_jb, t1, t2);
+          merge(rt, t1, t2, prv_jb);
         }
       }
-      __syncthreads();
+    };
+    auto ptile = [&](int c0, const E* cur, int at) __attribute__((always_inline)) {
+      if constexpr (kPack) {
+        f32x16 acc[PRT];
+#pragma unroll
+        for (int rt = 0; rt < PRT; ++rt) {
+#pragma unroll
+          for (int i = 0; i < 16; ++i) acc[rt][i] = 2.f;
+          pt1[rt] = pt2[rt] = 0u;
+        }
+        const E* arow = cur + (at * 32 + (lane & 31)) * ldsw;
+        const bf16x8* ap = reinterpret_cast<const bf16x8*>(arow + 8 * (lane >> 5));
+        constexpr int VPI = 32 / NS;  // previous-tile values folded per step pair
+        bf16x8 a0 = ap[0], a1 = ap[2];
+#pragma unroll
+        for (int s = 0; s < NS; s += 2) {
+          // the next step pair's fragments are read before this pair's MFMAs
+          bf16x8 n0 = a0, n1 = a1;
+          if (s + 2 < NS) {
+            n0 = ap[2 * (s + 2)];
+            n1 = ap[2 * (s + 3)];
+          }
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int rt = 0; rt < PRT; ++rt)
+            acc[rt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, bfr[rt][s], acc[rt], 0, 0, 0);
+#pragma unroll
+          for (int rt = 0; rt < PRT; ++rt)
+            acc[rt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, bfr[rt][s + 1], acc[rt], 0, 0, 0);
+          // (folded unconditionally: the result is used only for a whole
+          // previous tile, so no branch splits the MFMAs from the folds)
+#pragma unroll
+          for (int rt = 0; rt < PRT; ++rt)
+#pragma unroll
+            for (int q = 0; q < VPI; ++q)
+              fold(prv[rt], (s / 2) * VPI + q, false, prv_jb, pt1[rt], pt2[rt]);
+          // issue order: the two fragment reads, then each MFMA followed by a
+          // few fold operations, which run while that MFMA occupies the unit
+          __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+#pragma unroll
+          for (int g = 0; g < 2 * PRT; ++g) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x002, 3 * VPI / 2, 0);
+          }
+          __builtin_amdgcn_sched_barrier(0);
+          a0 = n0;
+          a1 = n1;
+        }
+        finish_prev(true);
+#pragma unroll
+        for (int rt = 0; rt < PRT; ++rt) prv[rt] = acc[rt];
+        prv_jb = c0 + at * 32 + 4 * (lane >> 5);
+        prv_state = (c0 + at * 32 + 32 <= A.k) ? 1 : 2;
+      }
+    };
+
+    // one chunk of CC centres against the wave's rows, from LDS at cur
+    auto chunk = [&](int c0, const E* cur) __attribute__((always_inline)) {
+      if constexpr (kPack) {
+#pragma unroll
+        for (int at = 0; at < CC / 32; ++at) ptile(c0, cur, at);
+        return;
+      }
+      // candidate pass (and FP32): products, then the tile's epilogue
 #pragma unroll
       for (int at = 0; at < CC / 32; ++at) {
         f32x16 acc[RT];
@@ -211,15 +339,34 @@ __global__ __launch_bounds__(MfmaCfg<BF16>::WAVES * 64) void k_dense_sim(DenseSi
         for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
           for (int i = 0; i < 16; ++i) acc[rt][i] = 0.f;
-        const E* arow = lds + (at * 32 + (lane & 31)) * ldsw;
+        const E* arow = cur + (at * 32 + (lane & 31)) * ldsw;
+        if constexpr (BF16) {
+          // fragments of K steps s + 2, s + 3 are read from LDS before the
+          // products of steps s, s + 1 are issued (the scheduling fences
+          // keep that order), so LDS latency hides behind four MFMAs
+          const bf16x8* ap = reinterpret_cast<const bf16x8*>(arow + 8 * (lane >> 5));
+          bf16x8 a0 = ap[0], a1 = ap[2];
 #pragma unroll
-        for (int s = 0; s < NS; ++s) {
-          if constexpr (BF16) {
-            const bf16x8 a = *reinterpret_cast<const bf16x8*>(arow + s * KSTEP + 8 * (lane >> 5));
+          for (int s = 0; s < NS; s += 2) {
+            bf16x8 n0 = a0, n1 = a1;
+            if (s + 2 < NS) {
+              n0 = ap[2 * (s + 2)];
+              n1 = ap[2 * (s + 3)];
+            }
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int rt = 0; rt < RT; ++rt)
-              acc[rt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bfr[rt][s], acc[rt], 0, 0, 0);
-          } else {
+              acc[rt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, bfr[rt][s], acc[rt], 0, 0, 0);
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+              acc[rt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, bfr[rt][s + 1], acc[rt], 0, 0, 0);
+            __builtin_amdgcn_sched_barrier(0);
+            a0 = n0;
+            a1 = n1;
+          }
+        } else {
+#pragma unroll
+          for (int s = 0; s < NS; ++s) {
             const float a = arow[s * KSTEP + (lane >> 5)];
 #pragma unroll
             for (int rt = 0; rt < RT; ++rt)
@@ -242,7 +389,65 @@ __global__ __launch_bounds__(MfmaCfg<BF16>::WAVES * 64) void k_dense_sim(DenseSi
                                                               (int)(slot[rt] - blk), A);
         }
       }
+    };
+
+    if constexpr (BF16) {
+      // Centres reach LDS by direct buffer-to-LDS loads (no registers) into
+      // two buffers: chunk c + 1 is in flight while chunk c is multiplied.
+      // A wave-wide load fills 64 consecutive 16-byte units; units that fall
+      // on a row's padding slot are masked off.  The two buffers are
+      // separate arrays and the loop alternates them statically, so the
+      // wait for a load into one buffer is never placed before reads of the
+      // other.
+      // raw buffer over the kpad x dp centre array (32-bit data format word)
+      const __amdgpu_buffer_rsrc_t cres = __builtin_amdgcn_make_buffer_rsrc(
+          const_cast<E*>(Ce), (short)0, A.kpad * dp * 2, 0x00020000);
+      // every wave is done with both buffers (previous row block)
+      __syncthreads();
+      fetch_chunk<CC, dp, kDenseWaves>(cres, 0, ldsA, wave, lane);
+      for (int c0 = 0; c0 < A.kpad; c0 += 2 * CC) {
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+        if (c0 + CC < A.kpad) fetch_chunk<CC, dp, kDenseWaves>(cres, c0 + CC, ldsB, wave, lane);
+        chunk(c0, ldsA);
+        if (c0 + CC < A.kpad) {
+          asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+          __syncthreads();
+          if (c0 + 2 * CC < A.kpad)
+            fetch_chunk<CC, dp, kDenseWaves>(cres, c0 + 2 * CC, ldsA, wave, lane);
+          chunk(c0 + CC, ldsB);
+        }
+      }
+    } else {
+      for (int c0 = 0; c0 < A.kpad; c0 += CC) {
+        __syncthreads();
+        // stage centres [c0, c0 + CC) into LDS, 16 bytes per thread and
+        // step; all loads are issued before the first LDS write
+        constexpr int VEC = 16 / sizeof(E);
+        constexpr int per_row = dp / VEC;
+        constexpr int NT = kDenseWaves * 64;
+        constexpr int TOTAL = CC * per_row;
+        constexpr int STEPS = (TOTAL + NT - 1) / NT;
+        float4 st[STEPS];
+#pragma unroll
+        for (int q = 0; q < STEPS; ++q) {
+          const int e = threadIdx.x + q * NT;
+          const int r = e / per_row, c = (e - r * per_row) * VEC;
+          if (TOTAL % NT == 0 || e < TOTAL)
+            st[q] = *reinterpret_cast<const float4*>(Ce + (size_t)(c0 + r) * dp + c);
+        }
+#pragma unroll
+        for (int q = 0; q < STEPS; ++q) {
+          const int e = threadIdx.x + q * NT;
+          const int r = e / per_row, c = (e - r * per_row) * VEC;
+          if (TOTAL % NT == 0 || e < TOTAL)
+            *reinterpret_cast<float4*>(lds + r * ldsw + c) = st[q];
+        }
+        __syncthreads();
+        chunk(c0, lds);
+      }
     }
+    if constexpr (kPack) finish_prev(false);  // the last tile
     if (MODE == 1) {
       __syncthreads();
       for (int i = threadIdx.x; i < ROWS_PER_BLOCK; i += kDenseWaves * 64)
@@ -255,14 +460,33 @@ __global__ __launch_bounds__(MfmaCfg<BF16>::WAVES * 64) void k_dense_sim(DenseSi
         const float om1 = __shfl_xor(m1[rt], 32, 64);
         const float om2 = __shfl_xor(m2[rt], 32, 64);
         const int oj1 = __shfl_xor(j1[rt], 32, 64);
-        float b = m1[rt], s2v = fmaxf(m2[rt], om2);
+        float b, s2v;
         int bj = j1[rt];
-        if (om1 > b || (om1 == b && oj1 < bj)) {
-          s2v = fmaxf(s2v, b);
-          b = om1;
-          bj = oj1;
+        if constexpr (kPack) {
+          // patterns of values offset by 2: compare as integers, then undo
+          // the offset (exact for patterns in [1, 4))
+          const unsigned a1 = __float_as_uint(m1[rt]), a2 = __float_as_uint(m2[rt]);
+          const unsigned o1 = __float_as_uint(om1), o2 = __float_as_uint(om2);
+          unsigned kb = a1, ks = max(a2, o2);
+          if (o1 > kb || (o1 == kb && oj1 < bj)) {
+            ks = max(ks, kb);
+            kb = o1;
+            bj = oj1;
+          } else {
+            ks = max(ks, o1);
+          }
+          b = __uint_as_float(kb) - 2.f;
+          s2v = A.k > 1 ? __uint_as_float(ks) - 2.f : -INFINITY;  // k = 1: no second
         } else {
-          s2v = fmaxf(s2v, om1);
+          b = m1[rt];
+          s2v = fmaxf(m2[rt], om2);
+          if (om1 > b || (om1 == b && oj1 < bj)) {
+            s2v = fmaxf(s2v, b);
+            b = om1;
+            bj = oj1;
+          } else {
+            s2v = fmaxf(s2v, om1);
+          }
         }
         if (lane < 32 && rowid[rt] >= 0) {
           A.best[slot[rt]] = b;
@@ -275,13 +499,19 @@ __global__ __launch_bounds__(MfmaCfg<BF16>::WAVES * 64) void k_dense_sim(DenseSi
 }
 
 
-// Rigorous bound on |s_hat - <x, c>| for one row of the dense contraction:
-// BF16 rounds x and the centre copy (2^-9 each, RNE) with exact products and
-// FP32 accumulation over dp terms; FP32 rounds the centre copy and every
-// product and sum.
+// Rigorous bound on |s_hat - <x, c>| for one row of the dense contraction.
+// BF16: x is rounded once to BF16 and the centre twice (FP64 -> FP32 ->
+// BF16), relative errors 2^-8 and 2^-8 + 2^-24 (8-bit significand, RNE);
+// products are exact; the FP32 accumulation starts at 2 (the top-2 pass
+// offsets values by 2) so every partial sum is below 3 |x||c| + 2, taken with
+// unit 2^-23 to cover accumulation that truncates; replacing four low bits
+// of the offset value and removing the offset add below 2^-17.
+// FP32: the centre copy, every product and every sum (unit 2^-23 for the
+// sums, as above).  Both are relative to sum |x_t c_t| <= |x| |c| <= 1 + eta.
 __device__ __forceinline__ double dense_eps(bool bf16, int dp, double eta) {
-  const double unit = bf16 ? (2.0 * 0.001953125 + 3.814697265625e-06 + (dp + 2) * kU32)
-                           : ((dp + 3) * kU32);
+  const double unit = bf16 ? (2.0 * 0.00390625 + 1.52587890625e-05 + 2.0 * kU32 +
+                              6.0 * (dp + 2) * kU32 + 7.62939453125e-06)
+                           : ((2 * dp + 3) * kU32);
   return unit * (1.0 + eta) * 1.01;
 }
 
@@ -722,8 +952,8 @@ __global__ __launch_bounds__(kBlock) void k_dense_row_eta(const float* __restric
 
 }  // namespace
 
-size_t dense_sim_lds_bytes(bool bf16, int dp) {
-  if (bf16) return (size_t)MfmaCfg<true>::CC * (dp + 8) * 2;
+size_t dense_sim_lds_bytes(bool bf16, int dp) {  // dynamic part (BF16 buffers are static)
+  if (bf16) return 0;
   return (size_t)MfmaCfg<false>::CC * (dp + 4) * 4;
 }
 
@@ -734,6 +964,8 @@ hipError_t launch_dense_sim(const DenseSimArgs& A, bool bf16, int mode, hipStrea
   if (blocks > 4 * kMaxGridBlocks) blocks = 4 * kMaxGridBlocks;
   if (blocks < 1) blocks = 1;
   const size_t lds = dense_sim_lds_bytes(bf16, A.dp);
+  // BF16 centres are read through a buffer resource with 32-bit byte offsets
+  if (bf16 && (int64_t)A.kpad * A.dp * 2 > (int64_t)INT32_MAX) return hipErrorInvalidValue;
   const dim3 grid((unsigned)blocks), block(waves * 64);
 #define SKM_DS(B, M, D) \
   hipLaunchKernelGGL((k_dense_sim<B, M, D>), grid, block, lds, s, A)

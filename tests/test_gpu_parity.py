@@ -361,6 +361,26 @@ def test_dense_fit_small_matches_oracle(skm, torch_cuda, precision):
             assert np.array_equal(a, base[0]) and np.array_equal(C64, base[1])
 
 
+@pytest.mark.parametrize("d,k", [(37, 5), (100, 45), (200, 100), (64, 33)])
+def test_dense_bf16_ragged_matches_oracle(skm, torch_cuda, d, k):
+    """BF16 top-2 pass where the last centre tiles reach past k (k not a
+    multiple of 32, down to a tile of padding only) at the padded widths
+    dp = 64, 128 and 256: whole trajectories equal the oracle's."""
+    torch = torch_cuda
+    X = datagen.dense_vmf(4000, d, max(4, k // 2), 900 + d)
+    C0 = X[datagen.init_rows(X.shape[0], k, 77 + k)].copy()
+    Xd = skm.DeviceDense.from_host(X)
+    ref = oracle.fit(dense_csr(X), C0, "lloyd", 25)
+    for v in ["lloyd", "hamerly"]:
+        say("case dense bf16 ragged d=%d k=%d %s" % (d, k, v))
+        a, C, C64, st = run_fit(skm, torch, Xd, C0, k, v, 25, precision=1)
+        say("  iters=%d rechecks=%d (oracle iters %d)" % (st.iterations, st.rechecks,
+                                                         ref.iterations))
+        assert st.iterations == ref.iterations
+        assert np.array_equal(a, ref.a)
+        assert np.linalg.norm(C64 - ref.C, axis=1).max() < 1e-6
+
+
 def test_c4_full_size_bf16_subsample(skm, torch_cuda):
     """Full c4 workload (n=2e6 vMF rows, d=256, k=4096), BF16 MFMA with
     error-widened bounds: step 1 from the initial centres against FP64 on a
