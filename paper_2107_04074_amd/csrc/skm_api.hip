@@ -462,7 +462,9 @@ int fit_dense(const skm_matrix* X, int32_t k, const float* init_centers, int32_t
   DenseRun R{P, X, ws, s};
   const int64_t n = P.n, d = P.d;
   const double delta_c = (double)(d + 8) * kU64 * 1.01 + 1e-300;
-  const double delta_g = (double)(d + 2) * kU64 * 1.01 + 2.0 * delta_c + 1e-15;
+  // Gram entries on FP64 matrix cores: unit 2^-52 also covers accumulation
+  // that truncates
+  const double delta_g = (double)(d + 2) * 2.0 * kU64 * 1.01 + 2.0 * delta_c + 1e-15;
   const double fx = fixed_point_scale(n);
   const double fx_inv = 1.0 / fx;
   double* C64 = R.ptr<double>(P.C64);
@@ -837,7 +839,9 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
 
   const int64_t n = P.n, d = P.d;
   const double delta_c = (double)(d + 8) * kU64 * 1.01 + 1e-300;
-  const double delta_g = (double)(d + 2) * kU64 * 1.01 + 2.0 * delta_c + 1e-15;
+  // Gram entries on FP64 matrix cores: unit 2^-52 also covers accumulation
+  // that truncates
+  const double delta_g = (double)(d + 2) * 2.0 * kU64 * 1.01 + 2.0 * delta_c + 1e-15;
   const double fx = fixed_point_scale(n);
   const double fx_inv = 1.0 / fx;
 
