@@ -1,12 +1,16 @@
 // Dense-row kernels for gfx950: the similarity contraction of the assignment
 // step (Section 5) on MFMA matrix cores, in BF16 (FP32 accumulate) or FP32.
 //
+//  k_dense_prep     one pass over the rows: the bound on | |x(i)| - 1 | per
+//                   row and, for BF16, the padded BF16 copy of the rows.
 //  k_dense_sim      rows x centres on MFMA.  Centres are streamed through LDS
-//                   in chunks shared by the block's waves; every wave keeps
+//                   in chunks shared by the block's waves (BF16: loaded into
+//                   two buffers directly, one chunk ahead); every wave keeps
 //                   its rows' operand fragments in registers for the whole
 //                   centre loop.  Epilogue: running top-2 per row (assignment,
-//                   bounds) or, in candidate mode, every centre within the
-//                   error band of the row's best value.
+//                   bounds; BF16 folds a tile while the next one multiplies)
+//                   or, in candidate mode, every centre within the error band
+//                   of the row's best value.
 //  k_dense_exact    FP64 re-decision of the rows whose best and second best
 //                   lie within the rigorous error band: one canonical FP64
 //                   chain per candidate against the FP64 master centre.
@@ -894,15 +898,6 @@ __global__ __launch_bounds__(kBlock) void k_copy_assign(const int32_t* __restric
 }
 
 // ---- conversions ----
-__global__ __launch_bounds__(kBlock) void k_rows_to_bf16(const float* __restrict__ X, int64_t ldx,
-                                                         int64_t n, int64_t d, int dp,
-                                                         __bf16* __restrict__ Xb) {
-  const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const int64_t i = e / dp;
-  const int t = (int)(e - i * dp);
-  if (i < n) Xb[e] = (__bf16)(t < d ? X[(size_t)i * ldx + t] : 0.f);
-}
-
 // FP64 masters -> packed MFMA operand rows (bf16 or f32), dirty rows only.
 __global__ __launch_bounds__(kBlock) void k_pack_centres(const double* __restrict__ C64,
                                                          int32_t k, int64_t d, int dp,
@@ -917,29 +912,55 @@ __global__ __launch_bounds__(kBlock) void k_pack_centres(const double* __restric
   }
 }
 
-// | |x_i| - 1 | for dense rows, one wave per row.
-__global__ __launch_bounds__(kBlock) void k_dense_row_eta(const float* __restrict__ X, int64_t ldx,
-                                                          int64_t n, int64_t d,
-                                                          float* __restrict__ eta,
-                                                          float* __restrict__ max_eta) {
+// One pass over dense rows: | |x_i| - 1 | bound per row (FP64 sum of squares)
+// and, when Xb is given, the BF16 copy padded to dp columns.  One wave per
+// row, grid-strided; lane l takes columns 4l .. 4l + 3 of every 256-column
+// step (one 16-byte load when the rows allow it).
+__global__ __launch_bounds__(kBlock) void k_dense_prep(const float* __restrict__ X, int64_t ldx,
+                                                       int64_t n, int64_t d, int dp, int vec,
+                                                       float* __restrict__ eta,
+                                                       float* __restrict__ max_eta,
+                                                       __bf16* __restrict__ Xb) {
+  typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
   const int lane = threadIdx.x & 63;
-  const int64_t i = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
-  float e32 = 0.f;
-  if (i < n) {
+  const int64_t w0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
+  const int64_t nw = ((int64_t)gridDim.x * kBlock) >> 6;
+  const int width = Xb ? dp : (int)d;  // dp >= d; columns d .. dp - 1 of the copy are 0
+  float emax = 0.f;
+  for (int64_t i = w0; i < n; i += nw) {
+    const float* xr = X + (size_t)i * ldx;
     double ss = 0.0;
-    for (int64_t t = lane; t < d; t += 64) {
-      const double x = X[(size_t)i * ldx + t];
-      ss = fma(x, x, ss);
+    for (int c = 4 * lane; c < width; c += 256) {
+      float v[4];
+      if (vec && c + 3 < d) {
+        const float4 q = *reinterpret_cast<const float4*>(xr + c);
+        v[0] = q.x;
+        v[1] = q.y;
+        v[2] = q.z;
+        v[3] = q.w;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] = (c + e < d) ? xr[c + e] : 0.f;
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) ss = fma((double)v[e], (double)v[e], ss);
+      if (Xb) {
+        bf16x4 b;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) b[e] = (__bf16)v[e];
+        *reinterpret_cast<bf16x4*>(Xb + (size_t)i * dp + c) = b;
+      }
     }
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) ss += __shfl_xor(ss, off, 64);
     const double dev = fabs(sqrt(ss) - 1.0) + (double)(d + 4) * kU64 * 2.0 + 1e-300;
-    e32 = __double2float_ru(dev);
+    const float e32 = __double2float_ru(dev);
     if (lane == 0) eta[i] = e32;
+    emax = fmaxf(emax, e32);
   }
   if (max_eta) {
     __shared__ float wmax[kBlock / 64];
-    if (lane == 0) wmax[threadIdx.x >> 6] = e32;
+    if (lane == 0) wmax[threadIdx.x >> 6] = emax;
     __syncthreads();
     if (threadIdx.x == 0) {
       float m = 0.f;
@@ -1080,13 +1101,6 @@ hipError_t launch_copy_assign(const int32_t* a, int32_t* a_old, int64_t n, hipSt
   return hipGetLastError();
 }
 
-hipError_t launch_rows_to_bf16(const float* X, int64_t ldx, int64_t n, int64_t d, int dp,
-                               void* Xb, hipStream_t s) {
-  hipLaunchKernelGGL(k_rows_to_bf16, dim3(nblocks(n * dp)), dim3(kBlock), 0, s, X, ldx, n, d, dp,
-                     reinterpret_cast<__bf16*>(Xb));
-  return hipGetLastError();
-}
-
 hipError_t launch_pack_centres(const double* C64, int32_t k, int64_t d, int dp,
                                const int32_t* dirty, int bf16, void* out, hipStream_t s) {
   hipLaunchKernelGGL(k_pack_centres, dim3((unsigned)k), dim3(kBlock), 0, s, C64, k, d, dp, dirty,
@@ -1094,10 +1108,14 @@ hipError_t launch_pack_centres(const double* C64, int32_t k, int64_t d, int dp,
   return hipGetLastError();
 }
 
-hipError_t launch_dense_row_eta(const float* X, int64_t ldx, int64_t n, int64_t d, float* eta,
-                                float* max_eta, hipStream_t s) {
-  hipLaunchKernelGGL(k_dense_row_eta, dim3(nblocks(n * 64)), dim3(kBlock), 0, s, X, ldx, n, d,
-                     eta, max_eta);
+hipError_t launch_dense_prep(const float* X, int64_t ldx, int64_t n, int64_t d, int dp,
+                             float* eta, float* max_eta, void* Xb, hipStream_t s) {
+  const int vec = ((uintptr_t)X % 16 == 0 && ldx % 4 == 0) ? 1 : 0;
+  int64_t blocks = (n + kBlock / 64 - 1) / (kBlock / 64);
+  if (blocks > 8192) blocks = 8192;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_dense_prep, dim3((unsigned)blocks), dim3(kBlock), 0, s, X, ldx, n, d, dp,
+                     vec, eta, max_eta, reinterpret_cast<__bf16*>(Xb));
   return hipGetLastError();
 }
 

@@ -500,11 +500,10 @@ int fit_dense(const skm_matrix* X, int32_t k, const float* init_centers, int32_t
     SKM_HIP(hipMemsetAsync(norm64, 0, (size_t)k * 8, s));
     SKM_HIP(hipMemsetAsync(R.ptr<float>(P.maxeta), 0, kCounterSlots * 4, s));
     SKM_HIP(launch_fill_i32(a_old, n, -1, s));
-    SKM_HIP(launch_dense_row_eta(X->dense, X->ld, n, d, R.ptr<float>(P.eta),
-                                 R.ptr<float>(P.maxeta), s));
+    SKM_HIP(launch_dense_prep(X->dense, X->ld, n, d, P.dp, R.ptr<float>(P.eta),
+                              R.ptr<float>(P.maxeta), P.bf16 ? R.ptr<char>(P.Xb) : nullptr, s));
     SKM_HIP(launch_init_centres(init_centers, k, d, 1, C64, R.ptr<double>(P.initnorm), s));
     SKM_HIP(launch_pack_centres(C64, k, d, P.dp, nullptr, P.bf16, Cp, s));
-    if (P.bf16) SKM_HIP(launch_rows_to_bf16(X->dense, X->ld, n, d, P.dp, R.ptr<char>(P.Xb), s));
     if (o.validate >= 1) {
       float hslots[kCounterSlots];
       float hmax = 0.f;
@@ -673,7 +672,8 @@ int assign_dense(const skm_matrix* X, int32_t k, const float* centers, int32_t* 
     SKM_HIP(hipMemsetAsync(Cp, 0, (size_t)P.kpad * P.dp * 4, s));
     SKM_HIP(hipMemsetAsync(R.ptr<Persist>(P.per), 0, sizeof(Persist), s));
     SKM_HIP(hipMemsetAsync(R.ptr<Counters>(P.cnt), 0, kCounterSlots * sizeof(Counters), s));
-    SKM_HIP(launch_dense_row_eta(X->dense, X->ld, P.n, P.d, R.ptr<float>(P.eta), nullptr, s));
+    SKM_HIP(launch_dense_prep(X->dense, X->ld, P.n, P.d, P.dp, R.ptr<float>(P.eta), nullptr,
+                              nullptr, s));
     SKM_HIP(launch_init_centres(centers, k, P.d, 0, C64, nullptr, s));
     SKM_HIP(launch_pack_centres(C64, k, P.d, P.dp, nullptr, 0, Cp, s));
     SKM_HIP(dense_step(R, assign_out, 0, nullptr, nullptr, best_out, second_out,

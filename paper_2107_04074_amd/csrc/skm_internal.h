@@ -262,12 +262,10 @@ hipError_t launch_dense_update_scan(const float* X, int64_t ldx, const int32_t* 
                                     int32_t* a_old, int64_t n, int64_t d, double fx,
                                     long long* S, int32_t* dirty, hipStream_t s);
 hipError_t launch_copy_assign(const int32_t* a, int32_t* a_old, int64_t n, hipStream_t s);
-hipError_t launch_rows_to_bf16(const float* X, int64_t ldx, int64_t n, int64_t d, int dp,
-                               void* Xb, hipStream_t s);
 hipError_t launch_pack_centres(const double* C64, int32_t k, int64_t d, int dp,
                                const int32_t* dirty, int bf16, void* out, hipStream_t s);
-hipError_t launch_dense_row_eta(const float* X, int64_t ldx, int64_t n, int64_t d, float* eta,
-                                float* max_eta, hipStream_t s);
+hipError_t launch_dense_prep(const float* X, int64_t ldx, int64_t n, int64_t d, int dp,
+                             float* eta, float* max_eta, void* Xb, hipStream_t s);
 
 // ---- launchers (kernels_assign.hip) ----
 hipError_t launch_assign(const AssignArgs& A, int mode, hipStream_t s);
