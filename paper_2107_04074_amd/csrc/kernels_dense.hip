@@ -102,13 +102,21 @@ __device__ __forceinline__ void tile_epilogue(const f32x16& acc, int jb, int k, 
     j1 = gt ? jb + ti : j1;
     m1 = gt ? t1 : m1;
   } else {
+    // a 16-bit mask of the values at or above the threshold first (no
+    // branches), then one append per set bit: few values pass
+    unsigned hit = 0u;
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
       const int j = jb + 8 * (i >> 2) + (i & 3);
-      if ((!ragged || j < k) && acc[i] >= thr && rowid >= 0) {
-        const int pos = atomicAdd(&lcnt[lrow], 1);  // LDS counter of the row
-        if (pos < A.cand_cap) A.cand[slot * A.cand_cap + pos] = j;
-      }
+      hit |= ((!ragged || j < k) && acc[i] >= thr) ? (1u << i) : 0u;
+    }
+    if (rowid < 0) hit = 0u;
+    while (hit) {
+      const int i = __builtin_ctz(hit);
+      hit &= hit - 1u;
+      const int j = jb + 8 * (i >> 2) + (i & 3);
+      const int pos = atomicAdd(&lcnt[lrow], 1);  // LDS counter of the row
+      if (pos < A.cand_cap) A.cand[slot * A.cand_cap + pos] = j;
     }
   }
 }
