@@ -241,6 +241,16 @@ def main():
     torch.cuda.synchronize()
     pruned_per_iter = [round(1.0 - float(x) / (n_rows * k), 4)
                        for x in st_pi.sims_per_iter[:st_pi.iterations]]
+    # the same with the bound tests at every step (schedule 1, as the paper
+    # runs them); the default schedule switches tests off while they prune
+    # little, and such steps prune nothing
+    pruned_tested = None
+    if vb != "lloyd":
+        _, _, _, st_ps = skm.fit(Xd, k, C0d, vb, max_iter, workspace=workspace(args.variant),
+                                 want_centers=False, per_iter=True, precision=vp, schedule=1)
+        torch.cuda.synchronize()
+        pruned_tested = [round(1.0 - float(x) / (n_rows * k), 4)
+                         for x in st_ps.sims_per_iter[:st_ps.iterations]]
     iters = sum(s.iterations for s in stats)
     ms_per_step = elapsed / args.steps * 1e3
     value = iters / elapsed
@@ -303,6 +313,7 @@ def main():
         "sims_per_s_lloyd_equiv": round(lloyd_equiv_sims / elapsed, 1),
         "pruned_fraction": round(1.0 - sims / lloyd_equiv_sims, 4),
         "pruned_per_iter": pruned_per_iter,
+        "pruned_per_iter_tests_every_step": pruned_tested,
         "rechecks_per_fit": st.rechecks,
         "variants": variants,
         "roofline": {

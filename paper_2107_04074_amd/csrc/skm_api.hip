@@ -486,8 +486,16 @@ int fit_dense(const skm_matrix* X, int32_t k, const float* init_centers, int32_t
   int32_t iterations = 0, converged = 0;
   int64_t tot_sims = 0, tot_rechecks = 0, sk_launches = 0, sk_rows = 0;
   double objective = 0.0, sk_ms = 0.0, tight_rate = 1.0;
-  bool first_gram = true;
+  bool first_gram = true, gram_stale = false;
   int gram_updates = 0, gram_since_exact = 0;
+  // The bound tests switch off while they do not pay; results are the same
+  // either way, since a step without tests is an exhaustive step that sets l
+  // and u afresh.  After a tested step that prunes fewer than
+  // kDenseTestMin of the rows, the next off_gap steps run exhaustively, the
+  // gap doubling from 2 up to 64 while tests keep failing (schedule = 1:
+  // tests at every step, as the paper runs them).
+  constexpr double kDenseTestMin = 0.15;
+  int32_t off_until = 0, off_gap = 2;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   {
     if (o.profile) {
@@ -518,7 +526,7 @@ int fit_dense(const skm_matrix* X, int32_t k, const float* init_centers, int32_t
     }
     for (int32_t t = 0; t < max_iter; ++t) {
       SKM_HIP(hipMemsetAsync(cnt, 0, kCounterSlots * sizeof(Counters), s));
-      const bool exhaustive = t == 0 || variant == SKM_LLOYD;
+      const bool exhaustive = t == 0 || variant == SKM_LLOYD || t < off_until;
       const int32_t* rows = nullptr;
       const unsigned long long* rows_count = nullptr;
       if (!exhaustive) {
@@ -558,6 +566,14 @@ int fit_dense(const skm_matrix* X, int32_t k, const float* init_centers, int32_t
       const Counters tc = sum_slots(hm);
       const int64_t changed = (int64_t)tc.changed;
       const int64_t walked = exhaustive ? n : (int64_t)hm->per.list_total;
+      if (!exhaustive && o.schedule == 0) {
+        if ((double)(n - walked) < kDenseTestMin * (double)n) {
+          off_until = t + 1 + off_gap;
+          off_gap = std::min(off_gap * 2, 64);
+        } else {
+          off_gap = 2;
+        }
+      }
       if (ev0) {
         float ms = 0.f;
         SKM_HIP(hipEventElapsedTime(&ms, ev0, ev1));
@@ -599,17 +615,22 @@ int fit_dense(const skm_matrix* X, int32_t k, const float* init_centers, int32_t
                                      ps, mm, per, s));
       SKM_HIP(launch_pack_centres(C64, k, d, P.dp, dirty, P.bf16, Cp, s));
       if (P.gram) {
-        if (gram_exact_step(gram_updates, gram_since_exact, changed, n)) {
-          // after carried steps every tile's partials are stale
-          SKM_HIP(launch_gram(C64, k, d, dirty, (first_gram || gram_since_exact > 0) ? 1 : 0,
-                              gpart, P.nslice, P.slice_len, G, gmax, delta_g, per, s));
+        if (t + 1 < off_until) {
+          gram_stale = true;  // no tests next step: the Gram waits for one that has them
+        } else if (gram_stale || gram_exact_step(gram_updates, gram_since_exact, changed, n)) {
+          // after carried or skipped steps every tile's partials are stale
+          SKM_HIP(launch_gram(C64, k, d, dirty,
+                              (first_gram || gram_since_exact > 0 || gram_stale) ? 1 : 0, gpart,
+                              P.nslice, P.slice_len, G, gmax, delta_g, per, s));
           first_gram = false;
+          gram_stale = false;
           gram_since_exact = 0;
+          ++gram_updates;
         } else {
           SKM_HIP(launch_gram_carry(G, k, pc, ps, delta_g, gmax, s));
           ++gram_since_exact;
+          ++gram_updates;
         }
-        ++gram_updates;
       }
       SKM_HIP(launch_clear_dirty(dirty, k, s));
     }

@@ -347,9 +347,13 @@ def test_dense_fit_small_matches_oracle(skm, torch_cuda, precision):
     Xc = dense_csr(X)
     ref = oracle.fit(Xc, C0, "lloyd", 40)
     base = None
-    for v in ["lloyd", "hamerly", "simp_hamerly"]:
-        say("case dense fit precision=%d %s" % (precision, v))
-        a, C, C64, st = run_fit(skm, torch, Xd, C0, 64, v, 40, precision=precision)
+    # schedule 1 runs the bound tests at every step; the default switches
+    # them off while they prune little
+    for v, sched in [("lloyd", 0), ("hamerly", 0), ("simp_hamerly", 0), ("hamerly", 1),
+                     ("simp_hamerly", 1)]:
+        say("case dense fit precision=%d %s schedule=%d" % (precision, v, sched))
+        a, C, C64, st = run_fit(skm, torch, Xd, C0, 64, v, 40, precision=precision,
+                                schedule=sched)
         say("  iters=%d sims=%d rechecks=%d (oracle iters %d)" % (
             st.iterations, st.sims_point_center, st.rechecks, ref.iterations))
         assert st.iterations == ref.iterations
@@ -371,9 +375,9 @@ def test_dense_bf16_ragged_matches_oracle(skm, torch_cuda, d, k):
     C0 = X[datagen.init_rows(X.shape[0], k, 77 + k)].copy()
     Xd = skm.DeviceDense.from_host(X)
     ref = oracle.fit(dense_csr(X), C0, "lloyd", 25)
-    for v in ["lloyd", "hamerly"]:
-        say("case dense bf16 ragged d=%d k=%d %s" % (d, k, v))
-        a, C, C64, st = run_fit(skm, torch, Xd, C0, k, v, 25, precision=1)
+    for v, sched in [("lloyd", 0), ("hamerly", 0), ("hamerly", 1)]:
+        say("case dense bf16 ragged d=%d k=%d %s schedule=%d" % (d, k, v, sched))
+        a, C, C64, st = run_fit(skm, torch, Xd, C0, k, v, 25, precision=1, schedule=sched)
         say("  iters=%d rechecks=%d (oracle iters %d)" % (st.iterations, st.rechecks,
                                                          ref.iterations))
         assert st.iterations == ref.iterations
