@@ -109,17 +109,17 @@ typedef struct {            /* [host]; an all-zero struct means defaults      */
                                with HIP events on `stream` (fills the
                                sim_kernel_* statistics; adds event records) */
   double norm_tol;          /* default 1e-4                                   */
-  /* Warm start (CSR input; all three set or all NULL): the result of the
-     first assignment step against init_centers, as skm_seed_kmeanspp
-     returns it -- assignment int32[n] and the FP64 best and second-best
-     similarities double[n] in the canonical order.  skm_fit then takes
+  /* Warm start (CSR or dense input; all three set or all NULL): the
+     result of the first assignment step against init_centers, as
+     skm_seed_kmeanspp returns it -- assignment int32[n] and the FP64 best
+     and second-best similarities double[n] in the canonical order.  skm_fit then takes
      that step from these arrays instead of recomputing it and sets its
      bounds from them, so pruning starts with the second step (the
      seeding/bounds synergy named in the paper's conclusion). */
   const int32_t* warm_assign;
   const double* warm_best;
   const double* warm_second;
-  int32_t schedule;         /* CSR bounded variants.  0 (default): the bound
+  int32_t schedule;         /* Bounded variants.  0 (default): the bound
                                tests (Sections 5.1-5.5) and the tightening of
                                l(i) run only while they prune enough to pay
                                for themselves, otherwise the step walks every
@@ -209,7 +209,9 @@ size_t skm_seed_workspace_size(const skm_matrix* X, int32_t k);
  * (alpha = 1: cosine dissimilarity; alpha = 1.5: the metric form), as the
  * first row whose running weight sum exceeds u[t] W (W = total weight).
  * Rows already chosen have weight 0 (no row is drawn twice); when W = 0 the
- * lowest-index row not yet chosen is taken.  CSR input only.
+ * lowest-index row not yet chosen is taken.  CSR or dense input (a dense
+ * row is treated as the CSR row that stores every column, so both give the
+ * same values).
  *   alpha          >= 1.
  *   uniforms       [host] double[k], each in [0, 1): the caller's draws.
  *   chosen_out     int32[k]: the chosen row indices in draw order.
@@ -238,7 +240,7 @@ size_t skm_seed_afkmc2_workspace_size(const skm_matrix* X, int32_t k, int32_t ch
  * (the first row whose running q sum exceeds the draw): the chain starts at
  * the first proposal and moves to proposal y when d(y) q(x) > u d(x) q(y),
  * with d(.) = max(0, alpha - max_c <., c>) over the centres chosen so far.
- * A row can be chosen twice.  CSR input only.
+ * A row can be chosen twice.  CSR or dense input.
  *   chain          >= 1 proposals per centre.
  *   alpha          >= 1.
  *   uniforms       [host] double[1 + (k-1)(2 chain - 1)] in [0, 1): u[0],

@@ -892,10 +892,10 @@ __global__ __launch_bounds__(kBlock) void k_warm_start(
     const int32_t* __restrict__ wa, const double* __restrict__ wb,
     const double* __restrict__ ws2, const float* __restrict__ eta, double delta_c,
     int32_t* __restrict__ a, float* __restrict__ l, float* __restrict__ u,
-    float* __restrict__ ue, float* __restrict__ uy, int32_t ng) {
+    float* __restrict__ ue, float* __restrict__ uy, int32_t ng, int64_t dense_d) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
-  const int64_t m = rp[i + 1] - rp[i];
+  const int64_t m = rp ? rp[i + 1] - rp[i] : dense_d;  // terms of the FP64 chain
   const double e = (double)eta[i];
   const double nx = (1.0 + e) * 1.01 + 1e-30;
   const double rho64 = (double)(m + 2) * kU64 * nx + 1.01 * (e + delta_c) + 1e-15;
@@ -988,10 +988,10 @@ hipError_t launch_assign_mode(const AssignArgs& A, hipStream_t s) {
 hipError_t launch_warm_start(const int64_t* rp, int64_t n, int32_t k, int32_t kp,
                              const int32_t* wa, const double* wb, const double* ws2,
                              const float* eta, double delta_c, int32_t* a, float* l, float* u,
-                             float* ue, float* uy, int32_t ng, hipStream_t s) {
+                             float* ue, float* uy, int32_t ng, hipStream_t s, int64_t dense_d) {
   const unsigned blocks = (unsigned)((n + kBlock - 1) / kBlock);
   hipLaunchKernelGGL(k_warm_start, dim3(blocks), dim3(kBlock), 0, s, rp, n, k, kp, wa, wb, ws2,
-                     eta, delta_c, a, l, u, ue, uy, ng);
+                     eta, delta_c, a, l, u, ue, uy, ng, dense_d);
   return hipGetLastError();
 }
 

@@ -28,16 +28,58 @@ namespace skm {
 namespace {
 using namespace dev;
 
+// The canonical FP64 similarity (dot64_serial / dot64_group) of a dense row:
+// a dense row is a CSR row that stores every column, entry t being column
+// t, so the partial sums, chains and pairwise tree are the same.
+__device__ __forceinline__ double dot64_serial_dense(const float* __restrict__ x, int64_t d,
+                                                     const double* __restrict__ c) {
+  double st[7];
+#pragma unroll
+  for (int p = 0; p < 64; ++p) {
+    double s = 0.0;
+    for (int64_t t = p; t < d; t += 64) s = fma((double)x[t], c[t], s);
+    int lev = 0;
+#pragma unroll
+    for (int q = p; q & 1; q >>= 1) s = st[lev++] + s;
+    st[lev] = s;
+  }
+  return st[6];
+}
+
+// One lane per partial sum (G = 64 lanes), then the same pairwise tree.
+__device__ __forceinline__ double dot64_wave_dense(const float* __restrict__ x, int64_t d,
+                                                   const double* __restrict__ c, int lane) {
+  double s = 0.0;
+  for (int64_t t = lane; t < d; t += 64) s = fma((double)x[t], c[t], s);
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) s += __shfl_xor(s, off, 64);
+  return s;
+}
+
+// Rows of either layout: CSR (rp, ci, v) or dense (x non-null, ld, d).
+struct SeedRows {
+  const int64_t* rp;
+  const int32_t* ci;
+  const float* v;
+  const float* x;
+  int64_t ld;
+};
+
+__device__ __forceinline__ double row_dot64(const SeedRows& R, int64_t i, int64_t d,
+                                            const double* __restrict__ c) {
+  if (R.x) return dot64_serial_dense(R.x + (size_t)i * R.ld, d, c);
+  return dot64_serial(R.ci, R.v, R.rp[i], R.rp[i + 1], c);
+}
+
 __global__ __launch_bounds__(kBlock) void k_kpp_update(
-    const int64_t* __restrict__ rp, const int32_t* __restrict__ ci, const float* __restrict__ v,
-    int64_t n, const double* __restrict__ c, int32_t t, double alpha,
+    SeedRows R, int64_t n, int64_t d, const double* __restrict__ c, int32_t t, double alpha,
     const uint8_t* __restrict__ taken, int32_t* __restrict__ a, double* __restrict__ best,
     double* __restrict__ second, double* __restrict__ w, double* __restrict__ part) {
   __shared__ double sw[kBlock];
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   double wi = 0.0;
   if (i < n) {
-    const double s = dot64_serial(ci, v, rp[i], rp[i + 1], c);
+    const double s = row_dot64(R, i, d, c);
     double b = best[i], s2 = second[i];
     if (s > b) {
       s2 = b;
@@ -150,34 +192,37 @@ __global__ __launch_bounds__(kBlock) void k_kpp_select(const double* __restrict_
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_kpp_densify(const int64_t* __restrict__ rp,
-                                                        const int32_t* __restrict__ ci,
-                                                        const float* __restrict__ v, int64_t d,
+__global__ __launch_bounds__(kBlock) void k_kpp_densify(SeedRows R, int64_t d,
                                                         const int32_t* __restrict__ chosen,
                                                         int32_t t, float* __restrict__ centres) {
   const int64_t p = chosen[t];
   float* c = centres + (size_t)t * d;
-  for (int64_t e = rp[p] + threadIdx.x; e < rp[p + 1]; e += kBlock) c[ci[e]] = v[e];
+  if (R.x) {
+    for (int64_t q = threadIdx.x; q < d; q += kBlock) c[q] = R.x[(size_t)p * R.ld + q];
+  } else {
+    for (int64_t e = R.rp[p] + threadIdx.x; e < R.rp[p + 1]; e += kBlock) c[R.ci[e]] = R.v[e];
+  }
 }
 
 }  // namespace
 
-hipError_t launch_kpp_step(const int64_t* rp, const int32_t* ci, const float* v, int64_t n,
-                           int64_t d, int32_t t, double alpha, const double* u_dev,
+hipError_t launch_kpp_step(const int64_t* rp, const int32_t* ci, const float* v, const float* x,
+                           int64_t ld, int64_t n, int64_t d, int32_t t, double alpha,
+                           const double* u_dev,
                            uint8_t* taken, int32_t* chosen, float* centres, double* c64,
                            int32_t* a, double* best, double* second, double* w, double* part,
                            hipStream_t s) {
   const int64_t nb = (n + kBlock - 1) / kBlock;
+  const SeedRows R{rp, ci, v, x, ld};
   hipLaunchKernelGGL(k_kpp_select, dim3(1), dim3(kBlock), 0, s, part, nb, w, n, u_dev, t, taken,
                      chosen);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_kpp_densify, dim3(1), dim3(kBlock), 0, s, rp, ci, v, d, chosen, t,
-                     centres);
+  hipLaunchKernelGGL(k_kpp_densify, dim3(1), dim3(kBlock), 0, s, R, d, chosen, t, centres);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = launch_init_centres(centres + (size_t)t * d, 1, d, 1, c64, nullptr, s)) != hipSuccess)
     return e;
-  hipLaunchKernelGGL(k_kpp_update, dim3((unsigned)nb), dim3(kBlock), 0, s, rp, ci, v, n, c64, t,
+  hipLaunchKernelGGL(k_kpp_update, dim3((unsigned)nb), dim3(kBlock), 0, s, R, n, d, c64, t,
                      alpha, taken, a, best, second, w, part);
   return hipGetLastError();
 }
@@ -197,14 +242,12 @@ namespace {
 using namespace dev;
 
 // w(x) = max(0, alpha - <x, c0>) in the canonical FP64 order.
-__global__ __launch_bounds__(kBlock) void k_afk_weights(const int64_t* __restrict__ rp,
-                                                        const int32_t* __restrict__ ci,
-                                                        const float* __restrict__ v, int64_t n,
+__global__ __launch_bounds__(kBlock) void k_afk_weights(SeedRows R, int64_t n, int64_t d,
                                                         const double* __restrict__ c0,
                                                         double alpha, double* __restrict__ w) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
-  const double x = alpha - dot64_serial(ci, v, rp[i], rp[i + 1], c0);
+  const double x = alpha - row_dot64(R, i, d, c0);
   w[i] = x > 0.0 ? x : 0.0;
 }
 
@@ -245,17 +288,18 @@ __global__ void k_afk_propose(const double* __restrict__ prefix, int64_t n,
 // d(y_j) = max(0, alpha - max_{c < t} <y_j, c>): one block per proposal,
 // each wave takes every fourth centre.
 __global__ __launch_bounds__(kBlock) void k_afk_dissim(
-    const int64_t* __restrict__ rp, const int32_t* __restrict__ ci, const float* __restrict__ v,
-    int64_t d, const double* __restrict__ C64, int32_t t, double alpha,
+    SeedRows R, int64_t d, const double* __restrict__ C64, int32_t t, double alpha,
     const int32_t* __restrict__ cand, double* __restrict__ dcand) {
   __shared__ double wmax[kBlock / 64];
   const int j = blockIdx.x;
   const int64_t y = cand[j];
-  const int64_t beg = rp[y], end = rp[y + 1];
+  const int64_t beg = R.x ? 0 : R.rp[y], end = R.x ? 0 : R.rp[y + 1];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   double best = -INFINITY;
   for (int c = wave; c < t; c += kBlock / 64) {
-    const double s = dot64_group<64>(ci, v, beg, end, C64 + (size_t)c * d, lane);
+    const double s =
+        R.x ? dot64_wave_dense(R.x + (size_t)y * R.ld, d, C64 + (size_t)c * d, lane)
+            : dot64_group<64>(R.ci, R.v, beg, end, C64 + (size_t)c * d, lane);
     best = s > best ? s : best;
   }
   if (lane == 0) wmax[wave] = best;
@@ -301,18 +345,20 @@ __global__ void k_afk_first(const double* __restrict__ u, int64_t n, int32_t* __
 
 }  // namespace
 
-hipError_t launch_afkmc2(const int64_t* rp, const int32_t* ci, const float* v, int64_t n,
-                         int64_t d, int32_t k, int32_t m, double alpha, const double* u_dev,
+hipError_t launch_afkmc2(const int64_t* rp, const int32_t* ci, const float* v, const float* x,
+                         int64_t ld, int64_t n, int64_t d, int32_t k, int32_t m, double alpha,
+                         const double* u_dev,
                          int32_t* chosen, float* centres, double* C64, double* w, double* W,
                          double* prefix, int32_t* cand, double* dcand, hipStream_t s) {
   hipError_t e;
   const unsigned nblk = (unsigned)((n + kBlock - 1) / kBlock);
+  const SeedRows R{rp, ci, v, x, ld};
   hipLaunchKernelGGL(k_afk_first, dim3(1), dim3(64), 0, s, u_dev, n, chosen);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_kpp_densify, dim3(1), dim3(kBlock), 0, s, rp, ci, v, d, chosen, 0, centres);
+  hipLaunchKernelGGL(k_kpp_densify, dim3(1), dim3(kBlock), 0, s, R, d, chosen, 0, centres);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = launch_init_centres(centres, 1, d, 1, C64, nullptr, s)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_afk_weights, dim3(nblk), dim3(kBlock), 0, s, rp, ci, v, n, C64, alpha, w);
+  hipLaunchKernelGGL(k_afk_weights, dim3(nblk), dim3(kBlock), 0, s, R, n, d, C64, alpha, w);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_afk_prefix, dim3(1), dim3(64), 0, s, w, n, W, prefix);
   if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -321,14 +367,13 @@ hipError_t launch_afkmc2(const int64_t* rp, const int32_t* ci, const float* v, i
     hipLaunchKernelGGL(k_afk_propose, dim3((unsigned)((m + kBlock - 1) / kBlock)), dim3(kBlock), 0,
                        s, prefix, n, ut, m, cand);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_afk_dissim, dim3((unsigned)m), dim3(kBlock), 0, s, rp, ci, v, d, C64, t,
-                       alpha, cand, dcand);
+    hipLaunchKernelGGL(k_afk_dissim, dim3((unsigned)m), dim3(kBlock), 0, s, R, d, C64, t, alpha,
+                       cand, dcand);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_afk_chain, dim3(1), dim3(64), 0, s, cand, dcand, w, W, n, ut + m, m, t,
                        chosen);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_kpp_densify, dim3(1), dim3(kBlock), 0, s, rp, ci, v, d, chosen, t,
-                       centres);
+    hipLaunchKernelGGL(k_kpp_densify, dim3(1), dim3(kBlock), 0, s, R, d, chosen, t, centres);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = launch_init_centres(centres + (size_t)t * d, 1, d, 1, C64 + (size_t)t * d, nullptr,
                                  s)) != hipSuccess)

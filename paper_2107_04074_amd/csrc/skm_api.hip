@@ -447,6 +447,7 @@ int fit_dense(const skm_matrix* X, int32_t k, const float* init_centers, int32_t
   DensePlan P;
   int rc = make_dense_plan(X, k, variant, o.precision, &P);
   if (rc != SKM_OK) return rc;
+  const bool warm = o.warm_assign != nullptr;  // the three warm arrays go together
   if (workspace && workspace_bytes < P.total)
     return fail(SKM_ERR_OUT_OF_MEMORY, "workspace has %zu bytes, %zu needed", workspace_bytes,
                 P.total);
@@ -524,7 +525,71 @@ int fit_dense(const skm_matrix* X, int32_t k, const float* init_centers, int32_t
         goto done;
       }
     }
-    for (int32_t t = 0; t < max_iter; ++t) {
+    // centre step after assignment step t (changed rows moved): recompute all
+    // sums when many rows moved, else apply the moved rows (both give the
+    // same fixed-point sums); movement, packed copy, Gram, clear dirty flags
+    auto centre_step = [&](int32_t t, int64_t changed) -> hipError_t {
+      hipError_t e;
+      if (t == 0 || changed * 32 > n) {
+        if ((e = launch_cluster_sums(assign_out, n, k, X->dense, X->ld, d, fx,
+                                     R.ptr<int32_t>(P.ccnt), R.ptr<int32_t>(P.cstart),
+                                     R.ptr<int32_t>(P.ccur), R.ptr<int32_t>(P.perm), S, dirty,
+                                     &per->scan_dummy, s)) != hipSuccess)
+          return e;
+        if ((e = launch_copy_assign(assign_out, a_old, n, s)) != hipSuccess) return e;
+      } else {
+        if ((e = launch_dense_update_scan(X->dense, X->ld, assign_out, a_old, n, d, fx, S, dirty,
+                                          s)) != hipSuccess)
+          return e;
+      }
+      if ((e = launch_sumsq_partial(S, k, d, fx_inv, dirty, part_sq, P.nchunk, s)) != hipSuccess)
+        return e;
+      if ((e = launch_normalize_move(S, k, d, fx_inv, dirty, part_sq, C64, part, P.nchunk, s)) !=
+          hipSuccess)
+        return e;
+      if ((e = launch_centre_finalize(k, d, dirty, norm64, part_sq, part, P.nchunk, delta_c, pc,
+                                      ps, mm, per, s)) != hipSuccess)
+        return e;
+      if ((e = launch_pack_centres(C64, k, d, P.dp, dirty, P.bf16, Cp, s)) != hipSuccess)
+        return e;
+      if (P.gram) {
+        if (t + 1 < off_until) {
+          gram_stale = true;  // no tests next step: the Gram waits for one that has them
+        } else if (gram_stale || gram_exact_step(gram_updates, gram_since_exact, changed, n)) {
+          // after carried or skipped steps every tile's partials are stale
+          if ((e = launch_gram(C64, k, d, dirty,
+                               (first_gram || gram_since_exact > 0 || gram_stale) ? 1 : 0, gpart,
+                               P.nslice, P.slice_len, G, gmax, delta_g, per, s)) != hipSuccess)
+            return e;
+          first_gram = false;
+          gram_stale = false;
+          gram_since_exact = 0;
+          ++gram_updates;
+        } else {
+          if ((e = launch_gram_carry(G, k, pc, ps, delta_g, gmax, s)) != hipSuccess) return e;
+          ++gram_since_exact;
+          ++gram_updates;
+        }
+      }
+      return launch_clear_dirty(dirty, k, s);
+    };
+    int32_t t_first = 0;
+    if (warm) {
+      // the first step's assignment and FP64 top-2 are given (a seeding's
+      // cache): bounds only, then the centre step
+      SKM_HIP(launch_warm_start(nullptr, n, k, 0, o.warm_assign, o.warm_best, o.warm_second,
+                                R.ptr<float>(P.eta), delta_c, assign_out,
+                                P.bounds ? R.ptr<float>(P.l) : nullptr,
+                                P.bounds ? R.ptr<float>(P.u) : nullptr, nullptr, nullptr, 0, s,
+                                d));
+      if (stats && stats->changed_per_iter && stats->per_iter_len > 0)
+        stats->changed_per_iter[0] = n;
+      if (stats && stats->sims_per_iter && stats->per_iter_len > 0) stats->sims_per_iter[0] = 0;
+      iterations = 1;
+      SKM_HIP(centre_step(0, n));
+      t_first = 1;
+    }
+    for (int32_t t = t_first; t < max_iter; ++t) {
       SKM_HIP(hipMemsetAsync(cnt, 0, kCounterSlots * sizeof(Counters), s));
       const bool exhaustive = t == 0 || variant == SKM_LLOYD || t < off_until;
       const int32_t* rows = nullptr;
@@ -597,41 +662,7 @@ int fit_dense(const skm_matrix* X, int32_t k, const float* init_centers, int32_t
         converged = 1;
         break;
       }
-      // centre step: recompute all sums when many rows moved, else apply
-      // the moved rows (both give the same fixed-point sums)
-      if (t == 0 || changed * 32 > n) {
-        SKM_HIP(launch_cluster_sums(assign_out, n, k, X->dense, X->ld, d, fx,
-                                    R.ptr<int32_t>(P.ccnt), R.ptr<int32_t>(P.cstart),
-                                    R.ptr<int32_t>(P.ccur), R.ptr<int32_t>(P.perm), S, dirty,
-                                    &per->scan_dummy, s));
-        SKM_HIP(launch_copy_assign(assign_out, a_old, n, s));
-      } else {
-        SKM_HIP(launch_dense_update_scan(X->dense, X->ld, assign_out, a_old, n, d, fx, S, dirty,
-                                         s));
-      }
-      SKM_HIP(launch_sumsq_partial(S, k, d, fx_inv, dirty, part_sq, P.nchunk, s));
-      SKM_HIP(launch_normalize_move(S, k, d, fx_inv, dirty, part_sq, C64, part, P.nchunk, s));
-      SKM_HIP(launch_centre_finalize(k, d, dirty, norm64, part_sq, part, P.nchunk, delta_c, pc,
-                                     ps, mm, per, s));
-      SKM_HIP(launch_pack_centres(C64, k, d, P.dp, dirty, P.bf16, Cp, s));
-      if (P.gram) {
-        if (t + 1 < off_until) {
-          gram_stale = true;  // no tests next step: the Gram waits for one that has them
-        } else if (gram_stale || gram_exact_step(gram_updates, gram_since_exact, changed, n)) {
-          // after carried or skipped steps every tile's partials are stale
-          SKM_HIP(launch_gram(C64, k, d, dirty,
-                              (first_gram || gram_since_exact > 0 || gram_stale) ? 1 : 0, gpart,
-                              P.nslice, P.slice_len, G, gmax, delta_g, per, s));
-          first_gram = false;
-          gram_stale = false;
-          gram_since_exact = 0;
-          ++gram_updates;
-        } else {
-          SKM_HIP(launch_gram_carry(G, k, pc, ps, delta_g, gmax, s));
-          ++gram_since_exact;
-          ++gram_updates;
-        }
-      }
+      SKM_HIP(centre_step(t, changed));
       SKM_HIP(launch_clear_dirty(dirty, k, s));
     }
     SKM_HIP(hipMemcpyAsync(&hm->per, per, sizeof(Persist), hipMemcpyDeviceToHost, s));
@@ -833,7 +864,6 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
     return fail(SKM_ERR_INVALID_ARG, "warm_assign, warm_best and warm_second go together");
   const bool warm = nwarm == 3;
   if (X->fmt == SKM_DENSE_F32) {
-    if (warm) return fail(SKM_ERR_UNSUPPORTED, "warm start needs CSR input");
     return fit_dense(X, k, init_centers, variant, max_iter, o, workspace, workspace_bytes,
                      assign_out, centers_out, centers64_out, stats, static_cast<hipStream_t>(stream));
   }
@@ -1151,10 +1181,14 @@ struct SeedPlan {
          chosen_dummy = 0, total = 0;
 };
 
+// Dense rows for the seeding kernels (nullptr: CSR).
+const float* dense_rows(const skm_matrix* X) {
+  return X->fmt == SKM_DENSE_F32 ? X->dense : nullptr;
+}
+
 int make_seed_plan(const skm_matrix* X, int32_t k, SeedPlan* S) {
   int rc = check_matrix(X);
   if (rc != SKM_OK) return rc;
-  if (X->fmt != SKM_CSR_F32) return fail(SKM_ERR_UNSUPPORTED, "k-means++ seeding needs CSR input");
   if (k < 1 || k > X->n) return fail(SKM_ERR_INVALID_ARG, "need 1 <= k <= n (k = %d)", (int)k);
   const size_t n = (size_t)X->n, d = (size_t)X->d, nb = (n + kBlock - 1) / kBlock;
   size_t cur = 0;
@@ -1224,7 +1258,8 @@ int skm_seed_kmeanspp(const skm_matrix* X, int32_t k, double alpha, const double
     SKM_HIP(launch_fill_f64(best, n, -INFINITY, s));
     SKM_HIP(launch_fill_f64(second, n, -INFINITY, s));
     for (int32_t t = 0; t < k; ++t)
-      SKM_HIP(launch_kpp_step(X->row_ptr, X->col_idx, X->val, n, d, t, alpha, u_dev, taken,
+      SKM_HIP(launch_kpp_step(X->row_ptr, X->col_idx, X->val, dense_rows(X), X->ld, n, d, t,
+                              alpha, u_dev, taken,
                               chosen_out, centres, at<double>(ws, S.c64), a, best, second,
                               at<double>(ws, S.w), at<double>(ws, S.part), s));
   }
@@ -1242,7 +1277,6 @@ struct AfkPlan {
 int make_afk_plan(const skm_matrix* X, int32_t k, int32_t chain, AfkPlan* S) {
   int rc = check_matrix(X);
   if (rc != SKM_OK) return rc;
-  if (X->fmt != SKM_CSR_F32) return fail(SKM_ERR_UNSUPPORTED, "AFK-MC2 seeding needs CSR input");
   if (k < 1 || k > X->n) return fail(SKM_ERR_INVALID_ARG, "need 1 <= k <= n (k = %d)", (int)k);
   if (chain < 1 || chain > (1 << 20))
     return fail(SKM_ERR_INVALID_ARG, "need 1 <= chain <= 2^20 (chain = %d)", (int)chain);
@@ -1303,7 +1337,8 @@ int skm_seed_afkmc2(const skm_matrix* X, int32_t k, int32_t chain, double alpha,
     double* u_dev = at<double>(ws, S.u);
     SKM_HIP(hipMemcpyAsync(u_dev, uniforms, S.nu * sizeof(double), hipMemcpyHostToDevice, s));
     SKM_HIP(hipMemsetAsync(centres, 0, (size_t)k * X->d * sizeof(float), s));
-    SKM_HIP(launch_afkmc2(X->row_ptr, X->col_idx, X->val, X->n, X->d, k, chain, alpha, u_dev,
+    SKM_HIP(launch_afkmc2(X->row_ptr, X->col_idx, X->val, dense_rows(X), X->ld, X->n, X->d, k,
+                          chain, alpha, u_dev,
                           chosen_out, centres, at<double>(ws, S.C64), at<double>(ws, S.w),
                           at<double>(ws, S.W), at<double>(ws, S.prefix), at<int32_t>(ws, S.cand),
                           at<double>(ws, S.dcand), s));

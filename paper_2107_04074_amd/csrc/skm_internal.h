@@ -319,11 +319,13 @@ __host__ __device__ inline bool gram_exact_step(int updates_done, int since_exac
   return updates_done < 2 || since_exact >= 3 || changed * 20 > n;
 }
 // First assignment step from a given assignment and FP64 top-2 (uy: the
-// Yin-Yang group bounds, nullable, ng per row).
+// Yin-Yang group bounds, nullable, ng per row).  rp = nullptr: dense rows of
+// dense_d columns.
 hipError_t launch_warm_start(const int64_t* rp, int64_t n, int32_t k, int32_t kp,
                              const int32_t* wa, const double* wb, const double* ws2,
                              const float* eta, double delta_c, int32_t* a, float* l, float* u,
-                             float* ue, float* uy, int32_t ng, hipStream_t s);
+                             float* ue, float* uy, int32_t ng, hipStream_t s,
+                             int64_t dense_d = 0);
 // Cosine and sine of every Yin-Yang group's largest movement.
 hipError_t launch_group_move(const double* pc, const double* ps, int32_t k, int32_t ng,
                              double* gpc, double* gps, hipStream_t s);
@@ -331,16 +333,18 @@ hipError_t launch_group_move(const double* pc, const double* ps, int32_t k, int3
 // centres (FP32 k x d, zeroed) and its unit FP64 copy to c64 (d), refresh
 // every row's running top-2 (a, best, second), weights w and per-block
 // weight sums part.
-hipError_t launch_kpp_step(const int64_t* rp, const int32_t* ci, const float* v, int64_t n,
-                           int64_t d, int32_t t, double alpha, const double* u_dev,
+hipError_t launch_kpp_step(const int64_t* rp, const int32_t* ci, const float* v, const float* x,
+                           int64_t ld, int64_t n, int64_t d, int32_t t, double alpha,
+                           const double* u_dev,
                            uint8_t* taken, int32_t* chosen, float* centres, double* c64,
                            int32_t* a, double* best, double* second, double* w, double* part,
                            hipStream_t s);
 // AFK-MC2 seeding: chooses k rows (chosen), writes them to centres (FP32
 // k x d, zeroed by the caller) and their unit FP64 copies to C64 (k x d).
 // Scratch: w, prefix (n each), W (1), cand (m), dcand (m).
-hipError_t launch_afkmc2(const int64_t* rp, const int32_t* ci, const float* v, int64_t n,
-                         int64_t d, int32_t k, int32_t m, double alpha, const double* u_dev,
+hipError_t launch_afkmc2(const int64_t* rp, const int32_t* ci, const float* v, const float* x,
+                         int64_t ld, int64_t n, int64_t d, int32_t k, int32_t m, double alpha,
+                         const double* u_dev,
                          int32_t* chosen, float* centres, double* C64, double* w, double* W,
                          double* prefix, int32_t* cand, double* dcand, hipStream_t s);
 // Gram slicing over d: number of column slices and their length.

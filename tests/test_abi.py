@@ -158,8 +158,10 @@ def test_seeding_and_warm_start_arguments_are_rejected(lib):
     assert lib.skm_seed_workspace_size(ctypes.byref(m), 3) > 0
     assert lib.skm_seed_workspace_size(ctypes.byref(m), 11) == 0  # k > n
     md = skm.SkmMatrix(skm.DENSE_F32, 0, 10, 20, 0, None, None, None, 0x1000, 20)
-    assert lib.skm_seed_workspace_size(ctypes.byref(md), 3) == 0
-    assert b"CSR" in lib.skm_last_error()
+    assert lib.skm_seed_workspace_size(ctypes.byref(md), 3) > 0  # dense rows are accepted
+    wide = skm.SkmMatrix(skm.DENSE_F32, 0, 10, 300, 0, None, None, None, 0x1000, 300)
+    assert lib.skm_seed_workspace_size(ctypes.byref(wide), 3) == 0
+    assert b"d <= 256" in lib.skm_last_error()
     call = lambda alpha, uu: lib.skm_seed_kmeanspp(ctypes.byref(m), 3, alpha, uu, 0x5000, None,
                                                    None, None, None, None, 0, None)
     assert call(0.5, u) == skm.ERR_INVALID_ARG and b"alpha" in lib.skm_last_error()
@@ -168,16 +170,13 @@ def test_seeding_and_warm_start_arguments_are_rejected(lib):
     neg = (ctypes.c_double * 3)(-0.1, 0.5, 0.2)
     assert call(1.0, neg) == skm.ERR_INVALID_ARG
     assert call(1.0, None) == skm.ERR_INVALID_ARG
-    # warm start: all three arrays or none; CSR only
+    # warm start: all three arrays or none (CSR and dense alike)
     st = skm.SkmStats()
     o = skm.SkmOptions(0, 0, 0, 0, 0.0, 0x7000, None, None)
-    rc = lib.skm_fit(ctypes.byref(m), 3, 0x5000, 0, 5, ctypes.byref(o), None, 0, 0x4000, None,
-                     None, ctypes.byref(st), None)
-    assert rc == skm.ERR_INVALID_ARG and b"warm" in lib.skm_last_error()
-    o = skm.SkmOptions(0, 0, 0, 0, 0.0, 0x7000, 0x7100, 0x7200)
-    rc = lib.skm_fit(ctypes.byref(md), 3, 0x5000, 0, 5, ctypes.byref(o), None, 0, 0x4000, None,
-                     None, ctypes.byref(st), None)
-    assert rc == skm.ERR_UNSUPPORTED
+    for mm in (m, md):
+        rc = lib.skm_fit(ctypes.byref(mm), 3, 0x5000, 0, 5, ctypes.byref(o), None, 0, 0x4000,
+                         None, None, ctypes.byref(st), None)
+        assert rc == skm.ERR_INVALID_ARG and b"warm" in lib.skm_last_error()
 
 
 def test_afkmc2_arguments_are_rejected(lib):

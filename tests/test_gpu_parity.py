@@ -365,11 +365,11 @@ def test_dense_fit_small_matches_oracle(skm, torch_cuda, precision):
             assert np.array_equal(a, base[0]) and np.array_equal(C64, base[1])
 
 
-@pytest.mark.parametrize("d,k", [(37, 5), (100, 45), (200, 100), (64, 33)])
+@pytest.mark.parametrize("d,k", [(37, 5), (100, 45), (200, 100), (64, 33), (20, 7), (64, 1)])
 def test_dense_bf16_ragged_matches_oracle(skm, torch_cuda, d, k):
     """BF16 top-2 pass where the last centre tiles reach past k (k not a
-    multiple of 32, down to a tile of padding only) at the padded widths
-    dp = 64, 128 and 256: whole trajectories equal the oracle's."""
+    multiple of 32, down to a tile of padding only, and k = 1) at the padded
+    widths dp = 32, 64, 128 and 256: whole trajectories equal the oracle's."""
     torch = torch_cuda
     X = datagen.dense_vmf(4000, d, max(4, k // 2), 900 + d)
     C0 = X[datagen.init_rows(X.shape[0], k, 77 + k)].copy()

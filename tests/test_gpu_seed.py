@@ -103,3 +103,76 @@ def test_afkmc2_matches_oracle(skm, torch_cuda, name, n, k, chain, alpha):
     torch.cuda.synchronize()
     assert np.array_equal(ch.cpu().numpy(), ref)
     assert np.array_equal(C.cpu().numpy(), datagen.init_centers_csr(X, ref))
+
+
+# ------------------------------------------------------------ dense rows
+def dense_csr(D):
+    """A dense matrix as the CSR matrix that stores every column (what the
+    oracle reads)."""
+    n, d = D.shape
+    rp = np.arange(0, n * d + 1, d, dtype=np.int64)
+    return datagen.CSR(n, d, rp, np.tile(np.arange(d, dtype=np.int32), n),
+                       np.ascontiguousarray(D, np.float32).ravel())
+
+
+@pytest.mark.parametrize("n,d,k,alpha", [(3000, 64, 20, 1.0), (5000, 200, 150, 1.5),
+                                         (2000, 37, 7, 1.0)])
+def test_seeding_dense_matches_oracle(skm, torch_cuda, n, d, k, alpha):
+    torch = torch_cuda
+    say("case seed dense n=%d d=%d k=%d alpha=%g" % (n, d, k, alpha))
+    X = datagen.dense_vmf(n, d, max(4, k // 3), 700 + d)
+    u = np.random.default_rng(k + d).random(k)
+    ch_ref, a_ref, s1_ref, s2_ref = oracle.kmeanspp(dense_csr(X), k, alpha, u)
+    Xd = skm.DeviceDense.from_host(X)
+    ch, C, a, s1, s2 = skm.seed_kmeanspp(Xd, k, u, alpha)
+    torch.cuda.synchronize()
+    assert np.array_equal(ch.cpu().numpy(), ch_ref)
+    assert np.array_equal(C.cpu().numpy(), X[ch_ref].astype(np.float32))
+    assert np.array_equal(a.cpu().numpy(), a_ref)
+    assert np.abs(s1.cpu().numpy() - s1_ref).max() < 1e-12
+    fin = np.isfinite(s2_ref)
+    assert np.array_equal(np.isfinite(s2.cpu().numpy()), fin)
+    assert np.abs(s2.cpu().numpy()[fin] - s2_ref[fin]).max(initial=0.0) < 1e-12
+
+
+@pytest.mark.parametrize("n,d,k,chain", [(3000, 64, 20, 20), (2000, 37, 9, 1)])
+def test_afkmc2_dense_matches_oracle(skm, torch_cuda, n, d, k, chain):
+    torch = torch_cuda
+    say("case afkmc2 dense n=%d d=%d k=%d chain=%d" % (n, d, k, chain))
+    X = datagen.dense_vmf(n, d, max(4, k // 3), 800 + d)
+    u = np.random.default_rng(k + chain).random(1 + (k - 1) * (2 * chain - 1))
+    ref = oracle.afkmc2(dense_csr(X), k, chain, 1.0, u)
+    Xd = skm.DeviceDense.from_host(X)
+    ch, C = skm.seed_afkmc2(Xd, k, chain, u, 1.0)
+    torch.cuda.synchronize()
+    assert np.array_equal(ch.cpu().numpy(), ref)
+    assert np.array_equal(C.cpu().numpy(), X[ref].astype(np.float32))
+
+
+@pytest.mark.parametrize("variant,precision", [("lloyd", 0), ("hamerly", 0), ("hamerly", 1),
+                                               ("simp_hamerly", 1)])
+def test_warm_start_dense_equals_cold_fit(skm, torch_cuda, variant, precision):
+    """Dense rows: a fit started from the seeding's cached first step ends
+    exactly where the cold fit from the same centres does (tests at every
+    step, so the warm bounds are used from step 2 on)."""
+    torch = torch_cuda
+    X = datagen.dense_vmf(20000, 128, 40, 4343)
+    k = 64
+    u = np.random.default_rng(5).random(k)
+    Xd = skm.DeviceDense.from_host(X)
+    ch, C, a, s1, s2 = skm.seed_kmeanspp(Xd, k, u)
+    say("case warm start dense %s precision=%d" % (variant, precision))
+    ac, Cc, _, stc = skm.fit(Xd, k, C, variant, 40, precision=precision, schedule=1)
+    aw, Cw, _, stw = skm.fit(Xd, k, C, variant, 40, precision=precision, schedule=1,
+                             warm=(a, s1, s2))
+    torch.cuda.synchronize()
+    assert torch.equal(ac, aw) and torch.equal(Cc, Cw)
+    assert stc.iterations == stw.iterations and stc.converged == stw.converged
+    assert np.array_equal(stc.changed_per_iter, stw.changed_per_iter)
+    assert stw.sims_point_center < stc.sims_point_center
+    say("  iterations %d, sims cold %d warm %d" % (stc.iterations, stc.sims_point_center,
+                                                  stw.sims_point_center))
+    if variant == "hamerly" and precision == 1:
+        ref = oracle.fit(dense_csr(X), X[ch.cpu().numpy()].astype(np.float32), "lloyd", 40)
+        assert ref.iterations == stw.iterations
+        assert np.array_equal(aw.cpu().numpy(), ref.a)
