@@ -210,9 +210,10 @@ def _options(bound_form=0, precision=0, validate=0, norm_tol=0.0, profile=0, war
     return SkmOptions(bound_form, precision, validate, profile, norm_tol, *w, schedule, 0)
 
 
-def seed_kmeanspp(X: DeviceCSR, k: int, uniforms, alpha: float = 1.0, workspace=None):
-    """Runs skm_seed_kmeanspp with the caller's uniforms (k floats in
-    [0, 1)).  Returns (chosen int32, centers float32 (k, d), assign int32,
+def seed_kmeanspp(X: "DeviceCSR | DeviceDense", k: int, uniforms, alpha: float = 1.0,
+                  workspace=None):
+    """Runs skm_seed_kmeanspp (CSR or dense rows) with the caller's uniforms
+    (k floats in [0, 1)).  Returns (chosen int32, centers float32 (k, d), assign int32,
     best float64, second float64) device tensors; asynchronous."""
     import torch
     lib = load()
@@ -237,9 +238,9 @@ def seed_kmeanspp(X: DeviceCSR, k: int, uniforms, alpha: float = 1.0, workspace=
     return chosen, centers, a, best, second
 
 
-def seed_afkmc2(X: DeviceCSR, k: int, chain: int, uniforms, alpha: float = 1.0,
-                workspace=None):
-    """Runs skm_seed_afkmc2 with the caller's draws (1 + (k-1)(2 chain - 1)
+def seed_afkmc2(X: "DeviceCSR | DeviceDense", k: int, chain: int, uniforms,
+                alpha: float = 1.0, workspace=None):
+    """Runs skm_seed_afkmc2 (CSR or dense rows) with the caller's draws (1 + (k-1)(2 chain - 1)
     floats in [0, 1)).  Returns (chosen int32, centers float32 (k, d));
     asynchronous."""
     import torch
