@@ -155,8 +155,13 @@ __global__ __launch_bounds__(MfmaCfg<BF16>::WAVES * 64) void k_dense_sim(DenseSi
   constexpr int kDenseWaves = Cfg::WAVES;
   typedef typename Cfg::elem E;
   constexpr int KSTEP = Cfg::KSTEP, RT = Cfg::RT, CC = Cfg::CC;
-  // BF16 top-2 pass: values offset by 2 and packed with their place
+  // BF16 top-2 pass: values offset by a positive constant and packed with their place
   constexpr bool kPack = BF16 && MODE == 0;
+  // accumulator start of tile rt (values arrive offset by it, all positive);
+  // distinct per tile so that each folds into its first MFMA as an inline
+  // constant
+  constexpr float kOffset[2] = {2.f, 4.f};
+  static_assert(!kPack || RT <= 2, "one offset per row tile");
   constexpr int ROWS_PER_WAVE = 32 * RT;
   constexpr int ROWS_PER_BLOCK = ROWS_PER_WAVE * kDenseWaves;
   extern __shared__ char smem[];
@@ -238,9 +243,10 @@ __global__ __launch_bounds__(MfmaCfg<BF16>::WAVES * 64) void k_dense_sim(DenseSi
       for (int i = 0; i < 16; ++i) prv[rt][i] = 0.f;
       pt1[rt] = pt2[rt] = 0u;
     }
-    // Value i of a tile into a lane's running top-2.  The accumulator starts
-    // at 2, so a value v arrives as v + 2, in [1, 4), where bit patterns
-    // order like values; the low four bits of the pattern are replaced by
+    // Value i of a tile into a lane's running top-2.  The accumulator of row
+    // tile rt starts at kOffset[rt] (2 or 4), so a value v arrives as
+    // v + kOffset[rt] > 0, where bit patterns order like values; the low
+    // four bits of the pattern are replaced by
     // the value's place in the tile (15 - i, so that the earlier centre wins
     // an exact tie).  The top-2 is then an integer maximum and
     // median-of-three per value, and the place of the maximum is read back
@@ -287,7 +293,7 @@ __global__ __launch_bounds__(MfmaCfg<BF16>::WAVES * 64) void k_dense_sim(DenseSi
 #pragma unroll
         for (int rt = 0; rt < PRT; ++rt) {
 #pragma unroll
-          for (int i = 0; i < 16; ++i) acc[rt][i] = 2.f;
+          for (int i = 0; i < 16; ++i) acc[rt][i] = kOffset[rt];
           pt1[rt] = pt2[rt] = 0u;
         }
         const E* arow = cur + (at * 32 + (lane & 31)) * ldsw;
@@ -475,8 +481,8 @@ __global__ __launch_bounds__(MfmaCfg<BF16>::WAVES * 64) void k_dense_sim(DenseSi
         float b, s2v;
         int bj = j1[rt];
         if constexpr (kPack) {
-          // patterns of values offset by 2: compare as integers, then undo
-          // the offset (exact for patterns in [1, 4))
+          // patterns of offset values: compare as integers, then undo the
+          // offset (exact: the pattern lies within a factor 2 of it)
           const unsigned a1 = __float_as_uint(m1[rt]), a2 = __float_as_uint(m2[rt]);
           const unsigned o1 = __float_as_uint(om1), o2 = __float_as_uint(om2);
           unsigned kb = a1, ks = max(a2, o2);
@@ -487,8 +493,8 @@ __global__ __launch_bounds__(MfmaCfg<BF16>::WAVES * 64) void k_dense_sim(DenseSi
           } else {
             ks = max(ks, o1);
           }
-          b = __uint_as_float(kb) - 2.f;
-          s2v = A.k > 1 ? __uint_as_float(ks) - 2.f : -INFINITY;  // k = 1: no second
+          b = __uint_as_float(kb) - kOffset[rt];
+          s2v = A.k > 1 ? __uint_as_float(ks) - kOffset[rt] : -INFINITY;  // k = 1: no second
         } else {
           b = m1[rt];
           s2v = fmaxf(m2[rt], om2);
@@ -514,15 +520,15 @@ __global__ __launch_bounds__(MfmaCfg<BF16>::WAVES * 64) void k_dense_sim(DenseSi
 // Rigorous bound on |s_hat - <x, c>| for one row of the dense contraction.
 // BF16: x is rounded once to BF16 and the centre twice (FP64 -> FP32 ->
 // BF16), relative errors 2^-8 and 2^-8 + 2^-24 (8-bit significand, RNE);
-// products are exact; the FP32 accumulation starts at 2 (the top-2 pass
-// offsets values by 2) so every partial sum is below 3 |x||c| + 2, taken with
+// products are exact; the FP32 accumulation starts at 2 or 4 (the top-2 pass
+// offsets values) so every partial sum is below 5 |x||c| + 4, taken with
 // unit 2^-23 to cover accumulation that truncates; replacing four low bits
-// of the offset value and removing the offset add below 2^-17.
+// of the offset value (below 8) and removing the offset add below 2^-17.
 // FP32: the centre copy, every product and every sum (unit 2^-23 for the
 // sums, as above).  Both are relative to sum |x_t c_t| <= |x| |c| <= 1 + eta.
 __device__ __forceinline__ double dense_eps(bool bf16, int dp, double eta) {
   const double unit = bf16 ? (2.0 * 0.00390625 + 1.52587890625e-05 + 2.0 * kU32 +
-                              6.0 * (dp + 2) * kU32 + 7.62939453125e-06)
+                              10.5 * (dp + 2) * kU32 + 7.62939453125e-06)
                            : ((2 * dp + 3) * kU32);
   return unit * (1.0 + eta) * 1.01;
 }
