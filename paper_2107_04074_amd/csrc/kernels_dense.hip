@@ -66,12 +66,6 @@ struct MfmaCfg<false> {
   typedef float elem;
 };
 
-// One 32x32 accumulator tile of a row block.  Mode 0 folds the lane's 16
-// values into its running top-2: first a tile-local top-2 (index as a
-// compile-time offset, second best by median-of-three), then one merge.
-// Selects instead of fmaxf keep NaN canonicalisation out of the loop; the
-// inputs are finite.  Mode 1 emits every centre at or above the row's
-// threshold.  `ragged` masks centres >= k (only the last tile has them).
 // Median of three unsigned integers, one instruction.
 __device__ __forceinline__ unsigned umed3(unsigned a, unsigned b, unsigned c) {
   unsigned r;
@@ -79,6 +73,12 @@ __device__ __forceinline__ unsigned umed3(unsigned a, unsigned b, unsigned c) {
   return r;
 }
 
+// One 32x32 accumulator tile of a row block.  Mode 0 folds the lane's 16
+// values into its running top-2: first a tile-local top-2 (index as a
+// compile-time offset, second best by median-of-three), then one merge.
+// Selects instead of fmaxf keep NaN canonicalisation out of the loop; the
+// inputs are finite.  Mode 1 emits every centre at or above the row's
+// threshold.  `ragged` masks centres >= k (only the last tiles have them).
 template <int MODE>
 __device__ __forceinline__ void tile_epilogue(const f32x16& acc, int jb, int k, bool ragged,
                                               float& m1, int& j1, float& m2, float thr,
