@@ -848,21 +848,54 @@ __global__ __launch_bounds__(kBlock) void k_scatter_rows(const int32_t* __restri
     perm[atomicAdd(&cursor[a[i]], 1)] = (int32_t)i;
 }
 
-// One block per cluster, one thread per column (d <= 256 per pass).
+// One block per cluster.  Wave w takes the cluster's rows w, w + 4, ...;
+// lane l takes columns 4l .. 4l + 3 of every 256-column step (one 16-byte
+// load when the rows allow it), so every row is one coalesced read.  The four
+// waves' partial sums meet in LDS: integer additions, so the sums do not
+// depend on which wave took which row.
 __global__ __launch_bounds__(kBlock) void k_cluster_sums(const int32_t* __restrict__ perm,
                                                          const int32_t* __restrict__ start,
                                                          const int32_t* __restrict__ cnt,
                                                          const float* __restrict__ X, int64_t ldx,
-                                                         int64_t d, double fx,
+                                                         int64_t d, double fx, int vec,
                                                          long long* __restrict__ S,
                                                          int32_t* __restrict__ dirty) {
+  constexpr int W = kBlock / 64;
+  __shared__ long long part[W][256];
   const int j = blockIdx.x;
   const int32_t b = start[j], m = cnt[j];
-  for (int64_t t = threadIdx.x; t < d; t += kBlock) {
-    long long acc = 0;
-    for (int32_t q = 0; q < m; ++q)
-      acc += __double2ll_rn((double)X[(size_t)perm[b + q] * ldx + t] * fx);
-    S[(size_t)j * d + t] = acc;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int64_t c0 = 0; c0 < d; c0 += 256) {
+    const int64_t c = c0 + 4 * lane;
+    long long acc[4] = {0, 0, 0, 0};
+#pragma unroll 4
+    for (int32_t q = w; q < m; q += W) {
+      const float* xr = X + (size_t)perm[b + q] * ldx;
+      float v[4];
+      if (vec && c + 3 < d) {
+        const float4 f = *reinterpret_cast<const float4*>(xr + c);
+        v[0] = f.x;
+        v[1] = f.y;
+        v[2] = f.z;
+        v[3] = f.w;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] = (c + e < d) ? xr[c + e] : 0.f;
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[e] += __double2ll_rn((double)v[e] * fx);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) part[w][4 * lane + e] = acc[e];
+    __syncthreads();
+    const int t = threadIdx.x;  // kBlock = 256 columns of this step
+    if (c0 + t < d) {
+      long long sum = 0;
+#pragma unroll
+      for (int q = 0; q < W; ++q) sum += part[q][t];
+      S[(size_t)j * d + c0 + t] = sum;
+    }
+    __syncthreads();
   }
   if (threadIdx.x == 0) dirty[j] = 1;
 }
@@ -1092,8 +1125,9 @@ hipError_t launch_cluster_sums(const int32_t* a, int64_t n, int32_t k, const flo
   hipLaunchKernelGGL(k_scatter_rows, dim3((unsigned)blocks), dim3(kBlock), 0, s, a, n, cursor,
                      perm);
   if ((e = hipGetLastError()) != hipSuccess) return e;
+  const int vec = ((uintptr_t)X % 16 == 0 && ldx % 4 == 0) ? 1 : 0;
   hipLaunchKernelGGL(k_cluster_sums, dim3((unsigned)k), dim3(kBlock), 0, s, perm, start, cnt, X,
-                     ldx, d, fx, S, dirty);
+                     ldx, d, fx, vec, S, dirty);
   return hipGetLastError();
 }
 
