@@ -385,6 +385,31 @@ def test_dense_bf16_ragged_matches_oracle(skm, torch_cuda, d, k):
         assert np.linalg.norm(C64 - ref.C, axis=1).max() < 1e-6
 
 
+def test_dense_shape_sweep_matches_oracle(skm, torch_cuda):
+    """Seeded sweep of small dense shapes (row counts that leave partial
+    waves and blocks, widths on both sides of every padded width, k on both
+    sides of the 32-centre tiles and 64-centre chunks), FP32 and BF16, Lloyd
+    and Hamerly: whole trajectories equal the oracle's."""
+    torch = torch_cuda
+    rng = np.random.default_rng(20260)
+    shapes = [(1, 3, 1), (70, 17, 2), (300, 31, 31), (513, 33, 32), (600, 64, 33),
+              (777, 65, 63), (1000, 100, 64), (1029, 129, 65), (640, 200, 100),
+              (900, 256, 129)]
+    for n, d, k in shapes:
+        X = datagen.dense_vmf(n, d, max(2, k // 2), int(rng.integers(1 << 30)))
+        C0 = X[datagen.init_rows(n, k, int(rng.integers(1 << 30)))].copy()
+        ref = oracle.fit(dense_csr(X), C0, "lloyd", 15)
+        Xd = skm.DeviceDense.from_host(X)
+        for prec in (0, 1):
+            for v in ("lloyd", "hamerly"):
+                say("case dense sweep n=%d d=%d k=%d precision=%d %s" % (n, d, k, prec, v))
+                a, C, C64, st = run_fit(skm, torch, Xd, C0, k, v, 15, precision=prec,
+                                        schedule=1)
+                assert st.iterations == ref.iterations
+                assert np.array_equal(a, ref.a)
+                assert np.linalg.norm(C64 - ref.C, axis=1).max() < 1e-6
+
+
 def test_c4_full_size_bf16_subsample(skm, torch_cuda):
     """Full c4 workload (n=2e6 vMF rows, d=256, k=4096), BF16 MFMA with
     error-widened bounds: step 1 from the initial centres against FP64 on a
