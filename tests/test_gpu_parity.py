@@ -385,6 +385,27 @@ def test_dense_bf16_ragged_matches_oracle(skm, torch_cuda, d, k):
         assert np.linalg.norm(C64 - ref.C, axis=1).max() < 1e-6
 
 
+def test_sparse_k_sweep_matches_oracle(skm, torch_cuda):
+    """k on both sides of every centre-copy width the row walk specialises
+    for (one 64-centre lane set, 128-byte lines of 32 FP32 or 64 FP16
+    centres, the 2048 / 4096 ends), every variant, FP32 and FP16 copies:
+    whole trajectories equal the oracle's on a small tf-idf matrix."""
+    torch = torch_cuda
+    X = datagen.sparse_tfidf(4200, 3000, 30.0, 9090)
+    Xd = skm.DeviceCSR.from_host(X)
+    for k in (1, 2, 63, 64, 65, 127, 128, 129, 255, 256, 257, 513, 1025, 2047, 2049, 4096):
+        C0 = datagen.init_centers_csr(X, datagen.init_rows(X.n, k, 31 + k))
+        ref = oracle.fit(X, C0, "lloyd", 8)
+        for v in VARIANTS:
+            for prec in (0, 2):
+                say("case sparse k sweep k=%d %s precision=%d" % (k, v, prec))
+                a, C, C64, st = run_fit(skm, torch, Xd, C0, k, v, 8, precision=prec,
+                                        schedule=1)
+                assert st.iterations == ref.iterations
+                assert np.array_equal(a, ref.a)
+                assert np.linalg.norm(C64 - ref.C, axis=1).max() < 1e-6
+
+
 def test_dense_shape_sweep_matches_oracle(skm, torch_cuda):
     """Seeded sweep of small dense shapes (row counts that leave partial
     waves and blocks, widths on both sides of every padded width, k on both
