@@ -569,10 +569,10 @@ __global__ __launch_bounds__(kBlock) void k_dense_post(DensePostArgs A) {
   if (threadIdx.x == 0 && sh_changed) atomicAdd(&counter_slot(A.cnt)->changed, sh_changed);
 }
 
-// FP64 re-decision of the flagged rows against the FP64 master centres, one
-// wave per row: the listed candidates one after another, each by the whole
-// wave; a row with more candidates than the list holds evaluates all k
-// centres, one lane each with a sequential FP64 chain.  Either order is
+// FP64 re-decision of the flagged rows against the FP64 master centres, two
+// rows per wave: the listed candidates one after another, each by the row's
+// half-wave; a row with more candidates than the list holds evaluates all k
+// centres with the whole wave, one lane each with a sequential FP64 chain.  Either order is
 // fixed, and the winner (FP64 argmax, tie rule) does not depend on the order
 // in which the candidates were listed.
 __global__ __launch_bounds__(kBlock) void k_dense_exact(DenseExactArgs A) {
@@ -583,68 +583,94 @@ __global__ __launch_bounds__(kBlock) void k_dense_exact(DenseExactArgs A) {
   }
   __syncthreads();
   const int lane = threadIdx.x & 63;
+  const int half = lane >> 5, hl = lane & 31;
   const int64_t count = (int64_t)(*A.near_count);
+  const int64_t nw = ((int64_t)gridDim.x * kBlock) >> 6;
   unsigned long long moved = 0, rech = 0;
-  for (int64_t w = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6; w < count;
-       w += ((int64_t)gridDim.x * kBlock) >> 6) {
-    const int64_t sl = A.near_list[w];            // slot of the similarity pass
-    const int64_t row = A.rows ? A.rows[sl] : sl;
-    const int prev = A.read_prev ? A.a[row] : -1;
-    const int nc = A.cand_n[w];
-    const bool all = nc > A.cand_cap;
-    const int ncand = all ? A.k : nc;
-    const float* x = A.X + (size_t)row * A.ldx;
+  // two flagged rows per wave, one per half-wave, so that two rows' chains
+  // of dependent loads are in flight together
+  for (int64_t w0 = (((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6) * 2; w0 < count;
+       w0 += 2 * nw) {
+    const int64_t w = w0 + half;
+    const bool valid = w < count;
+    int64_t sl = 0, row = 0;
+    int prev = -1, nc = 0;
+    if (valid) {
+      sl = A.near_list[w];  // slot of the similarity pass
+      row = A.rows ? A.rows[sl] : sl;
+      prev = A.read_prev ? A.a[row] : -1;
+      nc = A.cand_n[w];
+    }
     double cb = -INFINITY;
     int cj = INT_MAX;
-    if (!all) {
-      // listed candidates one at a time, the whole wave on each: lane l
-      // holds terms 4l .. 4l+3 (d <= 256), a four-term FMA chain, then a
-      // fixed xor tree over the lanes; every lane ends with the same value
-      double xv[4];
+    if (valid && nc <= A.cand_cap) {
+      // listed candidates one at a time, the half-wave on each: lane l of
+      // the half holds terms l + 32 q (d <= 256), an eight-term FMA chain,
+      // then a fixed xor tree over the half's lanes; all its lanes end with
+      // the same value
+      const float* x = A.X + (size_t)row * A.ldx;
+      double xv[8];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int t = 4 * lane + q;
+      for (int q = 0; q < 8; ++q) {
+        const int t = hl + 32 * q;
         xv[q] = (t < A.d) ? (double)x[t] : 0.0;
       }
       const int32_t* cl = A.cand + (size_t)w * A.cand_cap;
-      for (int c = 0; c < ncand; ++c) {
+      for (int c = 0; c < nc; ++c) {
         const int j = cl[c];
         const double* cj64 = A.C64 + (size_t)j * A.d;
         double acc = 0.0;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int t = 4 * lane + q;
+        for (int q = 0; q < 8; ++q) {
+          const int t = hl + 32 * q;
           acc = fma(xv[q], (t < A.d) ? cj64[t] : 0.0, acc);
         }
 #pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+        for (int off = 16; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
         if (better64(acc, j, cb, cj, prev)) {
           cb = acc;
           cj = j;
         }
       }
-    } else {
-      // more candidates than the list holds: every centre, one lane each
-      for (int c = lane; c < ncand; c += 64) {
+    }
+    // rows with more candidates than the list holds: the whole wave takes
+    // every centre, one lane each with a sequential FP64 chain, one such row
+    // at a time
+    for (int h = 0; h < 2; ++h) {
+      const int64_t wh = w0 + h;
+      if (wh >= count) break;
+      const int nch = A.cand_n[wh];
+      if (nch <= A.cand_cap) continue;
+      const int64_t slh = A.near_list[wh];
+      const int64_t rowh = A.rows ? A.rows[slh] : slh;
+      const int prevh = A.read_prev ? A.a[rowh] : -1;
+      const float* xh = A.X + (size_t)rowh * A.ldx;
+      double ob = -INFINITY;
+      int oj = INT_MAX;
+      for (int c = lane; c < A.k; c += 64) {
         const double* cj64 = A.C64 + (size_t)c * A.d;
         double acc = 0.0;
-        for (int t = 0; t < A.d; ++t) acc = fma((double)x[t], cj64[t], acc);
-        if (better64(acc, c, cb, cj, prev)) {
-          cb = acc;
-          cj = c;
+        for (int t = 0; t < A.d; ++t) acc = fma((double)xh[t], cj64[t], acc);
+        if (better64(acc, c, ob, oj, prevh)) {
+          ob = acc;
+          oj = c;
         }
       }
-    }
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-      const double ob = __shfl_xor(cb, off, 64);
-      const int oj = __shfl_xor(cj, off, 64);
-      if (better64(ob, oj, cb, cj, prev)) {
+      for (int off = 32; off >= 1; off >>= 1) {
+        const double b2 = __shfl_xor(ob, off, 64);
+        const int j2 = __shfl_xor(oj, off, 64);
+        if (better64(b2, j2, ob, oj, prevh)) {
+          ob = b2;
+          oj = j2;
+        }
+      }
+      if (half == h) {
         cb = ob;
         cj = oj;
       }
     }
-    if (lane == 0) {
+    if (valid && hl == 0) {
       A.a[row] = cj;
       moved += (cj != prev) ? 1 : 0;
       rech += 1;
