@@ -518,19 +518,30 @@ __global__ __launch_bounds__(MfmaCfg<BF16>::WAVES * 64) void k_dense_sim(DenseSi
 
 
 // Rigorous bound on |s_hat - <x, c>| for one row of the dense contraction.
-// BF16: x is rounded once to BF16 and the centre twice (FP64 -> FP32 ->
-// BF16), relative errors 2^-8 and 2^-8 + 2^-24 (8-bit significand, RNE);
-// products are exact; the FP32 accumulation starts at 2 or 4 (the top-2 pass
-// offsets values) so every partial sum is below 5 |x||c| + 4, taken with
-// unit 2^-23 to cover accumulation that truncates; replacing four low bits
-// of the offset value (below 8) and removing the offset add below 2^-17.
+// BF16: the pass multiplies x^ = x + dx and c^ = c + dc (the BF16 copies);
+// by Cauchy-Schwarz <x^, c^> - <x, c> = <dx, c> + <x, dc> + <dx, dc> is at
+// most rx |c| + |x| rc + rx rc, with rx = |dx| measured per row when the
+// copy is made and rc the largest |dc| of any centre copy made in the fit
+// (both rounded up; without them, the worst case of RNE to an 8-bit
+// significand: rx <= 2^-8 |x|, rc <= (2^-8 + 2^-24) |c|).  Products are
+// exact; the FP32 accumulation starts at 2 or 4 (the top-2 pass offsets
+// values) so every partial sum is below 5 |x||c| + 4, taken with unit 2^-23
+// to cover accumulation that truncates; replacing four low bits of the
+// offset value (below 8) and removing the offset add below 2^-17.
 // FP32: the centre copy, every product and every sum (unit 2^-23 for the
-// sums, as above).  Both are relative to sum |x_t c_t| <= |x| |c| <= 1 + eta.
-__device__ __forceinline__ double dense_eps(bool bf16, int dp, double eta) {
-  const double unit = bf16 ? (2.0 * 0.00390625 + 1.52587890625e-05 + 2.0 * kU32 +
-                              10.5 * (dp + 2) * kU32 + 7.62939453125e-06)
-                           : ((2 * dp + 3) * kU32);
-  return unit * (1.0 + eta) * 1.01;
+// sums, as above).  Relative terms are relative to sum |x_t c_t| <= |x| |c|
+// <= 1 + eta; the factor 1.01 covers |x^| |c^| and |c| - 1.
+__device__ __forceinline__ double dense_eps(bool bf16, int dp, double eta, const float* xr,
+                                            const float* rcmax, int64_t row) {
+  if (!bf16) return (2 * dp + 3) * kU32 * (1.0 + eta) * 1.01;
+  const double acc = (2.0 * kU32 + 10.5 * (dp + 2) * kU32 + 7.62939453125e-06) * (1.0 + eta);
+  if (!xr || !rcmax)
+    return ((2.0 * 0.00390625 + 1.52587890625e-05) * (1.0 + eta) + acc) * 1.01;
+  float rc32 = 0.f;
+#pragma unroll
+  for (int q = 0; q < kRcSlots; ++q) rc32 = fmaxf(rc32, rcmax[q]);
+  const double rx = (double)xr[row], rc = (double)rc32;
+  return (rx + (1.0 + eta) * rc + rx * rc + acc) * 1.01;
 }
 
 // Decision after the top-2 pass: clear rows are final (FP32/BF16 argmax is
@@ -547,7 +558,7 @@ __global__ __launch_bounds__(kBlock) void k_dense_post(DensePostArgs A) {
     const int64_t row = A.rows ? A.rows[sl] : sl;
     const int prev = A.read_prev ? A.a[row] : -1;
     const double eta = (double)A.eta[row];
-    const double eps = dense_eps(A.bf16, A.dp, eta);
+    const double eps = dense_eps(A.bf16, A.dp, eta, A.xr, A.rcmax, row);
     const double b = A.best[sl], s2 = A.second[sl];
     const bool near = A.k > 1 && b - s2 <= 2.0 * eps;
     A.near[sl] = near ? 1 : 0;
@@ -677,7 +688,7 @@ __global__ __launch_bounds__(kBlock) void k_dense_exact(DenseExactArgs A) {
       if (A.best_out) A.best_out[row] = (float)cb;
       if (A.second_out && cj != A.best_j[sl]) A.second_out[row] = A.best[sl];
       const double eta = (double)A.eta[row];
-      const double eps = dense_eps(A.bf16, A.dp, eta);
+      const double eps = dense_eps(A.bf16, A.dp, eta, A.xr, A.rcmax, row);
       const double slack = 1.01 * (eta + A.delta_c);
       const double rho64 = (double)(A.d + 2) * kU64 * (1.0 + eta) * 1.01 + slack + 1e-15;
       const double rho = eps + slack + 1e-12;
@@ -975,25 +986,53 @@ __global__ __launch_bounds__(kBlock) void k_copy_assign(const int32_t* __restric
 __global__ __launch_bounds__(kBlock) void k_pack_centres(const double* __restrict__ C64,
                                                          int32_t k, int64_t d, int dp,
                                                          const int32_t* __restrict__ dirty,
-                                                         int bf16, void* __restrict__ out) {
+                                                         int bf16, void* __restrict__ out,
+                                                         float* __restrict__ rcmax) {
   const int j = blockIdx.x;
   if (j >= k || (dirty && !dirty[j])) return;
+  double rr = 0.0;  // |c^ - c|^2 of the BF16 copy (each difference exact)
   for (int t = threadIdx.x; t < dp; t += kBlock) {
     const double c = t < d ? C64[(size_t)j * d + t] : 0.0;
-    if (bf16) reinterpret_cast<__bf16*>(out)[(size_t)j * dp + t] = (__bf16)(float)c;
-    else reinterpret_cast<float*>(out)[(size_t)j * dp + t] = (float)c;
+    if (bf16) {
+      const __bf16 h = (__bf16)(float)c;
+      reinterpret_cast<__bf16*>(out)[(size_t)j * dp + t] = h;
+      const double e = (double)(float)h - c;
+      rr = fma(e, e, rr);
+    } else {
+      reinterpret_cast<float*>(out)[(size_t)j * dp + t] = (float)c;
+    }
+  }
+  if (bf16 && rcmax) {
+    // largest copy error of the fit so far, kept in kRcSlots slots (by
+    // centre) so that few blocks meet on one address: the largest slot bounds
+    // every current copy
+    __shared__ double part[kBlock / 64];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) rr += __shfl_xor(rr, off, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = rr;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int w = 0; w < kBlock / 64; ++w) t += part[w];
+      const float r32 = __double2float_ru(sqrt(t) * (1.0 + 1e-12));
+      int* slot = reinterpret_cast<int*>(rcmax) + (j % kRcSlots);
+      if (__float_as_int(r32) > __atomic_load_n(slot, __ATOMIC_RELAXED))
+        atomicMax(slot, __float_as_int(r32));
+    }
   }
 }
 
 // One pass over dense rows: | |x_i| - 1 | bound per row (FP64 sum of squares)
-// and, when Xb is given, the BF16 copy padded to dp columns.  One wave per
+// and, when Xb is given, the BF16 copy padded to dp columns with the norm of
+// its rounding error per row (xerr, rounded up; each difference is exact).  One wave per
 // row, grid-strided; lane l takes columns 4l .. 4l + 3 of every 256-column
 // step (one 16-byte load when the rows allow it).
 __global__ __launch_bounds__(kBlock) void k_dense_prep(const float* __restrict__ X, int64_t ldx,
                                                        int64_t n, int64_t d, int dp, int vec,
                                                        float* __restrict__ eta,
                                                        float* __restrict__ max_eta,
-                                                       __bf16* __restrict__ Xb) {
+                                                       __bf16* __restrict__ Xb,
+                                                       float* __restrict__ xerr) {
   typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
   const int lane = threadIdx.x & 63;
   const int64_t w0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
@@ -1002,7 +1041,7 @@ __global__ __launch_bounds__(kBlock) void k_dense_prep(const float* __restrict__
   float emax = 0.f;
   for (int64_t i = w0; i < n; i += nw) {
     const float* xr = X + (size_t)i * ldx;
-    double ss = 0.0;
+    double ss = 0.0, rr = 0.0;
     for (int c = 4 * lane; c < width; c += 256) {
       float v[4];
       if (vec && c + 3 < d) {
@@ -1020,12 +1059,20 @@ __global__ __launch_bounds__(kBlock) void k_dense_prep(const float* __restrict__
       if (Xb) {
         bf16x4 b;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) b[e] = (__bf16)v[e];
+        for (int e = 0; e < 4; ++e) {
+          b[e] = (__bf16)v[e];
+          const double r = (double)((float)b[e] - v[e]);
+          rr = fma(r, r, rr);
+        }
         *reinterpret_cast<bf16x4*>(Xb + (size_t)i * dp + c) = b;
       }
     }
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) ss += __shfl_xor(ss, off, 64);
+    for (int off = 32; off >= 1; off >>= 1) {
+      ss += __shfl_xor(ss, off, 64);
+      rr += __shfl_xor(rr, off, 64);
+    }
+    if (xerr && lane == 0) xerr[i] = __double2float_ru(sqrt(rr) * (1.0 + 1e-12));
     const double dev = fabs(sqrt(ss) - 1.0) + (double)(d + 4) * kU64 * 2.0 + 1e-300;
     const float e32 = __double2float_ru(dev);
     if (lane == 0) eta[i] = e32;
@@ -1176,20 +1223,21 @@ hipError_t launch_copy_assign(const int32_t* a, int32_t* a_old, int64_t n, hipSt
 }
 
 hipError_t launch_pack_centres(const double* C64, int32_t k, int64_t d, int dp,
-                               const int32_t* dirty, int bf16, void* out, hipStream_t s) {
+                               const int32_t* dirty, int bf16, void* out, float* rcmax,
+                               hipStream_t s) {
   hipLaunchKernelGGL(k_pack_centres, dim3((unsigned)k), dim3(kBlock), 0, s, C64, k, d, dp, dirty,
-                     bf16, out);
+                     bf16, out, rcmax);
   return hipGetLastError();
 }
 
 hipError_t launch_dense_prep(const float* X, int64_t ldx, int64_t n, int64_t d, int dp,
-                             float* eta, float* max_eta, void* Xb, hipStream_t s) {
+                             float* eta, float* max_eta, void* Xb, float* xr, hipStream_t s) {
   const int vec = ((uintptr_t)X % 16 == 0 && ldx % 4 == 0) ? 1 : 0;
   int64_t blocks = (n + kBlock / 64 - 1) / (kBlock / 64);
   if (blocks > 8192) blocks = 8192;
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(k_dense_prep, dim3((unsigned)blocks), dim3(kBlock), 0, s, X, ldx, n, d, dp,
-                     vec, eta, max_eta, reinterpret_cast<__bf16*>(Xb));
+                     vec, eta, max_eta, reinterpret_cast<__bf16*>(Xb), xr);
   return hipGetLastError();
 }
 

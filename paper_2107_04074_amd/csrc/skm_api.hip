@@ -252,7 +252,7 @@ struct DensePlan {
          second = 0, thr = 0, near = 0, rflag = 0, rows = 0, nlist = 0, nrows = 0, nthr = 0,
          bcnt = 0, boff = 0, cand = 0, cand_n = 0, ccnt = 0, cstart = 0, ccur = 0, perm = 0,
          norm64 = 0, part = 0, part_sq = 0, pc = 0, ps = 0, dirty = 0, mm = 0, G = 0, gmax = 0,
-         gpart = 0, cnt = 0, per = 0, maxeta = 0, initnorm = 0, total = 0;
+         gpart = 0, cnt = 0, per = 0, maxeta = 0, initnorm = 0, xr = 0, rcmax = 0, total = 0;
 };
 
 int make_dense_plan(const skm_matrix* X, int32_t k, int32_t variant, int32_t precision,
@@ -287,7 +287,11 @@ int make_dense_plan(const skm_matrix* X, int32_t k, int32_t variant, int32_t pre
   };
   const size_t n = (size_t)X->n, d = (size_t)X->d, kk = (size_t)k;
   const size_t es = P->bf16 ? 2 : 4;
-  if (P->bf16) P->Xb = take(n * (size_t)P->dp * 2);
+  if (P->bf16) {
+    P->Xb = take(n * (size_t)P->dp * 2);
+    P->xr = take(n * 4);
+    P->rcmax = take(kRcSlots * 4);
+  }
   P->Cp = take((size_t)P->kpad * P->dp * es);
   P->C64 = take(kk * d * sizeof(double));
   P->S = take(kk * d * sizeof(long long));
@@ -386,6 +390,8 @@ hipError_t dense_step(const DenseRun& R, int32_t* a, int read_prev, const int32_
   Q.best_j = S1.best_j;
   Q.second = S1.second;
   Q.eta = R.ptr<float>(P.eta);
+  Q.xr = P.bf16 ? R.ptr<float>(P.xr) : nullptr;
+  Q.rcmax = P.bf16 ? R.ptr<float>(P.rcmax) : nullptr;
   Q.delta_c = (double)(P.d + 8) * kU64 * 1.01 + 1e-300;
   Q.a = a;
   Q.l = P.bounds ? R.ptr<float>(P.l) : nullptr;
@@ -430,6 +436,8 @@ hipError_t dense_step(const DenseRun& R, int32_t* a, int read_prev, const int32_
   E.best = S1.best;
   E.best_j = S1.best_j;
   E.eta = Q.eta;
+  E.xr = Q.xr;
+  E.rcmax = Q.rcmax;
   E.delta_c = Q.delta_c;
   E.a = a;
   E.l = Q.l;
@@ -509,10 +517,13 @@ int fit_dense(const skm_matrix* X, int32_t k, const float* init_centers, int32_t
     SKM_HIP(hipMemsetAsync(norm64, 0, (size_t)k * 8, s));
     SKM_HIP(hipMemsetAsync(R.ptr<float>(P.maxeta), 0, kCounterSlots * 4, s));
     SKM_HIP(launch_fill_i32(a_old, n, -1, s));
+    float* rcmax = P.bf16 ? R.ptr<float>(P.rcmax) : nullptr;
+    if (rcmax) SKM_HIP(hipMemsetAsync(rcmax, 0, kRcSlots * 4, s));
     SKM_HIP(launch_dense_prep(X->dense, X->ld, n, d, P.dp, R.ptr<float>(P.eta),
-                              R.ptr<float>(P.maxeta), P.bf16 ? R.ptr<char>(P.Xb) : nullptr, s));
+                              R.ptr<float>(P.maxeta), P.bf16 ? R.ptr<char>(P.Xb) : nullptr,
+                              P.bf16 ? R.ptr<float>(P.xr) : nullptr, s));
     SKM_HIP(launch_init_centres(init_centers, k, d, 1, C64, R.ptr<double>(P.initnorm), s));
-    SKM_HIP(launch_pack_centres(C64, k, d, P.dp, nullptr, P.bf16, Cp, s));
+    SKM_HIP(launch_pack_centres(C64, k, d, P.dp, nullptr, P.bf16, Cp, rcmax, s));
     if (o.validate >= 1) {
       float hslots[kCounterSlots];
       float hmax = 0.f;
@@ -550,7 +561,8 @@ int fit_dense(const skm_matrix* X, int32_t k, const float* init_centers, int32_t
       if ((e = launch_centre_finalize(k, d, dirty, norm64, part_sq, part, P.nchunk, delta_c, pc,
                                       ps, mm, per, s)) != hipSuccess)
         return e;
-      if ((e = launch_pack_centres(C64, k, d, P.dp, dirty, P.bf16, Cp, s)) != hipSuccess)
+      if ((e = launch_pack_centres(C64, k, d, P.dp, dirty, P.bf16, Cp,
+                                   P.bf16 ? R.ptr<float>(P.rcmax) : nullptr, s)) != hipSuccess)
         return e;
       if (P.gram) {
         if (t + 1 < off_until) {
@@ -725,9 +737,9 @@ int assign_dense(const skm_matrix* X, int32_t k, const float* centers, int32_t* 
     SKM_HIP(hipMemsetAsync(R.ptr<Persist>(P.per), 0, sizeof(Persist), s));
     SKM_HIP(hipMemsetAsync(R.ptr<Counters>(P.cnt), 0, kCounterSlots * sizeof(Counters), s));
     SKM_HIP(launch_dense_prep(X->dense, X->ld, P.n, P.d, P.dp, R.ptr<float>(P.eta), nullptr,
-                              nullptr, s));
+                              nullptr, nullptr, s));
     SKM_HIP(launch_init_centres(centers, k, P.d, 0, C64, nullptr, s));
-    SKM_HIP(launch_pack_centres(C64, k, P.d, P.dp, nullptr, 0, Cp, s));
+    SKM_HIP(launch_pack_centres(C64, k, P.d, P.dp, nullptr, 0, Cp, nullptr, s));
     SKM_HIP(dense_step(R, assign_out, 0, nullptr, nullptr, best_out, second_out,
                        R.ptr<Counters>(P.cnt)));
   }

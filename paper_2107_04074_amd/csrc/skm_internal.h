@@ -18,6 +18,7 @@ constexpr int kMaxGridBlocks = 2048;  // persistent grids: 8 blocks per CU
 // so that no single address takes more than a few atomics; the host sums
 // the slots after each step and clears them before the next.
 constexpr int kCounterSlots = 64;
+constexpr int kRcSlots = 16;      // slots of the largest BF16 centre-copy error
 struct Counters {                 // one 128-byte line
   unsigned long long changed;     // rows whose assignment changed
   unsigned long long sims;        // point-centre similarities evaluated
@@ -185,6 +186,8 @@ struct DensePostArgs {
   const int32_t* best_j;
   const float* second;
   const float* eta;
+  const float* xr;            // BF16: per-row |x^ - x| (nullable: worst case)
+  const float* rcmax;         // BF16: largest centre-copy error, kRcSlots slots (nullable: worst case)
   double delta_c;
   int32_t* a;
   float* l;
@@ -212,6 +215,8 @@ struct DenseExactArgs {
   const float* best;          // per slot
   const int32_t* best_j;
   const float* eta;
+  const float* xr;            // as in DensePostArgs
+  const float* rcmax;
   double delta_c;
   int32_t* a;
   float* l;
@@ -263,9 +268,10 @@ hipError_t launch_dense_update_scan(const float* X, int64_t ldx, const int32_t* 
                                     long long* S, int32_t* dirty, hipStream_t s);
 hipError_t launch_copy_assign(const int32_t* a, int32_t* a_old, int64_t n, hipStream_t s);
 hipError_t launch_pack_centres(const double* C64, int32_t k, int64_t d, int dp,
-                               const int32_t* dirty, int bf16, void* out, hipStream_t s);
+                               const int32_t* dirty, int bf16, void* out, float* rcmax,
+                               hipStream_t s);
 hipError_t launch_dense_prep(const float* X, int64_t ldx, int64_t n, int64_t d, int dp,
-                             float* eta, float* max_eta, void* Xb, hipStream_t s);
+                             float* eta, float* max_eta, void* Xb, float* xr, hipStream_t s);
 
 // ---- launchers (kernels_assign.hip) ----
 hipError_t launch_assign(const AssignArgs& A, int mode, hipStream_t s);
