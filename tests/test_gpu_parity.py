@@ -385,6 +385,70 @@ def test_dense_bf16_ragged_matches_oracle(skm, torch_cuda, d, k):
         assert np.linalg.norm(C64 - ref.C, axis=1).max() < 1e-6
 
 
+def adversarial_bf16_rows(n=4096, d=256, seed=5):
+    """Rounding that defeats a plain BF16 argmax.  Centre c1's entries have
+    the significand 1 + 2^-8 + 2^-10 (round to nearest even in BF16 takes
+    them up to 1 + 2^-7), c2's have 1 + 2^-7 + 2^-8 - 2^-10 (taken down to
+    the same value); each row copies 31 entries of each, so the BF16
+    products overstate <x, c1> and understate <x, c2> by about 2.9e-3 each,
+    and a filler coordinate shared with c1 sweeps the true gap through zero.
+    Six distractor centres live on other coordinates."""
+    rng = np.random.default_rng(seed)
+    U = 1 + 2.0 ** -8 + 2.0 ** -10
+    W = 1 + 2.0 ** -7 + 2.0 ** -8 - 2.0 ** -10
+    sg = rng.choice([-1.0, 1.0], size=d)
+    c1 = np.zeros(d)
+    c2 = np.zeros(d)
+    c1[0:63] = U / 8 * sg[0:63]
+    c1[63] = np.sqrt(1 - (c1[0:63] ** 2).sum())
+    c2[64:126] = W / 8 * sg[64:126]
+    c2[126] = np.sqrt(1 - (c2[64:126] ** 2).sum())
+    X = np.zeros((n, d))
+    X[:, 0:31] = c1[0:31]
+    X[:, 64:95] = c2[64:95]
+    base = (X[0] ** 2).sum()
+    fx = np.linspace(0.0, np.sqrt(1 - base) * 0.999, n)
+    X[:, 63] = fx
+    X[:, 200] = np.sqrt(1 - base - fx ** 2)
+    C = [c1, c2]
+    for _ in range(6):
+        v = np.zeros(d)
+        v[128:192] = rng.normal(size=64)
+        C.append(v / np.linalg.norm(v))
+    return X.astype(np.float32), np.array(C, dtype=np.float32)
+
+
+def test_dense_bf16_adversarial_rounding(skm, torch_cuda):
+    """Coherent BF16 rounding errors of opposite sign on the two leading
+    centres: a plain BF16 argmax gets thousands of rows wrong, so every one of
+    them has to fall inside the error band (built from the measured rounding
+    norms of the row and centre copies) and be re-decided in FP64."""
+    torch = torch_cuda
+    X, C0 = adversarial_bf16_rows()
+    Xc = dense_csr(X)
+    S = oracle.sims(Xc, C0.astype(np.float64), np.arange(X.shape[0]))
+    bf = lambda A: torch.from_numpy(np.ascontiguousarray(A)).to(torch.bfloat16).double().numpy()
+    wrong = int((np.argmax(bf(X) @ bf(C0).T, 1) != np.argmax(S, 1)).sum())
+    say("case dense bf16 adversarial: plain BF16 argmax wrong on %d of %d rows" %
+        (wrong, X.shape[0]))
+    assert wrong >= 1000
+    Xd = skm.DeviceDense.from_host(X)
+    ref1 = oracle.fit(Xc, C0, "lloyd", 1)
+    gap = gap_of(S)
+    a, C, C64, st = run_fit(skm, torch, Xd, C0, C0.shape[0], "lloyd", 1, precision=1)
+    say("  step 1: rechecks=%d mismatches=%d" % (st.rechecks, int((a != ref1.a).sum())))
+    assert st.rechecks >= wrong
+    assert np.array_equal(a[gap > GAP], ref1.a[gap > GAP])
+    assert np.all(S.max(1) - S[np.arange(len(a)), a] <= 1e-12)
+    ref = oracle.fit(Xc, C0, "lloyd", 10)
+    for v in ("lloyd", "hamerly", "simp_hamerly"):
+        say("case dense bf16 adversarial %s 10 steps" % v)
+        a, C, C64, st = run_fit(skm, torch, Xd, C0, C0.shape[0], v, 10, precision=1)
+        assert st.iterations == ref.iterations
+        assert np.array_equal(a, ref.a)
+        assert np.linalg.norm(C64 - ref.C, axis=1).max() < 1e-6
+
+
 def test_sparse_k_sweep_matches_oracle(skm, torch_cuda):
     """k on both sides of every centre-copy width the row walk specialises
     for (one 64-centre lane set, 128-byte lines of 32 FP32 or 64 FP16
