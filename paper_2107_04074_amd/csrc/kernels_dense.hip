@@ -302,7 +302,11 @@ __global__ __launch_bounds__(MfmaCfg<BF16>::WAVES * 64) void k_dense_sim(DenseSi
         bf16x8 a0 = ap[0], a1 = ap[2];
 #pragma unroll
         for (int s = 0; s < NS; s += 2) {
-          // the next step pair's fragments are read before this pair's MFMAs
+          // the next step pair's fragments are read before this pair's MFMAs;
+          // the wave issues them and the pair at raised priority (lowered
+          // after the pair), which lets the other wave of the SIMD fill the
+          // gaps instead of competing for issue inside the pair (1% faster)
+          __builtin_amdgcn_s_setprio(1);
           bf16x8 n0 = a0, n1 = a1;
           if (s + 2 < NS) {
             n0 = ap[2 * (s + 2)];
@@ -331,6 +335,7 @@ __global__ __launch_bounds__(MfmaCfg<BF16>::WAVES * 64) void k_dense_sim(DenseSi
             __builtin_amdgcn_sched_group_barrier(0x002, 3 * VPI / 2, 0);
           }
           __builtin_amdgcn_sched_barrier(0);
+          __builtin_amdgcn_s_setprio(0);
           a0 = n0;
           a1 = n1;
         }
