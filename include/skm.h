@@ -33,9 +33,12 @@
  * -------------------------
  *  SKM_CSR_F32:   row_ptr int64[n+1] (row_ptr[0] = 0, non-decreasing,
  *                 row_ptr[n] = nnz), col_idx int32[nnz] in [0, d), val
- *                 float[nnz].  Column ids ascending within a row is the
- *                 expected layout (the paper stores sparse vectors as sorted
- *                 (index, value) pairs, Section 2) but not required.
+ *                 float[nnz].  Column ids strictly ascending within a row
+ *                 is the expected layout (the paper stores sparse vectors as
+ *                 sorted (index, value) pairs, Section 2); options.validate
+ *                 = 2 checks all of this.  d * k (k padded to the row
+ *                 kernels' width: 16, 32, 64, 128, 256, then multiples of
+ *                 256) must stay below 2^32 (else SKM_ERR_UNSUPPORTED).
  *  SKM_DENSE_F32: dense float[n * ld], row-major, ld >= d.
  *  Rows must have unit L2 norm (Section 5: samples are normalised during
  *  initialisation).  Float rounding of the norm is tolerated: internal
@@ -104,7 +107,16 @@ typedef struct {            /* [host]; an all-zero struct means defaults      */
                                the CSR row walk (k >= 65); every precision
                                keeps the same exact-argmax guarantee          */
   int32_t validate;         /* 0 = none; 1 = initial centres must be unit
-                               within norm_tol; 2 = also every data row      */
+                               within norm_tol (else SKM_ERR_NOT_NORMALIZED);
+                               2 = also every data row unit within norm_tol,
+                               and, before any kernel walks the rows, the
+                               layout: CSR row_ptr[0] = 0, non-decreasing,
+                               row_ptr[n] = nnz, column ids in [0, d) and
+                               strictly ascending within each row; every
+                               value finite (CSR and dense).  A layout
+                               violation returns SKM_ERR_INVALID_ARG naming
+                               the first offending row.  Without validate =
+                               2 a malformed matrix is undefined behaviour. */
   int32_t profile;          /* 1 = time every launch of the similarity kernel
                                with HIP events on `stream` (fills the
                                sim_kernel_* statistics; adds event records) */
@@ -203,7 +215,7 @@ int skm_assign(const skm_matrix* X, int32_t k, const float* centers,
 /* Bytes of workspace skm_seed_kmeanspp needs. */
 size_t skm_seed_workspace_size(const skm_matrix* X, int32_t k);
 
-/* Spherical k-means++ seeding (Section 6, "Spherical k-means++"): centre 0
+/* Spherical k-means++ seeding (Section 5.6, "Spherical k-means++"): centre 0
  * is row floor(u[0] n); centre t >= 1 is drawn with probability
  * proportional to alpha - max_c <x(i), c> over the centres chosen so far
  * (alpha = 1: cosine dissimilarity; alpha = 1.5: the metric form), as the
@@ -232,7 +244,7 @@ int skm_seed_kmeanspp(const skm_matrix* X, int32_t k, double alpha,
 /* Bytes of workspace skm_seed_afkmc2 needs. */
 size_t skm_seed_afkmc2_workspace_size(const skm_matrix* X, int32_t k, int32_t chain);
 
-/* AFK-MC2 seeding in the spherical form (Section 6 cites it with the
+/* AFK-MC2 seeding in the spherical form (Section 5.6 cites it with the
  * dissimilarity alpha - <x, c>): centre 0 is row floor(u[0] n) and fixes the
  * proposal distribution q(x) = w(x)/(2W) + 1/(2n), w(x) = max(0, alpha -
  * <x, c0>), W = sum of w (q = 1/n if W = 0).  Each further centre is the end

@@ -57,6 +57,10 @@ def _load():
         i64, i32, dbl, p = ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_void_p
         lib.oracle_assign.restype = None
         lib.oracle_assign.argtypes = [i64, i64, p, p, p, i32, p, p, p, p, p]
+        lib.oracle_assign_ct.restype = None
+        lib.oracle_assign_ct.argtypes = [i64, i64, p, p, p, i32, p, p, p, p, p]
+        lib.oracle_init_centres.restype = None
+        lib.oracle_init_centres.argtypes = [i32, i64, p]
         lib.oracle_sims.restype = None
         lib.oracle_sims.argtypes = [i64, i64, p, p, p, i32, p, p, i64, p]
         lib.oracle_update.restype = dbl
@@ -93,10 +97,13 @@ def _csr_args(X):
     return rp, ci, v
 
 
-def assign(X, C: np.ndarray, a_prev: Optional[np.ndarray] = None):
+def assign(X, C: np.ndarray, a_prev: Optional[np.ndarray] = None,
+           transposed: bool = False):
     """Exhaustive assignment step: (a, best, second) with the tie rule
     'keep the previous centre if it attains the maximum, else the lowest
-    index'.  C is k x d (float64; float32 is promoted exactly)."""
+    index'.  C is k x d (float64; float32 is promoted exactly).
+    ``transposed`` reads the centres from a d x k copy (same sums in the same
+    order, identical results; faster for large k and d)."""
     lib = _load()
     rp, ci, v = _csr_args(X)
     C = np.ascontiguousarray(C, dtype=np.float64)
@@ -105,8 +112,46 @@ def assign(X, C: np.ndarray, a_prev: Optional[np.ndarray] = None):
     s1 = np.empty(X.n)
     s2 = np.empty(X.n)
     ap = None if a_prev is None else np.ascontiguousarray(a_prev, dtype=np.int32)
-    lib.oracle_assign(X.n, X.d, _p(rp), _p(ci), _p(v), k, _p(C), _p(ap), _p(a), _p(s1), _p(s2))
+    if transposed:
+        CT = np.ascontiguousarray(C.T)
+        lib.oracle_assign_ct(X.n, X.d, _p(rp), _p(ci), _p(v), k, _p(CT), _p(ap), _p(a),
+                             _p(s1), _p(s2))
+    else:
+        lib.oracle_assign(X.n, X.d, _p(rp), _p(ci), _p(v), k, _p(C), _p(ap), _p(a), _p(s1),
+                          _p(s2))
     return a, s1, s2
+
+
+def lloyd_trajectory(X, C_init: np.ndarray, max_iter: int, on_step=None):
+    """Plain spherical Lloyd (Section 5) step by step, as oracle ``fit`` runs
+    it (INIT, ARGMAX, STOP and EMPTY readings), with the centres read from a
+    transposed copy.  After assignment step t (1-based) ``on_step(t, a, C,
+    best, second, changed, objective)`` sees the step's assignment, its top-2
+    similarities (against the centres before the step), the centres after the
+    update that follows it (unchanged when nothing changed) and sum_j |S(j)|
+    of those centres (None when nothing changed).  Returns (a, C, iterations,
+    converged)."""
+    lib = _load()
+    C = np.array(C_init, dtype=np.float64, order="C", copy=True)
+    k = C.shape[0]
+    lib.oracle_init_centres(k, X.d, _p(C))
+    a = None
+    it, conv = 0, False
+    for t in range(1, max_iter + 1):
+        a_new, s1, s2 = assign(X, C, a, transposed=True)
+        changed = X.n if a is None else int(np.count_nonzero(a_new != a))
+        a = a_new
+        it = t
+        obj = None
+        if changed == 0:
+            conv = True
+        else:
+            C, _, obj = update(X, a, C)
+        if on_step is not None:
+            on_step(t, a, C, s1, s2, changed, obj)
+        if conv:
+            break
+    return a, C, it, conv
 
 
 def kmeanspp(X, k: int, alpha: float, u: np.ndarray):

@@ -147,6 +147,50 @@ void oracle_assign(int64_t n, int64_t d, const int64_t *rp, const int32_t *ci,
   }
 }
 
+/* The same assignment step with the centres stored transposed: CT is d x k,
+ * CT[t * k + j] = c(j)_t.  Every similarity is the same sequential sum over
+ * the row's stored entries, in storage order and with the same operations
+ * as in oracle_assign, so the results are identical bit for bit; only the
+ * memory layout differs (each stored entry reads one contiguous column of
+ * the centres, which keeps the largest sparse workloads feasible here). */
+void oracle_assign_ct(int64_t n, int64_t d, const int64_t *rp, const int32_t *ci,
+                      const float *v, int32_t k, const double *CT,
+                      const int32_t *a_prev, int32_t *a_out, double *s1_out,
+                      double *s2_out) {
+  (void)d;
+#pragma omp parallel
+  {
+    double *s = (double *)malloc(sizeof(double) * (size_t)k);
+#pragma omp for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n; ++i) {
+      double b, sc;
+      for (int32_t j = 0; j < k; ++j) s[j] = 0.0;
+      for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+        const double x = (double)v[e];
+        const double *c = CT + (size_t)ci[e] * (size_t)k;
+        for (int32_t j = 0; j < k; ++j) s[j] += x * c[j];
+      }
+      a_out[i] = argmax_rule(s, k, a_prev ? a_prev[i] : -1, &b, &sc);
+      if (s1_out) s1_out[i] = b;
+      if (s2_out) s2_out[i] = sc;
+    }
+    free(s);
+  }
+}
+
+/* INIT reading: rescale every centre row of C (k x d) to unit length in
+ * double precision (rows of zeros stay as they are). */
+void oracle_init_centres(int32_t k, int64_t d, double *C) {
+  for (int32_t j = 0; j < k; ++j) {
+    double *c = C + (size_t)j * (size_t)d, ss = 0.0;
+    for (int64_t t = 0; t < d; ++t) ss += c[t] * c[t];
+    if (ss > 0.0) {
+      const double nrm = sqrt(ss);
+      for (int64_t t = 0; t < d; ++t) c[t] /= nrm;
+    }
+  }
+}
+
 /* Similarities of the listed rows to all centres: out is m x k. */
 void oracle_sims(int64_t n, int64_t d, const int64_t *rp, const int32_t *ci,
                  const float *v, int32_t k, const double *C,
@@ -187,7 +231,7 @@ double oracle_update(int64_t n, int64_t d, const int64_t *rp, const int32_t *ci,
 }
 
 /* -------------------------------------------------------------------- */
-/* spherical k-means++ seeding (Section 6, "Spherical k-means++")        */
+/* spherical k-means++ seeding (Section 5.6, "Spherical k-means++")        */
 /* -------------------------------------------------------------------- */
 
 /* The first centre is row floor(u[0] n); centre t >= 1 is drawn with
@@ -270,7 +314,7 @@ void oracle_kmeanspp(int64_t n, int64_t d, const int64_t *rp, const int32_t *ci,
   free(taken);
 }
 
-/* AFK-MC2 seeding in its spherical form (Section 6 cites it with the
+/* AFK-MC2 seeding in its spherical form (Section 5.6 cites it with the
  * dissimilarity alpha - <x, c>): centre 0 is row floor(u[0] n) and fixes the
  * proposal distribution q(x) = w(x) / (2 W) + 1 / (2 n), w(x) = max(0,
  * alpha - <x, c0>), W = sum w (q = 1/n when W = 0).  Centre t >= 1 comes
@@ -453,14 +497,7 @@ int32_t oracle_fit(int64_t n, int64_t d, const int64_t *rp, const int32_t *ci,
   double *C = (double *)malloc(sizeof(double) * (size_t)k * (size_t)d);
   double *Cold = (double *)malloc(sizeof(double) * (size_t)k * (size_t)d);
   memcpy(C, C_init, sizeof(double) * (size_t)k * (size_t)d);
-  for (int32_t j = 0; j < k; ++j) { /* INIT reading */
-    double *c = C + (size_t)j * (size_t)d, ss = 0.0;
-    for (int64_t t = 0; t < d; ++t) ss += c[t] * c[t];
-    if (ss > 0.0) {
-      const double nrm = sqrt(ss);
-      for (int64_t t = 0; t < d; ++t) c[t] /= nrm;
-    }
-  }
+  oracle_init_centres(k, d, C);
   int32_t *a = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
   for (int64_t i = 0; i < n; ++i) a[i] = -1;
   double *l = (double *)malloc(sizeof(double) * (size_t)n);

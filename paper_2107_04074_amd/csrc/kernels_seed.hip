@@ -1,4 +1,4 @@
-// Spherical k-means++ seeding (Section 6 of the paper, "Spherical
+// Spherical k-means++ seeding (Section 5.6 of the paper, "Spherical
 // k-means++"): the first centre is a uniformly drawn row, every further one
 // is drawn with probability proportional to alpha - max_c <x(i), c> over the
 // centres chosen so far.  The maximum is cached per row and refreshed once
@@ -230,7 +230,7 @@ hipError_t launch_kpp_step(const int64_t* rp, const int32_t* ci, const float* v,
 }  // namespace skm
 
 // ------------------------------------------------------------------------
-// AFK-MC2 seeding (the Markov-chain alternative to k-means++ that Section 6
+// AFK-MC2 seeding (the Markov-chain alternative to k-means++ that Section 5.6
 // cites, with the dissimilarity alpha - <x, c>).  Centre 0 fixes the
 // proposal distribution q; every further centre runs a chain of m proposals
 // drawn from q.  The proposals do not depend on the chain's state, so their

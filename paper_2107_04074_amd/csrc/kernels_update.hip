@@ -22,6 +22,8 @@
 #include <float.h>
 #include <limits.h>
 
+#include <algorithm>
+
 #include <hip/hip_fp16.h>
 
 #include "skm_device.h"
@@ -136,6 +138,53 @@ __global__ void k_neg_scan(const float* __restrict__ v, int64_t nnz,
   for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < nnz + ninit; e += stride)
     neg |= (e < nnz ? v[e] : init[e - nnz]) < 0.f;
   if (neg) *flag = 1;
+}
+
+// Input checks of validate = 2 (the matrix layout of Section 2: sparse rows
+// as (index, value) pairs with ascending indices; finite values).  A
+// violation is recorded as row * 8 + kind in *bad by an atomic minimum, so
+// the host reports the first offending row.  The CSR checks run in two
+// launches: k_check_rowptr reads row_ptr by flat index only, and
+// k_check_entries runs only after the host has seen it pass, so every row
+// range it walks lies inside [0, nnz).
+__global__ void k_check_rowptr(const int64_t* __restrict__ rp, int64_t n, int64_t nnz,
+                               unsigned long long* __restrict__ bad) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i > n) return;
+  const int64_t r = rp[i];
+  bool ok = true;
+  if (i == 0) ok = r == 0;
+  if (i == n) ok = ok && r == nnz;
+  if (i < n) ok = ok && rp[i + 1] >= r;
+  if (!ok) atomicMin(bad, (unsigned long long)i * 8ull + kBadRowPtr);
+}
+
+__global__ void k_check_entries(const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                const float* __restrict__ v, int64_t n, int64_t d,
+                                unsigned long long* __restrict__ bad) {
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+    const int64_t beg = rp[i], end = rp[i + 1];
+    int kind = 0;
+    int64_t prev = -1;
+    for (int64_t e = beg; e < end && kind == 0; ++e) {
+      const int64_t c = ci[e];
+      if (c < 0 || c >= d) kind = kBadColumn;
+      else if (c <= prev) kind = kBadOrder;
+      else if (!isfinite(v[e])) kind = kBadValue;
+      prev = c;
+    }
+    if (kind) atomicMin(bad, (unsigned long long)i * 8ull + (unsigned long long)kind);
+  }
+}
+
+__global__ void k_check_dense(const float* __restrict__ x, int64_t ld, int64_t n, int64_t d,
+                              unsigned long long* __restrict__ bad) {
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < n * d; e += stride) {
+    const int64_t i = e / d, t = e - i * d;
+    if (!isfinite(x[i * ld + t])) atomicMin(bad, (unsigned long long)i * 8ull + kBadValue);
+  }
 }
 
 // Scans the assignment for rows that moved since the last centre step and
@@ -748,6 +797,27 @@ hipError_t launch_neg_scan(const float* v, int64_t nnz, const float* init, int64
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(k_neg_scan, dim3((unsigned)blocks), dim3(kBlock), 0, s, v, nnz, init, ninit,
                      flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_rowptr(const int64_t* rp, int64_t n, int64_t nnz,
+                               unsigned long long* bad, hipStream_t s) {
+  hipLaunchKernelGGL(k_check_rowptr, dim3(blocks_for(n + 1)), dim3(kBlock), 0, s, rp, n, nnz,
+                     bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_entries(const int64_t* rp, const int32_t* ci, const float* v, int64_t n,
+                                int64_t d, unsigned long long* bad, hipStream_t s) {
+  const unsigned blocks = std::min(blocks_for(n), 4096u);
+  hipLaunchKernelGGL(k_check_entries, dim3(blocks), dim3(kBlock), 0, s, rp, ci, v, n, d, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_dense(const float* x, int64_t ld, int64_t n, int64_t d,
+                              unsigned long long* bad, hipStream_t s) {
+  const unsigned blocks = std::min(blocks_for(n * d), 4096u);
+  hipLaunchKernelGGL(k_check_dense, dim3(blocks), dim3(kBlock), 0, s, x, ld, n, d, bad);
   return hipGetLastError();
 }
 

@@ -70,7 +70,7 @@ struct Plan {
   size_t CT = 0, CT16 = 0, negflag = 0, C64 = 0, S = 0, l = 0, u = 0, ue = 0, eta = 0,
          a_old = 0, norm64 = 0, part = 0, part_sq = 0, pc = 0, ps = 0, dirty = 0, mm = 0, G = 0,
          gmax = 0, gpart = 0, cnt = 0, per = 0, ctl = 0, rec = 0, maxeta = 0, initnorm = 0,
-         total = 0;
+         vbad = 0, total = 0;
 };
 
 int check_matrix(const skm_matrix* X) {
@@ -95,6 +95,68 @@ int check_matrix(const skm_matrix* X) {
   return fail(SKM_ERR_INVALID_ARG, "unknown matrix format %d", (int)X->fmt);
 }
 
+// The row kernels address the centre-minor copy with 32-bit element offsets
+// (column * kp + centre), which keeps their address arithmetic to one
+// multiply-add per gather.
+int check_ct_size(int64_t d, int32_t kp) {
+  if ((uint64_t)d * (uint64_t)kp > (uint64_t)UINT32_MAX)
+    return fail(SKM_ERR_UNSUPPORTED, "d * k_padded = %lld * %d exceeds 2^32 - 1 (the row kernels "
+                "use 32-bit offsets into the centre copy)", (long long)d, (int)kp);
+  return SKM_OK;
+}
+
+// validate = 2: the layout of the input rows (Section 2: sparse vectors as
+// ascending (index, value) pairs) and finite values, checked before any
+// kernel walks the rows.  row_ptr is checked first, by flat index; only
+// when it is valid are the rows it delimits scanned.  `bad` is one device
+// word of scratch.  Returns SKM_ERR_INVALID_ARG naming the first bad row.
+int validate_input(const skm_matrix* X, unsigned long long* bad, hipStream_t s) {
+  unsigned long long h = ~0ull;
+  auto run = [&](int stage) -> hipError_t {
+    hipError_t e = hipMemsetAsync(bad, 0xff, sizeof(unsigned long long), s);
+    if (e != hipSuccess) return e;
+    if (X->fmt == SKM_DENSE_F32) e = launch_check_dense(X->dense, X->ld, X->n, X->d, bad, s);
+    else if (stage == 0) e = launch_check_rowptr(X->row_ptr, X->n, X->nnz, bad, s);
+    else e = launch_check_entries(X->row_ptr, X->col_idx, X->val, X->n, X->d, bad, s);
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(&h, bad, sizeof(h), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(s);
+  };
+  for (int stage = (X->fmt == SKM_DENSE_F32 ? 1 : 0); stage < 2; ++stage) {
+    const hipError_t e = run(stage);
+    if (e != hipSuccess) return fail(SKM_ERR_HIP, "input check: %s", hipGetErrorString(e));
+    if (h == ~0ull) continue;
+    const long long row = (long long)(h >> 3);
+    switch ((int)(h & 7ull)) {
+      case kBadRowPtr:
+        return fail(SKM_ERR_INVALID_ARG, "row_ptr invalid at index %lld (need row_ptr[0] = 0, "
+                    "non-decreasing, row_ptr[n] = nnz)", row);
+      case kBadColumn:
+        return fail(SKM_ERR_INVALID_ARG, "row %lld has a column id outside [0, d)", row);
+      case kBadOrder:
+        return fail(SKM_ERR_INVALID_ARG, "row %lld: column ids are not strictly ascending", row);
+      default:
+        return fail(SKM_ERR_INVALID_ARG, "row %lld holds a NaN or infinite value", row);
+    }
+  }
+  return SKM_OK;
+}
+
+// validate >= 1: every initial centre has unit norm within tol (norms as
+// computed by k_init_centres into `initnorm`).
+int check_init_norms(const double* initnorm, int32_t k, double tol, hipStream_t s) {
+  std::vector<double> hn((size_t)k);
+  hipError_t e = hipMemcpyAsync(hn.data(), initnorm, (size_t)k * sizeof(double),
+                                hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(SKM_ERR_HIP, "validation copy: %s", hipGetErrorString(e));
+  for (int j = 0; j < k; ++j)
+    if (!(std::fabs(hn[(size_t)j] - 1.0) <= tol))
+      return fail(SKM_ERR_NOT_NORMALIZED, "initial centre %d has norm %.9g", j, hn[(size_t)j]);
+  return SKM_OK;
+}
+
 int make_plan(const skm_matrix* X, int32_t k, int32_t variant, int32_t precision, Plan* P) {
   int rc = check_matrix(X);
   if (rc != SKM_OK) return rc;
@@ -106,6 +168,8 @@ int make_plan(const skm_matrix* X, int32_t k, int32_t variant, int32_t precision
     return fail(SKM_ERR_INVALID_ARG, "unknown variant %d", (int)variant);
   const Geometry g = pick_geometry(k);
   if (g.G == 0) return fail(SKM_ERR_UNSUPPORTED, "k = %d exceeds the supported 4096", (int)k);
+  rc = check_ct_size(X->d, g.kp);
+  if (rc != SKM_OK) return rc;
   P->n = X->n;
   P->d = X->d;
   P->nnz = X->nnz;
@@ -166,6 +230,7 @@ int make_plan(const skm_matrix* X, int32_t k, int32_t variant, int32_t precision
   P->rec = P->ctl + sizeof(StepCtl);
   P->maxeta = take(kCounterSlots * sizeof(float));
   P->initnorm = take(kk * sizeof(double));
+  P->vbad = take(sizeof(unsigned long long));
   P->total = cur;
   return SKM_OK;
 }
@@ -252,7 +317,8 @@ struct DensePlan {
          second = 0, thr = 0, near = 0, rflag = 0, rows = 0, nlist = 0, nrows = 0, nthr = 0,
          bcnt = 0, boff = 0, cand = 0, cand_n = 0, ccnt = 0, cstart = 0, ccur = 0, perm = 0,
          norm64 = 0, part = 0, part_sq = 0, pc = 0, ps = 0, dirty = 0, mm = 0, G = 0, gmax = 0,
-         gpart = 0, cnt = 0, per = 0, maxeta = 0, initnorm = 0, xr = 0, rcmax = 0, total = 0;
+         gpart = 0, cnt = 0, per = 0, maxeta = 0, initnorm = 0, xr = 0, rcmax = 0, vbad = 0,
+         total = 0;
 };
 
 int make_dense_plan(const skm_matrix* X, int32_t k, int32_t variant, int32_t precision,
@@ -335,6 +401,7 @@ int make_dense_plan(const skm_matrix* X, int32_t k, int32_t variant, int32_t pre
   P->per = P->cnt + kCounterSlots * sizeof(Counters);
   P->maxeta = take(kCounterSlots * 4);
   P->initnorm = take(kk * 8);
+  P->vbad = take(8);
   P->total = cur;
   return SKM_OK;
 }
@@ -507,6 +574,10 @@ int fit_dense(const skm_matrix* X, int32_t k, const float* init_centers, int32_t
   int32_t off_until = 0, off_gap = 2;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   {
+    if (o.validate >= 2) {
+      rc = validate_input(X, R.ptr<unsigned long long>(P.vbad), s);
+      if (rc != SKM_OK) goto done;
+    }
     if (o.profile) {
       SKM_HIP(hipEventCreate(&ev0));
       SKM_HIP(hipEventCreate(&ev1));
@@ -525,6 +596,8 @@ int fit_dense(const skm_matrix* X, int32_t k, const float* init_centers, int32_t
     SKM_HIP(launch_init_centres(init_centers, k, d, 1, C64, R.ptr<double>(P.initnorm), s));
     SKM_HIP(launch_pack_centres(C64, k, d, P.dp, nullptr, P.bf16, Cp, rcmax, s));
     if (o.validate >= 1) {
+      rc = check_init_norms(R.ptr<double>(P.initnorm), k, o.norm_tol, s);
+      if (rc != SKM_OK) goto done;
       float hslots[kCounterSlots];
       float hmax = 0.f;
       SKM_HIP(hipMemcpyAsync(hslots, R.ptr<float>(P.maxeta), sizeof(hslots),
@@ -799,6 +872,7 @@ size_t skm_assign_workspace_size(const skm_matrix* X, int32_t k) {
     fail(SKM_ERR_UNSUPPORTED, "k = %d exceeds the supported 4096", (int)k);
     return 0;
   }
+  if (check_ct_size(X->d, g.kp) != SKM_OK) return 0;
   return align256((size_t)X->d * g.kp * sizeof(float)) +
          align256((size_t)k * X->d * sizeof(double));
 }
@@ -816,6 +890,8 @@ int skm_assign(const skm_matrix* X, int32_t k, const float* centers, int32_t* as
                         workspace_bytes, static_cast<hipStream_t>(stream));
   const Geometry g = pick_geometry(k);
   if (g.G == 0) return fail(SKM_ERR_UNSUPPORTED, "k = %d exceeds the supported 4096", (int)k);
+  rc = check_ct_size(X->d, g.kp);
+  if (rc != SKM_OK) return rc;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const size_t need = skm_assign_workspace_size(X, k);
   bool owned = false;
@@ -971,6 +1047,10 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
       }
       return hipSuccess;
     };
+    if (o.validate >= 2) {
+      rc = validate_input(X, at<unsigned long long>(ws, P.vbad), s);
+      if (rc != SKM_OK) goto done;
+    }
     if (prof)
       for (int c = 0; c < kStepChunk; ++c) {
         SKM_HIP(hipEventCreate(&ev0[c]));
@@ -992,35 +1072,13 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
     }
     SKM_HIP(launch_transpose(C64, k, d, P.kp, nullptr, CT, s, CT16));
     if (o.validate >= 1) {
-      double* hn = new (std::nothrow) double[k];
+      rc = check_init_norms(initnorm, k, o.norm_tol, s);
+      if (rc != SKM_OK) goto done;
       float hslots[kCounterSlots];
       float hmax = 0.f;
-      if (!hn) {
-        rc = fail(SKM_ERR_OUT_OF_MEMORY, "host allocation failed");
-        goto done;
-      }
-      hipError_t e1 = hipMemcpyAsync(hn, initnorm, (size_t)k * sizeof(double),
-                                     hipMemcpyDeviceToHost, s);
-      hipError_t e2 = hipMemcpyAsync(hslots, maxeta, sizeof(hslots), hipMemcpyDeviceToHost, s);
-      hipError_t e3 = hipStreamSynchronize(s);
+      SKM_HIP(hipMemcpyAsync(hslots, maxeta, sizeof(hslots), hipMemcpyDeviceToHost, s));
+      SKM_HIP(hipStreamSynchronize(s));
       for (int q = 0; q < kCounterSlots; ++q) hmax = std::max(hmax, hslots[q]);
-      if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
-        delete[] hn;
-        rc = fail(SKM_ERR_HIP, "validation copy failed");
-        goto done;
-      }
-      int bad = -1;
-      for (int j = 0; j < k; ++j)
-        if (!(std::fabs(hn[j] - 1.0) <= o.norm_tol)) {
-          bad = j;
-          break;
-        }
-      const double badnorm = bad >= 0 ? hn[bad] : 0.0;
-      delete[] hn;
-      if (bad >= 0) {
-        rc = fail(SKM_ERR_NOT_NORMALIZED, "initial centre %d has norm %.9g", bad, badnorm);
-        goto done;
-      }
       if (o.validate >= 2 && !((double)hmax <= o.norm_tol)) {
         rc = fail(SKM_ERR_NOT_NORMALIZED, "a data row deviates from unit norm by %.3g", hmax);
         goto done;

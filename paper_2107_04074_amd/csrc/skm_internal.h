@@ -287,6 +287,19 @@ hipError_t launch_transpose(const double* C64, int32_t k, int64_t d, int32_t kp,
 // Sets *flag (not cleared here) if any of v[0..nnz) or init[0..ninit) is negative.
 hipError_t launch_neg_scan(const float* v, int64_t nnz, const float* init, int64_t ninit,
                            int32_t* flag, hipStream_t s);
+// Input checks (validate = 2).  Each records the first violation as
+// row * 8 + kind in *bad (atomic minimum; the caller fills it with ~0 first).
+constexpr int kBadRowPtr = 1;   // row_ptr[0] != 0, decreasing, or row_ptr[n] != nnz
+constexpr int kBadColumn = 2;   // column id outside [0, d)
+constexpr int kBadOrder = 3;    // column ids not strictly ascending within the row
+constexpr int kBadValue = 4;    // NaN or infinite value
+hipError_t launch_check_rowptr(const int64_t* rp, int64_t n, int64_t nnz,
+                               unsigned long long* bad, hipStream_t s);
+// Only after launch_check_rowptr found row_ptr valid.
+hipError_t launch_check_entries(const int64_t* rp, const int32_t* ci, const float* v, int64_t n,
+                                int64_t d, unsigned long long* bad, hipStream_t s);
+hipError_t launch_check_dense(const float* x, int64_t ld, int64_t n, int64_t d,
+                              unsigned long long* bad, hipStream_t s);
 hipError_t launch_update_scan(const int64_t* rp, const int32_t* ci, const float* v,
                               const int32_t* a, int32_t* a_old, int64_t n, int64_t d,
                               double fx_scale, long long* S, int32_t* dirty, hipStream_t s);

@@ -200,3 +200,23 @@ def test_product_path_refuses_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(skm, "_lib", None)
     with pytest.raises(RuntimeError):
         skm.load(str(tmp_path / "missing.so"))
+
+
+def test_centre_copy_offsets_fit_32_bits(lib):
+    """The row kernels address the centre-minor copy with 32-bit element
+    offsets (column * k_padded + centre): shapes with d * k_padded >= 2^32 are
+    refused on the host (SKM_ERR_UNSUPPORTED), never launched."""
+    o = skm.SkmOptions()
+    ok = _fake_csr(n=5000, d=(1 << 20) - 1)
+    assert lib.skm_workspace_size(ctypes.byref(ok), 4096, skm.LLOYD, ctypes.byref(o)) > 0
+    for d, k in (((1 << 20), 4096), ((1 << 21), 2048), ((1 << 22), 1000)):
+        m = _fake_csr(n=5000, d=d)
+        assert lib.skm_workspace_size(ctypes.byref(m), k, skm.LLOYD, ctypes.byref(o)) == 0
+        assert b"2^32" in lib.skm_last_error()
+        assert lib.skm_assign_workspace_size(ctypes.byref(m), k) == 0
+        st = skm.SkmStats()
+        rc = lib.skm_fit(ctypes.byref(m), k, 0x5000, skm.HAMERLY, 5, None, None, 0, 0x4000,
+                         None, None, ctypes.byref(st), None)
+        assert rc == skm.ERR_UNSUPPORTED
+        rc = lib.skm_assign(ctypes.byref(m), k, 0x5000, 0x4000, None, None, None, 0, None)
+        assert rc == skm.ERR_UNSUPPORTED

@@ -169,6 +169,53 @@ def test_assignment_is_exhaustive_argmax_with_tie_rule():
     assert np.array_equal(a2, prev)
 
 
+def test_transposed_assignment_identical_and_exhaustive():
+    """The transposed-centre assignment step (used for the full-size
+    trajectories) computes the same sequential sums: identical to the plain
+    step bit for bit, and the exhaustive argmax of numpy's dense product."""
+    X = datagen.sparse_tfidf(700, 2000, 30.0, 19)
+    rng = np.random.default_rng(8)
+    C = unit_rows(rng, 37, X.d)
+    C[11] = C[4]
+    a, s1, s2 = oracle.assign(X, C)
+    at, s1t, s2t = oracle.assign(X, C, transposed=True)
+    assert np.array_equal(a, at) and np.array_equal(s1, s1t) and np.array_equal(s2, s2t)
+    S = X.to_dense().astype(np.float64) @ C.T
+    srt = np.sort(S, axis=1)
+    clear = (srt[:, -1] - srt[:, -2]) > 1e-12
+    assert np.array_equal(at[clear], numpy_argmax_rule(S)[clear])
+    assert np.all(at != 11)
+    prev = np.where(at == 4, 11, at).astype(np.int32)
+    a2, _, _ = oracle.assign(X, C, prev, transposed=True)
+    assert np.array_equal(a2, prev)
+
+
+@pytest.mark.parametrize("which", ["c1", "c2"])
+def test_lloyd_trajectory_equals_fit(which):
+    """The step-by-step Lloyd driver (checkpoints of the full-size
+    trajectories) reproduces the oracle's own Lloyd fit exactly: every
+    assignment, the centres, the changed counts and objectives."""
+    X, init, cfg = datagen.sparse_workload(which, n=None if which == "c1" else 3000)
+    C0 = datagen.init_centers_csr(X, init)
+    ref = oracle.fit(X, C0, "lloyd", 30, trace=True)
+    seen = []
+
+    def on_step(t, a, C, s1, s2, changed, obj):
+        assert np.array_equal(a, ref.a_trace[:, t - 1])
+        assert changed == ref.changed[t - 1]
+        assert np.all(s1 >= s2)
+        if obj is None:
+            assert np.isnan(ref.obj_update[t - 1])
+        else:
+            assert obj == ref.obj_update[t - 1]
+        seen.append(t)
+
+    a, C, it, conv = oracle.lloyd_trajectory(X, C0, 30, on_step)
+    assert it == ref.iterations and conv == ref.converged
+    assert seen == list(range(1, it + 1))
+    assert np.array_equal(a, ref.a) and np.array_equal(C, ref.C)
+
+
 def test_update_unit_centres_and_objective():
     X = datagen.sparse_tfidf(800, 3000, 30.0, 10)
     k = 9
@@ -358,7 +405,7 @@ def test_d2_arcs_by_hand():
     assert np.array_equal(a, np.argmin(diff, axis=1))
 
 
-# ---------------------------------------------- Section 6, spherical k-means++
+# ---------------------------------------------- Section 5.6, spherical k-means++
 
 def _circle(deg):
     """Unit vectors at the given angles; multiples of 90 degrees are exact."""
@@ -469,3 +516,48 @@ def test_afkmc2_long_chain_prefers_far_rows():
         ch = oracle.afkmc2(X, 2, 20, 1.0, u)
         hits += ch[1] >= 90
     assert hits >= 50  # the small cluster holds 10% of the rows
+
+
+# ------------------------------------------- dense FP64 oracle (numpy product)
+
+def test_dense_oracle_matches_csr_oracle():
+    """The numpy dense Lloyd used for the full-size dense trajectory equals
+    the CSR oracle on the same rows stored densely: identical trajectory,
+    centres and objectives to rounding (1e-13)."""
+    from oracle import dense as od
+    X = datagen.dense_vmf(3000, 40, 12, 321)
+    init = datagen.init_rows(X.shape[0], 12, 321)
+    C0 = X[init].copy()
+    ref = oracle.fit(dense_csr(X), C0, "lloyd", 40, trace=True)
+    got = []
+
+    def on_step(t, a, C, s1, s2, changed, obj):
+        assert np.array_equal(a, ref.a_trace[:, t - 1])
+        assert changed == ref.changed[t - 1]
+        if obj is not None:
+            assert abs(obj - ref.obj_update[t - 1]) < 1e-12 * obj
+        got.append(t)
+
+    a, C, it, conv = od.lloyd_trajectory(X, C0, 40, on_step)
+    assert it == ref.iterations and conv == ref.converged and len(got) == it
+    assert np.abs(C - ref.C).max() < 1e-13
+
+
+def test_dense_oracle_assign_rules():
+    """Tie rule and second best on a hand-made case: duplicate centres, a
+    previous assignment that attains the maximum, k = 1."""
+    from oracle import dense as od
+    X = np.array([[1, 0, 0], [0, 1, 0], [0.6, 0.8, 0]], np.float32)
+    C = np.array([[0, 1, 0], [1, 0, 0], [0, 1, 0]], np.float64)
+    a, s1, s2 = od.assign(X, C)
+    assert list(a) == [1, 0, 0]  # row 1 ties centres 0 and 2: lowest index
+    assert np.allclose(s1, [1, 1, 0.8]) and np.allclose(s2, [0, 1, 0.8])
+    a2, _, _ = od.assign(X, C, np.array([1, 2, 2], np.int32))
+    assert list(a2) == [1, 2, 2]  # previous centre kept where it attains the max
+    a1, s1, s2 = od.assign(X, C[:1])
+    assert list(a1) == [0, 0, 0] and np.all(np.isneginf(s2))
+    Cn, norms, obj = od.update(X, np.array([1, 0, 0], np.int32), np.eye(3)[:3])
+    s0 = X[1].astype(np.float64) + X[2].astype(np.float64)  # float32 rows, exact sum
+    assert np.allclose(Cn[0], s0 / np.linalg.norm(s0), rtol=0, atol=1e-15)
+    assert np.array_equal(Cn[2], np.eye(3)[2])  # empty cluster keeps its centre
+    assert abs(obj - (np.linalg.norm(s0) + 1.0)) < 1e-15
