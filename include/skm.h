@@ -212,6 +212,29 @@ int skm_assign(const skm_matrix* X, int32_t k, const float* centers,
                int32_t* assign_out, float* best_sim_out, float* second_sim_out,
                void* workspace, size_t workspace_bytes, void* stream);
 
+/* skm_assign for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * The same assignment step as skm_assign on CSR input (same kernels, same
+ * results), but the centre copies live in a buffer the library owns: one
+ * static device array of SKM_NOALLOC_SCRATCH_BYTES per GPU, held from the
+ * library's load until the process ends.  The call allocates nothing, frees
+ * nothing and enqueues only kernels on `stream` (the buffer is cleared by a
+ * fill kernel, not hipMemset); the first call on a device looks the
+ * buffer's address up (hipGetSymbolAddress, host only).
+ *   Size limit: align256(d * k_padded * 4) + align256(k * d * 8) bytes (the
+ *   skm_assign_workspace_size of the same problem) must not exceed
+ *   SKM_NOALLOC_SCRATCH_BYTES, else SKM_ERR_UNSUPPORTED and nothing is
+ *   enqueued.  Dense input: SKM_ERR_UNSUPPORTED.
+ *   Sharing: every call on one GPU uses that GPU's buffer, which keeps the
+ *   last call's contents.  Calls that overlap on one GPU (several streams or
+ *   host threads) race and give undefined results; order them on one
+ *   stream.
+ * Arguments and outputs as in skm_assign.  Asynchronous. */
+#define SKM_NOALLOC_SCRATCH_BYTES (64u << 20)
+int skm_assign_noalloc(const skm_matrix* X, int32_t k, const float* centers,
+                       int32_t* assign_out, float* best_sim_out, float* second_sim_out,
+                       void* stream);
+
 /* Bytes of workspace skm_seed_kmeanspp needs. */
 size_t skm_seed_workspace_size(const skm_matrix* X, int32_t k);
 

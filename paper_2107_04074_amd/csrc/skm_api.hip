@@ -19,6 +19,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <mutex>
 #include <new>
 #include <string>
 #include <thread>
@@ -26,6 +27,12 @@
 
 #include "../../include/skm.h"
 #include "skm_internal.h"
+
+// Device buffer of skm_assign_noalloc: every GPU that loads this library
+// holds one copy until the process ends.  Host code never passes `scratch`
+// itself to a kernel or a copy (on the host it only names the symbol): its
+// address on a device comes from hipGetSymbolAddress (scratch_address).
+static __device__ __align__(256) unsigned char scratch[SKM_NOALLOC_SCRATCH_BYTES];
 
 namespace skm {
 namespace {
@@ -821,6 +828,74 @@ done:
   return rc;
 }
 
+// Device address of `scratch` on the device of `stream` (the current device
+// for the null stream), looked up once per device with that device current
+// and kept for later calls.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+
+int scratch_address(hipStream_t stream, void** out) {
+  int cur = 0, dev = 0;
+  hipError_t e = hipGetDevice(&cur);
+  if (e == hipSuccess) {
+    dev = cur;
+    if (stream) e = hipStreamGetDevice(stream, &dev);
+  }
+  if (e != hipSuccess) return fail(SKM_ERR_HIP, "device of the stream: %s", hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(SKM_ERR_UNSUPPORTED, "device %d beyond the %d this library tracks", dev,
+                kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    if (dev != cur && (e = hipSetDevice(dev)) != hipSuccess)
+      return fail(SKM_ERR_HIP, "hipSetDevice(%d): %s", dev, hipGetErrorString(e));
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (dev != cur) (void)hipSetDevice(cur);
+    if (e != hipSuccess || !p)
+      return fail(SKM_ERR_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                  hipGetErrorString(e));
+    g_scratch_addr[dev] = p;
+  }
+  *out = g_scratch_addr[dev];
+  return SKM_OK;
+}
+
+// Assignment step of CSR rows against fixed centres, in the workspace `ws`
+// (centre-minor FP32 copy, then the FP64 centres).  Only kernels are
+// enqueued (the copy is cleared by a fill kernel), so the same path serves
+// callers that capture the stream into a graph.
+int assign_csr(const skm_matrix* X, int32_t k, int32_t kp, const float* centers,
+               int32_t* assign_out, float* best_sim_out, float* second_sim_out, void* ws,
+               hipStream_t s) {
+  int rc = SKM_OK;
+  float* CT = at<float>(ws, 0);
+  double* C64 = at<double>(ws, align256((size_t)X->d * kp * sizeof(float)));
+  {
+    SKM_HIP(launch_fill_i32(reinterpret_cast<int32_t*>(CT), X->d * (int64_t)kp, 0, s));
+    SKM_HIP(launch_init_centres(centers, k, X->d, 0, C64, nullptr, s));
+    SKM_HIP(launch_transpose(C64, k, X->d, kp, nullptr, CT, s));
+    AssignArgs A{};
+    A.rp = X->row_ptr;
+    A.ci = X->col_idx;
+    A.v = X->val;
+    A.CT = CT;
+    A.C64 = C64;
+    A.d = X->d;
+    A.k = k;
+    A.kp = kp;
+    A.n_rows = X->n;
+    A.a = assign_out;
+    A.read_prev = 0;
+    A.best_out = best_sim_out;
+    A.second_out = second_sim_out;
+    SKM_HIP(launch_assign(A, kModeAssign, s));
+  }
+done:
+  return rc;
+}
+
 }  // namespace
 }  // namespace skm
 
@@ -904,31 +979,35 @@ int skm_assign(const skm_matrix* X, int32_t k, const float* centers, int32_t* as
     return fail(SKM_ERR_OUT_OF_MEMORY, "workspace has %zu bytes, %zu needed", workspace_bytes,
                 need);
   }
-  float* CT = at<float>(ws, 0);
-  double* C64 = at<double>(ws, align256((size_t)X->d * g.kp * sizeof(float)));
-  {
-    SKM_HIP(hipMemsetAsync(CT, 0, (size_t)X->d * g.kp * sizeof(float), s));
-    SKM_HIP(launch_init_centres(centers, k, X->d, 0, C64, nullptr, s));
-    SKM_HIP(launch_transpose(C64, k, X->d, g.kp, nullptr, CT, s));
-    AssignArgs A{};
-    A.rp = X->row_ptr;
-    A.ci = X->col_idx;
-    A.v = X->val;
-    A.CT = CT;
-    A.C64 = C64;
-    A.d = X->d;
-    A.k = k;
-    A.kp = g.kp;
-    A.n_rows = X->n;
-    A.a = assign_out;
-    A.read_prev = 0;
-    A.best_out = best_sim_out;
-    A.second_out = second_sim_out;
-    SKM_HIP(launch_assign(A, kModeAssign, s));
-  }
-done:
+  rc = assign_csr(X, k, g.kp, centers, assign_out, best_sim_out, second_sim_out, ws, s);
   if (owned) (void)hipFreeAsync(ws, s);
   return rc;
+}
+
+int skm_assign_noalloc(const skm_matrix* X, int32_t k, const float* centers,
+                       int32_t* assign_out, float* best_sim_out, float* second_sim_out,
+                       void* stream) {
+  g_last_error.clear();
+  int rc = check_matrix(X);
+  if (rc != SKM_OK) return rc;
+  if (X->fmt != SKM_CSR_F32)
+    return fail(SKM_ERR_UNSUPPORTED, "skm_assign_noalloc takes CSR input");
+  if (k < 1) return fail(SKM_ERR_INVALID_ARG, "need k >= 1");
+  if (!centers || !assign_out) return fail(SKM_ERR_INVALID_ARG, "centers/assign_out NULL");
+  const Geometry g = pick_geometry(k);
+  if (g.G == 0) return fail(SKM_ERR_UNSUPPORTED, "k = %d exceeds the supported 4096", (int)k);
+  rc = check_ct_size(X->d, g.kp);
+  if (rc != SKM_OK) return rc;
+  const size_t need = skm_assign_workspace_size(X, k);
+  if (need > (size_t)SKM_NOALLOC_SCRATCH_BYTES)
+    return fail(SKM_ERR_UNSUPPORTED, "d = %lld, k = %d need %zu bytes of centre copies; the "
+                "no-allocation buffer holds %zu", (long long)X->d, (int)k, need,
+                (size_t)SKM_NOALLOC_SCRATCH_BYTES);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  void* ws = nullptr;
+  rc = scratch_address(s, &ws);
+  if (rc != SKM_OK) return rc;
+  return assign_csr(X, k, g.kp, centers, assign_out, best_sim_out, second_sim_out, ws, s);
 }
 
 int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t variant,

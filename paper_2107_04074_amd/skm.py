@@ -25,6 +25,7 @@ OK, ERR_INVALID_ARG, ERR_NOT_NORMALIZED, ERR_OUT_OF_MEMORY, ERR_HIP, ERR_UNSUPPO
 
 # Every symbol include/skm.h declares.
 EXPORTS = ("skm_workspace_size", "skm_assign_workspace_size", "skm_fit", "skm_assign",
+           "skm_assign_noalloc",
            "skm_seed_workspace_size", "skm_seed_kmeanspp",
            "skm_seed_afkmc2_workspace_size", "skm_seed_afkmc2",
            "skm_fit_batched_workspace_size", "skm_fit_batched",
@@ -87,6 +88,8 @@ def load(path: str = LIB_PATH):
                             ctypes.POINTER(SkmStats), p]
     lib.skm_assign.restype = ctypes.c_int
     lib.skm_assign.argtypes = [ctypes.POINTER(SkmMatrix), i32, p, p, p, p, p, sz, p]
+    lib.skm_assign_noalloc.restype = ctypes.c_int
+    lib.skm_assign_noalloc.argtypes = [ctypes.POINTER(SkmMatrix), i32, p, p, p, p, p]
     lib.skm_fit_batched_workspace_size.restype = sz
     lib.skm_fit_batched_workspace_size.argtypes = [i32, ctypes.POINTER(SkmMatrix), p, i32,
                                                    ctypes.POINTER(SkmOptions), i32]
@@ -338,6 +341,27 @@ def assign(X: DeviceCSR, centers, workspace=None, want_second=True):
     c = centers.contiguous()
     _check(lib.skm_assign(ctypes.byref(m), k, _ptr(c), _ptr(a), _ptr(best), _ptr(second),
                           _ptr(workspace), workspace.numel(), _stream()))
+    return a, best, second
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def assign_noalloc(X: DeviceCSR, centers, a=None, best=None, second=None):
+    """Runs skm_assign_noalloc (CSR rows, library-owned scratch, no device
+    allocation inside the call) into the given output tensors (allocated here
+    when None).  Returns (assign, best, second); asynchronous on the current
+    stream."""
+    import torch
+    lib = load()
+    dev = X.col.device
+    k = int(centers.shape[0])
+    m = X.matrix()
+    a = torch.empty(X.n, dtype=torch.int32, device=dev) if a is None else a
+    best = torch.empty(X.n, dtype=torch.float32, device=dev) if best is None else best
+    c = centers.contiguous()
+    _check(lib.skm_assign_noalloc(ctypes.byref(m), k, _ptr(c), _ptr(a), _ptr(best),
+                                  _ptr(second), _stream()))
     return a, best, second
 
 
