@@ -36,9 +36,10 @@
  *                 float[nnz].  Column ids strictly ascending within a row
  *                 is the expected layout (the paper stores sparse vectors as
  *                 sorted (index, value) pairs, Section 2); options.validate
- *                 = 2 checks all of this.  d * k (k padded to the row
- *                 kernels' width: 16, 32, 64, 128, 256, then multiples of
- *                 256) must stay below 2^32 (else SKM_ERR_UNSUPPORTED).
+ *                 = 2 checks all of this.  d * k_padded (k rounded up
+ *                 to a power of two, at least 16: the width of the centre
+ *                 copy the row kernels read) must stay below 2^32 (else
+ *                 SKM_ERR_UNSUPPORTED).
  *  SKM_DENSE_F32: dense float[n * ld], row-major, ld >= d.
  *  Rows must have unit L2 norm (Section 5: samples are normalised during
  *  initialisation).  Float rounding of the norm is tolerated: internal
