@@ -139,7 +139,9 @@ typedef struct {            /* [host]; an all-zero struct means defaults      */
                                row and refreshes every bound exactly; 1: they
                                run at every step, as in the paper.  Results
                                are the same either way; only work differs.  */
-  int32_t reserved1;
+  int32_t batch_tile_rows;  /* skm_fit_batched in lockstep (workers = 0): rows
+                               per work item of the batched row walk; 0 takes
+                               the measured table compiled into the library */
 } skm_options;
 
 typedef struct {            /* [host] filled by skm_fit                       */
@@ -290,27 +292,37 @@ int skm_seed_afkmc2(const skm_matrix* X, int32_t k, int32_t chain, double alpha,
                     void* workspace, size_t workspace_bytes, void* stream);
 
 /* Many independent problems in one call (the batched setting: hundreds of
- * small clustering problems, each solved as in skm_fit).  The library runs
- * `workers` host threads, each with its own HIP stream on the caller's
- * current device and its own slice of the workspace; problems are dealt to
- * the first free worker, most expensive first (stored entries x k), so their
- * per-step launches and synchronisations overlap on the GPU.  Results are
- * identical to calling skm_fit on each problem.
+ * small clustering problems, each solved as in skm_fit; results and
+ * statistics are identical to calling skm_fit on each problem).
+ *   workers = 0, CSR input, SKM_LLOYD / SKM_HAMERLY / SKM_SIMP_HAMERLY, FP32
+ *     similarities, no validate / profile / warm start: lockstep.  All
+ *     problems advance one assignment step at a time on `stream`; every
+ *     kernel of a step serves all problems (work items name the problem):
+ *     the row walk is one persistent launch per centre-copy width that takes
+ *     (problem, row tile) items from a device queue, with tile sizes from a
+ *     table measured on this GPU (options.batch_tile_rows overrides it), and
+ *     the centre step is one launch per kernel.  Steps after the first are
+ *     queued eight at a time as one captured HIP graph, replayed until every
+ *     problem has stopped.
+ *   otherwise (or workers >= 1): `workers` host threads (0: min(nprob, 4)),
+ *     each with its own HIP stream on the caller's current device and its
+ *     own slice of the workspace, run skm_fit on the problems, most
+ *     expensive (stored entries x k) first.
  *   nprob            >= 1 problems.
  *   Xs, ks           [host] arrays of nprob matrices and centre counts.
  *   inits            [host] array of nprob device pointers (float[k_b*d_b]).
  *   variant, opt     as in skm_fit, shared by all problems (opt nullable).
  *   max_iters        [host] int32[nprob], each >= 1.
- *   workers          concurrent streams; 0 picks min(nprob, 4) (the GPU
- *                    runs four hardware queues per process by default).
- *   workspace        >= skm_fit_batched_workspace_size() bytes or NULL.
+ *   workspace        >= skm_fit_batched_workspace_size() bytes (same
+ *                    arguments) or NULL.
  *   assign_outs      [host] array of nprob device pointers (int32[n_b]).
  *   centers_outs     [host] array (nullable; entries nullable) of float[k_b*d_b].
- *   stats            [host] skm_stats[nprob] (nullable), as in skm_fit.
- * Ordering: the workers start after the work already enqueued on `stream`
- * and the call returns after every problem finished.  On error the first
- * failing problem (lowest index) is reported and problems not yet started
- * are skipped. */
+ *   stats            [host] skm_stats[nprob] (nullable), as in skm_fit
+ *                    (sim_kernel_ms stays 0 in lockstep).
+ * Ordering: work starts after what is already enqueued on `stream`; the
+ * call returns after every problem finished.  On error the first failing
+ * problem (lowest index) is reported and problems not yet started are
+ * skipped. */
 size_t skm_fit_batched_workspace_size(int32_t nprob, const skm_matrix* Xs,
                                       const int32_t* ks, int32_t variant,
                                       const skm_options* opt, int32_t workers);

@@ -594,12 +594,13 @@ constexpr int assign_min_waves() {
   return (WAVE_ROW && R == 1) ? 3 : 1;
 }
 
+// Rows row_base + (row group of this thread), then every rstride rows, below
+// row_end; per-step counts go to counter slot `slot`.
 template <int G, int R, int VEC, int MODE, bool WAVE_ROW>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
-    assign_min_waves<R, WAVE_ROW>()))) void k_assign_csr(AssignArgs A) {
+__device__ __forceinline__ void assign_rows(const AssignArgs& A, int64_t row_base,
+                                            int64_t row_end, int64_t rstride, int slot) {
   static_assert(VEC == 4 || (VEC == 8 && WAVE_ROW), "FP16 centres need the wave layout");
   constexpr int NACC = R * VEC / 4;
-  constexpr int GPB = WAVE_ROW ? kBlock / 64 : kBlock / G;
   const int gl = threadIdx.x & (G - 1);
   const int gib = WAVE_ROW ? (int)(threadIdx.x >> 6) : (int)(threadIdx.x / G);
   // the lane that writes per-row results and counts (one row per wave: every
@@ -626,7 +627,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
   // one row per wave: the bounds and the first 64 entries of the wave's next
   // row are loaded while the current row is processed, so a row's walk
   // starts without waiting for them
-  const int64_t rstride = (int64_t)gridDim.x * GPB;
   const int wl = threadIdx.x & 63;
   constexpr bool kBounded = MODE == kModeHamerly || MODE == kModeYinYang || MODE == kModeElkan;
   // row pointers of the next row as loaded (made wave-uniform only when
@@ -659,8 +659,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
   };
   RowIn nin{-1, 0.f, 0.f, 0.f};
   if constexpr (WAVE_ROW) {
-    const int64_t r0 = (int64_t)blockIdx.x * GPB + gib;
-    if (r0 < A.n_rows) {
+    const int64_t r0 = row_base + gib;
+    if (r0 < row_end) {
       nbr = A.rp[r0];
       ner = A.rp[r0 + 1];
       nin = load_in(r0);
@@ -668,7 +668,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
     }
   }
 
-  for (int64_t row = (int64_t)blockIdx.x * GPB + gib; row < A.n_rows; row += rstride) {
+  for (int64_t row = row_base + gib; row < row_end; row += rstride) {
     int64_t beg, end;
     int c0 = 0;
     float x0 = 0.f;
@@ -680,7 +680,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
       x0 = wx;
       ri = nin;
       nbr = ner = 0;
-      if (row + rstride < A.n_rows) {
+      if (row + rstride < row_end) {
         nbr = A.rp[row + rstride];
         ner = A.rp[row + rstride + 1];
         nin = load_in(row + rstride);
@@ -867,7 +867,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
   if (my_sims) atomicAdd(&sh[6], my_sims);
   __syncthreads();
   if (threadIdx.x == 0) {
-    Counters* c = counter_slot(A.cnt);
+    Counters* c = A.cnt + slot;
     // similarities: those of the walked rows (all k, or the walked groups)
     // plus one per tightened row
     if (sh[6] + sh[4]) atomicAdd(&c->sims, sh[6] + sh[4]);
@@ -879,6 +879,43 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
     if (sh[3]) atomicAdd(&c->changed, sh[3]);
     if (sh[4]) atomicAdd(&c->tightened, sh[4]);
     if (sh[5]) atomicAdd(&c->tight_saved, sh[5]);
+  }
+}
+
+template <int G, int R, int VEC, int MODE, bool WAVE_ROW>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
+    assign_min_waves<R, WAVE_ROW>()))) void k_assign_csr(AssignArgs A) {
+  constexpr int GPB = WAVE_ROW ? kBlock / 64 : kBlock / G;
+  assign_rows<G, R, VEC, MODE, WAVE_ROW>(A, (int64_t)blockIdx.x * GPB, A.n_rows,
+                                         (int64_t)gridDim.x * GPB,
+                                         (int)(blockIdx.x % kCounterSlots));
+}
+
+// Batched fits: a persistent grid takes (problem, first row) items from the
+// atomic counter *queue and walks the item's tile of rows with the
+// problem's own arguments (the same body as k_assign_csr, so each problem's
+// rows get exactly its single-fit results).
+template <int G, int R, int VEC, int MODE, bool WAVE_ROW>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
+    assign_min_waves<R, WAVE_ROW>()))) void k_assign_batched(const AssignArgs* __restrict__ args,
+                                                             int arg_stride, int arg_off,
+                                                             const int2* __restrict__ items,
+                                                             int n_items, int tile_rows,
+                                                             unsigned int* __restrict__ queue) {
+  constexpr int GPB = WAVE_ROW ? kBlock / 64 : kBlock / G;
+  __shared__ int sh_item;
+  for (;;) {
+    if (threadIdx.x == 0) sh_item = (int)atomicAdd(queue, 1u);
+    __syncthreads();
+    const int it = sh_item;
+    __syncthreads();  // read by every thread before thread 0 takes the next item
+    if (it >= n_items) break;
+    const int2 w = items[it];
+    const int p = __builtin_amdgcn_readfirstlane(w.x);
+    const AssignArgs& A = args[(size_t)p * arg_stride + arg_off];
+    const int64_t r0 = w.y;
+    const int64_t r1 = (r0 + tile_rows < A.n_rows) ? r0 + tile_rows : A.n_rows;
+    assign_rows<G, R, VEC, MODE, WAVE_ROW>(A, r0, r1, GPB, it % kCounterSlots);
   }
 }
 
@@ -1000,6 +1037,50 @@ hipError_t launch_group_move(const double* pc, const double* ps, int32_t k, int3
   hipLaunchKernelGGL(k_group_move, dim3((unsigned)((ng + kBlock - 1) / kBlock)), dim3(kBlock), 0,
                      s, pc, ps, k, ng, gpc, gps);
   return hipGetLastError();
+}
+
+namespace {
+template <int MODE>
+hipError_t launch_assign_batched_mode(const AssignArgs* args, int arg_stride, int arg_off,
+                                      const int2* items, int n_items, int tile_rows, int kp,
+                                      unsigned int* queue, hipStream_t s) {
+  int blocks = n_items < kMaxGridBlocks ? n_items : kMaxGridBlocks;
+  if (blocks < 1) return hipSuccess;
+  const dim3 grid((unsigned)blocks), block(kBlock);
+#define SKM_BCASE(KP, GG, RR, WW)                                                          \
+  case KP:                                                                                  \
+    hipLaunchKernelGGL((k_assign_batched<GG, RR, 4, MODE, WW>), grid, block, 0, s, args,    \
+                       arg_stride, arg_off, items, n_items, tile_rows, queue);              \
+    break;
+  switch (kp) {
+    SKM_BCASE(16, 4, 1, false)
+    SKM_BCASE(32, 8, 1, false)
+    SKM_BCASE(64, 16, 1, false)
+    SKM_BCASE(128, 32, 1, true)
+    SKM_BCASE(256, 64, 1, true)
+    SKM_BCASE(512, 64, 2, true)
+    SKM_BCASE(1024, 64, 4, true)
+    SKM_BCASE(2048, 64, 8, true)
+    SKM_BCASE(4096, 64, 16, true)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef SKM_BCASE
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_assign_batched(const AssignArgs* args, int arg_stride, int arg_off,
+                                 const int2* items, int n_items, int tile_rows, int kp,
+                                 int mode, unsigned int* queue, hipStream_t s) {
+  if (mode == kModeFit)
+    return launch_assign_batched_mode<kModeFit>(args, arg_stride, arg_off, items, n_items,
+                                                tile_rows, kp, queue, s);
+  if (mode == kModeHamerly)
+    return launch_assign_batched_mode<kModeHamerly>(args, arg_stride, arg_off, items, n_items,
+                                                    tile_rows, kp, queue, s);
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_assign(const AssignArgs& A, int mode, hipStream_t s) {

@@ -47,11 +47,11 @@ __device__ __forceinline__ T block_sum(T x, T* sh) {
   return r;
 }
 
-__global__ __launch_bounds__(kBlock) void k_row_eta(const int64_t* __restrict__ rp,
-                                                    const float* __restrict__ v, int64_t n,
-                                                    float* __restrict__ eta,
-                                                    float* __restrict__ max_eta) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+__device__ __forceinline__ void row_eta_body(const int64_t* __restrict__ rp,
+                                             const float* __restrict__ v, int64_t n,
+                                             float* __restrict__ eta,
+                                             float* __restrict__ max_eta, int64_t bx) {
+  const int64_t i = bx * kBlock + threadIdx.x;
   float e32 = 0.f;
   if (i < n) {
     const int64_t beg = rp[i], end = rp[i + 1];
@@ -71,18 +71,23 @@ __global__ __launch_bounds__(kBlock) void k_row_eta(const int64_t* __restrict__ 
     if (threadIdx.x == 0) {
       float m = 0.f;
       for (int w = 0; w < kBlock / 64; ++w) m = fmaxf(m, wmax[w]);
-      if (m > 0.f) atomicMax(reinterpret_cast<int*>(max_eta) + (blockIdx.x % kCounterSlots),
+      if (m > 0.f) atomicMax(reinterpret_cast<int*>(max_eta) + (int)(bx % kCounterSlots),
                              __float_as_int(m));
     }
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_init_centres(const float* __restrict__ init,
-                                                         int64_t d, int normalize,
-                                                         double* __restrict__ C64,
-                                                         double* __restrict__ init_norm) {
+__global__ __launch_bounds__(kBlock) void k_row_eta(const int64_t* __restrict__ rp,
+                                                    const float* __restrict__ v, int64_t n,
+                                                    float* __restrict__ eta,
+                                                    float* __restrict__ max_eta) {
+  row_eta_body(rp, v, n, eta, max_eta, blockIdx.x);
+}
+
+__device__ __forceinline__ void init_centres_body(const float* __restrict__ init, int64_t d,
+                                                  int normalize, double* __restrict__ C64,
+                                                  double* __restrict__ init_norm, int j) {
   __shared__ double sh[kBlock];
-  const int j = blockIdx.x;
   const float* x = init + (size_t)j * d;
   double ss = 0.0;
   for (int64_t t = threadIdx.x; t < d; t += kBlock) ss = fma((double)x[t], (double)x[t], ss);
@@ -93,17 +98,24 @@ __global__ __launch_bounds__(kBlock) void k_init_centres(const float* __restrict
   for (int64_t t = threadIdx.x; t < d; t += kBlock) c[t] = scale ? (double)x[t] / nrm : (double)x[t];
 }
 
+__global__ __launch_bounds__(kBlock) void k_init_centres(const float* __restrict__ init,
+                                                         int64_t d, int normalize,
+                                                         double* __restrict__ C64,
+                                                         double* __restrict__ init_norm) {
+  init_centres_body(init, d, normalize, C64, init_norm, blockIdx.x);
+}
+
 // 64 x 64 tile transpose with float conversion.  Tiles whose 64 centres are
 // all clean are skipped (their FP32 copy is already current).
-__global__ __launch_bounds__(kBlock) void k_transpose(const double* __restrict__ C64, int32_t k,
-                                                      int64_t d, int32_t kp,
-                                                      const int32_t* __restrict__ dirty,
-                                                      float* __restrict__ CT,
-                                                      __half* __restrict__ CT16) {
+__device__ __forceinline__ void transpose_body(const double* __restrict__ C64, int32_t k,
+                                               int64_t d, int32_t kp,
+                                               const int32_t* __restrict__ dirty,
+                                               float* __restrict__ CT, __half* __restrict__ CT16,
+                                               int64_t bx, int by) {
   __shared__ float tile[64][65];
   __shared__ int any;
-  const int64_t t0 = (int64_t)blockIdx.x * 64;
-  const int j0 = blockIdx.y * 64;
+  const int64_t t0 = bx * 64;
+  const int j0 = by * 64;
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 64 x 4
   if (threadIdx.x == 0) any = 0;
   __syncthreads();
@@ -126,6 +138,14 @@ __global__ __launch_bounds__(kBlock) void k_transpose(const double* __restrict__
       if (CT16) CT16[(size_t)t * kp + j] = __float2half(tile[tx][tt]);
     }
   }
+}
+
+__global__ __launch_bounds__(kBlock) void k_transpose(const double* __restrict__ C64, int32_t k,
+                                                      int64_t d, int32_t kp,
+                                                      const int32_t* __restrict__ dirty,
+                                                      float* __restrict__ CT,
+                                                      __half* __restrict__ CT16) {
+  transpose_body(C64, k, d, kp, dirty, CT, CT16, blockIdx.x, blockIdx.y);
 }
 
 // Sets *flag when a stored value or an initial-centre value is negative
@@ -195,14 +215,17 @@ __global__ void k_check_dense(const float* __restrict__ x, int64_t ld, int64_t n
 // finding its entry's row by a binary search over the prefix; a batch of
 // entries is loaded before its atomics, so no lane waits for one row at a
 // time.  Fixed-point sums make the order of the atomics irrelevant.
-__global__ __launch_bounds__(kBlock) void k_update_scan(
+// Rows [row0, row_end) of one block, in steps of `stride` rows.
+__device__ __forceinline__ void update_scan_body(
     const int64_t* __restrict__ rp, const int32_t* __restrict__ ci, const float* __restrict__ v,
-    const int32_t* __restrict__ a, int32_t* __restrict__ a_old, int64_t n, int64_t d,
-    double fx, long long* __restrict__ S, int32_t* __restrict__ dirty) {
+    const int32_t* __restrict__ a, int32_t* __restrict__ a_old, int64_t row0, int64_t row_end,
+    int64_t stride, int64_t d, double fx, long long* __restrict__ S,
+    int32_t* __restrict__ dirty) {
   constexpr int kB = 4;  // entries per lane loaded before their atomics
   const int lane = threadIdx.x & 63;
-  const int64_t wave0 = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63);
-  for (int64_t base = wave0; base < n; base += (int64_t)gridDim.x * kBlock) {
+  const int64_t n = row_end;
+  const int64_t wave0 = row0 + (threadIdx.x & ~63);
+  for (int64_t base = wave0; base < n; base += stride) {
     const int64_t i = base + lane;
     int32_t nw = -1, old = -1;
     if (i < n) {
@@ -266,17 +289,23 @@ __global__ __launch_bounds__(kBlock) void k_update_scan(
   }
 }
 
+__global__ __launch_bounds__(kBlock) void k_update_scan(
+    const int64_t* __restrict__ rp, const int32_t* __restrict__ ci, const float* __restrict__ v,
+    const int32_t* __restrict__ a, int32_t* __restrict__ a_old, int64_t n, int64_t d,
+    double fx, long long* __restrict__ S, int32_t* __restrict__ dirty) {
+  update_scan_body(rp, ci, v, a, a_old, (int64_t)blockIdx.x * kBlock, n,
+                   (int64_t)gridDim.x * kBlock, d, fx, S, dirty);
+}
+
 constexpr int kMoveChunk = 4096;
 
 // Partial sums of squares of S(j) over column chunks (dirty clusters only).
-__global__ __launch_bounds__(kBlock) void k_sumsq_partial(const long long* __restrict__ S,
-                                                          int64_t d, double fx_inv,
-                                                          const int32_t* __restrict__ dirty,
-                                                          double* __restrict__ part_sq,
-                                                          int nchunk) {
+__device__ __forceinline__ void sumsq_partial_body(const long long* __restrict__ S, int64_t d,
+                                                   double fx_inv,
+                                                   const int32_t* __restrict__ dirty,
+                                                   double* __restrict__ part_sq, int nchunk,
+                                                   int ch, int j) {
   __shared__ double sh[kBlock];
-  const int j = blockIdx.y;
-  const int ch = blockIdx.x;
   if (!dirty[j]) return;
   const int64_t t0 = (int64_t)ch * kMoveChunk;
   const int64_t t1 = (t0 + kMoveChunk < d) ? t0 + kMoveChunk : d;
@@ -290,6 +319,14 @@ __global__ __launch_bounds__(kBlock) void k_sumsq_partial(const long long* __res
   if (threadIdx.x == 0) part_sq[(size_t)j * nchunk + ch] = tot;
 }
 
+__global__ __launch_bounds__(kBlock) void k_sumsq_partial(const long long* __restrict__ S,
+                                                          int64_t d, double fx_inv,
+                                                          const int32_t* __restrict__ dirty,
+                                                          double* __restrict__ part_sq,
+                                                          int nchunk) {
+  sumsq_partial_body(S, d, fx_inv, dirty, part_sq, nchunk, blockIdx.x, blockIdx.y);
+}
+
 __device__ __forceinline__ double chunk_norm(const double* __restrict__ part_sq, int j,
                                              int nchunk) {
   double ss = 0.0;
@@ -297,13 +334,11 @@ __device__ __forceinline__ double chunk_norm(const double* __restrict__ part_sq,
   return sqrt(ss);
 }
 
-__global__ __launch_bounds__(kBlock) void k_normalize_move(
+__device__ __forceinline__ void normalize_move_body(
     const long long* __restrict__ S, int64_t d, double fx_inv, const int32_t* __restrict__ dirty,
     const double* __restrict__ part_sq, double* __restrict__ C64, double* __restrict__ part,
-    int nchunk) {
+    int nchunk, int ch, int j) {
   __shared__ double sh[kBlock];
-  const int j = blockIdx.y;
-  const int ch = blockIdx.x;
   if (!dirty[j]) return;
   const double nrm = chunk_norm(part_sq, j, nchunk);
   const int64_t t0 = (int64_t)ch * kMoveChunk;
@@ -323,6 +358,13 @@ __global__ __launch_bounds__(kBlock) void k_normalize_move(
   if (threadIdx.x == 0) part[(size_t)j * nchunk + ch] = tot;
 }
 
+__global__ __launch_bounds__(kBlock) void k_normalize_move(
+    const long long* __restrict__ S, int64_t d, double fx_inv, const int32_t* __restrict__ dirty,
+    const double* __restrict__ part_sq, double* __restrict__ C64, double* __restrict__ part,
+    int nchunk) {
+  normalize_move_body(S, d, fx_inv, dirty, part_sq, C64, part, nchunk, blockIdx.x, blockIdx.y);
+}
+
 struct MinPair {
   double v;
   int j;
@@ -334,7 +376,7 @@ __device__ __forceinline__ MinPair min_pair(MinPair a, MinPair b) {
 }
 
 // Single block.
-__global__ __launch_bounds__(kBlock) void k_centre_finalize(
+__device__ __forceinline__ void centre_finalize_body(
     int32_t k, int64_t d, const int32_t* __restrict__ dirty, double* __restrict__ norm64,
     const double* __restrict__ part_sq, const double* __restrict__ part, int nchunk,
     double delta_c, double* __restrict__ pc, double* __restrict__ ps, MoveMin* __restrict__ mm,
@@ -408,6 +450,14 @@ __global__ __launch_bounds__(kBlock) void k_centre_finalize(
   }
 }
 
+__global__ __launch_bounds__(kBlock) void k_centre_finalize(
+    int32_t k, int64_t d, const int32_t* __restrict__ dirty, double* __restrict__ norm64,
+    const double* __restrict__ part_sq, const double* __restrict__ part, int nchunk,
+    double delta_c, double* __restrict__ pc, double* __restrict__ ps, MoveMin* __restrict__ mm,
+    Persist* __restrict__ per) {
+  centre_finalize_body(k, d, dirty, norm64, part_sq, part, nchunk, delta_c, pc, ps, mm, per);
+}
+
 __global__ void k_clear_dirty(int32_t* dirty, int32_t k) {
   const int j = blockIdx.x * kBlock + threadIdx.x;
   if (j < k) dirty[j] = 0;
@@ -426,13 +476,12 @@ constexpr int kGramT = 64;
 constexpr int kGramK = 32;
 constexpr int kGramLoads = kGramT * kGramK / kBlock;  // per panel and thread
 
-__global__ __launch_bounds__(kBlock) void k_gram_partial(const double* __restrict__ C64,
-                                                         int32_t k, int64_t d,
-                                                         const int32_t* __restrict__ dirty,
-                                                         int force_all, double* __restrict__ part,
-                                                         int64_t slice_len,
-                                                         Persist* __restrict__ per,
-                                                         const StepCtl* __restrict__ ctl) {
+__device__ __forceinline__ void gram_partial_body(const double* __restrict__ C64, int32_t k,
+                                                  int64_t d, const int32_t* __restrict__ dirty,
+                                                  int force_all, double* __restrict__ part,
+                                                  int64_t slice_len, Persist* __restrict__ per,
+                                                  const StepCtl* __restrict__ ctl, int pair,
+                                                  int s) {
   __shared__ double As[kGramT][kGramK + 1];
   __shared__ double Bs[kGramT][kGramK + 1];
   __shared__ int any;
@@ -441,7 +490,7 @@ __global__ __launch_bounds__(kBlock) void k_gram_partial(const double* __restric
     force_all = ctl->gram_force;
   }
   const int nt = (k + kGramT - 1) / kGramT;
-  int idx = blockIdx.x, ta = 0;
+  int idx = pair, ta = 0;
   while (idx >= nt - ta) {
     idx -= nt - ta;
     ++ta;
@@ -458,7 +507,6 @@ __global__ __launch_bounds__(kBlock) void k_gram_partial(const double* __restric
     __syncthreads();
     if (!any) return;
   }
-  const int s = blockIdx.y;
   const int64_t ts = (int64_t)s * slice_len;
   const int64_t te = (ts + slice_len < d) ? ts + slice_len : d;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -532,17 +580,27 @@ __global__ __launch_bounds__(kBlock) void k_gram_partial(const double* __restric
   }
 }
 
+__global__ __launch_bounds__(kBlock) void k_gram_partial(const double* __restrict__ C64,
+                                                         int32_t k, int64_t d,
+                                                         const int32_t* __restrict__ dirty,
+                                                         int force_all, double* __restrict__ part,
+                                                         int64_t slice_len,
+                                                         Persist* __restrict__ per,
+                                                         const StepCtl* __restrict__ ctl) {
+  gram_partial_body(C64, k, d, dirty, force_all, part, slice_len, per, ctl, blockIdx.x,
+                    blockIdx.y);
+}
+
 // Row a of G (slices summed in slice order) and gmax[a] = the largest
 // off-diagonal entry of the row widened by delta_g (capped at 1), or -3
 // (no centre-centre pruning) for k = 1.  One block per row.
-__global__ __launch_bounds__(kBlock) void k_gram_finalize(const double* __restrict__ part,
-                                                          int32_t k, int nslice, double delta_g,
-                                                          double* __restrict__ G,
-                                                          double* __restrict__ gmax,
-                                                          const StepCtl* __restrict__ ctl) {
+__device__ __forceinline__ void gram_finalize_body(const double* __restrict__ part, int32_t k,
+                                                   int nslice, double delta_g,
+                                                   double* __restrict__ G,
+                                                   double* __restrict__ gmax,
+                                                   const StepCtl* __restrict__ ctl, int a) {
   __shared__ double sh[kBlock / 64];
   if (ctl && ctl->gram_mode != 1) return;
-  const int a = blockIdx.x;
   const int64_t kk = (int64_t)k * k;
   double m = -INFINITY;
   for (int b = threadIdx.x; b < k; b += kBlock) {
@@ -571,6 +629,14 @@ __global__ __launch_bounds__(kBlock) void k_gram_finalize(const double* __restri
   }
 }
 
+__global__ __launch_bounds__(kBlock) void k_gram_finalize(const double* __restrict__ part,
+                                                          int32_t k, int nslice, double delta_g,
+                                                          double* __restrict__ G,
+                                                          double* __restrict__ gmax,
+                                                          const StepCtl* __restrict__ ctl) {
+  gram_finalize_body(part, k, nslice, delta_g, G, gmax, ctl, blockIdx.x);
+}
+
 // Carries the centre-centre bounds across a centre step without the d-long
 // products: centres a and b moved by at most the angles whose cosines and
 // sines are (pc, ps), so their angle shrank by at most theta_a + theta_b and
@@ -578,15 +644,13 @@ __global__ __launch_bounds__(kBlock) void k_gram_finalize(const double* __restri
 // bound of <c_a, c_b> (1 once theta_a + theta_b reaches pi or the old angle).
 // Every update adds 4e-15 for its own FP64 rounding.  One block per row;
 // (a, b) and (b, a) get bitwise equal values.
-__global__ __launch_bounds__(kBlock) void k_gram_carry(double* __restrict__ G, int32_t k,
-                                                       const double* __restrict__ pc,
-                                                       const double* __restrict__ ps,
-                                                       double delta_g,
-                                                       double* __restrict__ gmax,
-                                                       const StepCtl* __restrict__ ctl) {
+__device__ __forceinline__ void gram_carry_body(double* __restrict__ G, int32_t k,
+                                                const double* __restrict__ pc,
+                                                const double* __restrict__ ps, double delta_g,
+                                                double* __restrict__ gmax,
+                                                const StepCtl* __restrict__ ctl, int a) {
   __shared__ double sh[kBlock / 64];
   if (ctl && ctl->gram_mode != 2) return;
-  const int a = blockIdx.x;
   const double pa = pc[a], sa = ps[a];
   double m = -INFINITY;
   for (int b = threadIdx.x; b < k; b += kBlock) {
@@ -611,6 +675,15 @@ __global__ __launch_bounds__(kBlock) void k_gram_carry(double* __restrict__ G, i
     for (int w = 1; w < kBlock / 64; ++w) mm = fmax(mm, sh[w]);
     gmax[a] = (k > 1) ? fmin(1.0, mm + delta_g) : -3.0;
   }
+}
+
+__global__ __launch_bounds__(kBlock) void k_gram_carry(double* __restrict__ G, int32_t k,
+                                                       const double* __restrict__ pc,
+                                                       const double* __restrict__ ps,
+                                                       double delta_g,
+                                                       double* __restrict__ gmax,
+                                                       const StepCtl* __restrict__ ctl) {
+  gram_carry_body(G, k, pc, ps, delta_g, gmax, ctl, blockIdx.x);
 }
 
 __global__ void k_c64_to_f32(const double* __restrict__ in, int64_t count, float* __restrict__ out) {
@@ -661,9 +734,12 @@ __global__ void k_step_init(StepCtl* ctl, int gram_on, int warm, double test_min
 //  - tightening: always at the first three steps and while the last
 //    measured pruning rate of tightening reaches tight_min, else probed
 //    with the same doubling gap.
-__global__ void k_step_end(const Counters* __restrict__ cnt, StepCtl* __restrict__ ctl,
-                           StepRec* __restrict__ rec, const Persist* __restrict__ per, int32_t t,
-                           int64_t n, int32_t* __restrict__ dirty, int32_t k, int gram_queued) {
+__device__ __forceinline__ void step_end_body(const Counters* __restrict__ cnt,
+                                              StepCtl* __restrict__ ctl,
+                                              StepRec* __restrict__ rec,
+                                              const Persist* __restrict__ per, int32_t t,
+                                              int64_t n, int32_t* __restrict__ dirty, int32_t k,
+                                              int gram_queued) {
   const int i = threadIdx.x;
   // the previous centre update's dirty flags have been read by now
   for (int j = i; j < k; j += 64) dirty[j] = 0;
@@ -760,6 +836,133 @@ __global__ void k_step_end(const Counters* __restrict__ cnt, StepCtl* __restrict
     }
   }
   *ctl = c;
+}
+
+__global__ void k_step_end(const Counters* __restrict__ cnt, StepCtl* __restrict__ ctl,
+                           StepRec* __restrict__ rec, const Persist* __restrict__ per, int32_t t,
+                           int64_t n, int32_t* __restrict__ dirty, int32_t k, int gram_queued) {
+  step_end_body(cnt, ctl, rec, per, t, n, dirty, k, gram_queued);
+}
+
+// ------------------------------------------------------------------------
+// Batched fits: the kernels above with their arguments taken from the
+// problem's FitView; every block serves one work item (.x = problem).  The
+// bodies are the single-problem ones, so every problem computes exactly
+// what its own fit computes.
+// ------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_b_row_eta(const FitView* __restrict__ V,
+                                                      const int2* __restrict__ items) {
+  const int2 w = items[blockIdx.x];
+  const FitView& f = V[w.x];
+  row_eta_body(f.rp, f.v, f.n, f.eta, f.maxeta, (int64_t)w.y / kBlock);
+}
+
+__global__ __launch_bounds__(kBlock) void k_b_init_centres(const FitView* __restrict__ V,
+                                                           const int2* __restrict__ items) {
+  const int2 w = items[blockIdx.x];
+  const FitView& f = V[w.x];
+  init_centres_body(f.init, f.d, 1, f.C64, f.initnorm, w.y);
+}
+
+__global__ __launch_bounds__(kBlock) void k_b_transpose(const FitView* __restrict__ V,
+                                                        const int4* __restrict__ items,
+                                                        int use_dirty) {
+  const int4 w = items[blockIdx.x];
+  const FitView& f = V[w.x];
+  const int64_t ntt = (f.d + 63) / 64;
+  const int64_t end = ((int64_t)w.z + kTransposeGroup < ntt) ? w.z + kTransposeGroup : ntt;
+  for (int64_t tt = w.z; tt < end; ++tt) {
+    transpose_body(f.C64, f.k, f.d, f.kp, use_dirty ? f.dirty : nullptr, f.CT, nullptr, tt, w.y);
+    __syncthreads();  // the next tile reuses the LDS tile
+  }
+}
+
+__global__ void k_b_step_init(const FitView* __restrict__ V, int nprob) {
+  const int p = blockIdx.x * kBlock + threadIdx.x;
+  if (p >= nprob) return;
+  const FitView& f = V[p];
+  StepCtl c{};
+  c.gram_on = f.gram;
+  c.tests = 1;
+  c.test_gap = 2;
+  c.test_min = f.test_min;
+  c.tighten = 1;
+  c.tight_gap = 4;
+  c.tight_rate = 1.0;
+  c.tight_min = f.tight_min;
+  c.max_iter = f.max_iter;
+  *f.ctl = c;
+}
+
+// One wave per problem: step_end_body with the step index the problem keeps
+// in its StepCtl; a problem that reaches its max_iter stops with stop = 2
+// (the centre update of that last step still runs, as in a single fit).
+__global__ void k_b_step_end(const FitView* __restrict__ V, int slot) {
+  const FitView& f = V[blockIdx.x];
+  StepCtl* ctl = f.ctl;
+  const int32_t t = ctl->step;
+  const int32_t was_stopped = ctl->stop;
+  step_end_body(f.cnt + (size_t)slot * kCounterSlots, ctl, f.rec + slot, f.per, t, f.n,
+                f.dirty, f.k, 1);
+  if (threadIdx.x == 0 && !was_stopped) {
+    ctl->step = t + 1;
+    if (t + 1 >= ctl->max_iter && ctl->stop == 0) {
+      ctl->stop = 2;
+      ctl->gram_mode = 0;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_b_update_scan(const FitView* __restrict__ V,
+                                                          const int2* __restrict__ items) {
+  const int2 w = items[blockIdx.x];
+  const FitView& f = V[w.x];
+  const int64_t end = ((int64_t)w.y + kBlock < f.n) ? (int64_t)w.y + kBlock : f.n;
+  update_scan_body(f.rp, f.ci, f.v, f.a, f.a_old, w.y, end, kBlock, f.d, f.fx, f.S, f.dirty);
+}
+
+__global__ __launch_bounds__(kBlock) void k_b_sumsq(const FitView* __restrict__ V,
+                                                    const int2* __restrict__ items) {
+  const int2 w = items[blockIdx.x];
+  const FitView& f = V[w.x];
+  for (int ch = 0; ch < f.nchunk; ++ch)
+    sumsq_partial_body(f.S, f.d, f.fx_inv, f.dirty, f.part_sq, f.nchunk, ch, w.y);
+}
+
+__global__ __launch_bounds__(kBlock) void k_b_normalize(const FitView* __restrict__ V,
+                                                        const int2* __restrict__ items) {
+  const int2 w = items[blockIdx.x];
+  const FitView& f = V[w.x];
+  for (int ch = 0; ch < f.nchunk; ++ch)
+    normalize_move_body(f.S, f.d, f.fx_inv, f.dirty, f.part_sq, f.C64, f.part, f.nchunk, ch,
+                        w.y);
+}
+
+__global__ __launch_bounds__(kBlock) void k_b_finalize(const FitView* __restrict__ V) {
+  const FitView& f = V[blockIdx.x];
+  centre_finalize_body(f.k, f.d, f.dirty, f.norm64, f.part_sq, f.part, f.nchunk, f.delta_c, f.pc,
+                       f.ps, f.mm, f.per);
+}
+
+__global__ __launch_bounds__(kBlock) void k_b_gram_partial(const FitView* __restrict__ V,
+                                                           const int4* __restrict__ items) {
+  const int4 w = items[blockIdx.x];
+  const FitView& f = V[w.x];
+  gram_partial_body(f.C64, f.k, f.d, f.dirty, 0, f.gpart, f.slice_len, f.per, f.ctl, w.y, w.z);
+}
+
+__global__ __launch_bounds__(kBlock) void k_b_gram_finalize(const FitView* __restrict__ V,
+                                                            const int2* __restrict__ items) {
+  const int2 w = items[blockIdx.x];
+  const FitView& f = V[w.x];
+  gram_finalize_body(f.gpart, f.k, f.nslice, f.delta_g, f.G, f.gmax, f.ctl, w.y);
+}
+
+__global__ __launch_bounds__(kBlock) void k_b_gram_carry(const FitView* __restrict__ V,
+                                                         const int2* __restrict__ items) {
+  const int2 w = items[blockIdx.x];
+  const FitView& f = V[w.x];
+  gram_carry_body(f.G, f.k, f.pc, f.ps, f.delta_g, f.gmax, f.ctl, w.y);
 }
 
 unsigned blocks_for(int64_t count) {
@@ -926,6 +1129,75 @@ hipError_t launch_fill_f64(double* p, int64_t count, double value, hipStream_t s
 
 hipError_t launch_fill_i32(int32_t* p, int64_t count, int32_t value, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(count)), dim3(kBlock), 0, s, p, count, value);
+  return hipGetLastError();
+}
+
+hipError_t launch_b_row_eta(const FitView* V, const int2* items, int n_items, hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_b_row_eta, dim3((unsigned)n_items), dim3(kBlock), 0, s, V, items);
+  return hipGetLastError();
+}
+
+hipError_t launch_b_init_centres(const FitView* V, const int2* items, int n_items,
+                                 hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_b_init_centres, dim3((unsigned)n_items), dim3(kBlock), 0, s, V, items);
+  return hipGetLastError();
+}
+
+hipError_t launch_b_transpose(const FitView* V, const int4* items, int n_items, int use_dirty,
+                              hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_b_transpose, dim3((unsigned)n_items), dim3(kBlock), 0, s, V, items,
+                     use_dirty);
+  return hipGetLastError();
+}
+
+hipError_t launch_b_step_init(const FitView* V, int nprob, hipStream_t s) {
+  hipLaunchKernelGGL(k_b_step_init, dim3(blocks_for(nprob)), dim3(kBlock), 0, s, V, nprob);
+  return hipGetLastError();
+}
+
+hipError_t launch_b_step_end(const FitView* V, int nprob, int slot, hipStream_t s) {
+  hipLaunchKernelGGL(k_b_step_end, dim3((unsigned)nprob), dim3(64), 0, s, V, slot);
+  return hipGetLastError();
+}
+
+hipError_t launch_b_update_scan(const FitView* V, const int2* items, int n_items, hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_b_update_scan, dim3((unsigned)n_items), dim3(kBlock), 0, s, V, items);
+  return hipGetLastError();
+}
+
+hipError_t launch_b_sumsq(const FitView* V, const int2* items, int n_items, hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_b_sumsq, dim3((unsigned)n_items), dim3(kBlock), 0, s, V, items);
+  return hipGetLastError();
+}
+
+hipError_t launch_b_normalize(const FitView* V, const int2* items, int n_items, hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_b_normalize, dim3((unsigned)n_items), dim3(kBlock), 0, s, V, items);
+  return hipGetLastError();
+}
+
+hipError_t launch_b_finalize(const FitView* V, int nprob, hipStream_t s) {
+  hipLaunchKernelGGL(k_b_finalize, dim3((unsigned)nprob), dim3(kBlock), 0, s, V);
+  return hipGetLastError();
+}
+
+hipError_t launch_b_gram(const FitView* V, const int4* pair_items, int n_pair_items,
+                         const int2* centre_items, int n_centre_items, hipStream_t s) {
+  if (n_pair_items <= 0 || n_centre_items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_b_gram_partial, dim3((unsigned)n_pair_items), dim3(kBlock), 0, s, V,
+                     pair_items);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_b_gram_finalize, dim3((unsigned)n_centre_items), dim3(kBlock), 0, s, V,
+                     centre_items);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_b_gram_carry, dim3((unsigned)n_centre_items), dim3(kBlock), 0, s, V,
+                     centre_items);
   return hipGetLastError();
 }
 

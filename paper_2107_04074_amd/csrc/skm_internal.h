@@ -73,11 +73,13 @@ struct StepCtl {
   int32_t tighten;                // the next assignment step tightens
   int32_t tight_next;             // step of the next tightening probe
   int32_t tight_gap;              // probe interval, doubled after each failed probe
-  int32_t pad0;
+  int32_t step;                   // batched fits: assignment steps taken so far
   double test_min;                // pruned-row fraction below which tests are switched off
   double tight_rate;              // pruned / tightened when last measured
   double tight_min;               // rate below which tightening is switched off
-  double pad[6];
+  int32_t max_iter;               // batched fits: the problem's step limit (stop = 2 there)
+  int32_t pad1;
+  double pad[5];
 };
 static_assert(sizeof(StepRec) == 96 && sizeof(StepCtl) == 128, "record layout");
 
@@ -245,6 +247,75 @@ struct DenseHamerlyArgs {
   int32_t* flag;
   Counters* cnt;
 };
+
+// ------------------------------------------------------------------------
+// Batched fits: many small CSR problems advance in lockstep, one assignment
+// step at a time, each kernel of a step serving every problem (work items
+// name the problem).  Everything a kernel needs of problem p is in FitView p.
+// ------------------------------------------------------------------------
+struct FitView {
+  const int64_t* rp;
+  const int32_t* ci;
+  const float* v;
+  int64_t n, d;
+  int32_t k, kp;
+  const float* init;          // caller's initial centres, k x d
+  float* CT;                  // d x kp FP32 centre copy
+  double* C64;                // k x d
+  long long* S;               // k x d fixed-point member sums
+  float* eta;
+  int32_t* a;
+  int32_t* a_old;
+  double* norm64;
+  double* part;
+  double* part_sq;
+  double* pc;
+  double* ps;
+  int32_t* dirty;
+  MoveMin* mm;
+  double* G;                  // Gram variants only
+  double* gmax;
+  double* gpart;
+  Counters* cnt;              // kStepChunk x kCounterSlots
+  Persist* per;
+  StepCtl* ctl;
+  StepRec* rec;               // kStepChunk records
+  float* maxeta;              // kCounterSlots
+  double* initnorm;           // k
+  int32_t nchunk, nslice;
+  int64_t slice_len;
+  double fx, fx_inv, delta_c, delta_g;
+  double test_min, tight_min;
+  int32_t gram;               // the variant keeps centre-centre products
+  int32_t max_iter;
+};
+
+// Work items of the batched kernels: .x names the problem.
+//  rows      (p, first row): 256 rows (row_eta, update) or the tuned tile (walk)
+//  centres   (p, centre j)
+//  transpose (p, centre tile, first column tile, 0): kTransposeGroup column tiles
+//  gram      (p, tile pair, column slice, 0)
+constexpr int kTransposeGroup = 16;
+hipError_t launch_b_row_eta(const FitView* V, const int2* items, int n_items, hipStream_t s);
+hipError_t launch_b_init_centres(const FitView* V, const int2* items, int n_items,
+                                 hipStream_t s);
+hipError_t launch_b_transpose(const FitView* V, const int4* items, int n_items, int use_dirty,
+                              hipStream_t s);
+hipError_t launch_b_step_init(const FitView* V, int nprob, hipStream_t s);
+hipError_t launch_b_step_end(const FitView* V, int nprob, int slot, hipStream_t s);
+hipError_t launch_b_update_scan(const FitView* V, const int2* items, int n_items, hipStream_t s);
+hipError_t launch_b_sumsq(const FitView* V, const int2* items, int n_items, hipStream_t s);
+hipError_t launch_b_normalize(const FitView* V, const int2* items, int n_items, hipStream_t s);
+hipError_t launch_b_finalize(const FitView* V, int nprob, hipStream_t s);
+hipError_t launch_b_gram(const FitView* V, const int4* pair_items, int n_pair_items,
+                         const int2* centre_items, int n_centre_items, hipStream_t s);
+// Row walk of one assignment step for every problem of one centre-copy width
+// (kp): a persistent grid takes (problem, row tile) items from an atomic
+// queue (*queue must be 0 at launch).  args[item.x * arg_stride + arg_off]
+// are the walk arguments of the item's problem; mode as in launch_assign.
+hipError_t launch_assign_batched(const AssignArgs* args, int arg_stride, int arg_off,
+                                 const int2* items, int n_items, int tile_rows, int kp,
+                                 int mode, unsigned int* queue, hipStream_t s);
 
 // ---- launchers (kernels_dense.hip) ----
 size_t dense_sim_lds_bytes(bool bf16, int dp);

@@ -132,8 +132,16 @@ def test_batched_arguments_are_rejected(lib):
     biggest = max(lib.skm_workspace_size(ctypes.byref(ms[b]), ks[b], skm.HAMERLY, None)
                   for b in range(3))
     assert one >= biggest and three == 3 * one
-    # auto worker count never exceeds the number of problems
-    assert lib.skm_fit_batched_workspace_size(3, ms, ks, skm.HAMERLY, None, 0) == three
+    # workers = 0 (lockstep): every problem keeps its own state, plus the
+    # shared views, walk arguments, control blocks and work items
+    lock = lib.skm_fit_batched_workspace_size(3, ms, ks, skm.HAMERLY, None, 0)
+    singles = sum(lib.skm_workspace_size(ctypes.byref(ms[b]), ks[b], skm.HAMERLY, None)
+                  for b in range(3))
+    assert lock >= singles
+    # variants without a lockstep form take the host-thread slots (at most
+    # one worker per problem)
+    assert (lib.skm_fit_batched_workspace_size(3, ms, ks, skm.ELKAN, None, 0) ==
+            lib.skm_fit_batched_workspace_size(3, ms, ks, skm.ELKAN, None, 3))
     # a bad problem is named
     ks_bad = (ctypes.c_int32 * 3)(3, 0, 2)
     assert lib.skm_fit_batched_workspace_size(3, ms, ks_bad, skm.HAMERLY, None, 1) == 0
