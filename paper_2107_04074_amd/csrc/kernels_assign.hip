@@ -288,6 +288,7 @@ __device__ __forceinline__ float row_walk(const int32_t* __restrict__ ci,
 struct RowIn {
   int prev;
   float l, u, eta;
+  int run;  // chunked walks after the first chunk: the row is walked this step
 };
 
 // Hamerly mode prologue (Sections 5.3 / 5.4): Eq. (6) for l(i), the guarded
@@ -540,7 +541,7 @@ template <int G, int VEC>
 __device__ __forceinline__ void group_redecide(unsigned long long cm, const int32_t* ci,
                                                const float* v, int64_t beg, int64_t end,
                                                const double* C64, int64_t d, int gl, int prev,
-                                               double& cb, int& cj) {
+                                               double& cb, int& cj, int j0 = 0) {
   cb = -INFINITY;
   cj = INT_MAX;
   const int base = (int)(threadIdx.x & 63) - gl;  // first lane of the group
@@ -555,7 +556,7 @@ __device__ __forceinline__ void group_redecide(unsigned long long cm, const int3
     const unsigned long long sm = ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
     const int bit = __builtin_ctzll(sm);
     if (gl == src) cm &= cm - 1ull;
-    const int j = VEC * (src + G * (bit / VEC)) + bit % VEC;
+    const int j = j0 + VEC * (src + G * (bit / VEC)) + bit % VEC;
     const double sv = dot64_group<G>(ci, v, beg, end, C64 + (size_t)j * d, gl);
     if (better64(sv, j, cb, cj, prev)) {
       cb = sv;
@@ -596,9 +597,12 @@ constexpr int assign_min_waves() {
 
 // Rows row_base + (row group of this thread), then every rstride rows, below
 // row_end; per-step counts go to counter slot `slot`.
-template <int G, int R, int VEC, int MODE, bool WAVE_ROW>
+template <int G, int R, int VEC, int MODE, bool WAVE_ROW, bool CHUNK = false>
 __device__ __forceinline__ void assign_rows(const AssignArgs& A, int64_t row_base,
                                             int64_t row_end, int64_t rstride, int slot) {
+  static_assert(!CHUNK || (WAVE_ROW && G == 64 && R == 1 &&
+                           (MODE == kModeFit || MODE == kModeHamerly)),
+                "chunked walks: one chunk of 64 x VEC centres per lane row, fit/Hamerly");
   static_assert(VEC == 4 || (VEC == 8 && WAVE_ROW), "FP16 centres need the wave layout");
   constexpr int NACC = R * VEC / 4;
   const int gl = threadIdx.x & (G - 1);
@@ -622,7 +626,9 @@ __device__ __forceinline__ void assign_rows(const AssignArgs& A, int64_t row_bas
                      my_saved = 0, my_sims = 0;
   const float4* CT4 = reinterpret_cast<const float4*>(A.CT);
   const int kp4 = A.kp >> 2;
-  const int k = A.k;
+  // a chunked launch walks centres j0 ... j0 + k - 1 (k counts them)
+  const int j0 = CHUNK ? A.j0 : 0;
+  const int k = CHUNK ? min(A.k - j0, R * G * VEC) : A.k;
 
   // one row per wave: the bounds and the first 64 entries of the wave's next
   // row are loaded while the current row is processed, so a row's walk
@@ -650,14 +656,15 @@ __device__ __forceinline__ void assign_rows(const AssignArgs& A, int64_t row_bas
     }
   };
   auto load_in = [&](int64_t r) -> RowIn {
-    RowIn x{-1, 0.f, 0.f, 0.f};
+    RowIn x{-1, 0.f, 0.f, 0.f, 1};
     if (A.read_prev) x.prev = A.a[r];
     if constexpr (kBounded) x.l = A.l[r];
     if constexpr (MODE == kModeHamerly) x.u = A.u[r];
     if constexpr (MODE != kModeAssign) x.eta = A.eta[r];
+    if constexpr (CHUNK) x.run = j0 > 0 ? (A.rs[r].flags & 1) : 1;
     return x;
   };
-  RowIn nin{-1, 0.f, 0.f, 0.f};
+  RowIn nin{-1, 0.f, 0.f, 0.f, 1};
   if constexpr (WAVE_ROW) {
     const int64_t r0 = row_base + gib;
     if (r0 < row_end) {
@@ -702,7 +709,14 @@ __device__ __forceinline__ void assign_rows(const AssignArgs& A, int64_t row_bas
     constexpr bool kPartial = (MODE == kModeYinYang || MODE == kModeElkan) && WAVE_ROW &&
                               VEC == 4 && R >= 2 && R <= 8;
     unsigned need = ~0u;
-    if constexpr (kBounded) {
+    if constexpr (CHUNK) {
+      // later chunks walk only the rows the first chunk's tests left
+      if (j0 > 0 && !ri.run) {
+        next_window();
+        continue;
+      }
+    }
+    if constexpr (kBounded) if (!CHUNK || j0 == 0) {
       uint64_t surv0 = ~0ull, surv1 = ~0ull;
       const bool skip =
           MODE == kModeHamerly
@@ -714,6 +728,9 @@ __device__ __forceinline__ void assign_rows(const AssignArgs& A, int64_t row_bas
               : elkan_prologue<G, R, VEC, kPartial>(A, row, ri, beg, end, gl, leader, tighten,
                                                     lead_sub, my_tight, my_saved, need);
       if (skip) {
+        if constexpr (CHUNK) {
+          if (leader) A.rs[row].flags = 0;  // pruned: the later chunks skip the row
+        }
         if constexpr (WAVE_ROW) next_window();
         continue;
       }
@@ -733,9 +750,11 @@ __device__ __forceinline__ void assign_rows(const AssignArgs& A, int64_t row_bas
     float4 acc[NACC];
     float nrm2;
     if constexpr (WAVE_ROW) {
-      nrm2 = row_walk<G, R, VEC, kPartial>(A.ci, A.v, beg, end, c0, x0,
-                                           VEC == 8 ? (const void*)A.CT16 : (const void*)A.CT,
-                                           A.kp, wl, acc, need);
+      const char* ctb = VEC == 8 ? static_cast<const char*>(A.CT16)
+                                 : reinterpret_cast<const char*>(A.CT);
+      if constexpr (CHUNK) ctb += (size_t)j0 * (VEC == 8 ? 2 : 4);
+      nrm2 = row_walk<G, R, VEC, kPartial>(A.ci, A.v, beg, end, c0, x0, ctb, A.kp, wl, acc,
+                                           need);
       next_window();
     } else {
       nrm2 = row_sims<G, R, false>(A.ci, A.v, beg, end, CT4, kp4, gl, ~0u, acc);
@@ -761,10 +780,10 @@ __device__ __forceinline__ void assign_rows(const AssignArgs& A, int64_t row_bas
         const int j = VEC * (gl + G * r) + q;
         if (j < k && ((need >> r) & 1u)) {
           const float sv = f4get(acc[(r * VEC + q) >> 2], q & 3);
-          if (better32(sv, j, b, bj, prev)) {
+          if (better32(sv, j0 + j, b, bj, prev)) {
             s2 = fmaxf(s2, b);
             b = sv;
-            bj = j;
+            bj = j0 + j;
           } else {
             s2 = fmaxf(s2, sv);
           }
@@ -799,10 +818,78 @@ __device__ __forceinline__ void assign_rows(const AssignArgs& A, int64_t row_bas
         }
       double cb;
       int cj;
-      group_redecide<G, VEC>(cm, A.ci, A.v, beg, end, A.C64, A.d, gl, prev, cb, cj);
+      group_redecide<G, VEC>(cm, A.ci, A.v, beg, end, A.C64, A.d, gl, prev, cb, cj, j0);
       abest = cj;
       best64 = cb;
       rechecked = true;
+    }
+
+    if constexpr (CHUNK) {
+      // merge this chunk's exact winner into the row's running result: FP32
+      // values decide where they are apart by more than their error bounds,
+      // else both winners get their canonical FP64 values
+      double vw = rechecked ? best64 : (double)b;
+      double ew = rechecked ? 0.0 : eps;
+      int jw = abest;
+      bool xw = rechecked;
+      double sec = rechecked ? (double)b : (double)s2;
+      double emax = eps;
+      bool any = rechecked;
+      if (j0 > 0) {
+        const RowRun rr = A.rs[row];
+        double vc = rr.best, ec = rr.err;
+        int jc = rr.bj;
+        bool xc = (rr.flags & 2) != 0;
+        any = any || (rr.flags & 4) != 0;
+        emax = fmax(emax, rr.errmax);
+        sec = fmax(sec, rr.second);
+        if (!(xc && xw) && fabs(vw - vc) <= ew + ec + 1e-12) {
+          if (!xc) vc = dot64_group<G>(A.ci, A.v, beg, end, A.C64 + (size_t)jc * A.d, gl);
+          if (!xw) vw = dot64_group<G>(A.ci, A.v, beg, end, A.C64 + (size_t)jw * A.d, gl);
+          xc = xw = true;
+          ec = ew = 0.0;
+          any = true;
+        }
+        const bool win = (xc && xw) ? better64(vw, jw, vc, jc, prev) : vw > vc;
+        if (win) {
+          sec = fmax(sec, vc);
+        } else {
+          sec = fmax(sec, vw);
+          vw = vc;
+          ew = ec;
+          jw = jc;
+          xw = xc;
+        }
+      }
+      if (!A.chunk_last) {
+        if (leader) {
+          RowRun o;
+          o.best = vw;
+          o.second = sec;
+          o.err = ew;
+          o.errmax = emax;
+          o.bj = jw;
+          o.flags = 1 | (xw ? 2 : 0) | (any ? 4 : 0);
+          A.rs[row] = o;
+        }
+      } else if (leader) {
+        const double eta = (double)ri.eta;
+        const double slack = 1.01 * (eta + A.delta_c);
+        const double rho32 = emax + slack + 1e-12;
+        const double rho64 = (double)(m + 2) * kU64 * nx + slack + 1e-15;
+        A.a[row] = jw;
+        my_changed += (jw != prev) ? 1ull : 0ull;
+        if (A.l) A.l[row] = __double2float_rd(fmax(xw ? vw - rho64 : vw - rho32, -1.0));
+        if (A.u) {
+          const double hi = (A.k == 1) ? -1.0 : sec + rho32;
+          A.u[row] = __double2float_ru(fmin(hi, 1.0));
+        }
+        my_rows += 1;
+        my_nnz += (unsigned long long)m;
+        my_rechecks += any ? 1 : 0;
+      }
+      if (leader) my_sims += row_sims_done;
+      continue;
     }
 
     if (MODE == kModeAssign) {
@@ -882,13 +969,13 @@ __device__ __forceinline__ void assign_rows(const AssignArgs& A, int64_t row_bas
   }
 }
 
-template <int G, int R, int VEC, int MODE, bool WAVE_ROW>
+template <int G, int R, int VEC, int MODE, bool WAVE_ROW, bool CHUNK = false>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
     assign_min_waves<R, WAVE_ROW>()))) void k_assign_csr(AssignArgs A) {
   constexpr int GPB = WAVE_ROW ? kBlock / 64 : kBlock / G;
-  assign_rows<G, R, VEC, MODE, WAVE_ROW>(A, (int64_t)blockIdx.x * GPB, A.n_rows,
-                                         (int64_t)gridDim.x * GPB,
-                                         (int)(blockIdx.x % kCounterSlots));
+  assign_rows<G, R, VEC, MODE, WAVE_ROW, CHUNK>(A, (int64_t)blockIdx.x * GPB, A.n_rows,
+                                                (int64_t)gridDim.x * GPB,
+                                                (int)(blockIdx.x % kCounterSlots));
 }
 
 // Batched fits: a persistent grid takes (problem, first row) items from the
@@ -1081,6 +1168,32 @@ hipError_t launch_assign_batched(const AssignArgs* args, int arg_stride, int arg
     return launch_assign_batched_mode<kModeHamerly>(args, arg_stride, arg_off, items, n_items,
                                                     tile_rows, kp, queue, s);
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_assign_chunk(const AssignArgs& A, int mode, hipStream_t s) {
+  const bool half = A.CT16 != nullptr;
+  int64_t blocks = (A.n_rows + 3) / 4;  // one row per wave
+  if (blocks > kMaxGridBlocks) blocks = kMaxGridBlocks;
+  if (blocks < 1) blocks = 1;
+  const dim3 grid((unsigned)blocks), block(kBlock);
+  if (half) {
+    if (mode == kModeFit)
+      hipLaunchKernelGGL((k_assign_csr<64, 1, 8, kModeFit, true, true>), grid, block, 0, s, A);
+    else if (mode == kModeHamerly)
+      hipLaunchKernelGGL((k_assign_csr<64, 1, 8, kModeHamerly, true, true>), grid, block, 0, s,
+                         A);
+    else
+      return hipErrorInvalidValue;
+  } else {
+    if (mode == kModeFit)
+      hipLaunchKernelGGL((k_assign_csr<64, 1, 4, kModeFit, true, true>), grid, block, 0, s, A);
+    else if (mode == kModeHamerly)
+      hipLaunchKernelGGL((k_assign_csr<64, 1, 4, kModeHamerly, true, true>), grid, block, 0, s,
+                         A);
+    else
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_assign(const AssignArgs& A, int mode, hipStream_t s) {

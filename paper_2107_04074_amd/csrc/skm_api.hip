@@ -74,11 +74,13 @@ struct Plan {
   bool half = false;  // FP16 centre copy for the row walk
   bool yy = false;    // Yin-Yang group bounds
   int32_t ng = 0;     // Yin-Yang groups
+  int chunk = 0;      // centres per launch of a chunked row walk (0: one launch)
+  int nq = 1;         // launches per walk
   size_t uy = 0, gpc = 0, gps = 0;
   size_t CT = 0, CT16 = 0, negflag = 0, C64 = 0, S = 0, l = 0, u = 0, ue = 0, eta = 0,
          a_old = 0, norm64 = 0, part = 0, part_sq = 0, pc = 0, ps = 0, dirty = 0, mm = 0, G = 0,
          gmax = 0, gpart = 0, cnt = 0, per = 0, ctl = 0, rec = 0, maxeta = 0, initnorm = 0,
-         vbad = 0, total = 0;
+         vbad = 0, rs = 0, total = 0;
 };
 
 int check_matrix(const skm_matrix* X) {
@@ -239,6 +241,17 @@ int make_plan(const skm_matrix* X, int32_t k, int32_t variant, int32_t precision
   P->maxeta = take(kCounterSlots * sizeof(float));
   P->initnorm = take(kk * sizeof(double));
   P->vbad = take(sizeof(unsigned long long));
+  // Lloyd and the Hamerly variants walk wide centre copies a chunk of 1 KB
+  // per centre row at a time: the walk streams those fastest, and a chunk's
+  // slice of the copy is a quarter (FP32, k <= 1024) of the whole, which the
+  // last-level cache holds where the whole does not
+  const int chunk = P->half ? kChunkF16 : kChunkF32;
+  if ((variant == SKM_LLOYD || variant == SKM_HAMERLY || variant == SKM_SIMP_HAMERLY) &&
+      g.kp > chunk) {
+    P->chunk = chunk;
+    P->nq = (k + chunk - 1) / chunk;
+    P->rs = take(n * sizeof(RowRun));
+  }
   P->total = cur;
   return SKM_OK;
 }
@@ -1494,6 +1507,20 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
   float* maxeta = at<float>(ws, P.maxeta);
   double* initnorm = at<double>(ws, P.initnorm);
 
+  RowRun* rs = P.chunk ? at<RowRun>(ws, P.rs) : nullptr;
+  // one assignment-step walk in `mode`: one launch, or one per chunk of
+  // centres with the running per-row results in rs
+  auto walk = [&](AssignArgs& A, int mode) -> hipError_t {
+    if (!P.chunk) return launch_assign(A, mode, s);
+    for (int q = 0; q < P.nq; ++q) {
+      A.j0 = q * P.chunk;
+      A.chunk_last = q == P.nq - 1 ? 1 : 0;
+      A.rs = rs;
+      const hipError_t e = launch_assign_chunk(A, mode, s);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  };
   int32_t iterations = 0, converged = 0;
   int64_t tot_sims = 0, tot_rechecks = 0, sk_launches = 0, sk_rows = 0, sk_nnz = 0;
   double sk_ms = 0.0;
@@ -1640,14 +1667,14 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
         A.gps = gps;
         const int plain = P.elkan ? kModeFitElkanInit : kModeFit;
         if (exhaustive || t < off_until) {
-          SKM_HIP(launch_assign(A, plain, s));
+          SKM_HIP(walk(A, plain));
         } else {
           // with the bound tests, or (switched off by the step control) a
           // full walk that refreshes every bound: the plain fit kernel
           A.gate = 1;
-          SKM_HIP(launch_assign(A, P.elkan ? kModeElkan : P.yy ? kModeYinYang : kModeHamerly, s));
+          SKM_HIP(walk(A, P.elkan ? kModeElkan : P.yy ? kModeYinYang : kModeHamerly));
           A.gate = 2;
-          SKM_HIP(launch_assign(A, P.elkan ? kModeFitElkanInit : kModeFit, s));
+          SKM_HIP(walk(A, P.elkan ? kModeFitElkanInit : kModeFit));
         }
         if (prof) SKM_HIP(hipEventRecord(ev1[c], s));
         const bool gram = (int64_t)t + 1 >= off_until;

@@ -111,6 +111,18 @@ enum AssignMode {
   kModeElkan = 5          // Elkan step: pair bounds, point and pair tests, walk if needed
 };
 
+// Running result of a row across the launches of a chunked walk (the
+// centres walked a chunk at a time): the best value so far (the canonical
+// FP64 value when exact, else the FP32 one with error bound err), the
+// largest value of every other centre seen so far (FP32 or FP64), the largest
+// FP32 error bound of any chunk, the best centre, and flags (bit 0: the row
+// is walked in this step; bit 1: best is exact; bit 2: some FP64
+// re-decision was made for the row).
+struct RowRun {
+  double best, second, err, errmax;
+  int32_t bj, flags;
+};
+
 struct AssignArgs {
   const int64_t* rp;
   const int32_t* ci;
@@ -156,8 +168,19 @@ struct AssignArgs {
   int32_t ng;
   const double* gpc;
   const double* gps;
+  // chunked walks (fit and Hamerly modes at large k): this launch walks
+  // centres j0 ... j0 + chunk - 1 (kp stays the row stride of the centre
+  // copies); chunk_last marks the launch of the last chunk; rs holds every
+  // row's running result between the launches
+  int32_t j0;
+  int32_t chunk_last;
+  RowRun* rs;
 };
 constexpr int kYYGroup = 32;  // centres per Yin-Yang group
+// Centres per launch of a chunked walk: 1 KB of every centre row, which is
+// what the row walk streams fastest (FP32 copy 256, FP16 copy 512).
+constexpr int kChunkF32 = 256;
+constexpr int kChunkF16 = 512;
 
 
 struct DenseSimArgs {
@@ -346,6 +369,9 @@ hipError_t launch_dense_prep(const float* X, int64_t ldx, int64_t n, int64_t d, 
 
 // ---- launchers (kernels_assign.hip) ----
 hipError_t launch_assign(const AssignArgs& A, int mode, hipStream_t s);
+// One launch of a chunked walk (fit or Hamerly mode; A.j0, A.chunk_last and
+// A.rs set; FP32 copy: chunks of kChunkF32, FP16 copy: kChunkF16).
+hipError_t launch_assign_chunk(const AssignArgs& A, int mode, hipStream_t s);
 
 
 // ---- launchers (kernels_update.hip) ----
