@@ -802,7 +802,8 @@ __device__ __forceinline__ void assign_rows(const AssignArgs& A, int64_t row_bas
     bool rechecked = false;
     double best64 = 0.0;
     int abest = bj;
-    if (k > 1 && (double)b - (double)s2 <= 2.0 * eps) {
+    // (chunked walks defer this decision: see the merge below)
+    if (!CHUNK && k > 1 && (double)b - (double)s2 <= 2.0 * eps) {
       // 1e-12 below the band: the FP64 winner is a candidate whichever FP32
       // summation order produced b
       const double thr = (double)b - 2.0 * eps - 1e-12;
@@ -825,32 +826,58 @@ __device__ __forceinline__ void assign_rows(const AssignArgs& A, int64_t row_bas
     }
 
     if constexpr (CHUNK) {
-      // merge this chunk's exact winner into the row's running result: FP32
-      // values decide where they are apart by more than their error bounds,
-      // else both winners get their canonical FP64 values
-      double vw = rechecked ? best64 : (double)b;
-      double ew = rechecked ? 0.0 : eps;
-      int jw = abest;
-      bool xw = rechecked;
-      double sec = rechecked ? (double)b : (double)s2;
-      double emax = eps;
-      bool any = rechecked;
+      // Merge this chunk into the row's running result.  A winner is kept as
+      // its FP32 value (error bound ew) until an FP64 decision is needed: a
+      // chunk whose FP32 top two lie within their error bounds is marked
+      // ambiguous (its FP32 winner may not be its FP64 winner) and resolved
+      // only if it can still win -- if its value overlaps another winner's,
+      // or if it is the winner after the last chunk -- by re-evaluating every
+      // centre of that chunk in the canonical FP64 order.  Overlapping
+      // winners are compared by their canonical FP64 values.  `sec` bounds
+      // every other centre's similarity (FP32 values, error <= emax).
+      constexpr int CW = R * G * VEC;  // centres per chunk
+      auto resolve = [&](int jsel, int flags, double& v, int& j, double& sec_io) {
+        if (flags & 8) {  // ambiguous chunk: its exact winner among all its centres
+          const int c0 = (jsel / CW) * CW;
+          const int kc = min(A.k - c0, CW);
+          const int lo = VEC * gl;
+          const unsigned long long cm =
+              kc - lo >= VEC ? ((1ull << VEC) - 1ull)
+                             : (kc - lo > 0 ? (1ull << (kc - lo)) - 1ull : 0ull);
+          sec_io = fmax(sec_io, v);  // the FP32 best may be another centre's
+          double cb;
+          int cj;
+          group_redecide<G, VEC>(cm, A.ci, A.v, beg, end, A.C64, A.d, gl, prev, cb, cj, c0);
+          v = cb;
+          j = cj;
+        } else if (!(flags & 2)) {
+          v = dot64_group<G>(A.ci, A.v, beg, end, A.C64 + (size_t)j * A.d, gl);
+        }
+      };
+      double vw = (double)b, ew = eps, sec = (double)s2, emax = eps;
+      int jw = bj;
+      int fw = (k > 1 && (double)b - (double)s2 <= 2.0 * eps) ? 8 : 0;
+      bool any = false;
       if (j0 > 0) {
         const RowRun rr = A.rs[row];
         double vc = rr.best, ec = rr.err;
-        int jc = rr.bj;
-        bool xc = (rr.flags & 2) != 0;
-        any = any || (rr.flags & 4) != 0;
+        int jc = rr.bj, fc = rr.flags;
+        any = (fc & 4) != 0;
         emax = fmax(emax, rr.errmax);
         sec = fmax(sec, rr.second);
-        if (!(xc && xw) && fabs(vw - vc) <= ew + ec + 1e-12) {
-          if (!xc) vc = dot64_group<G>(A.ci, A.v, beg, end, A.C64 + (size_t)jc * A.d, gl);
-          if (!xw) vw = dot64_group<G>(A.ci, A.v, beg, end, A.C64 + (size_t)jw * A.d, gl);
-          xc = xw = true;
-          ec = ew = 0.0;
+        bool win;
+        if (vw - ew > vc + ec + 1e-12) {
+          win = true;
+        } else if (vc - ec > vw + ew + 1e-12) {
+          win = false;
+        } else {
+          resolve(jw, fw, vw, jw, sec);
+          resolve(jc, fc, vc, jc, sec);
+          fw = fc = 2;
+          ew = ec = 0.0;
           any = true;
+          win = better64(vw, jw, vc, jc, prev);
         }
-        const bool win = (xc && xw) ? better64(vw, jw, vc, jc, prev) : vw > vc;
         if (win) {
           sec = fmax(sec, vc);
         } else {
@@ -858,8 +885,14 @@ __device__ __forceinline__ void assign_rows(const AssignArgs& A, int64_t row_bas
           vw = vc;
           ew = ec;
           jw = jc;
-          xw = xc;
+          fw = fc;
         }
+      }
+      if (A.chunk_last && (fw & 8)) {
+        resolve(jw, fw, vw, jw, sec);
+        fw = 2;
+        ew = 0.0;
+        any = true;
       }
       if (!A.chunk_last) {
         if (leader) {
@@ -869,10 +902,11 @@ __device__ __forceinline__ void assign_rows(const AssignArgs& A, int64_t row_bas
           o.err = ew;
           o.errmax = emax;
           o.bj = jw;
-          o.flags = 1 | (xw ? 2 : 0) | (any ? 4 : 0);
+          o.flags = 1 | (fw & 10) | (any ? 4 : 0);
           A.rs[row] = o;
         }
       } else if (leader) {
+        const bool xw = (fw & 2) != 0;
         const double eta = (double)ri.eta;
         const double slack = 1.01 * (eta + A.delta_c);
         const double rho32 = emax + slack + 1e-12;
