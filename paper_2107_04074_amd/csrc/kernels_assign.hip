@@ -1205,28 +1205,17 @@ hipError_t launch_assign_batched(const AssignArgs* args, int arg_stride, int arg
 }
 
 hipError_t launch_assign_chunk(const AssignArgs& A, int mode, hipStream_t s) {
-  const bool half = A.CT16 != nullptr;
+  if (A.CT16 != nullptr) return hipErrorInvalidValue;  // FP32 centre copy only
   int64_t blocks = (A.n_rows + 3) / 4;  // one row per wave
   if (blocks > kMaxGridBlocks) blocks = kMaxGridBlocks;
   if (blocks < 1) blocks = 1;
   const dim3 grid((unsigned)blocks), block(kBlock);
-  if (half) {
-    if (mode == kModeFit)
-      hipLaunchKernelGGL((k_assign_csr<64, 1, 8, kModeFit, true, true>), grid, block, 0, s, A);
-    else if (mode == kModeHamerly)
-      hipLaunchKernelGGL((k_assign_csr<64, 1, 8, kModeHamerly, true, true>), grid, block, 0, s,
-                         A);
-    else
-      return hipErrorInvalidValue;
-  } else {
-    if (mode == kModeFit)
-      hipLaunchKernelGGL((k_assign_csr<64, 1, 4, kModeFit, true, true>), grid, block, 0, s, A);
-    else if (mode == kModeHamerly)
-      hipLaunchKernelGGL((k_assign_csr<64, 1, 4, kModeHamerly, true, true>), grid, block, 0, s,
-                         A);
-    else
-      return hipErrorInvalidValue;
-  }
+  if (mode == kModeFit)
+    hipLaunchKernelGGL((k_assign_csr<64, 1, 4, kModeFit, true, true>), grid, block, 0, s, A);
+  else if (mode == kModeHamerly)
+    hipLaunchKernelGGL((k_assign_csr<64, 1, 4, kModeHamerly, true, true>), grid, block, 0, s, A);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

@@ -241,15 +241,14 @@ int make_plan(const skm_matrix* X, int32_t k, int32_t variant, int32_t precision
   P->maxeta = take(kCounterSlots * sizeof(float));
   P->initnorm = take(kk * sizeof(double));
   P->vbad = take(sizeof(unsigned long long));
-  // Lloyd and the Hamerly variants walk wide centre copies a chunk of 1 KB
-  // per centre row at a time: the walk streams those fastest, and a chunk's
-  // slice of the copy is a quarter (FP32, k <= 1024) of the whole, which the
-  // last-level cache holds where the whole does not
-  const int chunk = P->half ? kChunkF16 : kChunkF32;
+  // Lloyd and the Hamerly variants walk wide FP32 centre copies a chunk of
+  // 1 KB per centre row at a time: the walk streams those fastest, and a
+  // chunk's slice of the copy is at most a quarter of it (k <= 1024), which
+  // the last-level cache holds where the whole copy does not
   if ((variant == SKM_LLOYD || variant == SKM_HAMERLY || variant == SKM_SIMP_HAMERLY) &&
-      g.kp > chunk) {
-    P->chunk = chunk;
-    P->nq = (k + chunk - 1) / chunk;
+      !P->half && g.kp > kChunkF32) {
+    P->chunk = kChunkF32;
+    P->nq = (k + kChunkF32 - 1) / kChunkF32;
     P->rs = take(n * sizeof(RowRun));
   }
   P->total = cur;

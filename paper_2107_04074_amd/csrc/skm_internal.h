@@ -177,10 +177,9 @@ struct AssignArgs {
   RowRun* rs;
 };
 constexpr int kYYGroup = 32;  // centres per Yin-Yang group
-// Centres per launch of a chunked walk: 1 KB of every centre row, which is
-// what the row walk streams fastest (FP32 copy 256, FP16 copy 512).
+// Centres per launch of a chunked walk (FP32 centre copy): 1 KB of every
+// centre row, which is what the row walk streams fastest.
 constexpr int kChunkF32 = 256;
-constexpr int kChunkF16 = 512;
 
 
 struct DenseSimArgs {
@@ -369,8 +368,8 @@ hipError_t launch_dense_prep(const float* X, int64_t ldx, int64_t n, int64_t d, 
 
 // ---- launchers (kernels_assign.hip) ----
 hipError_t launch_assign(const AssignArgs& A, int mode, hipStream_t s);
-// One launch of a chunked walk (fit or Hamerly mode; A.j0, A.chunk_last and
-// A.rs set; FP32 copy: chunks of kChunkF32, FP16 copy: kChunkF16).
+// One launch of a chunked walk (fit or Hamerly mode, FP32 centre copy,
+// chunks of kChunkF32 centres; A.j0, A.chunk_last and A.rs set).
 hipError_t launch_assign_chunk(const AssignArgs& A, int mode, hipStream_t s);
 
 
