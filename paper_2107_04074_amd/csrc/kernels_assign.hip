@@ -289,6 +289,7 @@ struct RowIn {
   int prev;
   float l, u, eta;
   int run;  // chunked walks after the first chunk: the row is walked this step
+  uint64_t surv0, surv1;  // chunked Yin-Yang walks: the groups left to walk
 };
 
 // Hamerly mode prologue (Sections 5.3 / 5.4): Eq. (6) for l(i), the guarded
@@ -502,29 +503,31 @@ __device__ __forceinline__ bool elkan_prologue(const AssignArgs& A, int64_t row,
 }
 
 // After a walk: every walked Yin-Yang group's bound becomes the largest
-// computed similarity of the group's centres other than the new assignment
-// (plus the error band, rounded up); -1 for a group with no other centre.
-// A group of kYYGroup centres is kYYGroup / VEC consecutive lanes of one
-// chunk; need has bit r set when chunk r was walked.
+// computed similarity of the group's centres other than `abest` (plus the
+// error band, rounded up); -1 for a group with no other centre.  A group of
+// kYYGroup centres is kYYGroup / VEC consecutive lanes of one chunk; need
+// has bit r set when chunk r was walked.  The lanes hold centres cbase ...
+// cbase + kc - 1 (a chunked walk's slice; cbase a multiple of kYYGroup).
 template <int G, int R, int VEC>
 __device__ __forceinline__ void write_group_bounds(const AssignArgs& A, int64_t row,
                                                    const float4 (&acc)[R * VEC / 4], int gl,
                                                    int abest, double rho32, bool writer,
-                                                   unsigned need) {
+                                                   unsigned need, int cbase = 0, int kc = -1) {
   constexpr int SEG = (kYYGroup / VEC < G) ? kYYGroup / VEC : G;  // lanes per group
+  if (kc < 0) kc = A.k;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     float m = -INFINITY;
 #pragma unroll
     for (int q = 0; q < VEC; ++q) {
       const int j = VEC * (gl + G * r) + q;
-      if (j < A.k && j != abest) m = fmaxf(m, f4get(acc[(r * VEC + q) >> 2], q & 3));
+      if (j < kc && cbase + j != abest) m = fmaxf(m, f4get(acc[(r * VEC + q) >> 2], q & 3));
     }
 #pragma unroll
     for (int off = SEG / 2; off >= 1; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, SEG));
     const int j0 = VEC * (gl + G * r);
-    if (writer && (gl % SEG) == 0 && j0 < A.k && ((need >> r) & 1u)) {
-      const int f = j0 / kYYGroup;
+    if (writer && (gl % SEG) == 0 && j0 < kc && ((need >> r) & 1u)) {
+      const int f = (cbase + j0) / kYYGroup;
       const float val = (m == -INFINITY) ? -1.0f
                                          : __double2float_ru(fmin((double)m + rho32, 1.0));
       A.uy[(size_t)row * A.ng + f] = val;
@@ -600,9 +603,15 @@ constexpr int assign_min_waves() {
 template <int G, int R, int VEC, int MODE, bool WAVE_ROW, bool CHUNK = false>
 __device__ __forceinline__ void assign_rows(const AssignArgs& A, int64_t row_base,
                                             int64_t row_end, int64_t rstride, int slot) {
-  static_assert(!CHUNK || (WAVE_ROW && G == 64 && R == 1 &&
-                           (MODE == kModeFit || MODE == kModeHamerly)),
-                "chunked walks: one chunk of 64 x VEC centres per lane row, fit/Hamerly");
+  static_assert(!CHUNK || (WAVE_ROW && G == 64 && R == 1 && VEC == 4 &&
+                           (MODE == kModeFit || MODE == kModeHamerly || MODE == kModeYinYang)),
+                "chunked walks: one chunk of 64 x 4 centres per lane row, fit/Hamerly/Yin-Yang");
+  // chunked Yin-Yang: the first chunk's prologue leaves a set of groups to
+  // walk (kept in the row's running record); every chunk walks its own
+  constexpr bool kChunkYY = CHUNK && MODE == kModeYinYang;
+  // chunked walks that may carry Yin-Yang group bounds (the Yin-Yang step
+  // and the fit's plain walk)
+  constexpr bool kChunkGroups = CHUNK && (MODE == kModeYinYang || MODE == kModeFit);
   static_assert(VEC == 4 || (VEC == 8 && WAVE_ROW), "FP16 centres need the wave layout");
   constexpr int NACC = R * VEC / 4;
   const int gl = threadIdx.x & (G - 1);
@@ -656,15 +665,20 @@ __device__ __forceinline__ void assign_rows(const AssignArgs& A, int64_t row_bas
     }
   };
   auto load_in = [&](int64_t r) -> RowIn {
-    RowIn x{-1, 0.f, 0.f, 0.f, 1};
+    RowIn x{-1, 0.f, 0.f, 0.f, 1, ~0ull, ~0ull};
     if (A.read_prev) x.prev = A.a[r];
     if constexpr (kBounded) x.l = A.l[r];
     if constexpr (MODE == kModeHamerly) x.u = A.u[r];
     if constexpr (MODE != kModeAssign) x.eta = A.eta[r];
     if constexpr (CHUNK) x.run = j0 > 0 ? (A.rs[r].flags & 1) : 1;
+    if constexpr (kChunkYY)
+      if (j0 > 0) {
+        x.surv0 = A.rs[r].surv0;
+        x.surv1 = A.rs[r].surv1;
+      }
     return x;
   };
-  RowIn nin{-1, 0.f, 0.f, 0.f, 1};
+  RowIn nin{-1, 0.f, 0.f, 0.f, 1, ~0ull, ~0ull};
   if constexpr (WAVE_ROW) {
     const int64_t r0 = row_base + gib;
     if (r0 < row_end) {
@@ -716,15 +730,17 @@ __device__ __forceinline__ void assign_rows(const AssignArgs& A, int64_t row_bas
         continue;
       }
     }
+    // groups (bit f) a Yin-Yang walk visits this step
+    uint64_t surv0 = ri.surv0, surv1 = ri.surv1;
     if constexpr (kBounded) if (!CHUNK || j0 == 0) {
-      uint64_t surv0 = ~0ull, surv1 = ~0ull;
       const bool skip =
           MODE == kModeHamerly
               ? hamerly_prologue<G>(A, row, ri, beg, end, gl, leader, tighten, my_tight,
                                     my_saved)
           : MODE == kModeYinYang
-              ? yinyang_prologue<G, kPartial>(A, row, ri, beg, end, gl, leader, tighten,
-                                              my_tight, my_saved, surv0, surv1)
+              ? yinyang_prologue<G, kPartial || kChunkYY>(A, row, ri, beg, end, gl, leader,
+                                                          tighten, my_tight, my_saved, surv0,
+                                                          surv1)
               : elkan_prologue<G, R, VEC, kPartial>(A, row, ri, beg, end, gl, leader, tighten,
                                                     lead_sub, my_tight, my_saved, need);
       if (skip) {
@@ -746,22 +762,44 @@ __device__ __forceinline__ void assign_rows(const AssignArgs& A, int64_t row_bas
         }
       }
     }
+    if constexpr (kChunkYY) {
+      // this chunk's lanes: the groups the filters left (the assigned
+      // centre's group among them)
+      need = 0u;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int jl = VEC * (gl + G * r);
+        const int f = (j0 + jl) / kYYGroup;
+        const bool walk =
+            jl < k && (((f < 64 ? (surv0 >> f) : (surv1 >> (f - 64))) & 1ull) != 0ull);
+        need |= walk ? (1u << r) : 0u;
+      }
+    }
 
     float4 acc[NACC];
-    float nrm2;
+    float nrm2 = 0.f;
+    // false: no group of this chunk is walked (chunked Yin-Yang); the row's
+    // running result is carried on unchanged
+    bool walked = true;
+    if constexpr (kChunkYY) walked = group_or<G>(need) != 0u;
     if constexpr (WAVE_ROW) {
       const char* ctb = VEC == 8 ? static_cast<const char*>(A.CT16)
                                  : reinterpret_cast<const char*>(A.CT);
       if constexpr (CHUNK) ctb += (size_t)j0 * (VEC == 8 ? 2 : 4);
-      nrm2 = row_walk<G, R, VEC, kPartial>(A.ci, A.v, beg, end, c0, x0, ctb, A.kp, wl, acc,
-                                           need);
+      if (walked) {
+        nrm2 = row_walk<G, R, VEC, kPartial || kChunkYY>(A.ci, A.v, beg, end, c0, x0, ctb,
+                                                         A.kp, wl, acc, need);
+      } else {
+#pragma unroll
+        for (int q = 0; q < NACC; ++q) acc[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+      }
       next_window();
     } else {
       nrm2 = row_sims<G, R, false>(A.ci, A.v, beg, end, CT4, kp4, gl, ~0u, acc);
     }
     // similarities computed for this row (wave-uniform)
     unsigned long long row_sims_done = (unsigned long long)k;
-    if constexpr (kPartial) {
+    if constexpr (kPartial || kChunkYY) {
       int mine = 0;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
@@ -794,8 +832,9 @@ __device__ __forceinline__ void assign_rows(const AssignArgs& A, int64_t row_bas
 
     // rigorous bound on |fl32 sim - <x, c>| for any summation order: (m+1)
     // roundings of the FMA chain plus the rounding of the centre copy,
-    // scaled by |x| |c|
-    const double nx = sqrt((double)nrm2) * 1.01 + 1e-30;
+    // scaled by |x| |c| (|x| <= 1 + eta where the walk measured no norm)
+    const double nx = walked ? sqrt((double)nrm2) * 1.01 + 1e-30
+                             : (1.0 + (double)ri.eta) * 1.01 + 1e-30;
     const double eps = VEC == 8 ? fp16_eps((double)b, m, nx, A.delta_c, *A.negflag == 0)
                                 : (double)(m + 3) * kU32 * nx;
 
@@ -858,6 +897,22 @@ __device__ __forceinline__ void assign_rows(const AssignArgs& A, int64_t row_bas
       int jw = bj;
       int fw = (k > 1 && (double)b - (double)s2 <= 2.0 * eps) ? 8 : 0;
       bool any = false;
+      // this chunk's winner is the row's running winner after the merge
+      bool cand_running = true;
+      // Yin-Yang group bounds (the fit's plain walk too): every group bound
+      // must cover each of its centres other than the final assignment.  A
+      // chunk's groups leave out the chunk's winner only while it is the
+      // running winner and exactly decided; a running winner that later
+      // loses is added to its group's bound here.
+      const double eta_r = (double)ri.eta;
+      const double slack_r = 1.01 * (eta_r + A.delta_c);
+      auto raise_group = [&](int j, double v, double e) {
+        if (kChunkGroups && A.uy != nullptr && leader && j >= 0 && j < A.k) {
+          float* p = A.uy + (size_t)row * A.ng + j / kYYGroup;
+          const double hi = v + e + (double)(m + 2) * kU64 * nx + slack_r + 1e-12;
+          *p = fmaxf(*p, __double2float_ru(fmin(hi, 1.0)));
+        }
+      };
       if (j0 > 0) {
         const RowRun rr = A.rs[row];
         double vc = rr.best, ec = rr.err;
@@ -865,8 +920,16 @@ __device__ __forceinline__ void assign_rows(const AssignArgs& A, int64_t row_bas
         any = (fc & 4) != 0;
         emax = fmax(emax, rr.errmax);
         sec = fmax(sec, rr.second);
+        // A chunk that walked no centre (chunked Yin-Yang: every group of
+        // the chunk filtered out) has no candidate (index INT_MAX), and the
+        // running result has none until some chunk walked: an empty side
+        // never takes part in a comparison.
         bool win;
-        if (vw - ew > vc + ec + 1e-12) {
+        if (!walked) {
+          win = false;
+        } else if (jc == INT_MAX) {
+          win = true;
+        } else if (vw - ew > vc + ec + 1e-12) {
           win = true;
         } else if (vc - ec > vw + ew + 1e-12) {
           win = false;
@@ -880,12 +943,14 @@ __device__ __forceinline__ void assign_rows(const AssignArgs& A, int64_t row_bas
         }
         if (win) {
           sec = fmax(sec, vc);
+          raise_group(jc, vc, ec);
         } else {
           sec = fmax(sec, vw);
           vw = vc;
           ew = ec;
           jw = jc;
           fw = fc;
+          cand_running = false;
         }
       }
       if (A.chunk_last && (fw & 8)) {
@@ -893,6 +958,11 @@ __device__ __forceinline__ void assign_rows(const AssignArgs& A, int64_t row_bas
         fw = 2;
         ew = 0.0;
         any = true;
+      }
+      if (kChunkGroups && A.uy != nullptr && walked) {
+        const int excl = (cand_running && !(fw & 8)) ? jw : -1;
+        write_group_bounds<G, R, VEC>(A, row, acc, gl, excl, eps + slack_r + 1e-12, lead_sub,
+                                      need, j0, k);
       }
       if (!A.chunk_last) {
         if (leader) {
@@ -903,6 +973,8 @@ __device__ __forceinline__ void assign_rows(const AssignArgs& A, int64_t row_bas
           o.errmax = emax;
           o.bj = jw;
           o.flags = 1 | (fw & 10) | (any ? 4 : 0);
+          o.surv0 = surv0;
+          o.surv1 = surv1;
           A.rs[row] = o;
         }
       } else if (leader) {
@@ -911,6 +983,9 @@ __device__ __forceinline__ void assign_rows(const AssignArgs& A, int64_t row_bas
         const double slack = 1.01 * (eta + A.delta_c);
         const double rho32 = emax + slack + 1e-12;
         const double rho64 = (double)(m + 2) * kU64 * nx + slack + 1e-15;
+        // jw is a centre: the chunk holding the previous assignment's group
+        // is always walked (the guard only keeps the store in range)
+        jw = (jw >= 0 && jw < A.k) ? jw : (prev >= 0 ? prev : 0);
         A.a[row] = jw;
         my_changed += (jw != prev) ? 1ull : 0ull;
         if (A.l) A.l[row] = __double2float_rd(fmax(xw ? vw - rho64 : vw - rho32, -1.0));
@@ -1214,6 +1289,8 @@ hipError_t launch_assign_chunk(const AssignArgs& A, int mode, hipStream_t s) {
     hipLaunchKernelGGL((k_assign_csr<64, 1, 4, kModeFit, true, true>), grid, block, 0, s, A);
   else if (mode == kModeHamerly)
     hipLaunchKernelGGL((k_assign_csr<64, 1, 4, kModeHamerly, true, true>), grid, block, 0, s, A);
+  else if (mode == kModeYinYang)
+    hipLaunchKernelGGL((k_assign_csr<64, 1, 4, kModeYinYang, true, true>), grid, block, 0, s, A);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

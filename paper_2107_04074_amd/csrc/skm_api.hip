@@ -241,11 +241,12 @@ int make_plan(const skm_matrix* X, int32_t k, int32_t variant, int32_t precision
   P->maxeta = take(kCounterSlots * sizeof(float));
   P->initnorm = take(kk * sizeof(double));
   P->vbad = take(sizeof(unsigned long long));
-  // Lloyd and the Hamerly variants walk wide FP32 centre copies a chunk of
-  // 1 KB per centre row at a time: the walk streams those fastest, and a
-  // chunk's slice of the copy is at most a quarter of it (k <= 1024), which
-  // the last-level cache holds where the whole copy does not
-  if ((variant == SKM_LLOYD || variant == SKM_HAMERLY || variant == SKM_SIMP_HAMERLY) &&
+  // Lloyd, the Hamerly variants and Yin-Yang walk wide FP32 centre copies a
+  // chunk of 1 KB per centre row at a time: the walk streams those fastest,
+  // and a chunk's slice of the copy is at most a quarter of it (k <= 1024),
+  // which the last-level cache holds where the whole copy does not
+  if ((variant == SKM_LLOYD || variant == SKM_HAMERLY || variant == SKM_SIMP_HAMERLY ||
+       variant == SKM_YINYANG) &&
       !P->half && g.kp > kChunkF32) {
     P->chunk = kChunkF32;
     P->nq = (k + kChunkF32 - 1) / kChunkF32;

@@ -115,12 +115,15 @@ enum AssignMode {
 // centres walked a chunk at a time): the best value so far (the canonical
 // FP64 value when exact, else the FP32 one with error bound err), the
 // largest value of every other centre seen so far (FP32 or FP64), the largest
-// FP32 error bound of any chunk, the best centre, and flags (bit 0: the row
+// FP32 error bound of any chunk, the best centre, flags (bit 0: the row
 // is walked in this step; bit 1: best is exact; bit 2: some FP64
-// re-decision was made for the row).
+// re-decision was made for the row; bit 3: best is the FP32 winner of a
+// chunk whose top two lie within their error bounds), and for Yin-Yang the
+// groups (bit f of surv0, then surv1) that this step's filters left to walk.
 struct RowRun {
   double best, second, err, errmax;
   int32_t bj, flags;
+  uint64_t surv0, surv1;
 };
 
 struct AssignArgs {
@@ -368,8 +371,8 @@ hipError_t launch_dense_prep(const float* X, int64_t ldx, int64_t n, int64_t d, 
 
 // ---- launchers (kernels_assign.hip) ----
 hipError_t launch_assign(const AssignArgs& A, int mode, hipStream_t s);
-// One launch of a chunked walk (fit or Hamerly mode, FP32 centre copy,
-// chunks of kChunkF32 centres; A.j0, A.chunk_last and A.rs set).
+// One launch of a chunked walk (fit, Hamerly or Yin-Yang mode, FP32 centre
+// copy, chunks of kChunkF32 centres; A.j0, A.chunk_last and A.rs set).
 hipError_t launch_assign_chunk(const AssignArgs& A, int mode, hipStream_t s);
 
 
