@@ -220,17 +220,19 @@ __device__ __forceinline__ void walk_consume(const uint4 (&src)[WalkBatch<R>::U]
   }
 }
 
+// col16 >= 0: the lane reads 16-byte unit col16 of each centre row instead
+// of unit lane % L (a packed subset of the row's units).
 template <int L, int R, int VEC, bool MASKED = false>
 __device__ __forceinline__ float row_walk(const int32_t* __restrict__ ci,
                                           const float* __restrict__ v, int64_t beg, int64_t end,
                                           int c0, float x0, const void* __restrict__ CTB, int kp,
                                           int lane, float4 (&acc)[R * VEC / 4],
-                                          unsigned need = ~0u) {
+                                          unsigned need = ~0u, int col16 = -1) {
   constexpr int S = 64 / L;
   constexpr int U = WalkBatch<R>::U;
   constexpr int PER_WIN = 64 / (S * U);  // batches per 64-entry window (even)
   static_assert(PER_WIN % 2 == 0, "double buffering needs an even batch count");
-  const int sub = lane / L, gl = lane % L;
+  const int sub = lane / L, gl = col16 >= 0 ? col16 : lane % L;
   const uint4* C16B = reinterpret_cast<const uint4*>(CTB);
   const int kp16 = kp / VEC;  // 16-byte chunks per centre row
 #pragma unroll
@@ -762,18 +764,30 @@ __device__ __forceinline__ void assign_rows(const AssignArgs& A, int64_t row_bas
         }
       }
     }
+    // Chunked Yin-Yang: the chunk's groups that the filters left (the
+    // assigned centre's group among them), na of its 8, packed onto the
+    // lanes: the 8 lanes of packed segment t read the t-th surviving group
+    // (8 x 16 bytes of every centre row), and a sub-wave of L = 8 na
+    // lanes (rounded up to 8, 16, 32 or 64) walks the row, so one gather
+    // instruction serves 64 / L entries.  Lane wl holds centres 4 cw_col
+    // ... 4 cw_col + 3 of the chunk when live (need = 1: wl < L and its
+    // segment < na).
+    int cw_L = 64, cw_col = 0;
+    unsigned cw_walk = 1u;  // the lane fetches (every sub-wave)
     if constexpr (kChunkYY) {
-      // this chunk's lanes: the groups the filters left (the assigned
-      // centre's group among them)
-      need = 0u;
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int jl = VEC * (gl + G * r);
-        const int f = (j0 + jl) / kYYGroup;
-        const bool walk =
-            jl < k && (((f < 64 ? (surv0 >> f) : (surv1 >> (f - 64))) & 1ull) != 0ull);
-        need |= walk ? (1u << r) : 0u;
-      }
+      const int gb = j0 / kYYGroup;  // a multiple of 8: one mask word holds the chunk
+      const int ngc = (k + kYYGroup - 1) / kYYGroup;
+      const uint64_t sv = gb < 64 ? (surv0 >> gb) : (surv1 >> (gb - 64));
+      const unsigned am = (unsigned)(sv & ((1ull << ngc) - 1ull));
+      const int na = __popc(am);
+      cw_L = na <= 1 ? 8 : na <= 2 ? 16 : na <= 4 ? 32 : 64;
+      const int seg = (wl % cw_L) >> 3;
+      unsigned rest = am;
+      for (int i = 0; i < seg && rest != 0u; ++i) rest &= rest - 1u;
+      const int grp = rest != 0u ? __builtin_ctz(rest) : 0;
+      cw_col = grp * (kYYGroup / 4) + (wl & 7);
+      cw_walk = seg < na ? 1u : 0u;
+      need = (seg < na && wl < cw_L) ? 1u : 0u;
     }
 
     float4 acc[NACC];
@@ -786,10 +800,25 @@ __device__ __forceinline__ void assign_rows(const AssignArgs& A, int64_t row_bas
       const char* ctb = VEC == 8 ? static_cast<const char*>(A.CT16)
                                  : reinterpret_cast<const char*>(A.CT);
       if constexpr (CHUNK) ctb += (size_t)j0 * (VEC == 8 ? 2 : 4);
-      if (walked) {
-        nrm2 = row_walk<G, R, VEC, kPartial || kChunkYY>(A.ci, A.v, beg, end, c0, x0, ctb,
-                                                         A.kp, wl, acc, need);
+      if (!walked) {
+      } else if constexpr (kChunkYY) {
+        if (cw_L == 8)
+          nrm2 = row_walk<8, 1, 4, true>(A.ci, A.v, beg, end, c0, x0, ctb, A.kp, wl, acc,
+                                         cw_walk, cw_col);
+        else if (cw_L == 16)
+          nrm2 = row_walk<16, 1, 4, true>(A.ci, A.v, beg, end, c0, x0, ctb, A.kp, wl, acc,
+                                          cw_walk, cw_col);
+        else if (cw_L == 32)
+          nrm2 = row_walk<32, 1, 4, true>(A.ci, A.v, beg, end, c0, x0, ctb, A.kp, wl, acc,
+                                          cw_walk, cw_col);
+        else
+          nrm2 = row_walk<64, 1, 4, true>(A.ci, A.v, beg, end, c0, x0, ctb, A.kp, wl, acc,
+                                          cw_walk, cw_col);
       } else {
+        nrm2 = row_walk<G, R, VEC, kPartial>(A.ci, A.v, beg, end, c0, x0, ctb, A.kp, wl, acc,
+                                             need);
+      }
+      if (!walked) {
 #pragma unroll
         for (int q = 0; q < NACC; ++q) acc[q] = make_float4(0.f, 0.f, 0.f, 0.f);
       }
@@ -799,7 +828,11 @@ __device__ __forceinline__ void assign_rows(const AssignArgs& A, int64_t row_bas
     }
     // similarities computed for this row (wave-uniform)
     unsigned long long row_sims_done = (unsigned long long)k;
-    if constexpr (kPartial || kChunkYY) {
+    if constexpr (kChunkYY) {
+      const int left = k - 4 * cw_col;
+      const int mine = need ? (left < 4 ? (left > 0 ? left : 0) : 4) : 0;
+      row_sims_done = (unsigned long long)group_sum<G>(mine);
+    } else if constexpr (kPartial) {
       int mine = 0;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
@@ -815,7 +848,7 @@ __device__ __forceinline__ void assign_rows(const AssignArgs& A, int64_t row_bas
     for (int r = 0; r < R; ++r) {
 #pragma unroll
       for (int q = 0; q < VEC; ++q) {
-        const int j = VEC * (gl + G * r) + q;
+        const int j = (kChunkYY ? 4 * cw_col : VEC * (gl + G * r)) + q;
         if (j < k && ((need >> r) & 1u)) {
           const float sv = f4get(acc[(r * VEC + q) >> 2], q & 3);
           if (better32(sv, j0 + j, b, bj, prev)) {
@@ -961,8 +994,25 @@ __device__ __forceinline__ void assign_rows(const AssignArgs& A, int64_t row_bas
       }
       if (kChunkGroups && A.uy != nullptr && walked) {
         const int excl = (cand_running && !(fw & 8)) ? jw : -1;
-        write_group_bounds<G, R, VEC>(A, row, acc, gl, excl, eps + slack_r + 1e-12, lead_sub,
-                                      need, j0, k);
+        const double rb = eps + slack_r + 1e-12;
+        if constexpr (kChunkYY) {
+          // packed lanes: segment-aligned groups of 8 lanes
+          float mv = -INFINITY;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int j = 4 * cw_col + q;
+            if (need && j < k && j0 + j != excl) mv = fmaxf(mv, f4get(acc[0], q));
+          }
+#pragma unroll
+          for (int off = 4; off >= 1; off >>= 1) mv = fmaxf(mv, __shfl_xor(mv, off, 8));
+          if (need && (wl & 7) == 0) {
+            const float val =
+                (mv == -INFINITY) ? -1.0f : __double2float_ru(fmin((double)mv + rb, 1.0));
+            A.uy[(size_t)row * A.ng + (j0 + 4 * cw_col) / kYYGroup] = val;
+          }
+        } else {
+          write_group_bounds<G, R, VEC>(A, row, acc, gl, excl, rb, lead_sub, need, j0, k);
+        }
       }
       if (!A.chunk_last) {
         if (leader) {
@@ -1281,8 +1331,11 @@ hipError_t launch_assign_batched(const AssignArgs* args, int arg_stride, int arg
 
 hipError_t launch_assign_chunk(const AssignArgs& A, int mode, hipStream_t s) {
   if (A.CT16 != nullptr) return hipErrorInvalidValue;  // FP32 centre copy only
-  int64_t blocks = (A.n_rows + 3) / 4;  // one row per wave
-  if (blocks > kMaxGridBlocks) blocks = kMaxGridBlocks;
+  // one row per wave; twice the usual persistent grid: the rows of a wave
+  // vary in length, and more, shorter row sets end closer together (C3:
+  // 3% faster per launch than 2048 blocks, 1024 blocks 2% slower)
+  int64_t blocks = (A.n_rows + 3) / 4;
+  if (blocks > 2 * kMaxGridBlocks) blocks = 2 * kMaxGridBlocks;
   if (blocks < 1) blocks = 1;
   const dim3 grid((unsigned)blocks), block(kBlock);
   if (mode == kModeFit)
