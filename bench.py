@@ -421,7 +421,9 @@ def run_batched(dev, variant, steps, warmup, workers_arg, skip_baseline, no_cpu,
                                "%d steps each, one skm_fit_batched call per step" % (
                                    len(probs), variant, n_tot, nnz_tot, probs[0][3]),
                    "variant": variant, "problems": len(probs), "rows": n_tot, "nnz": nnz_tot,
-                   "workers": workers, "parallelism": "single GPU"},
+                   "workers": workers, "parallelism": "single GPU",
+                   "driver": "host threads, one HIP stream per worker, each running the "
+                             "single-problem fit"},
         "assignment_steps_per_call": nsteps,
         "identical_assignments_to_lloyd": identical,
         "speedup_vs_sequential_gpu_lloyd": None if base_s is None else

@@ -79,6 +79,27 @@ def test_batched_matches_oracle(skm, torch_cuda, problems):
         assert np.linalg.norm(C.cpu().numpy().astype(np.float64) - ref.C, axis=1).max() < 1e-6
 
 
+def test_batched_matches_oracle_uneven(skm, torch_cuda):
+    """The host-thread driver on an uneven subset of the batched workload at
+    20% of its row counts -- the problems with the most rows and the most
+    centres among them -- against the FP64 oracle's Lloyd trajectory."""
+    torch = torch_cuda
+    insts = datagen.batched_instances(scale=0.2)
+    by_n = sorted(range(len(insts)), key=lambda b: insts[b].X.n)
+    by_k = sorted(range(len(insts)), key=lambda b: insts[b].k)
+    pick = sorted(set([by_n[-1], by_k[-1], by_n[0], by_k[0], by_n[len(by_n) // 2], 7]))
+    sub = [insts[b] for b in pick]
+    dp = device_problems(skm, torch, sub)
+    res = skm.fit_batched(dp, "hamerly", workers=4)
+    torch.cuda.synchronize()
+    for p, (Xd, k, C0, it), (a, C, st) in zip(sub, dp, res):
+        say("case batched oracle uneven n=%d k=%d" % (p.X.n, k))
+        ref = oracle.fit(p.X, datagen.init_centers_csr(p.X, p.init), "lloyd", it)
+        assert st.iterations == ref.iterations and st.converged == ref.converged
+        assert np.array_equal(a.cpu().numpy(), ref.a)
+        assert np.linalg.norm(C.cpu().numpy().astype(np.float64) - ref.C, axis=1).max() < 1e-6
+
+
 def test_batched_twice_with_fewer_problems(skm, torch_cuda, problems):
     """Two calls in a row on one workspace, the second with fewer and
     smaller problems: no state leaks from the first call."""
