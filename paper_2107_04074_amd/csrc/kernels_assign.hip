@@ -504,6 +504,86 @@ __device__ __forceinline__ bool elkan_prologue(const AssignArgs& A, int64_t row,
   return !alive;
 }
 
+// Elkan prologue of a chunked walk (first launch of a step, one row per
+// wave): the same tests as elkan_prologue over all kp / 256 slices of the
+// row's pair bounds.  Every pair bound is updated with its centre's movement
+// (guarded Eq. (7)) and stored; a walked row then gets exact bounds for the
+// centres it walks.  The survivors go to A.umask (bit q of word t: unit
+// 64 t + q, i.e. centres 256 t + 4 q ... + 3, holds a centre whose tests
+// failed; the assigned centre's unit is always set); word 0 is also
+// returned in w0.  Returns true when the row needs no walk (l(i) stored).
+__device__ __forceinline__ bool elkan_chunk_prologue(const AssignArgs& A, int64_t row,
+                                                     const RowIn& ri, int64_t beg, int64_t end,
+                                                     int gl, bool leader, int tighten,
+                                                     unsigned long long& tight,
+                                                     unsigned long long& saved, uint64_t& w0) {
+  const int k = A.k;
+  const int prev = ri.prev;
+  const int m = (int)(end - beg);
+  const double eta = (double)ri.eta;
+  const double slack = 1.01 * (eta + A.delta_c);
+  const double rho32 = (double)(m + 3) * kU32 * (1.0 + eta) * 1.01 + slack + 1e-12;
+  const double mu = 4.0 * (double)(m + 2) * kU64 * (1.0 + eta) + 4.0 * A.delta_c + 1e-15;
+  double ld = lower_upd((double)ri.l, A.pc[prev], A.ps[prev]) - 4e-15;
+  float4* uer4 = reinterpret_cast<float4*>(A.ue + (size_t)row * A.kp);
+  const int nw = A.kp / kChunkF32;
+  uint64_t* um = A.umask + (size_t)row * nw;
+  // every pair bound updated with its centre's movement, kept in place
+  for (int t = 0; t < nw; ++t) {
+    const int jb = kChunkF32 * t + 4 * gl;
+    float4 uv = uer4[jb / 4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int j = jb + q;
+      if (j < k) {
+        const double nu = upper_upd((double)f4get(uv, q), A.pc[j], A.ps[j]) + 4e-15;
+        f4set(uv, q, __double2float_ru(fmin(nu, 1.0)));
+      }
+    }
+    uer4[jb / 4] = uv;
+  }
+  const double* Grow = A.Gm ? A.Gm + (size_t)prev * k : nullptr;
+  // the point test, then the pair tests of every unit (bounds read back
+  // from where this lane stored them); the leader stores the words
+  auto tests = [&](double lcur) -> bool {
+    const double M = lcur - mu;
+    const bool cc_ok = !A.simplified && Grow != nullptr && lcur > 0.0 && M > 0.0;
+    const double T = cc_ok ? cc_threshold(lcur, M) - 4e-15 : -3.0;
+    if (cc_ok && A.gmax[prev] <= T) return false;  // no other centre can win
+    bool any = false;
+    for (int t = 0; t < nw; ++t) {
+      const int jb = kChunkF32 * t + 4 * gl;
+      const float4 uv = uer4[jb / 4];
+      bool alive = false;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int j = jb + q;
+        if (j < k && j != prev) {
+          const bool by_u = (lcur - (double)f4get(uv, q)) >= mu;  // u(i, j) <= l(i)
+          const bool by_cc = cc_ok && (Grow[j] + A.delta_g <= T);  // cc(a, j) <= l(i)
+          alive = alive || (!by_u && !by_cc);
+        }
+      }
+      uint64_t w = __ballot(alive);
+      any = any || w != 0ull;
+      if (t == prev / kChunkF32) w |= 1ull << ((prev % kChunkF32) / 4);
+      if (t == 0) w0 = w;
+      if (leader) um[t] = w;
+    }
+    return any;
+  };
+  bool alive = tests(ld);
+  if (alive && tighten) {
+    const float s32 = group_col_dot32<64>(A.ci, A.v, beg, end, A.CT, A.kp, prev, gl);
+    ld = fmax(ld, (double)s32 - rho32);
+    if (leader) tight += 1;
+    alive = tests(ld);
+    if (!alive && leader) saved += 1;
+  }
+  if (!alive && leader) A.l[row] = __double2float_rd(fmax(ld, -1.0));
+  return !alive;
+}
+
 // After a walk: every walked Yin-Yang group's bound becomes the largest
 // computed similarity of the group's centres other than `abest` (plus the
 // error band, rounded up); -1 for a group with no other centre.  A group of
@@ -606,14 +686,22 @@ template <int G, int R, int VEC, int MODE, bool WAVE_ROW, bool CHUNK = false>
 __device__ __forceinline__ void assign_rows(const AssignArgs& A, int64_t row_base,
                                             int64_t row_end, int64_t rstride, int slot) {
   static_assert(!CHUNK || (WAVE_ROW && G == 64 && R == 1 && VEC == 4 &&
-                           (MODE == kModeFit || MODE == kModeHamerly || MODE == kModeYinYang)),
-                "chunked walks: one chunk of 64 x 4 centres per lane row, fit/Hamerly/Yin-Yang");
+                           (MODE == kModeFit || MODE == kModeHamerly || MODE == kModeYinYang ||
+                            MODE == kModeElkan || MODE == kModeFitElkanInit)),
+                "chunked walks: one chunk of 64 x 4 centres per lane row");
   // chunked Yin-Yang: the first chunk's prologue leaves a set of groups to
   // walk (kept in the row's running record); every chunk walks its own
   constexpr bool kChunkYY = CHUNK && MODE == kModeYinYang;
   // chunked walks that may carry Yin-Yang group bounds (the Yin-Yang step
   // and the fit's plain walk)
   constexpr bool kChunkGroups = CHUNK && (MODE == kModeYinYang || MODE == kModeFit);
+  // chunked Elkan: the first launch's prologue stores which 4-centre units
+  // of each 256-centre slice hold a surviving centre; every launch packs its
+  // slice's surviving units onto the first lanes of a sub-wave
+  constexpr bool kChunkEl = CHUNK && MODE == kModeElkan;
+  // chunked walks that store exact Elkan pair bounds for what they walk
+  constexpr bool kChunkPairs = CHUNK && (MODE == kModeElkan || MODE == kModeFitElkanInit);
+  constexpr bool kPacked = kChunkYY || kChunkEl;
   static_assert(VEC == 4 || (VEC == 8 && WAVE_ROW), "FP16 centres need the wave layout");
   constexpr int NACC = R * VEC / 4;
   const int gl = threadIdx.x & (G - 1);
@@ -734,17 +822,23 @@ __device__ __forceinline__ void assign_rows(const AssignArgs& A, int64_t row_bas
     }
     // groups (bit f) a Yin-Yang walk visits this step
     uint64_t surv0 = ri.surv0, surv1 = ri.surv1;
+    // chunked Elkan: surviving units of the first slice (first launch)
+    uint64_t ew0 = 0ull;
     if constexpr (kBounded) if (!CHUNK || j0 == 0) {
-      const bool skip =
-          MODE == kModeHamerly
-              ? hamerly_prologue<G>(A, row, ri, beg, end, gl, leader, tighten, my_tight,
-                                    my_saved)
-          : MODE == kModeYinYang
-              ? yinyang_prologue<G, kPartial || kChunkYY>(A, row, ri, beg, end, gl, leader,
-                                                          tighten, my_tight, my_saved, surv0,
-                                                          surv1)
-              : elkan_prologue<G, R, VEC, kPartial>(A, row, ri, beg, end, gl, leader, tighten,
-                                                    lead_sub, my_tight, my_saved, need);
+      bool skip;
+      if constexpr (MODE == kModeHamerly)
+        skip = hamerly_prologue<G>(A, row, ri, beg, end, gl, leader, tighten, my_tight,
+                                   my_saved);
+      else if constexpr (MODE == kModeYinYang)
+        skip = yinyang_prologue<G, kPartial || kChunkYY>(A, row, ri, beg, end, gl, leader,
+                                                         tighten, my_tight, my_saved, surv0,
+                                                         surv1);
+      else if constexpr (kChunkEl)
+        skip = elkan_chunk_prologue(A, row, ri, beg, end, gl, leader, tighten, my_tight,
+                                    my_saved, ew0);
+      else
+        skip = elkan_prologue<G, R, VEC, kPartial>(A, row, ri, beg, end, gl, leader, tighten,
+                                                   lead_sub, my_tight, my_saved, need);
       if (skip) {
         if constexpr (CHUNK) {
           if (leader) A.rs[row].flags = 0;  // pruned: the later chunks skip the row
@@ -789,19 +883,38 @@ __device__ __forceinline__ void assign_rows(const AssignArgs& A, int64_t row_bas
       cw_walk = seg < na ? 1u : 0u;
       need = (seg < na && wl < cw_L) ? 1u : 0u;
     }
+    if constexpr (kChunkEl) {
+      // the slice's surviving 4-centre units (ns of 64) onto lanes 0 ... ns-1
+      // in unit order: lane wl's unit goes to slot (units set below it) when
+      // set, else to ns + (units clear below it) -- a permutation of the
+      // lanes; a sub-wave of L = 8, 16, 32 or 64 lanes walks them
+      const uint64_t w =
+          j0 == 0 ? ew0 : A.umask[(size_t)row * (A.kp / kChunkF32) + j0 / kChunkF32];
+      const int ns = __popcll(w);
+      cw_L = ns <= 8 ? 8 : ns <= 16 ? 16 : ns <= 32 ? 32 : 64;
+      const bool mine = ((w >> wl) & 1ull) != 0ull;
+      const int below = (int)__builtin_amdgcn_mbcnt_hi(
+          (uint32_t)(w >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)w, 0u));
+      const int slot = mine ? below : ns + (wl - below);
+      const int unit = __builtin_amdgcn_ds_permute(slot * 4, wl);
+      const int pos = wl % cw_L;
+      cw_col = __shfl(unit, pos, 64) & 63;
+      cw_walk = pos < ns ? 1u : 0u;
+      need = wl < ns ? 1u : 0u;
+    }
 
     float4 acc[NACC];
     float nrm2 = 0.f;
     // false: no group of this chunk is walked (chunked Yin-Yang); the row's
     // running result is carried on unchanged
     bool walked = true;
-    if constexpr (kChunkYY) walked = group_or<G>(need) != 0u;
+    if constexpr (kPacked) walked = group_or<G>(need) != 0u;
     if constexpr (WAVE_ROW) {
       const char* ctb = VEC == 8 ? static_cast<const char*>(A.CT16)
                                  : reinterpret_cast<const char*>(A.CT);
       if constexpr (CHUNK) ctb += (size_t)j0 * (VEC == 8 ? 2 : 4);
       if (!walked) {
-      } else if constexpr (kChunkYY) {
+      } else if constexpr (kPacked) {
         if (cw_L == 8)
           nrm2 = row_walk<8, 1, 4, true>(A.ci, A.v, beg, end, c0, x0, ctb, A.kp, wl, acc,
                                          cw_walk, cw_col);
@@ -828,7 +941,7 @@ __device__ __forceinline__ void assign_rows(const AssignArgs& A, int64_t row_bas
     }
     // similarities computed for this row (wave-uniform)
     unsigned long long row_sims_done = (unsigned long long)k;
-    if constexpr (kChunkYY) {
+    if constexpr (kPacked) {
       const int left = k - 4 * cw_col;
       const int mine = need ? (left < 4 ? (left > 0 ? left : 0) : 4) : 0;
       row_sims_done = (unsigned long long)group_sum<G>(mine);
@@ -848,7 +961,7 @@ __device__ __forceinline__ void assign_rows(const AssignArgs& A, int64_t row_bas
     for (int r = 0; r < R; ++r) {
 #pragma unroll
       for (int q = 0; q < VEC; ++q) {
-        const int j = (kChunkYY ? 4 * cw_col : VEC * (gl + G * r)) + q;
+        const int j = (kPacked ? 4 * cw_col : VEC * (gl + G * r)) + q;
         if (j < k && ((need >> r) & 1u)) {
           const float sv = f4get(acc[(r * VEC + q) >> 2], q & 3);
           if (better32(sv, j0 + j, b, bj, prev)) {
@@ -991,6 +1104,21 @@ __device__ __forceinline__ void assign_rows(const AssignArgs& A, int64_t row_bas
         fw = 2;
         ew = 0.0;
         any = true;
+      }
+      if constexpr (kChunkPairs) {
+        // exact pair bounds of the centres this launch walked (padding: 1)
+        if (walked && need) {
+          const int jl = kChunkEl ? 4 * cw_col : 4 * gl;
+          const double rb = eps + slack_r + 1e-12;
+          float4 o;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int j = jl + q;
+            f4set(o, q, j < k ? __double2float_ru(fmin((double)f4get(acc[0], q) + rb, 1.0))
+                              : 1.0f);
+          }
+          reinterpret_cast<float4*>(A.ue + (size_t)row * A.kp + j0)[jl / 4] = o;
+        }
       }
       if (kChunkGroups && A.uy != nullptr && walked) {
         const int excl = (cand_running && !(fw & 8)) ? jw : -1;
@@ -1344,6 +1472,11 @@ hipError_t launch_assign_chunk(const AssignArgs& A, int mode, hipStream_t s) {
     hipLaunchKernelGGL((k_assign_csr<64, 1, 4, kModeHamerly, true, true>), grid, block, 0, s, A);
   else if (mode == kModeYinYang)
     hipLaunchKernelGGL((k_assign_csr<64, 1, 4, kModeYinYang, true, true>), grid, block, 0, s, A);
+  else if (mode == kModeElkan)
+    hipLaunchKernelGGL((k_assign_csr<64, 1, 4, kModeElkan, true, true>), grid, block, 0, s, A);
+  else if (mode == kModeFitElkanInit)
+    hipLaunchKernelGGL((k_assign_csr<64, 1, 4, kModeFitElkanInit, true, true>), grid, block, 0,
+                       s, A);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

@@ -80,7 +80,7 @@ struct Plan {
   size_t CT = 0, CT16 = 0, negflag = 0, C64 = 0, S = 0, l = 0, u = 0, ue = 0, eta = 0,
          a_old = 0, norm64 = 0, part = 0, part_sq = 0, pc = 0, ps = 0, dirty = 0, mm = 0, G = 0,
          gmax = 0, gpart = 0, cnt = 0, per = 0, ctl = 0, rec = 0, maxeta = 0, initnorm = 0,
-         vbad = 0, rs = 0, total = 0;
+         vbad = 0, rs = 0, umask = 0, total = 0;
 };
 
 int check_matrix(const skm_matrix* X) {
@@ -241,16 +241,16 @@ int make_plan(const skm_matrix* X, int32_t k, int32_t variant, int32_t precision
   P->maxeta = take(kCounterSlots * sizeof(float));
   P->initnorm = take(kk * sizeof(double));
   P->vbad = take(sizeof(unsigned long long));
-  // Lloyd, the Hamerly variants and Yin-Yang walk wide FP32 centre copies a
-  // chunk of 1 KB per centre row at a time: the walk streams those fastest,
-  // and a chunk's slice of the copy is at most a quarter of it (k <= 1024),
-  // which the last-level cache holds where the whole copy does not
-  if ((variant == SKM_LLOYD || variant == SKM_HAMERLY || variant == SKM_SIMP_HAMERLY ||
-       variant == SKM_YINYANG) &&
-      !P->half && g.kp > kChunkF32) {
+  // Every CSR variant walks a wide FP32 centre copy a chunk of 1 KB per
+  // centre row at a time: the walk streams those fastest, and a chunk's
+  // slice of the copy is at most a quarter of it (k <= 1024), which the
+  // last-level cache holds where the whole copy does not.  Elkan keeps one
+  // survival word per row and 256-centre slice.
+  if (!P->half && g.kp > kChunkF32) {
     P->chunk = kChunkF32;
     P->nq = (k + kChunkF32 - 1) / kChunkF32;
     P->rs = take(n * sizeof(RowRun));
+    if (P->elkan) P->umask = take(n * (size_t)(g.kp / kChunkF32) * sizeof(uint64_t));
   }
   P->total = cur;
   return SKM_OK;
@@ -1508,6 +1508,7 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
   double* initnorm = at<double>(ws, P.initnorm);
 
   RowRun* rs = P.chunk ? at<RowRun>(ws, P.rs) : nullptr;
+  uint64_t* umask = (P.chunk && P.elkan) ? at<uint64_t>(ws, P.umask) : nullptr;
   // one assignment-step walk in `mode`: one launch, or one per chunk of
   // centres with the running per-row results in rs
   auto walk = [&](AssignArgs& A, int mode) -> hipError_t {
@@ -1516,6 +1517,7 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
       A.j0 = q * P.chunk;
       A.chunk_last = q == P.nq - 1 ? 1 : 0;
       A.rs = rs;
+      A.umask = umask;
       const hipError_t e = launch_assign_chunk(A, mode, s);
       if (e != hipSuccess) return e;
     }

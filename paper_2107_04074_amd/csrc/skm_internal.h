@@ -171,13 +171,17 @@ struct AssignArgs {
   int32_t ng;
   const double* gpc;
   const double* gps;
-  // chunked walks (fit and Hamerly modes at large k): this launch walks
-  // centres j0 ... j0 + chunk - 1 (kp stays the row stride of the centre
-  // copies); chunk_last marks the launch of the last chunk; rs holds every
-  // row's running result between the launches
+  // chunked walks (FP32 copy at large k): this launch walks centres j0 ...
+  // j0 + chunk - 1 (kp stays the row stride of the centre copies);
+  // chunk_last marks the launch of the last chunk; rs holds every row's
+  // running result between the launches
   int32_t j0;
   int32_t chunk_last;
   RowRun* rs;
+  // chunked Elkan: per row kp / 256 words, bit q of word t set when the
+  // 4-centre unit 64 t + q holds a centre whose pair tests failed (or the
+  // assigned centre); written by the first launch of a step
+  uint64_t* umask;
 };
 constexpr int kYYGroup = 32;  // centres per Yin-Yang group
 // Centres per launch of a chunked walk (FP32 centre copy): 1 KB of every
@@ -371,8 +375,9 @@ hipError_t launch_dense_prep(const float* X, int64_t ldx, int64_t n, int64_t d, 
 
 // ---- launchers (kernels_assign.hip) ----
 hipError_t launch_assign(const AssignArgs& A, int mode, hipStream_t s);
-// One launch of a chunked walk (fit, Hamerly or Yin-Yang mode, FP32 centre
-// copy, chunks of kChunkF32 centres; A.j0, A.chunk_last and A.rs set).
+// One launch of a chunked walk (fit, Hamerly, Yin-Yang, Elkan or Elkan-init
+// mode, FP32 centre copy, chunks of kChunkF32 centres; A.j0, A.chunk_last
+// and A.rs set, and A.umask for Elkan).
 hipError_t launch_assign_chunk(const AssignArgs& A, int mode, hipStream_t s);
 
 

@@ -92,7 +92,8 @@ def run(torch, skm, Xd, k, C0, variant, t, precision):
     return a.cpu().numpy(), C64.cpu().numpy(), st
 
 
-@pytest.mark.parametrize("variant,precision", [("hamerly", 0), ("yinyang", 0), ("yinyang", 2)])
+@pytest.mark.parametrize("variant,precision", [("hamerly", 0), ("yinyang", 0), ("simp_elkan", 0),
+                                               ("yinyang", 2)])
 def test_c3_trajectory_against_oracle(env, variant, precision):
     torch, skm = env
     G = np.load(os.path.join(GOLDEN, "c3_lloyd_trajectory.npz"))

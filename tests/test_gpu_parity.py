@@ -245,8 +245,9 @@ def test_fit_partial_walks(skm, torch_cuda):
 def test_fit_chunked_group_walks(skm, torch_cuda):
     """k = 800 with the FP32 copy (padded to 1024): the row walk takes the
     centres in four launches of 256 (the last one 32), carrying every row's
-    running winner between launches, and Yin-Yang walks only the groups its
-    filters leave in each launch, so a launch may walk no group of a row.
+    running winner between launches; Yin-Yang walks only the groups its
+    filters leave in each launch and Elkan only the 4-centre units holding a
+    centre whose pair tests failed, so a launch may walk nothing of a row.
     Rows from a von Mises-Fisher mixture (60 components, d = 48, stored as
     CSR) keep the centres moving for 14 steps; every variant's whole
     trajectory must equal the oracle's Lloyd trajectory, with the tests at
@@ -258,13 +259,14 @@ def test_fit_chunked_group_walks(skm, torch_cuda):
     say("case chunked group walks: oracle")
     ref = oracle.fit(X, C0, "lloyd", T)
     Xd = skm.DeviceCSR.from_host(X)
-    for v, sched in [("yinyang", 1), ("yinyang", 0), ("hamerly", 1), ("lloyd", 0)]:
+    for v, sched in [("yinyang", 1), ("yinyang", 0), ("elkan", 1), ("simp_elkan", 0),
+                     ("hamerly", 1), ("lloyd", 0)]:
         say("case chunked group walks %s schedule=%d" % (v, sched))
         a, C, C64, st = run_fit(skm, torch, Xd, C0, k, v, T, schedule=sched)
         say("  iters=%d sims=%d of %d" % (st.iterations, st.sims_point_center,
                                           X.n * k * st.iterations))
-        if v == "yinyang" and sched == 1:
-            # walked rows skip groups: the count is no multiple of k
+        if v in ("yinyang", "elkan") and sched == 1:
+            # walked rows skip groups / units: the count is no multiple of k
             assert st.sims_point_center < X.n * k * st.iterations
             assert st.sims_point_center % k != 0
         assert st.iterations == ref.iterations and st.converged == ref.converged
