@@ -417,11 +417,11 @@ __device__ __forceinline__ bool yinyang_prologue(const AssignArgs& A, int64_t ro
 // walked row gets every similarity and hence every pair bound exactly.
 // The lanes hold the pair bounds in the walk's layout.  Returns true when
 // the row needs no walk.
-template <int G, int R, int VEC, bool PARTIAL>
+template <int G, int R, int VEC>
 __device__ __forceinline__ bool elkan_prologue(const AssignArgs& A, int64_t row, const RowIn& ri,
                                                int64_t beg, int64_t end, int gl, bool leader,
                                                int tighten, bool writer, unsigned long long& tight,
-                                               unsigned long long& saved, unsigned& need) {
+                                               unsigned long long& saved) {
   constexpr int NACC = R * VEC / 4;
   const int k = A.k;
   const int prev = ri.prev;
@@ -486,18 +486,6 @@ __device__ __forceinline__ bool elkan_prologue(const AssignArgs& A, int64_t row,
       for (int q4 = 0; q4 < NACC; ++q4) {
         const int r = (4 * q4) / VEC, q0 = (4 * q4) % VEC;
         uer4[(VEC * (gl + G * r) + q0) / 4] = uv[q4];
-      }
-    }
-  } else if constexpr (PARTIAL) {
-    // walk the chunks with a surviving centre and the assigned centre's
-    // chunk; the others keep their updated pair bounds
-    const int pc4 = prev / VEC;
-    need = cmask | ((pc4 % G == gl) ? (1u << (pc4 / G)) : 0u);
-    if (writer) {
-#pragma unroll
-      for (int q4 = 0; q4 < NACC; ++q4) {
-        const int r = (4 * q4) / VEC, q0 = (4 * q4) % VEC;
-        if (!((need >> r) & 1u)) uer4[(VEC * (gl + G * r) + q0) / 4] = uv[q4];
       }
     }
   }
@@ -803,15 +791,8 @@ __device__ __forceinline__ void assign_rows(const AssignArgs& A, int64_t row_bas
     }
     const int m = (int)(end - beg);
     const int prev = ri.prev;
-    // Yin-Yang and Elkan with one row per wave and the FP32 copy at
-    // 256 < k <= 2048 walk only what their filters leave: the groups of the
-    // group filter, or the chunks holding a centre whose pair tests failed
-    // (bit r of need: this lane's chunk r is walked).  A group of 32 centres
-    // is one 128-byte line per stored entry there, and those walks are bound
-    // by the bytes they fetch; shorter or FP16 walks are bound by latency,
-    // where masked gathers save nothing and the masks cost occupancy.
-    constexpr bool kPartial = (MODE == kModeYinYang || MODE == kModeElkan) && WAVE_ROW &&
-                              VEC == 4 && R >= 2 && R <= 8;
+    // lanes whose centres the walk computes (bit r: chunk r of the lane);
+    // only the packed chunked walks leave lanes out
     unsigned need = ~0u;
     if constexpr (CHUNK) {
       // later chunks walk only the rows the first chunk's tests left
@@ -830,32 +811,20 @@ __device__ __forceinline__ void assign_rows(const AssignArgs& A, int64_t row_bas
         skip = hamerly_prologue<G>(A, row, ri, beg, end, gl, leader, tighten, my_tight,
                                    my_saved);
       else if constexpr (MODE == kModeYinYang)
-        skip = yinyang_prologue<G, kPartial || kChunkYY>(A, row, ri, beg, end, gl, leader,
-                                                         tighten, my_tight, my_saved, surv0,
-                                                         surv1);
+        skip = yinyang_prologue<G, kChunkYY>(A, row, ri, beg, end, gl, leader, tighten,
+                                             my_tight, my_saved, surv0, surv1);
       else if constexpr (kChunkEl)
         skip = elkan_chunk_prologue(A, row, ri, beg, end, gl, leader, tighten, my_tight,
                                     my_saved, ew0);
       else
-        skip = elkan_prologue<G, R, VEC, kPartial>(A, row, ri, beg, end, gl, leader, tighten,
-                                                   lead_sub, my_tight, my_saved, need);
+        skip = elkan_prologue<G, R, VEC>(A, row, ri, beg, end, gl, leader, tighten, lead_sub,
+                                         my_tight, my_saved);
       if (skip) {
         if constexpr (CHUNK) {
           if (leader) A.rs[row].flags = 0;  // pruned: the later chunks skip the row
         }
         if constexpr (WAVE_ROW) next_window();
         continue;
-      }
-      if constexpr (kPartial && MODE == kModeYinYang) {
-        need = 0u;
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-          const int j0 = VEC * (gl + G * r);
-          const int f = j0 / kYYGroup;
-          const bool walk =
-              j0 < k && (((f < 64 ? (surv0 >> f) : (surv1 >> (f - 64))) & 1ull) != 0ull);
-          need |= walk ? (1u << r) : 0u;
-        }
       }
     }
     // Chunked Yin-Yang: the chunk's groups that the filters left (the
@@ -928,8 +897,7 @@ __device__ __forceinline__ void assign_rows(const AssignArgs& A, int64_t row_bas
           nrm2 = row_walk<64, 1, 4, true>(A.ci, A.v, beg, end, c0, x0, ctb, A.kp, wl, acc,
                                           cw_walk, cw_col);
       } else {
-        nrm2 = row_walk<G, R, VEC, kPartial>(A.ci, A.v, beg, end, c0, x0, ctb, A.kp, wl, acc,
-                                             need);
+        nrm2 = row_walk<G, R, VEC>(A.ci, A.v, beg, end, c0, x0, ctb, A.kp, wl, acc);
       }
       if (!walked) {
 #pragma unroll
@@ -944,14 +912,6 @@ __device__ __forceinline__ void assign_rows(const AssignArgs& A, int64_t row_bas
     if constexpr (kPacked) {
       const int left = k - 4 * cw_col;
       const int mine = need ? (left < 4 ? (left > 0 ? left : 0) : 4) : 0;
-      row_sims_done = (unsigned long long)group_sum<G>(mine);
-    } else if constexpr (kPartial) {
-      int mine = 0;
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int j0 = VEC * (gl + G * r);
-        if ((need >> r) & 1u) mine += (k - j0 < VEC) ? k - j0 : VEC;
-      }
       row_sims_done = (unsigned long long)group_sum<G>(mine);
     }
 
@@ -1210,7 +1170,6 @@ __device__ __forceinline__ void assign_rows(const AssignArgs& A, int64_t row_bas
 #pragma unroll
         for (int q4 = 0; q4 < NACC; ++q4) {
           const int r = (4 * q4) / VEC, q0 = (4 * q4) % VEC;
-          if (!((need >> r) & 1u)) continue;  // kept its updated bound
           float4 o;
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
