@@ -55,15 +55,18 @@ def test_seeding_matches_oracle(skm, torch_cuda, name, n, k, alpha):
     assert np.abs(s2.cpu().numpy()[fin] - s2_ref[fin]).max(initial=0.0) < 1e-12
 
 
-@pytest.mark.parametrize("variant", ["lloyd", "hamerly", "elkan", "simp_hamerly", "yinyang"])
-def test_warm_start_equals_cold_fit(skm, torch_cuda, variant):
+# k = 600 takes the chunked row walk (three launches of up to 256 centres
+# per step) with bounds set from the seeding's cache
+@pytest.mark.parametrize("variant,k", [("lloyd", 100), ("hamerly", 100), ("elkan", 100),
+                                       ("simp_hamerly", 100), ("yinyang", 100),
+                                       ("hamerly", 600), ("elkan", 600), ("yinyang", 600)])
+def test_warm_start_equals_cold_fit(skm, torch_cuda, variant, k):
     torch = torch_cuda
     X, _, cfg = datagen.sparse_workload("c2", 20000)
-    k = 100
     u = np.random.default_rng(11).random(k)
     Xd = skm.DeviceCSR.from_host(X)
     ch, C, a, s1, s2 = skm.seed_kmeanspp(Xd, k, u)
-    say("case warm start %s" % variant)
+    say("case warm start %s k=%d" % (variant, k))
     ac, Cc, _, stc = skm.fit(Xd, k, C, variant, 60)
     aw, Cw, _, stw = skm.fit(Xd, k, C, variant, 60, warm=(a, s1, s2))
     torch.cuda.synchronize()
