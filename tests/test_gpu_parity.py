@@ -242,19 +242,22 @@ def test_fit_partial_walks(skm, torch_cuda):
         assert np.linalg.norm(C64 - ref.C, axis=1).max() < 1e-6
 
 
-def test_fit_chunked_group_walks(skm, torch_cuda):
+@pytest.mark.parametrize("k", [800, 2049])
+def test_fit_chunked_group_walks(skm, torch_cuda, k):
     """k = 800 with the FP32 copy (padded to 1024): the row walk takes the
     centres in four launches of 256 (the last one 32), carrying every row's
     running winner between launches; Yin-Yang walks only the groups its
     filters leave in each launch and Elkan only the 4-centre units holding a
     centre whose pair tests failed, so a launch may walk nothing of a row.
-    Rows from a von Mises-Fisher mixture (60 components, d = 48, stored as
-    CSR) keep the centres moving for 14 steps; every variant's whole
-    trajectory must equal the oracle's Lloyd trajectory, with the tests at
-    every step and with the default schedule."""
+    k = 2049 (padded to 4096): nine launches, the last with one centre, and
+    sixteen Elkan survival words per row.  Rows from a von Mises-Fisher
+    mixture (60 components, d = 48, stored as CSR) keep the centres moving
+    for several steps; every variant's whole trajectory must equal the
+    oracle's Lloyd trajectory, with the tests at every step and with the
+    default schedule."""
     torch = torch_cuda
     X = dense_csr(datagen.dense_vmf(12000, 48, 60, 4242))
-    k, T = 800, 60
+    T = 60
     C0 = datagen.init_centers_csr(X, datagen.init_rows(X.n, k, 11))
     say("case chunked group walks: oracle")
     ref = oracle.fit(X, C0, "lloyd", T)
