@@ -47,8 +47,9 @@
  *
  * Numerics
  * --------
- *  Similarities are evaluated in FP32 (sparse: one sequential FMA chain per
- *  (row, centre) over the stored entries; dense: MFMA).  Whenever the best
+ *  Similarities are evaluated in FP32 (sparse: FMA chains over the stored
+ *  entries, a few partial chains per (row, centre) added in a fixed order;
+ *  dense: MFMA); the error bound used holds for any summation order.  Whenever the best
  *  and second best FP32 values lie within the rigorous FP32 error bound of
  *  each other, the candidates are re-evaluated in FP64 against the FP64
  *  master centres, so every assignment equals the argmax of the FP64 dot
@@ -161,7 +162,8 @@ typedef struct {            /* [host] filled by skm_fit                       */
   int32_t reserved0;
   /* work of the dominant similarity kernel: for CSR input the row-walk
      kernel of each assignment step (one or two launches per step: with and
-     without bound tests, one of which returns at once), for dense input the
+     without bound tests, one of which returns at once; with the FP32 centre
+     copy at k > 256 that many per 256-centre slice), for dense input the
      first MFMA similarity pass of each step; steps, rows walked and their
      stored entries (rows x d for dense), and (profile = 1) the summed
      duration from HIP events recorded around each step's launches on
@@ -181,6 +183,7 @@ size_t skm_workspace_size(const skm_matrix* X, int32_t k, int32_t variant,
 size_t skm_assign_workspace_size(const skm_matrix* X, int32_t k);
 
 /* Spherical k-means from the given initial centres.
+ *   k              1 <= k <= n, at most 4096 (SKM_ERR_UNSUPPORTED above).
  *   init_centers   float[k*d] row-major; rows are rescaled to unit length in
  *                  FP64 before the first step (the paper's centres are unit
  *                  vectors; rows picked from float data are unit only to
