@@ -673,10 +673,11 @@ constexpr int assign_min_waves() {
 template <int G, int R, int VEC, int MODE, bool WAVE_ROW, bool CHUNK = false>
 __device__ __forceinline__ void assign_rows(const AssignArgs& A, int64_t row_base,
                                             int64_t row_end, int64_t rstride, int slot) {
-  static_assert(!CHUNK || (WAVE_ROW && G == 64 && R == 1 && VEC == 4 &&
+  static_assert(!CHUNK || (WAVE_ROW && G == 64 && R == 1 &&
+                           (VEC == 4 || MODE == kModeYinYang) &&
                            (MODE == kModeFit || MODE == kModeHamerly || MODE == kModeYinYang ||
                             MODE == kModeElkan || MODE == kModeFitElkanInit)),
-                "chunked walks: one chunk of 64 x 4 centres per lane row");
+                "chunked walks: one chunk of 64 x VEC centres per lane row (FP16: Yin-Yang)");
   // chunked Yin-Yang: the first chunk's prologue leaves a set of groups to
   // walk (kept in the row's running record); every chunk walks its own
   constexpr bool kChunkYY = CHUNK && MODE == kModeYinYang;
@@ -828,27 +829,29 @@ __device__ __forceinline__ void assign_rows(const AssignArgs& A, int64_t row_bas
       }
     }
     // Chunked Yin-Yang: the chunk's groups that the filters left (the
-    // assigned centre's group among them), na of its 8, packed onto the
-    // lanes: the 8 lanes of packed segment t read the t-th surviving group
-    // (8 x 16 bytes of every centre row), and a sub-wave of L = 8 na
-    // lanes (rounded up to 8, 16, 32 or 64) walks the row, so one gather
-    // instruction serves 64 / L entries.  Lane wl holds centres 4 cw_col
-    // ... 4 cw_col + 3 of the chunk when live (need = 1: wl < L and its
-    // segment < na).
+    // assigned centre's group among them), na of its 64 / GL, packed onto
+    // the lanes: the GL lanes of packed segment t (a group is GL 16-byte
+    // units of a centre row: 8 with the FP32 copy, 4 with FP16) read the
+    // t-th surviving group, and a sub-wave of L = GL na lanes (rounded up to
+    // 8, 16, 32 or 64) walks the row, so one gather instruction serves
+    // 64 / L entries.  Lane wl holds centres VEC cw_col ... VEC cw_col +
+    // VEC - 1 of the chunk when live (need = 1: wl < L and its segment < na).
+    constexpr int GL = kYYGroup / VEC;
     int cw_L = 64, cw_col = 0;
     unsigned cw_walk = 1u;  // the lane fetches (every sub-wave)
     if constexpr (kChunkYY) {
-      const int gb = j0 / kYYGroup;  // a multiple of 8: one mask word holds the chunk
+      const int gb = j0 / kYYGroup;  // a multiple of 64 / GL: one mask word holds the chunk
       const int ngc = (k + kYYGroup - 1) / kYYGroup;
       const uint64_t sv = gb < 64 ? (surv0 >> gb) : (surv1 >> (gb - 64));
       const unsigned am = (unsigned)(sv & ((1ull << ngc) - 1ull));
       const int na = __popc(am);
-      cw_L = na <= 1 ? 8 : na <= 2 ? 16 : na <= 4 ? 32 : 64;
-      const int seg = (wl % cw_L) >> 3;
+      const int lanes = GL * na;
+      cw_L = lanes <= 8 ? 8 : lanes <= 16 ? 16 : lanes <= 32 ? 32 : 64;
+      const int seg = (wl % cw_L) / GL;
       unsigned rest = am;
       for (int i = 0; i < seg && rest != 0u; ++i) rest &= rest - 1u;
       const int grp = rest != 0u ? __builtin_ctz(rest) : 0;
-      cw_col = grp * (kYYGroup / 4) + (wl & 7);
+      cw_col = grp * GL + (wl % GL);
       cw_walk = seg < na ? 1u : 0u;
       need = (seg < na && wl < cw_L) ? 1u : 0u;
     }
@@ -885,16 +888,16 @@ __device__ __forceinline__ void assign_rows(const AssignArgs& A, int64_t row_bas
       if (!walked) {
       } else if constexpr (kPacked) {
         if (cw_L == 8)
-          nrm2 = row_walk<8, 1, 4, true>(A.ci, A.v, beg, end, c0, x0, ctb, A.kp, wl, acc,
+          nrm2 = row_walk<8, 1, VEC, true>(A.ci, A.v, beg, end, c0, x0, ctb, A.kp, wl, acc,
                                          cw_walk, cw_col);
         else if (cw_L == 16)
-          nrm2 = row_walk<16, 1, 4, true>(A.ci, A.v, beg, end, c0, x0, ctb, A.kp, wl, acc,
+          nrm2 = row_walk<16, 1, VEC, true>(A.ci, A.v, beg, end, c0, x0, ctb, A.kp, wl, acc,
                                           cw_walk, cw_col);
         else if (cw_L == 32)
-          nrm2 = row_walk<32, 1, 4, true>(A.ci, A.v, beg, end, c0, x0, ctb, A.kp, wl, acc,
+          nrm2 = row_walk<32, 1, VEC, true>(A.ci, A.v, beg, end, c0, x0, ctb, A.kp, wl, acc,
                                           cw_walk, cw_col);
         else
-          nrm2 = row_walk<64, 1, 4, true>(A.ci, A.v, beg, end, c0, x0, ctb, A.kp, wl, acc,
+          nrm2 = row_walk<64, 1, VEC, true>(A.ci, A.v, beg, end, c0, x0, ctb, A.kp, wl, acc,
                                           cw_walk, cw_col);
       } else {
         nrm2 = row_walk<G, R, VEC>(A.ci, A.v, beg, end, c0, x0, ctb, A.kp, wl, acc);
@@ -910,8 +913,8 @@ __device__ __forceinline__ void assign_rows(const AssignArgs& A, int64_t row_bas
     // similarities computed for this row (wave-uniform)
     unsigned long long row_sims_done = (unsigned long long)k;
     if constexpr (kPacked) {
-      const int left = k - 4 * cw_col;
-      const int mine = need ? (left < 4 ? (left > 0 ? left : 0) : 4) : 0;
+      const int left = k - VEC * cw_col;
+      const int mine = need ? (left < VEC ? (left > 0 ? left : 0) : VEC) : 0;
       row_sims_done = (unsigned long long)group_sum<G>(mine);
     }
 
@@ -921,7 +924,7 @@ __device__ __forceinline__ void assign_rows(const AssignArgs& A, int64_t row_bas
     for (int r = 0; r < R; ++r) {
 #pragma unroll
       for (int q = 0; q < VEC; ++q) {
-        const int j = (kPacked ? 4 * cw_col : VEC * (gl + G * r)) + q;
+        const int j = VEC * (kPacked ? cw_col : gl + G * r) + q;
         if (j < k && ((need >> r) & 1u)) {
           const float sv = f4get(acc[(r * VEC + q) >> 2], q & 3);
           if (better32(sv, j0 + j, b, bj, prev)) {
@@ -1084,19 +1087,19 @@ __device__ __forceinline__ void assign_rows(const AssignArgs& A, int64_t row_bas
         const int excl = (cand_running && !(fw & 8)) ? jw : -1;
         const double rb = eps + slack_r + 1e-12;
         if constexpr (kChunkYY) {
-          // packed lanes: segment-aligned groups of 8 lanes
+          // packed lanes: segment-aligned groups of GL lanes
           float mv = -INFINITY;
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const int j = 4 * cw_col + q;
-            if (need && j < k && j0 + j != excl) mv = fmaxf(mv, f4get(acc[0], q));
+          for (int q = 0; q < VEC; ++q) {
+            const int j = VEC * cw_col + q;
+            if (need && j < k && j0 + j != excl) mv = fmaxf(mv, f4get(acc[q >> 2], q & 3));
           }
 #pragma unroll
-          for (int off = 4; off >= 1; off >>= 1) mv = fmaxf(mv, __shfl_xor(mv, off, 8));
-          if (need && (wl & 7) == 0) {
+          for (int off = GL / 2; off >= 1; off >>= 1) mv = fmaxf(mv, __shfl_xor(mv, off, GL));
+          if (need && (wl % GL) == 0) {
             const float val =
                 (mv == -INFINITY) ? -1.0f : __double2float_ru(fmin((double)mv + rb, 1.0));
-            A.uy[(size_t)row * A.ng + (j0 + 4 * cw_col) / kYYGroup] = val;
+            A.uy[(size_t)row * A.ng + (j0 + VEC * cw_col) / kYYGroup] = val;
           }
         } else {
           write_group_bounds<G, R, VEC>(A, row, acc, gl, excl, rb, lead_sub, need, j0, k);
@@ -1417,7 +1420,8 @@ hipError_t launch_assign_batched(const AssignArgs* args, int arg_stride, int arg
 }
 
 hipError_t launch_assign_chunk(const AssignArgs& A, int mode, hipStream_t s) {
-  if (A.CT16 != nullptr) return hipErrorInvalidValue;  // FP32 centre copy only
+  // FP16 centre copy: Yin-Yang steps only (chunks of 512 centres)
+  if (A.CT16 != nullptr && mode != kModeYinYang) return hipErrorInvalidValue;
   // one row per wave; twice the usual persistent grid: the rows of a wave
   // vary in length, and more, shorter row sets end closer together (C3:
   // 3% faster per launch than 2048 blocks, 1024 blocks 2% slower)
@@ -1429,6 +1433,8 @@ hipError_t launch_assign_chunk(const AssignArgs& A, int mode, hipStream_t s) {
     hipLaunchKernelGGL((k_assign_csr<64, 1, 4, kModeFit, true, true>), grid, block, 0, s, A);
   else if (mode == kModeHamerly)
     hipLaunchKernelGGL((k_assign_csr<64, 1, 4, kModeHamerly, true, true>), grid, block, 0, s, A);
+  else if (mode == kModeYinYang && A.CT16 != nullptr)
+    hipLaunchKernelGGL((k_assign_csr<64, 1, 8, kModeYinYang, true, true>), grid, block, 0, s, A);
   else if (mode == kModeYinYang)
     hipLaunchKernelGGL((k_assign_csr<64, 1, 4, kModeYinYang, true, true>), grid, block, 0, s, A);
   else if (mode == kModeElkan)

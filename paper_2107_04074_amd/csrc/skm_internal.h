@@ -187,6 +187,8 @@ constexpr int kYYGroup = 32;  // centres per Yin-Yang group
 // Centres per launch of a chunked walk (FP32 centre copy): 1 KB of every
 // centre row, which is what the row walk streams fastest.
 constexpr int kChunkF32 = 256;
+// The same 1 KB per centre row with the FP16 copy (Yin-Yang steps).
+constexpr int kChunkF16 = 512;
 
 
 struct DenseSimArgs {
@@ -376,8 +378,9 @@ hipError_t launch_dense_prep(const float* X, int64_t ldx, int64_t n, int64_t d, 
 // ---- launchers (kernels_assign.hip) ----
 hipError_t launch_assign(const AssignArgs& A, int mode, hipStream_t s);
 // One launch of a chunked walk (fit, Hamerly, Yin-Yang, Elkan or Elkan-init
-// mode, FP32 centre copy, chunks of kChunkF32 centres; A.j0, A.chunk_last
-// and A.rs set, and A.umask for Elkan).
+// mode with the FP32 centre copy, chunks of kChunkF32 centres; Yin-Yang mode
+// with the FP16 copy, chunks of kChunkF16; A.j0, A.chunk_last and A.rs set,
+// and A.umask for Elkan).
 hipError_t launch_assign_chunk(const AssignArgs& A, int mode, hipStream_t s);
 
 
