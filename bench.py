@@ -462,7 +462,8 @@ def run_batched(dev, variant, steps, warmup, workers_arg, skip_baseline, no_cpu,
 SPARSE_TABLE = {
     "c2": ["lloyd", "simp_hamerly", "hamerly", "simp_elkan", "elkan", "yinyang",
            "lloyd_fp16", "hamerly_fp16", "yinyang_fp16"],
-    "c3": ["lloyd_fp16", "hamerly_fp16", "yinyang", "yinyang_fp16", "simp_elkan"],
+    "c3": ["lloyd_fp16", "hamerly_fp16", "yinyang", "yinyang_fp16", "simp_elkan",
+           "simp_elkan_fp16"],
     "c1": ["lloyd", "hamerly", "elkan", "yinyang"],
 }
 DENSE_TABLE = ["lloyd_bf16", "simp_hamerly_bf16", "hamerly_fp32"]

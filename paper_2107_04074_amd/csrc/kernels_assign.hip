@@ -493,18 +493,21 @@ __device__ __forceinline__ bool elkan_prologue(const AssignArgs& A, int64_t row,
 }
 
 // Elkan prologue of a chunked walk (first launch of a step, one row per
-// wave): the same tests as elkan_prologue over all kp / 256 slices of the
-// row's pair bounds.  Every pair bound is updated with its centre's movement
-// (guarded Eq. (7)) and stored; a walked row then gets exact bounds for the
-// centres it walks.  The survivors go to A.umask (bit q of word t: unit
-// 64 t + q, i.e. centres 256 t + 4 q ... + 3, holds a centre whose tests
-// failed; the assigned centre's unit is always set); word 0 is also
-// returned in w0.  Returns true when the row needs no walk (l(i) stored).
+// wave): the same tests as elkan_prologue over all kp / (64 VEC) slices of
+// the row's pair bounds.  Every pair bound is updated with its centre's
+// movement (guarded Eq. (7)) and stored; a walked row then gets exact bounds
+// for the centres it walks.  The survivors go to A.umask (bit q of word t:
+// unit 64 t + q, i.e. centres 64 VEC t + VEC q ... + VEC - 1, holds a centre
+// whose tests failed; the assigned centre's unit is always set); word 0 is
+// also returned in w0.  Returns true when the row needs no walk (l(i)
+// stored).
+template <int VEC>
 __device__ __forceinline__ bool elkan_chunk_prologue(const AssignArgs& A, int64_t row,
                                                      const RowIn& ri, int64_t beg, int64_t end,
                                                      int gl, bool leader, int tighten,
                                                      unsigned long long& tight,
                                                      unsigned long long& saved, uint64_t& w0) {
+  constexpr int SL = 64 * VEC;  // centres per slice (one launch of the walk)
   const int k = A.k;
   const int prev = ri.prev;
   const int m = (int)(end - beg);
@@ -514,21 +517,24 @@ __device__ __forceinline__ bool elkan_chunk_prologue(const AssignArgs& A, int64_
   const double mu = 4.0 * (double)(m + 2) * kU64 * (1.0 + eta) + 4.0 * A.delta_c + 1e-15;
   double ld = lower_upd((double)ri.l, A.pc[prev], A.ps[prev]) - 4e-15;
   float4* uer4 = reinterpret_cast<float4*>(A.ue + (size_t)row * A.kp);
-  const int nw = A.kp / kChunkF32;
+  const int nw = A.kp / SL;
   uint64_t* um = A.umask + (size_t)row * nw;
   // every pair bound updated with its centre's movement, kept in place
   for (int t = 0; t < nw; ++t) {
-    const int jb = kChunkF32 * t + 4 * gl;
-    float4 uv = uer4[jb / 4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int j = jb + q;
-      if (j < k) {
-        const double nu = upper_upd((double)f4get(uv, q), A.pc[j], A.ps[j]) + 4e-15;
-        f4set(uv, q, __double2float_ru(fmin(nu, 1.0)));
+    for (int h = 0; h < VEC / 4; ++h) {
+      const int jb = SL * t + VEC * gl + 4 * h;
+      float4 uv = uer4[jb / 4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int j = jb + q;
+        if (j < k) {
+          const double nu = upper_upd((double)f4get(uv, q), A.pc[j], A.ps[j]) + 4e-15;
+          f4set(uv, q, __double2float_ru(fmin(nu, 1.0)));
+        }
       }
+      uer4[jb / 4] = uv;
     }
-    uer4[jb / 4] = uv;
   }
   const double* Grow = A.Gm ? A.Gm + (size_t)prev * k : nullptr;
   // the point test, then the pair tests of every unit (bounds read back
@@ -540,21 +546,24 @@ __device__ __forceinline__ bool elkan_chunk_prologue(const AssignArgs& A, int64_
     if (cc_ok && A.gmax[prev] <= T) return false;  // no other centre can win
     bool any = false;
     for (int t = 0; t < nw; ++t) {
-      const int jb = kChunkF32 * t + 4 * gl;
-      const float4 uv = uer4[jb / 4];
       bool alive = false;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int j = jb + q;
-        if (j < k && j != prev) {
-          const bool by_u = (lcur - (double)f4get(uv, q)) >= mu;  // u(i, j) <= l(i)
-          const bool by_cc = cc_ok && (Grow[j] + A.delta_g <= T);  // cc(a, j) <= l(i)
-          alive = alive || (!by_u && !by_cc);
+      for (int h = 0; h < VEC / 4; ++h) {
+        const int jb = SL * t + VEC * gl + 4 * h;
+        const float4 uv = uer4[jb / 4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int j = jb + q;
+          if (j < k && j != prev) {
+            const bool by_u = (lcur - (double)f4get(uv, q)) >= mu;  // u(i, j) <= l(i)
+            const bool by_cc = cc_ok && (Grow[j] + A.delta_g <= T);  // cc(a, j) <= l(i)
+            alive = alive || (!by_u && !by_cc);
+          }
         }
       }
       uint64_t w = __ballot(alive);
       any = any || w != 0ull;
-      if (t == prev / kChunkF32) w |= 1ull << ((prev % kChunkF32) / 4);
+      if (t == prev / SL) w |= 1ull << ((prev % SL) / VEC);
       if (t == 0) w0 = w;
       if (leader) um[t] = w;
     }
@@ -674,7 +683,7 @@ template <int G, int R, int VEC, int MODE, bool WAVE_ROW, bool CHUNK = false>
 __device__ __forceinline__ void assign_rows(const AssignArgs& A, int64_t row_base,
                                             int64_t row_end, int64_t rstride, int slot) {
   static_assert(!CHUNK || (WAVE_ROW && G == 64 && R == 1 &&
-                           (VEC == 4 || MODE == kModeYinYang) &&
+                           (VEC == 4 || MODE == kModeYinYang || MODE == kModeElkan) &&
                            (MODE == kModeFit || MODE == kModeHamerly || MODE == kModeYinYang ||
                             MODE == kModeElkan || MODE == kModeFitElkanInit)),
                 "chunked walks: one chunk of 64 x VEC centres per lane row (FP16: Yin-Yang)");
@@ -815,8 +824,8 @@ __device__ __forceinline__ void assign_rows(const AssignArgs& A, int64_t row_bas
         skip = yinyang_prologue<G, kChunkYY>(A, row, ri, beg, end, gl, leader, tighten,
                                              my_tight, my_saved, surv0, surv1);
       else if constexpr (kChunkEl)
-        skip = elkan_chunk_prologue(A, row, ri, beg, end, gl, leader, tighten, my_tight,
-                                    my_saved, ew0);
+        skip = elkan_chunk_prologue<VEC>(A, row, ri, beg, end, gl, leader, tighten, my_tight,
+                                         my_saved, ew0);
       else
         skip = elkan_prologue<G, R, VEC>(A, row, ri, beg, end, gl, leader, tighten, lead_sub,
                                          my_tight, my_saved);
@@ -861,7 +870,7 @@ __device__ __forceinline__ void assign_rows(const AssignArgs& A, int64_t row_bas
       // set, else to ns + (units clear below it) -- a permutation of the
       // lanes; a sub-wave of L = 8, 16, 32 or 64 lanes walks them
       const uint64_t w =
-          j0 == 0 ? ew0 : A.umask[(size_t)row * (A.kp / kChunkF32) + j0 / kChunkF32];
+          j0 == 0 ? ew0 : A.umask[(size_t)row * (A.kp / (64 * VEC)) + j0 / (64 * VEC)];
       const int ns = __popcll(w);
       cw_L = ns <= 8 ? 8 : ns <= 16 ? 16 : ns <= 32 ? 32 : 64;
       const bool mine = ((w >> wl) & 1ull) != 0ull;
@@ -1071,16 +1080,19 @@ __device__ __forceinline__ void assign_rows(const AssignArgs& A, int64_t row_bas
       if constexpr (kChunkPairs) {
         // exact pair bounds of the centres this launch walked (padding: 1)
         if (walked && need) {
-          const int jl = kChunkEl ? 4 * cw_col : 4 * gl;
+          const int jl = VEC * (kChunkEl ? cw_col : gl);
           const double rb = eps + slack_r + 1e-12;
-          float4 o;
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const int j = jl + q;
-            f4set(o, q, j < k ? __double2float_ru(fmin((double)f4get(acc[0], q) + rb, 1.0))
-                              : 1.0f);
+          for (int h = 0; h < VEC / 4; ++h) {
+            float4 o;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int j = jl + 4 * h + q;
+              f4set(o, q,
+                    j < k ? __double2float_ru(fmin((double)f4get(acc[h], q) + rb, 1.0)) : 1.0f);
+            }
+            reinterpret_cast<float4*>(A.ue + (size_t)row * A.kp + j0)[jl / 4 + h] = o;
           }
-          reinterpret_cast<float4*>(A.ue + (size_t)row * A.kp + j0)[jl / 4] = o;
         }
       }
       if (kChunkGroups && A.uy != nullptr && walked) {
@@ -1420,8 +1432,9 @@ hipError_t launch_assign_batched(const AssignArgs* args, int arg_stride, int arg
 }
 
 hipError_t launch_assign_chunk(const AssignArgs& A, int mode, hipStream_t s) {
-  // FP16 centre copy: Yin-Yang steps only (chunks of 512 centres)
-  if (A.CT16 != nullptr && mode != kModeYinYang) return hipErrorInvalidValue;
+  // FP16 centre copy: Yin-Yang and Elkan steps only (chunks of 512 centres)
+  if (A.CT16 != nullptr && mode != kModeYinYang && mode != kModeElkan)
+    return hipErrorInvalidValue;
   // one row per wave; twice the usual persistent grid: the rows of a wave
   // vary in length, and more, shorter row sets end closer together (C3:
   // 3% faster per launch than 2048 blocks, 1024 blocks 2% slower)
@@ -1437,6 +1450,8 @@ hipError_t launch_assign_chunk(const AssignArgs& A, int mode, hipStream_t s) {
     hipLaunchKernelGGL((k_assign_csr<64, 1, 8, kModeYinYang, true, true>), grid, block, 0, s, A);
   else if (mode == kModeYinYang)
     hipLaunchKernelGGL((k_assign_csr<64, 1, 4, kModeYinYang, true, true>), grid, block, 0, s, A);
+  else if (mode == kModeElkan && A.CT16 != nullptr)
+    hipLaunchKernelGGL((k_assign_csr<64, 1, 8, kModeElkan, true, true>), grid, block, 0, s, A);
   else if (mode == kModeElkan)
     hipLaunchKernelGGL((k_assign_csr<64, 1, 4, kModeElkan, true, true>), grid, block, 0, s, A);
   else if (mode == kModeFitElkanInit)

@@ -75,7 +75,7 @@ struct Plan {
   bool yy = false;    // Yin-Yang group bounds
   int32_t ng = 0;     // Yin-Yang groups
   int chunk = 0;      // centres per launch of a chunked row walk (0: one launch)
-  int chunk16 = 0, nq16 = 0;  // Yin-Yang steps with the FP16 copy: chunk width, launches
+  int chunk16 = 0, nq16 = 0;  // Yin-Yang / Elkan steps, FP16 copy: chunk width, launches
   int nq = 1;         // launches per walk
   size_t uy = 0, gpc = 0, gps = 0;
   size_t CT = 0, CT16 = 0, negflag = 0, C64 = 0, S = 0, l = 0, u = 0, ue = 0, eta = 0,
@@ -253,14 +253,16 @@ int make_plan(const skm_matrix* X, int32_t k, int32_t variant, int32_t precision
     P->rs = take(n * sizeof(RowRun));
     if (P->elkan) P->umask = take(n * (size_t)(g.kp / kChunkF32) * sizeof(uint64_t));
   }
-  // Yin-Yang with the FP16 copy at k > 512: the steps with tests walk 1 KB of
-  // every FP16 centre row per launch, packing each row's surviving groups
-  // (the plain steps, and Lloyd and Hamerly with the FP16 copy, walk whole
-  // rows in one launch: that copy fits the last-level cache)
-  if (P->yy && P->half && g.kp > kChunkF16) {
+  // Yin-Yang and Elkan with the FP16 copy at k > 512: the steps with tests
+  // walk 1 KB of every FP16 centre row per launch, packing each row's
+  // surviving groups / units (the plain steps, and Lloyd and Hamerly with
+  // the FP16 copy, walk whole rows in one launch: that copy fits the
+  // last-level cache)
+  if ((P->yy || P->elkan) && P->half && g.kp > kChunkF16) {
     P->chunk16 = kChunkF16;
     P->nq16 = (k + kChunkF16 - 1) / kChunkF16;
     P->rs = take(n * sizeof(RowRun));
+    if (P->elkan) P->umask = take(n * (size_t)(g.kp / kChunkF16) * sizeof(uint64_t));
   }
   P->total = cur;
   return SKM_OK;
@@ -1518,15 +1520,16 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
   double* initnorm = at<double>(ws, P.initnorm);
 
   RowRun* rs = (P.chunk || P.chunk16) ? at<RowRun>(ws, P.rs) : nullptr;
-  uint64_t* umask = (P.chunk && P.elkan) ? at<uint64_t>(ws, P.umask) : nullptr;
+  uint64_t* umask = ((P.chunk || P.chunk16) && P.elkan) ? at<uint64_t>(ws, P.umask) : nullptr;
   // one assignment-step walk in `mode`: one launch, or one per chunk of
   // centres with the running per-row results in rs
   auto walk = [&](AssignArgs& A, int mode) -> hipError_t {
-    if (P.chunk16 && mode == kModeYinYang) {
+    if (P.chunk16 && (mode == kModeYinYang || mode == kModeElkan)) {
       for (int q = 0; q < P.nq16; ++q) {
         A.j0 = q * P.chunk16;
         A.chunk_last = q == P.nq16 - 1 ? 1 : 0;
         A.rs = rs;
+        A.umask = umask;
         const hipError_t e = launch_assign_chunk(A, mode, s);
         if (e != hipSuccess) return e;
       }

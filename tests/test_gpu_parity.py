@@ -263,10 +263,11 @@ def test_fit_chunked_group_walks(skm, torch_cuda, k):
     ref = oracle.fit(X, C0, "lloyd", T)
     Xd = skm.DeviceCSR.from_host(X)
     # (variant, schedule, precision): precision 2 walks the FP16 copy, whose
-    # Yin-Yang steps take 512 centres per launch
+    # Yin-Yang and Elkan steps take 512 centres per launch
     for v, sched, prec in [("yinyang", 1, 0), ("yinyang", 0, 0), ("elkan", 1, 0),
                            ("simp_elkan", 0, 0), ("hamerly", 1, 0), ("lloyd", 0, 0),
-                           ("yinyang", 1, 2), ("yinyang", 0, 2)]:
+                           ("yinyang", 1, 2), ("yinyang", 0, 2), ("elkan", 1, 2),
+                           ("simp_elkan", 0, 2)]:
         say("case chunked group walks %s schedule=%d precision=%d" % (v, sched, prec))
         a, C, C64, st = run_fit(skm, torch, Xd, C0, k, v, T, schedule=sched, precision=prec)
         say("  iters=%d sims=%d of %d" % (st.iterations, st.sims_point_center,
