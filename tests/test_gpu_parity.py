@@ -282,6 +282,33 @@ def test_fit_chunked_group_walks(skm, torch_cuda, k):
         assert np.linalg.norm(C64 - ref.C, axis=1).max() < 1e-6
 
 
+def test_fit_chunked_duplicate_centres(skm, torch_cuda):
+    """Identical centres in different launches of a chunked walk (k = 600:
+    FP32 slices of 256, FP16 slices of 512): every row with such a pair at
+    its maximum is an exact FP64 tie across launches, which must go to the
+    previous assignment if it attains the maximum, else to the lowest index,
+    as in the oracle's Lloyd trajectory (the duplicate that loses keeps its
+    centre, R3).  Every variant, both centre copies, tests at every step."""
+    torch = torch_cuda
+    X = dense_csr(datagen.dense_vmf(6000, 48, 40, 515))
+    k, T = 600, 40
+    rows = datagen.init_rows(X.n, k, 23)
+    for src, dst in [(3, 260), (3, 520), (100, 356), (300, 599), (511, 512)]:
+        rows[dst] = rows[src]
+    C0 = datagen.init_centers_csr(X, rows)
+    say("case chunked duplicate centres: oracle")
+    ref = oracle.fit(X, C0, "lloyd", T)
+    Xd = skm.DeviceCSR.from_host(X)
+    for v in VARIANTS:
+        for prec in (0, 2):
+            say("case chunked duplicate centres %s precision=%d" % (v, prec))
+            a, C, C64, st = run_fit(skm, torch, Xd, C0, k, v, T, schedule=1, precision=prec)
+            assert st.iterations == ref.iterations and st.converged == ref.converged
+            assert np.array_equal(st.changed_per_iter, ref.changed)
+            assert np.array_equal(a, ref.a)
+            assert np.linalg.norm(C64 - ref.C, axis=1).max() < 1e-6
+
+
 def test_fit_c2_full_size(skm, torch_cuda):
     """Full c2 workload (n=1e5, d=5e4, k=100) run to no-change: every
     variant identical to the oracle's full FP64 Lloyd trajectory."""
