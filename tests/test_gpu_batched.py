@@ -79,6 +79,33 @@ def test_batched_matches_oracle(skm, torch_cuda, problems):
         assert np.linalg.norm(C.cpu().numpy().astype(np.float64) - ref.C, axis=1).max() < 1e-6
 
 
+@pytest.mark.parametrize("variant,precision", [("hamerly", 0), ("yinyang", 0), ("elkan", 0),
+                                               ("yinyang", 2)])
+def test_batched_chunked_problems(skm, torch_cuda, variant, precision):
+    """Problems wide enough for the chunked row walk (k = 300, 600, 1100)
+    next to a small one, run by the batched driver on a shared workspace:
+    each equals its own fit and the oracle's Lloyd trajectory."""
+    torch = torch_cuda
+    specs = [(3000, 300, 1), (4000, 600, 2), (2500, 1100, 3), (1500, 40, 4)]
+    probs, refs = [], []
+    for n, k, seed in specs:
+        X = datagen.sparse_tfidf(n, 6000, 40.0, 700 + seed)
+        C0 = datagen.init_centers_csr(X, datagen.init_rows(X.n, k, seed))
+        Xd = skm.DeviceCSR.from_host(X)
+        probs.append((Xd, k, torch.from_numpy(C0).cuda(), 12))
+        refs.append((X, C0))
+    say("case batched chunked %s precision=%d" % (variant, precision))
+    res = skm.fit_batched(probs, variant, workers=3, precision=precision)
+    torch.cuda.synchronize()
+    for (Xd, k, C0, it), (a, C, st), (X, C0h) in zip(probs, res, refs):
+        a1, C1, _, st1 = skm.fit(Xd, k, C0, variant, it, per_iter=False, precision=precision)
+        torch.cuda.synchronize()
+        assert torch.equal(a, a1) and torch.equal(C, C1), k
+        assert st.iterations == st1.iterations, k
+        ref = oracle.fit(X, C0h, "lloyd", it)
+        assert st.iterations == ref.iterations and np.array_equal(a.cpu().numpy(), ref.a), k
+
+
 def test_batched_matches_oracle_uneven(skm, torch_cuda):
     """The host-thread driver on an uneven subset of the batched workload at
     20% of its row counts -- the problems with the most rows and the most

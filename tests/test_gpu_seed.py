@@ -55,20 +55,22 @@ def test_seeding_matches_oracle(skm, torch_cuda, name, n, k, alpha):
     assert np.abs(s2.cpu().numpy()[fin] - s2_ref[fin]).max(initial=0.0) < 1e-12
 
 
-# k = 600 takes the chunked row walk (three launches of up to 256 centres
-# per step) with bounds set from the seeding's cache
-@pytest.mark.parametrize("variant,k", [("lloyd", 100), ("hamerly", 100), ("elkan", 100),
-                                       ("simp_hamerly", 100), ("yinyang", 100),
-                                       ("hamerly", 600), ("elkan", 600), ("yinyang", 600)])
-def test_warm_start_equals_cold_fit(skm, torch_cuda, variant, k):
+# k = 600 takes the chunked row walk (three launches of up to 256 FP32 or
+# two of up to 512 FP16 centres per step) with bounds set from the seeding's
+# cache
+@pytest.mark.parametrize("variant,k,precision", [
+    ("lloyd", 100, 0), ("hamerly", 100, 0), ("elkan", 100, 0), ("simp_hamerly", 100, 0),
+    ("yinyang", 100, 0), ("hamerly", 600, 0), ("elkan", 600, 0), ("yinyang", 600, 0),
+    ("elkan", 600, 2), ("yinyang", 600, 2)])
+def test_warm_start_equals_cold_fit(skm, torch_cuda, variant, k, precision):
     torch = torch_cuda
     X, _, cfg = datagen.sparse_workload("c2", 20000)
     u = np.random.default_rng(11).random(k)
     Xd = skm.DeviceCSR.from_host(X)
     ch, C, a, s1, s2 = skm.seed_kmeanspp(Xd, k, u)
-    say("case warm start %s k=%d" % (variant, k))
-    ac, Cc, _, stc = skm.fit(Xd, k, C, variant, 60)
-    aw, Cw, _, stw = skm.fit(Xd, k, C, variant, 60, warm=(a, s1, s2))
+    say("case warm start %s k=%d precision=%d" % (variant, k, precision))
+    ac, Cc, _, stc = skm.fit(Xd, k, C, variant, 60, precision=precision)
+    aw, Cw, _, stw = skm.fit(Xd, k, C, variant, 60, warm=(a, s1, s2), precision=precision)
     torch.cuda.synchronize()
     assert torch.equal(ac, aw) and torch.equal(Cc, Cw)
     assert stc.iterations == stw.iterations and stc.converged == stw.converged
