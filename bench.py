@@ -82,6 +82,33 @@ def measured_traffic(kernel, workload, variant):
             "file": os.path.relpath(path, ROOT)}
 
 
+def walk_layout_choices(probs):
+    """Row-walk layouts the compiled tuning table (csrc/walk_tuning.h,
+    written by tune_walk.py) picks for these CSR problems with the FP32
+    copy: problems per (padded width, row-length class, layout)."""
+    import re
+    path = os.path.join(ROOT, "paper_2107_04074_amd", "csrc", "walk_tuning.h")
+    text = open(path).read()
+    short = int(re.search(r"kWalkTuneShortRow\s*=\s*(\d+)", text).group(1))
+    body = re.search(r"kWalkTune\[kWalkTuneRowClasses\]\[kWalkTuneWidths\]\s*=\s*\{(.*?)\};",
+                     text, re.S).group(1)
+    table = [[int(v) for v in r.split(",")] for r in re.findall(r"\{([^{}]*)\}", body)]
+    counts = {}
+    for X, k, _, _ in probs:
+        kp = 16
+        while kp < k:
+            kp *= 2
+        if kp > 256:
+            continue
+        rc = 0 if X.nnz < short * X.n else 1
+        lay = table[rc][kp.bit_length() - 5]
+        key = "kp%d_%s_%s" % (kp, "short" if rc == 0 else "long",
+                              "alternative" if lay else "default")
+        counts[key] = counts.get(key, 0) + 1
+    return {"table": table, "tuner": "paper_2107_04074_amd/tune_walk.py",
+            "problems": dict(sorted(counts.items()))}
+
+
 def split(v, dense):
     """'<variant>' with an optional precision suffix: '_fp32' (FP32
     similarities), '_bf16' (dense: BF16 matrix cores), '_fp16' (CSR: FP16
@@ -431,6 +458,7 @@ def run_batched(dev, variant, steps, warmup, workers_arg, skip_baseline, no_cpu,
         "sequential_gpu_lloyd": None if base_s is None else {
             "ms": round(base_s * 1e3, 3), "iters_per_s": round(total_steps(base_res) / base_s, 3)},
         "worker_sweep_ms": sweep,
+        "walk_layouts": walk_layout_choices(probs),
         "sims_per_s_raw": round(sims / elapsed, 1),
         "sims_per_s_lloyd_equiv": round(lloyd_sims / elapsed, 1),
         "sims_fraction": round(sims / max(lloyd_sims, 1), 4),

@@ -142,7 +142,18 @@ typedef struct {            /* [host]; an all-zero struct means defaults      */
                                are the same either way; only work differs.  */
   int32_t batch_tile_rows;  /* skm_fit_batched in lockstep (workers = 0): rows
                                per work item of the batched row walk; 0 takes
-                               the measured table compiled into the library */
+                               the table compiled into the library (the
+                               lockstep driver is switched off in this
+                               build, so the value is not used) */
+  int32_t walk_layout;      /* Lloyd, Hamerly and simplified Hamerly fits on
+                               CSR rows with the FP32 centre copy and
+                               16 < k <= 256: 0 = the layout the library's
+                               tuning table (measured by tune_walk.py) picks
+                               for k and the mean row length; 1 = the
+                               default layout; 2 = the alternative (one row
+                               per wave throughout).  Results are identical;
+                               only speed differs.  Other fits ignore it.  */
+  int32_t reserved1;        /* must be 0 */
 } skm_options;
 
 typedef struct {            /* [host] filled by skm_fit                       */

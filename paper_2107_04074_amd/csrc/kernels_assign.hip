@@ -1324,7 +1324,11 @@ hipError_t launch_assign_mode(const AssignArgs& A, hipStream_t s) {
   const Geometry g = pick_geometry(A.k);
   if (g.G == 0 || g.kp != A.kp) return hipErrorInvalidValue;
   const bool half = A.CT16 != nullptr && A.kp >= 128;
-  const int gpb = (half || g.G >= 32) ? kBlock / 64 : kBlock / g.G;  // rows per block
+  // the alternative layout (one row per wave throughout) of the measured
+  // table: FP32 copy, k in (16, 256], plain and Hamerly walks
+  constexpr bool kLayouts = MODE == kModeFit || MODE == kModeHamerly;
+  const bool alt = kLayouts && !half && A.layout == 1 && A.kp >= 32 && A.kp <= 256;
+  const int gpb = (half || g.G >= 32 || alt) ? kBlock / 64 : kBlock / g.G;  // rows per block
   int64_t blocks = (A.n_rows + gpb - 1) / gpb;
   if (blocks > kMaxGridBlocks) blocks = kMaxGridBlocks;
   if (blocks < 1) blocks = 1;
@@ -1347,6 +1351,21 @@ hipError_t launch_assign_mode(const AssignArgs& A, hipStream_t s) {
         return hipErrorInvalidValue;
     }
   } else {
+    if constexpr (kLayouts) {
+      if (alt) {
+        // one row per wave: sub-waves of 8 / 16 lanes (k <= 64), or of 16 /
+        // 32 lanes holding two 16-byte units each (k <= 256)
+        switch (A.kp) {
+          SKM_CASE(32, 8, 1, 4, true)
+          SKM_CASE(64, 16, 1, 4, true)
+          SKM_CASE(128, 16, 2, 4, true)
+          SKM_CASE(256, 32, 2, 4, true)
+          default:
+            return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+      }
+    }
     // k <= 64: several rows per wave (groups of 4..16 lanes); k in (64, 128]:
     // one row per wave, half-waves on alternating entries; larger k: one row
     // per wave, R float4 chunks per lane

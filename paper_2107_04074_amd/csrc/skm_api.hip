@@ -28,6 +28,7 @@
 #include "../../include/skm.h"
 #include "batch_tuning.h"
 #include "skm_internal.h"
+#include "walk_tuning.h"
 
 // Device buffer of skm_assign_noalloc: every GPU that loads this library
 // holds one copy until the process ends.  Host code never passes `scratch`
@@ -939,6 +940,18 @@ constexpr int kCtlBytes = 1024;               // Persist + StepCtl + kStepChunk 
 static_assert(sizeof(Persist) + sizeof(StepCtl) + kStepChunk * sizeof(StepRec) <= kCtlBytes,
               "control block");
 
+// Row-walk layout of a fit's FP32 plain and Hamerly walks: forced by
+// walk_layout (1 default, 2 alternative), else the measured table's entry
+// for the padded width and the mean row length.
+int32_t walk_layout_for(const skm_options& o, int32_t kp, int64_t n, int64_t nnz) {
+  if (o.walk_layout != 0) return o.walk_layout - 1;
+  int c = 0;
+  while ((16 << c) < kp) ++c;
+  if (c >= kWalkTuneWidths) return 0;
+  const int rc = (double)nnz < (double)kWalkTuneShortRow * (double)n ? 0 : 1;
+  return kWalkTune[rc][c];
+}
+
 int width_class(int kp) {
   int c = 0;
   while ((16 << c) < kp) ++c;
@@ -1451,6 +1464,8 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
     return fail(SKM_ERR_INVALID_ARG, "bound_form must be 0 or 1");
   if (o.schedule != 0 && o.schedule != 1)
     return fail(SKM_ERR_INVALID_ARG, "schedule must be 0 or 1");
+  if (o.walk_layout < 0 || o.walk_layout > 2 || o.reserved1 != 0)
+    return fail(SKM_ERR_INVALID_ARG, "walk_layout must be 0, 1 or 2 (reserved1 0)");
   const int nwarm = (o.warm_assign != nullptr) + (o.warm_best != nullptr) +
                     (o.warm_second != nullptr);
   if (nwarm != 0 && nwarm != 3)
@@ -1649,6 +1664,7 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
     // without bound tests: only the plain walk is queued for them, and no
     // Gram kernels before them
     int64_t off_until = INT64_MIN;
+    const int32_t layout = walk_layout_for(o, P.kp, n, X->nnz);
     for (int32_t t0 = warm ? 1 : 0; t0 < max_iter;) {
       const int ch = (int)std::min<int64_t>(kStepChunk, (int64_t)max_iter - t0);
       SKM_HIP(hipMemsetAsync(cnt, 0, (size_t)ch * kCounterSlots * sizeof(Counters), s));
@@ -1690,6 +1706,7 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
         A.ng = P.ng;
         A.gpc = gpc;
         A.gps = gps;
+        A.layout = layout;
         const int plain = P.elkan ? kModeFitElkanInit : kModeFit;
         if (exhaustive || t < off_until) {
           SKM_HIP(walk(A, plain));
@@ -2001,6 +2018,8 @@ int skm_fit_batched(int32_t nprob, const skm_matrix* Xs, const int32_t* ks,
     return fail(SKM_ERR_INVALID_ARG, "bound_form must be 0 or 1");
   if (o.schedule != 0 && o.schedule != 1)
     return fail(SKM_ERR_INVALID_ARG, "schedule must be 0 or 1");
+  if (o.walk_layout < 0 || o.walk_layout > 2 || o.reserved1 != 0)
+    return fail(SKM_ERR_INVALID_ARG, "walk_layout must be 0, 1 or 2 (reserved1 0)");
   if (workers == 0 && lockstep_eligible(nprob, Xs, variant, o)) {
     Lockstep L;
     int rc = plan_lockstep(nprob, Xs, ks, variant, o, &L);

@@ -488,6 +488,31 @@ def test_sparse_k_sweep_matches_oracle(skm, torch_cuda):
                 assert np.linalg.norm(C64 - ref.C, axis=1).max() < 1e-6
 
 
+@pytest.mark.parametrize("layout", [1, 2])
+def test_walk_layouts_match_oracle(skm, torch_cuda, layout):
+    """Both row-walk layouts of the FP32 copy that the tuning table chooses
+    between (walk_layout 1: the default, 2: one row per wave throughout), at k
+    on both sides of every tuned width (16 < k <= 256), short and long rows,
+    Lloyd, Hamerly and simplified Hamerly, tests adaptive and at every step:
+    whole trajectories equal the oracle's."""
+    torch = torch_cuda
+    for mean, seed in ((12.0, 7070), (60.0, 7071)):
+        X = datagen.sparse_tfidf(3100, 2500, mean, seed)
+        Xd = skm.DeviceCSR.from_host(X)
+        for k in (17, 32, 33, 64, 65, 128, 129, 256):
+            C0 = datagen.init_centers_csr(X, datagen.init_rows(X.n, k, 77 + k))
+            ref = oracle.fit(X, C0, "lloyd", 10)
+            for v in ("lloyd", "hamerly", "simp_hamerly"):
+                for sched in (0, 1):
+                    say("case walk layout %d mean row %g k=%d %s schedule=%d" %
+                        (layout, mean, k, v, sched))
+                    a, C, C64, st = run_fit(skm, torch, Xd, C0, k, v, 10, schedule=sched,
+                                            walk_layout=layout)
+                    assert st.iterations == ref.iterations
+                    assert np.array_equal(a, ref.a)
+                    assert np.linalg.norm(C64 - ref.C, axis=1).max() < 1e-6
+
+
 def test_dense_shape_sweep_matches_oracle(skm, torch_cuda):
     """Seeded sweep of small dense shapes (row counts that leave partial
     waves and blocks, widths on both sides of every padded width, k on both
