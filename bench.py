@@ -487,6 +487,76 @@ def run_batched(dev, variant, steps, warmup, workers_arg, skip_baseline, no_cpu,
     return out
 
 
+# Dimensionality experiment (Section 6, the run times on the DBLP
+# author-conference matrix and on its transpose): the same number of stored
+# entries as many short rows over few columns, or as few long rows over many
+# columns.  Seeded synthetic stand-ins with the shapes and densities of Table 1.
+DIMS_SHAPES = (("rows_1842986_x_cols_5236", 1_842_986, 5_236, 2.9),
+               ("rows_5236_x_cols_1842986", 5_236, 1_842_986, 1032.0))
+DIMS_K = (10, 50, 200, 500)
+DIMS_VARIANTS = ("lloyd", "simp_hamerly", "hamerly", "simp_elkan", "elkan", "yinyang")
+
+
+def run_dims(dev, max_iter):
+    """Every variant at every k on both shapes: ms per fit (best of two after
+    a warm-up), the row walks' time in it (HIP events, one more fit), steps,
+    similarities computed (fraction of Lloyd's), rows re-decided in FP64 per
+    step and the centre-centre inner products the full variants evaluated;
+    assignments are checked identical to the Lloyd fit's."""
+    import torch
+    import datagen
+    from paper_2107_04074_amd import skm
+    rows = []
+    for si, (name, n, d, mean) in enumerate(DIMS_SHAPES):
+        t0 = time.time()
+        Xh = datagen.sparse_tfidf(n, d, mean, datagen.BASE_SEED + 60 + si)
+        X = skm.DeviceCSR.from_host(Xh, dev)
+        log("generated %s: n=%d d=%d nnz=%d in %.1fs" % (name, Xh.n, Xh.d, Xh.nnz,
+                                                        time.time() - t0))
+        for k in DIMS_K:
+            init = datagen.init_rows(Xh.n, k, datagen.BASE_SEED + 70 + k)
+            C0 = torch.from_numpy(datagen.init_centers_csr(Xh, init)).to(dev)
+            ref = None
+            for v in DIMS_VARIANTS:
+                ws = torch.empty(skm.workspace_size(X, k, v), dtype=torch.uint8, device=dev)
+
+                def fit():
+                    return skm.fit(X, k, C0, v, max_iter, workspace=ws, want_centers=False,
+                                   per_iter=False)
+                fit()
+                best, (a, _, _, st) = timed(fit, 2)
+                # the row walks' share, from one more fit with events around them
+                st_p = skm.fit(X, k, C0, v, max_iter, workspace=ws, want_centers=False,
+                               per_iter=False, profile=1)[3]
+                if ref is None:
+                    ref = (a, st.iterations, best)
+                row = {"shape": name, "k": k, "variant": v, "ms_per_fit": round(best * 1e3, 3),
+                       "steps": st.iterations,
+                       "speedup_vs_gpu_lloyd": round(ref[2] / best, 3),
+                       "sims_fraction": round(st.sims_point_center /
+                                              (Xh.n * k * st.iterations), 4),
+                       "centre_centre_products": st.sims_center_center,
+                       "fp64_redecided_rows_per_step": round(st.rechecks / st.iterations, 1),
+                       "row_walk_ms_per_fit": round(st_p.sim_kernel_ms, 3),
+                       "identical": bool(torch.equal(a, ref[0])) and st.iterations == ref[1]}
+                rows.append(row)
+                log("%s k=%d %-13s %9.3f ms/fit  walks %8.3f ms  steps %d  sims %.3f  cc %d  "
+                    "redecided/step %d  identical %s" % (
+                        name, k, v, best * 1e3, st_p.sim_kernel_ms, st.iterations,
+                        row["sims_fraction"], st.sims_center_center,
+                        st.rechecks // max(st.iterations, 1), row["identical"]))
+                del ws
+        del X
+        torch.cuda.empty_cache()
+    return {"config": {"workload": "dims: shapes of the DBLP author-conference matrix and its "
+                                   "transpose (1842986 x 5236, 2.9 entries per row; 5236 x "
+                                   "1842986, 1032 per row), k in %s, at most %d steps, FP32 "
+                                   "copy" % (list(DIMS_K), max_iter),
+                       "parallelism": "single GPU"},
+            "dtype": "f32", "table": rows,
+            "all_identical": all(r["identical"] for r in rows)}
+
+
 SPARSE_TABLE = {
     "c2": ["lloyd", "simp_hamerly", "hamerly", "simp_elkan", "elkan", "yinyang",
            "lloyd_fp16", "hamerly_fp16", "yinyang_fp16"],
@@ -504,8 +574,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--variant", default="hamerly")
     ap.add_argument("--workload", default="all",
-                    choices=["all", "c1", "c2", "c3", "c4", "c5"],
-                    help="all (default): c3 headline, then c4, c5 and c2 as secondary records")
+                    choices=["all", "c1", "c2", "c3", "c4", "c5", "dims"],
+                    help="all (default): c3 headline, then c4, c5 and c2 as secondary "
+                         "records; dims: the dimensionality experiment (not timed by default)")
     ap.add_argument("--workers", type=int, default=0,
                     help="c5: concurrent streams of the batched fit (0 = sweep 1, 2, 4, 8 "
                          "untimed and keep the fastest)")
@@ -546,6 +617,12 @@ def main():
     common = {"metric": METRIC, "unit": "iters/s", "n_gpus": 1, "steps": args.steps,
               "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
               "vs_baseline": None, "data": "synthetic"}
+
+    if head == "dims":
+        out = dict(common)
+        out.update(run_dims(dev, args.max_iter or 20))
+        print(json.dumps(out), flush=True)
+        return
 
     if head == "c5":
         rec = run_batched(dev, args.variant, args.steps, args.warmup, args.workers,

@@ -169,7 +169,27 @@ int check_init_norms(const double* initnorm, int32_t k, double tol, hipStream_t 
   return SKM_OK;
 }
 
-int make_plan(const skm_matrix* X, int32_t k, int32_t variant, int32_t precision, Plan* P) {
+// An FP32 centre copy above this size does not fit the 256 MB last-level
+// cache; a 256-centre slice of it does (measured on the large sparse
+// workload: 1.38 times faster than whole rows at a 410 MB copy).
+constexpr double kChunkAlwaysBytes = 256.0 * 1024.0 * 1024.0;
+
+// Whether a fit's FP32 row walk takes 256 centres per launch (chunk_walk 1)
+// or whole rows (2); 0: always sliced for Elkan and Yin-Yang and when the
+// copy exceeds the last-level cache, else the measured table's entry.
+bool chunk_fp32(int32_t chunk_walk, bool packed, int64_t n, int64_t d, int64_t nnz, int kp) {
+  if (kp <= kChunkF32) return false;
+  if (packed || chunk_walk == 1) return true;
+  if (chunk_walk == 2) return false;
+  if ((double)d * (double)kp * 4.0 > kChunkAlwaysBytes) return true;
+  int c = 0;
+  while ((512 << c) < kp) ++c;
+  const int rc = (double)nnz < (double)kWalkTuneShortRow * (double)n ? 0 : 1;
+  return kChunkTune[rc][c < kChunkTuneWidths ? c : kChunkTuneWidths - 1] != 0;
+}
+
+int make_plan(const skm_matrix* X, int32_t k, int32_t variant, int32_t precision, Plan* P,
+              int32_t chunk_walk = 0) {
   int rc = check_matrix(X);
   if (rc != SKM_OK) return rc;
   if (precision != 0 && precision != 2)
@@ -243,12 +263,15 @@ int make_plan(const skm_matrix* X, int32_t k, int32_t variant, int32_t precision
   P->maxeta = take(kCounterSlots * sizeof(float));
   P->initnorm = take(kk * sizeof(double));
   P->vbad = take(sizeof(unsigned long long));
-  // Every CSR variant walks a wide FP32 centre copy a chunk of 1 KB per
-  // centre row at a time: the walk streams those fastest, and a chunk's
-  // slice of the copy is at most a quarter of it (k <= 1024), which the
-  // last-level cache holds where the whole copy does not.  Elkan keeps one
-  // survival word per row and 256-centre slice.
-  if (!P->half && g.kp > kChunkF32) {
+  // A wide FP32 centre copy is walked a chunk of 1 KB per centre row at a
+  // time where that pays (chunk_fp32): the walk streams those fastest, and a
+  // chunk's slice of the copy is at most a quarter of it (k <= 1024), which
+  // the last-level cache holds where the whole copy does not; short rows and
+  // cache-resident copies can favour one launch over whole rows instead
+  // (the measured table).  Elkan and Yin-Yang always slice (their walks pack
+  // each slice's surviving centres); Elkan keeps one survival word per row
+  // and 256-centre slice.
+  if (!P->half && chunk_fp32(chunk_walk, P->elkan || P->yy, P->n, P->d, P->nnz, g.kp)) {
     P->chunk = kChunkF32;
     P->nq = (k + kChunkF32 - 1) / kChunkF32;
     P->rs = take(n * sizeof(RowRun));
@@ -1366,7 +1389,13 @@ size_t skm_workspace_size(const skm_matrix* X, int32_t k, int32_t variant,
     return D.total;
   }
   Plan P;
-  if (make_plan(X, k, variant, opt ? opt->precision : 0, &P) != SKM_OK) return 0;
+  if (opt && (opt->chunk_walk < 0 || opt->chunk_walk > 2)) {
+    fail(SKM_ERR_INVALID_ARG, "chunk_walk must be 0, 1 or 2");
+    return 0;
+  }
+  if (make_plan(X, k, variant, opt ? opt->precision : 0, &P, opt ? opt->chunk_walk : 0) !=
+      SKM_OK)
+    return 0;
   return P.total;
 }
 
@@ -1464,8 +1493,10 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
     return fail(SKM_ERR_INVALID_ARG, "bound_form must be 0 or 1");
   if (o.schedule != 0 && o.schedule != 1)
     return fail(SKM_ERR_INVALID_ARG, "schedule must be 0 or 1");
-  if (o.walk_layout < 0 || o.walk_layout > 2 || o.reserved1 != 0)
-    return fail(SKM_ERR_INVALID_ARG, "walk_layout must be 0, 1 or 2 (reserved1 0)");
+  if (o.walk_layout < 0 || o.walk_layout > 2)
+    return fail(SKM_ERR_INVALID_ARG, "walk_layout must be 0, 1 or 2");
+  if (o.chunk_walk < 0 || o.chunk_walk > 2)
+    return fail(SKM_ERR_INVALID_ARG, "chunk_walk must be 0, 1 or 2");
   const int nwarm = (o.warm_assign != nullptr) + (o.warm_best != nullptr) +
                     (o.warm_second != nullptr);
   if (nwarm != 0 && nwarm != 3)
@@ -1476,7 +1507,7 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
                      assign_out, centers_out, centers64_out, stats, static_cast<hipStream_t>(stream));
   }
   Plan P;
-  int rc = make_plan(X, k, variant, o.precision, &P);
+  int rc = make_plan(X, k, variant, o.precision, &P, o.chunk_walk);
   if (rc != SKM_OK) return rc;
   if (workspace && workspace_bytes < P.total)
     return fail(SKM_ERR_OUT_OF_MEMORY, "workspace has %zu bytes, %zu needed", workspace_bytes,
@@ -2018,8 +2049,10 @@ int skm_fit_batched(int32_t nprob, const skm_matrix* Xs, const int32_t* ks,
     return fail(SKM_ERR_INVALID_ARG, "bound_form must be 0 or 1");
   if (o.schedule != 0 && o.schedule != 1)
     return fail(SKM_ERR_INVALID_ARG, "schedule must be 0 or 1");
-  if (o.walk_layout < 0 || o.walk_layout > 2 || o.reserved1 != 0)
-    return fail(SKM_ERR_INVALID_ARG, "walk_layout must be 0, 1 or 2 (reserved1 0)");
+  if (o.walk_layout < 0 || o.walk_layout > 2)
+    return fail(SKM_ERR_INVALID_ARG, "walk_layout must be 0, 1 or 2");
+  if (o.chunk_walk < 0 || o.chunk_walk > 2)
+    return fail(SKM_ERR_INVALID_ARG, "chunk_walk must be 0, 1 or 2");
   if (workers == 0 && lockstep_eligible(nprob, Xs, variant, o)) {
     Lockstep L;
     int rc = plan_lockstep(nprob, Xs, ks, variant, o, &L);

@@ -45,7 +45,7 @@ class SkmOptions(ctypes.Structure):
                 ("norm_tol", ctypes.c_double), ("warm_assign", ctypes.c_void_p),
                 ("warm_best", ctypes.c_void_p), ("warm_second", ctypes.c_void_p),
                 ("schedule", ctypes.c_int32), ("batch_tile_rows", ctypes.c_int32),
-                ("walk_layout", ctypes.c_int32), ("reserved1", ctypes.c_int32)]
+                ("walk_layout", ctypes.c_int32), ("chunk_walk", ctypes.c_int32)]
 
 
 class SkmStats(ctypes.Structure):
@@ -207,16 +207,18 @@ class FitStats:
 
 
 def _options(bound_form=0, precision=0, validate=0, norm_tol=0.0, profile=0, warm=None,
-             schedule=0, batch_tile_rows=0, walk_layout=0):
+             schedule=0, batch_tile_rows=0, walk_layout=0, chunk_walk=0):
     """warm: (assign, best, second) device tensors from seed_kmeanspp;
     schedule: 1 runs the bound tests at every step (0 = adaptive);
     batch_tile_rows: rows per work item of the lockstep batched walk (0 =
     the library's table; that driver is switched off);
     walk_layout: row-walk layout of FP32 Lloyd/Hamerly fits at 16 < k <= 256
-    (0 = the library's tuning table, 1 = default layout, 2 = alternative)."""
+    (0 = the library's tuning table, 1 = default layout, 2 = alternative);
+    chunk_walk: FP32 Lloyd/Hamerly fits at 256 < k: 0 = the tuning table
+    (sliced above a 256 MB copy), 1 = 256-centre slices, 2 = whole rows."""
     w = (None, None, None) if warm is None else tuple(_ptr(t) for t in warm)
     return SkmOptions(bound_form, precision, validate, profile, norm_tol, *w, schedule,
-                      batch_tile_rows, walk_layout, 0)
+                      batch_tile_rows, walk_layout, chunk_walk)
 
 
 def seed_kmeanspp(X: "DeviceCSR | DeviceDense", k: int, uniforms, alpha: float = 1.0,

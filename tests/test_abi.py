@@ -101,11 +101,15 @@ def test_invalid_arguments_are_rejected(lib):
     rc = lib.skm_fit(ctypes.byref(m), 3, 0x5000, 0, 5, ctypes.byref(bad), None, 0, 0x4000,
                      None, None, ctypes.byref(st), None)
     assert rc == skm.ERR_INVALID_ARG and b"schedule" in lib.skm_last_error()
-    for layout, res in ((3, 0), (-1, 0), (1, 5)):  # walk_layout out of range, reserved1 set
-        bad = skm.SkmOptions(0, 0, 0, 0, 0.0, None, None, None, 0, 0, layout, res)
+    for layout, cw, what in ((3, 0, b"walk_layout"), (-1, 0, b"walk_layout"),
+                             (0, 3, b"chunk_walk"), (1, -1, b"chunk_walk")):
+        bad = skm.SkmOptions(0, 0, 0, 0, 0.0, None, None, None, 0, 0, layout, cw)
         rc = lib.skm_fit(ctypes.byref(m), 3, 0x5000, 0, 5, ctypes.byref(bad), None, 0, 0x4000,
                          None, None, ctypes.byref(st), None)
-        assert rc == skm.ERR_INVALID_ARG and b"walk_layout" in lib.skm_last_error()
+        assert rc == skm.ERR_INVALID_ARG and what in lib.skm_last_error()
+    bad = skm.SkmOptions(0, 0, 0, 0, 0.0, None, None, None, 0, 0, 0, 4)
+    assert lib.skm_workspace_size(ctypes.byref(m), 3, skm.HAMERLY, ctypes.byref(bad)) == 0
+    assert b"chunk_walk" in lib.skm_last_error()
     # undersized caller workspace
     rc = lib.skm_fit(ctypes.byref(m), 3, 0x5000, 0, 5, None, 0x6000, 16, 0x4000, None, None,
                      ctypes.byref(st), None)
@@ -236,9 +240,10 @@ def test_centre_copy_offsets_fit_32_bits(lib):
 
 
 def test_walk_tuning_table_is_well_formed():
-    """The compiled row-walk layout table (written by tune_walk.py): one
+    """The compiled row-walk tables (written by tune_walk.py): layouts, one
     entry per row-length class and padded width kp = 16 ... 256, each 0 or
-    1, and kp = 16 (no alternative layout) always 0."""
+    1, kp = 16 (no alternative layout) always 0; slicing, one entry per
+    class and kp = 512 ... 4096, each 0 or 1."""
     path = os.path.join(os.path.dirname(skm.__file__), "csrc", "walk_tuning.h")
     text = open(path).read()
     body = re.search(r"kWalkTune\[kWalkTuneRowClasses\]\[kWalkTuneWidths\]\s*=\s*\{(.*?)\};",
@@ -247,3 +252,8 @@ def test_walk_tuning_table_is_well_formed():
     assert len(rows) == 2 and all(len(r) == 5 for r in rows)
     assert all(v in (0, 1) for r in rows for v in r)
     assert all(r[0] == 0 for r in rows)
+    body = re.search(r"kChunkTune\[kWalkTuneRowClasses\]\[kChunkTuneWidths\]\s*=\s*\{(.*?)\};",
+                     text, re.S).group(1)
+    rows = [[int(v) for v in r.split(",")] for r in re.findall(r"\{([^{}]*)\}", body)]
+    assert len(rows) == 2 and all(len(r) == 4 for r in rows)
+    assert all(v in (0, 1) for r in rows for v in r)

@@ -95,10 +95,11 @@ def test_batched_chunked_problems(skm, torch_cuda, variant, precision):
         probs.append((Xd, k, torch.from_numpy(C0).cuda(), 12))
         refs.append((X, C0))
     say("case batched chunked %s precision=%d" % (variant, precision))
-    res = skm.fit_batched(probs, variant, workers=3, precision=precision)
+    res = skm.fit_batched(probs, variant, workers=3, precision=precision, chunk_walk=1)
     torch.cuda.synchronize()
     for (Xd, k, C0, it), (a, C, st), (X, C0h) in zip(probs, res, refs):
-        a1, C1, _, st1 = skm.fit(Xd, k, C0, variant, it, per_iter=False, precision=precision)
+        a1, C1, _, st1 = skm.fit(Xd, k, C0, variant, it, per_iter=False, precision=precision,
+                                 chunk_walk=1)
         torch.cuda.synchronize()
         assert torch.equal(a, a1) and torch.equal(C, C1), k
         assert st.iterations == st1.iterations, k

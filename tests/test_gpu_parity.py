@@ -269,7 +269,10 @@ def test_fit_chunked_group_walks(skm, torch_cuda, k):
                            ("yinyang", 1, 2), ("yinyang", 0, 2), ("elkan", 1, 2),
                            ("simp_elkan", 0, 2)]:
         say("case chunked group walks %s schedule=%d precision=%d" % (v, sched, prec))
-        a, C, C64, st = run_fit(skm, torch, Xd, C0, k, v, T, schedule=sched, precision=prec)
+        # chunk_walk = 1: Lloyd and Hamerly slice too (their choice is the
+        # tuning table's otherwise; Elkan and Yin-Yang always slice)
+        a, C, C64, st = run_fit(skm, torch, Xd, C0, k, v, T, schedule=sched, precision=prec,
+                                chunk_walk=1)
         say("  iters=%d sims=%d of %d" % (st.iterations, st.sims_point_center,
                                           X.n * k * st.iterations))
         if v in ("yinyang", "elkan") and sched == 1:
@@ -302,7 +305,8 @@ def test_fit_chunked_duplicate_centres(skm, torch_cuda):
     for v in VARIANTS:
         for prec in (0, 2):
             say("case chunked duplicate centres %s precision=%d" % (v, prec))
-            a, C, C64, st = run_fit(skm, torch, Xd, C0, k, v, T, schedule=1, precision=prec)
+            a, C, C64, st = run_fit(skm, torch, Xd, C0, k, v, T, schedule=1, precision=prec,
+                                    chunk_walk=1)
             assert st.iterations == ref.iterations and st.converged == ref.converged
             assert np.array_equal(st.changed_per_iter, ref.changed)
             assert np.array_equal(a, ref.a)
@@ -480,12 +484,16 @@ def test_sparse_k_sweep_matches_oracle(skm, torch_cuda):
         ref = oracle.fit(X, C0, "lloyd", 8)
         for v in VARIANTS:
             for prec in (0, 2):
-                say("case sparse k sweep k=%d %s precision=%d" % (k, v, prec))
-                a, C, C64, st = run_fit(skm, torch, Xd, C0, k, v, 8, precision=prec,
-                                        schedule=1)
-                assert st.iterations == ref.iterations
-                assert np.array_equal(a, ref.a)
-                assert np.linalg.norm(C64 - ref.C, axis=1).max() < 1e-6
+                # FP32 Lloyd / Hamerly above 256 centres: 256-centre slices
+                # and whole rows (the tuning table picks one of them)
+                sliceable = prec == 0 and k > 256 and v in ("lloyd", "hamerly", "simp_hamerly")
+                for cw in ((1, 2) if sliceable else (0,)):
+                    say("case sparse k sweep k=%d %s precision=%d chunk_walk=%d" % (k, v, prec, cw))
+                    a, C, C64, st = run_fit(skm, torch, Xd, C0, k, v, 8, precision=prec,
+                                            schedule=1, chunk_walk=cw)
+                    assert st.iterations == ref.iterations
+                    assert np.array_equal(a, ref.a)
+                    assert np.linalg.norm(C64 - ref.C, axis=1).max() < 1e-6
 
 
 @pytest.mark.parametrize("layout", [1, 2])

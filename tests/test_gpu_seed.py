@@ -69,8 +69,9 @@ def test_warm_start_equals_cold_fit(skm, torch_cuda, variant, k, precision):
     Xd = skm.DeviceCSR.from_host(X)
     ch, C, a, s1, s2 = skm.seed_kmeanspp(Xd, k, u)
     say("case warm start %s k=%d precision=%d" % (variant, k, precision))
-    ac, Cc, _, stc = skm.fit(Xd, k, C, variant, 60, precision=precision)
-    aw, Cw, _, stw = skm.fit(Xd, k, C, variant, 60, warm=(a, s1, s2), precision=precision)
+    ac, Cc, _, stc = skm.fit(Xd, k, C, variant, 60, precision=precision, chunk_walk=1)
+    aw, Cw, _, stw = skm.fit(Xd, k, C, variant, 60, warm=(a, s1, s2), precision=precision,
+                             chunk_walk=1)
     torch.cuda.synchronize()
     assert torch.equal(ac, aw) and torch.equal(Cc, Cw)
     assert stc.iterations == stw.iterations and stc.converged == stw.converged
