@@ -153,18 +153,17 @@ typedef struct {            /* [host]; an all-zero struct means defaults      */
                                default layout; 2 = the alternative (one row
                                per wave throughout).  Results are identical;
                                only speed differs.  Other fits ignore it.  */
-  int32_t chunk_walk;       /* CSR rows, FP32 centre copy, 256 < k <= 4096,
-                               Lloyd, Hamerly and simplified Hamerly fits:
+  int32_t chunk_walk;       /* CSR rows, FP32 centre copy, 256 < k <= 4096:
                                0 = walk the centres 256 at a time (one
-                               launch per slice) or whole rows (one launch)
-                               as the library's tuning table (measured by
-                               tune_walk.py) picks for k and the mean row
-                               length, always sliced when the copy exceeds
-                               256 MB; 1 = always sliced; 2 = always whole
-                               rows.  Elkan and Yin-Yang always slice there
-                               (their walks pack the surviving centres of
-                               each slice).  Results are identical; only
-                               speed and workspace size differ.          */
+                               launch per slice; Elkan and Yin-Yang pack
+                               each slice's surviving centres) or whole rows
+                               (one launch) as the library's tuning table
+                               (measured by tune_walk.py) picks for the
+                               variant, k and the mean row length, always
+                               sliced when the copy exceeds 256 MB; 1 =
+                               always sliced; 2 = always whole rows.
+                               Results are identical; only speed and
+                               workspace size differ.                     */
 } skm_options;
 
 typedef struct {            /* [host] filled by skm_fit                       */

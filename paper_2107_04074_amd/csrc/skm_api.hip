@@ -175,17 +175,18 @@ int check_init_norms(const double* initnorm, int32_t k, double tol, hipStream_t 
 constexpr double kChunkAlwaysBytes = 256.0 * 1024.0 * 1024.0;
 
 // Whether a fit's FP32 row walk takes 256 centres per launch (chunk_walk 1)
-// or whole rows (2); 0: always sliced for Elkan and Yin-Yang and when the
-// copy exceeds the last-level cache, else the measured table's entry.
-bool chunk_fp32(int32_t chunk_walk, bool packed, int64_t n, int64_t d, int64_t nnz, int kp) {
+// or whole rows (2); 0: always sliced when the copy exceeds the last-level
+// cache, else the measured table's entry for the variant's family (0 Lloyd
+// and Hamerly, 1 Elkan, 2 Yin-Yang), the row-length class and the width.
+bool chunk_fp32(int32_t chunk_walk, int family, int64_t n, int64_t d, int64_t nnz, int kp) {
   if (kp <= kChunkF32) return false;
-  if (packed || chunk_walk == 1) return true;
+  if (chunk_walk == 1) return true;
   if (chunk_walk == 2) return false;
   if ((double)d * (double)kp * 4.0 > kChunkAlwaysBytes) return true;
   int c = 0;
   while ((512 << c) < kp) ++c;
   const int rc = (double)nnz < (double)kWalkTuneShortRow * (double)n ? 0 : 1;
-  return kChunkTune[rc][c < kChunkTuneWidths ? c : kChunkTuneWidths - 1] != 0;
+  return kChunkTune[family][rc][c < kChunkTuneWidths ? c : kChunkTuneWidths - 1] != 0;
 }
 
 int make_plan(const skm_matrix* X, int32_t k, int32_t variant, int32_t precision, Plan* P,
@@ -264,14 +265,15 @@ int make_plan(const skm_matrix* X, int32_t k, int32_t variant, int32_t precision
   P->initnorm = take(kk * sizeof(double));
   P->vbad = take(sizeof(unsigned long long));
   // A wide FP32 centre copy is walked a chunk of 1 KB per centre row at a
-  // time where that pays (chunk_fp32): the walk streams those fastest, and a
+  // time where that pays (chunk_fp32): the walk streams those fastest, a
   // chunk's slice of the copy is at most a quarter of it (k <= 1024), which
-  // the last-level cache holds where the whole copy does not; short rows and
+  // the last-level cache holds where the whole copy does not, and Elkan and
+  // Yin-Yang pack each slice's surviving centres; short rows and
   // cache-resident copies can favour one launch over whole rows instead
-  // (the measured table).  Elkan and Yin-Yang always slice (their walks pack
-  // each slice's surviving centres); Elkan keeps one survival word per row
-  // and 256-centre slice.
-  if (!P->half && chunk_fp32(chunk_walk, P->elkan || P->yy, P->n, P->d, P->nnz, g.kp)) {
+  // (the measured table).  Elkan keeps one survival word per row and
+  // 256-centre slice.
+  if (!P->half && chunk_fp32(chunk_walk, P->elkan ? 1 : P->yy ? 2 : 0, P->n, P->d, P->nnz,
+                             g.kp)) {
     P->chunk = kChunkF32;
     P->nq = (k + kChunkF32 - 1) / kChunkF32;
     P->rs = take(n * sizeof(RowRun));

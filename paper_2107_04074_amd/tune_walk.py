@@ -8,14 +8,16 @@ csrc/walk_tuning.h:
     skm_options.walk_layout 1 (default) against 2 (one row per wave
     throughout); the alternative is taken when at least 2% faster;
   - slicing, kp = 512, 1024, 2048, 4096 (10,000 columns, so every copy stays
-    below the 256 MB the library always slices above): chunk_walk 1 (256
-    centres per launch) against 2 (whole rows in one launch); whole rows are
-    taken when at least 2% faster.
+    below the 256 MB the library always slices above), per variant family
+    (Lloyd and Hamerly; simplified and full Elkan; Yin-Yang): chunk_walk 1
+    (256 centres per launch) against 2 (whole rows in one launch); whole
+    rows are taken when at least 2% faster.
 
-Each cell times a Lloyd and a Hamerly fit (k = 3 kp / 4, 15 steps at most),
-best of the repetitions.  Both alternatives must give identical assignments
-(the exact argmax does not depend on the FP32 summation order or the
-launch split); the tuner stops with an error if they do not.
+Each cell times one fit of every variant of its family (layouts: Lloyd and
+Hamerly; k = 3 kp / 4, 15 steps at most), best of the repetitions.  Both
+alternatives must give identical assignments (the exact argmax does not
+depend on the FP32 summation order or the launch split); the tuner stops
+with an error if they do not.
 
     python -m paper_2107_04074_amd.tune_walk [--out PATH] [--reps 5]
 
@@ -33,16 +35,17 @@ LAYOUT_WIDTHS = (32, 64, 128, 256)      # kp = 16 has only the default layout
 CHUNK_WIDTHS = (512, 1024, 2048, 4096)
 N_ROWS, STEPS, SEED = 20_000, 15, 20_240_611
 D_LAYOUT, D_CHUNK = 20_000, 10_000
+FAMILIES = (("lloyd", "hamerly"), ("simp_elkan", "elkan"), ("yinyang",))
 
 
-def _walk_times(skm, torch, X, k, C0, ws, reps, **opt):
-    """Best row-walk time (profile = 1) over `reps` of a Lloyd fit and of a
-    Hamerly fit, summed, in seconds, and the assignments."""
-    best = [1e30, 1e30]
+def _walk_times(skm, torch, X, k, C0, ws, reps, variants, **opt):
+    """Best row-walk time (profile = 1) over `reps` of a fit of each variant,
+    summed, in seconds, and the assignments."""
+    best = [1e30] * len(variants)
     out = []
     for _ in range(reps):
         out = []
-        for i, var in enumerate(("lloyd", "hamerly")):
+        for i, var in enumerate(variants):
             a, _, _, st = skm.fit(X, k, C0, var, STEPS, workspace=ws, want_centers=False,
                                   per_iter=False, profile=1, **opt)
             torch.cuda.synchronize()
@@ -51,16 +54,15 @@ def _walk_times(skm, torch, X, k, C0, ws, reps, **opt):
     return sum(best), out
 
 
-def _compare(skm, torch, X, Xh, k, reps, opt_a, opt_b, what, datagen, dev):
+def _compare(skm, torch, X, Xh, k, reps, variants, opt_a, opt_b, what, datagen, dev):
     init = datagen.init_rows(Xh.n, k, SEED + k)
     C0 = torch.from_numpy(datagen.init_centers_csr(Xh, init)).to(dev)
-    size = max(skm.workspace_size(X, k, "hamerly", **opt_a),
-               skm.workspace_size(X, k, "hamerly", **opt_b))
+    size = max(skm.workspace_size(X, k, v, **o) for v in variants for o in (opt_a, opt_b))
     ws = torch.empty(size, dtype=torch.uint8, device=dev)
-    _walk_times(skm, torch, X, k, C0, ws, 1, **opt_a)  # warm-up of every kernel
-    _walk_times(skm, torch, X, k, C0, ws, 1, **opt_b)
-    ta, aa = _walk_times(skm, torch, X, k, C0, ws, reps, **opt_a)
-    tb, ab = _walk_times(skm, torch, X, k, C0, ws, reps, **opt_b)
+    _walk_times(skm, torch, X, k, C0, ws, 1, variants, **opt_a)  # warm-up of every kernel
+    _walk_times(skm, torch, X, k, C0, ws, 1, variants, **opt_b)
+    ta, aa = _walk_times(skm, torch, X, k, C0, ws, reps, variants, **opt_a)
+    tb, ab = _walk_times(skm, torch, X, k, C0, ws, reps, variants, **opt_b)
     for x, y in zip(aa, ab):
         if not torch.equal(x, y):
             raise RuntimeError("%s: the alternatives disagree at k=%d" % (what, k))
@@ -75,7 +77,7 @@ def tune(out_path: str, reps: int = 5):
 
     dev = torch.device("cuda:0")
     layout = [[0] * 5 for _ in ROW_CLASSES]
-    chunk = [[1] * 4 for _ in ROW_CLASSES]
+    chunk = [[[1] * 4 for _ in ROW_CLASSES] for _ in FAMILIES]
     notes = []
     for rc, mean in ROW_CLASSES:
         for d, widths in ((D_LAYOUT, LAYOUT_WIDTHS), (D_CHUNK, CHUNK_WIDTHS)):
@@ -84,21 +86,26 @@ def tune(out_path: str, reps: int = 5):
             for kp in widths:
                 k = 3 * kp // 4
                 if kp <= 256:
-                    t0, t1 = _compare(skm, torch, X, Xh, k, reps, {"walk_layout": 1},
-                                      {"walk_layout": 2}, "layouts", datagen, dev)
+                    t0, t1 = _compare(skm, torch, X, Xh, k, reps, FAMILIES[0],
+                                      {"walk_layout": 1}, {"walk_layout": 2}, "layouts",
+                                      datagen, dev)
                     pick = 1 if t1 < 0.98 * t0 else 0
                     layout[rc][kp.bit_length() - 5] = pick
                     note = ("layout kp %4d, mean row %2d, d %d: %.3f ms default, %.3f ms "
                             "alternative -> %d" % (kp, int(mean), d, t0 * 1e3, t1 * 1e3, pick))
-                else:
-                    t0, t1 = _compare(skm, torch, X, Xh, k, reps, {"chunk_walk": 1},
+                    notes.append(note)
+                    print(note, flush=True)
+                    continue
+                for fam, variants in enumerate(FAMILIES):
+                    t0, t1 = _compare(skm, torch, X, Xh, k, reps, variants, {"chunk_walk": 1},
                                       {"chunk_walk": 2}, "slicing", datagen, dev)
                     pick = 0 if t1 < 0.98 * t0 else 1
-                    chunk[rc][kp.bit_length() - 10] = pick
-                    note = ("slices kp %4d, mean row %2d, d %d: %.3f ms sliced, %.3f ms whole "
-                            "rows -> %d" % (kp, int(mean), d, t0 * 1e3, t1 * 1e3, pick))
-                notes.append(note)
-                print(note, flush=True)
+                    chunk[fam][rc][kp.bit_length() - 10] = pick
+                    note = ("slices %-18s kp %4d, mean row %2d, d %d: %.3f ms sliced, %.3f ms "
+                            "whole rows -> %d" % ("+".join(variants), kp, int(mean), d,
+                                                  t0 * 1e3, t1 * 1e3, pick))
+                    notes.append(note)
+                    print(note, flush=True)
             del X
             torch.cuda.empty_cache()
     props = torch.cuda.get_device_properties(0)
@@ -114,11 +121,11 @@ def _rows(table):
 
 def _write(path: str, layout, chunk, notes, device: str) -> None:
     body = [
-        "// Row-walk choices of the FP32 centre copy for Lloyd and Hamerly fits, per",
-        "// row-length class (0: under 48 stored entries per row on average, 1: 48",
-        "// or more).  Written by paper_2107_04074_amd/tune_walk.py on %s," % device,
-        "// %d seeded tf-idf rows, k = 3 kp / 4, row-walk time of a Lloyd and a" % N_ROWS,
-        "// Hamerly fit of %d steps at most (HIP events), best of the repetitions:" % STEPS,
+        "// Row-walk choices of the FP32 centre copy, per row-length class (0: under",
+        "// 48 stored entries per row on average, 1: 48 or more).  Written by",
+        "// paper_2107_04074_amd/tune_walk.py on %s, %d seeded" % (device, N_ROWS),
+        "// tf-idf rows, k = 3 kp / 4, summed row-walk time of one fit of every variant",
+        "// of the family (%d steps at most, HIP events), best of the repetitions:" % STEPS,
     ]
     body += ["//   " + n for n in notes]
     body += [
@@ -137,12 +144,15 @@ def _write(path: str, layout, chunk, notes, device: str) -> None:
         "constexpr int kWalkTune[kWalkTuneRowClasses][kWalkTuneWidths] = {",
         _rows(layout),
         "};",
-        "// Slicing per padded width kp = 512, 1024, 2048, 4096 (index log2(kp) - 9)",
-        "// while the copy fits the last-level cache: 1 = walk 256 centres per",
-        "// launch, 0 = whole rows in one launch.",
+        "// Slicing per variant family (0: Lloyd and Hamerly, 1: Elkan, 2: Yin-Yang),",
+        "// row-length class and padded width kp = 512, 1024, 2048, 4096 (index",
+        "// log2(kp) - 9) while the copy fits the last-level cache: 1 = walk 256",
+        "// centres per launch, 0 = whole rows in one launch.",
+        "constexpr int kChunkTuneFamilies = 3;",
         "constexpr int kChunkTuneWidths = 4;",
-        "constexpr int kChunkTune[kWalkTuneRowClasses][kChunkTuneWidths] = {",
-        _rows(chunk),
+        "constexpr int kChunkTune[kChunkTuneFamilies][kWalkTuneRowClasses][kChunkTuneWidths] = {",
+        ",\n".join("    {" + ", ".join("{" + ", ".join(str(v) for v in r) + "}" for r in fam) + "}"
+                   for fam in chunk),
         "};",
         "}  // namespace skm",
         "",

@@ -243,7 +243,7 @@ def test_walk_tuning_table_is_well_formed():
     """The compiled row-walk tables (written by tune_walk.py): layouts, one
     entry per row-length class and padded width kp = 16 ... 256, each 0 or
     1, kp = 16 (no alternative layout) always 0; slicing, one entry per
-    class and kp = 512 ... 4096, each 0 or 1."""
+    variant family, class and kp = 512 ... 4096, each 0 or 1."""
     path = os.path.join(os.path.dirname(skm.__file__), "csrc", "walk_tuning.h")
     text = open(path).read()
     body = re.search(r"kWalkTune\[kWalkTuneRowClasses\]\[kWalkTuneWidths\]\s*=\s*\{(.*?)\};",
@@ -252,8 +252,8 @@ def test_walk_tuning_table_is_well_formed():
     assert len(rows) == 2 and all(len(r) == 5 for r in rows)
     assert all(v in (0, 1) for r in rows for v in r)
     assert all(r[0] == 0 for r in rows)
-    body = re.search(r"kChunkTune\[kWalkTuneRowClasses\]\[kChunkTuneWidths\]\s*=\s*\{(.*?)\};",
-                     text, re.S).group(1)
+    body = re.search(r"kChunkTune\[kChunkTuneFamilies\]\[kWalkTuneRowClasses\]"
+                     r"\[kChunkTuneWidths\]\s*=\s*\{(.*?)\};", text, re.S).group(1)
     rows = [[int(v) for v in r.split(",")] for r in re.findall(r"\{([^{}]*)\}", body)]
-    assert len(rows) == 2 and all(len(r) == 4 for r in rows)
+    assert len(rows) == 3 * 2 and all(len(r) == 4 for r in rows)
     assert all(v in (0, 1) for r in rows for v in r)

@@ -484,9 +484,9 @@ def test_sparse_k_sweep_matches_oracle(skm, torch_cuda):
         ref = oracle.fit(X, C0, "lloyd", 8)
         for v in VARIANTS:
             for prec in (0, 2):
-                # FP32 Lloyd / Hamerly above 256 centres: 256-centre slices
-                # and whole rows (the tuning table picks one of them)
-                sliceable = prec == 0 and k > 256 and v in ("lloyd", "hamerly", "simp_hamerly")
+                # FP32 copy above 256 centres: 256-centre slices and whole
+                # rows (the tuning table picks one of them)
+                sliceable = prec == 0 and k > 256
                 for cw in ((1, 2) if sliceable else (0,)):
                     say("case sparse k sweep k=%d %s precision=%d chunk_walk=%d" % (k, v, prec, cw))
                     a, C, C64, st = run_fit(skm, torch, Xd, C0, k, v, 8, precision=prec,
