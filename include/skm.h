@@ -183,8 +183,9 @@ typedef struct {            /* [host] filled by skm_fit                       */
   int32_t reserved0;
   /* work of the dominant similarity kernel: for CSR input the row-walk
      kernel of each assignment step (one or two launches per step: with and
-     without bound tests, one of which returns at once; with the FP32 centre
-     copy at k > 256 that many per 256-centre slice), for dense input the
+     without bound tests, one of which returns at once; where the FP32 walk
+     slices the centres (k > 256, see chunk_walk) that many per 256-centre
+     slice), for dense input the
      first MFMA similarity pass of each step; steps, rows walked and their
      stored entries (rows x d for dense), and (profile = 1) the summed
      duration from HIP events recorded around each step's launches on
