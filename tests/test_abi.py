@@ -257,3 +257,28 @@ def test_walk_tuning_table_is_well_formed():
     rows = [[int(v) for v in r.split(",")] for r in re.findall(r"\{([^{}]*)\}", body)]
     assert len(rows) == 3 * 2 and all(len(r) == 4 for r in rows)
     assert all(v in (0, 1) for r in rows for v in r)
+
+
+def test_tuner_writes_a_table_the_library_compiles(tmp_path):
+    """tune_walk.py's header writer: its output compiles with the names and
+    shapes the library reads (checked by static_asserts in a host-only
+    translation unit), so a re-measured table drops in without edits."""
+    from paper_2107_04074_amd import tune_walk
+    hdr = tmp_path / "walk_tuning.h"
+    layout = [[0, 1, 0, 1, 0], [0, 0, 1, 1, 0]]
+    chunk = [[[1, 0, 1, 0], [0, 1, 1, 1]], [[1, 1, 0, 0], [0, 0, 1, 1]],
+             [[0, 0, 0, 0], [1, 1, 1, 1]]]
+    tune_walk._write(str(hdr), layout, chunk, ["note"], "test device")
+    src = tmp_path / "t.cc"
+    src.write_text(
+        '#include "walk_tuning.h"\n'
+        "using namespace skm;\n"
+        "static_assert(kWalkTuneWidths == 5 && kWalkTuneRowClasses == 2, \"\");\n"
+        "static_assert(kChunkTuneFamilies == 3 && kChunkTuneWidths == 4, \"\");\n"
+        "static_assert(kWalkTune[1][2] == 1 && kWalkTune[0][4] == 0, \"\");\n"
+        "static_assert(kChunkTune[0][0][2] == 1 && kChunkTune[1][1][3] == 1, \"\");\n"
+        "static_assert(kChunkTune[2][0][0] == 0 && kChunkTune[2][1][0] == 1, \"\");\n"
+        "int main() { return kWalkTuneShortRow == 48 ? 0 : 1; }\n")
+    r = subprocess.run(["g++", "-std=c++17", "-fsyntax-only", "-I", str(tmp_path), str(src)],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
