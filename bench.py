@@ -89,7 +89,8 @@ def walk_layout_choices(probs):
     import re
     path = os.path.join(ROOT, "paper_2107_04074_amd", "csrc", "walk_tuning.h")
     text = open(path).read()
-    short = int(re.search(r"kWalkTuneShortRow\s*=\s*(\d+)", text).group(1))
+    bounds = [int(v) for v in re.search(r"kWalkTuneRowBound\[[^\]]*\]\s*=\s*\{([^}]*)\}",
+                                       text).group(1).split(",")]
     body = re.search(r"kWalkTune\[kWalkTuneRowClasses\]\[kWalkTuneWidths\]\s*=\s*\{(.*?)\};",
                      text, re.S).group(1)
     table = [[int(v) for v in r.split(",")] for r in re.findall(r"\{([^{}]*)\}", body)]
@@ -100,10 +101,11 @@ def walk_layout_choices(probs):
             kp *= 2
         if kp > 256:
             continue
-        rc = 0 if X.nnz < short * X.n else 1
+        rc = 0
+        while rc < len(bounds) and X.nnz >= bounds[rc] * X.n:
+            rc += 1
         lay = table[rc][kp.bit_length() - 5]
-        key = "kp%d_%s_%s" % (kp, "short" if rc == 0 else "long",
-                              "alternative" if lay else "default")
+        key = "kp%d_rowclass%d_%s" % (kp, rc, "alternative" if lay else "default")
         counts[key] = counts.get(key, 0) + 1
     return {"table": table, "tuner": "paper_2107_04074_amd/tune_walk.py",
             "problems": dict(sorted(counts.items()))}

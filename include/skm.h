@@ -146,13 +146,15 @@ typedef struct {            /* [host]; an all-zero struct means defaults      */
                                lockstep driver is switched off in this
                                build, so the value is not used) */
   int32_t walk_layout;      /* Lloyd, Hamerly and simplified Hamerly fits on
-                               CSR rows with the FP32 centre copy and
-                               16 < k <= 256: 0 = the layout the library's
-                               tuning table (measured by tune_walk.py) picks
-                               for k and the mean row length; 1 = the
-                               default layout; 2 = the alternative (one row
-                               per wave throughout).  Results are identical;
-                               only speed differs.  Other fits ignore it.  */
+                               CSR rows with the FP32 centre copy, 16 < k
+                               <= 512, whole-row walks: 0 = the layout the
+                               library's tuning table (measured by
+                               tune_walk.py) picks for k and the mean row
+                               length; 1 = the default layout; 2 = the
+                               alternative (one row per wave at k <= 64,
+                               four rows per wave above).  Results are
+                               identical; only speed differs.  Other fits
+                               ignore it.                                 */
   int32_t chunk_walk;       /* CSR rows, FP32 centre copy, 256 < k <= 4096:
                                0 = walk the centres 256 at a time (one
                                launch per slice; Elkan and Yin-Yang pack

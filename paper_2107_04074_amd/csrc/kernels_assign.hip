@@ -1324,11 +1324,13 @@ hipError_t launch_assign_mode(const AssignArgs& A, hipStream_t s) {
   const Geometry g = pick_geometry(A.k);
   if (g.G == 0 || g.kp != A.kp) return hipErrorInvalidValue;
   const bool half = A.CT16 != nullptr && A.kp >= 128;
-  // the alternative layout (one row per wave throughout) of the measured
-  // table: FP32 copy, k in (16, 256], plain and Hamerly walks
+  // the alternative layout of the measured table (FP32 copy, k in (16, 512],
+  // plain and Hamerly walks): one row per wave at k <= 64, four rows per
+  // wave (groups of 16 lanes) above
   constexpr bool kLayouts = MODE == kModeFit || MODE == kModeHamerly;
-  const bool alt = kLayouts && !half && A.layout == 1 && A.kp >= 32 && A.kp <= 256;
-  const int gpb = (half || g.G >= 32 || alt) ? kBlock / 64 : kBlock / g.G;  // rows per block
+  const bool alt = kLayouts && !half && A.layout == 1 && A.kp >= 32 && A.kp <= 512;
+  const int gpb = alt ? (A.kp <= 64 ? kBlock / 64 : kBlock / 16)
+                      : ((half || g.G >= 32) ? kBlock / 64 : kBlock / g.G);  // rows per block
   int64_t blocks = (A.n_rows + gpb - 1) / gpb;
   if (blocks > kMaxGridBlocks) blocks = kMaxGridBlocks;
   if (blocks < 1) blocks = 1;
@@ -1353,13 +1355,14 @@ hipError_t launch_assign_mode(const AssignArgs& A, hipStream_t s) {
   } else {
     if constexpr (kLayouts) {
       if (alt) {
-        // one row per wave: sub-waves of 8 / 16 lanes (k <= 64), or of 16 /
-        // 32 lanes holding two 16-byte units each (k <= 256)
+        // k <= 64: one row per wave in sub-waves of 8 / 16 lanes; above:
+        // a group of 16 lanes per row, each lane k_p / 64 16-byte units
         switch (A.kp) {
           SKM_CASE(32, 8, 1, 4, true)
           SKM_CASE(64, 16, 1, 4, true)
-          SKM_CASE(128, 16, 2, 4, true)
-          SKM_CASE(256, 32, 2, 4, true)
+          SKM_CASE(128, 16, 2, 4, false)
+          SKM_CASE(256, 16, 4, 4, false)
+          SKM_CASE(512, 16, 8, 4, false)
           default:
             return hipErrorInvalidValue;
         }

@@ -174,6 +174,15 @@ int check_init_norms(const double* initnorm, int32_t k, double tol, hipStream_t 
 // workload: 1.38 times faster than whole rows at a 410 MB copy).
 constexpr double kChunkAlwaysBytes = 256.0 * 1024.0 * 1024.0;
 
+// Row-length class of the tuning tables: the first class whose bound on the
+// mean stored entries per row exceeds this matrix's mean, else the last.
+int row_class(int64_t n, int64_t nnz) {
+  int rc = 0;
+  while (rc < kWalkTuneRowClasses - 1 && (double)nnz >= (double)kWalkTuneRowBound[rc] * (double)n)
+    ++rc;
+  return rc;
+}
+
 // Whether a fit's FP32 row walk takes 256 centres per launch (chunk_walk 1)
 // or whole rows (2); 0: always sliced when the copy exceeds the last-level
 // cache, else the measured table's entry for the variant's family (0 Lloyd
@@ -185,8 +194,8 @@ bool chunk_fp32(int32_t chunk_walk, int family, int64_t n, int64_t d, int64_t nn
   if ((double)d * (double)kp * 4.0 > kChunkAlwaysBytes) return true;
   int c = 0;
   while ((512 << c) < kp) ++c;
-  const int rc = (double)nnz < (double)kWalkTuneShortRow * (double)n ? 0 : 1;
-  return kChunkTune[family][rc][c < kChunkTuneWidths ? c : kChunkTuneWidths - 1] != 0;
+  return kChunkTune[family][row_class(n, nnz)][c < kChunkTuneWidths ? c : kChunkTuneWidths - 1] !=
+         0;
 }
 
 int make_plan(const skm_matrix* X, int32_t k, int32_t variant, int32_t precision, Plan* P,
@@ -973,8 +982,7 @@ int32_t walk_layout_for(const skm_options& o, int32_t kp, int64_t n, int64_t nnz
   int c = 0;
   while ((16 << c) < kp) ++c;
   if (c >= kWalkTuneWidths) return 0;
-  const int rc = (double)nnz < (double)kWalkTuneShortRow * (double)n ? 0 : 1;
-  return kWalkTune[rc][c];
+  return kWalkTune[row_class(n, nnz)][c];
 }
 
 int width_class(int kp) {

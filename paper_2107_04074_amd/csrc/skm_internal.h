@@ -182,7 +182,7 @@ struct AssignArgs {
   // 4-centre unit 64 t + q holds a centre whose pair tests failed (or the
   // assigned centre); written by the first launch of a step
   uint64_t* umask;
-  // row-walk layout of the FP32 copy at kp = 32 ... 256 for the fit and
+  // row-walk layout of the FP32 copy at kp = 32 ... 512 for the fit and
   // Hamerly modes (0 default, 1 alternative; see walk_tuning.h)
   int32_t layout;
 };

@@ -212,8 +212,8 @@ def _options(bound_form=0, precision=0, validate=0, norm_tol=0.0, profile=0, war
     schedule: 1 runs the bound tests at every step (0 = adaptive);
     batch_tile_rows: rows per work item of the lockstep batched walk (0 =
     the library's table; that driver is switched off);
-    walk_layout: row-walk layout of FP32 Lloyd/Hamerly fits at 16 < k <= 256
-    (0 = the library's tuning table, 1 = default layout, 2 = alternative);
+    walk_layout: row-walk layout of FP32 Lloyd/Hamerly whole-row walks at
+    16 < k <= 512 (0 = the library's tuning table, 1 = default, 2 = alternative);
     chunk_walk: FP32 CSR fits at 256 < k: 0 = the tuning table (sliced above
     a 256 MB copy), 1 = 256-centre slices, 2 = whole rows."""
     w = (None, None, None) if warm is None else tuple(_ptr(t) for t in warm)

@@ -1,17 +1,19 @@
 """Row-walk tuner (needs a GPU).  Times (HIP events around every assignment
 step's walk) the alternatives of the FP32 centre copy's row walk on seeded
-synthetic tf-idf rows, for both row-length classes of the table (short: 24
-stored entries per row on average, long: 80), and writes
+synthetic tf-idf rows, for the three row-length classes of the table (6,
+30 and 80 stored entries per row on average), and writes
 csrc/walk_tuning.h:
 
-  - layouts, padded widths kp = 32, 64, 128, 256 (20,000 columns):
-    skm_options.walk_layout 1 (default) against 2 (one row per wave
-    throughout); the alternative is taken when at least 2% faster;
+  - layouts, padded widths kp = 32 ... 512 (20,000 columns; whole rows):
+    skm_options.walk_layout 1 (default) against 2 (kp <= 64: one row per
+    wave; above: four rows per wave); the alternative is taken when at
+    least 2% faster;
   - slicing, kp = 512, 1024, 2048, 4096 (10,000 columns, so every copy stays
     below the 256 MB the library always slices above), per variant family
     (Lloyd and Hamerly; simplified and full Elkan; Yin-Yang): chunk_walk 1
-    (256 centres per launch) against 2 (whole rows in one launch); whole
-    rows are taken when at least 2% faster.
+    (256 centres per launch) against 2 (whole rows in one launch, at kp =
+    512 in the layout just measured for Lloyd and Hamerly); whole rows are
+    taken when at least 2% faster.
 
 Each cell times one fit of every variant of its family (layouts: Lloyd and
 Hamerly; k = 3 kp / 4, 15 steps at most), best of the repetitions.  Both
@@ -30,10 +32,13 @@ import os
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-ROW_CLASSES = ((0, 24.0), (1, 80.0))   # (class, mean stored entries per row)
-LAYOUT_WIDTHS = (32, 64, 128, 256)      # kp = 16 has only the default layout
+# (class, mean stored entries per row of the tuning matrix); a matrix falls
+# into the first class whose bound exceeds its mean
+ROW_CLASSES = ((0, 6.0), (1, 30.0), (2, 80.0))
+ROW_BOUNDS = (20, 48)
+LAYOUT_WIDTHS = (32, 64, 128, 256, 512)  # kp = 16 has only the default layout
 CHUNK_WIDTHS = (512, 1024, 2048, 4096)
-N_ROWS, STEPS, SEED = 20_000, 15, 20_240_611
+N_ROWS, STEPS, SEED = 100_000, 15, 20_240_611
 D_LAYOUT, D_CHUNK = 20_000, 10_000
 FAMILIES = (("lloyd", "hamerly"), ("simp_elkan", "elkan"), ("yinyang",))
 
@@ -76,18 +81,22 @@ def tune(out_path: str, reps: int = 5):
     from paper_2107_04074_amd import skm
 
     dev = torch.device("cuda:0")
-    layout = [[0] * 5 for _ in ROW_CLASSES]
+    layout = [[0] * 6 for _ in ROW_CLASSES]
     chunk = [[[1] * 4 for _ in ROW_CLASSES] for _ in FAMILIES]
     notes = []
     for rc, mean in ROW_CLASSES:
         for d, widths in ((D_LAYOUT, LAYOUT_WIDTHS), (D_CHUNK, CHUNK_WIDTHS)):
+            if d == D_CHUNK:
+                # whole rows at kp = 512 in the layout just measured
+                whole512 = layout[rc][5] + 1
             Xh = datagen.sparse_tfidf(N_ROWS, d, mean, SEED + rc)
             X = skm.DeviceCSR.from_host(Xh, dev)
             for kp in widths:
                 k = 3 * kp // 4
-                if kp <= 256:
+                if d == D_LAYOUT:
                     t0, t1 = _compare(skm, torch, X, Xh, k, reps, FAMILIES[0],
-                                      {"walk_layout": 1}, {"walk_layout": 2}, "layouts",
+                                      {"walk_layout": 1, "chunk_walk": 2},
+                                      {"walk_layout": 2, "chunk_walk": 2}, "layouts",
                                       datagen, dev)
                     pick = 1 if t1 < 0.98 * t0 else 0
                     layout[rc][kp.bit_length() - 5] = pick
@@ -97,8 +106,11 @@ def tune(out_path: str, reps: int = 5):
                     print(note, flush=True)
                     continue
                 for fam, variants in enumerate(FAMILIES):
+                    whole = {"chunk_walk": 2}
+                    if kp == 512 and fam == 0:
+                        whole["walk_layout"] = whole512
                     t0, t1 = _compare(skm, torch, X, Xh, k, reps, variants, {"chunk_walk": 1},
-                                      {"chunk_walk": 2}, "slicing", datagen, dev)
+                                      whole, "slicing", datagen, dev)
                     pick = 0 if t1 < 0.98 * t0 else 1
                     chunk[fam][rc][kp.bit_length() - 10] = pick
                     note = ("slices %-18s kp %4d, mean row %2d, d %d: %.3f ms sliced, %.3f ms "
@@ -122,7 +134,7 @@ def _rows(table):
 def _write(path: str, layout, chunk, notes, device: str) -> None:
     body = [
         "// Row-walk choices of the FP32 centre copy, per row-length class (0: under",
-        "// 48 stored entries per row on average, 1: 48 or more).  Written by",
+        "// %d stored entries per row on average, 1: under %d, 2: more).  Written by" % ROW_BOUNDS,
         "// paper_2107_04074_amd/tune_walk.py on %s, %d seeded" % (device, N_ROWS),
         "// tf-idf rows, k = 3 kp / 4, summed row-walk time of one fit of every variant",
         "// of the family (%d steps at most, HIP events), best of the repetitions:" % STEPS,
@@ -132,15 +144,18 @@ def _write(path: str, layout, chunk, notes, device: str) -> None:
         "#pragma once",
         "",
         "namespace skm {",
-        "// Layout per padded width kp = 16, 32, 64, 128, 256 (index log2(kp) - 4).",
-        "// 0: the default layout (k <= 64: a group of kp/4 lanes per row, several rows",
-        "// per wave; k in (64, 256]: one row per wave, one 16-byte unit per lane);",
-        "// 1: the alternative (k in (16, 64]: one row per wave in sub-waves of kp/4",
-        "// lanes, 64/(kp/4) stored entries per gather instruction; k in (64, 256]:",
-        "// one row per wave, two 16-byte units per lane, sub-waves of kp/8 lanes).",
-        "constexpr int kWalkTuneWidths = 5;",
-        "constexpr int kWalkTuneRowClasses = 2;",
-        "constexpr int kWalkTuneShortRow = 48;  // mean stored entries per row below: class 0",
+        "// Layout per padded width kp = 16, 32, ..., 512 (index log2(kp) - 4) of a",
+        "// whole-row walk.  0: the default layout (k <= 64: a group of kp/4 lanes per",
+        "// row, several rows per wave; k in (64, 512]: one row per wave, in two",
+        "// sub-waves of 32 lanes at kp = 128, one 16-byte unit per lane at 256, two",
+        "// at 512); 1: the alternative (k in (16, 64]: one row per wave in sub-waves",
+        "// of kp/4 lanes, 64/(kp/4) stored entries per gather instruction; k in",
+        "// (64, 512]: a group of 16 lanes per row, four rows per wave, kp/64 16-byte",
+        "// units per lane).",
+        "constexpr int kWalkTuneWidths = 6;",
+        "constexpr int kWalkTuneRowClasses = 3;",
+        "// mean stored entries per row below which a matrix is in class 0, 1",
+        "constexpr int kWalkTuneRowBound[kWalkTuneRowClasses - 1] = {%d, %d};" % ROW_BOUNDS,
         "constexpr int kWalkTune[kWalkTuneRowClasses][kWalkTuneWidths] = {",
         _rows(layout),
         "};",

@@ -241,21 +241,21 @@ def test_centre_copy_offsets_fit_32_bits(lib):
 
 def test_walk_tuning_table_is_well_formed():
     """The compiled row-walk tables (written by tune_walk.py): layouts, one
-    entry per row-length class and padded width kp = 16 ... 256, each 0 or
-    1, kp = 16 (no alternative layout) always 0; slicing, one entry per
-    variant family, class and kp = 512 ... 4096, each 0 or 1."""
+    entry per row-length class (three) and padded width kp = 16 ... 512,
+    each 0 or 1, kp = 16 (no alternative layout) always 0; slicing, one
+    entry per variant family, class and kp = 512 ... 4096, each 0 or 1."""
     path = os.path.join(os.path.dirname(skm.__file__), "csrc", "walk_tuning.h")
     text = open(path).read()
     body = re.search(r"kWalkTune\[kWalkTuneRowClasses\]\[kWalkTuneWidths\]\s*=\s*\{(.*?)\};",
                      text, re.S).group(1)
     rows = [[int(v) for v in r.split(",")] for r in re.findall(r"\{([^{}]*)\}", body)]
-    assert len(rows) == 2 and all(len(r) == 5 for r in rows)
+    assert len(rows) == 3 and all(len(r) == 6 for r in rows)
     assert all(v in (0, 1) for r in rows for v in r)
     assert all(r[0] == 0 for r in rows)
     body = re.search(r"kChunkTune\[kChunkTuneFamilies\]\[kWalkTuneRowClasses\]"
                      r"\[kChunkTuneWidths\]\s*=\s*\{(.*?)\};", text, re.S).group(1)
     rows = [[int(v) for v in r.split(",")] for r in re.findall(r"\{([^{}]*)\}", body)]
-    assert len(rows) == 3 * 2 and all(len(r) == 4 for r in rows)
+    assert len(rows) == 3 * 3 and all(len(r) == 4 for r in rows)
     assert all(v in (0, 1) for r in rows for v in r)
 
 
@@ -265,20 +265,22 @@ def test_tuner_writes_a_table_the_library_compiles(tmp_path):
     translation unit), so a re-measured table drops in without edits."""
     from paper_2107_04074_amd import tune_walk
     hdr = tmp_path / "walk_tuning.h"
-    layout = [[0, 1, 0, 1, 0], [0, 0, 1, 1, 0]]
-    chunk = [[[1, 0, 1, 0], [0, 1, 1, 1]], [[1, 1, 0, 0], [0, 0, 1, 1]],
-             [[0, 0, 0, 0], [1, 1, 1, 1]]]
+    layout = [[0, 1, 0, 1, 0, 1], [0, 0, 1, 1, 0, 0], [0, 0, 0, 0, 0, 1]]
+    chunk = [[[1, 0, 1, 0], [0, 1, 1, 1], [0, 0, 0, 1]], [[1, 1, 0, 0], [0, 0, 1, 1], [1, 0, 0, 0]],
+             [[0, 0, 0, 0], [1, 1, 1, 1], [0, 1, 0, 1]]]
     tune_walk._write(str(hdr), layout, chunk, ["note"], "test device")
     src = tmp_path / "t.cc"
     src.write_text(
         '#include "walk_tuning.h"\n'
         "using namespace skm;\n"
-        "static_assert(kWalkTuneWidths == 5 && kWalkTuneRowClasses == 2, \"\");\n"
+        "static_assert(kWalkTuneWidths == 6 && kWalkTuneRowClasses == 3, \"\");\n"
         "static_assert(kChunkTuneFamilies == 3 && kChunkTuneWidths == 4, \"\");\n"
-        "static_assert(kWalkTune[1][2] == 1 && kWalkTune[0][4] == 0, \"\");\n"
+        "static_assert(kWalkTune[1][2] == 1 && kWalkTune[0][5] == 1, \"\");\n"
         "static_assert(kChunkTune[0][0][2] == 1 && kChunkTune[1][1][3] == 1, \"\");\n"
         "static_assert(kChunkTune[2][0][0] == 0 && kChunkTune[2][1][0] == 1, \"\");\n"
-        "int main() { return kWalkTuneShortRow == 48 ? 0 : 1; }\n")
+        "static_assert(kWalkTune[2][5] == 1 && kChunkTune[1][2][0] == 1, \"\");\n"
+        "static_assert(kWalkTuneRowBound[0] < kWalkTuneRowBound[1], \"\");\n"
+        "int main() { return 0; }\n")
     r = subprocess.run(["g++", "-std=c++17", "-fsyntax-only", "-I", str(tmp_path), str(src)],
                        capture_output=True, text=True)
     assert r.returncode == 0, r.stderr

@@ -499,23 +499,25 @@ def test_sparse_k_sweep_matches_oracle(skm, torch_cuda):
 @pytest.mark.parametrize("layout", [1, 2])
 def test_walk_layouts_match_oracle(skm, torch_cuda, layout):
     """Both row-walk layouts of the FP32 copy that the tuning table chooses
-    between (walk_layout 1: the default, 2: one row per wave throughout), at k
-    on both sides of every tuned width (16 < k <= 256), short and long rows,
-    Lloyd, Hamerly and simplified Hamerly, tests adaptive and at every step:
-    whole trajectories equal the oracle's."""
+    between (walk_layout 1: the default, 2: one row per wave at k <= 64, four
+    rows per wave above), at k on both sides of every tuned width (16 < k <=
+    512, whole-row walks), short and long rows, Lloyd, Hamerly, simplified
+    Hamerly and Yin-Yang, tests adaptive and at every step: whole
+    trajectories equal the oracle's."""
     torch = torch_cuda
-    for mean, seed in ((12.0, 7070), (60.0, 7071)):
+    for mean, seed in ((12.0, 7070), (30.0, 7072), (60.0, 7071)):
         X = datagen.sparse_tfidf(3100, 2500, mean, seed)
         Xd = skm.DeviceCSR.from_host(X)
-        for k in (17, 32, 33, 64, 65, 128, 129, 256):
+        for k in (17, 32, 33, 64, 65, 128, 129, 256, 257, 512):
             C0 = datagen.init_centers_csr(X, datagen.init_rows(X.n, k, 77 + k))
             ref = oracle.fit(X, C0, "lloyd", 10)
-            for v in ("lloyd", "hamerly", "simp_hamerly"):
+            # Yin-Yang: its plain steps take the fit walk, so the layout too
+            for v in ("lloyd", "hamerly", "simp_hamerly", "yinyang"):
                 for sched in (0, 1):
                     say("case walk layout %d mean row %g k=%d %s schedule=%d" %
                         (layout, mean, k, v, sched))
                     a, C, C64, st = run_fit(skm, torch, Xd, C0, k, v, 10, schedule=sched,
-                                            walk_layout=layout)
+                                            walk_layout=layout, chunk_walk=2)
                     assert st.iterations == ref.iterations
                     assert np.array_equal(a, ref.a)
                     assert np.linalg.norm(C64 - ref.C, axis=1).max() < 1e-6
