@@ -284,3 +284,34 @@ def test_tuner_writes_a_table_the_library_compiles(tmp_path):
     r = subprocess.run(["g++", "-std=c++17", "-fsyntax-only", "-I", str(tmp_path), str(src)],
                        capture_output=True, text=True)
     assert r.returncode == 0, r.stderr
+
+
+def _walk_table(name):
+    text = open(os.path.join(os.path.dirname(skm.__file__), "csrc", "walk_tuning.h")).read()
+    body = re.search(name + r"\[[^=]*=\s*\{(.*?)\};", text, re.S).group(1)
+    return [[int(v) for v in r.split(",")] for r in re.findall(r"\{([^{}]*)\}", body)]
+
+
+def test_slicing_decision_follows_the_table(lib):
+    """Whether a fit slices the FP32 centre copy at k > 256 shows in its
+    workspace (a 56-byte running record per row when sliced): chunk_walk 1
+    and 2 force the two sizes; 0 follows the compiled table for the variant
+    family and row-length class, and always slices above a 256 MB copy."""
+    bounds = [int(v) for v in re.search(
+        r"kWalkTuneRowBound\[[^\]]*\]\s*=\s*\{([^}]*)\}",
+        open(os.path.join(os.path.dirname(skm.__file__), "csrc",
+                          "walk_tuning.h")).read()).group(1).split(",")]
+    table = _walk_table("kChunkTune")  # family-major rows of 4 widths
+    n, k = 5000, 500  # k_p = 512: width index 0
+    for fam, variant in ((0, skm.HAMERLY), (1, skm.ELKAN), (2, skm.YINYANG)):
+        for rc, mean in enumerate((3, 30, 90)):
+            assert mean < bounds[rc] if rc < len(bounds) else mean >= bounds[-1]
+            for d, big in ((20000, False), (200000, True)):  # copy 41 MB / 410 MB
+                m = _fake_csr(n=n, d=d, nnz=n * mean)
+                size = {}
+                for cw in (0, 1, 2):
+                    o = skm.SkmOptions(0, 0, 0, 0, 0.0, None, None, None, 0, 0, 0, cw)
+                    size[cw] = lib.skm_workspace_size(ctypes.byref(m), k, variant, ctypes.byref(o))
+                assert size[1] > size[2] > 0
+                sliced = big or table[3 * fam + rc][0] == 1
+                assert size[0] == (size[1] if sliced else size[2]), (fam, rc, d)
