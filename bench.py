@@ -577,8 +577,8 @@ def main():
     ap.add_argument("--variant", default="hamerly")
     ap.add_argument("--workload", default="all",
                     choices=["all", "c1", "c2", "c3", "c4", "c5", "dims"],
-                    help="all (default): c3 headline, then c4, c5 and c2 as secondary "
-                         "records; dims: the dimensionality experiment (not timed by default)")
+                    help="all (default): c3 headline, then c4, c5, c2 and the dimensionality "
+                         "experiment (dims) as secondary records")
     ap.add_argument("--workers", type=int, default=0,
                     help="c5: concurrent streams of the batched fit (0 = sweep 1, 2, 4, 8 "
                          "untimed and keep the fastest)")
@@ -656,9 +656,11 @@ def main():
         # secondary records: each workload's own line of figures, same
         # timing rules, fewer timed fits
         workloads = {}
-        for name in ("c4", "c5", "c2"):
+        for name in ("c4", "c5", "c2", "dims"):
             t0 = time.time()
-            if name == "c5":
+            if name == "dims":
+                r = run_dims(dev, 20)
+            elif name == "c5":
                 r = run_batched(dev, "hamerly", 2, 1, 0, False, args.no_cpu)
             else:
                 Q = Problem(name, dev)
