@@ -523,6 +523,29 @@ def test_walk_layouts_match_oracle(skm, torch_cuda, layout):
                     assert np.linalg.norm(C64 - ref.C, axis=1).max() < 1e-6
 
 
+def test_short_rows_exact_ties_match_oracle(skm, torch_cuda):
+    """Rows of about three stored entries (the density of the paper's DBLP
+    author-conference matrix): many rows have exactly equal FP64
+    similarities to several centres (their terms are absent from those
+    centres), so the tie rule decides them.  At k = 100, 200 and 500 the
+    tuning tables pick the grouped layout and whole-row walks; every variant
+    (and the sliced walk, forced) must follow the oracle's Lloyd trajectory."""
+    torch = torch_cuda
+    X = datagen.sparse_tfidf(30000, 3000, 3.0, 8181)
+    Xd = skm.DeviceCSR.from_host(X)
+    for k in (100, 200, 500):
+        C0 = datagen.init_centers_csr(X, datagen.init_rows(X.n, k, 17 + k))
+        ref = oracle.fit(X, C0, "lloyd", 12)
+        for v in VARIANTS:
+            for cw in ((0, 1) if k > 256 else (0,)):
+                say("case short rows k=%d %s chunk_walk=%d" % (k, v, cw))
+                a, C, C64, st = run_fit(skm, torch, Xd, C0, k, v, 12, schedule=1, chunk_walk=cw)
+                assert st.iterations == ref.iterations
+                assert np.array_equal(a, ref.a)
+                assert np.linalg.norm(C64 - ref.C, axis=1).max() < 1e-6
+        say("  k=%d: %d of %d rows re-decided in FP64 in the last fit" % (k, st.rechecks, X.n))
+
+
 def test_dense_shape_sweep_matches_oracle(skm, torch_cuda):
     """Seeded sweep of small dense shapes (row counts that leave partial
     waves and blocks, widths on both sides of every padded width, k on both
