@@ -618,7 +618,10 @@ __device__ __forceinline__ void write_group_bounds(const AssignArgs& A, int64_t 
 // set bits of cm (bit VEC r + q = centre VEC (gl + G r) + q).  Candidates are
 // taken one at a time, lowest lane and bit first, and the whole group
 // computes each one's canonical FP64 similarity; every lane returns the same
-// winner under the tie order.
+// winner under the tie order.  Rows of at most 8 stored entries (where whole
+// sets of centres tie exactly: those holding none of the row's terms) let
+// every lane evaluate its own candidates with the one-lane form of the same
+// value, and the group keeps the best under the tie order.
 template <int G, int VEC>
 __device__ __forceinline__ void group_redecide(unsigned long long cm, const int32_t* ci,
                                                const float* v, int64_t beg, int64_t end,
@@ -626,6 +629,19 @@ __device__ __forceinline__ void group_redecide(unsigned long long cm, const int3
                                                double& cb, int& cj, int j0 = 0) {
   cb = -INFINITY;
   cj = INT_MAX;
+  if (end - beg <= 8) {
+    for (unsigned long long c = cm; c != 0ull; c &= c - 1ull) {
+      const int bit = __builtin_ctzll(c);
+      const int j = j0 + VEC * (gl + G * (bit / VEC)) + bit % VEC;
+      const double sv = dot64_short(ci, v, beg, end, C64 + (size_t)j * d);
+      if (better64(sv, j, cb, cj, prev)) {
+        cb = sv;
+        cj = j;
+      }
+    }
+    group_best64<G>(cb, cj, prev);
+    return;
+  }
   const int base = (int)(threadIdx.x & 63) - gl;  // first lane of the group
   for (;;) {
     const unsigned long long wave = __ballot(cm != 0ull);

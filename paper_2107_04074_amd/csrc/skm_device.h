@@ -58,6 +58,19 @@ __device__ __forceinline__ double dot64_group(const int32_t* __restrict__ ci,
   return part[0];
 }
 
+// The same canonical value computed by one lane for a row of at most 8
+// stored entries: partials 8 ... 63 are zero, so the tree reduces to the
+// pairwise sum of the first eight partials plus the zero subtrees (+0.0).
+__device__ __forceinline__ double dot64_short(const int32_t* __restrict__ ci,
+                                              const float* __restrict__ v, int64_t beg,
+                                              int64_t end, const double* __restrict__ c) {
+  double p[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q)
+    p[q] = (beg + q < end) ? fma((double)v[beg + q], c[ci[beg + q]], 0.0) : 0.0;
+  return (((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7]))) + 0.0;
+}
+
 __device__ __forceinline__ double dot64_serial(const int32_t* __restrict__ ci,
                                                const float* __restrict__ v, int64_t beg,
                                                int64_t end, const double* __restrict__ c) {
