@@ -3,57 +3,57 @@
 // paper_2107_04074_amd/tune_walk.py on gfx950, 256 compute units, 100000 seeded
 // tf-idf rows, k = 3 kp / 4, summed row-walk time of one fit of every variant
 // of the family (15 steps at most, HIP events), best of the repetitions:
-//   layout kp   32, mean row  6, d 20000: 1.085 ms default, 3.294 ms alternative -> 0
-//   layout kp   64, mean row  6, d 20000: 1.312 ms default, 3.400 ms alternative -> 0
-//   layout kp  128, mean row  6, d 20000: 3.830 ms default, 1.889 ms alternative -> 1
-//   layout kp  256, mean row  6, d 20000: 3.774 ms default, 3.104 ms alternative -> 1
-//   layout kp  512, mean row  6, d 20000: 5.457 ms default, 6.532 ms alternative -> 0
-//   slices lloyd+hamerly      kp  512, mean row  6, d 10000: 8.612 ms sliced, 4.766 ms whole rows -> 0
-//   slices simp_elkan+elkan   kp  512, mean row  6, d 10000: 19.539 ms sliced, 11.785 ms whole rows -> 0
-//   slices yinyang            kp  512, mean row  6, d 10000: 6.891 ms sliced, 3.183 ms whole rows -> 0
-//   slices lloyd+hamerly      kp 1024, mean row  6, d 10000: 13.094 ms sliced, 8.238 ms whole rows -> 0
-//   slices simp_elkan+elkan   kp 1024, mean row  6, d 10000: 42.385 ms sliced, 20.954 ms whole rows -> 0
-//   slices yinyang            kp 1024, mean row  6, d 10000: 11.458 ms sliced, 4.765 ms whole rows -> 0
-//   slices lloyd+hamerly      kp 2048, mean row  6, d 10000: 33.609 ms sliced, 15.418 ms whole rows -> 0
-//   slices simp_elkan+elkan   kp 2048, mean row  6, d 10000: 97.106 ms sliced, 71.444 ms whole rows -> 0
-//   slices yinyang            kp 2048, mean row  6, d 10000: 29.160 ms sliced, 9.264 ms whole rows -> 0
-//   slices lloyd+hamerly      kp 4096, mean row  6, d 10000: 87.611 ms sliced, 37.846 ms whole rows -> 0
-//   slices simp_elkan+elkan   kp 4096, mean row  6, d 10000: 209.954 ms sliced, 134.302 ms whole rows -> 0
-//   slices yinyang            kp 4096, mean row  6, d 10000: 72.161 ms sliced, 25.485 ms whole rows -> 0
-//   layout kp   32, mean row 30, d 20000: 1.741 ms default, 3.226 ms alternative -> 0
-//   layout kp   64, mean row 30, d 20000: 2.049 ms default, 3.436 ms alternative -> 0
-//   layout kp  128, mean row 30, d 20000: 4.168 ms default, 3.263 ms alternative -> 1
-//   layout kp  256, mean row 30, d 20000: 4.949 ms default, 6.085 ms alternative -> 0
-//   layout kp  512, mean row 30, d 20000: 9.377 ms default, 13.647 ms alternative -> 0
-//   slices lloyd+hamerly      kp  512, mean row 30, d 10000: 13.068 ms sliced, 8.926 ms whole rows -> 0
-//   slices simp_elkan+elkan   kp  512, mean row 30, d 10000: 23.489 ms sliced, 14.013 ms whole rows -> 0
-//   slices yinyang            kp  512, mean row 30, d 10000: 8.462 ms sliced, 4.707 ms whole rows -> 0
-//   slices lloyd+hamerly      kp 1024, mean row 30, d 10000: 17.603 ms sliced, 18.714 ms whole rows -> 1
-//   slices simp_elkan+elkan   kp 1024, mean row 30, d 10000: 36.816 ms sliced, 26.698 ms whole rows -> 0
-//   slices yinyang            kp 1024, mean row 30, d 10000: 13.234 ms sliced, 9.685 ms whole rows -> 0
-//   slices lloyd+hamerly      kp 2048, mean row 30, d 10000: 31.561 ms sliced, 41.161 ms whole rows -> 1
-//   slices simp_elkan+elkan   kp 2048, mean row 30, d 10000: 68.589 ms sliced, 72.548 ms whole rows -> 1
-//   slices yinyang            kp 2048, mean row 30, d 10000: 24.802 ms sliced, 20.588 ms whole rows -> 0
-//   slices lloyd+hamerly      kp 4096, mean row 30, d 10000: 62.462 ms sliced, 100.986 ms whole rows -> 1
-//   slices simp_elkan+elkan   kp 4096, mean row 30, d 10000: 133.165 ms sliced, 149.128 ms whole rows -> 1
-//   slices yinyang            kp 4096, mean row 30, d 10000: 46.714 ms sliced, 49.836 ms whole rows -> 1
-//   layout kp   32, mean row 80, d 20000: 3.694 ms default, 4.501 ms alternative -> 0
-//   layout kp   64, mean row 80, d 20000: 4.550 ms default, 5.102 ms alternative -> 0
-//   layout kp  128, mean row 80, d 20000: 7.111 ms default, 7.846 ms alternative -> 0
-//   layout kp  256, mean row 80, d 20000: 11.634 ms default, 15.755 ms alternative -> 0
-//   layout kp  512, mean row 80, d 20000: 25.284 ms default, 34.085 ms alternative -> 0
-//   slices lloyd+hamerly      kp  512, mean row 80, d 10000: 31.277 ms sliced, 22.717 ms whole rows -> 0
-//   slices simp_elkan+elkan   kp  512, mean row 80, d 10000: 42.116 ms sliced, 25.639 ms whole rows -> 0
-//   slices yinyang            kp  512, mean row 80, d 10000: 16.189 ms sliced, 11.632 ms whole rows -> 0
-//   slices lloyd+hamerly      kp 1024, mean row 80, d 10000: 41.495 ms sliced, 54.546 ms whole rows -> 1
-//   slices simp_elkan+elkan   kp 1024, mean row 80, d 10000: 63.605 ms sliced, 58.129 ms whole rows -> 0
-//   slices yinyang            kp 1024, mean row 80, d 10000: 24.459 ms sliced, 27.502 ms whole rows -> 1
-//   slices lloyd+hamerly      kp 2048, mean row 80, d 10000: 68.775 ms sliced, 131.042 ms whole rows -> 1
-//   slices simp_elkan+elkan   kp 2048, mean row 80, d 10000: 104.208 ms sliced, 138.999 ms whole rows -> 1
-//   slices yinyang            kp 2048, mean row 80, d 10000: 42.424 ms sliced, 65.782 ms whole rows -> 1
-//   slices lloyd+hamerly      kp 4096, mean row 80, d 10000: 137.100 ms sliced, 330.301 ms whole rows -> 1
-//   slices simp_elkan+elkan   kp 4096, mean row 80, d 10000: 203.343 ms sliced, 341.883 ms whole rows -> 1
-//   slices yinyang            kp 4096, mean row 80, d 10000: 83.792 ms sliced, 163.930 ms whole rows -> 1
+//   layout kp   32, mean row  6, d 20000: 0.949 ms default, 2.875 ms alternative -> 0
+//   layout kp   64, mean row  6, d 20000: 1.064 ms default, 3.011 ms alternative -> 0
+//   layout kp  128, mean row  6, d 20000: 3.121 ms default, 1.421 ms alternative -> 1
+//   layout kp  256, mean row  6, d 20000: 3.190 ms default, 2.367 ms alternative -> 1
+//   layout kp  512, mean row  6, d 20000: 3.776 ms default, 4.415 ms alternative -> 0
+//   slices lloyd+hamerly      kp  512, mean row  6, d 10000: 6.915 ms sliced, 3.699 ms whole rows -> 0
+//   slices simp_elkan+elkan   kp  512, mean row  6, d 10000: 17.882 ms sliced, 10.723 ms whole rows -> 0
+//   slices yinyang            kp  512, mean row  6, d 10000: 6.155 ms sliced, 2.650 ms whole rows -> 0
+//   slices lloyd+hamerly      kp 1024, mean row  6, d 10000: 10.403 ms sliced, 6.063 ms whole rows -> 0
+//   slices simp_elkan+elkan   kp 1024, mean row  6, d 10000: 30.573 ms sliced, 18.593 ms whole rows -> 0
+//   slices yinyang            kp 1024, mean row  6, d 10000: 9.586 ms sliced, 3.637 ms whole rows -> 0
+//   slices lloyd+hamerly      kp 2048, mean row  6, d 10000: 19.332 ms sliced, 11.292 ms whole rows -> 0
+//   slices simp_elkan+elkan   kp 2048, mean row  6, d 10000: 61.052 ms sliced, 66.895 ms whole rows -> 1
+//   slices yinyang            kp 2048, mean row  6, d 10000: 17.755 ms sliced, 7.143 ms whole rows -> 0
+//   slices lloyd+hamerly      kp 4096, mean row  6, d 10000: 38.264 ms sliced, 31.619 ms whole rows -> 0
+//   slices simp_elkan+elkan   kp 4096, mean row  6, d 10000: 121.033 ms sliced, 127.725 ms whole rows -> 1
+//   slices yinyang            kp 4096, mean row  6, d 10000: 34.069 ms sliced, 21.750 ms whole rows -> 0
+//   layout kp   32, mean row 30, d 20000: 1.734 ms default, 3.178 ms alternative -> 0
+//   layout kp   64, mean row 30, d 20000: 2.045 ms default, 3.442 ms alternative -> 0
+//   layout kp  128, mean row 30, d 20000: 4.176 ms default, 3.251 ms alternative -> 1
+//   layout kp  256, mean row 30, d 20000: 4.944 ms default, 6.076 ms alternative -> 0
+//   layout kp  512, mean row 30, d 20000: 9.294 ms default, 13.668 ms alternative -> 0
+//   slices lloyd+hamerly      kp  512, mean row 30, d 10000: 12.991 ms sliced, 8.921 ms whole rows -> 0
+//   slices simp_elkan+elkan   kp  512, mean row 30, d 10000: 23.460 ms sliced, 13.995 ms whole rows -> 0
+//   slices yinyang            kp  512, mean row 30, d 10000: 8.439 ms sliced, 4.681 ms whole rows -> 0
+//   slices lloyd+hamerly      kp 1024, mean row 30, d 10000: 17.517 ms sliced, 18.885 ms whole rows -> 1
+//   slices simp_elkan+elkan   kp 1024, mean row 30, d 10000: 36.796 ms sliced, 26.722 ms whole rows -> 0
+//   slices yinyang            kp 1024, mean row 30, d 10000: 13.212 ms sliced, 9.739 ms whole rows -> 0
+//   slices lloyd+hamerly      kp 2048, mean row 30, d 10000: 31.487 ms sliced, 41.061 ms whole rows -> 1
+//   slices simp_elkan+elkan   kp 2048, mean row 30, d 10000: 68.401 ms sliced, 72.538 ms whole rows -> 1
+//   slices yinyang            kp 2048, mean row 30, d 10000: 24.748 ms sliced, 20.570 ms whole rows -> 0
+//   slices lloyd+hamerly      kp 4096, mean row 30, d 10000: 62.355 ms sliced, 100.475 ms whole rows -> 1
+//   slices simp_elkan+elkan   kp 4096, mean row 30, d 10000: 132.993 ms sliced, 148.756 ms whole rows -> 1
+//   slices yinyang            kp 4096, mean row 30, d 10000: 46.565 ms sliced, 49.591 ms whole rows -> 1
+//   layout kp   32, mean row 80, d 20000: 3.695 ms default, 4.447 ms alternative -> 0
+//   layout kp   64, mean row 80, d 20000: 4.529 ms default, 5.085 ms alternative -> 0
+//   layout kp  128, mean row 80, d 20000: 7.081 ms default, 7.830 ms alternative -> 0
+//   layout kp  256, mean row 80, d 20000: 11.607 ms default, 15.687 ms alternative -> 0
+//   layout kp  512, mean row 80, d 20000: 25.088 ms default, 33.853 ms alternative -> 0
+//   slices lloyd+hamerly      kp  512, mean row 80, d 10000: 31.199 ms sliced, 22.762 ms whole rows -> 0
+//   slices simp_elkan+elkan   kp  512, mean row 80, d 10000: 42.073 ms sliced, 25.844 ms whole rows -> 0
+//   slices yinyang            kp  512, mean row 80, d 10000: 16.154 ms sliced, 11.663 ms whole rows -> 0
+//   slices lloyd+hamerly      kp 1024, mean row 80, d 10000: 41.452 ms sliced, 54.348 ms whole rows -> 1
+//   slices simp_elkan+elkan   kp 1024, mean row 80, d 10000: 63.549 ms sliced, 58.147 ms whole rows -> 0
+//   slices yinyang            kp 1024, mean row 80, d 10000: 24.293 ms sliced, 27.462 ms whole rows -> 1
+//   slices lloyd+hamerly      kp 2048, mean row 80, d 10000: 69.015 ms sliced, 128.929 ms whole rows -> 1
+//   slices simp_elkan+elkan   kp 2048, mean row 80, d 10000: 104.224 ms sliced, 137.540 ms whole rows -> 1
+//   slices yinyang            kp 2048, mean row 80, d 10000: 42.145 ms sliced, 64.884 ms whole rows -> 1
+//   slices lloyd+hamerly      kp 4096, mean row 80, d 10000: 137.565 ms sliced, 332.011 ms whole rows -> 1
+//   slices simp_elkan+elkan   kp 4096, mean row 80, d 10000: 203.081 ms sliced, 341.101 ms whole rows -> 1
+//   slices yinyang            kp 4096, mean row 80, d 10000: 83.312 ms sliced, 167.891 ms whole rows -> 1
 #pragma once
 
 namespace skm {
@@ -82,7 +82,7 @@ constexpr int kChunkTuneFamilies = 3;
 constexpr int kChunkTuneWidths = 4;
 constexpr int kChunkTune[kChunkTuneFamilies][kWalkTuneRowClasses][kChunkTuneWidths] = {
     {{0, 0, 0, 0}, {0, 1, 1, 1}, {0, 1, 1, 1}},
-    {{0, 0, 0, 0}, {0, 0, 1, 1}, {0, 0, 1, 1}},
+    {{0, 0, 1, 1}, {0, 0, 1, 1}, {0, 0, 1, 1}},
     {{0, 0, 0, 0}, {0, 0, 0, 1}, {0, 1, 1, 1}}
 };
 }  // namespace skm
