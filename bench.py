@@ -492,9 +492,12 @@ def run_batched(dev, variant, steps, warmup, workers_arg, skip_baseline, no_cpu,
 # Dimensionality experiment (Section 6, the run times on the DBLP
 # author-conference matrix and on its transpose): the same number of stored
 # entries as many short rows over few columns, or as few long rows over many
-# columns.  Seeded synthetic stand-ins with the shapes and densities of Table 1.
+# columns; beside them the shape of RCV-1 (Table 1), on which Table 3 shows the
+# largest speed-ups of the bounded variants.  Seeded synthetic stand-ins with
+# the shapes and densities of Table 1.
 DIMS_SHAPES = (("rows_1842986_x_cols_5236", 1_842_986, 5_236, 2.9),
-               ("rows_5236_x_cols_1842986", 5_236, 1_842_986, 1032.0))
+               ("rows_5236_x_cols_1842986", 5_236, 1_842_986, 1032.0),
+               ("rows_804414_x_cols_47236", 804_414, 47_236, 75.6))
 DIMS_K = (10, 50, 200, 500)
 DIMS_VARIANTS = ("lloyd", "simp_hamerly", "hamerly", "simp_elkan", "elkan", "yinyang")
 
@@ -552,8 +555,9 @@ def run_dims(dev, max_iter):
         torch.cuda.empty_cache()
     return {"config": {"workload": "dims: shapes of the DBLP author-conference matrix and its "
                                    "transpose (1842986 x 5236, 2.9 entries per row; 5236 x "
-                                   "1842986, 1032 per row), k in %s, at most %d steps, FP32 "
-                                   "copy" % (list(DIMS_K), max_iter),
+                                   "1842986, 1032 per row) and of RCV-1 (804414 x 47236, 75.6 "
+                                   "per row), k in %s, at most %d steps, FP32 copy" % (
+                                       list(DIMS_K), max_iter),
                        "parallelism": "single GPU"},
             "dtype": "f32", "table": rows,
             "all_identical": all(r["identical"] for r in rows)}
