@@ -495,9 +495,12 @@ def run_batched(dev, variant, steps, warmup, workers_arg, skip_baseline, no_cpu,
 # columns; beside them the shape of RCV-1 (Table 1), on which Table 3 shows the
 # largest speed-ups of the bounded variants.  Seeded synthetic stand-ins with
 # the shapes and densities of Table 1.
-DIMS_SHAPES = (("rows_1842986_x_cols_5236", 1_842_986, 5_236, 2.9),
-               ("rows_5236_x_cols_1842986", 5_236, 1_842_986, 1032.0),
-               ("rows_804414_x_cols_47236", 804_414, 47_236, 75.6))
+DIMS_SHAPES = (("rows_1842986_x_cols_5236", 1_842_986, 5_236, 2.9, 0),
+               ("rows_5236_x_cols_1842986", 5_236, 1_842_986, 1032.0, 0),
+               ("rows_804414_x_cols_47236", 804_414, 47_236, 75.6, 0),
+               # the RCV-1 shape again with topic structure (100 topics), so that
+               # the centres settle as they do on real text
+               ("rows_804414_x_cols_47236_topics", 804_414, 47_236, 75.6, 100))
 DIMS_K = (10, 50, 200, 500)
 DIMS_VARIANTS = ("lloyd", "simp_hamerly", "hamerly", "simp_elkan", "elkan", "yinyang")
 
@@ -512,9 +515,9 @@ def run_dims(dev, max_iter):
     import datagen
     from paper_2107_04074_amd import skm
     rows = []
-    for si, (name, n, d, mean) in enumerate(DIMS_SHAPES):
+    for si, (name, n, d, mean, topics) in enumerate(DIMS_SHAPES):
         t0 = time.time()
-        Xh = datagen.sparse_tfidf(n, d, mean, datagen.BASE_SEED + 60 + si)
+        Xh = datagen.sparse_tfidf(n, d, mean, datagen.BASE_SEED + 60 + si, topics=topics)
         X = skm.DeviceCSR.from_host(Xh, dev)
         log("generated %s: n=%d d=%d nnz=%d in %.1fs" % (name, Xh.n, Xh.d, Xh.nnz,
                                                         time.time() - t0))
@@ -556,7 +559,8 @@ def run_dims(dev, max_iter):
     return {"config": {"workload": "dims: shapes of the DBLP author-conference matrix and its "
                                    "transpose (1842986 x 5236, 2.9 entries per row; 5236 x "
                                    "1842986, 1032 per row) and of RCV-1 (804414 x 47236, 75.6 "
-                                   "per row), k in %s, at most %d steps, FP32 copy" % (
+                                   "per row; plain, and with 100 topics), k in %s, at most %d "
+                                   "steps, FP32 copy" % (
                                        list(DIMS_K), max_iter),
                        "parallelism": "single GPU"},
             "dtype": "f32", "table": rows,

@@ -65,6 +65,9 @@ def _load():
         lib.skmgen_row_lengths.argtypes = [i64, i64, dbl, dbl, u64, p]
         lib.skmgen_sparse_fill.restype = i64
         lib.skmgen_sparse_fill.argtypes = [i64, i64, dbl, u64, p, p, p, p, p, p, p]
+        lib.skmgen_sparse_fill_topics.restype = i64
+        lib.skmgen_sparse_fill_topics.argtypes = [i64, i64, dbl, u64, i32, dbl, p, p, p, p,
+                                                  p, p, p]
         lib.skmgen_vmf.restype = None
         lib.skmgen_vmf.argtypes = [i64, i64, i32, dbl, dbl, u64, p, p, p, p]
         _lib = lib
@@ -109,10 +112,15 @@ class CSR:
 
 
 def sparse_tfidf(n: int, d: int, mean_nnz: float, seed: int,
-                 sigma: float = 0.5, zipf_s: float = 1.1) -> CSR:
+                 sigma: float = 0.5, zipf_s: float = 1.1, topics: int = 0,
+                 topic_share: float = 0.7) -> CSR:
     """SPARSE(n, d, mean_nnz, seed): log-normal row lengths (arithmetic mean
     ``mean_nnz``, sigma 0.5), distinct Zipf(1.1) terms, Geometric(1/2) term
-    frequencies, ln(1+tf)*ln(n/df) weights, unit rows stored as float32."""
+    frequencies, ln(1+tf)*ln(n/df) weights, unit rows stored as float32.
+    ``topics`` > 0: every row belongs to one of that many topics and takes
+    each term, with probability ``topic_share``, through its topic's own
+    rank -> column permutation (rows of a topic share their frequent terms);
+    0 gives the plain rows above."""
     lib = _load()
     m = np.empty(n, dtype=np.int32)
     cap = lib.skmgen_row_lengths(n, d, float(mean_nnz), float(sigma), seed, _ptr(m))
@@ -121,8 +129,15 @@ def sparse_tfidf(n: int, d: int, mean_nnz: float, seed: int,
     val = np.empty(max(cap, 1), dtype=np.float32)
     n_out = ctypes.c_int64(0)
     dropped = ctypes.c_int64(0)
-    nnz = lib.skmgen_sparse_fill(n, d, float(zipf_s), seed, _ptr(m), _ptr(rp), _ptr(col),
-                                 _ptr(val), ctypes.byref(n_out), ctypes.byref(dropped), None)
+    if topics > 0:
+        nnz = lib.skmgen_sparse_fill_topics(n, d, float(zipf_s), seed, int(topics),
+                                            float(topic_share), _ptr(m), _ptr(rp), _ptr(col),
+                                            _ptr(val), ctypes.byref(n_out),
+                                            ctypes.byref(dropped), None)
+    else:
+        nnz = lib.skmgen_sparse_fill(n, d, float(zipf_s), seed, _ptr(m), _ptr(rp),
+                                     _ptr(col), _ptr(val), ctypes.byref(n_out),
+                                     ctypes.byref(dropped), None)
     rows = n_out.value
     return CSR(rows, d, rp[: rows + 1].copy(), col[:nnz].copy(), val[:nnz].copy(),
                dropped.value)

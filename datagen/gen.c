@@ -68,7 +68,7 @@ static double rng_gamma(rng_t *r, double alpha) {
 }
 
 enum { STREAM_LEN = 1, STREAM_TERMS = 2, STREAM_PERM = 3, STREAM_VMF = 4,
-       STREAM_MEANS = 5 };
+       STREAM_MEANS = 5, STREAM_TOPIC = 6, STREAM_TOPIC_PERM = 7 };
 
 /* ------------------------------------------------------------------------ */
 /* sparse tf-idf rows                                                        */
@@ -115,10 +115,36 @@ static int cmp_entry(const void *a, const void *b) {
  * row_ptr has n+1 slots, col/val have sum(m) slots.  Returns the final nnz;
  * *n_out receives the number of rows kept, *dropped the number removed.
  * idf_out (nullable, d slots) receives idf per column. */
+static int64_t sparse_fill(int64_t n, int64_t d, double zipf_s, uint64_t seed,
+                           int32_t topics, double topic_share, const int32_t *m,
+                           int64_t *row_ptr, int32_t *col, float *val, int64_t *n_out,
+                           int64_t *dropped, double *idf_out);
+
 int64_t skmgen_sparse_fill(int64_t n, int64_t d, double zipf_s, uint64_t seed,
                            const int32_t *m, int64_t *row_ptr, int32_t *col,
                            float *val, int64_t *n_out, int64_t *dropped,
                            double *idf_out) {
+  return sparse_fill(n, d, zipf_s, seed, 0, 0.0, m, row_ptr, col, val, n_out, dropped,
+                     idf_out);
+}
+
+/* The same rows with topic structure: every row draws one of `topics`
+ * topics (uniformly), and each of its terms takes, with probability
+ * topic_share, its column from the topic's own seeded rank -> column
+ * permutation instead of the shared one, so rows of one topic share their
+ * frequent terms.  topics = 0 gives exactly skmgen_sparse_fill's rows. */
+int64_t skmgen_sparse_fill_topics(int64_t n, int64_t d, double zipf_s, uint64_t seed,
+                                  int32_t topics, double topic_share, const int32_t *m,
+                                  int64_t *row_ptr, int32_t *col, float *val,
+                                  int64_t *n_out, int64_t *dropped, double *idf_out) {
+  return sparse_fill(n, d, zipf_s, seed, topics, topic_share, m, row_ptr, col, val, n_out,
+                     dropped, idf_out);
+}
+
+static int64_t sparse_fill(int64_t n, int64_t d, double zipf_s, uint64_t seed,
+                           int32_t topics, double topic_share, const int32_t *m,
+                           int64_t *row_ptr, int32_t *col, float *val, int64_t *n_out,
+                           int64_t *dropped, double *idf_out) {
   double *cdf = (double *)malloc(sizeof(double) * (size_t)d);
   double acc = 0.0;
   for (int64_t r = 0; r < d; ++r) {
@@ -140,6 +166,23 @@ int64_t skmgen_sparse_fill(int64_t n, int64_t d, double zipf_s, uint64_t seed,
     }
   }
 
+  /* per-topic rank -> column permutations */
+  int32_t *tperm = NULL;
+  if (topics > 0) {
+    tperm = (int32_t *)malloc(sizeof(int32_t) * (size_t)d * (size_t)topics);
+    for (int32_t t = 0; t < topics; ++t) {
+      int32_t *pt = tperm + (size_t)t * (size_t)d;
+      for (int64_t r = 0; r < d; ++r) pt[r] = (int32_t)r;
+      rng_t pr = rng_make(seed, STREAM_TOPIC_PERM, (uint64_t)t);
+      for (int64_t r = d - 1; r > 0; --r) {
+        int64_t j = (int64_t)(rng_u64(&pr) % (uint64_t)(r + 1));
+        int32_t x = pt[r];
+        pt[r] = pt[j];
+        pt[j] = x;
+      }
+    }
+  }
+
   int64_t *off = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + 1));
   off[0] = 0;
   for (int64_t i = 0; i < n; ++i) off[i + 1] = off[i] + m[i];
@@ -156,6 +199,12 @@ int64_t skmgen_sparse_fill(int64_t n, int64_t d, double zipf_s, uint64_t seed,
       rng_t r = rng_make(seed, STREAM_TERMS, (uint64_t)i);
       const int64_t base = off[i];
       const int32_t mi = m[i];
+      const int32_t *tp = NULL;
+      rng_t rt;
+      if (topics > 0) {
+        rt = rng_make(seed, STREAM_TOPIC, (uint64_t)i);
+        tp = tperm + (size_t)(rng_u64(&rt) % (uint64_t)topics) * (size_t)d;
+      }
       int32_t got = 0;
       while (got < mi) {
         const double target = rng_unif(&r) * total_w;
@@ -164,12 +213,16 @@ int64_t skmgen_sparse_fill(int64_t n, int64_t d, double zipf_s, uint64_t seed,
           int64_t mid = (lo + hi) >> 1;
           if (cdf[mid] >= target) hi = mid; else lo = mid + 1;
         }
-        if (used[lo]) continue;
-        used[lo] = 1;
-        ranks[got] = (int32_t)lo;
+        /* repeats are rejected by column (by rank without topics) */
+        const int32_t c =
+            (tp != NULL && rng_unif(&rt) < topic_share) ? tp[lo] : perm[lo];
+        const int64_t key = tp != NULL ? (int64_t)c : lo;
+        if (used[key]) continue;
+        used[key] = 1;
+        ranks[got] = (int32_t)key;
         uint64_t bits = rng_u64(&r);
         int tf = 1 + (bits ? __builtin_ctzll(bits) : 63);
-        col[base + got] = perm[lo];
+        col[base + got] = c;
         w[base + got] = log1p((double)tf);
         ++got;
       }
@@ -243,6 +296,7 @@ int64_t skmgen_sparse_fill(int64_t n, int64_t d, double zipf_s, uint64_t seed,
   free(w);
   free(off);
   free(perm);
+  free(tperm);
   free(cdf);
   return nnz;
 }

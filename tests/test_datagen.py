@@ -41,6 +41,29 @@ def test_sparse_statistics():
     assert np.median(df) < 0.01 * X.n
 
 
+def test_sparse_topics_structure_and_default():
+    """topics = 0 is the plain generator; with topics the rows keep the CSR
+    contract (ascending distinct columns, unit norm) and form clusters: a
+    seeded FP64 Lloyd fit with k = topics converges in far fewer steps than
+    on plain rows and finds clusters of nearly equal size (the topics)."""
+    import oracle
+    a = datagen.sparse_tfidf(4000, 3000, 40.0, 99)
+    b = datagen.sparse_tfidf(4000, 3000, 40.0, 99, topics=0)
+    assert np.array_equal(a.col, b.col) and np.array_equal(a.val, b.val)
+    t = datagen.sparse_tfidf(4000, 3000, 40.0, 99, topics=10)
+    assert not (t.nnz == a.nnz and np.array_equal(t.col, a.col))
+    rp = t.row_ptr
+    for i in range(t.n):
+        assert np.all(np.diff(t.col[rp[i]:rp[i + 1]]) > 0)
+    norms = np.sqrt(np.add.reduceat(t.val.astype(np.float64) ** 2, rp[:-1]))
+    assert np.abs(norms - 1.0).max() < 1e-6
+    fits = [oracle.fit(X, datagen.init_centers_csr(X, datagen.init_rows(X.n, 10, 5)), "lloyd", 30)
+            for X in (a, t)]
+    assert fits[1].iterations + 4 <= fits[0].iterations
+    sizes = np.bincount(fits[1].a, minlength=10)
+    assert np.all(np.abs(sizes - t.n / 10) < 0.25 * t.n / 10)
+
+
 def test_vmf_rows_unit_and_concentrated():
     X, comp = datagen.dense_vmf(4000, 64, 8, 11, return_components=True)
     nr = np.linalg.norm(X.astype(np.float64), axis=1)
