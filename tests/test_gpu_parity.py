@@ -546,6 +546,30 @@ def test_short_rows_exact_ties_match_oracle(skm, torch_cuda):
         say("  k=%d: %d of %d rows re-decided in FP64 in the last fit" % (k, st.rechecks, X.n))
 
 
+def test_topical_rows_match_oracle(skm, torch_cuda):
+    """Rows with topic structure (20 topics), where the centres settle and
+    the bounds prune far more than on plain rows: every variant, tests at
+    every step and adaptive, FP32 and FP16 copies, follows the oracle's
+    Lloyd trajectory."""
+    torch = torch_cuda
+    X = datagen.sparse_tfidf(20000, 8000, 40.0, 5151, topics=20)
+    Xd = skm.DeviceCSR.from_host(X)
+    for k in (20, 100, 300):
+        C0 = datagen.init_centers_csr(X, datagen.init_rows(X.n, k, 23 + k))
+        ref = oracle.fit(X, C0, "lloyd", 20)
+        for v in VARIANTS:
+            for sched, prec in ((1, 0), (0, 0), (1, 2)):
+                if prec == 2 and k < 65:
+                    continue
+                say("case topical rows k=%d %s schedule=%d precision=%d" % (k, v, sched, prec))
+                a, C, C64, st = run_fit(skm, torch, Xd, C0, k, v, 20, schedule=sched,
+                                        precision=prec)
+                assert st.iterations == ref.iterations
+                assert np.array_equal(a, ref.a)
+                assert np.linalg.norm(C64 - ref.C, axis=1).max() < 1e-6
+                say("  sims %.3f of Lloyd's" % (st.sims_point_center / (X.n * k * st.iterations)))
+
+
 def test_dense_shape_sweep_matches_oracle(skm, torch_cuda):
     """Seeded sweep of small dense shapes (row counts that leave partial
     waves and blocks, widths on both sides of every padded width, k on both
