@@ -163,7 +163,11 @@ typedef struct {            /* [host]; an all-zero struct means defaults      */
                                (measured by tune_walk.py) picks for the
                                variant, k and the mean row length, always
                                sliced when the copy exceeds 256 MB; 1 =
-                               always sliced; 2 = always whole rows.
+                               always sliced, and Elkan and Yin-Yang at
+                               128 < k <= 256 walk their one slice packed
+                               (only the centres whose bounds fail; faster
+                               where the bounds prune most pairs, slower
+                               where they do not); 2 = always whole rows.
                                Results are identical; only speed and
                                workspace size differ.                     */
 } skm_options;

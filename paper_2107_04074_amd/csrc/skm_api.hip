@@ -188,7 +188,11 @@ int row_class(int64_t n, int64_t nnz) {
 // cache, else the measured table's entry for the variant's family (0 Lloyd
 // and Hamerly, 1 Elkan, 2 Yin-Yang), the row-length class and the width.
 bool chunk_fp32(int32_t chunk_walk, int family, int64_t n, int64_t d, int64_t nnz, int kp) {
-  if (kp <= kChunkF32) return false;
+  if (kp < kChunkF32) return false;
+  // one slice of 256: Elkan and Yin-Yang on request, so that the walk visits
+  // only the centres whose bounds fail (a whole-row walk visits all of a row's
+  // centres once any pair survives); faster where the bounds prune most pairs
+  if (kp == kChunkF32) return family != 0 && chunk_walk == 1;
   if (chunk_walk == 1) return true;
   if (chunk_walk == 2) return false;
   if ((double)d * (double)kp * 4.0 > kChunkAlwaysBytes) return true;

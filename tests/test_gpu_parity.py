@@ -485,9 +485,12 @@ def test_sparse_k_sweep_matches_oracle(skm, torch_cuda):
         for v in VARIANTS:
             for prec in (0, 2):
                 # FP32 copy above 256 centres: 256-centre slices and whole
-                # rows (the tuning table picks one of them)
+                # rows (the tuning table picks one of them); Elkan and
+                # Yin-Yang at 128 < k <= 256: one packed slice on request
                 sliceable = prec == 0 and k > 256
-                for cw in ((1, 2) if sliceable else (0,)):
+                packed = prec == 0 and 128 < k <= 256 and ("elkan" in v or v == "yinyang")
+                cws = (1, 2) if sliceable else (0, 1) if packed else (0,)
+                for cw in cws:
                     say("case sparse k sweep k=%d %s precision=%d chunk_walk=%d" % (k, v, prec, cw))
                     a, C, C64, st = run_fit(skm, torch, Xd, C0, k, v, 8, precision=prec,
                                             schedule=1, chunk_walk=cw)
@@ -558,12 +561,15 @@ def test_topical_rows_match_oracle(skm, torch_cuda):
         C0 = datagen.init_centers_csr(X, datagen.init_rows(X.n, k, 23 + k))
         ref = oracle.fit(X, C0, "lloyd", 20)
         for v in VARIANTS:
-            for sched, prec in ((1, 0), (0, 0), (1, 2)):
-                if prec == 2 and k < 65:
+            # chunk_walk 1 at k = 100 and 300: 256-centre slices (at k = 100
+            # one packed slice for Elkan and Yin-Yang, whole rows otherwise)
+            for sched, prec, cw in ((1, 0, 0), (0, 0, 0), (1, 2, 0), (0, 0, 1)):
+                if prec == 2 and k < 65 or cw == 1 and k < 65:
                     continue
-                say("case topical rows k=%d %s schedule=%d precision=%d" % (k, v, sched, prec))
+                say("case topical rows k=%d %s schedule=%d precision=%d chunk_walk=%d" %
+                    (k, v, sched, prec, cw))
                 a, C, C64, st = run_fit(skm, torch, Xd, C0, k, v, 20, schedule=sched,
-                                        precision=prec)
+                                        precision=prec, chunk_walk=cw)
                 assert st.iterations == ref.iterations
                 assert np.array_equal(a, ref.a)
                 assert np.linalg.norm(C64 - ref.C, axis=1).max() < 1e-6
