@@ -162,14 +162,18 @@ typedef struct {            /* [host]; an all-zero struct means defaults      */
                                (one launch) as the library's tuning table
                                (measured by tune_walk.py) picks for the
                                variant, k and the mean row length, always
-                               sliced when the copy exceeds 256 MB; 1 =
-                               always sliced, and Elkan and Yin-Yang at
-                               128 < k <= 256 walk their one slice packed
-                               (only the centres whose bounds fail; faster
-                               where the bounds prune most pairs, slower
-                               where they do not); 2 = always whole rows.
-                               Results are identical; only speed and
-                               workspace size differ.                     */
+                               sliced when the copy exceeds 256 MB;
+                               Yin-Yang where whole rows are picked at
+                               k > 128 times its steps with tests both
+                               ways (whole rows, packed slices) in the
+                               first eight steps and keeps the faster;
+                               1 = always sliced, and Elkan and Yin-Yang
+                               at 128 < k <= 256 walk their one slice
+                               packed (only the centres whose bounds fail;
+                               faster where the bounds prune most pairs,
+                               slower where they do not); 2 = always whole
+                               rows.  Results are identical; only speed
+                               and workspace size differ.                 */
 } skm_options;
 
 typedef struct {            /* [host] filled by skm_fit                       */

@@ -78,6 +78,9 @@ struct Plan {
   int chunk = 0;      // centres per launch of a chunked row walk (0: one launch)
   int chunk16 = 0, nq16 = 0;  // Yin-Yang / Elkan steps, FP16 copy: chunk width, launches
   int nq = 1;         // launches per walk
+  // Yin-Yang, FP32 copy, whole rows chosen at kp >= 256: the steps with tests
+  // may switch to 256-centre slices (packed groups) during the fit
+  bool yy_adapt = false;
   size_t uy = 0, gpc = 0, gps = 0;
   size_t CT = 0, CT16 = 0, negflag = 0, C64 = 0, S = 0, l = 0, u = 0, ue = 0, eta = 0,
          a_old = 0, norm64 = 0, part = 0, part_sq = 0, pc = 0, ps = 0, dirty = 0, mm = 0, G = 0,
@@ -291,6 +294,13 @@ int make_plan(const skm_matrix* X, int32_t k, int32_t variant, int32_t precision
     P->nq = (k + kChunkF32 - 1) / kChunkF32;
     P->rs = take(n * sizeof(RowRun));
     if (P->elkan) P->umask = take(n * (size_t)(g.kp / kChunkF32) * sizeof(uint64_t));
+  } else if (!P->half && P->yy && chunk_walk == 0 && g.kp >= kChunkF32) {
+    // whole rows: a row walk covers every group of a row with a surviving
+    // group, so where the group filter leaves few groups per row, packed
+    // slices walk far fewer centres; the fit measures that (below)
+    P->yy_adapt = true;
+    P->nq = (k + kChunkF32 - 1) / kChunkF32;
+    P->rs = take(n * sizeof(RowRun));
   }
   // Yin-Yang and Elkan with the FP16 copy at k > 512: the steps with tests
   // walk 1 KB of every FP16 centre row per launch, packing each row's
@@ -1579,8 +1589,18 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
   float* maxeta = at<float>(ws, P.maxeta);
   double* initnorm = at<double>(ws, P.initnorm);
 
-  RowRun* rs = (P.chunk || P.chunk16) ? at<RowRun>(ws, P.rs) : nullptr;
+  RowRun* rs = (P.chunk || P.chunk16 || P.yy_adapt) ? at<RowRun>(ws, P.rs) : nullptr;
   uint64_t* umask = ((P.chunk || P.chunk16) && P.elkan) ? at<uint64_t>(ws, P.umask) : nullptr;
+  // Yin-Yang with yy_adapt: which walk its steps with tests take.  The
+  // first chunk of steps times both (HIP events around each step's walk;
+  // steps 2, 5, 6, ... whole rows, 3, 4, 7, ... packed slices, so that a
+  // trend over the steps favours neither), and the rest of the fit keeps
+  // the faster: packed slices pay where the group filter leaves few groups
+  // per row, which the rows' structure decides, not the problem's shape.
+  int yy_choice = 0;  // 0 timing both, 1 whole rows, 2 packed slices
+  bool yy_pack_step = false;
+  double yy_ms[2] = {0.0, 0.0};
+  int yy_steps[2] = {0, 0};
   // one assignment-step walk in `mode`: one launch, or one per chunk of
   // centres with the running per-row results in rs
   auto walk = [&](AssignArgs& A, int mode) -> hipError_t {
@@ -1595,9 +1615,11 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
       }
       return hipSuccess;
     }
-    if (!P.chunk) return launch_assign(A, mode, s);
+    if (!P.chunk && !(yy_pack_step && mode == kModeYinYang)) return launch_assign(A, mode, s);
+    // slices need the running record and a copy at least one slice wide
+    if (rs == nullptr || P.kp < kChunkF32) return hipErrorInvalidValue;
     for (int q = 0; q < P.nq; ++q) {
-      A.j0 = q * P.chunk;
+      A.j0 = q * kChunkF32;
       A.chunk_last = q == P.nq - 1 ? 1 : 0;
       A.rs = rs;
       A.umask = umask;
@@ -1610,6 +1632,7 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
   int64_t tot_sims = 0, tot_rechecks = 0, sk_launches = 0, sk_rows = 0, sk_nnz = 0;
   double sk_ms = 0.0;
   const bool prof = o.profile != 0;
+  const bool timed = prof || P.yy_adapt;
   hipEvent_t ev0[kStepChunk] = {}, ev1[kStepChunk] = {};
   double objective = 0.0;
   {
@@ -1643,7 +1666,7 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
       rc = validate_input(X, at<unsigned long long>(ws, P.vbad), s);
       if (rc != SKM_OK) goto done;
     }
-    if (prof)
+    if (timed)
       for (int c = 0; c < kStepChunk; ++c) {
         SKM_HIP(hipEventCreate(&ev0[c]));
         SKM_HIP(hipEventCreate(&ev1[c]));
@@ -1717,7 +1740,9 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
         const int32_t t = t0 + c;
         Counters* cs = cnt + (size_t)c * kCounterSlots;
         const bool exhaustive = (t == 0) || variant == SKM_LLOYD;
-        if (prof) SKM_HIP(hipEventRecord(ev0[c], s));
+        yy_pack_step = P.yy_adapt && (yy_choice == 2 || (yy_choice == 0 && t >= 2 &&
+                                                          ((t - 2) % 4 == 1 || (t - 2) % 4 == 2)));
+        if (timed) SKM_HIP(hipEventRecord(ev0[c], s));
         AssignArgs A{};
         A.rp = X->row_ptr;
         A.ci = X->col_idx;
@@ -1763,7 +1788,7 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
           A.gate = 2;
           SKM_HIP(walk(A, P.elkan ? kModeFitElkanInit : kModeFit));
         }
-        if (prof) SKM_HIP(hipEventRecord(ev1[c], s));
+        if (timed) SKM_HIP(hipEventRecord(ev1[c], s));
         const bool gram = (int64_t)t + 1 >= off_until;
         SKM_HIP(launch_step_end(cs, ctl, rec + c, per, t, n, dirty, k, gram ? 1 : 0, s));
         SKM_HIP(centre_update(gram));
@@ -1776,10 +1801,15 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
         const StepRec& r = hm->rec[c];
         if (!r.valid) break;
         const int32_t t = t0 + c;
-        if (prof) {
+        if (timed) {
           float ms = 0.f;
           SKM_HIP(hipEventElapsedTime(&ms, ev0[c], ev1[c]));
-          sk_ms += ms;
+          if (prof) sk_ms += ms;
+          if (P.yy_adapt && yy_choice == 0 && t >= 2) {
+            const int w = ((t - 2) % 4 == 1 || (t - 2) % 4 == 2) ? 1 : 0;
+            yy_ms[w] += ms;
+            yy_steps[w] += 1;
+          }
         }
         sk_launches += 1;
         sk_rows += (int64_t)r.rows_done;
@@ -1799,6 +1829,9 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
       }
       t0 += ch;
       off_until = hm->ctl.tests ? INT64_MIN : (int64_t)hm->ctl.test_next;
+      // packed slices only where clearly faster (3%)
+      if (P.yy_adapt && yy_choice == 0 && yy_steps[0] >= 2 && yy_steps[1] >= 2)
+        yy_choice = yy_ms[1] / yy_steps[1] < 0.97 * (yy_ms[0] / yy_steps[0]) ? 2 : 1;
     }
     // final objective (after the last update) and centre-centre count
     SKM_HIP(hipMemcpyAsync(&hm->per, per, sizeof(Persist), hipMemcpyDeviceToHost, s));

@@ -576,6 +576,36 @@ def test_topical_rows_match_oracle(skm, torch_cuda):
                 say("  sims %.3f of Lloyd's" % (st.sims_point_center / (X.n * k * st.iterations)))
 
 
+def test_yinyang_timed_walk_choice_matches_oracle(skm, torch_cuda):
+    """Yin-Yang with whole-row walks (k_p >= 256) times its steps with tests
+    both ways in the first chunk of steps (whole rows at steps 2, 5, 6,
+    packed 256-centre slices at 3, 4, 7) and keeps the faster: steps of the
+    two walks alternate in both directions, and every fit follows the
+    oracle's Lloyd trajectory whichever walk it keeps, on topic-structured
+    and plain rows, tests adaptive and at every step, against whole rows
+    and packed slices throughout."""
+    torch = torch_cuda
+    for topics, seed in ((20, 5353), (0, 5354)):
+        X = datagen.sparse_tfidf(20000, 8000, 40.0, seed, topics=topics)
+        Xd = skm.DeviceCSR.from_host(X)
+        for k in (129, 200, 256, 300, 600):
+            C0 = datagen.init_centers_csr(X, datagen.init_rows(X.n, k, 41 + k))
+            ref = oracle.fit(X, C0, "lloyd", 30)
+            sims = {}
+            for sched in (0, 1):
+                for cw in (0, 1, 2):
+                    say("case yinyang switch topics=%d k=%d schedule=%d chunk_walk=%d" %
+                        (topics, k, sched, cw))
+                    a, C, C64, st = run_fit(skm, torch, Xd, C0, k, "yinyang", 30, schedule=sched,
+                                            chunk_walk=cw)
+                    assert st.iterations == ref.iterations
+                    assert np.array_equal(a, ref.a)
+                    assert np.linalg.norm(C64 - ref.C, axis=1).max() < 1e-6
+                    sims[sched, cw] = st.sims_point_center
+            say("  similarities: timed choice %d, packed %d, whole rows %d" %
+                (sims[1, 0], sims[1, 1], sims[1, 2]))
+
+
 def test_dense_shape_sweep_matches_oracle(skm, torch_cuda):
     """Seeded sweep of small dense shapes (row counts that leave partial
     waves and blocks, widths on both sides of every padded width, k on both
