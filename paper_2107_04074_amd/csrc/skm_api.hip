@@ -78,9 +78,10 @@ struct Plan {
   int chunk = 0;      // centres per launch of a chunked row walk (0: one launch)
   int chunk16 = 0, nq16 = 0;  // Yin-Yang / Elkan steps, FP16 copy: chunk width, launches
   int nq = 1;         // launches per walk
-  // Yin-Yang, FP32 copy, whole rows chosen at kp >= 256: the steps with tests
-  // may switch to 256-centre slices (packed groups) during the fit
-  bool yy_adapt = false;
+  // Yin-Yang at kp >= 256 and Elkan at kp >= 512, FP32 copy, whole rows
+  // chosen: the steps with tests may switch to packed 256-centre slices
+  // during the fit
+  bool pack_adapt = false;
   size_t uy = 0, gpc = 0, gps = 0;
   size_t CT = 0, CT16 = 0, negflag = 0, C64 = 0, S = 0, l = 0, u = 0, ue = 0, eta = 0,
          a_old = 0, norm64 = 0, part = 0, part_sq = 0, pc = 0, ps = 0, dirty = 0, mm = 0, G = 0,
@@ -294,13 +295,17 @@ int make_plan(const skm_matrix* X, int32_t k, int32_t variant, int32_t precision
     P->nq = (k + kChunkF32 - 1) / kChunkF32;
     P->rs = take(n * sizeof(RowRun));
     if (P->elkan) P->umask = take(n * (size_t)(g.kp / kChunkF32) * sizeof(uint64_t));
-  } else if (!P->half && P->yy && chunk_walk == 0 && g.kp >= kChunkF32) {
-    // whole rows: a row walk covers every group of a row with a surviving
-    // group, so where the group filter leaves few groups per row, packed
-    // slices walk far fewer centres; the fit measures that (below)
-    P->yy_adapt = true;
+  } else if (!P->half && chunk_walk == 0 &&
+             ((P->yy && g.kp >= kChunkF32) || (P->elkan && g.kp > kChunkF32))) {
+    // whole rows: a row walk covers every centre of a row with a surviving
+    // pair or group, so where the tests leave few per row, packed slices
+    // walk far fewer centres; the fit measures which is faster (Elkan's
+    // one packed slice gained at most 6% on topical rows and lost up to 7%
+    // to its timing steps on plain ones)
+    P->pack_adapt = true;
     P->nq = (k + kChunkF32 - 1) / kChunkF32;
     P->rs = take(n * sizeof(RowRun));
+    if (P->elkan) P->umask = take(n * (size_t)(g.kp / kChunkF32) * sizeof(uint64_t));
   }
   // Yin-Yang and Elkan with the FP16 copy at k > 512: the steps with tests
   // walk 1 KB of every FP16 centre row per launch, packing each row's
@@ -1589,18 +1594,20 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
   float* maxeta = at<float>(ws, P.maxeta);
   double* initnorm = at<double>(ws, P.initnorm);
 
-  RowRun* rs = (P.chunk || P.chunk16 || P.yy_adapt) ? at<RowRun>(ws, P.rs) : nullptr;
-  uint64_t* umask = ((P.chunk || P.chunk16) && P.elkan) ? at<uint64_t>(ws, P.umask) : nullptr;
-  // Yin-Yang with yy_adapt: which walk its steps with tests take.  The
-  // first chunk of steps times both (HIP events around each step's walk;
-  // steps 2, 5, 6, ... whole rows, 3, 4, 7, ... packed slices, so that a
+  RowRun* rs = (P.chunk || P.chunk16 || P.pack_adapt) ? at<RowRun>(ws, P.rs) : nullptr;
+  uint64_t* umask =
+      ((P.chunk || P.chunk16 || P.pack_adapt) && P.elkan) ? at<uint64_t>(ws, P.umask) : nullptr;
+  // Elkan and Yin-Yang with pack_adapt: which walk their steps with tests
+  // take.  The first chunk of steps times both (HIP events around each
+  // step's walk; steps 2 and 5 whole rows, 3 and 4 packed slices, so that a
   // trend over the steps favours neither), and the rest of the fit keeps
-  // the faster: packed slices pay where the group filter leaves few groups
-  // per row, which the rows' structure decides, not the problem's shape.
-  int yy_choice = 0;  // 0 timing both, 1 whole rows, 2 packed slices
-  bool yy_pack_step = false;
-  double yy_ms[2] = {0.0, 0.0};
-  int yy_steps[2] = {0, 0};
+  // the faster: packed slices pay where the tests leave few centres per
+  // row, which the rows' structure decides, not the problem's shape.
+  int pack_choice = 0;  // 0 timing both, 1 whole rows, 2 packed slices
+  bool pack_step = false;
+  double pack_ms[2] = {0.0, 0.0};
+  int pack_steps[2] = {0, 0};
+  const int pack_mode = P.elkan ? kModeElkan : kModeYinYang;
   // one assignment-step walk in `mode`: one launch, or one per chunk of
   // centres with the running per-row results in rs
   auto walk = [&](AssignArgs& A, int mode) -> hipError_t {
@@ -1615,7 +1622,7 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
       }
       return hipSuccess;
     }
-    if (!P.chunk && !(yy_pack_step && mode == kModeYinYang)) return launch_assign(A, mode, s);
+    if (!P.chunk && !(pack_step && mode == pack_mode)) return launch_assign(A, mode, s);
     // slices need the running record and a copy at least one slice wide
     if (rs == nullptr || P.kp < kChunkF32) return hipErrorInvalidValue;
     for (int q = 0; q < P.nq; ++q) {
@@ -1632,7 +1639,7 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
   int64_t tot_sims = 0, tot_rechecks = 0, sk_launches = 0, sk_rows = 0, sk_nnz = 0;
   double sk_ms = 0.0;
   const bool prof = o.profile != 0;
-  const bool timed = prof || P.yy_adapt;
+  const bool timed = prof || P.pack_adapt;
   hipEvent_t ev0[kStepChunk] = {}, ev1[kStepChunk] = {};
   double objective = 0.0;
   {
@@ -1740,8 +1747,7 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
         const int32_t t = t0 + c;
         Counters* cs = cnt + (size_t)c * kCounterSlots;
         const bool exhaustive = (t == 0) || variant == SKM_LLOYD;
-        yy_pack_step = P.yy_adapt && (yy_choice == 2 || (yy_choice == 0 && t >= 2 &&
-                                                          ((t - 2) % 4 == 1 || (t - 2) % 4 == 2)));
+        pack_step = P.pack_adapt && (pack_choice == 2 || (pack_choice == 0 && (t == 3 || t == 4)));
         if (timed) SKM_HIP(hipEventRecord(ev0[c], s));
         AssignArgs A{};
         A.rp = X->row_ptr;
@@ -1805,10 +1811,10 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
           float ms = 0.f;
           SKM_HIP(hipEventElapsedTime(&ms, ev0[c], ev1[c]));
           if (prof) sk_ms += ms;
-          if (P.yy_adapt && yy_choice == 0 && t >= 2) {
-            const int w = ((t - 2) % 4 == 1 || (t - 2) % 4 == 2) ? 1 : 0;
-            yy_ms[w] += ms;
-            yy_steps[w] += 1;
+          if (P.pack_adapt && pack_choice == 0 && t >= 2 && t <= 5) {
+            const int w = (t == 3 || t == 4) ? 1 : 0;
+            pack_ms[w] += ms;
+            pack_steps[w] += 1;
           }
         }
         sk_launches += 1;
@@ -1830,8 +1836,8 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
       t0 += ch;
       off_until = hm->ctl.tests ? INT64_MIN : (int64_t)hm->ctl.test_next;
       // packed slices only where clearly faster (3%)
-      if (P.yy_adapt && yy_choice == 0 && yy_steps[0] >= 2 && yy_steps[1] >= 2)
-        yy_choice = yy_ms[1] / yy_steps[1] < 0.97 * (yy_ms[0] / yy_steps[0]) ? 2 : 1;
+      if (P.pack_adapt && pack_choice == 0 && pack_steps[0] >= 2 && pack_steps[1] >= 2)
+        pack_choice = pack_ms[1] / pack_steps[1] < 0.97 * (pack_ms[0] / pack_steps[0]) ? 2 : 1;
     }
     // final objective (after the last update) and centre-centre count
     SKM_HIP(hipMemcpyAsync(&hm->per, per, sizeof(Persist), hipMemcpyDeviceToHost, s));

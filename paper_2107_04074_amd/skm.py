@@ -215,8 +215,9 @@ def _options(bound_form=0, precision=0, validate=0, norm_tol=0.0, profile=0, war
     walk_layout: row-walk layout of FP32 Lloyd/Hamerly whole-row walks at
     16 < k <= 512 (0 = the library's tuning table, 1 = default, 2 = alternative);
     chunk_walk: FP32 CSR fits at 256 < k: 0 = the tuning table (sliced above
-    a 256 MB copy; Yin-Yang on whole rows at 128 < k times both walks of its
-    steps with tests and keeps the faster), 1 = 256-centre slices (Elkan and
+    a 256 MB copy; Yin-Yang at 128 < k and Elkan at 256 < k on whole rows
+    time both walks of their steps with tests and keep the faster), 1 =
+    256-centre slices (Elkan and
     Yin-Yang at 128 < k <= 256: one packed slice), 2 = whole rows."""
     w = (None, None, None) if warm is None else tuple(_ptr(t) for t in warm)
     return SkmOptions(bound_form, precision, validate, profile, norm_tol, *w, schedule,

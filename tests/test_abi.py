@@ -314,12 +314,12 @@ def test_slicing_decision_follows_the_table(lib):
                     size[cw] = lib.skm_workspace_size(ctypes.byref(m), k, variant, ctypes.byref(o))
                 assert size[1] > size[2] > 0
                 sliced = big or table[3 * fam + rc][0] == 1
-                # Yin-Yang keeps the running record for slices it may
-                # switch to during the fit, whole rows or not
-                assert size[0] == (size[1] if sliced or fam == 2 else size[2]), (fam, rc, d)
+                # Elkan and Yin-Yang keep what slices need (running record,
+                # Elkan's survival words): they may switch to them mid-fit
+                assert size[0] == (size[1] if sliced or fam > 0 else size[2]), (fam, rc, d)
     # 128 < k <= 256: whole rows unless chunk_walk 1 asks Elkan or Yin-Yang
-    # for their one packed slice (Yin-Yang by default may switch to it);
-    # Lloyd and Hamerly never slice there
+    # for their one packed slice (by default they may switch to it); Lloyd
+    # and Hamerly never slice there
     m = _fake_csr(n=n, d=200000, nnz=n * 30)
     for variant, packs in ((skm.HAMERLY, False), (skm.ELKAN, True), (skm.YINYANG, True)):
         size = {}
@@ -328,4 +328,5 @@ def test_slicing_decision_follows_the_table(lib):
             size[cw] = lib.skm_workspace_size(ctypes.byref(m), 200, variant, ctypes.byref(o))
         assert size[2] > 0
         assert (size[1] > size[2]) if packs else (size[1] == size[2]), variant
+        # the timed choice at this width: Yin-Yang only
         assert size[0] == (size[1] if variant == skm.YINYANG else size[2]), variant

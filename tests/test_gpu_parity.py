@@ -576,14 +576,15 @@ def test_topical_rows_match_oracle(skm, torch_cuda):
                 say("  sims %.3f of Lloyd's" % (st.sims_point_center / (X.n * k * st.iterations)))
 
 
-def test_yinyang_timed_walk_choice_matches_oracle(skm, torch_cuda):
-    """Yin-Yang with whole-row walks (k_p >= 256) times its steps with tests
-    both ways in the first chunk of steps (whole rows at steps 2, 5, 6,
-    packed 256-centre slices at 3, 4, 7) and keeps the faster: steps of the
-    two walks alternate in both directions, and every fit follows the
-    oracle's Lloyd trajectory whichever walk it keeps, on topic-structured
-    and plain rows, tests adaptive and at every step, against whole rows
-    and packed slices throughout."""
+@pytest.mark.parametrize("variant", ["yinyang", "elkan", "simp_elkan"])
+def test_timed_walk_choice_matches_oracle(skm, torch_cuda, variant):
+    """Yin-Yang (k_p >= 256) and Elkan (k_p >= 512) with whole-row walks time
+    their steps with tests both ways in the first chunk of steps (whole rows
+    at steps 2 and 5, packed 256-centre slices at 3 and 4) and keep the
+    faster: steps of the two walks alternate in both directions, and every
+    fit follows the oracle's Lloyd trajectory whichever walk it keeps, on
+    topic-structured and plain rows, tests adaptive and at every step,
+    against whole rows and packed slices throughout."""
     torch = torch_cuda
     for topics, seed in ((20, 5353), (0, 5354)):
         X = datagen.sparse_tfidf(20000, 8000, 40.0, seed, topics=topics)
@@ -594,9 +595,9 @@ def test_yinyang_timed_walk_choice_matches_oracle(skm, torch_cuda):
             sims = {}
             for sched in (0, 1):
                 for cw in (0, 1, 2):
-                    say("case yinyang switch topics=%d k=%d schedule=%d chunk_walk=%d" %
-                        (topics, k, sched, cw))
-                    a, C, C64, st = run_fit(skm, torch, Xd, C0, k, "yinyang", 30, schedule=sched,
+                    say("case timed walk %s topics=%d k=%d schedule=%d chunk_walk=%d" %
+                        (variant, topics, k, sched, cw))
+                    a, C, C64, st = run_fit(skm, torch, Xd, C0, k, variant, 30, schedule=sched,
                                             chunk_walk=cw)
                     assert st.iterations == ref.iterations
                     assert np.array_equal(a, ref.a)
