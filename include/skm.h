@@ -164,10 +164,11 @@ typedef struct {            /* [host]; an all-zero struct means defaults      */
                                variant, k and the mean row length, always
                                sliced when the copy exceeds 256 MB;
                                Yin-Yang at k > 128 and Elkan at k > 256
-                               where whole rows are picked time their
-                               steps with tests both ways (whole rows,
-                               packed slices) in the first eight steps
-                               and keep the faster;
+                               where whole rows are picked (and rows hold
+                               20 or more stored entries on average) time
+                               their steps with tests both ways (whole
+                               rows, packed slices) in the first eight
+                               steps and keep the faster;
                                1 = always sliced, and Elkan and Yin-Yang
                                at 128 < k <= 256 walk their one slice
                                packed (only the centres whose bounds fail;

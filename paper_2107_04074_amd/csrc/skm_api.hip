@@ -295,13 +295,15 @@ int make_plan(const skm_matrix* X, int32_t k, int32_t variant, int32_t precision
     P->nq = (k + kChunkF32 - 1) / kChunkF32;
     P->rs = take(n * sizeof(RowRun));
     if (P->elkan) P->umask = take(n * (size_t)(g.kp / kChunkF32) * sizeof(uint64_t));
-  } else if (!P->half && chunk_walk == 0 &&
+  } else if (!P->half && chunk_walk == 0 && row_class(P->n, P->nnz) > 0 &&
              ((P->yy && g.kp >= kChunkF32) || (P->elkan && g.kp > kChunkF32))) {
     // whole rows: a row walk covers every centre of a row with a surviving
     // pair or group, so where the tests leave few per row, packed slices
     // walk far fewer centres; the fit measures which is faster (Elkan's
     // one packed slice gained at most 6% on topical rows and lost up to 7%
-    // to its timing steps on plain ones)
+    // to its timing steps on plain ones; on rows under 20 stored entries
+    // the per-row work of a slice outweighs what it saves, and the two
+    // timing steps alone cost Yin-Yang 7-13% of a fit)
     P->pack_adapt = true;
     P->nq = (k + kChunkF32 - 1) / kChunkF32;
     P->rs = take(n * sizeof(RowRun));
