@@ -61,7 +61,11 @@ def test_batched_equals_individual_fits(skm, torch_cuda, problems, variant, work
         assert torch.equal(a, a1), b
         assert torch.equal(C, C1), b
         assert st.iterations == st1.iterations and st.converged == st1.converged, b
-        assert st.sims_point_center == st1.sims_point_center, b
+        # Elkan and Yin-Yang time their walk choice at wide k (whole rows or
+        # packed slices), so two runs may count different similarities; the
+        # results may not differ
+        if variant not in ("elkan", "simp_elkan", "yinyang"):
+            assert st.sims_point_center == st1.sims_point_center, b
     say("  %d problems, iterations %s" % (len(res), [r[2].iterations for r in res]))
 
 
