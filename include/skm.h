@@ -168,7 +168,9 @@ typedef struct {            /* [host]; an all-zero struct means defaults      */
                                20 or more stored entries on average) time
                                their steps with tests both ways (whole
                                rows, packed slices) in the first eight
-                               steps and keep the faster;
+                               steps and keep the faster, as do Lloyd and
+                               Hamerly (every walk) for copies of 64 MB
+                               to 256 MB where the table picks whole rows;
                                1 = always sliced, and Elkan and Yin-Yang
                                at 128 < k <= 256 walk their one slice
                                packed (only the centres whose bounds fail;

@@ -80,8 +80,8 @@ struct Plan {
   int nq = 1;         // launches per walk
   // Yin-Yang at kp >= 256 and Elkan at kp >= 512, FP32 copy, whole rows
   // chosen: the steps with tests may switch to packed 256-centre slices
-  // during the fit
-  bool pack_adapt = false;
+  // during the fit; Lloyd and Hamerly (pack_all) may slice every walk
+  bool pack_adapt = false, pack_all = false;
   size_t uy = 0, gpc = 0, gps = 0;
   size_t CT = 0, CT16 = 0, negflag = 0, C64 = 0, S = 0, l = 0, u = 0, ue = 0, eta = 0,
          a_old = 0, norm64 = 0, part = 0, part_sq = 0, pc = 0, ps = 0, dirty = 0, mm = 0, G = 0,
@@ -177,6 +177,12 @@ int check_init_norms(const double* initnorm, int32_t k, double tol, hipStream_t 
 // cache; a 256-centre slice of it does (measured: 1.38 times faster than
 // whole rows at a 410 MB copy, 10^6 rows of ~150 entries, k = 1000).
 constexpr double kChunkAlwaysBytes = 256.0 * 1024.0 * 1024.0;
+// Lloyd and Hamerly fits whose copy is at least this size (and below the one
+// above) time slices against the table's whole rows in their first steps:
+// the table was measured on 10,000-column copies (20 MB at 512 centres),
+// and a 97 MB copy (47,236 columns, 512 centres) walked 1.02-1.10 times
+// faster in slices, the more so on topic-structured rows.
+constexpr double kTimedSliceBytes = 64.0 * 1024.0 * 1024.0;
 
 // Row-length class of the tuning tables: the first class whose bound on the
 // mean stored entries per row exceeds this matrix's mean, else the last.
@@ -296,15 +302,19 @@ int make_plan(const skm_matrix* X, int32_t k, int32_t variant, int32_t precision
     P->rs = take(n * sizeof(RowRun));
     if (P->elkan) P->umask = take(n * (size_t)(g.kp / kChunkF32) * sizeof(uint64_t));
   } else if (!P->half && chunk_walk == 0 && row_class(P->n, P->nnz) > 0 &&
-             ((P->yy && g.kp >= kChunkF32) || (P->elkan && g.kp > kChunkF32))) {
+             ((P->yy && g.kp >= kChunkF32) || (P->elkan && g.kp > kChunkF32) ||
+              (!P->yy && !P->elkan && g.kp > kChunkF32 &&
+               (double)P->d * (double)g.kp * 4.0 >= kTimedSliceBytes))) {
     // whole rows: a row walk covers every centre of a row with a surviving
     // pair or group, so where the tests leave few per row, packed slices
-    // walk far fewer centres; the fit measures which is faster (Elkan's
+    // walk far fewer centres (Lloyd and Hamerly: a slice of a large copy
+    // stays cached); the fit measures which is faster (Elkan's
     // one packed slice gained at most 6% on topical rows and lost up to 7%
     // to its timing steps on plain ones; on rows under 20 stored entries
     // the per-row work of a slice outweighs what it saves, and the two
     // timing steps alone cost Yin-Yang 7-13% of a fit)
     P->pack_adapt = true;
+    P->pack_all = !P->yy && !P->elkan;
     P->nq = (k + kChunkF32 - 1) / kChunkF32;
     P->rs = take(n * sizeof(RowRun));
     if (P->elkan) P->umask = take(n * (size_t)(g.kp / kChunkF32) * sizeof(uint64_t));
@@ -1599,12 +1609,14 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
   RowRun* rs = (P.chunk || P.chunk16 || P.pack_adapt) ? at<RowRun>(ws, P.rs) : nullptr;
   uint64_t* umask =
       ((P.chunk || P.chunk16 || P.pack_adapt) && P.elkan) ? at<uint64_t>(ws, P.umask) : nullptr;
-  // Elkan and Yin-Yang with pack_adapt: which walk their steps with tests
-  // take.  The first chunk of steps times both (HIP events around each
-  // step's walk; steps 2 and 5 whole rows, 3 and 4 packed slices, so that a
-  // trend over the steps favours neither), and the rest of the fit keeps
-  // the faster: packed slices pay where the tests leave few centres per
-  // row, which the rows' structure decides, not the problem's shape.
+  // Fits with pack_adapt: which walk their steps with tests (Lloyd and
+  // Hamerly: all their walks) take.  The first chunk of steps times both
+  // (HIP events around each step's walk; steps 2 and 5 whole rows, 3 and 4
+  // slices, so that a trend over the steps favours neither), and the rest
+  // of the fit keeps the faster: packed slices pay where the tests leave
+  // few centres per row, and slices of a large copy where the rows' terms
+  // spread the gathers over it, which the rows' structure decides, not the
+  // problem's shape.
   int pack_choice = 0;  // 0 timing both, 1 whole rows, 2 packed slices
   bool pack_step = false;
   double pack_ms[2] = {0.0, 0.0};
@@ -1624,7 +1636,8 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
       }
       return hipSuccess;
     }
-    if (!P.chunk && !(pack_step && mode == pack_mode)) return launch_assign(A, mode, s);
+    if (!P.chunk && !(pack_step && (P.pack_all || mode == pack_mode)))
+      return launch_assign(A, mode, s);
     // slices need the running record and a copy at least one slice wide
     if (rs == nullptr || P.kp < kChunkF32) return hipErrorInvalidValue;
     for (int q = 0; q < P.nq; ++q) {

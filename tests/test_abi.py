@@ -319,6 +319,15 @@ def test_slicing_decision_follows_the_table(lib):
                 # (not on rows under 20 stored entries: class 0)
                 assert size[0] == (size[1] if sliced or (fam > 0 and rc > 0) else size[2]), \
                     (fam, rc, d)
+    # Lloyd and Hamerly: a copy of 64 MB or more below 256 MB (here 102 MB,
+    # k_p = 512, long rows) slices, or keeps the running record of the slices
+    # its first steps time against the table's whole rows
+    m = _fake_csr(n=n, d=50000, nnz=n * 90)
+    size = {}
+    for cw in (0, 1, 2):
+        o = skm.SkmOptions(0, 0, 0, 0, 0.0, None, None, None, 0, 0, 0, cw)
+        size[cw] = lib.skm_workspace_size(ctypes.byref(m), k, skm.HAMERLY, ctypes.byref(o))
+    assert size[0] == size[1] > size[2] > 0
     # 128 < k <= 256: whole rows unless chunk_walk 1 asks Elkan or Yin-Yang
     # for their one packed slice (by default they may switch to it); Lloyd
     # and Hamerly never slice there

@@ -607,6 +607,29 @@ def test_timed_walk_choice_matches_oracle(skm, torch_cuda, variant):
                 (sims[1, 0], sims[1, 1], sims[1, 2]))
 
 
+def test_timed_slices_large_copy_matches_oracle(skm, torch_cuda):
+    """Lloyd and the Hamerly variants with an FP32 copy of 64 MB or more
+    (40,000 columns, k_p = 512) where the table picks whole rows time
+    256-centre slices against whole rows in their first steps (slices at
+    steps 3 and 4) and keep the faster: every fit follows the oracle's Lloyd
+    trajectory, on topic-structured and plain rows, tests adaptive and at
+    every step."""
+    torch = torch_cuda
+    for topics, seed in ((20, 5355), (0, 5356)):
+        X = datagen.sparse_tfidf(8000, 40000, 30.0, seed, topics=topics)
+        Xd = skm.DeviceCSR.from_host(X)
+        for k in (257, 400):
+            C0 = datagen.init_centers_csr(X, datagen.init_rows(X.n, k, 43 + k))
+            ref = oracle.fit(X, C0, "lloyd", 20)
+            for v in ("lloyd", "hamerly", "simp_hamerly"):
+                for sched in (0, 1):
+                    say("case timed slices %s topics=%d k=%d schedule=%d" % (v, topics, k, sched))
+                    a, C, C64, st = run_fit(skm, torch, Xd, C0, k, v, 20, schedule=sched)
+                    assert st.iterations == ref.iterations
+                    assert np.array_equal(a, ref.a)
+                    assert np.linalg.norm(C64 - ref.C, axis=1).max() < 1e-6
+
+
 def test_dense_shape_sweep_matches_oracle(skm, torch_cuda):
     """Seeded sweep of small dense shapes (row counts that leave partial
     waves and blocks, widths on both sides of every padded width, k on both
