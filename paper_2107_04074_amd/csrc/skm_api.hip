@@ -1828,7 +1828,11 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
           if (prof) sk_ms += ms;
           if (P.pack_adapt && pack_choice == 0 && t >= 2 && t <= 5) {
             const int w = (t == 3 || t == 4) ? 1 : 0;
-            pack_ms[w] += ms;
+            // Lloyd and Hamerly: time per computed similarity, so that a
+            // Hamerly step with tests (fewer rows walked) and a plain one
+            // compare; Elkan and Yin-Yang: time, since computing fewer
+            // similarities is what their packed slices are for
+            pack_ms[w] += P.pack_all ? (double)ms / (double)std::max<uint64_t>(r.sims, 1) : ms;
             pack_steps[w] += 1;
           }
         }
