@@ -1613,10 +1613,10 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
   // Hamerly: all their walks) take.  The first chunk of steps times both
   // (HIP events around each step's walk; steps 2 and 5 whole rows, 3 and 4
   // slices, so that a trend over the steps favours neither), and the rest
-  // of the fit keeps the faster: packed slices pay where the tests leave
-  // few centres per row, and slices of a large copy where the rows' terms
-  // spread the gathers over it, which the rows' structure decides, not the
-  // problem's shape.
+  // of the fit (from step 6: the first chunk ends there) keeps the faster:
+  // packed slices pay where the tests leave few centres per row, and slices
+  // of a large copy where the rows' terms spread the gathers over it, which
+  // the rows' structure decides, not the problem's shape.
   int pack_choice = 0;  // 0 timing both, 1 whole rows, 2 packed slices
   bool pack_step = false;
   double pack_ms[2] = {0.0, 0.0};
@@ -1756,7 +1756,10 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
     int64_t off_until = INT64_MIN;
     const int32_t layout = walk_layout_for(o, P.kp, n, X->nnz);
     for (int32_t t0 = warm ? 1 : 0; t0 < max_iter;) {
-      const int ch = (int)std::min<int64_t>(kStepChunk, (int64_t)max_iter - t0);
+      int ch = (int)std::min<int64_t>(kStepChunk, (int64_t)max_iter - t0);
+      // a timed walk choice ends the first chunk with its last timing step,
+      // so the chosen walk starts at step 6
+      if (P.pack_adapt && pack_choice == 0 && t0 < 6) ch = std::min(ch, 6 - (int)t0);
       SKM_HIP(hipMemsetAsync(cnt, 0, (size_t)ch * kCounterSlots * sizeof(Counters), s));
       for (int c = 0; c < ch; ++c) {
         const int32_t t = t0 + c;
