@@ -78,9 +78,10 @@ struct Plan {
   int chunk = 0;      // centres per launch of a chunked row walk (0: one launch)
   int chunk16 = 0, nq16 = 0;  // Yin-Yang / Elkan steps, FP16 copy: chunk width, launches
   int nq = 1;         // launches per walk
-  // Yin-Yang at kp >= 256 and Elkan at kp >= 512, FP32 copy, whole rows
-  // chosen: the steps with tests may switch to packed 256-centre slices
-  // during the fit; Lloyd and Hamerly (pack_all) may slice every walk
+  // FP32 copy, whole rows chosen, Yin-Yang at kp >= 256 and Elkan at kp >=
+  // 512: the steps with tests may switch to packed 256-centre slices during
+  // the fit; Lloyd and Hamerly with a copy of 64 MB or more (pack_all): every
+  // walk may switch to slices
   bool pack_adapt = false, pack_all = false;
   size_t uy = 0, gpc = 0, gps = 0;
   size_t CT = 0, CT16 = 0, negflag = 0, C64 = 0, S = 0, l = 0, u = 0, ue = 0, eta = 0,
@@ -308,11 +309,11 @@ int make_plan(const skm_matrix* X, int32_t k, int32_t variant, int32_t precision
     // whole rows: a row walk covers every centre of a row with a surviving
     // pair or group, so where the tests leave few per row, packed slices
     // walk far fewer centres (Lloyd and Hamerly: a slice of a large copy
-    // stays cached); the fit measures which is faster (Elkan's
-    // one packed slice gained at most 6% on topical rows and lost up to 7%
-    // to its timing steps on plain ones; on rows under 20 stored entries
-    // the per-row work of a slice outweighs what it saves, and the two
-    // timing steps alone cost Yin-Yang 7-13% of a fit)
+    // stays cached); the fit measures which is faster.  Not for Elkan's one
+    // slice at kp = 256 (it gained at most 6% on topical rows and lost up to
+    // 7% to its timing steps on plain ones), nor for rows under 20 stored
+    // entries (a slice's per-row work outweighs what it saves, and the two
+    // timing steps alone cost Yin-Yang 7-13% of a fit).
     P->pack_adapt = true;
     P->pack_all = !P->yy && !P->elkan;
     P->nq = (k + kChunkF32 - 1) / kChunkF32;
