@@ -1620,8 +1620,9 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
   // the rows' structure decides, not the problem's shape.
   int pack_choice = 0;  // 0 timing both, 1 whole rows, 2 packed slices
   bool pack_step = false;
-  double pack_ms[2] = {0.0, 0.0};
-  int pack_steps[2] = {0, 0};
+  // [without, with bound tests][whole rows, slices]
+  double pack_ms[2][2] = {};
+  int pack_steps[2][2] = {};
   const int pack_mode = P.elkan ? kModeElkan : kModeYinYang;
   // one assignment-step walk in `mode`: one launch, or one per chunk of
   // centres with the running per-row results in rs
@@ -1657,6 +1658,11 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
   const bool prof = o.profile != 0;
   const bool timed = prof || P.pack_adapt;
   hipEvent_t ev0[kStepChunk] = {}, ev1[kStepChunk] = {};
+  // timed walk choice: an event between the two gated walks of a step (the
+  // one whose kernel works takes nearly all the time: steps with and
+  // without bound tests are told apart) and whether the step was gated
+  hipEvent_t evm[kStepChunk] = {};
+  bool gated[kStepChunk] = {};
   double objective = 0.0;
   {
     // centre step: member sums of the moved rows, renormalisation and
@@ -1693,6 +1699,7 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
       for (int c = 0; c < kStepChunk; ++c) {
         SKM_HIP(hipEventCreate(&ev0[c]));
         SKM_HIP(hipEventCreate(&ev1[c]));
+        if (P.pack_adapt) SKM_HIP(hipEventCreate(&evm[c]));
       }
     SKM_HIP(hipMemsetAsync(CT, 0, (size_t)d * P.kp * sizeof(float), s));
     SKM_HIP(hipMemsetAsync(S, 0, (size_t)k * d * sizeof(long long), s));
@@ -1803,13 +1810,15 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
         A.gps = gps;
         A.layout = layout;
         const int plain = P.elkan ? kModeFitElkanInit : kModeFit;
-        if (exhaustive || t < off_until) {
+        gated[c] = !(exhaustive || t < off_until);
+        if (!gated[c]) {
           SKM_HIP(walk(A, plain));
         } else {
           // with the bound tests, or (switched off by the step control) a
           // full walk that refreshes every bound: the plain fit kernel
           A.gate = 1;
           SKM_HIP(walk(A, P.elkan ? kModeElkan : P.yy ? kModeYinYang : kModeHamerly));
+          if (P.pack_adapt) SKM_HIP(hipEventRecord(evm[c], s));
           A.gate = 2;
           SKM_HIP(walk(A, P.elkan ? kModeFitElkanInit : kModeFit));
         }
@@ -1832,12 +1841,18 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
           if (prof) sk_ms += ms;
           if (P.pack_adapt && pack_choice == 0 && t >= 2 && t <= 5) {
             const int w = (t == 3 || t == 4) ? 1 : 0;
-            // Lloyd and Hamerly: time per computed similarity, so that a
-            // Hamerly step with tests (fewer rows walked) and a plain one
-            // compare; Elkan and Yin-Yang: time, since computing fewer
-            // similarities is what their packed slices are for
-            pack_ms[w] += P.pack_all ? (double)ms / (double)std::max<uint64_t>(r.sims, 1) : ms;
-            pack_steps[w] += 1;
+            int tested = 0;
+            if (gated[c]) {
+              float m1 = 0.f;
+              SKM_HIP(hipEventElapsedTime(&m1, ev0[c], evm[c]));
+              tested = m1 > ms - m1 ? 1 : 0;
+            }
+            // Lloyd and Hamerly: time per computed similarity (a step with
+            // tests walks fewer rows); Elkan and Yin-Yang: time, since
+            // computing fewer similarities is what their packed slices are for
+            pack_ms[tested][w] +=
+                P.pack_all ? (double)ms / (double)std::max<uint64_t>(r.sims, 1) : ms;
+            pack_steps[tested][w] += 1;
           }
         }
         sk_launches += 1;
@@ -1858,9 +1873,21 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
       }
       t0 += ch;
       off_until = hm->ctl.tests ? INT64_MIN : (int64_t)hm->ctl.test_next;
-      // packed slices only where clearly faster (3%)
-      if (P.pack_adapt && pack_choice == 0 && pack_steps[0] >= 2 && pack_steps[1] >= 2)
-        pack_choice = pack_ms[1] / pack_steps[1] < 0.97 * (pack_ms[0] / pack_steps[0]) ? 2 : 1;
+      // after the timing steps: compare steps of one kind (Elkan and
+      // Yin-Yang: with tests, the only walks they pack; Lloyd and Hamerly:
+      // plain first), slices only where clearly faster (3%); no comparable
+      // pair: whole rows
+      if (P.pack_adapt && pack_choice == 0 && t0 >= 6) {
+        pack_choice = 1;
+        const int order[2] = {P.pack_all ? 0 : 1, P.pack_all ? 1 : -1};
+        for (int q : order) {
+          if (q < 0 || pack_steps[q][0] == 0 || pack_steps[q][1] == 0) continue;
+          const double whole = pack_ms[q][0] / pack_steps[q][0];
+          const double sliced = pack_ms[q][1] / pack_steps[q][1];
+          pack_choice = sliced < 0.97 * whole ? 2 : 1;
+          break;
+        }
+      }
     }
     // final objective (after the last update) and centre-centre count
     SKM_HIP(hipMemcpyAsync(&hm->per, per, sizeof(Persist), hipMemcpyDeviceToHost, s));
@@ -1889,6 +1916,7 @@ done:
   for (int c = 0; c < kStepChunk; ++c) {
     if (ev0[c]) (void)hipEventDestroy(ev0[c]);
     if (ev1[c]) (void)hipEventDestroy(ev1[c]);
+    if (evm[c]) (void)hipEventDestroy(evm[c]);
   }
   if (owned) {
     (void)hipFreeAsync(ws, s);
