@@ -94,6 +94,33 @@ def test_warm_start_equals_cold_fit(skm, torch_cuda, variant, k, precision):
         assert np.array_equal(aw.cpu().numpy(), ref.a)
 
 
+@pytest.mark.parametrize("variant,k", [("yinyang", 200), ("yinyang", 300), ("elkan", 300),
+                                       ("hamerly", 300)])
+def test_warm_start_timed_walk_equals_cold_fit(skm, torch_cuda, variant, k):
+    """Topic-structured rows, walk choice left to the fit (Elkan and Yin-Yang
+    time whole rows against packed slices; Hamerly, with a copy of 64 MB or
+    more, against slices): a warm start times its steps from step 1 on and
+    ends where the cold fit does, and both follow the oracle's Lloyd
+    trajectory from the seeded centres."""
+    torch = torch_cuda
+    d = 40000 if variant == "hamerly" else 8000
+    X = datagen.sparse_tfidf(12000, d, 40.0, 6161, topics=20)
+    u = np.random.default_rng(13).random(k)
+    Xd = skm.DeviceCSR.from_host(X)
+    ch, C, a, s1, s2 = skm.seed_kmeanspp(Xd, k, u)
+    say("case warm start timed walk %s k=%d" % (variant, k))
+    ac, Cc, _, stc = skm.fit(Xd, k, C, variant, 25)
+    aw, Cw, _, stw = skm.fit(Xd, k, C, variant, 25, warm=(a, s1, s2))
+    torch.cuda.synchronize()
+    assert torch.equal(ac, aw) and torch.equal(Cc, Cw)
+    assert stc.iterations == stw.iterations and stc.converged == stw.converged
+    ref = oracle.fit(X, C.cpu().numpy(), "lloyd", 25)
+    assert stc.iterations == ref.iterations
+    assert np.array_equal(ac.cpu().numpy(), ref.a)
+    say("  iterations %d, sims cold %d warm %d" % (stc.iterations, stc.sims_point_center,
+                                                  stw.sims_point_center))
+
+
 @pytest.mark.parametrize("name,n,k,chain,alpha", [("c1", None, 10, 20, 1.0),
                                                   ("c1", None, 10, 5, 1.5),
                                                   ("c2", 20000, 100, 50, 1.0),
