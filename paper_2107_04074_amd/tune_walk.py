@@ -24,6 +24,12 @@ with an error if they do not.
     python -m paper_2107_04074_amd.tune_walk [--out PATH] [--reps 5]
 
 Rebuild the library afterwards (python -m paper_2107_04074_amd.build).
+
+The tables hold the plan's first choice.  Where they pick whole rows, a fit
+still times slices against them in its first steps when the rows' structure
+rather than their shape decides (Elkan and Yin-Yang: packed slices for the
+steps with tests; Lloyd and Hamerly: copies of 64 MB or more, larger than
+the ones measured here) and keeps the faster.
 """
 from __future__ import annotations
 
