@@ -1656,7 +1656,21 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
   int64_t tot_sims = 0, tot_rechecks = 0, sk_launches = 0, sk_rows = 0, sk_nnz = 0;
   double sk_ms = 0.0;
   const bool prof = o.profile != 0;
-  const bool timed = prof || P.pack_adapt;
+  // Bounded fits on rows under 20 stored entries: a row's walk is a few
+  // gathers, and the tests' bookkeeping can cost more than the walks they
+  // save however much they prune.  Step 2 runs plain (the walk that
+  // refreshes every bound, as after the step control switched the tests
+  // off); if the steps with tests of steps 2-5 were not at least 5% faster
+  // than the plain ones, the rest of the fit keeps the tests off but for
+  // the step control's own widening probes (its threshold rises above any
+  // pruning rate).
+  const bool test_probe = P.bounds && o.schedule == 0 && !P.pack_adapt &&
+                          row_class(n, X->nnz) == 0;
+  int test_choice = 0;  // 0 timing, 1 decided
+  double test_ms[2] = {0.0, 0.0};
+  int test_steps[2] = {0, 0};
+  const double tests_off_min = 2.0;  // above any pruned share
+  const bool timed = prof || P.pack_adapt || test_probe;
   hipEvent_t ev0[kStepChunk] = {}, ev1[kStepChunk] = {};
   // timed walk choice: an event between the two gated walks of a step (the
   // one whose kernel works takes nearly all the time: steps with and
@@ -1699,7 +1713,7 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
       for (int c = 0; c < kStepChunk; ++c) {
         SKM_HIP(hipEventCreate(&ev0[c]));
         SKM_HIP(hipEventCreate(&ev1[c]));
-        if (P.pack_adapt) SKM_HIP(hipEventCreate(&evm[c]));
+        if (P.pack_adapt || test_probe) SKM_HIP(hipEventCreate(&evm[c]));
       }
     SKM_HIP(hipMemsetAsync(CT, 0, (size_t)d * P.kp * sizeof(float), s));
     SKM_HIP(hipMemsetAsync(S, 0, (size_t)k * d * sizeof(long long), s));
@@ -1767,7 +1781,8 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
       int ch = (int)std::min<int64_t>(kStepChunk, (int64_t)max_iter - t0);
       // a timed walk choice ends the first chunk with its last timing step,
       // so the chosen walk starts at step 6
-      if (P.pack_adapt && pack_choice == 0 && t0 < 6) ch = std::min(ch, 6 - (int)t0);
+      if ((P.pack_adapt && pack_choice == 0) || (test_probe && test_choice == 0))
+        if (t0 < 6) ch = std::min(ch, 6 - (int)t0);
       SKM_HIP(hipMemsetAsync(cnt, 0, (size_t)ch * kCounterSlots * sizeof(Counters), s));
       for (int c = 0; c < ch; ++c) {
         const int32_t t = t0 + c;
@@ -1810,7 +1825,7 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
         A.gps = gps;
         A.layout = layout;
         const int plain = P.elkan ? kModeFitElkanInit : kModeFit;
-        gated[c] = !(exhaustive || t < off_until);
+        gated[c] = !(exhaustive || t < off_until || (test_probe && test_choice == 0 && t == 2));
         if (!gated[c]) {
           SKM_HIP(walk(A, plain));
         } else {
@@ -1818,7 +1833,7 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
           // full walk that refreshes every bound: the plain fit kernel
           A.gate = 1;
           SKM_HIP(walk(A, P.elkan ? kModeElkan : P.yy ? kModeYinYang : kModeHamerly));
-          if (P.pack_adapt) SKM_HIP(hipEventRecord(evm[c], s));
+          if (P.pack_adapt || test_probe) SKM_HIP(hipEventRecord(evm[c], s));
           A.gate = 2;
           SKM_HIP(walk(A, P.elkan ? kModeFitElkanInit : kModeFit));
         }
@@ -1854,6 +1869,16 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
                 P.pack_all ? (double)ms / (double)std::max<uint64_t>(r.sims, 1) : ms;
             pack_steps[tested][w] += 1;
           }
+          if (test_probe && test_choice == 0 && t >= 2 && t <= 5) {
+            int tested = 0;
+            if (gated[c]) {
+              float m1 = 0.f;
+              SKM_HIP(hipEventElapsedTime(&m1, ev0[c], evm[c]));
+              tested = m1 > ms - m1 ? 1 : 0;
+            }
+            test_ms[tested] += ms;
+            test_steps[tested] += 1;
+          }
         }
         sk_launches += 1;
         sk_rows += (int64_t)r.rows_done;
@@ -1877,6 +1902,15 @@ int skm_fit(const skm_matrix* X, int32_t k, const float* init_centers, int32_t v
       // Yin-Yang: with tests, the only walks they pack; Lloyd and Hamerly:
       // plain first), slices only where clearly faster (3%); no comparable
       // pair: whole rows
+      if (test_probe && test_choice == 0 && t0 >= 6) {
+        test_choice = 1;
+        if (test_steps[0] > 0 && test_steps[1] > 0 &&
+            test_ms[1] / test_steps[1] > 0.95 * (test_ms[0] / test_steps[0])) {
+          // nothing runs on the stream now (the records were just read)
+          SKM_HIP(hipMemcpyAsync(&ctl->test_min, &tests_off_min, sizeof(double),
+                                 hipMemcpyHostToDevice, s));
+        }
+      }
       if (P.pack_adapt && pack_choice == 0 && t0 >= 6) {
         pack_choice = 1;
         const int order[2] = {P.pack_all ? 0 : 1, P.pack_all ? 1 : -1};
