@@ -137,9 +137,13 @@ typedef struct {            /* [host]; an all-zero struct means defaults      */
                                tests (Sections 5.1-5.5) and the tightening of
                                l(i) run only while they prune enough to pay
                                for themselves, otherwise the step walks every
-                               row and refreshes every bound exactly; 1: they
-                               run at every step, as in the paper.  Results
-                               are the same either way; only work differs.  */
+                               row and refreshes every bound exactly (on rows
+                               under 20 stored entries the fit also times a
+                               plain step against steps with tests and keeps
+                               the tests off when they are not faster); 1:
+                               they run at every step, as in the paper.
+                               Results are the same either way; only work
+                               differs.                                    */
   int32_t batch_tile_rows;  /* skm_fit_batched in lockstep (workers = 0): rows
                                per work item of the batched row walk; 0 takes
                                the table compiled into the library (the
